@@ -1,0 +1,122 @@
+/*
+ * cro.h -- plain FP64 CPU oracle for CR-Solver (arXiv 2607.11340).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, scalar, single-threaded
+ * reference that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no code, header, table or constant with the GPU library.
+ *
+ * Conventions (all arrays are row-major C arrays of double, item-major):
+ *   u    tendon displacements of one configuration, u[3*i + j] = length change of
+ *        tendon j (at angle alpha_j = 2*pi*j/3) in segment i relative to L_i
+ *        (Sec. III-B, eq. 4).
+ *   z    bending coordinates of one configuration, z[2*i] = a_i = theta_i cos phi_i,
+ *        z[2*i+1] = b_i = theta_i sin phi_i (the iterate of the solver).
+ *   T    a pose as 12 doubles, 3x4 row-major [R | p].
+ * A trajectory (kinds PATH/TRAJ) stores H+1 configurations back to back.
+ */
+#ifndef CRO_H
+#define CRO_H
+#include <stdint.h>
+
+#define CRO_MAX_SEG 6
+#define CRO_MAX_DIR (2 * CRO_MAX_SEG)
+
+enum { CRO_IK = 0, CRO_PATH = 1, CRO_TRAJ = 2 };
+enum {
+  CRO_SOLVED = 1,
+  CRO_LIMIT_VIOLATION = 2,
+  CRO_COLLISION = 4,
+  CRO_NONFINITE = 8,
+  CRO_NOT_CONVERGED = 16
+};
+
+typedef struct {
+  int32_t n_seg;       /* n, 1..CRO_MAX_SEG */
+  int32_t pts_per_seg; /* K backbone sample points per segment (collision) */
+  double L[CRO_MAX_SEG];     /* arc length of each segment, m */
+  double r[CRO_MAX_SEG];     /* tendon routing radius r_c of each segment, m */
+  double u_max[CRO_MAX_SEG]; /* bound on |tendon displacement|, m */
+  double theta_max;          /* bound on each bending angle theta_i, rad */
+} cro_robot;
+
+typedef struct {
+  double w_pos, w_rot;   /* pose residual weights */
+  double rho_lim;        /* tendon-limit (and velocity/acceleration hinge) penalty */
+  double rho_curv;       /* bending-angle limit penalty */
+  double rho_coll;       /* obstacle penetration penalty */
+  double margin;         /* safety margin delta, m */
+  double rho_eq;         /* trajectory endpoint equality penalty */
+  double w_len;          /* trajectory tip path-length weight */
+  double w_vel, w_acc;   /* tendon velocity / acceleration smoothness weights */
+  double v_max, a_max;   /* tendon velocity / acceleration bounds (INFINITY = off) */
+  double dt;             /* time step */
+} cro_weights;
+
+typedef struct {
+  int32_t n_final, k_init, k_final, ls_max;
+  double lambda0, lambda_min, lambda_max, dup_eps;
+} cro_opts;
+
+typedef struct {
+  int32_t kind;          /* CRO_IK, CRO_PATH, CRO_TRAJ */
+  int32_t H;             /* horizon: H+1 waypoints (0 for IK) */
+  const double* task;    /* IK: T[12]; PATH: T[(H+1)*12]; TRAJ: u_start[3n], u_goal[3n] */
+  int32_t n_sph;         /* number of spheres */
+  const double* sph;     /* [n_sph][4]: cx, cy, cz, radius */
+} cro_problem;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* tendon displacements -> bending coordinates, and the zero-sum lift back */
+void cro_u_to_z(const cro_robot* rb, const double* u, double* z);
+void cro_z_to_u(const cro_robot* rb, const double* z, double* u);
+
+/* Forward kinematics of one configuration u[3n].
+ * arc[3n]: (kappa, phi, L) per segment; frames[12n] or NULL: T_{0,i} of each
+ * segment tip; pts[3nK] or NULL: backbone points, point k=1..K of segment i at
+ * index (i*K + k-1)*3.  Returns 0. */
+int cro_fk(const cro_robot* rb, const double* u, double* arc, double* frames, double* pts);
+
+/* Penalised cost (eq. 17) of one seed of one problem, with u[(H+1)*3n].
+ * grad_u (same shape) receives dC/du when non-NULL. */
+double cro_cost(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
+                const double* u, double* grad_u);
+
+/* Residual vector r and dense Jacobian J = dr/dz ([m][(H+1)*2n]) at z.
+ * Returns the number of residual rows m, or -1 if it would exceed cap_rows. */
+int cro_residuals(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
+                  const double* z, double* r, double* J, int cap_rows);
+
+/* Pose error of configuration z against pose T (eq. 18 and its parts):
+ * out[0] = ||log(T_ee^-1 T)||_2, out[1] = position error (m), out[2] = rotation angle (rad). */
+void cro_pose_error(const cro_robot* rb, const double* z, const double* T, double* out);
+
+/* k Levenberg-Marquardt iterations with backtracking line search on one seed.
+ * z and *lambda are updated in place.  Returns 1 if the seed failed (non-finite cost). */
+int cro_lm(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o,
+           double* z, double* lambda, int iters, double* cost_out, int* trials_out);
+
+/* Cholesky solve of M x = y for symmetric positive definite M (N x N, lower triangle
+ * read) with half bandwidth bw.  x holds y on entry.  Returns 0, or -1 on a
+ * non-positive pivot.  M is overwritten by its factor. */
+int cro_chol_solve(int N, int bw, double* M, double* x);
+
+/* SelectTop of Algorithm 1: indices of n_final candidates out of S. */
+void cro_select_top(int S, int nz, const double* z, const double* e, const double* pen,
+                    const int32_t* failed, int n_final, double dup_eps, int32_t* idx_out);
+
+/* Two-stage solve of one problem from S seeds u_seed[S][(H+1)*3n]
+ * (Algorithm 1 for IK; the same template for PATH and TRAJ).
+ * u_out[(H+1)*3n], err_out[2] (position m, rotation rad), *status (bits),
+ * *best_idx (winning seed), *best_cost.  Returns 0, or -1 on bad arguments. */
+int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
+              const cro_opts* o, int S, const double* u_seed, double* u_out,
+              double* err_out, int32_t* status, int32_t* best_idx, double* best_cost);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs for CR-Solver workloads.
+
+This module only draws random numbers and describes workload shapes.  It holds
+none of the method's arithmetic (no kinematics, no cost, no solver), so both the
+GPU library and the CPU oracle can be fed from it.  Every array is float64 and
+item-major: actuations are ``[..., n, 3]`` tendon displacements in metres.
+
+Poses that must be reachable (IK targets, path references) are made by the
+caller from actuations drawn here, by running forward kinematics on its own side.
+
+Recipes (the paper's benchmark sets are not available, so these stand in for
+its 1000 uniformly sampled IK targets, its smooth reference paths and its random
+sphere scenes; Sec. V-B, V-C, V-D):
+  * uniform actuation: per segment u ~ U[-b, b]^3, minus its mean (tendon lengths
+    of an inextensible segment sum to 3 L, eq. 4), accepted iff max |u| <= b;
+  * smooth actuation path: per tendon a constant plus three Fourier harmonics with
+    1/k amplitudes over the horizon, made zero-sum per segment and scaled so that
+    max |u| <= 0.9 b;
+  * spheres: centres uniform in a caller-given box, radii uniform in [r_lo, r_hi].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 20260000
+
+# Workload shapes.  Robot geometry in metres; b = bound on |tendon displacement|.
+WORKLOADS = {
+    "ik_plain_1seg": dict(
+        kind="ik", L=[0.10], r=[0.010], b=0.010, P=16, S=64,
+        k_init=100, k_final=0, n_final=0, K=10, dtype="f64", seed=BASE_SEED + 1),
+    "ik_batched_3seg": dict(
+        kind="ik", L=[0.10, 0.08, 0.06], r=[0.010, 0.008, 0.006], b=0.008, P=4096, S=256,
+        k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 2),
+    "path_4seg": dict(
+        kind="path", L=[0.08] * 4, r=[0.008] * 4, b=0.006, P=512, H=63, S=32,
+        k_init=100, k_final=20, n_final=4, K=10, dtype="f32", seed=BASE_SEED + 3,
+        weights=dict(w_vel=1e-2, w_acc=1e-2)),
+    "traj_5seg": dict(
+        kind="traj", L=[0.06] * 5, r=[0.006] * 5, b=0.006, P=256, H=31, S=64, M=64,
+        k_init=80, k_final=20, n_final=4, K=64, dtype="f32", seed=BASE_SEED + 4),
+}
+
+
+def rng_for(name: str, salt: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(WORKLOADS[name]["seed"] * 1000 + salt))
+
+
+def uniform_actuation(rng: np.random.Generator, n: int, b, count: int) -> np.ndarray:
+    """`count` actuations [count, n, 3], each segment zero-sum with |u| <= b."""
+    b = np.broadcast_to(np.asarray(b, dtype=np.float64), (n,))
+    out = np.empty((count, n, 3))
+    for i in range(n):
+        filled = 0
+        while filled < count:
+            m = max(16, int(1.2 * (count - filled)) + 16)
+            x = rng.uniform(-b[i], b[i], size=(m, 3))
+            x = x - x.mean(axis=1, keepdims=True)
+            ok = x[np.abs(x).max(axis=1) <= b[i]]
+            take = min(len(ok), count - filled)
+            out[filled:filled + take, i] = ok[:take]
+            filled += take
+    return out
+
+
+def smooth_actuation_paths(rng: np.random.Generator, n: int, b, count: int, T: int) -> np.ndarray:
+    """`count` smooth actuation trajectories [count, T, n, 3] with max |u| <= 0.9 b."""
+    b = np.broadcast_to(np.asarray(b, dtype=np.float64), (n,))
+    t = np.arange(T, dtype=np.float64) / max(T - 1, 1)
+    out = np.empty((count, T, n, 3))
+    for i in range(n):
+        base = rng.uniform(-1.0, 1.0, size=(count, 1, 3))
+        sig = np.repeat(base, T, axis=1)
+        for k in (1, 2, 3):
+            cc = rng.uniform(-1.0, 1.0, size=(count, 1, 3))
+            ss = rng.uniform(-1.0, 1.0, size=(count, 1, 3))
+            ang = 2.0 * np.pi * k * t[None, :, None]
+            sig = sig + (cc * np.cos(ang) + ss * np.sin(ang)) / k
+        sig = sig - sig.mean(axis=2, keepdims=True)
+        peak = np.abs(sig).max(axis=(1, 2), keepdims=True)
+        out[:, :, i, :] = sig * (0.9 * b[i] / np.maximum(peak, 1e-300))
+    return out
+
+
+def perturbed_linear_paths(rng: np.random.Generator, u_start: np.ndarray, u_goal: np.ndarray,
+                           count: int, T: int, b, amp: float = 0.5) -> np.ndarray:
+    """Trajectory seeds [count, T, n, 3] between u_start and u_goal ([n, 3] each):
+    seed 0 is the straight interpolation (the linear initializer of Sec. V-C),
+    the others add two half-sine bumps per tendon of amplitude U[-amp, amp] * b,
+    made zero-sum and scaled per waypoint back inside |u| <= b."""
+    n = u_start.shape[0]
+    b = np.broadcast_to(np.asarray(b, dtype=np.float64), (n,))
+    s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
+    lin = (1.0 - s)[:, None, None] * u_start[None] + s[:, None, None] * u_goal[None]
+    out = np.repeat(lin[None], count, axis=0)
+    for q in range(1, count):
+        bump = np.zeros((T, n, 3))
+        for k in (1, 2):
+            c = rng.uniform(-amp, amp, size=(n, 3)) * b[:, None]
+            bump += np.sin(np.pi * k * s)[:, None, None] * c[None]
+        bump -= bump.mean(axis=2, keepdims=True)
+        x = out[q] + bump
+        peak = np.abs(x).max(axis=2)  # [T, n]
+        scale = np.minimum(1.0, b[None, :] / np.maximum(peak, 1e-300))
+        out[q] = x * scale[:, :, None]
+    return out
+
+
+def spheres(rng: np.random.Generator, count: int, lo, hi, r_lo: float, r_hi: float) -> np.ndarray:
+    """`count` spheres [count, 4] = (cx, cy, cz, radius), centres uniform in [lo, hi]^3."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    c = rng.uniform(lo, hi, size=(count, 3))
+    r = rng.uniform(r_lo, r_hi, size=(count, 1))
+    return np.concatenate([c, r], axis=1)
