@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""One-GPU benchmark of the CR-Solver hot path on MI355X (gfx950).
+
+Workload (the configuration the headline metric is quoted on): batched two-stage
+inverse kinematics of a 3-segment tendon-driven robot (segment lengths
+0.10/0.08/0.06 m, tendon radii 0.010/0.008/0.006 m, |u| <= 0.008 m), 4096
+reachable 6-DoF targets (forward kinematics of seeded uniform actuations), 256
+uniform seeds per target, 150 FP32 + 50 FP64 Levenberg-Marquardt iterations,
+N_final = 8 (Algorithm 1).  One step = one cr_solve_ik call over the whole batch
+(stage 1, SelectTop, stage 2, argmin).  Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line: IK solves/s, success rate at <= 1 mm / 1 degree, the
+roofline of the dominant kernel (FP32 stage 1, algorithmic flops from the
+library's own op tally, duration from HIP events recorded on the solve's stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOAD = "ik_batched_3seg"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tally-seeds", type=int, default=256)
+    ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                                           "ik_stage1_traffic.json"))
+    return ap.parse_args()
+
+
+def build_inputs(cr, I, torch):
+    spec = I.WORKLOADS[WORKLOAD]
+    n, P, S = len(spec["L"]), spec["P"], spec["S"]
+    rng = I.rng_for(WORKLOAD)
+    u_true = I.uniform_actuation(rng, n, spec["b"], P)               # [P, n, 3]
+    seeds = I.uniform_actuation(rng, n, spec["b"], P * S)           # [P*S, n, 3]
+    robot = cr.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n)
+    dev = torch.device("cuda:0")
+    u_true_d = torch.tensor(u_true.reshape(P, -1).T.copy(), device=dev)
+    frames = cr.fk(robot, u_true_d, arc=False, frames=True)["frames"]  # [12n, P] float64
+    T = frames[12 * (n - 1):12 * n].contiguous()
+    useed = torch.tensor(seeds.reshape(P * S, -1).T.copy(), device=dev)
+    return spec, robot, u_true, seeds, T, useed
+
+
+def cpu_baseline(spec, T_host, seeds, budget_s):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    n = len(spec["L"])
+    rb = O.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n)
+    W = O.Weights()
+    opts = O.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    S = spec["S"]
+    done, t0 = 0, time.perf_counter()
+    solved = 0
+    while True:
+        p = done
+        res = O.solve(rb, W, O.Problem("ik", T_host[p]), opts, seeds[p * S:(p + 1) * S])
+        solved += int(res["status"] == O.SOLVED)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or done >= spec["P"]:
+            break
+    return dict(value=done / el, unit="IK solves/s", cores=1, kind="oracle",
+                sample=f"first {done} of {spec['P']} targets x {S} seeds, full {spec['k_init']}+{spec['k_final']} "
+                       f"iterations, single thread, {el:.1f} s; {solved}/{done} solved")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              f"(problems are independent, see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2607_11340_amd import crsolver as cr
+    from paper_2607_11340_amd import inputs as I
+
+    spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
+    P, S = spec["P"], spec["S"]
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    weights = cr.Weights()
+    ws = torch.empty(cr.ik_workspace_bytes(robot, P, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    out = (torch.empty((3 * robot.n, P), dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"),
+           torch.empty((P,), dtype=torch.int32, device="cuda"))
+
+    def step():
+        cr.solve_ik(robot, T, useed, weights, opts, dtype=torch.float32, workspace=ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    cr.lib.cr_timing_enable(1)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    stage_ms = (C.c_double * 4)()
+    ncalls = C.c_int64(0)
+    cr._check(cr.lib.cr_timing_read(stage_ms, C.byref(ncalls)))
+    cr.lib.cr_timing_enable(0)
+    ms_per_step = total_ms / args.steps
+    stage_avg = [stage_ms[k] / max(ncalls.value, 1) for k in range(4)]
+    status = out[2].cpu().numpy()
+    err = out[1].cpu().numpy()
+    success = float((status == cr.SOLVED).mean())
+    print(f"bench: {args.steps} steps, {ms_per_step:.3f} ms/step, stages {['%.3f' % s for s in stage_avg]} ms, "
+          f"success {success:.4f}", file=sys.stderr, flush=True)
+
+    # algorithmic flops of the stage-1 kernel from the library's op tally over a seed sample
+    T_host = T.cpu().numpy().T.copy()                       # [P, 12]
+    rng = np.random.default_rng(1)
+    pick = rng.choice(P * S, size=min(args.tally_seeds, P * S), replace=False)
+    Ts = np.ascontiguousarray(T_host[pick // S])
+    us = np.ascontiguousarray(seeds[pick].reshape(len(pick), -1))
+    tally = (C.c_double * 8)()
+    rc, wc, oc = robot.c(), weights.c(), opts.c()
+    cr._check(cr.lib.cr_ik_flop_tally(C.byref(rc), C.byref(wc), C.byref(oc), len(pick),
+                                      Ts.ctypes.data_as(C.POINTER(C.c_double)),
+                                      us.ctypes.data_as(C.POINTER(C.c_double)), tally))
+    flops_per_seed = tally[0]
+    flops_launch = flops_per_seed * P * S
+    achieved = flops_launch / (stage_avg[0] * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+    roofline = dict(bound="alu", kernel="k_ik_stage1<3,float>", achieved=round(achieved, 3),
+                    peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    traffic=traffic, launch_ms=round(stage_avg[0], 4),
+                    flops_per_launch=flops_launch, flops_per_seed=round(flops_per_seed, 1),
+                    flops_per_normal_eq=tally[6], flops_per_cost_eval=tally[7],
+                    trials_per_seed=round(tally[5], 2), tally_sample_seeds=len(pick))
+
+    base = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        T34 = T_host.reshape(P, 3, 4)
+        base = cpu_baseline(spec, T34, seeds, args.cpu_seconds)
+
+    line = dict(
+        metric="IK solves/sec at <=1 mm/1 deg (success %); FK+grad evals/sec; %FP32 VALU peak",
+        value=round(P / (ms_per_step * 1e-3), 1), unit="IK solves/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
+        config=dict(workload=WORKLOAD, segments=len(spec["L"]), targets=P, seeds_per_target=S,
+                    k_init=spec["k_init"], k_final=spec["k_final"], n_final=spec["n_final"]),
+        success_rate=round(success, 4), max_pos_err_solved_m=float(np.nanmax(np.where(status == cr.SOLVED, err[0], 0))),
+        stage_ms=dict(stage1=round(stage_avg[0], 4), select=round(stage_avg[1], 4), stage2=round(stage_avg[2], 4),
+                      finalize=round(stage_avg[3], 4)),
+        roofline=roofline, cpu_baseline=base)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

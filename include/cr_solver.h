@@ -1,0 +1,221 @@
+/*
+ * cr_solver.h -- C ABI of the MI355X (gfx950) CR-Solver hot path.
+ *
+ * CR-Solver (arXiv 2607.11340) solves inverse kinematics, path following and
+ * trajectory planning of tendon-driven continuum robots as one penalised
+ * nonlinear least-squares problem (Sec. IV-A, eq. 17), optimised from many seeds
+ * at once by batched Levenberg-Marquardt (Sec. IV-C) inside a two-stage
+ * exploration/refinement template (Sec. IV-B, Algorithm 1).
+ *
+ * General rules for every entry point:
+ *  - No exception crosses this boundary; every call returns a cr_status.
+ *  - Arrays marked [device] are device pointers (HIP global memory), arrays
+ *    marked [host] are host pointers.  The caller owns all of them; the library
+ *    never frees caller memory and keeps no pointer after the call returns.
+ *  - Batched arrays are structure-of-arrays with the batch index fastest:
+ *    element (component c, item b) lives at x[c * ld + b].  Unless an explicit
+ *    `ld` is taken, ld equals the batch size of that array.
+ *  - A pose is 12 components, the 3x4 row-major matrix [R | p]:
+ *    c = 4*row + col, col 3 being the position (metres).
+ *  - Tendon displacements u (metres) are 3 components per segment,
+ *    c = 3*i + j for tendon j (at angle 2*pi*j/3 about the backbone) of
+ *    segment i; u is the tendon length minus the segment length, eq. (4).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and is
+ *    stream-ordered; no call synchronises the host unless stated.
+ *  - Shape, pointer, option and dtype errors return CR_EINVAL and launch
+ *    nothing; HIP failures return CR_EDEVICE; cr_last_error() gives the text.
+ *    Data-dependent trouble (NaN inputs, unreachable targets) never fails a
+ *    call: it is reported per problem in the status bits below.
+ */
+#ifndef CR_SOLVER_H
+#define CR_SOLVER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CR_OK = 0,
+  CR_EINVAL = 1,        /* invalid argument; nothing was launched */
+  CR_ENOMEM = 2,        /* workspace too small or allocation failed */
+  CR_EDEVICE = 3,       /* a HIP call failed */
+  CR_EUNSUPPORTED = 4   /* valid request this build does not implement */
+} cr_status;
+
+/* Floating-point type of a call's arrays and arithmetic. */
+typedef enum { CR_F32 = 0, CR_F64 = 1 } cr_dtype;
+
+/* Task kinds of Sec. IV-A. */
+typedef enum {
+  CR_KIND_IK = 0,    /* inverse kinematics, eq. (8)-(10) */
+  CR_KIND_PATH = 1,  /* path following, eq. (16) with the trajectory constraints */
+  CR_KIND_TRAJ = 2   /* trajectory planning, eq. (11)-(15) */
+} cr_kind;
+
+/* Per-problem status bits written by the solve calls (success criterion of
+ * Sec. V-B with the 1 mm / 1 degree thresholds). */
+enum {
+  CR_SOLVED = 1,          /* every check below passed */
+  CR_LIMIT_VIOLATION = 2, /* a tendon exceeds its bound by > 1e-6 m or theta > theta_max */
+  CR_COLLISION = 4,       /* a backbone point is inside an inflated sphere */
+  CR_NONFINITE = 8,       /* every candidate had a non-finite cost */
+  CR_NOT_CONVERGED = 16   /* position error > 1 mm or rotation error > 1 degree */
+};
+
+#define CR_MAX_SEG 6
+
+/* Robot geometry (Sec. III, piecewise constant curvature, 3 tendons per segment). [host] */
+typedef struct {
+  int32_t n_seg;              /* number of segments n, 1..CR_MAX_SEG */
+  int32_t pts_per_seg;        /* K backbone points per segment for collision, >= 1 */
+  double L[CR_MAX_SEG];       /* segment arc length (m), > 0 */
+  double r[CR_MAX_SEG];       /* tendon routing radius r_c (m), > 0; also the body radius */
+  double u_max[CR_MAX_SEG];   /* bound on |u| of each tendon of the segment (m), > 0 */
+  double theta_max;           /* bound on each bending angle (rad), default pi */
+} cr_robot;
+
+/* Spherical obstacles.  [host] struct, `sph` is [device] in the call's dtype for
+ * cr_cost_grad and double for the solve calls: sph[c * ld + m], c = cx, cy, cz, radius.
+ * per_problem = 0: one set of n_sph spheres shared by all problems;
+ * per_problem = 1: problem p owns spheres m = p * n_sph .. p * n_sph + n_sph - 1. */
+typedef struct {
+  int32_t n_sph;
+  int32_t per_problem;
+  const void* sph;
+  int64_t ld;
+} cr_spheres;
+
+/* Weights of the penalised cost, eq. (17).  [host] */
+typedef struct {
+  double w_pos, w_rot;   /* pose residual weights (1/m, 1/rad) */
+  double rho_lim;        /* tendon bound (and tendon velocity/acceleration bound) penalty */
+  double rho_curv;       /* bending-angle bound penalty */
+  double rho_coll;       /* obstacle clearance penalty */
+  double margin;         /* safety margin delta of eq. (10) (m) */
+  double rho_eq;         /* trajectory endpoint equality penalty */
+  double w_len;          /* trajectory tip path-length weight, eq. (11) squared */
+  double w_vel, w_acc;   /* quadratic tendon velocity / acceleration smoothness */
+  double v_max, a_max;   /* tendon velocity / acceleration bounds, INFINITY = off */
+  double dt;             /* time step of the finite differences */
+} cr_weights;
+
+/* Options of the two-stage solver (Algorithm 1) and of Levenberg-Marquardt.  [host] */
+typedef struct {
+  int32_t n_final;       /* N_final kept by SelectTop; 0 = plain method (no stage 2) */
+  int32_t k_init;        /* stage-1 iterations */
+  int32_t k_final;       /* stage-2 iterations */
+  int32_t ls_max;        /* line-search trials, step 1, 1/2, 1/4, ... (1..8) */
+  int32_t fp64_refine;   /* 1: stage 2 in FP64 when stage 1 runs in FP32 */
+  double lambda0, lambda_min, lambda_max;  /* LM damping: start, floor, ceiling */
+  double dup_eps;        /* SelectTop near-duplicate radius (infinity norm, rad) */
+} cr_opts;
+
+/* ------------------------------------------------------------------------- */
+
+/* Forward kinematics, Sec. III-A eq. (1)-(3) with the tendon map of eq. (4).
+ * B configurations u[3n][ld] [device] -> per segment i:
+ *   arc[3n][ld]    (kappa_i, phi_i, L_i): curvature 1/m, bending-plane azimuth in
+ *                  [0, 2 pi) (0 when straight), arc length;  [device] or NULL
+ *   frames[12n][ld] pose T_{0,i} of the tip of segment i (base frame at the
+ *                  origin, backbone leaving along +z);  [device] or NULL
+ *   pts[3nK][ld]   backbone points at arc fraction k/K, k = 1..K, component
+ *                  c = 3*(i*K + k-1) + xyz;  [device] or NULL
+ * The common mode of each segment's three tendons does not move the robot.
+ * FP32 frames are re-orthonormalised in FP64 before they are written.
+ * Errors: CR_EINVAL for a bad robot, B < 0, ld < B, u == NULL. */
+cr_status cr_fk(const cr_robot* robot, int64_t B, const void* u, int64_t ld, void* arc,
+                void* frames, void* pts, cr_dtype dtype, hipStream_t stream);
+
+/* Penalised cost (eq. 17) and its gradient for a batch of seeds, with the task
+ * objective of `kind` (IK eq. 8, path eq. 16, trajectory eq. 11) and the bound,
+ * clearance, smoothness and endpoint penalties of eq. (9)-(15).
+ *   P problems, S seeds each, H+1 waypoints per seed (H = 0 for IK).
+ *   task  [device] IK: T_target[12][P]; PATH: T_ref[12][(H+1)*P] at column
+ *         p*(H+1)+t; TRAJ: [6n][P], u_start (c < 3n) then u_goal.
+ *   u     [device] [3n][(H+1)*S*P], column (p*S + s)*(H+1) + t.
+ *   cost  [device] [S*P], column p*S + s: 1/2 sum of squared residuals.
+ *   grad  [device] like u, or NULL for cost only: dC/du (zero-sum per segment,
+ *         because the cost ignores each segment's common mode).
+ *   grad_scale [device] [S*P] or NULL: grad of seed p*S + s is multiplied by
+ *         grad_scale[p*S + s] (the upstream gradient of a backward pass).
+ * All arrays, spheres included, are in `dtype`.  The gradient is formed by an
+ * adjoint sweep over recomputed segment transforms (no stored Jacobian).
+ * Errors: CR_EINVAL for bad shapes (H != 0 for IK, H < 1 for TRAJ, H > 255,
+ * more than 512 spheres). */
+cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* spheres,
+                       const cr_weights* weights, int64_t P, int32_t H, int32_t S,
+                       const void* task, const void* u, void* cost, void* grad,
+                       const void* grad_scale, cr_dtype dtype, hipStream_t stream);
+
+/* Two-stage inverse kinematics, Algorithm 1: stage 1 runs k_init LM iterations
+ * on every seed in `dtype`; SelectTop keeps n_final per problem; stage 2 runs
+ * k_final LM iterations on those (in FP64 if fp64_refine or dtype is CR_F64);
+ * the answer is the argmin of the final cost (ties: lowest seed index).
+ *   T_target [device, double] [12][P];  u_seed [device, double] [3n][S*P],
+ *   column p*S + s.
+ *   u_out    [device, double] [3n][P]   zero-sum tendon displacements of q*
+ *   err_out  [device, double] [2][P]    position error (m), rotation error (rad)
+ *   status_out [device, int32] [P]      status bits
+ *   ws/ws_bytes [device] scratch of at least cr_solve_ik_workspace() bytes, or
+ *   NULL/0 to let the library allocate and free it stream-ordered.
+ * Calls that share one workspace must not overlap. */
+cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t P,
+                      const void* T_target, int32_t S, const void* u_seed,
+                      const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
+                      int32_t* status_out, void* ws, size_t ws_bytes, cr_dtype dtype,
+                      hipStream_t stream);
+
+/* Workspace bytes cr_solve_ik needs for these shapes (0 on invalid arguments). */
+size_t cr_solve_ik_workspace(const cr_robot* robot, int64_t P, int32_t S, const cr_opts* opts,
+                             cr_dtype dtype);
+
+/* SelectTop of Algorithm 1 on given candidates, per problem: order by e
+ * ascending (ties: lower index; failed candidates never kept), greedily keep
+ * candidates, a candidate within dup_eps (infinity norm over nz coordinates) of
+ * a kept one replaces it iff its pen is strictly lower and is skipped otherwise;
+ * if fewer than n_final remain, skipped ones refill in sorted order; -1 marks
+ * an empty slot.
+ *   z [device] [nz][S*P]; e, pen [device] [S*P]; failed [device, int32] [S*P]
+ *   or NULL; idx_out [device, int32] [n_final][P] (seed index within the problem).
+ * Errors: CR_EINVAL if S > 4096, n_final < 1 or n_final > 64. */
+cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const void* e,
+                        const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
+                        int32_t* idx_out, cr_dtype dtype, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Instrumentation (benchmarks).                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Stage timing of cr_solve_ik.  While enabled, every solve records HIP events on
+ * its own stream around its four stages (stage 1, SelectTop, stage 2, final
+ * argmin).  cr_timing_read() waits for the recorded calls, writes the summed
+ * milliseconds per stage to stage_ms[4] and the number of calls, and clears the
+ * record.  Enabling (or disabling) also clears it.  Process-wide state: one
+ * benchmark at a time. */
+void cr_timing_enable(int32_t on);
+cr_status cr_timing_read(double* stage_ms, int64_t* n_calls);
+
+/* Algorithmic operation count of the IK stage-1 kernel, measured by replaying the
+ * kernel's own arithmetic on the host with an op-counting scalar over n sample
+ * seeds (k_init iterations plus the final evaluation each).
+ *   T_target [host] [n][12] (pose of each sample's problem), u_seed [host] [n][3n].
+ *   out [host] [8]: per seed {total flops, add/sub/mul, div, sqrt, sin/cos/atan2,
+ *   line-search trials}, then the flops of one normal-equation evaluation and of
+ *   one cost evaluation (first sample).  An FMA counts 2; div, sqrt and each
+ *   transcendental count 1.  Runs on the calling thread; no device work. */
+cr_status cr_ik_flop_tally(const cr_robot* robot, const cr_weights* weights, const cr_opts* opts, int64_t n,
+                           const double* T_target, const double* u_seed, double* out);
+
+/* Text for a status code, and the thread's last error message. */
+const char* cr_status_string(cr_status s);
+const char* cr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CR_SOLVER_H */

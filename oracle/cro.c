@@ -1016,9 +1016,9 @@ int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, 
   }
 
   int ncand = S;
-  int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)S);
+  int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)(S > o->n_final ? S : o->n_final));
   for (int s = 0; s < S; s++) cand[s] = s;
-  if (o->n_final > 0 && o->n_final < S) {
+  if (o->n_final > 0) {
     /* SelectTop: rank by the unweighted pose error (eq. 8) for IK, by the total
      * cost for path/trajectory; near-duplicate ties go to the lower collision penalty */
     double* e = (double*)malloc(sizeof(double) * (size_t)S);

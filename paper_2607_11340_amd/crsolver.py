@@ -1,0 +1,318 @@
+"""Python binding of libcrsolver.so (the gfx950 CR-Solver hot path).
+
+Argument marshalling only: every entry point checks shapes, dtypes and devices of
+torch tensors, then passes raw device pointers and the current HIP stream to the
+C ABI declared in include/cr_solver.h.  There is no CPU fallback: if the HIP
+library is missing the import of this module raises.
+
+Layouts are structure-of-arrays with the batch index fastest (see cr_solver.h):
+  u       [3n, B]          tendon displacements, row 3*i + j
+  poses   [12, B]          3x4 row-major [R | p]
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrsolver.so")
+MAX_SEG = 6
+
+CR_OK, CR_EINVAL, CR_ENOMEM, CR_EDEVICE, CR_EUNSUPPORTED = 0, 1, 2, 3, 4
+F32, F64 = 0, 1
+KIND = {"ik": 0, "path": 1, "traj": 2}
+SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
+
+EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_select_top",
+           "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_status_string", "cr_last_error")
+
+
+class CRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class _Robot(C.Structure):
+    _fields_ = [("n_seg", C.c_int32), ("pts_per_seg", C.c_int32),
+                ("L", C.c_double * MAX_SEG), ("r", C.c_double * MAX_SEG),
+                ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double)]
+
+
+class _Spheres(C.Structure):
+    _fields_ = [("n_sph", C.c_int32), ("per_problem", C.c_int32), ("sph", C.c_void_p), ("ld", C.c_int64)]
+
+
+class _Weights(C.Structure):
+    _fields_ = [(k, C.c_double) for k in (
+        "w_pos", "w_rot", "rho_lim", "rho_curv", "rho_coll", "margin", "rho_eq",
+        "w_len", "w_vel", "w_acc", "v_max", "a_max", "dt")]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("n_final", C.c_int32), ("k_init", C.c_int32), ("k_final", C.c_int32),
+                ("ls_max", C.c_int32), ("fp64_refine", C.c_int32), ("lambda0", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("dup_eps", C.c_double)]
+
+
+@dataclass
+class Robot:
+    """Piecewise-constant-curvature robot with three tendons per segment (Sec. III)."""
+    L: list
+    r: list
+    u_max: list
+    pts_per_seg: int = 10
+    theta_max: float = math.pi
+
+    @property
+    def n(self) -> int:
+        return len(self.L)
+
+    def c(self) -> _Robot:
+        s = _Robot()
+        s.n_seg, s.pts_per_seg = self.n, self.pts_per_seg
+        for i in range(self.n):
+            s.L[i], s.r[i], s.u_max[i] = self.L[i], self.r[i], self.u_max[i]
+        s.theta_max = self.theta_max
+        return s
+
+
+@dataclass
+class Weights:
+    """Weights of the penalised cost, eq. (17)."""
+    w_pos: float = 1.0
+    w_rot: float = 1.0
+    rho_lim: float = 1e6
+    rho_curv: float = 1e2
+    rho_coll: float = 1e6
+    margin: float = 1e-3
+    rho_eq: float = 1e4
+    w_len: float = 1.0
+    w_vel: float = 1.0
+    w_acc: float = 1.0
+    v_max: float = float("inf")
+    a_max: float = float("inf")
+    dt: float = 1.0
+
+    def c(self) -> _Weights:
+        return _Weights(*[float(getattr(self, k)) for k, _ in _Weights._fields_])
+
+
+@dataclass
+class Opts:
+    """Two-stage solver options (Algorithm 1) and LM damping."""
+    n_final: int = 8
+    k_init: int = 150
+    k_final: int = 50
+    ls_max: int = 4
+    fp64_refine: int = 1
+    lambda0: float = 1e-3
+    lambda_min: float = 1e-12
+    lambda_max: float = 1e12
+    dup_eps: float = 1e-3
+
+    def c(self) -> _Opts:
+        return _Opts(self.n_final, self.k_init, self.k_final, self.ls_max, self.fp64_refine,
+                     self.lambda0, self.lambda_min, self.lambda_max, self.dup_eps)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2607_11340_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    R, S, W, O = C.POINTER(_Robot), C.POINTER(_Spheres), C.POINTER(_Weights), C.POINTER(_Opts)
+    L.cr_fk.argtypes = [R, i64, vp, i64, vp, vp, vp, C.c_int, vp]
+    L.cr_cost_grad.argtypes = [i32, R, S, W, i64, i32, i32, vp, vp, vp, vp, vp, C.c_int, vp]
+    L.cr_solve_ik.argtypes = [R, S, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
+    L.cr_solve_ik_workspace.argtypes = [R, i64, i32, O, C.c_int]
+    L.cr_solve_ik_workspace.restype = C.c_size_t
+    L.cr_select_top.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, C.c_int, vp]
+    L.cr_timing_enable.argtypes = [i32]
+    L.cr_timing_enable.restype = None
+    L.cr_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.cr_ik_flop_tally.argtypes = [R, W, O, i64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]
+    L.cr_status_string.argtypes = [C.c_int]
+    L.cr_status_string.restype = C.c_char_p
+    L.cr_last_error.restype = C.c_char_p
+    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_select_top", "cr_timing_read", "cr_ik_flop_tally"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != CR_OK:
+        raise CRError(rc, lib.cr_last_error().decode())
+
+
+def _stream(t: torch.Tensor):
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dt(dtype) -> int:
+    if dtype in (torch.float32, "f32", F32):
+        return F32
+    if dtype in (torch.float64, "f64", F64):
+        return F64
+    raise ValueError(f"dtype {dtype} not supported")
+
+
+def _tdt(code: int):
+    return torch.float64 if code == F64 else torch.float32
+
+
+def _need(t, shape, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _spheres_c(spheres, dtype) -> _Spheres:
+    """spheres: None, or (tensor [4, M] shared) or (tensor [4, M*P], per_problem=True)."""
+    if spheres is None:
+        return _Spheres(0, 0, None, 0)
+    t, per_problem, M = spheres
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.shape[0] != 4:
+        raise ValueError("spheres must be a contiguous CUDA tensor [4, ld] of the call's dtype")
+    return _Spheres(int(M), 1 if per_problem else 0, C.c_void_p(t.data_ptr()), int(t.shape[1]))
+
+
+def fk(robot: Robot, u: torch.Tensor, arc=True, frames=True, points=False):
+    """Forward kinematics of B configurations u [3n, B]; returns a dict of
+    arc [3n, B], frames [12n, B], pts [3nK, B] (those requested)."""
+    dt = _dt(u.dtype)
+    n, B = robot.n, u.shape[1]
+    _need(u, (3 * n, B), u.dtype, "u")
+    out = {}
+    a = torch.empty((3 * n, B), dtype=u.dtype, device=u.device) if arc else None
+    f = torch.empty((12 * n, B), dtype=u.dtype, device=u.device) if frames else None
+    p = torch.empty((3 * n * robot.pts_per_seg, B), dtype=u.dtype, device=u.device) if points else None
+    rc = robot.c()
+    _check(lib.cr_fk(C.byref(rc), B, _ptr(u), B, _ptr(a), _ptr(f), _ptr(p), dt, _stream(u)))
+    if arc:
+        out["arc"] = a
+    if frames:
+        out["frames"] = f
+    if points:
+        out["pts"] = p
+    return out
+
+
+def ik_workspace_bytes(robot: Robot, P: int, S: int, opts: Opts, dtype) -> int:
+    rc, oc = robot.c(), opts.c()
+    return int(lib.cr_solve_ik_workspace(C.byref(rc), P, S, C.byref(oc), _dt(dtype)))
+
+
+def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,
+             opts: Opts = None, dtype=torch.float32, spheres=None, workspace: torch.Tensor = None, out=None):
+    """Two-stage IK (Algorithm 1).  T_target [12, P] float64, u_seed [3n, S*P] float64
+    (column p*S + s).  `dtype` is the stage-1 precision.  Returns (u [3n, P],
+    err [2, P] (position m, rotation rad), status [P] int32)."""
+    weights = weights or Weights()
+    opts = opts or Opts()
+    n = robot.n
+    P = T_target.shape[1]
+    S = u_seed.shape[1] // max(P, 1)
+    _need(T_target, (12, P), torch.float64, "T_target")
+    _need(u_seed, (3 * n, S * P), torch.float64, "u_seed")
+    dev = T_target.device
+    if out is None:
+        out = (torch.empty((3 * n, P), dtype=torch.float64, device=dev),
+               torch.empty((2, P), dtype=torch.float64, device=dev),
+               torch.empty((P,), dtype=torch.int32, device=dev))
+    u_out, err, st = out
+    rc, wc, oc = robot.c(), weights.c(), opts.c()
+    sc = _spheres_c(spheres, torch.float64)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    _check(lib.cr_solve_ik(C.byref(rc), C.byref(sc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc),
+                           C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype),
+                           _stream(T_target)))
+    return u_out, err, st
+
+
+def select_top(z: torch.Tensor, e: torch.Tensor, pen: torch.Tensor, failed, P: int, S: int, n_final: int,
+               dup_eps: float = 1e-3):
+    """SelectTop of Algorithm 1 per problem.  z [nz, S*P], e/pen [S*P], failed int32 [S*P]
+    or None.  Returns idx [n_final, P] int32 (seed index within its problem, -1 = empty)."""
+    dt = _dt(e.dtype)
+    nz = z.shape[0]
+    _need(z, (nz, S * P), e.dtype, "z")
+    _need(e, (S * P,), e.dtype, "e")
+    _need(pen, (S * P,), e.dtype, "pen")
+    if failed is not None:
+        _need(failed, (S * P,), torch.int32, "failed")
+    idx = torch.empty((n_final, P), dtype=torch.int32, device=e.device)
+    _check(lib.cr_select_top(P, S, nz, _ptr(z), _ptr(e), _ptr(pen), _ptr(failed), n_final, dup_eps,
+                             _ptr(idx), dt, _stream(e)))
+    return idx
+
+
+@dataclass
+class CostProblem:
+    """A batch of P problems x S seeds x (H+1) waypoints for cr_cost_grad.
+    task: IK [12, P] poses; PATH [12, (H+1)*P] reference poses (column p*(H+1)+t);
+    TRAJ [6n, P] (u_start then u_goal).  spheres: None or (tensor [4, ld], per_problem, M)."""
+    robot: Robot
+    kind: str
+    P: int
+    S: int
+    H: int
+    task: torch.Tensor
+    weights: Weights = field(default_factory=Weights)
+    spheres: tuple = None
+
+
+def cost_grad(pb: CostProblem, u: torch.Tensor, grad: bool = True, grad_scale: torch.Tensor = None):
+    """Penalised cost (eq. 17) per seed [S*P] and, if grad, dC/du like u [3n, (H+1)*S*P]."""
+    dt = _dt(u.dtype)
+    n, T = pb.robot.n, pb.H + 1
+    B = pb.P * pb.S * T
+    _need(u, (3 * n, B), u.dtype, "u")
+    if pb.task.dtype != u.dtype:
+        raise ValueError("task must have the dtype of u")
+    cost = torch.empty((pb.S * pb.P,), dtype=u.dtype, device=u.device)
+    g = torch.empty_like(u) if grad else None
+    if grad_scale is not None:
+        _need(grad_scale, (pb.S * pb.P,), u.dtype, "grad_scale")
+    rc, wc = pb.robot.c(), pb.weights.c()
+    sc = _spheres_c(pb.spheres, u.dtype)
+    _check(lib.cr_cost_grad(KIND[pb.kind], C.byref(rc), C.byref(sc), C.byref(wc), pb.P, pb.H, pb.S,
+                            _ptr(pb.task), _ptr(u), _ptr(cost), _ptr(g), _ptr(grad_scale), dt, _stream(u)))
+    return (cost, g) if grad else cost
+
+
+class CostGrad(torch.autograd.Function):
+    """cost = CostGrad.apply(u, problem): forward evaluates the cost only; backward
+    recomputes the transforms and runs the adjoint kernel, scaled per seed by the
+    upstream gradient inside the kernel.  Only u is saved."""
+
+    @staticmethod
+    def forward(ctx, u, problem):
+        ctx.problem = problem
+        ctx.save_for_backward(u)
+        return cost_grad(problem, u.detach(), grad=False)
+
+    @staticmethod
+    def backward(ctx, gcost):
+        (u,) = ctx.saved_tensors
+        _, g = cost_grad(ctx.problem, u.detach(), grad=True, grad_scale=gcost.contiguous())
+        return g, None

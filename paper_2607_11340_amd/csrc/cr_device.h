@@ -1,0 +1,953 @@
+// cr_device.h -- device-side kinematics, cost and Levenberg-Marquardt pieces for
+// gfx950.  Everything is templated on the arithmetic type T (float or double) and,
+// where the segment count sizes register arrays, on NS (1..6) so that per-seed
+// state lives in VGPRs with compile-time indexing.
+//
+// Coordinates: each segment i is described by its bending coordinates
+// (a_i, b_i) = theta_i (cos phi_i, sin phi_i) (Sec. III-A, q = (theta, phi, L) with
+// L fixed); tendon displacements u map to them linearly through eq. (4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cr_solver.h"
+
+// Device functions are also compiled for the host so that the same arithmetic
+// can be replayed with an op-counting scalar (algorithmic flop accounting).
+#define CR_HD __host__ __device__ __forceinline__
+
+namespace crk {
+
+// ---------------------------------------------------------------------------
+// Parameters in the kernel's arithmetic type (passed by value as kernel args).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct RobotT {
+  int n, K;
+  T L[CR_MAX_SEG], r[CR_MAX_SEG], umax[CR_MAX_SEG];
+  T theta_max;
+};
+
+template <typename T>
+struct WeightsT {
+  T w_pos, w_rot;      // pose residual weights
+  T sq_lim, sq_curv;   // square roots of the bound penalties (residual scales)
+  T sq_coll, margin;
+  T sq_eq, sq_len, sq_vel, sq_acc;
+  T v_max, a_max, dt;
+  int has_vmax, has_amax;
+};
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+CR_HD T tsqrt(T x);
+template <>
+CR_HD float tsqrt<float>(float x) { return sqrtf(x); }
+template <>
+CR_HD double tsqrt<double>(double x) { return sqrt(x); }
+
+template <typename T>
+CR_HD T tatan2(T y, T x);
+template <>
+CR_HD float tatan2<float>(float y, float x) { return atan2f(y, x); }
+template <>
+CR_HD double tatan2<double>(double y, double x) { return atan2(y, x); }
+
+template <typename T>
+CR_HD void tsincos(T x, T* s, T* c);
+template <>
+CR_HD void tsincos<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <>
+CR_HD void tsincos<double>(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename T>
+CR_HD bool tfinite(T x) {
+  return __builtin_isfinite(x);
+}
+
+template <typename T>
+CR_HD void cross3(const T* a, const T* b, T* c) {
+  T c0 = a[1] * b[2] - a[2] * b[1];
+  T c1 = a[2] * b[0] - a[0] * b[2];
+  T c2 = a[0] * b[1] - a[1] * b[0];
+  c[0] = c0;
+  c[1] = c1;
+  c[2] = c2;
+}
+template <typename T>
+CR_HD T dot3(const T* a, const T* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+// y = M x  (row-major 3x3)
+template <typename T>
+CR_HD void mv3(const T* M, const T* x, T* y) {
+  T y0 = M[0] * x[0] + M[1] * x[1] + M[2] * x[2];
+  T y1 = M[3] * x[0] + M[4] * x[1] + M[5] * x[2];
+  T y2 = M[6] * x[0] + M[7] * x[1] + M[8] * x[2];
+  y[0] = y0;
+  y[1] = y1;
+  y[2] = y2;
+}
+// y = M^T x
+template <typename T>
+CR_HD void mtv3(const T* M, const T* x, T* y) {
+  T y0 = M[0] * x[0] + M[3] * x[1] + M[6] * x[2];
+  T y1 = M[1] * x[0] + M[4] * x[1] + M[7] * x[2];
+  T y2 = M[2] * x[0] + M[5] * x[1] + M[8] * x[2];
+  y[0] = y0;
+  y[1] = y1;
+  y[2] = y2;
+}
+// C = A B
+template <typename T>
+CR_HD void mm3(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// ---------------------------------------------------------------------------
+// Power series in s = theta^2.  (-1)^k / (2k + OFF)!  evaluated by Horner.
+// ---------------------------------------------------------------------------
+
+constexpr double inv_factorial(int m) {
+  double f = 1.0;
+  for (int i = 2; i <= m; ++i) f *= (double)i;
+  return 1.0 / f;
+}
+constexpr double alt_coef(int k, int off) { return ((k & 1) ? -1.0 : 1.0) * inv_factorial(2 * k + off); }
+
+// sum_{k<NT} alt_coef(k, OFF) s^k
+template <typename T, int OFF, int NT>
+CR_HD T alt_series(T s) {
+  T acc = T(alt_coef(NT - 1, OFF));
+#pragma unroll
+  for (int k = NT - 2; k >= 0; --k) acc = acc * s + T(alt_coef(k, OFF));
+  return acc;
+}
+// d/ds of the above
+template <typename T, int OFF, int NT>
+CR_HD T alt_series_d(T s) {
+  T acc = T((NT - 1) * alt_coef(NT - 1, OFF));
+#pragma unroll
+  for (int k = NT - 2; k >= 1; --k) acc = acc * s + T(k * alt_coef(k, OFF));
+  return acc;
+}
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<float> {
+  static constexpr int NT = 7;           // series terms for s < 1
+  static constexpr int NG = 5;           // gamma series terms
+  static constexpr float g_switch = 1.0f;
+};
+template <>
+struct Prec<double> {
+  static constexpr int NT = 10;
+  static constexpr int NG = 8;
+  static constexpr double g_switch = 0.25;
+};
+
+// Arc coefficients of Rodrigues' formula for the in-plane rotation vector
+// w = (-b, a, 0), |w| = theta, s = theta^2:
+//   A = (1 - cos theta)/s,  B = sin(theta)/theta,  C = (theta - sin theta)/theta^3
+// and the s-derivatives A', B'.  Series below s = 1 (no cancellation), closed
+// forms above.
+template <typename T>
+struct ArcCoef {
+  T A, B, C, Ap, Bp;
+};
+
+template <typename T, bool DERIV>
+CR_HD ArcCoef<T> arc_coef(T s) {
+  constexpr int NT = Prec<T>::NT;
+  ArcCoef<T> c;
+  if (s < T(1)) {
+    c.A = alt_series<T, 2, NT>(s);
+    c.B = alt_series<T, 1, NT>(s);
+    if (DERIV) {
+      c.C = alt_series<T, 3, NT>(s);
+      c.Ap = alt_series_d<T, 2, NT>(s);
+      c.Bp = alt_series_d<T, 1, NT>(s);
+    }
+  } else {
+    T th = tsqrt(s), sh, ch;
+    tsincos(T(0.5) * th, &sh, &ch);
+    T inv_s = T(1) / s;
+    c.A = T(2) * sh * sh * inv_s;
+    c.B = T(2) * sh * ch / th;
+    if (DERIV) {
+      T cth = ch * ch - sh * sh;
+      c.C = (T(1) - c.B) * inv_s;
+      c.Ap = (T(0.5) * c.B - c.A) * inv_s;
+      c.Bp = T(0.5) * (cth - c.B) * inv_s;
+    }
+  }
+  return c;
+}
+
+// gamma(q) = (1 - (theta/2) cot(theta/2)) / q and dgamma/dq, q = theta^2: the
+// [w]_x^2 coefficient of the inverse left Jacobian V^-1 = I - [w]_x/2 + gamma [w]_x^2.
+// Series: gamma = sum_{k>=1} |B_2k| q^(k-1) / (2k)! (Bernoulli numbers).
+CR_HD constexpr double bern_gamma_coef(int k) {
+  // |B_2k| / (2k)!, k = 1..9
+  return k == 1   ? (1.0 / 6.0) * inv_factorial(2)
+         : k == 2 ? (1.0 / 30.0) * inv_factorial(4)
+         : k == 3 ? (1.0 / 42.0) * inv_factorial(6)
+         : k == 4 ? (1.0 / 30.0) * inv_factorial(8)
+         : k == 5 ? (5.0 / 66.0) * inv_factorial(10)
+         : k == 6 ? (691.0 / 2730.0) * inv_factorial(12)
+         : k == 7 ? (7.0 / 6.0) * inv_factorial(14)
+         : k == 8 ? (3617.0 / 510.0) * inv_factorial(16)
+                  : (43867.0 / 798.0) * inv_factorial(18);
+}
+
+template <typename T, bool DERIV>
+CR_HD void gamma_coef(T q, T* gam, T* dgam) {
+  constexpr int NG = Prec<T>::NG;
+  if (q < T(Prec<T>::g_switch)) {
+    T acc = T(bern_gamma_coef(NG));
+#pragma unroll
+    for (int k = NG - 1; k >= 1; --k) acc = acc * q + T(bern_gamma_coef(k));
+    *gam = acc;
+    if (DERIV) {
+      T d = T((NG - 1) * bern_gamma_coef(NG));
+#pragma unroll
+      for (int k = NG - 1; k >= 2; --k) d = d * q + T((k - 1) * bern_gamma_coef(k));
+      *dgam = d;
+    }
+  } else {
+    T th = tsqrt(q), sh, ch;
+    tsincos(T(0.5) * th, &sh, &ch);
+    T cot = ch / sh;
+    T h = T(0.5) * th * cot;
+    T g = (T(1) - h) / q;
+    *gam = g;
+    if (DERIV) {
+      T dh = T(0.5) * cot - T(0.25) * th / (sh * sh);
+      *dgam = (-dh / (T(2) * th) - g) / q;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tendon map (eq. 4) for three tendons at 0, 120, 240 degrees:
+//   u_j = -r (a cos alpha_j + b sin alpha_j)
+//   a = (u_2 + u_3 - 2 u_1) / (3 r),  b = (u_3 - u_2) / (sqrt(3) r)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+CR_HD void u_to_ab(T u0, T u1, T u2, T r, T* a, T* b) {
+  *a = (u1 + u2 - T(2) * u0) / (T(3) * r);
+  *b = (u2 - u1) / (T(1.7320508075688772935) * r);
+}
+
+template <typename T>
+CR_HD void ab_to_u(T a, T b, T r, T* u) {
+  const T h3 = T(0.86602540378443864676);  // sqrt(3)/2
+  u[0] = -r * a;
+  u[1] = r * (T(0.5) * a - h3 * b);
+  u[2] = r * (T(0.5) * a + h3 * b);
+}
+
+// d u_j / d(a, b)
+template <typename T>
+CR_HD void lift_row(int j, T r, T* da, T* db) {
+  const T h3 = T(0.86602540378443864676);
+  *da = j == 0 ? -r : T(0.5) * r;
+  *db = j == 0 ? T(0) : (j == 1 ? -h3 * r : h3 * r);
+}
+
+// ---------------------------------------------------------------------------
+// Segment transform (eq. 1-3):  R = I + B [w]_x + A [w]_x^2,  w = (-b, a, 0),
+// d = L (A a, A b, B).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+CR_HD void seg_R_d(T a, T b, T L, const ArcCoef<T>& c, T* R, T* d) {
+  T s = a * a + b * b;
+  T Aab = c.A * a * b;
+  R[0] = T(1) - c.A * a * a;
+  R[1] = -Aab;
+  R[2] = c.B * a;
+  R[3] = -Aab;
+  R[4] = T(1) - c.A * b * b;
+  R[5] = c.B * b;
+  R[6] = -c.B * a;
+  R[7] = -c.B * b;
+  R[8] = T(1) - c.A * s;
+  d[0] = L * c.A * a;
+  d[1] = L * c.A * b;
+  d[2] = L * c.B;
+}
+
+// Value-only chain of NS segments: tip rotation Rc and position pc.
+template <int NS, typename T>
+CR_HD void fk_tip(const RobotT<T>& rb, const T* z, T* Rc, T* pc) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
+  pc[0] = pc[1] = pc[2] = T(0);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    T a = z[2 * i], b = z[2 * i + 1];
+    ArcCoef<T> c = arc_coef<T, false>(a * a + b * b);
+    T Ri[9], di[3], q[3], Rn[9];
+    seg_R_d(a, b, rb.L[i], c, Ri, di);
+    mv3(Rc, di, q);
+    pc[0] += q[0];
+    pc[1] += q[1];
+    pc[2] += q[2];
+    mm3(Rc, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SE(3) logarithm of E = [Re | te] (eq. 8, 16, 18):
+//   w = Log_SO3(Re), rho = V^-1(w) te.
+// ---------------------------------------------------------------------------
+
+template <typename T, bool DERIV>
+CR_HD void log_se3(const T* Re, const T* te, T* w, T* rho, T* gam, T* dgam) {
+  T c = T(0.5) * (Re[0] + Re[4] + Re[8] - T(1));
+  T v[3] = {T(0.5) * (Re[7] - Re[5]), T(0.5) * (Re[2] - Re[6]), T(0.5) * (Re[3] - Re[1])};
+  T x = dot3(v, v);  // sin^2(theta)
+  if (c > T(-0.9)) {
+    T f;
+    if (c > T(0) && x < T(1e-8)) {
+      f = T(1) + x * (T(1.0 / 6.0) + x * T(3.0 / 40.0));  // theta / sin(theta)
+    } else {
+      T sn = tsqrt(x);
+      f = tatan2(sn, c) / sn;
+    }
+    w[0] = f * v[0];
+    w[1] = f * v[1];
+    w[2] = f * v[2];
+  } else {
+    // near pi: (Re + Re^T)/2 = c I + (1 - c) n n^T; axis from the largest diagonal
+    T inv = T(1) / (T(1) - c);
+    T d0 = (Re[0] - c) * inv, d1 = (Re[4] - c) * inv, d2 = (Re[8] - c) * inv;
+    T n[3];
+    if (d0 >= d1 && d0 >= d2) {
+      T s = tsqrt(d0);
+      n[0] = s;
+      n[1] = T(0.5) * (Re[1] + Re[3]) * inv / s;
+      n[2] = T(0.5) * (Re[2] + Re[6]) * inv / s;
+    } else if (d1 >= d2) {
+      T s = tsqrt(d1);
+      n[0] = T(0.5) * (Re[1] + Re[3]) * inv / s;
+      n[1] = s;
+      n[2] = T(0.5) * (Re[5] + Re[7]) * inv / s;
+    } else {
+      T s = tsqrt(d2);
+      n[0] = T(0.5) * (Re[2] + Re[6]) * inv / s;
+      n[1] = T(0.5) * (Re[5] + Re[7]) * inv / s;
+      n[2] = s;
+    }
+    T sn = dot3(n, v);
+    bool flip = sn < T(0);
+    if (sn == T(0)) flip = (n[0] != T(0)) ? (n[0] < T(0)) : ((n[1] != T(0)) ? (n[1] < T(0)) : (n[2] < T(0)));
+    if (flip) {
+      n[0] = -n[0];
+      n[1] = -n[1];
+      n[2] = -n[2];
+      sn = -sn;
+    }
+    T th = tatan2(sn, c);
+    w[0] = th * n[0];
+    w[1] = th * n[1];
+    w[2] = th * n[2];
+  }
+  T g, dg = T(0);
+  gamma_coef<T, DERIV>(dot3(w, w), &g, &dg);
+  T u1[3], u2[3];
+  cross3(w, te, u1);
+  cross3(w, u1, u2);
+  rho[0] = te[0] - T(0.5) * u1[0] + g * u2[0];
+  rho[1] = te[1] - T(0.5) * u1[1] + g * u2[1];
+  rho[2] = te[2] - T(0.5) * u1[2] + g * u2[2];
+  *gam = g;
+  if (DERIV) *dgam = dg;
+}
+
+// Re = R^T Rt, te = R^T (pt - p) for a target pose T[12] (3x4 row-major).
+template <typename T>
+CR_HD void relative_pose(const T* R, const T* p, const T* Tt, T* Re, T* te) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Re[3 * i + j] = R[i] * Tt[j] + R[3 + i] * Tt[4 + j] + R[6 + i] * Tt[8 + j];
+  T dp[3] = {Tt[3] - p[0], Tt[7] - p[1], Tt[11] - p[2]};
+  mtv3(R, dp, te);
+}
+
+// ---------------------------------------------------------------------------
+// Bound penalties shared by every task (eq. 9): tendon hinge and bending hinge.
+// ---------------------------------------------------------------------------
+
+template <int NS, typename T>
+CR_HD T bounds_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* z) {
+  T c = T(0);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    T a = z[2 * i], b = z[2 * i + 1];
+    T u[3];
+    ab_to_u(a, b, rb.r[i], u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T viol = fabs(u[j]) - rb.umax[i];
+      if (viol > T(0)) {
+        T rr = w.sq_lim * viol;
+        c += T(0.5) * rr * rr;
+      }
+    }
+    T th = tsqrt(a * a + b * b);
+    T vt = th - rb.theta_max;
+    if (vt > T(0)) {
+      T rr = w.sq_curv * vt;
+      c += T(0.5) * rr * rr;
+    }
+  }
+  return c;
+}
+
+// packed lower-triangular index
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Adds the bound rows to cost, g = J^T r and H = J^T J (packed lower) for one configuration.
+// `off` is the column offset of this configuration's (a, b) block.
+template <int NS, int NZT, typename T>
+CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, int off,
+                                                 T* Hp, T* g, T& cost) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    T a = z[2 * i], b = z[2 * i + 1];
+    T u[3];
+    ab_to_u(a, b, rb.r[i], u);
+    const int ca = off + 2 * i, cb = off + 2 * i + 1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T viol = fabs(u[j]) - rb.umax[i];
+      if (viol > T(0)) {
+        T rr = w.sq_lim * viol;
+        T sg = u[j] < T(0) ? -w.sq_lim : w.sq_lim;
+        T ja, jb;
+        lift_row(j, rb.r[i], &ja, &jb);
+        ja *= sg;
+        jb *= sg;
+        cost += T(0.5) * rr * rr;
+        g[ca] += ja * rr;
+        g[cb] += jb * rr;
+        Hp[tri(ca, ca)] += ja * ja;
+        Hp[tri(cb, ca)] += jb * ja;
+        Hp[tri(cb, cb)] += jb * jb;
+      }
+    }
+    T th = tsqrt(a * a + b * b);
+    T vt = th - rb.theta_max;
+    if (vt > T(0)) {
+      T rr = w.sq_curv * vt;
+      T ja = w.sq_curv * a / th, jb = w.sq_curv * b / th;
+      cost += T(0.5) * rr * rr;
+      g[ca] += ja * rr;
+      g[cb] += jb * rr;
+      Hp[tri(ca, ca)] += ja * ja;
+      Hp[tri(cb, ca)] += jb * ja;
+      Hp[tri(cb, cb)] += jb * jb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// IK cost (value) and Gauss-Newton normal equations for one configuration.
+// ---------------------------------------------------------------------------
+
+// Pose part: returns 1/2 |(w_pos rho, w_rot w)|^2; optionally the unweighted |log|.
+template <int NS, typename T>
+CR_HD T ik_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z,
+                                     T* e_out) {
+  T Rc[9], pc[3], Re[9], te[3], om[3], rho[3], gam, dg;
+  fk_tip<NS>(rb, z, Rc, pc);
+  relative_pose(Rc, pc, Tt, Re, te);
+  log_se3<T, false>(Re, te, om, rho, &gam, &dg);
+  T r2 = w.w_pos * w.w_pos * dot3(rho, rho) + w.w_rot * w.w_rot * dot3(om, om);
+  if (e_out) *e_out = tsqrt(dot3(rho, rho) + dot3(om, om));
+  return T(0.5) * r2 + bounds_cost<NS>(rb, w, z);
+}
+
+// Normal equations H = J^T J (packed lower, 2NS x 2NS), g = J^T r and cost at z.
+//
+// Pose Jacobian: a change of z_k moves the tip by the spatial twist
+// (W_k, dp_k) with W_k = R_{0,i-1} J_l(w_i) e_k' and dp_k = R_{0,i-1} dd_i/dz_k
+// + W_k x (p_ee - p_{0,i}); in the tip frame that is (Jv, Jw) = R_ee^T (dp, W).
+// With E = T_ee^-1 T_t and E -> exp(-xi) E, the log changes by
+//   dw = -V^-1 Jw,  drho = -V^-1 (Jv - t x Jw) - N V^-1 Jw,
+//   N y = y x... = t x y / 2 + 2 gamma' (w . y) (w x (w x t)) - gamma (w x t) x y - gamma w x (t x y).
+template <int NS, typename T>
+CR_HD T ik_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z,
+                                          T* Hp, T* g) {
+  constexpr int NZ = 2 * NS;
+  T Rc[9], pc[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
+  pc[0] = pc[1] = pc[2] = T(0);
+  T Wc[NZ][3], Pc[NZ][3], Pi[NS][3];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    T a = z[2 * i], b = z[2 * i + 1];
+    ArcCoef<T> c = arc_coef<T, true>(a * a + b * b);
+    T Ri[9], di[3];
+    seg_R_d(a, b, rb.L[i], c, Ri, di);
+    const T L = rb.L[i];
+    // rotation-vector derivatives pushed to the parent frame: R_i J_r = J_l
+    T wa[3] = {-c.C * a * b, T(1) - c.C * b * b, -c.A * b};
+    T wb[3] = {c.C * a * a - T(1), c.C * a * b, c.A * a};
+    T dda[3] = {L * (c.A + T(2) * a * a * c.Ap), L * T(2) * a * b * c.Ap, L * T(2) * a * c.Bp};
+    T ddb[3] = {L * T(2) * a * b * c.Ap, L * (c.A + T(2) * b * b * c.Ap), L * T(2) * b * c.Bp};
+    mv3(Rc, wa, Wc[2 * i]);
+    mv3(Rc, wb, Wc[2 * i + 1]);
+    mv3(Rc, dda, Pc[2 * i]);
+    mv3(Rc, ddb, Pc[2 * i + 1]);
+    T q[3], Rn[9];
+    mv3(Rc, di, q);
+    pc[0] += q[0];
+    pc[1] += q[1];
+    pc[2] += q[2];
+    mm3(Rc, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+    Pi[i][0] = pc[0];
+    Pi[i][1] = pc[1];
+    Pi[i][2] = pc[2];
+  }
+  T Re[9], te[3], om[3], rho[3], gam, dgam;
+  relative_pose(Rc, pc, Tt, Re, te);
+  log_se3<T, true>(Re, te, om, rho, &gam, &dgam);
+  T r[6] = {w.w_pos * rho[0], w.w_pos * rho[1], w.w_pos * rho[2],
+            w.w_rot * om[0],  w.w_rot * om[1],  w.w_rot * om[2]};
+  T cost = T(0.5) * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
+  T u1[3], u2[3];
+  cross3(om, te, u1);
+  cross3(om, u1, u2);
+  T J[NZ][6];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    const int i = k / 2;
+    T rel[3] = {pc[0] - Pi[i][0], pc[1] - Pi[i][1], pc[2] - Pi[i][2]};
+    T dp[3], Jv[3], Jw[3];
+    cross3(Wc[k], rel, dp);
+    dp[0] += Pc[k][0];
+    dp[1] += Pc[k][1];
+    dp[2] += Pc[k][2];
+    mtv3(Rc, dp, Jv);
+    mtv3(Rc, Wc[k], Jw);
+    // y = V^-1 Jw
+    T t1[3], t2[3], y[3];
+    cross3(om, Jw, t1);
+    cross3(om, t1, t2);
+    y[0] = Jw[0] - T(0.5) * t1[0] + gam * t2[0];
+    y[1] = Jw[1] - T(0.5) * t1[1] + gam * t2[1];
+    y[2] = Jw[2] - T(0.5) * t1[2] + gam * t2[2];
+    // x = Jv - t x Jw ; Vx = V^-1 x
+    T x[3], Vx[3];
+    cross3(te, Jw, t1);
+    x[0] = Jv[0] - t1[0];
+    x[1] = Jv[1] - t1[1];
+    x[2] = Jv[2] - t1[2];
+    cross3(om, x, t1);
+    cross3(om, t1, t2);
+    Vx[0] = x[0] - T(0.5) * t1[0] + gam * t2[0];
+    Vx[1] = x[1] - T(0.5) * t1[1] + gam * t2[1];
+    Vx[2] = x[2] - T(0.5) * t1[2] + gam * t2[2];
+    // N y
+    T ty[3], u1y[3], wty[3];
+    cross3(te, y, ty);
+    cross3(u1, y, u1y);
+    cross3(om, ty, wty);
+    T s2 = T(2) * dgam * dot3(om, y);
+    T Ny[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Ny[m] = T(0.5) * ty[m] + s2 * u2[m] - gam * (u1y[m] + wty[m]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      J[k][m] = -w.w_pos * (Vx[m] + Ny[m]);
+      J[k][3 + m] = -w.w_rot * y[m];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc += J[k][m] * r[m];
+    g[k] = acc;
+#pragma unroll
+    for (int l = 0; l <= k; ++l) {
+      T h = T(0);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) h += J[k][m] * J[l][m];
+      Hp[tri(k, l)] = h;
+    }
+  }
+  bounds_normal_eq<NS, NZ>(rb, w, z, 0, Hp, g, cost);
+  return cost;
+}
+
+// ---------------------------------------------------------------------------
+// Dense Cholesky solve of a packed lower SPD matrix in registers.
+// Returns false on a non-positive (or non-finite) pivot.
+// ---------------------------------------------------------------------------
+
+template <int N, typename T>
+CR_HD bool chol_solve(T* A, T* x) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    T d = A[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= A[tri(j, k)] * A[tri(j, k)];
+    ok = ok && (d > T(0));
+    T ljj = tsqrt(d > T(0) ? d : T(1));
+    T inv = T(1) / ljj;
+    A[tri(j, j)] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      T v = A[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= A[tri(i, k)] * A[tri(j, k)];
+      A[tri(i, j)] = v * inv;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    T v = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= A[tri(i, k)] * x[k];
+    x[i] = v / A[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    T v = x[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) v -= A[tri(k, i)] * x[k];
+    x[i] = v / A[tri(i, i)];
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Levenberg-Marquardt with backtracking line search on one IK seed (Sec. IV-C):
+//   (H + lambda D) delta = -g, D = diag(max(H_jj, 1e-12));
+//   first alpha in 1, 1/2, ... with cost(z + alpha delta) <= cost + 1e-4 alpha g.delta;
+//   lambda /= 10 when the full step is taken, *= 10 when every trial fails.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct LMOpts {
+  int ls_max;
+  T lam_min, lam_max;
+};
+
+template <int NS, typename T>
+CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam,
+                                      int iters, const LMOpts<T>& o, bool& failed, int& trials) {
+  constexpr int NZ = 2 * NS;
+  constexpr int NP = NZ * (NZ + 1) / 2;
+  for (int it = 0; it < iters; ++it) {
+    T Hp[NP], g[NZ], dl[NZ];
+    T c0 = ik_normal_eq<NS>(rb, w, Tt, z, Hp, g);
+    if (!tfinite(c0)) {
+      failed = true;
+      break;
+    }
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      T hj = Hp[tri(j, j)];
+      Hp[tri(j, j)] = hj + lam * (hj > T(1e-12) ? hj : T(1e-12));
+      dl[j] = -g[j];
+    }
+    if (!chol_solve<NZ>(Hp, dl)) {
+      lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
+      continue;
+    }
+    T gd = T(0);
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) gd += g[j] * dl[j];
+    T alpha = T(1);
+    int acc = -1;
+    T zt[NZ];
+    for (int tr = 0; tr < o.ls_max; ++tr) {
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
+      T c = ik_cost<NS>(rb, w, Tt, zt, (T*)nullptr);
+      ++trials;
+      if (c <= c0 + T(1e-4) * alpha * gd) {
+        acc = tr;
+        break;
+      }
+      alpha *= T(0.5);
+    }
+    if (acc >= 0) {
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) z[j] = zt[j];
+      if (acc == 0) lam = lam / T(10) > o.lam_min ? lam / T(10) : o.lam_min;
+    } else {
+      lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
+    }
+  }
+}
+
+}  // namespace crk
+
+// ===========================================================================
+// Cost and gradient by adjoint sweep (eq. 8-17) for one configuration.
+//
+// Forward pass: chain the segments, keep for every segment j and coordinate k
+// the spatial twist column (W_jk, Pd_jk) -- the rotation axis rate and the
+// displacement rate of segment j's end -- and the end position pe_j.  A force f
+// applied at a point x distal to segment j's end contributes
+//   dC/dz_jk = W_jk . ((x - pe_j) x f) + Pd_jk . f,
+// so every distal force/torque can be accumulated into one wrench per segment
+// (force, moment about the origin) and swept back from the tip in O(n).
+// Backbone points inside segment j add their own-arc term directly.
+// ===========================================================================
+
+namespace crk {
+
+template <int NS, typename T>
+struct Fwd {
+  T W[2 * NS][3], Pd[2 * NS][3], pe[NS][3];  // twist columns and segment ends
+  T R[9], p[3];                              // tip frame
+  T F[NS][3], Mo[NS][3];                     // force and moment about the origin from points of segment i
+  T gz[2 * NS];                              // direct gradient terms (own arc, bounds)
+};
+
+// Sphere m, component c (cx, cy, cz, radius) is read as sph[m * ms + c * cs].
+template <int NS, typename T, bool GRAD>
+CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const T* sph, int M, int64_t ms,
+                       int64_t cs, Fwd<NS, T>& f) {
+  T cost = T(0);
+  T Rc[9], pc[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
+  pc[0] = pc[1] = pc[2] = T(0);
+  if (GRAD) {
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) f.gz[k] = T(0);
+  }
+  const int K = rb.K;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const T a = z[2 * i], b = z[2 * i + 1], L = rb.L[i];
+    const T s = a * a + b * b;
+    if (GRAD) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f.F[i][c] = f.Mo[i][c] = T(0);
+    }
+    // backbone points of this segment against every sphere (eq. 10)
+    if (M > 0) {
+      const T ri = rb.r[i];
+      for (int k = 1; k <= K; ++k) {
+        const T sg = T(k) / T(K);
+        ArcCoef<T> ck = arc_coef<T, GRAD>(sg * sg * s);
+        const T sa = sg * a, sb = sg * b, sL = sg * L;
+        T dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+        T x[3];
+        mv3(Rc, dk, x);
+        x[0] += pc[0];
+        x[1] += pc[1];
+        x[2] += pc[2];
+        T fx[3] = {T(0), T(0), T(0)};
+        bool any = false;
+        for (int m = 0; m < M; ++m) {
+          const T* sm = sph + m * ms;
+          const T d0 = x[0] - sm[0], d1 = x[1] - sm[cs], d2 = x[2] - sm[2 * cs];
+          const T reach = sm[3 * cs] + ri + w.margin;
+          const T d2s = d0 * d0 + d1 * d1 + d2 * d2;
+          if (d2s < reach * reach) {
+            const T dist = tsqrt(d2s);
+            const T viol = reach - dist;  // margin - (dist - R - r)
+            const T rr = w.sq_coll * viol;
+            cost += T(0.5) * rr * rr;
+            if (GRAD) {
+              // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
+              const T sc = dist > T(0) ? -w.sq_coll * rr / dist : T(0);
+              fx[0] += sc * d0;
+              fx[1] += sc * d1;
+              fx[2] += dist > T(0) ? sc * d2 : -w.sq_coll * rr;
+              any = true;
+            }
+          }
+        }
+        if (GRAD && any) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) f.F[i][c] += fx[c];
+          T mx[3];
+          cross3(x, fx, mx);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) f.Mo[i][c] += mx[c];
+          // own arc: x = pc + Rc d(sg a, sg b, sg L)
+          T q[3];
+          mtv3(Rc, fx, q);
+          const T dda[3] = {sL * (ck.A + T(2) * sa * sa * ck.Ap), sL * T(2) * sa * sb * ck.Ap, sL * T(2) * sa * ck.Bp};
+          const T ddb[3] = {sL * T(2) * sa * sb * ck.Ap, sL * (ck.A + T(2) * sb * sb * ck.Ap), sL * T(2) * sb * ck.Bp};
+          f.gz[2 * i] += sg * dot3(q, dda);
+          f.gz[2 * i + 1] += sg * dot3(q, ddb);
+        }
+      }
+    }
+    ArcCoef<T> c = arc_coef<T, GRAD>(s);
+    T Ri[9], di[3];
+    seg_R_d(a, b, L, c, Ri, di);
+    if (GRAD) {
+      T wa[3] = {-c.C * a * b, T(1) - c.C * b * b, -c.A * b};
+      T wb[3] = {c.C * a * a - T(1), c.C * a * b, c.A * a};
+      T dda[3] = {L * (c.A + T(2) * a * a * c.Ap), L * T(2) * a * b * c.Ap, L * T(2) * a * c.Bp};
+      T ddb[3] = {L * T(2) * a * b * c.Ap, L * (c.A + T(2) * b * b * c.Ap), L * T(2) * b * c.Bp};
+      mv3(Rc, wa, f.W[2 * i]);
+      mv3(Rc, wb, f.W[2 * i + 1]);
+      mv3(Rc, dda, f.Pd[2 * i]);
+      mv3(Rc, ddb, f.Pd[2 * i + 1]);
+    }
+    T q[3], Rn[9];
+    mv3(Rc, di, q);
+    pc[0] += q[0];
+    pc[1] += q[1];
+    pc[2] += q[2];
+    mm3(Rc, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+    if (GRAD) {
+      f.pe[i][0] = pc[0];
+      f.pe[i][1] = pc[1];
+      f.pe[i][2] = pc[2];
+    }
+    // bounds (eq. 9): tendon hinge and bending hinge
+    T u[3];
+    ab_to_u(a, b, rb.r[i], u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T viol = fabs(u[j]) - rb.umax[i];
+      if (viol > T(0)) {
+        const T rr = w.sq_lim * viol;
+        cost += T(0.5) * rr * rr;
+        if (GRAD) {
+          T ja, jb;
+          lift_row(j, rb.r[i], &ja, &jb);
+          const T sgn = u[j] < T(0) ? -w.sq_lim : w.sq_lim;
+          f.gz[2 * i] += sgn * ja * rr;
+          f.gz[2 * i + 1] += sgn * jb * rr;
+        }
+      }
+    }
+    const T th = tsqrt(s);
+    const T vt = th - rb.theta_max;
+    if (vt > T(0)) {
+      const T rr = w.sq_curv * vt;
+      cost += T(0.5) * rr * rr;
+      if (GRAD) {
+        f.gz[2 * i] += w.sq_curv * a / th * rr;
+        f.gz[2 * i + 1] += w.sq_curv * b / th * rr;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) f.R[k] = Rc[k];
+  f.p[0] = pc[0];
+  f.p[1] = pc[1];
+  f.p[2] = pc[2];
+  return cost;
+}
+
+// Pose objective log(T_ee^-1 T_t) with weights (eq. 8/16): returns 1/2 |r|^2 and, if
+// GRAD, the tip wrench (world force f, world torque tau) equivalent to the
+// gradient: dC/dxi_body = (lambda_v, lambda_w) = M^T r, f = R lambda_v, tau = R lambda_w.
+template <typename T, bool GRAD>
+CR_HD T pose_term(const WeightsT<T>& w, const T* R, const T* p, const T* Tt, T* f, T* tau) {
+  T Re[9], te[3], om[3], rho[3], gam, dgam = T(0);
+  relative_pose(R, p, Tt, Re, te);
+  log_se3<T, GRAD>(Re, te, om, rho, &gam, &dgam);
+  const T rr[3] = {w.w_pos * rho[0], w.w_pos * rho[1], w.w_pos * rho[2]};
+  const T ro[3] = {w.w_rot * om[0], w.w_rot * om[1], w.w_rot * om[2]};
+  const T cost = T(0.5) * (dot3(rr, rr) + dot3(ro, ro));
+  if (GRAD) {
+    // V^-T x = x + w x x / 2 + gamma w x (w x x)
+    auto vit = [&](const T* x, T* y) {
+      T t1[3], t2[3];
+      cross3(om, x, t1);
+      cross3(om, t1, t2);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c] = x[c] + T(0.5) * t1[c] + gam * t2[c];
+    };
+    T u1[3], u2[3];
+    cross3(om, te, u1);
+    cross3(om, u1, u2);
+    // N^T x = -t x x / 2 + 2 gamma' (u2 . x) w + gamma u1 x x - gamma t x (w x x)
+    T tx[3], u1x[3], wx[3], twx[3], Nt[3];
+    cross3(te, rr, tx);
+    cross3(u1, rr, u1x);
+    cross3(om, rr, wx);
+    cross3(te, wx, twx);
+    const T s2 = T(2) * dgam * dot3(u2, rr);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Nt[c] = T(-0.5) * tx[c] + s2 * om[c] + gam * (u1x[c] - twx[c]);
+    T a1[3], a2[3], a3[3], ta2[3], lv[3], lw[3];
+    vit(Nt, a1);
+    vit(rr, a2);
+    vit(ro, a3);
+    cross3(te, a2, ta2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lv[c] = -w.w_pos * a2[c];
+      lw[c] = -w.w_pos * (a1[c] + ta2[c]) - w.w_rot * a3[c];
+    }
+    mv3(R, lv, f);
+    mv3(R, lw, tau);
+  }
+  return cost;
+}
+
+// Reverse sweep: gz += contributions of the tip wrench (f_tip, tau_tip) and of
+// the per-segment point forces recorded in the forward pass.
+template <int NS, typename T>
+CR_HD void config_reverse(const Fwd<NS, T>& f, const T* f_tip, const T* tau_tip, T* gz) {
+  T Fd[3] = {f_tip[0], f_tip[1], f_tip[2]};
+  T Md[3];
+  cross3(f.p, f_tip, Md);
+  Md[0] += tau_tip[0];
+  Md[1] += tau_tip[1];
+  Md[2] += tau_tip[2];
+#pragma unroll
+  for (int j = NS - 1; j >= 0; --j) {
+    T pf[3], mom[3];
+    cross3(f.pe[j], Fd, pf);
+    mom[0] = Md[0] - pf[0];
+    mom[1] = Md[1] - pf[1];
+    mom[2] = Md[2] - pf[2];
+    gz[2 * j] = f.gz[2 * j] + dot3(f.W[2 * j], mom) + dot3(f.Pd[2 * j], Fd);
+    gz[2 * j + 1] = f.gz[2 * j + 1] + dot3(f.W[2 * j + 1], mom) + dot3(f.Pd[2 * j + 1], Fd);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Fd[c] += f.F[j][c];
+      Md[c] += f.Mo[j][c];
+    }
+  }
+}
+
+// dC/du from dC/dz for one segment: a = (u1 + u2 - 2 u0)/(3r), b = (u2 - u1)/(sqrt(3) r).
+template <typename T>
+CR_HD void gz_to_gu(T ga, T gb, T r, T* gu) {
+  const T i3r = T(1) / (T(3) * r), is3r = T(1) / (T(1.7320508075688772935) * r);
+  gu[0] = T(-2) * ga * i3r;
+  gu[1] = ga * i3r - gb * is3r;
+  gu[2] = ga * i3r + gb * is3r;
+}
+
+}  // namespace crk

@@ -1,0 +1,389 @@
+// cr_ik.hip -- two-stage inverse kinematics (Algorithm 1) on gfx950.
+//
+//   k_ik_stage1   one lane per seed: k_init LM iterations in the stage-1 type
+//                 (FP32 bulk or FP64), then the seed's unweighted pose error
+//                 (SelectTop key), collision penalty and final cost
+//   k_select      one workgroup per problem: LDS bitonic sort + greedy
+//                 near-duplicate pass (SelectTop)
+//   k_ik_stage2   one lane per kept candidate: k_final LM iterations in FP64
+//   k_ik_finalize one lane per problem: argmin of the final cost (ties to the
+//                 lower seed index), FP64 assessment and zero-sum output
+//
+// All per-seed state stays in VGPRs for the whole iteration loop; HBM sees the
+// seeds once and the per-seed summaries once.
+#include <float.h>
+
+#include "cr_internal.h"
+
+namespace crk {
+
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_ik_stage1(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
+                const double* __restrict__ useed, int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out,
+                T* __restrict__ pen_out, T* __restrict__ cost_out, int32_t* __restrict__ failed_out,
+                int32_t* __restrict__ trials_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t B = P * (int64_t)S;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int64_t p = b / S;
+  T tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = (T)Tt[c * P + p];
+  T z[NZ];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    u_to_ab((T)useed[(3 * i) * B + b], (T)useed[(3 * i + 1) * B + b], (T)useed[(3 * i + 2) * B + b], rb.r[i],
+            &z[2 * i], &z[2 * i + 1]);
+  T lam = lam0;
+  bool failed = false;
+  int trials = 0;
+  lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+  T e;
+  T c = ik_cost<NS>(rb, w, tt, z, &e);
+  if (!tfinite(c) || !tfinite(e)) failed = true;
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
+  e_out[b] = e;
+  pen_out[b] = T(0);
+  cost_out[b] = c;
+  failed_out[b] = failed ? 1 : 0;
+  trials_out[b] = trials;
+}
+
+// ---------------------------------------------------------------------------
+// SelectTop.  Keys (flag, e, index) are sorted ascending in LDS by a bitonic
+// network (flag 0 = valid, 1 = failed, 2 = padding); all keys are distinct, so
+// the order equals a stable sort by (flag, e).  Thread 0 then walks the order.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ bool key_less(T ea, int fa, T eb, int fb) {
+  // fa/fb pack (flag << 16) | index
+  int ga = fa >> 16, gb = fb >> 16;
+  if (ga != gb) return ga < gb;
+  if (ga == 0 && ea != eb) return ea < eb;
+  return (fa & 0xffff) < (fb & 0xffff);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_select(int64_t P, int S, int Spad, int nz, const T* __restrict__ z, const T* __restrict__ e,
+             const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final, T dup_eps,
+             int32_t* __restrict__ idx_out) {
+  extern __shared__ unsigned char smem[];
+  T* se = reinterpret_cast<T*>(smem);
+  int* sf = reinterpret_cast<int*>(se + Spad);
+  unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad);
+  const int64_t p = blockIdx.x;
+  const int64_t B = P * (int64_t)S;
+  for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
+    if (i < S) {
+      T ev = e[p * S + i];
+      int fl = (failed && failed[p * S + i]) || !tfinite(ev) ? 1 : 0;
+      se[i] = ev;
+      sf[i] = (fl << 16) | i;
+    } else {
+      se[i] = T(0);
+      sf[i] = (2 << 16) | i;
+    }
+    skipped[i] = 0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= Spad; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
+        int l = i ^ j;
+        if (l > i) {
+          bool up = (i & k) == 0;
+          T ei = se[i], el = se[l];
+          int fi = sf[i], fl = sf[l];
+          bool swap = up ? key_less(el, fl, ei, fi) : key_less(ei, fi, el, fl);
+          if (swap) {
+            se[i] = el;
+            se[l] = ei;
+            sf[i] = fl;
+            sf[l] = fi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x != 0) return;
+  int kept[64];
+  int nk = 0;
+  for (int q = 0; q < S && nk < n_final; ++q) {
+    int f = sf[q];
+    if ((f >> 16) != 0) break;
+    int c = f & 0xffff;
+    int dup = -1;
+    for (int k = 0; k < nk && dup < 0; ++k) {
+      T dmax = T(0);
+      for (int m = 0; m < nz; ++m) {
+        T d = fabs(z[m * B + p * S + c] - z[m * B + p * S + kept[k]]);
+        dmax = d > dmax ? d : dmax;
+      }
+      if (dmax <= dup_eps) dup = k;
+    }
+    if (dup < 0) {
+      kept[nk++] = c;
+    } else if (pen[p * S + c] < pen[p * S + kept[dup]]) {
+      skipped[kept[dup]] = 1;
+      kept[dup] = c;
+    } else {
+      skipped[c] = 1;
+    }
+  }
+  for (int q = 0; q < S && nk < n_final; ++q) {
+    int f = sf[q];
+    if ((f >> 16) != 0) break;
+    int c = f & 0xffff;
+    if (skipped[c]) {
+      kept[nk++] = c;
+      skipped[c] = 0;
+    }
+  }
+  for (int k = 0; k < n_final; ++k) idx_out[k * P + p] = k < nk ? kept[k] : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: FP64 refinement of the kept candidates, lambda restarted at lambda0.
+// ---------------------------------------------------------------------------
+
+template <int NS, typename T1>
+__global__ void __launch_bounds__(256)
+    k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
+                const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
+                int iters, double lam0, double* __restrict__ z2, double* __restrict__ cost2,
+                int32_t* __restrict__ failed2) {
+  constexpr int NZ = 2 * NS;
+  const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B2) return;
+  const int64_t p = b / nf;
+  const int k = (int)(b % nf);
+  const int s = sel[k * P + p];
+  if (s < 0) {
+#pragma unroll
+    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
+    cost2[b] = __builtin_nan("");
+    failed2[b] = 1;
+    return;
+  }
+  double tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = Tt[c * P + p];
+  double z[NZ];
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z[m] = (double)z1[m * B1 + p * S + s];
+  double lam = lam0;
+  bool failed = false;
+  int trials = 0;
+  lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+  double c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
+  if (!tfinite(c)) failed = true;
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
+  cost2[b] = c;
+  failed2[b] = failed ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Final argmin over candidates and FP64 assessment of the winner.
+// Candidates are either the nf stage-2 slots (sel != NULL: seed index sel[k])
+// or all S stage-1 seeds (seed index k).
+// ---------------------------------------------------------------------------
+
+template <int NS, typename TC>
+__global__ void __launch_bounds__(256)
+    k_ik_finalize(RobotT<double> rb, int64_t P, int nc, const int32_t* __restrict__ sel,
+                  const TC* __restrict__ zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
+                  const double* __restrict__ Tt, double* __restrict__ u_out, double* __restrict__ err_out,
+                  int32_t* __restrict__ status_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int64_t Bc = P * (int64_t)nc;
+  int best = -1, best_seed = 0;
+  double best_cost = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    const int64_t col = p * nc + k;
+    int seed = sel ? sel[k * P + p] : k;
+    double c = (double)costc[col];
+    if (seed < 0 || failedc[col] || !tfinite(c)) continue;
+    if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
+      best = k;
+      best_cost = c;
+      best_seed = seed;
+    }
+  }
+  if (best < 0) {
+    const double nan = __builtin_nan("");
+    for (int m = 0; m < 3 * NS; ++m) u_out[m * P + p] = nan;
+    err_out[p] = nan;
+    err_out[P + p] = nan;
+    status_out[p] = CR_NONFINITE;
+    return;
+  }
+  double z[NZ];
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z[m] = (double)zc[m * Bc + p * nc + best];
+  double tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = Tt[c * P + p];
+  double Rc[9], pc[3];
+  fk_tip<NS>(rb, z, Rc, pc);
+  double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
+  double pos = sqrt(dot3(dp, dp));
+  double Re[9], te[3];
+  relative_pose(Rc, pc, tt, Re, te);
+  double v[3] = {0.5 * (Re[7] - Re[5]), 0.5 * (Re[2] - Re[6]), 0.5 * (Re[3] - Re[1])};
+  double rot = atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0));
+  double viol = -DBL_MAX, thx = -DBL_MAX;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double u[3];
+    ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      u_out[(3 * i + j) * P + p] = u[j];
+      viol = fmax(viol, fabs(u[j]) - rb.umax[i]);
+    }
+    thx = fmax(thx, sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) - rb.theta_max);
+  }
+  int32_t st = 0;
+  if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
+  if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
+  if (st == 0) st = CR_SOLVED;
+  err_out[p] = pos;
+  err_out[P + p] = rot;
+  status_out[p] = st;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_opts& o, cr_dtype dtype,
+                           char* base, IkWorkspace* ws) {
+  const size_t t1 = dtype == CR_F64 ? 8 : 4;
+  const int64_t B = P * (int64_t)S;
+  const int nz = 2 * rb.n_seg;
+  const int nf = o.n_final > 0 ? o.n_final : 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return base ? (void*)(base + at) : nullptr;
+  };
+  IkWorkspace w{};
+  w.z1 = take(t1 * nz * B);
+  w.e1 = take(t1 * B);
+  w.pen1 = take(t1 * B);
+  w.cost1 = take(t1 * B);
+  w.failed1 = (int32_t*)take(4 * B);
+  w.trials1 = (int32_t*)take(4 * B);
+  w.sel = (int32_t*)take(4 * (size_t)(nf > 0 ? nf : 1) * P);
+  w.z2 = (double*)take(8 * (size_t)nz * (nf > 0 ? nf : 1) * P);
+  w.cost2 = (double*)take(8 * (size_t)(nf > 0 ? nf : 1) * P);
+  w.failed2 = (int32_t*)take(4 * (size_t)(nf > 0 ? nf : 1) * P);
+  if (ws) *ws = w;
+  return off;
+}
+
+static int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+template <int NS, typename T>
+static cr_status run_ik(const cr_robot& rb0, int64_t P, const double* Tt, int32_t S, const double* useed,
+                        const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
+                        const IkWorkspace& ws, hipStream_t st) {
+  RobotT<T> rb = robot_to<T>(rb0);
+  WeightsT<T> w = weights_to<T>(w0);
+  LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
+  const int64_t B = P * (int64_t)S;
+  const bool timed = timer_on();
+  if (timed) timer_begin_call(st);
+  hipLaunchKernelGGL((k_ik_stage1<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S, Tt,
+                     useed, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1,
+                     ws.trials1);
+  cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1");
+  if (rc != CR_OK) return rc;
+  if (timed) timer_mark(0, st);
+  const bool two_stage = o.n_final > 0;
+  RobotT<double> rbd = robot_to<double>(rb0);
+  if (two_stage) {
+    rc = launch_select(P, S, 2 * NS, ws.z1, ws.e1, ws.pen1, ws.failed1, o.n_final, o.dup_eps, ws.sel,
+                       sizeof(T) == 8 ? CR_F64 : CR_F32, st);
+    if (rc != CR_OK) return rc;
+    if (timed) timer_mark(1, st);
+    WeightsT<double> wd = weights_to<double>(w0);
+    LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
+    const int64_t B2 = P * (int64_t)o.n_final;
+    hipLaunchKernelGGL((k_ik_stage2<NS, T>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, (int)S,
+                       (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, ws.z2, ws.cost2,
+                       ws.failed2);
+    rc = check_hip(hipGetLastError(), "k_ik_stage2");
+    if (rc != CR_OK) return rc;
+    if (timed) timer_mark(2, st);
+    hipLaunchKernelGGL((k_ik_finalize<NS, double>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
+                       (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, u_out, err_out, status_out);
+  } else {
+    if (timed) {
+      timer_mark(1, st);
+      timer_mark(2, st);
+    }
+    hipLaunchKernelGGL((k_ik_finalize<NS, T>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
+                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, u_out,
+                       err_out, status_out);
+  }
+  rc = check_hip(hipGetLastError(), "k_ik_finalize");
+  if (timed) {
+    timer_mark(3, st);
+    timer_end_call();
+  }
+  return rc;
+}
+
+cr_status launch_solve_ik(const cr_robot& rb, int64_t P, const double* Tt, int32_t S, const double* useed,
+                          const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+                          int32_t* status_out, const IkWorkspace& ws, cr_dtype dtype, hipStream_t st) {
+#define CR_IK_CASE(N)                                                                                     \
+  case N:                                                                                                 \
+    return dtype == CR_F64 ? run_ik<N, double>(rb, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st) \
+                           : run_ik<N, float>(rb, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st);
+  switch (rb.n_seg) {
+    CR_IK_CASE(1)
+    CR_IK_CASE(2)
+    CR_IK_CASE(3)
+    CR_IK_CASE(4)
+    CR_IK_CASE(5)
+    CR_IK_CASE(6)
+    default:
+      return fail(CR_EINVAL, "n_seg out of range");
+  }
+#undef CR_IK_CASE
+}
+
+cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
+                        const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out, cr_dtype dtype,
+                        hipStream_t st) {
+  int Spad = 1;
+  while (Spad < S) Spad <<= 1;
+  const size_t tb = dtype == CR_F64 ? 8 : 4;
+  const size_t lds = Spad * (tb + 4) + Spad;
+  if (P == 0) return CR_OK;
+  if (dtype == CR_F64)
+    hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
+                       (const double*)z, (const double*)e, (const double*)pen, failed, (int)n_final, dup_eps, idx_out);
+  else
+    hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
+                       (const float*)z, (const float*)e, (const float*)pen, failed, (int)n_final, (float)dup_eps,
+                       idx_out);
+  return check_hip(hipGetLastError(), "k_select");
+}
+
+}  // namespace crk

@@ -1,0 +1,60 @@
+// cr_internal.h -- launchers shared between the kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cr_device.h"
+#include "cr_solver.h"
+
+namespace crk {
+
+// Records a message for cr_last_error() and returns the status.
+cr_status fail(cr_status s, const char* fmt, ...);
+cr_status check_hip(hipError_t e, const char* what);
+
+template <typename T>
+RobotT<T> robot_to(const cr_robot& r);
+template <typename T>
+WeightsT<T> weights_to(const cr_weights& w);
+
+cr_status launch_fk(const cr_robot& rb, int64_t B, const void* u, int64_t ld, void* arc, void* frames,
+                    void* pts, cr_dtype dtype, hipStream_t stream);
+
+struct IkWorkspace {
+  void* z1;         // [2n][S*P] stage-1 type
+  void* e1;         // [S*P]
+  void* pen1;       // [S*P]
+  void* cost1;      // [S*P]
+  int32_t* failed1; // [S*P]
+  int32_t* trials1; // [S*P]
+  int32_t* sel;     // [n_final][P]
+  double* z2;       // [2n][n_final*P]
+  double* cost2;    // [n_final*P]
+  int32_t* failed2; // [n_final*P]
+};
+size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_opts& o, cr_dtype dtype,
+                           char* base, IkWorkspace* ws);
+
+cr_status launch_solve_ik(const cr_robot& rb, int64_t P, const double* Tt, int32_t S, const double* useed,
+                          const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+                          int32_t* status_out, const IkWorkspace& ws, cr_dtype dtype, hipStream_t stream);
+
+cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
+                        const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out,
+                        cr_dtype dtype, hipStream_t stream);
+
+cr_status launch_cost_grad(int kind, const cr_robot& rb, const cr_spheres* sp, const cr_weights& w, int64_t P, int H,
+                           int S, const void* task, const void* u, void* cost, void* grad, const void* gscale,
+                           cr_dtype dtype, hipStream_t st);
+
+cr_status tally_ik_dispatch(const cr_robot& rb, const cr_weights& w, const cr_opts& o, int64_t n, const double* T,
+                            const double* u, double* out);
+
+// Stage timer: when enabled, solve calls record HIP events on their own stream
+// between their stages; marks are summed by timer_read().
+bool timer_on();
+void timer_begin_call(hipStream_t st);   // records the call's start mark
+void timer_mark(int stage, hipStream_t st);  // records the end of `stage` (0..3)
+void timer_end_call();
+
+}  // namespace crk
