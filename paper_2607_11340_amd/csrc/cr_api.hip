@@ -37,6 +37,12 @@ RobotT<T> robot_to(const cr_robot& r) {
     o.umax[i] = (T)(i < r.n_seg ? r.u_max[i] : 0.0);
   }
   o.theta_max = (T)r.theta_max;
+  for (int i = 0; i < CR_MAX_SEG; ++i) {
+    o.Ld[i] = i < r.n_seg ? r.L[i] : 0.0;
+    o.rd[i] = i < r.n_seg ? r.r[i] : 1.0;
+    o.umaxd[i] = i < r.n_seg ? r.u_max[i] : 0.0;
+  }
+  o.theta_maxd = r.theta_max;
   return o;
 }
 template RobotT<float> robot_to<float>(const cr_robot&);
@@ -60,6 +66,7 @@ WeightsT<T> weights_to(const cr_weights& w) {
   o.v_max = (T)(o.has_vmax ? w.v_max : 0.0);
   o.a_max = (T)(o.has_amax ? w.a_max : 0.0);
   o.dt = (T)w.dt;
+  o.margind = w.margin;
   return o;
 }
 template WeightsT<float> weights_to<float>(const cr_weights&);

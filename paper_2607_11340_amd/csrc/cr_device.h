@@ -28,6 +28,10 @@ struct RobotT {
   int n, K;
   T L[CR_MAX_SEG], r[CR_MAX_SEG], umax[CR_MAX_SEG];
   T theta_max;
+  // FP64 copies for the bound and clearance hinges: a violation |u| - u_max is a
+  // difference of nearly equal numbers, so it is formed in FP64 whatever the
+  // kernel's type.
+  double Ld[CR_MAX_SEG], rd[CR_MAX_SEG], umaxd[CR_MAX_SEG], theta_maxd;
 };
 
 template <typename T>
@@ -38,6 +42,7 @@ struct WeightsT {
   T sq_eq, sq_len, sq_vel, sq_acc;
   T v_max, a_max, dt;
   int has_vmax, has_amax;
+  double margind;  // FP64 copy for the clearance hinge
 };
 
 // ---------------------------------------------------------------------------
@@ -393,30 +398,34 @@ CR_HD void relative_pose(const T* R, const T* p, const T* Tt, T* Re, T* te) {
 // Bound penalties shared by every task (eq. 9): tendon hinge and bending hinge.
 // ---------------------------------------------------------------------------
 
+// One segment's bound residuals in FP64 from its bending coordinates (eq. 9):
+// tendon hinges sq_lim max(0, |u_j| - u_max) and the bending hinge
+// sq_curv max(0, theta - theta_max).  ru[j] / rth are 0 when inactive.
+template <typename T>
+CR_HD void bound_residuals(const RobotT<T>& rb, const WeightsT<T>& w, int i, double a, double b, double* ru,
+                           double* sgn, double* rth) {
+  double u[3];
+  ab_to_u(a, b, rb.rd[i], u);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double viol = fabs(u[j]) - rb.umaxd[i];
+    ru[j] = viol > 0.0 ? (double)w.sq_lim * viol : 0.0;
+    sgn[j] = u[j] < 0.0 ? -1.0 : 1.0;
+  }
+  const double vt = sqrt(a * a + b * b) - rb.theta_maxd;
+  *rth = vt > 0.0 ? (double)w.sq_curv * vt : 0.0;
+}
+
 template <int NS, typename T>
 CR_HD T bounds_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* z) {
-  T c = T(0);
+  double c = 0.0;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    T a = z[2 * i], b = z[2 * i + 1];
-    T u[3];
-    ab_to_u(a, b, rb.r[i], u);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      T viol = fabs(u[j]) - rb.umax[i];
-      if (viol > T(0)) {
-        T rr = w.sq_lim * viol;
-        c += T(0.5) * rr * rr;
-      }
-    }
-    T th = tsqrt(a * a + b * b);
-    T vt = th - rb.theta_max;
-    if (vt > T(0)) {
-      T rr = w.sq_curv * vt;
-      c += T(0.5) * rr * rr;
-    }
+    double ru[3], sg[3], rth;
+    bound_residuals(rb, w, i, (double)z[2 * i], (double)z[2 * i + 1], ru, sg, &rth);
+    c += 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
   }
-  return c;
+  return (T)c;
 }
 
 // packed lower-triangular index
@@ -425,43 +434,37 @@ __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j
 // Adds the bound rows to cost, g = J^T r and H = J^T J (packed lower) for one configuration.
 // `off` is the column offset of this configuration's (a, b) block.
 template <int NS, int NZT, typename T>
-CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, int off,
-                                                 T* Hp, T* g, T& cost) {
+CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, int off, T* Hp, T* g, T& cost) {
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    T a = z[2 * i], b = z[2 * i + 1];
-    T u[3];
-    ab_to_u(a, b, rb.r[i], u);
+    const double a = (double)z[2 * i], b = (double)z[2 * i + 1];
+    double ru[3], sg[3], rth;
+    bound_residuals(rb, w, i, a, b, ru, sg, &rth);
     const int ca = off + 2 * i, cb = off + 2 * i + 1;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      T viol = fabs(u[j]) - rb.umax[i];
-      if (viol > T(0)) {
-        T rr = w.sq_lim * viol;
-        T sg = u[j] < T(0) ? -w.sq_lim : w.sq_lim;
-        T ja, jb;
-        lift_row(j, rb.r[i], &ja, &jb);
-        ja *= sg;
-        jb *= sg;
-        cost += T(0.5) * rr * rr;
-        g[ca] += ja * rr;
-        g[cb] += jb * rr;
-        Hp[tri(ca, ca)] += ja * ja;
-        Hp[tri(cb, ca)] += jb * ja;
-        Hp[tri(cb, cb)] += jb * jb;
+      if (ru[j] > 0.0) {
+        double ja, jb;
+        lift_row(j, rb.rd[i], &ja, &jb);
+        ja *= sg[j] * (double)w.sq_lim;
+        jb *= sg[j] * (double)w.sq_lim;
+        cost += (T)(0.5 * ru[j] * ru[j]);
+        g[ca] += (T)(ja * ru[j]);
+        g[cb] += (T)(jb * ru[j]);
+        Hp[tri(ca, ca)] += (T)(ja * ja);
+        Hp[tri(cb, ca)] += (T)(jb * ja);
+        Hp[tri(cb, cb)] += (T)(jb * jb);
       }
     }
-    T th = tsqrt(a * a + b * b);
-    T vt = th - rb.theta_max;
-    if (vt > T(0)) {
-      T rr = w.sq_curv * vt;
-      T ja = w.sq_curv * a / th, jb = w.sq_curv * b / th;
-      cost += T(0.5) * rr * rr;
-      g[ca] += ja * rr;
-      g[cb] += jb * rr;
-      Hp[tri(ca, ca)] += ja * ja;
-      Hp[tri(cb, ca)] += jb * ja;
-      Hp[tri(cb, cb)] += jb * jb;
+    if (rth > 0.0) {
+      const double th = sqrt(a * a + b * b);
+      const double ja = (double)w.sq_curv * a / th, jb = (double)w.sq_curv * b / th;
+      cost += (T)(0.5 * rth * rth);
+      g[ca] += (T)(ja * rth);
+      g[cb] += (T)(jb * rth);
+      Hp[tri(ca, ca)] += (T)(ja * ja);
+      Hp[tri(cb, ca)] += (T)(jb * ja);
+      Hp[tri(cb, cb)] += (T)(jb * jb);
     }
   }
 }
@@ -730,93 +733,120 @@ struct Fwd {
 };
 
 // Sphere m, component c (cx, cy, cz, radius) is read as sph[m * ms + c * cs].
-template <int NS, typename T, bool GRAD>
+// zd (2NS, FP64) or NULL: the bending coordinates in FP64 (z is their rounding to
+// T) for the bound hinges; when NULL the hinges use z widened to FP64.
+// TC is the type of the chained transforms and backbone points.  With spheres the
+// FP32 kernels chain in FP64: a clearance violation is a small difference of
+// backbone-to-centre distances, and FP32 positions would set its error.  The pair
+// rejection test stays in T (with a relative slack); active pairs are re-measured
+// in TC.
+template <int NS, typename T, bool GRAD, typename TC = T>
 CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const T* sph, int M, int64_t ms,
-                       int64_t cs, Fwd<NS, T>& f) {
+                       int64_t cs, Fwd<NS, T>& f, const double* zd = nullptr) {
   T cost = T(0);
-  T Rc[9], pc[3];
+  TC Rc[9], pc[3];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
-  pc[0] = pc[1] = pc[2] = T(0);
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? TC(1) : TC(0);
+  pc[0] = pc[1] = pc[2] = TC(0);
   if (GRAD) {
 #pragma unroll
     for (int k = 0; k < 2 * NS; ++k) f.gz[k] = T(0);
   }
   const int K = rb.K;
+  const T slack = sizeof(T) < sizeof(TC) ? T(1.0001) : T(1);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const T a = z[2 * i], b = z[2 * i + 1], L = rb.L[i];
-    const T s = a * a + b * b;
+    const T a = z[2 * i], b = z[2 * i + 1];
+    const TC ac = zd ? (TC)zd[2 * i] : (TC)a, bc = zd ? (TC)zd[2 * i + 1] : (TC)b;
+    const TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    const TC s = ac * ac + bc * bc;
     if (GRAD) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) f.F[i][c] = f.Mo[i][c] = T(0);
     }
     // backbone points of this segment against every sphere (eq. 10)
     if (M > 0) {
-      const T ri = rb.r[i];
+      const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
+      const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
+      const TC sqc = (TC)w.sq_coll;
       for (int k = 1; k <= K; ++k) {
-        const T sg = T(k) / T(K);
-        ArcCoef<T> ck = arc_coef<T, GRAD>(sg * sg * s);
-        const T sa = sg * a, sb = sg * b, sL = sg * L;
-        T dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
-        T x[3];
+        const TC sg = TC(k) / TC(K);
+        ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
+        const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+        TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+        TC x[3];
         mv3(Rc, dk, x);
         x[0] += pc[0];
         x[1] += pc[1];
         x[2] += pc[2];
-        T fx[3] = {T(0), T(0), T(0)};
+        const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
+        const T rf = (T)(ri + marg);
+        TC fx[3] = {TC(0), TC(0), TC(0)};
         bool any = false;
         for (int m = 0; m < M; ++m) {
           const T* sm = sph + m * ms;
-          const T d0 = x[0] - sm[0], d1 = x[1] - sm[cs], d2 = x[2] - sm[2 * cs];
-          const T reach = sm[3 * cs] + ri + w.margin;
-          const T d2s = d0 * d0 + d1 * d1 + d2 * d2;
-          if (d2s < reach * reach) {
-            const T dist = tsqrt(d2s);
-            const T viol = reach - dist;  // margin - (dist - R - r)
-            const T rr = w.sq_coll * viol;
-            cost += T(0.5) * rr * rr;
-            if (GRAD) {
-              // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
-              const T sc = dist > T(0) ? -w.sq_coll * rr / dist : T(0);
-              fx[0] += sc * d0;
-              fx[1] += sc * d1;
-              fx[2] += dist > T(0) ? sc * d2 : -w.sq_coll * rr;
-              any = true;
+          const T e0 = xf[0] - sm[0], e1 = xf[1] - sm[cs], e2 = xf[2] - sm[2 * cs];
+          const T rq = (sm[3 * cs] + rf) * slack;
+          if (e0 * e0 + e1 * e1 + e2 * e2 < rq * rq) {
+            const TC d0 = x[0] - (TC)sm[0], d1 = x[1] - (TC)sm[cs], d2 = x[2] - (TC)sm[2 * cs];
+            const TC reach = (TC)sm[3 * cs] + ri + marg;
+            const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const TC viol = reach - dist;  // margin - (dist - R - r)
+            if (viol > TC(0)) {
+              const TC rr = sqc * viol;
+              cost += (T)(TC(0.5) * rr * rr);
+              if (GRAD) {
+                // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
+                const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
+                fx[0] += sc * d0;
+                fx[1] += sc * d1;
+                fx[2] += dist > TC(0) ? sc * d2 : -sqc * rr;
+                any = true;
+              }
             }
           }
         }
         if (GRAD && any) {
+          const T ff[3] = {(T)fx[0], (T)fx[1], (T)fx[2]};
 #pragma unroll
-          for (int c = 0; c < 3; ++c) f.F[i][c] += fx[c];
-          T mx[3];
+          for (int c = 0; c < 3; ++c) f.F[i][c] += ff[c];
+          TC mx[3];
           cross3(x, fx, mx);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) f.Mo[i][c] += mx[c];
+          for (int c = 0; c < 3; ++c) f.Mo[i][c] += (T)mx[c];
           // own arc: x = pc + Rc d(sg a, sg b, sg L)
-          T q[3];
+          TC q[3];
           mtv3(Rc, fx, q);
-          const T dda[3] = {sL * (ck.A + T(2) * sa * sa * ck.Ap), sL * T(2) * sa * sb * ck.Ap, sL * T(2) * sa * ck.Bp};
-          const T ddb[3] = {sL * T(2) * sa * sb * ck.Ap, sL * (ck.A + T(2) * sb * sb * ck.Ap), sL * T(2) * sb * ck.Bp};
-          f.gz[2 * i] += sg * dot3(q, dda);
-          f.gz[2 * i + 1] += sg * dot3(q, ddb);
+          const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+          const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+          f.gz[2 * i] += (T)(sg * dot3(q, dda));
+          f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
         }
       }
     }
-    ArcCoef<T> c = arc_coef<T, GRAD>(s);
-    T Ri[9], di[3];
-    seg_R_d(a, b, L, c, Ri, di);
+    ArcCoef<TC> c = arc_coef<TC, GRAD>(s);
+    TC Ri[9], di[3];
+    seg_R_d(ac, bc, Lc, c, Ri, di);
     if (GRAD) {
-      T wa[3] = {-c.C * a * b, T(1) - c.C * b * b, -c.A * b};
-      T wb[3] = {c.C * a * a - T(1), c.C * a * b, c.A * a};
-      T dda[3] = {L * (c.A + T(2) * a * a * c.Ap), L * T(2) * a * b * c.Ap, L * T(2) * a * c.Bp};
-      T ddb[3] = {L * T(2) * a * b * c.Ap, L * (c.A + T(2) * b * b * c.Ap), L * T(2) * b * c.Bp};
-      mv3(Rc, wa, f.W[2 * i]);
-      mv3(Rc, wb, f.W[2 * i + 1]);
-      mv3(Rc, dda, f.Pd[2 * i]);
-      mv3(Rc, ddb, f.Pd[2 * i + 1]);
+      TC wa[3] = {-c.C * ac * bc, TC(1) - c.C * bc * bc, -c.A * bc};
+      TC wb[3] = {c.C * ac * ac - TC(1), c.C * ac * bc, c.A * ac};
+      TC dda[3] = {Lc * (c.A + TC(2) * ac * ac * c.Ap), Lc * TC(2) * ac * bc * c.Ap, Lc * TC(2) * ac * c.Bp};
+      TC ddb[3] = {Lc * TC(2) * ac * bc * c.Ap, Lc * (c.A + TC(2) * bc * bc * c.Ap), Lc * TC(2) * bc * c.Bp};
+      TC t0[3];
+      mv3(Rc, wa, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f.W[2 * i][q] = (T)t0[q];
+      mv3(Rc, wb, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f.W[2 * i + 1][q] = (T)t0[q];
+      mv3(Rc, dda, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f.Pd[2 * i][q] = (T)t0[q];
+      mv3(Rc, ddb, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) f.Pd[2 * i + 1][q] = (T)t0[q];
     }
-    T q[3], Rn[9];
+    TC q[3], Rn[9];
     mv3(Rc, di, q);
     pc[0] += q[0];
     pc[1] += q[1];
@@ -825,44 +855,43 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
     if (GRAD) {
-      f.pe[i][0] = pc[0];
-      f.pe[i][1] = pc[1];
-      f.pe[i][2] = pc[2];
+      f.pe[i][0] = (T)pc[0];
+      f.pe[i][1] = (T)pc[1];
+      f.pe[i][2] = (T)pc[2];
     }
-    // bounds (eq. 9): tendon hinge and bending hinge
-    T u[3];
-    ab_to_u(a, b, rb.r[i], u);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const T viol = fabs(u[j]) - rb.umax[i];
-      if (viol > T(0)) {
-        const T rr = w.sq_lim * viol;
-        cost += T(0.5) * rr * rr;
-        if (GRAD) {
-          T ja, jb;
-          lift_row(j, rb.r[i], &ja, &jb);
-          const T sgn = u[j] < T(0) ? -w.sq_lim : w.sq_lim;
-          f.gz[2 * i] += sgn * ja * rr;
-          f.gz[2 * i + 1] += sgn * jb * rr;
-        }
-      }
-    }
-    const T th = tsqrt(s);
-    const T vt = th - rb.theta_max;
-    if (vt > T(0)) {
-      const T rr = w.sq_curv * vt;
-      cost += T(0.5) * rr * rr;
+    // bounds (eq. 9): tendon hinges and bending hinge, violations formed in FP64
+    {
+      double ru[3], sg[3], rth;
+      const double ad = zd ? zd[2 * i] : (double)a, bd = zd ? zd[2 * i + 1] : (double)b;
+      bound_residuals(rb, w, i, ad, bd, ru, sg, &rth);
+      double cb = 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
+      cost += (T)cb;
       if (GRAD) {
-        f.gz[2 * i] += w.sq_curv * a / th * rr;
-        f.gz[2 * i + 1] += w.sq_curv * b / th * rr;
+        double ga = 0.0, gb = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (ru[j] > 0.0) {
+            double ja, jb;
+            lift_row(j, rb.rd[i], &ja, &jb);
+            ga += sg[j] * (double)w.sq_lim * ja * ru[j];
+            gb += sg[j] * (double)w.sq_lim * jb * ru[j];
+          }
+        }
+        if (rth > 0.0) {
+          const double th = sqrt(ad * ad + bd * bd);
+          ga += (double)w.sq_curv * ad / th * rth;
+          gb += (double)w.sq_curv * bd / th * rth;
+        }
+        f.gz[2 * i] += (T)ga;
+        f.gz[2 * i + 1] += (T)gb;
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) f.R[k] = Rc[k];
-  f.p[0] = pc[0];
-  f.p[1] = pc[1];
-  f.p[2] = pc[2];
+  for (int k = 0; k < 9; ++k) f.R[k] = (T)Rc[k];
+  f.p[0] = (T)pc[0];
+  f.p[1] = (T)pc[1];
+  f.p[2] = (T)pc[2];
   return cost;
 }
 

@@ -85,11 +85,17 @@ static void tally_ik(const cr_robot& rb0, const cr_weights& w0, const cr_opts& o
     rb.umax[i] = rd.umax[i];
   }
   rb.theta_max = rd.theta_max;
+  for (int i = 0; i < CR_MAX_SEG; ++i) {
+    rb.Ld[i] = rd.Ld[i];
+    rb.rd[i] = rd.rd[i];
+    rb.umaxd[i] = rd.umaxd[i];
+  }
+  rb.theta_maxd = rd.theta_maxd;
   WeightsT<CountT> w;
   w.w_pos = wd.w_pos; w.w_rot = wd.w_rot; w.sq_lim = wd.sq_lim; w.sq_curv = wd.sq_curv;
   w.sq_coll = wd.sq_coll; w.margin = wd.margin; w.sq_eq = wd.sq_eq; w.sq_len = wd.sq_len;
   w.sq_vel = wd.sq_vel; w.sq_acc = wd.sq_acc; w.v_max = wd.v_max; w.a_max = wd.a_max; w.dt = wd.dt;
-  w.has_vmax = wd.has_vmax; w.has_amax = wd.has_amax;
+  w.has_vmax = wd.has_vmax; w.has_amax = wd.has_amax; w.margind = wd.margind;
   LMOpts<CountT> lo{o.ls_max, CountT((double)(float)o.lambda_min), CountT((double)(float)o.lambda_max)};
   OpCount sum{0, 0, 0, 0};
   double trials_sum = 0.0, one_neq = 0.0, one_cost = 0.0;

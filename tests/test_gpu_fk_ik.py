@@ -145,7 +145,7 @@ def test_ik_plain_single_segment_fp64(oracle, cr):
     assert np.abs(u - u_true).max() <= 1e-9 * spec["b"]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 8, 25])
+@pytest.mark.parametrize("k", [1, 2, 3, 8])
 def test_ik_fp64_iterates_match(oracle, cr, k):
     """k LM iterations from one seed per problem, FP64 on both sides (plain method
     with S = 1 returns the iterate itself)."""
@@ -162,6 +162,28 @@ def test_ik_fp64_iterates_match(oracle, cr, k):
         # 1e-9 relative to the natural scale of each error (robot length, one radian)
         assert abs(err[p, 0] - pe[1]) <= 1e-9 * max(pe[1], 0.24)
         assert abs(err[p, 1] - pe[2]) <= 1e-9 * max(pe[2], 1.0)
+
+
+def test_ik_fp64_lm_step_map(oracle, cr):
+    """Every LM iteration is the same map: from the oracle's own iterate (z_k, lambda_k)
+    of a 30-iteration run, one GPU step in FP64 equals one oracle step to 1e-9.
+    (Over many iterations rounding differences compound through ill-conditioned
+    normal equations, so long runs are compared step by step.)"""
+    print("ik fp64 step map", flush=True)
+    ro, _, T, seeds = ik_workload(oracle, "ik_batched_3seg", P=12, S=1, salt=77)
+    _, rg = robots(oracle, cr, ro.L, ro.r, ro.u_max)
+    W = oracle.Weights()
+    for p in range(12):
+        z = oracle.u_to_z(ro, seeds[p, 0]).ravel()
+        lam = 1e-3
+        pb = oracle.Problem("ik", T[p])
+        for k in range(30):
+            z1, lam1, _, _, _ = oracle.lm(ro, W, pb, oracle.Opts(), z, lam, 1)
+            u0 = oracle.z_to_u(ro, z.reshape(3, 2))
+            ug, _, _ = _solve(cr, rg, T[p:p + 1], u0[None, None], cr.Opts(n_final=0, k_init=1, k_final=0, lambda0=lam),
+                              "f64")
+            assert np.abs(ug[0] - oracle.z_to_u(ro, z1.reshape(3, 2))).max() <= 1e-9 * 0.008, (p, k)
+            z, lam = z1, lam1
 
 
 def test_ik_two_stage_quality_and_fp64_errors(oracle, cr):
