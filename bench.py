@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tally-seeds", type=int, default=256)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one plain device copy of this many bytes (HBM counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                                                            "ik_stage1_traffic.json"))
     return ap.parse_args()
@@ -104,6 +106,13 @@ def main():
     def step():
         cr.solve_ik(robot, T, useed, weights, opts, dtype=torch.float32, workspace=ws, out=out)
 
+    if args.copy_bytes > 0:
+        src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -70,6 +70,20 @@ CR_HD void tsincos<float>(float x, float* s, float* c) { sincosf(x, s, c); }
 template <>
 CR_HD void tsincos<double>(double x, double* s, double* c) { sincos(x, s, c); }
 
+// 1/x: the hardware reciprocal (1 ulp) in FP32, an IEEE division in FP64.
+template <typename T>
+CR_HD T trcp(T x) {
+  return T(1) / x;
+}
+template <>
+CR_HD float trcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
 template <typename T>
 CR_HD bool tfinite(T x) {
   return __builtin_isfinite(x);
@@ -147,15 +161,21 @@ CR_HD T alt_series_d(T s) {
 
 template <typename T>
 struct Prec;
+// Series lengths and switch points.  FP32 keeps the polynomial up to s = 4
+// (theta < 2 rad, every bend the bounded robots reach), so the common path has
+// no transcendental call; the largest term there is 2/3 of the leading one, so
+// the sum loses no more than an ulp.
 template <>
 struct Prec<float> {
-  static constexpr int NT = 7;           // series terms for s < 1
-  static constexpr int NG = 5;           // gamma series terms
-  static constexpr float g_switch = 1.0f;
+  static constexpr int NT = 11;          // series terms for s < s_switch
+  static constexpr float s_switch = 4.0f;
+  static constexpr int NG = 8;           // gamma series terms for q < g_switch
+  static constexpr float g_switch = 4.0f;
 };
 template <>
 struct Prec<double> {
   static constexpr int NT = 10;
+  static constexpr double s_switch = 1.0;
   static constexpr int NG = 8;
   static constexpr double g_switch = 0.25;
 };
@@ -174,7 +194,7 @@ template <typename T, bool DERIV>
 CR_HD ArcCoef<T> arc_coef(T s) {
   constexpr int NT = Prec<T>::NT;
   ArcCoef<T> c;
-  if (s < T(1)) {
+  if (s < T(Prec<T>::s_switch)) {
     c.A = alt_series<T, 2, NT>(s);
     c.B = alt_series<T, 1, NT>(s);
     if (DERIV) {
@@ -185,9 +205,9 @@ CR_HD ArcCoef<T> arc_coef(T s) {
   } else {
     T th = tsqrt(s), sh, ch;
     tsincos(T(0.5) * th, &sh, &ch);
-    T inv_s = T(1) / s;
+    T inv_s = trcp(s);
     c.A = T(2) * sh * sh * inv_s;
-    c.B = T(2) * sh * ch / th;
+    c.B = T(2) * sh * ch * trcp(th);
     if (DERIV) {
       T cth = ch * ch - sh * sh;
       c.C = (T(1) - c.B) * inv_s;
@@ -231,13 +251,14 @@ CR_HD void gamma_coef(T q, T* gam, T* dgam) {
   } else {
     T th = tsqrt(q), sh, ch;
     tsincos(T(0.5) * th, &sh, &ch);
-    T cot = ch / sh;
+    const T ish = trcp(sh), iq = trcp(q);
+    T cot = ch * ish;
     T h = T(0.5) * th * cot;
-    T g = (T(1) - h) / q;
+    T g = (T(1) - h) * iq;
     *gam = g;
     if (DERIV) {
-      T dh = T(0.5) * cot - T(0.25) * th / (sh * sh);
-      *dgam = (-dh / (T(2) * th) - g) / q;
+      T dh = T(0.5) * cot - T(0.25) * th * ish * ish;
+      *dgam = (-dh * T(0.5) * trcp(th) - g) * iq;
     }
   }
 }
@@ -250,8 +271,9 @@ CR_HD void gamma_coef(T q, T* gam, T* dgam) {
 
 template <typename T>
 CR_HD void u_to_ab(T u0, T u1, T u2, T r, T* a, T* b) {
-  *a = (u1 + u2 - T(2) * u0) / (T(3) * r);
-  *b = (u2 - u1) / (T(1.7320508075688772935) * r);
+  const T ir = trcp(r);
+  *a = (u1 + u2 - T(2) * u0) * (T(1.0 / 3.0) * ir);
+  *b = (u2 - u1) * (T(0.57735026918962576451) * ir);
 }
 
 template <typename T>
@@ -331,30 +353,30 @@ CR_HD void log_se3(const T* Re, const T* te, T* w, T* rho, T* gam, T* dgam) {
       f = T(1) + x * (T(1.0 / 6.0) + x * T(3.0 / 40.0));  // theta / sin(theta)
     } else {
       T sn = tsqrt(x);
-      f = tatan2(sn, c) / sn;
+      f = tatan2(sn, c) * trcp(sn);
     }
     w[0] = f * v[0];
     w[1] = f * v[1];
     w[2] = f * v[2];
   } else {
     // near pi: (Re + Re^T)/2 = c I + (1 - c) n n^T; axis from the largest diagonal
-    T inv = T(1) / (T(1) - c);
+    T inv = trcp(T(1) - c);
     T d0 = (Re[0] - c) * inv, d1 = (Re[4] - c) * inv, d2 = (Re[8] - c) * inv;
     T n[3];
     if (d0 >= d1 && d0 >= d2) {
-      T s = tsqrt(d0);
+      T s = tsqrt(d0), is = T(0.5) * inv * trcp(s);
       n[0] = s;
-      n[1] = T(0.5) * (Re[1] + Re[3]) * inv / s;
-      n[2] = T(0.5) * (Re[2] + Re[6]) * inv / s;
+      n[1] = (Re[1] + Re[3]) * is;
+      n[2] = (Re[2] + Re[6]) * is;
     } else if (d1 >= d2) {
-      T s = tsqrt(d1);
-      n[0] = T(0.5) * (Re[1] + Re[3]) * inv / s;
+      T s = tsqrt(d1), is = T(0.5) * inv * trcp(s);
+      n[0] = (Re[1] + Re[3]) * is;
       n[1] = s;
-      n[2] = T(0.5) * (Re[5] + Re[7]) * inv / s;
+      n[2] = (Re[5] + Re[7]) * is;
     } else {
-      T s = tsqrt(d2);
-      n[0] = T(0.5) * (Re[2] + Re[6]) * inv / s;
-      n[1] = T(0.5) * (Re[5] + Re[7]) * inv / s;
+      T s = tsqrt(d2), is = T(0.5) * inv * trcp(s);
+      n[0] = (Re[2] + Re[6]) * is;
+      n[1] = (Re[5] + Re[7]) * is;
       n[2] = s;
     }
     T sn = dot3(n, v);
@@ -401,31 +423,36 @@ CR_HD void relative_pose(const T* R, const T* p, const T* Tt, T* Re, T* te) {
 // One segment's bound residuals in FP64 from its bending coordinates (eq. 9):
 // tendon hinges sq_lim max(0, |u_j| - u_max) and the bending hinge
 // sq_curv max(0, theta - theta_max).  ru[j] / rth are 0 when inactive.
-template <typename T>
-CR_HD void bound_residuals(const RobotT<T>& rb, const WeightsT<T>& w, int i, double a, double b, double* ru,
-                           double* sgn, double* rth) {
-  double u[3];
-  ab_to_u(a, b, rb.rd[i], u);
+// TH is the type the violations are formed in: FP64 where gradients are
+// reported (cost/gradient kernel), the kernel's own type inside the solver loop.
+template <typename TH, typename T>
+CR_HD void bound_residuals(const RobotT<T>& rb, const WeightsT<T>& w, int i, TH a, TH b, TH* ru, TH* sgn, TH* rth) {
+  const TH r = sizeof(TH) == 8 ? (TH)rb.rd[i] : (TH)rb.r[i];
+  const TH umax = sizeof(TH) == 8 ? (TH)rb.umaxd[i] : (TH)rb.umax[i];
+  const TH thmax = sizeof(TH) == 8 ? (TH)rb.theta_maxd : (TH)rb.theta_max;
+  TH u[3];
+  ab_to_u(a, b, r, u);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const double viol = fabs(u[j]) - rb.umaxd[i];
-    ru[j] = viol > 0.0 ? (double)w.sq_lim * viol : 0.0;
-    sgn[j] = u[j] < 0.0 ? -1.0 : 1.0;
+    const TH viol = fabs(u[j]) - umax;
+    ru[j] = viol > TH(0) ? (TH)w.sq_lim * viol : TH(0);
+    sgn[j] = u[j] < TH(0) ? TH(-1) : TH(1);
   }
-  const double vt = sqrt(a * a + b * b) - rb.theta_maxd;
-  *rth = vt > 0.0 ? (double)w.sq_curv * vt : 0.0;
+  const TH s = a * a + b * b;
+  // theta > theta_max  <=>  theta^2 > theta_max^2: the square root is taken only when active
+  *rth = s > thmax * thmax ? (TH)w.sq_curv * (tsqrt(s) - thmax) : TH(0);
 }
 
 template <int NS, typename T>
 CR_HD T bounds_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* z) {
-  double c = 0.0;
+  T c = T(0);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    double ru[3], sg[3], rth;
-    bound_residuals(rb, w, i, (double)z[2 * i], (double)z[2 * i + 1], ru, sg, &rth);
-    c += 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
+    T ru[3], sg[3], rth;
+    bound_residuals<T>(rb, w, i, z[2 * i], z[2 * i + 1], ru, sg, &rth);
+    c += T(0.5) * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
   }
-  return (T)c;
+  return c;
 }
 
 // packed lower-triangular index
@@ -437,34 +464,34 @@ template <int NS, int NZT, typename T>
 CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, int off, T* Hp, T* g, T& cost) {
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const double a = (double)z[2 * i], b = (double)z[2 * i + 1];
-    double ru[3], sg[3], rth;
-    bound_residuals(rb, w, i, a, b, ru, sg, &rth);
+    const T a = z[2 * i], b = z[2 * i + 1];
+    T ru[3], sg[3], rth;
+    bound_residuals<T>(rb, w, i, a, b, ru, sg, &rth);
     const int ca = off + 2 * i, cb = off + 2 * i + 1;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      if (ru[j] > 0.0) {
-        double ja, jb;
-        lift_row(j, rb.rd[i], &ja, &jb);
-        ja *= sg[j] * (double)w.sq_lim;
-        jb *= sg[j] * (double)w.sq_lim;
-        cost += (T)(0.5 * ru[j] * ru[j]);
-        g[ca] += (T)(ja * ru[j]);
-        g[cb] += (T)(jb * ru[j]);
-        Hp[tri(ca, ca)] += (T)(ja * ja);
-        Hp[tri(cb, ca)] += (T)(jb * ja);
-        Hp[tri(cb, cb)] += (T)(jb * jb);
+      if (ru[j] > T(0)) {
+        T ja, jb;
+        lift_row(j, rb.r[i], &ja, &jb);
+        ja *= sg[j] * w.sq_lim;
+        jb *= sg[j] * w.sq_lim;
+        cost += T(0.5) * ru[j] * ru[j];
+        g[ca] += ja * ru[j];
+        g[cb] += jb * ru[j];
+        Hp[tri(ca, ca)] += ja * ja;
+        Hp[tri(cb, ca)] += jb * ja;
+        Hp[tri(cb, cb)] += jb * jb;
       }
     }
-    if (rth > 0.0) {
-      const double th = sqrt(a * a + b * b);
-      const double ja = (double)w.sq_curv * a / th, jb = (double)w.sq_curv * b / th;
-      cost += (T)(0.5 * rth * rth);
-      g[ca] += (T)(ja * rth);
-      g[cb] += (T)(jb * rth);
-      Hp[tri(ca, ca)] += (T)(ja * ja);
-      Hp[tri(cb, ca)] += (T)(jb * ja);
-      Hp[tri(cb, cb)] += (T)(jb * jb);
+    if (rth > T(0)) {
+      const T ith = trcp(tsqrt(a * a + b * b));
+      const T ja = w.sq_curv * a * ith, jb = w.sq_curv * b * ith;
+      cost += T(0.5) * rth * rth;
+      g[ca] += ja * rth;
+      g[cb] += jb * rth;
+      Hp[tri(ca, ca)] += ja * ja;
+      Hp[tri(cb, ca)] += jb * ja;
+      Hp[tri(cb, cb)] += jb * jb;
     }
   }
 }
@@ -611,21 +638,21 @@ CR_HD T ik_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, con
 template <int N, typename T>
 CR_HD bool chol_solve(T* A, T* x) {
   bool ok = true;
+  T inv[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     T d = A[tri(j, j)];
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= A[tri(j, k)] * A[tri(j, k)];
     ok = ok && (d > T(0));
-    T ljj = tsqrt(d > T(0) ? d : T(1));
-    T inv = T(1) / ljj;
-    A[tri(j, j)] = ljj;
+    const T ljj = tsqrt(d > T(0) ? d : T(1));
+    inv[j] = trcp(ljj);
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       T v = A[tri(i, j)];
 #pragma unroll
       for (int k = 0; k < j; ++k) v -= A[tri(i, k)] * A[tri(j, k)];
-      A[tri(i, j)] = v * inv;
+      A[tri(i, j)] = v * inv[j];
     }
   }
 #pragma unroll
@@ -633,14 +660,14 @@ CR_HD bool chol_solve(T* A, T* x) {
     T v = x[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) v -= A[tri(i, k)] * x[k];
-    x[i] = v / A[tri(i, i)];
+    x[i] = v * inv[i];
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     T v = x[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) v -= A[tri(k, i)] * x[k];
-    x[i] = v / A[tri(i, i)];
+    x[i] = v * inv[i];
   }
   return ok;
 }
@@ -659,20 +686,20 @@ struct LMOpts {
 };
 
 template <int NS, typename T>
-CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam,
-                                      int iters, const LMOpts<T>& o, bool& failed, int& trials) {
+CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
+                 bool& failed, int& trials) {
   constexpr int NZ = 2 * NS;
   constexpr int NP = NZ * (NZ + 1) / 2;
   for (int it = 0; it < iters; ++it) {
     T Hp[NP], g[NZ], dl[NZ];
-    T c0 = ik_normal_eq<NS>(rb, w, Tt, z, Hp, g);
+    const T c0 = ik_normal_eq<NS>(rb, w, Tt, z, Hp, g);
     if (!tfinite(c0)) {
       failed = true;
       break;
     }
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
-      T hj = Hp[tri(j, j)];
+      const T hj = Hp[tri(j, j)];
       Hp[tri(j, j)] = hj + lam * (hj > T(1e-12) ? hj : T(1e-12));
       dl[j] = -g[j];
     }
@@ -689,7 +716,7 @@ CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T
     for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
       for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
-      T c = ik_cost<NS>(rb, w, Tt, zt, (T*)nullptr);
+      const T c = ik_cost<NS>(rb, w, Tt, zt, (T*)nullptr);
       ++trials;
       if (c <= c0 + T(1e-4) * alpha * gd) {
         acc = tr;
@@ -863,7 +890,7 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
     {
       double ru[3], sg[3], rth;
       const double ad = zd ? zd[2 * i] : (double)a, bd = zd ? zd[2 * i + 1] : (double)b;
-      bound_residuals(rb, w, i, ad, bd, ru, sg, &rth);
+      bound_residuals<double>(rb, w, i, ad, bd, ru, sg, &rth);
       double cb = 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
       cost += (T)cb;
       if (GRAD) {

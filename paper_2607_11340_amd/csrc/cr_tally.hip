@@ -65,6 +65,7 @@ CR_HD bool tfinite<CountT>(CountT x) {
 template <>
 struct Prec<CountT> {
   static constexpr int NT = Prec<float>::NT;
+  static constexpr double s_switch = Prec<float>::s_switch;
   static constexpr int NG = Prec<float>::NG;
   static constexpr double g_switch = Prec<float>::g_switch;
 };
