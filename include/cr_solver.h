@@ -174,6 +174,41 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
 size_t cr_solve_ik_workspace(const cr_robot* robot, int64_t P, int32_t S, const cr_opts* opts,
                              cr_dtype dtype);
 
+/* Path following (eq. 16 with the trajectory constraints of eq. 12-15) for P
+ * problems of H+1 waypoints, two-stage as in Algorithm 1 (Sec. IV-B): stage 1
+ * runs k_init LM iterations over whole trajectories (block-pentadiagonal normal
+ * equations, exact block Cholesky) on every seed in `dtype`; SelectTop keeps
+ * n_final per problem ranked by total cost; stage 2 refines them in FP64; the
+ * answer is the argmin of the final cost.
+ *   T_ref  [device, double] [12][(H+1)*P], column p*(H+1) + t.
+ *   u_seed [device, double] [3n][(H+1)*S*P], column (p*S + s)*(H+1) + t (the
+ *          exploration stage's trajectories, e.g. per-waypoint IK, Sec. IV-B).
+ *   u_out  [device, double] [3n][(H+1)*P]; err_out [2][P]: largest position /
+ *          rotation error over the waypoints; status_out [P].
+ *   spheres as in cr_cost_grad but double; ws/ws_bytes as in cr_solve_ik
+ *   (size from cr_solve_traj_workspace).
+ * Errors: CR_EINVAL for H > 255, S > 4096 or when (H+1) waypoints and the
+ * spheres exceed 64 KiB of LDS per workgroup. */
+cr_status cr_solve_path(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                        const void* T_ref, int32_t S, const void* u_seed, const cr_weights* weights,
+                        const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                        size_t ws_bytes, cr_dtype dtype, hipStream_t stream);
+
+/* Trajectory planning (eq. 11-15, endpoints penalised by eq. 17) between
+ * u_start and u_goal, H >= 1; otherwise as cr_solve_path.
+ *   u_start_goal [device, double] [6n][P]: u_start (c < 3n) then u_goal.
+ *   err_out: largest endpoint position / rotation error against the start and
+ *   goal poses; status adds CR_COLLISION for any penetrating backbone point. */
+cr_status cr_solve_traj(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                        const void* u_start_goal, int32_t S, const void* u_seed,
+                        const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
+                        int32_t* status_out, void* ws, size_t ws_bytes, cr_dtype dtype,
+                        hipStream_t stream);
+
+/* Workspace bytes cr_solve_path / cr_solve_traj need (0 on invalid arguments). */
+size_t cr_solve_traj_workspace(const cr_robot* robot, int64_t P, int32_t H, int32_t S,
+                               const cr_opts* opts, cr_dtype dtype);
+
 /* SelectTop of Algorithm 1 on given candidates, per problem: order by e
  * ascending (ties: lower index; failed candidates never kept), greedily keep
  * candidates, a candidate within dup_eps (infinity norm over nz coordinates) of

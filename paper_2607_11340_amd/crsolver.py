@@ -27,7 +27,8 @@ F32, F64 = 0, 1
 KIND = {"ik": 0, "path": 1, "traj": 2}
 SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 
-EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_select_top",
+EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_path", "cr_solve_traj",
+           "cr_solve_traj_workspace", "cr_select_top",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_status_string", "cr_last_error")
 
 
@@ -129,6 +130,10 @@ def _load():
     L.cr_fk.argtypes = [R, i64, vp, i64, vp, vp, vp, C.c_int, vp]
     L.cr_cost_grad.argtypes = [i32, R, S, W, i64, i32, i32, vp, vp, vp, vp, vp, C.c_int, vp]
     L.cr_solve_ik.argtypes = [R, S, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
+    L.cr_solve_path.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
+    L.cr_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
+    L.cr_solve_traj_workspace.argtypes = [R, i64, i32, i32, O, C.c_int]
+    L.cr_solve_traj_workspace.restype = C.c_size_t
     L.cr_solve_ik_workspace.argtypes = [R, i64, i32, O, C.c_int]
     L.cr_solve_ik_workspace.restype = C.c_size_t
     L.cr_select_top.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, C.c_int, vp]
@@ -140,7 +145,8 @@ def _load():
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
-    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_select_top", "cr_timing_read", "cr_ik_flop_tally"):
+    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_path", "cr_solve_traj", "cr_select_top",
+                 "cr_timing_read", "cr_ik_flop_tally"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -247,6 +253,55 @@ def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights
                            C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype),
                            _stream(T_target)))
     return u_out, err, st
+
+
+def traj_workspace_bytes(robot: Robot, P: int, H: int, S: int, opts: Opts, dtype) -> int:
+    rc, oc = robot.c(), opts.c()
+    return int(lib.cr_solve_traj_workspace(C.byref(rc), P, H, S, C.byref(oc), _dt(dtype)))
+
+
+def _solve_traj(kind: str, robot: Robot, task: torch.Tensor, u_seed: torch.Tensor, H: int, weights, opts, dtype,
+                spheres, workspace, out):
+    weights = weights or Weights()
+    opts = opts or Opts(n_final=4, k_init=100, k_final=20)
+    n, T = robot.n, H + 1
+    P = task.shape[1] // (T if kind == "path" else 1)
+    S = u_seed.shape[1] // max(T * P, 1)
+    if kind == "path":
+        _need(task, (12, T * P), torch.float64, "T_ref")
+    else:
+        _need(task, (6 * n, P), torch.float64, "u_start_goal")
+    _need(u_seed, (3 * n, T * S * P), torch.float64, "u_seed")
+    dev = task.device
+    if out is None:
+        out = (torch.empty((3 * n, T * P), dtype=torch.float64, device=dev),
+               torch.empty((2, P), dtype=torch.float64, device=dev),
+               torch.empty((P,), dtype=torch.int32, device=dev))
+    u_out, err, st = out
+    rc, wc, oc = robot.c(), weights.c(), opts.c()
+    sc = _spheres_c(spheres, torch.float64)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    fn = lib.cr_solve_path if kind == "path" else lib.cr_solve_traj
+    _check(fn(C.byref(rc), C.byref(sc), P, H, _ptr(task), S, _ptr(u_seed), C.byref(wc), C.byref(oc), _ptr(u_out),
+              _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype), _stream(task)))
+    return u_out, err, st
+
+
+def solve_path(robot: Robot, T_ref: torch.Tensor, u_seed: torch.Tensor, H: int, weights: Weights = None,
+               opts: Opts = None, dtype=torch.float32, spheres=None, workspace=None, out=None):
+    """Two-stage path following (eq. 16).  T_ref [12, (H+1)*P] float64 (column p*(H+1)+t),
+    u_seed [3n, (H+1)*S*P] float64 (column (p*S+s)*(H+1)+t).  Returns (u [3n, (H+1)*P],
+    err [2, P] (largest position m / rotation rad error over waypoints), status [P])."""
+    return _solve_traj("path", robot, T_ref, u_seed, H, weights, opts, dtype, spheres, workspace, out)
+
+
+def solve_traj(robot: Robot, u_start_goal: torch.Tensor, u_seed: torch.Tensor, H: int, weights: Weights = None,
+               opts: Opts = None, dtype=torch.float32, spheres=None, workspace=None, out=None):
+    """Two-stage trajectory planning (eq. 11-15).  u_start_goal [6n, P] float64 (start then
+    goal tendon displacements), u_seed as in solve_path.  err: largest endpoint error."""
+    return _solve_traj("traj", robot, u_start_goal, u_seed, H, weights, opts, dtype, spheres, workspace, out)
 
 
 def select_top(z: torch.Tensor, e: torch.Tensor, pen: torch.Tensor, failed, P: int, S: int, n_final: int,

@@ -249,6 +249,51 @@ cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const v
   return launch_select(P, S, nz, z, e, pen, failed, n_final, dup_eps, idx_out, dtype, stream);
 }
 
+static cr_status check_traj_args(const cr_robot* robot, const cr_spheres* spheres, const cr_weights* weights,
+                                 const cr_opts* opts, int64_t P, int32_t H, int32_t S, int kind, cr_dtype dtype) {
+  cr_status rc;
+  if ((rc = check_robot(robot)) != CR_OK || (rc = check_dtype(dtype)) != CR_OK || (rc = check_opts(opts)) != CR_OK ||
+      (rc = check_weights(weights)) != CR_OK)
+    return rc;
+  if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
+  if (H < (kind == CR_KIND_TRAJ ? 1 : 0) || H > 255) return fail(CR_EINVAL, "H=%d out of range", H);
+  if (P * (int64_t)S * (H + 1) > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "batch too large");
+  if (spheres && spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
+  if (spheres && spheres->n_sph > 0) {
+    if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
+    if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
+    const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
+    if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
+  }
+  return CR_OK;
+}
+
+static cr_status solve_traj_common(int kind, const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                                   const void* task, int32_t S, const void* u_seed, const cr_weights* weights,
+                                   const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                                   size_t ws_bytes, cr_dtype dtype, hipStream_t stream) {
+  cr_status rc = check_traj_args(robot, spheres, weights, opts, P, H, S, kind, dtype);
+  if (rc != CR_OK) return rc;
+  if (P == 0) return CR_OK;
+  if (!task || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
+  const size_t need = traj_workspace_bytes(*robot, P, S, H, *opts, dtype);
+  void* mem = ws;
+  if (ws) {
+    if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  } else {
+    rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
+    if (rc != CR_OK) return rc;
+  }
+  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  rc = launch_solve_traj(kind, *robot, sp, P, H, (const double*)task, S, (const double*)u_seed, *weights, *opts,
+                         (double*)u_out, (double*)err_out, status_out, mem, dtype, stream);
+  if (!ws) {
+    cr_status rc2 = check_hip(hipFreeAsync(mem, stream), "hipFreeAsync(workspace)");
+    if (rc == CR_OK) rc = rc2;
+  }
+  return rc;
+}
+
 void cr_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
   timer_release_all();
@@ -282,6 +327,30 @@ cr_status cr_ik_flop_tally(const cr_robot* robot, const cr_weights* weights, con
     return rc;
   if (n < 1 || !T_target || !u_seed || !out) return fail(CR_EINVAL, "need n >= 1 and non-NULL host arrays");
   return tally_ik_dispatch(*robot, *weights, *opts, n, T_target, u_seed, out);
+}
+
+cr_status cr_solve_path(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H, const void* T_ref,
+                        int32_t S, const void* u_seed, const cr_weights* weights, const cr_opts* opts, void* u_out,
+                        void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, cr_dtype dtype,
+                        hipStream_t stream) {
+  return solve_traj_common(CR_KIND_PATH, robot, spheres, P, H, T_ref, S, u_seed, weights, opts, u_out, err_out,
+                           status_out, ws, ws_bytes, dtype, stream);
+}
+
+cr_status cr_solve_traj(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                        const void* u_start_goal, int32_t S, const void* u_seed, const cr_weights* weights,
+                        const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes,
+                        cr_dtype dtype, hipStream_t stream) {
+  return solve_traj_common(CR_KIND_TRAJ, robot, spheres, P, H, u_start_goal, S, u_seed, weights, opts, u_out, err_out,
+                           status_out, ws, ws_bytes, dtype, stream);
+}
+
+size_t cr_solve_traj_workspace(const cr_robot* robot, int64_t P, int32_t H, int32_t S, const cr_opts* opts,
+                               cr_dtype dtype) {
+  if (check_robot(robot) != CR_OK || check_opts(opts) != CR_OK || check_dtype(dtype) != CR_OK || P < 0 || S < 1 ||
+      H < 0 || H > 255)
+    return 0;
+  return traj_workspace_bytes(*robot, P, S, H, *opts, dtype);
 }
 
 cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* spheres, const cr_weights* weights,

@@ -1007,3 +1007,227 @@ CR_HD void gz_to_gu(T ga, T gb, T r, T* gu) {
 }
 
 }  // namespace crk
+
+// ===========================================================================
+// Gauss-Newton blocks of one configuration for the trajectory solvers: pose
+// rows (if a target is given), bound rows, clearance rows of every active
+// point/sphere pair, and the tip position with its Jacobian (for the
+// path-length term, which couples neighbouring waypoints).
+// ===========================================================================
+
+namespace crk {
+
+// Adds the 6 pose rows of log(T_ee^-1 T_t) to Hp, g and returns their cost.
+// Columns: for coordinate k the spatial twist (W[k], dp[k]) of the tip, with
+// dp already including the lever arm to the tip.
+template <int NZ, typename T>
+CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (*dp)[3], const T* Tt, T* Hp,
+                  T* g) {
+  T Re[9], te[3], om[3], rho[3], gam, dgam;
+  relative_pose(Rc, pc, Tt, Re, te);
+  log_se3<T, true>(Re, te, om, rho, &gam, &dgam);
+  const T r[6] = {w.w_pos * rho[0], w.w_pos * rho[1], w.w_pos * rho[2],
+                  w.w_rot * om[0],  w.w_rot * om[1],  w.w_rot * om[2]};
+  T u1[3], u2[3];
+  cross3(om, te, u1);
+  cross3(om, u1, u2);
+  T J[NZ][6];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    T Jv[3], Jw[3], t1[3], t2[3], y[3], x[3], Vx[3];
+    mtv3(Rc, dp[k], Jv);
+    mtv3(Rc, W[k], Jw);
+    cross3(om, Jw, t1);
+    cross3(om, t1, t2);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) y[m] = Jw[m] - T(0.5) * t1[m] + gam * t2[m];
+    cross3(te, Jw, t1);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) x[m] = Jv[m] - t1[m];
+    cross3(om, x, t1);
+    cross3(om, t1, t2);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Vx[m] = x[m] - T(0.5) * t1[m] + gam * t2[m];
+    T ty[3], u1y[3], wty[3];
+    cross3(te, y, ty);
+    cross3(u1, y, u1y);
+    cross3(om, ty, wty);
+    const T s2 = T(2) * dgam * dot3(om, y);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      J[k][m] = -w.w_pos * (Vx[m] + T(0.5) * ty[m] + s2 * u2[m] - gam * (u1y[m] + wty[m]));
+      J[k][3 + m] = -w.w_rot * y[m];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    T acc = T(0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc += J[k][m] * r[m];
+    g[k] += acc;
+#pragma unroll
+    for (int l = 0; l <= k; ++l) {
+      T h = T(0);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) h += J[k][m] * J[l][m];
+      Hp[tri(k, l)] += h;
+    }
+  }
+  return T(0.5) * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
+}
+
+// Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
+// tip position and its Jacobian.  Tt may be NULL (no pose rows).  TC is the
+// chain type (FP64 when spheres are present, as in config_forward).
+template <int NS, typename T, typename TC>
+CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const T* sph, int M, int64_t ms,
+                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[2 * NS]) {
+  constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) Hp[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) g[k] = T(0);
+  T cost = T(0);
+  TC Rc[9], pc[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? TC(1) : TC(0);
+  pc[0] = pc[1] = pc[2] = TC(0);
+  T W[NZ][3], Pd[NZ][3], pe[NS][3];
+  const int K = rb.K;
+  const T slack = sizeof(T) < sizeof(TC) ? T(1.0001) : T(1);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const TC ac = (TC)z[2 * i], bc = (TC)z[2 * i + 1];
+    const TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    const TC s = ac * ac + bc * bc;
+    if (M > 0) {
+      const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
+      const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
+      const T rf = (T)(ri + marg);
+      for (int k = 1; k <= K; ++k) {
+        const TC sg = TC(k) / TC(K);
+        ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
+        const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+        TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+        TC x[3];
+        mv3(Rc, dk, x);
+        x[0] += pc[0];
+        x[1] += pc[1];
+        x[2] += pc[2];
+        const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
+        for (int m = 0; m < M; ++m) {
+          const T* sm = sph + m * ms;
+          const T e0 = xf[0] - sm[0], e1 = xf[1] - sm[cs], e2 = xf[2] - sm[2 * cs];
+          const T rq = (sm[3 * cs] + rf) * slack;
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+          const TC d0 = x[0] - (TC)sm[0], d1 = x[1] - (TC)sm[cs], d2 = x[2] - (TC)sm[2 * cs];
+          const TC reach = (TC)sm[3 * cs] + ri + marg;
+          const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const TC viol = reach - dist;
+          if (!(viol > TC(0))) continue;
+          const T rr = (T)((TC)w.sq_coll * viol);
+          // residual sq_coll (reach - |x - c|): row = -sq_coll n^T dx/dz
+          T nvec[3];
+          if (dist > TC(0)) {
+            const TC id = TC(1) / dist;
+            nvec[0] = (T)(d0 * id);
+            nvec[1] = (T)(d1 * id);
+            nvec[2] = (T)(d2 * id);
+          } else {
+            nvec[0] = nvec[1] = T(0);
+            nvec[2] = T(1);
+          }
+          T row[NZ];
+#pragma unroll
+          for (int q = 0; q < NZ; ++q) row[q] = T(0);
+#pragma unroll
+          for (int j = 0; j < NS; ++j) {
+            if (j < i) {
+              T xm[3] = {xf[0] - pe[j][0], xf[1] - pe[j][1], xf[2] - pe[j][2]}, c3[3];
+              cross3(xm, nvec, c3);
+              row[2 * j] = -w.sq_coll * (dot3(W[2 * j], c3) + dot3(Pd[2 * j], nvec));
+              row[2 * j + 1] = -w.sq_coll * (dot3(W[2 * j + 1], c3) + dot3(Pd[2 * j + 1], nvec));
+            }
+          }
+          {
+            TC nq[3] = {(TC)nvec[0], (TC)nvec[1], (TC)nvec[2]}, q[3];
+            mtv3(Rc, nq, q);
+            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+            row[2 * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
+            row[2 * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
+          }
+          cost += T(0.5) * rr * rr;
+#pragma unroll
+          for (int k1 = 0; k1 < NZ; ++k1) {
+            if (k1 <= 2 * i + 1) {
+              g[k1] += row[k1] * rr;
+#pragma unroll
+              for (int k2 = 0; k2 <= k1; ++k2) Hp[tri(k1, k2)] += row[k1] * row[k2];
+            }
+          }
+        }
+      }
+    }
+    ArcCoef<TC> c = arc_coef<TC, true>(s);
+    TC Ri[9], di[3];
+    seg_R_d(ac, bc, Lc, c, Ri, di);
+    {
+      TC wa[3] = {-c.C * ac * bc, TC(1) - c.C * bc * bc, -c.A * bc};
+      TC wb[3] = {c.C * ac * ac - TC(1), c.C * ac * bc, c.A * ac};
+      TC dda[3] = {Lc * (c.A + TC(2) * ac * ac * c.Ap), Lc * TC(2) * ac * bc * c.Ap, Lc * TC(2) * ac * c.Bp};
+      TC ddb[3] = {Lc * TC(2) * ac * bc * c.Ap, Lc * (c.A + TC(2) * bc * bc * c.Ap), Lc * TC(2) * bc * c.Bp};
+      TC t0[3];
+      mv3(Rc, wa, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) W[2 * i][q] = (T)t0[q];
+      mv3(Rc, wb, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) W[2 * i + 1][q] = (T)t0[q];
+      mv3(Rc, dda, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Pd[2 * i][q] = (T)t0[q];
+      mv3(Rc, ddb, t0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Pd[2 * i + 1][q] = (T)t0[q];
+    }
+    TC q[3], Rn[9];
+    mv3(Rc, di, q);
+    pc[0] += q[0];
+    pc[1] += q[1];
+    pc[2] += q[2];
+    mm3(Rc, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+    pe[i][0] = (T)pc[0];
+    pe[i][1] = (T)pc[1];
+    pe[i][2] = (T)pc[2];
+  }
+  T Rt[9], pt[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rt[k] = (T)Rc[k];
+  pt[0] = (T)pc[0];
+  pt[1] = (T)pc[1];
+  pt[2] = (T)pc[2];
+  // tip displacement rate of every coordinate (spatial, world frame)
+  T dp[NZ][3];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    const int j = k / 2;
+    T rel[3] = {pt[0] - pe[j][0], pt[1] - pe[j][1], pt[2] - pe[j][2]}, c3[3];
+    cross3(W[k], rel, c3);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      dp[k][m] = Pd[k][m] + c3[m];
+      Jp[m][k] = dp[k][m];
+    }
+  }
+  ptip[0] = pt[0];
+  ptip[1] = pt[1];
+  ptip[2] = pt[2];
+  if (Tt) cost += pose_rows<NZ>(w, Rt, pt, W, dp, Tt, Hp, g);
+  bounds_normal_eq<NS, NZ>(rb, w, z, 0, Hp, g, cost);
+  return cost;
+}
+
+}  // namespace crk

@@ -67,17 +67,17 @@ __device__ __forceinline__ bool key_less(T ea, int fa, T eb, int fb) {
   return (fa & 0xffff) < (fb & 0xffff);
 }
 
+// Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zs_c].
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_select(int64_t P, int S, int Spad, int nz, const T* __restrict__ z, const T* __restrict__ e,
-             const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final, T dup_eps,
-             int32_t* __restrict__ idx_out) {
+    k_select(int64_t P, int S, int Spad, int nz, const T* __restrict__ z, int64_t zs_m, int64_t zs_c,
+             const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final,
+             T dup_eps, int32_t* __restrict__ idx_out) {
   extern __shared__ unsigned char smem[];
   T* se = reinterpret_cast<T*>(smem);
   int* sf = reinterpret_cast<int*>(se + Spad);
   unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad);
   const int64_t p = blockIdx.x;
-  const int64_t B = P * (int64_t)S;
   for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
     if (i < S) {
       T ev = e[p * S + i];
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256)
     for (int k = 0; k < nk && dup < 0; ++k) {
       T dmax = T(0);
       for (int m = 0; m < nz; ++m) {
-        T d = fabs(z[m * B + p * S + c] - z[m * B + p * S + kept[k]]);
+        T d = fabs(z[m * zs_m + (p * S + c) * zs_c] - z[m * zs_m + (p * S + kept[k]) * zs_c]);
         dmax = d > dmax ? d : dmax;
       }
       if (dmax <= dup_eps) dup = k;
@@ -368,9 +368,9 @@ cr_status launch_solve_ik(const cr_robot& rb, int64_t P, const double* Tt, int32
 #undef CR_IK_CASE
 }
 
-cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
-                        const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out, cr_dtype dtype,
-                        hipStream_t st) {
+cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
+                                const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
+                                int32_t* idx_out, cr_dtype dtype, hipStream_t st) {
   int Spad = 1;
   while (Spad < S) Spad <<= 1;
   const size_t tb = dtype == CR_F64 ? 8 : 4;
@@ -378,12 +378,19 @@ cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const v
   if (P == 0) return CR_OK;
   if (dtype == CR_F64)
     hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
-                       (const double*)z, (const double*)e, (const double*)pen, failed, (int)n_final, dup_eps, idx_out);
+                       (const double*)z, zs_m, zs_c, (const double*)e, (const double*)pen, failed, (int)n_final,
+                       dup_eps, idx_out);
   else
     hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
-                       (const float*)z, (const float*)e, (const float*)pen, failed, (int)n_final, (float)dup_eps,
-                       idx_out);
+                       (const float*)z, zs_m, zs_c, (const float*)e, (const float*)pen, failed, (int)n_final,
+                       (float)dup_eps, idx_out);
   return check_hip(hipGetLastError(), "k_select");
+}
+
+cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
+                        const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out, cr_dtype dtype,
+                        hipStream_t st) {
+  return launch_select_strided(P, S, nz, z, P * (int64_t)S, 1, e, pen, failed, n_final, dup_eps, idx_out, dtype, st);
 }
 
 }  // namespace crk

@@ -43,6 +43,15 @@ cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const v
                         const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out,
                         cr_dtype dtype, hipStream_t stream);
 
+cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
+                                const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
+                                int32_t* idx_out, cr_dtype dtype, hipStream_t st);
+
+size_t traj_workspace_bytes(const cr_robot& rb, int64_t P, int S, int H, const cr_opts& o, cr_dtype dt);
+cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
+                            int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,
+                            double* err_out, int32_t* status_out, void* wsmem, cr_dtype dtype, hipStream_t st);
+
 cr_status launch_cost_grad(int kind, const cr_robot& rb, const cr_spheres* sp, const cr_weights& w, int64_t P, int H,
                            int S, const void* task, const void* u, void* cost, void* grad, const void* gscale,
                            cr_dtype dtype, hipStream_t st);

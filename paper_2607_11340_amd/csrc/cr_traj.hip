@@ -1,0 +1,931 @@
+// cr_traj.hip -- path following (eq. 16) and trajectory planning (eq. 11-15):
+// Levenberg-Marquardt over whole trajectories inside the two-stage template.
+//
+// Per LM iteration three kernels run over every trajectory (problem x seed):
+//   k_traj_build   one workgroup per trajectory, one lane per waypoint: each lane
+//                  forms its Gauss-Newton block (pose, bounds, clearance rows)
+//                  and, through LDS, the smoothness and path-length couplings to
+//                  waypoints t-1 and t-2; writes the block rows of
+//                  H = J^T J (diagonal, first and second sub-diagonal blocks) and g.
+//   k_traj_solve   one lane per trajectory: damping, block Cholesky of the
+//                  block-pentadiagonal H + lambda D (the exact banded factor),
+//                  forward and backward substitution, g.delta.
+//   k_traj_search  one workgroup per trajectory: backtracking line search; the
+//                  trial cost is block-reduced, so accept/reject is uniform per
+//                  workgroup; updates z and lambda.
+// Per trajectory and waypoint the workspace holds one record
+//   [ L_tt (packed, NP) | H_{t,t-1} -> L_{t,t-1} (NZ^2) | H_{t,t-2} -> L_{t,t-2} (NZ^2) | g (NZ) | y, delta (NZ) ]
+// and z is stored trajectory-major, waypoint, coordinate: [traj][t][k].
+#include <float.h>
+
+#include "cr_internal.h"
+
+namespace crk {
+
+template <typename T>
+struct TrajArgs {
+  int kind;                 // CR_KIND_PATH or CR_KIND_TRAJ
+  int H;                    // waypoints t = 0..H
+  int64_t P;                // problems
+  int per;                  // trajectories per problem in this launch
+  const double* task;       // PATH: poses [12][(H+1) P]; TRAJ: [6n][P]
+  const double* sph;        // spheres [4][sld] or NULL
+  int64_t sld;
+  int M, per_problem;
+};
+
+template <int NS>
+struct Rec {
+  static constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+  static constexpr int OL = 0, OB = NP, OC = NP + NZ * NZ, OG = NP + 2 * NZ * NZ, OY = OG + NZ;
+  static constexpr int SIZE = OY + NZ;
+};
+
+template <typename T>
+__device__ __forceinline__ T block_sum_all(T v, T* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  T s = T(0);
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_spheres(const TrajArgs<T>& ta, int64_t p, T* s_sph) {
+  for (int i = threadIdx.x; i < 4 * ta.M; i += blockDim.x) {
+    const int m = i >> 2, c = i & 3;
+    s_sph[i] = (T)ta.sph[c * ta.sld + (ta.per_problem ? p * ta.M : 0) + m];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pose(const TrajArgs<T>& ta, int64_t p, int t, T* Tt) {
+  const int64_t Tn = ta.H + 1;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) Tt[c] = (T)ta.task[c * (ta.P * Tn) + p * Tn + t];
+}
+
+// Cost of one trajectory (value only), all lanes of the workgroup participate;
+// lane t evaluates waypoint t.  If pen != NULL the collision part alone is also
+// returned (every other weight zeroed).  s_u, s_p: LDS scratch of (H+1)*3n and
+// (H+1)*3 values.
+template <int NS, typename T>
+__device__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int64_t p, const T* z,
+                       const T* s_sph, T* s_u, T* s_p, T* s_red, T* pen) {
+  constexpr int NU = 3 * NS;
+  const int t = threadIdx.x, H = ta.H;
+  const bool act = t <= H;
+  T cst = T(0), cpen = T(0);
+  if (act) {
+    Fwd<NS, T> f;
+    cst = ta.M > 0 ? config_forward<NS, T, false, double>(rb, w, z, s_sph, ta.M, 4, 1, f)
+                   : config_forward<NS, T, false>(rb, w, z, s_sph, 0, 4, 1, f);
+    if (pen && ta.M > 0) {
+      WeightsT<T> wc = w;
+      wc.sq_lim = wc.sq_curv = T(0);
+      Fwd<NS, T> f2;
+      cpen = config_forward<NS, T, false, double>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
+    }
+    if (ta.kind == CR_KIND_PATH) {
+      T Tt[12], ft[3], tq[3];
+      load_pose(ta, p, t, Tt);
+      cst += pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T u[3];
+      ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], u);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = u[j];
+    }
+    s_p[3 * t] = f.p[0];
+    s_p[3 * t + 1] = f.p[1];
+    s_p[3 * t + 2] = f.p[2];
+  }
+  __syncthreads();
+  if (act) {
+    const T idt = T(1) / w.dt, idt2 = idt * idt;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      if (t >= 1) {
+        const T v = (s_u[t * NU + m] - s_u[(t - 1) * NU + m]) * idt;
+        const T rr = w.sq_vel * v;
+        cst += T(0.5) * rr * rr;
+        if (w.has_vmax && fabs(v) > w.v_max) {
+          const T hr = w.sq_lim * (fabs(v) - w.v_max);
+          cst += T(0.5) * hr * hr;
+        }
+      }
+      if (t >= 2) {
+        const T a = (s_u[t * NU + m] - T(2) * s_u[(t - 1) * NU + m] + s_u[(t - 2) * NU + m]) * idt2;
+        const T rr = w.sq_acc * a;
+        cst += T(0.5) * rr * rr;
+        if (w.has_amax && fabs(a) > w.a_max) {
+          const T hr = w.sq_lim * (fabs(a) - w.a_max);
+          cst += T(0.5) * hr * hr;
+        }
+      }
+    }
+    if (ta.kind == CR_KIND_TRAJ) {
+      if (t >= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T rr = w.sq_len * (s_p[3 * t + c] - s_p[3 * (t - 1) + c]);
+          cst += T(0.5) * rr * rr;
+        }
+      }
+      if (t == 0 || t == H) {
+        const int off = t == 0 ? 0 : NU;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          T za, zb;
+          u_to_ab((T)ta.task[(off + 3 * i) * ta.P + p], (T)ta.task[(off + 3 * i + 1) * ta.P + p],
+                  (T)ta.task[(off + 3 * i + 2) * ta.P + p], rb.r[i], &za, &zb);
+          const T ra = w.sq_eq * (z[2 * i] - za), rb2 = w.sq_eq * (z[2 * i + 1] - zb);
+          cst += T(0.5) * (ra * ra + rb2 * rb2);
+        }
+      }
+    }
+  }
+  const T total = block_sum_all(cst, s_red);
+  if (pen) *pen = block_sum_all(cpen, s_red);
+  return total;
+}
+
+// ---------------------------------------------------------------------------
+
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_traj_init(int64_t nt, int Tn, const double* __restrict__ useed, const double* __restrict__ rr, T* __restrict__ Z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t B = nt * Tn;
+  if (i >= B) return;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double a, b;
+    u_to_ab(useed[(3 * s) * B + i], useed[(3 * s + 1) * B + i], useed[(3 * s + 2) * B + i], rr[s], &a, &b);
+    Z[i * 2 * NS + 2 * s] = (T)a;
+    Z[i * 2 * NS + 2 * s + 1] = (T)b;
+  }
+}
+
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_traj_build(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, const T* __restrict__ Z, T* __restrict__ blk,
+                 T* __restrict__ cost0, int32_t* __restrict__ failed) {
+  constexpr int NZ = 2 * NS, NU = 3 * NS, NP = NZ * (NZ + 1) / 2;
+  using R = Rec<NS>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int H = ta.H, Tn = H + 1;
+  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_u = s_sph + 4 * ta.M;
+  T* s_p = s_u + Tn * NU;
+  T* s_jp = s_p + Tn * 3;
+  T* s_red = s_jp + Tn * 3 * NZ;
+  const int64_t traj = blockIdx.x;
+  const int64_t p = traj / ta.per;
+  if (failed[traj]) return;  // uniform per workgroup
+  stage_spheres(ta, p, s_sph);
+  __syncthreads();
+  const int t = threadIdx.x;
+  const bool act = t < Tn;
+  T z[NZ], Hp[NP], g[NZ], ptip[3], Jp[3][NZ];
+  T cst = T(0);
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) z[k] = Z[(traj * Tn + t) * NZ + k];
+    T Tt[12];
+    if (ta.kind == CR_KIND_PATH) load_pose(ta, p, t, Tt);
+    const T* tp = ta.kind == CR_KIND_PATH ? Tt : nullptr;
+    cst = ta.M > 0 ? local_normal_eq<NS, T, double>(rb, w, z, s_sph, ta.M, 4, 1, tp, Hp, g, ptip, Jp)
+                   : local_normal_eq<NS, T, T>(rb, w, z, s_sph, 0, 4, 1, tp, Hp, g, ptip, Jp);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T u[3];
+      ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], u);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = u[j];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s_p[3 * t + c] = ptip[c];
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) s_jp[(t * 3 + c) * NZ + k] = Jp[c][k];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T Bm[NZ][NZ], Cm[NZ][NZ];
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) Bm[a][b] = Cm[a][b] = T(0);
+    const T idt = T(1) / w.dt, idt2 = idt * idt;
+    // tendon velocity / acceleration smoothness and their hinges (linear in the lifts)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int ca = 2 * i, cb = 2 * i + 1;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int m = 3 * i + j;
+        T ja, jb;
+        lift_row(j, rb.r[i], &ja, &jb);
+        const T o00 = ja * ja, o01 = ja * jb, o11 = jb * jb;
+        auto add_self = [&](T c1, T rr) {  // row with coefficient c1 on u_t
+          g[ca] += c1 * rr * ja;
+          g[cb] += c1 * rr * jb;
+          Hp[tri(ca, ca)] += c1 * c1 * o00;
+          Hp[tri(cb, ca)] += c1 * c1 * o01;
+          Hp[tri(cb, cb)] += c1 * c1 * o11;
+        };
+        auto add_off = [&](T (*X)[NZ], T c1c2) {  // coupling block entry c1 c2 lift^T lift
+          X[ca][ca] += c1c2 * o00;
+          X[ca][cb] += c1c2 * o01;
+          X[cb][ca] += c1c2 * o01;
+          X[cb][cb] += c1c2 * o11;
+        };
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int tau = t + k;
+          if (tau >= 1 && tau <= H) {
+            const T v = (s_u[tau * NU + m] - s_u[(tau - 1) * NU + m]) * idt;
+            const T rr = w.sq_vel * v;
+            const T cs = (k == 0 ? idt : -idt) * w.sq_vel;
+            if (k == 0) cst += T(0.5) * rr * rr;
+            add_self(cs, rr);
+            if (k == 0) add_off(Bm, cs * (-idt * w.sq_vel));
+            if (w.has_vmax && fabs(v) > w.v_max) {
+              const T sg = v < T(0) ? -w.sq_lim : w.sq_lim;
+              const T hr = w.sq_lim * (fabs(v) - w.v_max);
+              const T hs = sg * (k == 0 ? idt : -idt);
+              if (k == 0) cst += T(0.5) * hr * hr;
+              add_self(hs, hr);
+              if (k == 0) add_off(Bm, hs * (sg * -idt));
+            }
+          }
+        }
+        const T cf[3] = {T(1), T(-2), T(1)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int tau = t + k;
+          if (tau >= 2 && tau <= H) {
+            const T a = (s_u[tau * NU + m] - T(2) * s_u[(tau - 1) * NU + m] + s_u[(tau - 2) * NU + m]) * idt2;
+            const T rr = w.sq_acc * a;
+            const T cs = cf[k] * idt2 * w.sq_acc;
+            if (k == 0) cst += T(0.5) * rr * rr;
+            add_self(cs, rr);
+            if (k <= 1) add_off(Bm, cs * cf[k + 1] * idt2 * w.sq_acc);
+            if (k == 0) add_off(Cm, cs * cf[2] * idt2 * w.sq_acc);
+            if (w.has_amax && fabs(a) > w.a_max) {
+              const T sg = a < T(0) ? -w.sq_lim : w.sq_lim;
+              const T hr = w.sq_lim * (fabs(a) - w.a_max);
+              const T hs = sg * cf[k] * idt2;
+              if (k == 0) cst += T(0.5) * hr * hr;
+              add_self(hs, hr);
+              if (k <= 1) add_off(Bm, hs * sg * cf[k + 1] * idt2);
+              if (k == 0) add_off(Cm, hs * sg * cf[2] * idt2);
+            }
+          }
+        }
+      }
+    }
+    if (ta.kind == CR_KIND_TRAJ) {
+      // tip path length, eq. (11) squared, couples t and t - 1
+      const T sl2 = w.sq_len * w.sq_len;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T sw = T(0);  // multiplicity of J_p^T J_p on the diagonal block
+        T gr = T(0);
+        if (t >= 1) {
+          const T rr = w.sq_len * (s_p[3 * t + c] - s_p[3 * (t - 1) + c]);
+          cst += T(0.5) * rr * rr;
+          gr += w.sq_len * rr;
+          sw += sl2;
+#pragma unroll
+          for (int a = 0; a < NZ; ++a)
+#pragma unroll
+            for (int b = 0; b < NZ; ++b) Bm[a][b] -= sl2 * Jp[c][a] * s_jp[((t - 1) * 3 + c) * NZ + b];
+        }
+        if (t + 1 <= H) {
+          const T rr = w.sq_len * (s_p[3 * (t + 1) + c] - s_p[3 * t + c]);
+          gr -= w.sq_len * rr;
+          sw += sl2;
+        }
+#pragma unroll
+        for (int a = 0; a < NZ; ++a) {
+          g[a] += gr * Jp[c][a];
+#pragma unroll
+          for (int b = 0; b <= a; ++b) Hp[tri(a, b)] += sw * Jp[c][a] * Jp[c][b];
+        }
+      }
+      // endpoint equalities, penalised (eq. 17)
+      if (t == 0 || t == H) {
+        const int off = t == 0 ? 0 : NU;
+        const T se2 = w.sq_eq * w.sq_eq;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          T za, zb;
+          u_to_ab((T)ta.task[(off + 3 * i) * ta.P + p], (T)ta.task[(off + 3 * i + 1) * ta.P + p],
+                  (T)ta.task[(off + 3 * i + 2) * ta.P + p], rb.r[i], &za, &zb);
+          const T ra = w.sq_eq * (z[2 * i] - za), rb2 = w.sq_eq * (z[2 * i + 1] - zb);
+          cst += T(0.5) * (ra * ra + rb2 * rb2);
+          g[2 * i] += w.sq_eq * ra;
+          g[2 * i + 1] += w.sq_eq * rb2;
+          Hp[tri(2 * i, 2 * i)] += se2;
+          Hp[tri(2 * i + 1, 2 * i + 1)] += se2;
+        }
+      }
+    }
+    T* rec = blk + (traj * Tn + t) * R::SIZE;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) rec[R::OL + k] = Hp[k];
+#pragma unroll
+    for (int a = 0; a < NZ; ++a)
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) {
+        rec[R::OB + a * NZ + b] = Bm[a][b];
+        rec[R::OC + a * NZ + b] = Cm[a][b];
+      }
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
+  }
+  const T total = block_sum_all(cst, s_red);
+  if (threadIdx.x == 0) {
+    cost0[traj] = total;
+    if (!tfinite(total)) failed[traj] = 1;
+  }
+}
+
+// Block Cholesky of the block-pentadiagonal H + lambda D, in place, one lane per
+// trajectory; then y = L^-1 (-g) and delta = L^-T y; writes g.delta.
+template <int NS, typename T>
+__global__ void __launch_bounds__(64)
+    k_traj_solve(int64_t nt, int H, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
+                 int32_t* __restrict__ chol_ok, T* __restrict__ gd_out) {
+  constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+  using R = Rec<NS>;
+  const int64_t traj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (traj >= nt) return;
+  if (failed[traj]) return;
+  const int Tn = H + 1;
+  const T lm = lam[traj];
+  bool ok = true;
+  for (int t = 0; t < Tn; ++t) {
+    T* rec = blk + (traj * Tn + t) * R::SIZE;
+    T S[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) S[k] = rec[R::OL + k];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      const T hj = S[tri(j, j)];
+      S[tri(j, j)] = hj + lm * (hj > T(1e-12) ? hj : T(1e-12));
+    }
+    T y[NZ];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) y[k] = -rec[R::OG + k];
+    if (t >= 2) {
+      // L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T  (row by row: forward substitution)
+      const T* r2 = blk + (traj * Tn + t - 2) * R::SIZE;
+      const T* r1 = blk + (traj * Tn + t - 1) * R::SIZE;
+#pragma unroll
+      for (int a = 0; a < NZ; ++a) {
+        T x[NZ];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          T v = rec[R::OC + a * NZ + i];
+#pragma unroll
+          for (int j = 0; j < i; ++j) v -= r2[R::OL + tri(i, j)] * x[j];
+          x[i] = v / r2[R::OL + tri(i, i)];
+        }
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) rec[R::OC + a * NZ + i] = x[i];
+        // contributions of this row: to S (row a) and to y
+        T ya = y[a];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) ya -= x[i] * r2[R::OY + i];
+        y[a] = ya;
+        // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T (row a); L_{t-1,t-2} is row t-1's first sub-diagonal block
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) {
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) v += x[i] * r1[R::OB + b * NZ + i];
+          rec[R::OB + a * NZ + b] -= v;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) v += rec[R::OC + a * NZ + i] * rec[R::OC + b * NZ + i];
+          S[tri(a, b)] -= v;
+        }
+    }
+    if (t >= 1) {
+      // L_{t,t-1} = (H_{t,t-1} - ...) L_{t-1,t-1}^-T
+      const T* r1 = blk + (traj * Tn + t - 1) * R::SIZE;
+#pragma unroll
+      for (int a = 0; a < NZ; ++a) {
+        T x[NZ];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          T v = rec[R::OB + a * NZ + i];
+#pragma unroll
+          for (int j = 0; j < i; ++j) v -= r1[R::OL + tri(i, j)] * x[j];
+          x[i] = v / r1[R::OL + tri(i, i)];
+        }
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) rec[R::OB + a * NZ + i] = x[i];
+        T ya = y[a];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) ya -= x[i] * r1[R::OY + i];
+        y[a] = ya;
+      }
+#pragma unroll
+      for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) v += rec[R::OB + a * NZ + i] * rec[R::OB + b * NZ + i];
+          S[tri(a, b)] -= v;
+        }
+    }
+    // L_tt L_tt^T = S;  y_t = L_tt^-1 (...)
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      T dd = S[tri(j, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dd -= S[tri(j, k)] * S[tri(j, k)];
+      ok = ok && (dd > T(0));
+      const T ljj = tsqrt(dd > T(0) ? dd : T(1));
+      S[tri(j, j)] = ljj;
+#pragma unroll
+      for (int i = j + 1; i < NZ; ++i) {
+        T v = S[tri(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= S[tri(i, k)] * S[tri(j, k)];
+        S[tri(i, j)] = v / ljj;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      T v = y[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= S[tri(i, k)] * y[k];
+      y[i] = v / S[tri(i, i)];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) rec[R::OL + k] = S[k];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) rec[R::OY + k] = y[k];
+  }
+  // backward: delta_t = L_tt^-T (y_t - L_{t+1,t}^T delta_{t+1} - L_{t+2,t}^T delta_{t+2})
+  T gd = T(0);
+  for (int t = Tn - 1; t >= 0; --t) {
+    T* rec = blk + (traj * Tn + t) * R::SIZE;
+    T x[NZ];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) x[k] = rec[R::OY + k];
+    if (t + 1 < Tn) {
+      const T* q = blk + (traj * Tn + t + 1) * R::SIZE;
+#pragma unroll
+      for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) x[i] -= q[R::OB + a * NZ + i] * q[R::OY + a];
+    }
+    if (t + 2 < Tn) {
+      const T* q = blk + (traj * Tn + t + 2) * R::SIZE;
+#pragma unroll
+      for (int a = 0; a < NZ; ++a)
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) x[i] -= q[R::OC + a * NZ + i] * q[R::OY + a];
+    }
+#pragma unroll
+    for (int i = NZ - 1; i >= 0; --i) {
+      T v = x[i];
+#pragma unroll
+      for (int k = i + 1; k < NZ; ++k) v -= rec[R::OL + tri(k, i)] * x[k];
+      x[i] = v / rec[R::OL + tri(i, i)];
+    }
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      rec[R::OY + k] = x[k];
+      gd += rec[R::OG + k] * x[k];
+    }
+  }
+  chol_ok[traj] = ok ? 1 : 0;
+  gd_out[traj] = gd;
+}
+
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_traj_search(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
+                  const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
+                  const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, const int32_t* __restrict__ failed,
+                  int32_t* __restrict__ trials) {
+  constexpr int NZ = 2 * NS, NU = 3 * NS;
+  using R = Rec<NS>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int H = ta.H, Tn = H + 1;
+  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_u = s_sph + 4 * ta.M;
+  T* s_p = s_u + Tn * NU;
+  T* s_red = s_p + Tn * 3;
+  const int64_t traj = blockIdx.x;
+  const int64_t p = traj / ta.per;
+  if (failed[traj]) return;
+  if (!chol_ok[traj]) {
+    if (threadIdx.x == 0) lam[traj] = lam[traj] * T(10) < o.lam_max ? lam[traj] * T(10) : o.lam_max;
+    return;
+  }
+  stage_spheres(ta, p, s_sph);
+  const int t = threadIdx.x;
+  const bool act = t < Tn;
+  T z[NZ], dl[NZ], zt[NZ];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      z[k] = Z[(traj * Tn + t) * NZ + k];
+      dl[k] = blk[(traj * Tn + t) * R::SIZE + R::OY + k];
+    }
+  }
+  __syncthreads();
+  const T c0 = cost0[traj], gd = gd_in[traj];
+  T alpha = T(1);
+  int acc = -1, ntr = 0;
+  for (int tr = 0; tr < o.ls_max; ++tr) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) zt[k] = act ? z[k] + alpha * dl[k] : T(0);
+    const T c = traj_cost<NS>(rb, w, ta, p, zt, s_sph, s_u, s_p, s_red, (T*)nullptr);
+    ++ntr;
+    if (c <= c0 + T(1e-4) * alpha * gd) {
+      acc = tr;
+      break;
+    }
+    alpha *= T(0.5);
+  }
+  if (acc >= 0 && act) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) Z[(traj * Tn + t) * NZ + k] = zt[k];
+  }
+  if (threadIdx.x == 0) {
+    T l = lam[traj];
+    if (acc == 0) l = l / T(10) > o.lam_min ? l / T(10) : o.lam_min;
+    if (acc < 0) l = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    lam[traj] = l;
+    trials[traj] += ntr;
+  }
+}
+
+// Final cost and collision penalty of every trajectory (SelectTop keys, argmin).
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_traj_eval(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, const T* __restrict__ Z, T* __restrict__ cost,
+                T* __restrict__ pen, int32_t* __restrict__ failed) {
+  constexpr int NZ = 2 * NS, NU = 3 * NS;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int H = ta.H, Tn = H + 1;
+  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_u = s_sph + 4 * ta.M;
+  T* s_p = s_u + Tn * NU;
+  T* s_red = s_p + Tn * 3;
+  const int64_t traj = blockIdx.x;
+  const int64_t p = traj / ta.per;
+  stage_spheres(ta, p, s_sph);
+  const int t = threadIdx.x;
+  T z[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z[k] = t < Tn ? Z[(traj * Tn + t) * NZ + k] : T(0);
+  __syncthreads();
+  T pn;
+  const T c = traj_cost<NS>(rb, w, ta, p, z, s_sph, s_u, s_p, s_red, &pn);
+  if (threadIdx.x == 0) {
+    cost[traj] = c;
+    pen[traj] = pn;
+    if (!tfinite(c)) failed[traj] = 1;
+  }
+}
+
+// Stage-2 candidates: copy the selected stage-1 trajectories (FP64 state).
+template <int NS, typename T1>
+__global__ void __launch_bounds__(256)
+    k_traj_gather(int64_t P, int S, int nf, int Tn, const T1* __restrict__ Z1, const int32_t* __restrict__ sel,
+                  double* __restrict__ Z2, int32_t* __restrict__ failed2) {
+  constexpr int NZ = 2 * NS;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * nf * Tn) return;
+  const int64_t traj2 = i / Tn;
+  const int t = (int)(i % Tn);
+  const int64_t p = traj2 / nf;
+  const int k = (int)(traj2 % nf);
+  const int s = sel[k * P + p];
+  if (t == 0) failed2[traj2] = s < 0 ? 1 : 0;
+  const int64_t src = (p * S + (s < 0 ? 0 : s)) * Tn + t;
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) Z2[(traj2 * Tn + t) * NZ + m] = (double)Z1[src * NZ + m];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T* __restrict__ x, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// Argmin over candidates per problem and the FP64 assessment of the winner.
+template <int NS, typename TC>
+__global__ void __launch_bounds__(64)
+    k_traj_finalize(RobotT<double> rb, TrajArgs<double> ta, int nc, const int32_t* __restrict__ sel,
+                    const TC* __restrict__ Zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
+                    double* __restrict__ u_out, double* __restrict__ err_out, int32_t* __restrict__ status_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = ta.P;
+  if (p >= P) return;
+  const int Tn = ta.H + 1;
+  int best = -1, best_seed = 0;
+  double best_cost = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    const int64_t tr = p * nc + k;
+    const int seed = sel ? sel[k * P + p] : k;
+    const double c = (double)costc[tr];
+    if (seed < 0 || failedc[tr] || !tfinite(c)) continue;
+    if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
+      best = k;
+      best_cost = c;
+      best_seed = seed;
+    }
+  }
+  const int64_t BU = P * Tn;
+  if (best < 0) {
+    const double nan = __builtin_nan("");
+    for (int t = 0; t < Tn; ++t)
+      for (int m = 0; m < 3 * NS; ++m) u_out[m * BU + p * Tn + t] = nan;
+    err_out[p] = err_out[P + p] = nan;
+    status_out[p] = CR_NONFINITE;
+    return;
+  }
+  const int64_t tr = p * nc + best;
+  double pos = 0.0, rot = 0.0, viol = -DBL_MAX, thx = -DBL_MAX, gmin = DBL_MAX;
+  for (int t = 0; t < Tn; ++t) {
+    double z[NZ];
+#pragma unroll
+    for (int m = 0; m < NZ; ++m) z[m] = (double)Zc[(tr * Tn + t) * NZ + m];
+    double Rc[9], pc[3];
+    fk_tip<NS>(rb, z, Rc, pc);
+    bool check = ta.kind == CR_KIND_PATH || t == 0 || t == Tn - 1;
+    if (check) {
+      double tt[12];
+      if (ta.kind == CR_KIND_PATH) {
+        load_pose(ta, p, t, tt);
+      } else {
+        const int off = t == 0 ? 0 : 3 * NS;
+        double ze[NZ];
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+          u_to_ab(ta.task[(off + 3 * i) * P + p], ta.task[(off + 3 * i + 1) * P + p], ta.task[(off + 3 * i + 2) * P + p],
+                  rb.rd[i], &ze[2 * i], &ze[2 * i + 1]);
+        double Re2[9], pe2[3];
+        fk_tip<NS>(rb, ze, Re2, pe2);
+        for (int r = 0; r < 3; ++r) {
+          for (int c = 0; c < 3; ++c) tt[4 * r + c] = Re2[3 * r + c];
+          tt[4 * r + 3] = pe2[r];
+        }
+      }
+      double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
+      pos = fmax(pos, sqrt(dot3(dp, dp)));
+      double Re[9], te[3];
+      relative_pose(Rc, pc, tt, Re, te);
+      double v[3] = {0.5 * (Re[7] - Re[5]), 0.5 * (Re[2] - Re[6]), 0.5 * (Re[3] - Re[1])};
+      rot = fmax(rot, atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0)));
+    }
+    // bounds and zero-sum output
+    double Rp[9], pp[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    pp[0] = pp[1] = pp[2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      double u[3];
+      ab_to_u(z[2 * i], z[2 * i + 1], rb.rd[i], u);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        u_out[(3 * i + j) * BU + p * Tn + t] = u[j];
+        viol = fmax(viol, fabs(u[j]) - rb.umaxd[i]);
+      }
+      thx = fmax(thx, sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) - rb.theta_maxd);
+      // clearance (margin 0) of every backbone point
+      if (ta.M > 0) {
+        const double s = z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1];
+        for (int k = 1; k <= rb.K; ++k) {
+          const double sg = (double)k / (double)rb.K;
+          ArcCoef<double> ck = arc_coef<double, false>(sg * sg * s);
+          double Rk[9], dk[3], x[3];
+          seg_R_d(sg * z[2 * i], sg * z[2 * i + 1], sg * rb.Ld[i], ck, Rk, dk);
+          mv3(Rp, dk, x);
+          for (int m = 0; m < ta.M; ++m) {
+            const int64_t col = (ta.per_problem ? p * ta.M : 0) + m;
+            const double d0 = pp[0] + x[0] - ta.sph[col], d1 = pp[1] + x[1] - ta.sph[ta.sld + col],
+                         d2 = pp[2] + x[2] - ta.sph[2 * ta.sld + col];
+            gmin = fmin(gmin, sqrt(d0 * d0 + d1 * d1 + d2 * d2) - ta.sph[3 * ta.sld + col] - rb.rd[i]);
+          }
+        }
+      }
+      ArcCoef<double> c = arc_coef<double, false>(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]);
+      double Ri[9], di[3], q[3], Rn[9];
+      seg_R_d(z[2 * i], z[2 * i + 1], rb.Ld[i], c, Ri, di);
+      mv3(Rp, di, q);
+      pp[0] += q[0];
+      pp[1] += q[1];
+      pp[2] += q[2];
+      mm3(Rp, Ri, Rn);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rp[k] = Rn[k];
+    }
+  }
+  int32_t st = 0;
+  if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
+  if (gmin < 0.0) st |= CR_COLLISION;
+  if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
+  if (st == 0) st = CR_SOLVED;
+  err_out[p] = pos;
+  err_out[P + p] = rot;
+  status_out[p] = st;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct TrajWs {
+  void *Z1, *blk1, *lam1, *c01, *gd1, *cost1, *pen1;
+  int32_t *chol1, *fail1, *trials1, *sel;
+  double *Z2, *blk2, *lam2, *c02, *gd2, *cost2, *pen2, *rd;
+  int32_t *chol2, *fail2, *trials2;
+};
+
+static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype dt, char* base, TrajWs* w) {
+  const size_t t1 = dt == CR_F64 ? 8 : 4;
+  const int NZ = 2 * ns, NP = NZ * (NZ + 1) / 2, REC = NP + 2 * NZ * NZ + 2 * NZ;
+  const int64_t Tn = H + 1, n1 = P * S, n2 = P * (nf > 0 ? nf : 1);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t at = off;
+    off += al(b);
+    return base ? (void*)(base + at) : nullptr;
+  };
+  TrajWs x{};
+  x.Z1 = take(t1 * n1 * Tn * NZ);
+  x.blk1 = take(t1 * n1 * Tn * REC);
+  x.lam1 = take(t1 * n1);
+  x.c01 = take(t1 * n1);
+  x.gd1 = take(t1 * n1);
+  x.cost1 = take(t1 * n1);
+  x.pen1 = take(t1 * n1);
+  x.chol1 = (int32_t*)take(4 * n1);
+  x.fail1 = (int32_t*)take(4 * n1);
+  x.trials1 = (int32_t*)take(4 * n1);
+  x.sel = (int32_t*)take(4 * n2);
+  x.Z2 = (double*)take(8 * n2 * Tn * NZ);
+  x.blk2 = (double*)take(8 * n2 * Tn * REC);
+  x.lam2 = (double*)take(8 * n2);
+  x.c02 = (double*)take(8 * n2);
+  x.gd2 = (double*)take(8 * n2);
+  x.cost2 = (double*)take(8 * n2);
+  x.pen2 = (double*)take(8 * n2);
+  x.chol2 = (int32_t*)take(4 * n2);
+  x.fail2 = (int32_t*)take(4 * n2);
+  x.trials2 = (int32_t*)take(4 * n2);
+  x.rd = (double*)take(8 * CR_MAX_SEG);
+  if (w) *w = x;
+  return off;
+}
+
+size_t traj_workspace_bytes(const cr_robot& rb, int64_t P, int S, int H, const cr_opts& o, cr_dtype dt) {
+  return traj_ws_layout(rb.n_seg, P, S, H, o.n_final, dt, nullptr, nullptr);
+}
+
+template <int NS, typename T>
+static size_t traj_lds(int H, int M, bool build) {
+  const int Tn = H + 1, NZ = 2 * NS;
+  return sizeof(T) * (size_t)(4 * M + Tn * 3 * NS + Tn * 3 + (build ? Tn * 3 * NZ : 0) + 8);
+}
+
+template <int NS>
+bool traj_lds_ok(int H, int M) {
+  return traj_lds<NS, double>(H, M, true) <= 64 * 1024;
+}
+
+// One LM stage (k iterations) on nt trajectories in type T.
+template <int NS, typename T>
+static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, const LMOpts<T>& lo,
+                            int64_t nt, int iters, T* Z, T* blk, T* lam, T* c0, T* gd, int32_t* chol, int32_t* failed,
+                            int32_t* trials, hipStream_t st) {
+  const int Tn = ta.H + 1;
+  const int threads = ((Tn + 63) / 64) * 64;
+  const size_t lds_b = traj_lds<NS, T>(ta.H, ta.M, true), lds_s = traj_lds<NS, T>(ta.H, ta.M, false);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL((k_traj_build<NS, T>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, c0,
+                       failed);
+    hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + 63) / 64)), dim3(64), 0, st, nt, ta.H, blk, lam,
+                       failed, chol, gd);
+    hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
+                       lam, c0, gd, chol, failed, trials);
+  }
+  return check_hip(hipGetLastError(), "trajectory LM stage");
+}
+
+template <int NS, typename T1>
+static cr_status run_traj(int kind, const cr_robot& rb0, const cr_spheres* sp, int64_t P, int H, const double* task, int S,
+                          const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
+                          int32_t* status_out, const TrajWs& ws, hipStream_t st) {
+  const int Tn = H + 1;
+  const int64_t n1 = P * (int64_t)S;
+  RobotT<T1> rb1 = robot_to<T1>(rb0);
+  WeightsT<T1> w1 = weights_to<T1>(w0);
+  RobotT<double> rbd = robot_to<double>(rb0);
+  WeightsT<double> wd = weights_to<double>(w0);
+  const int M = sp ? sp->n_sph : 0;
+  TrajArgs<T1> ta1{kind, H, P, S, task, M > 0 ? (const double*)sp->sph : nullptr, M > 0 ? sp->ld : 0, M,
+                   M > 0 ? sp->per_problem : 0};
+  cr_status rc = check_hip(hipMemcpyAsync(ws.rd, rbd.rd, sizeof(double) * CR_MAX_SEG, hipMemcpyHostToDevice, st),
+                           "copy robot radii");
+  if (rc != CR_OK) return rc;
+  hipLaunchKernelGGL((k_traj_init<NS, T1>), dim3((unsigned)((n1 * Tn + 255) / 256)), dim3(256), 0, st, n1, Tn, useed,
+                     (const double*)ws.rd, (T1*)ws.Z1);
+  hipLaunchKernelGGL((k_fill<T1>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, (T1*)ws.lam1,
+                     (T1)o.lambda0);
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.fail1, 0);
+  hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.trials1, 0);
+  LMOpts<T1> lo1{o.ls_max, (T1)o.lambda_min, (T1)o.lambda_max};
+  rc = traj_stage<NS, T1>(rb1, w1, ta1, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1, (T1*)ws.lam1, (T1*)ws.c01,
+                          (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
+  if (rc != CR_OK) return rc;
+  const size_t lds_e1 = traj_lds<NS, T1>(H, M, false);
+  const int threads = ((Tn + 63) / 64) * 64;
+  hipLaunchKernelGGL((k_traj_eval<NS, T1>), dim3((unsigned)n1), dim3(threads), lds_e1, st, rb1, w1, ta1,
+                     (const T1*)ws.Z1, (T1*)ws.cost1, (T1*)ws.pen1, ws.fail1);
+  TrajArgs<double> tad{kind, H, P, S, task, ta1.sph, ta1.sld, M, ta1.per_problem};
+  if (o.n_final > 0) {
+    const int nf = o.n_final;
+    const int64_t n2 = P * (int64_t)nf;
+    // SelectTop ranks path/trajectory candidates by their total cost
+    rc = launch_select_strided(P, S, 2 * NS * Tn, ws.Z1, 1, 2 * NS * Tn, ws.cost1, ws.pen1, ws.fail1, nf, o.dup_eps,
+                               ws.sel, sizeof(T1) == 8 ? CR_F64 : CR_F32, st);
+    if (rc != CR_OK) return rc;
+    hipLaunchKernelGGL((k_traj_gather<NS, T1>), dim3((unsigned)((n2 * Tn + 255) / 256)), dim3(256), 0, st, P, S, nf,
+                       Tn, (const T1*)ws.Z1, ws.sel, ws.Z2, ws.fail2);
+    hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, ws.lam2, o.lambda0);
+    hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, ws.trials2, 0);
+    TrajArgs<double> ta2 = tad;
+    ta2.per = nf;
+    LMOpts<double> lo2{o.ls_max, o.lambda_min, o.lambda_max};
+    rc = traj_stage<NS, double>(rbd, wd, ta2, lo2, n2, o.k_final, ws.Z2, ws.blk2, ws.lam2, ws.c02, ws.gd2, ws.chol2,
+                                ws.fail2, ws.trials2, st);
+    if (rc != CR_OK) return rc;
+    const size_t lds_e2 = traj_lds<NS, double>(H, M, false);
+    hipLaunchKernelGGL((k_traj_eval<NS, double>), dim3((unsigned)n2), dim3(threads), lds_e2, st, rbd, wd, ta2,
+                       (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2);
+    hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, rbd, tad, nf,
+                       ws.sel, (const double*)ws.Z2, (const double*)ws.cost2, ws.fail2, u_out, err_out, status_out);
+  } else {
+    hipLaunchKernelGGL((k_traj_finalize<NS, T1>), dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, rbd, tad, S,
+                       (const int32_t*)nullptr, (const T1*)ws.Z1, (const T1*)ws.cost1, ws.fail1, u_out, err_out,
+                       status_out);
+  }
+  return check_hip(hipGetLastError(), "trajectory solve");
+}
+
+cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
+                            int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,
+                            double* err_out, int32_t* status_out, void* wsmem, cr_dtype dtype, hipStream_t st) {
+  TrajWs ws;
+  traj_ws_layout(rb.n_seg, P, S, H, o.n_final, dtype, (char*)wsmem, &ws);
+#define CR_TRAJ_CASE(N)                                                                                            \
+  case N:                                                                                                          \
+    if (!traj_lds_ok<N>(H, sp ? sp->n_sph : 0)) return fail(CR_EINVAL, "horizon x spheres exceed 64 KiB of LDS"); \
+    return dtype == CR_F64                                                                                         \
+               ? run_traj<N, double>(kind, rb, sp, P, H, task, S, useed, w, o, u_out, err_out, status_out, ws, st) \
+               : run_traj<N, float>(kind, rb, sp, P, H, task, S, useed, w, o, u_out, err_out, status_out, ws, st);
+  switch (rb.n_seg) {
+    CR_TRAJ_CASE(1)
+    CR_TRAJ_CASE(2)
+    CR_TRAJ_CASE(3)
+    CR_TRAJ_CASE(4)
+    CR_TRAJ_CASE(5)
+    CR_TRAJ_CASE(6)
+    default:
+      return fail(CR_EINVAL, "n_seg out of range");
+  }
+#undef CR_TRAJ_CASE
+}
+
+}  // namespace crk
