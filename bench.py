@@ -34,6 +34,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "path_4seg", "traj_5seg"],
+                    help="the headline IK workload, or one of the path / trajectory workloads")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
@@ -94,6 +96,8 @@ def main():
     from paper_2607_11340_amd import crsolver as cr
     from paper_2607_11340_amd import inputs as I
 
+    if args.workload != WORKLOAD:
+        return bench_trajectories(args, cr, I, torch)
     spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
     P, S = spec["P"], spec["S"]
     opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
@@ -181,6 +185,94 @@ def main():
         stage_ms=dict(stage1=round(stage_avg[0], 4), select=round(stage_avg[1], 4), stage2=round(stage_avg[2], 4),
                       finalize=round(stage_avg[3], 4)),
         roofline=roofline, cpu_baseline=base)
+    print(json.dumps(line), flush=True)
+
+
+def traj_inputs(name, cr, I, torch, O=None):
+    """Seeded inputs of the path-following or trajectory workload (host arrays plus
+    device tensors).  Path: smooth reference actuation paths, their FK poses as
+    reference, seeds = reference + N(0, 0.5 mm) per tendon.  Trajectory: uniform
+    start/goal actuations, perturbed straight-line seeds, spheres uniform in the
+    reachable box, rejected within 2 mm of the start or goal backbone."""
+    spec = I.WORKLOADS[name]
+    n, P, S, H, b = len(spec["L"]), spec["P"], spec["S"], spec["H"], spec["b"]
+    Tn = H + 1
+    rng = I.rng_for(name)
+    K = spec["K"]
+    robot = cr.Robot(L=spec["L"], r=spec["r"], u_max=[b] * n, pts_per_seg=K)
+    dev = torch.device("cuda:0")
+    out = dict(spec=spec, robot=robot, n=n, P=P, S=S, H=H)
+    if spec["kind"] == "path":
+        uref = I.smooth_actuation_paths(rng, n, b, P, Tn)                    # [P, Tn, n, 3]
+        fr = cr.fk(robot, torch.tensor(uref.reshape(P * Tn, -1).T.copy(), device=dev), arc=False)["frames"]
+        out["task"] = fr[12 * (n - 1):12 * n].contiguous()                  # [12, Tn*P]
+        seeds = np.clip(uref[:, None] + rng.normal(size=(P, S, Tn, n, 3)) * 5e-4, -b, b)
+        seeds -= seeds.mean(axis=-1, keepdims=True)
+        out["spheres"] = None
+    else:
+        ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
+        seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, Tn, b) for p in range(P)])
+        out["task"] = torch.tensor(np.concatenate([ends[:, 0].reshape(P, -1), ends[:, 1].reshape(P, -1)], 1).T.copy(),
+                                   device=dev)
+        M = spec["M"]
+        pts = cr.fk(robot, torch.tensor(ends.reshape(2 * P, -1).T.copy(), device=dev), arc=False, frames=False,
+                    points=True)["pts"].cpu().numpy().T.reshape(P, 2 * n * K, 3)
+        sph = np.zeros((P, M, 4))
+        body = np.tile(np.repeat(np.asarray(spec["r"]), K), 2)
+        for p in range(P):
+            m = 0
+            while m < M:
+                cand = I.spheres(rng, 2 * M, [-0.2, -0.2, 0.0], [0.2, 0.2, 0.3], 0.005, 0.02)
+                for s in cand:
+                    if m < M and (np.linalg.norm(pts[p] - s[:3], axis=1) - s[3] - body).min() > 2e-3:
+                        sph[p, m] = s
+                        m += 1
+        out["spheres"] = (torch.tensor(np.ascontiguousarray(sph.reshape(P * M, 4).T), device=dev), True, M)
+        out["sph_host"] = sph
+        out["ends"] = ends
+    out["seeds"] = seeds
+    out["useed"] = torch.tensor(seeds.reshape(P * S * Tn, -1).T.copy(), device=dev)
+    return out
+
+
+def bench_trajectories(args, cr, I, torch):
+    d = traj_inputs(args.workload, cr, I, torch)
+    spec, robot, P, S, H = d["spec"], d["robot"], d["P"], d["S"], d["H"]
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    weights = cr.Weights(**spec.get("weights", {}))
+    ws = torch.empty(cr.traj_workspace_bytes(robot, P, H, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    out = (torch.empty((3 * robot.n, (H + 1) * P), dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"),
+           torch.empty((P,), dtype=torch.int32, device="cuda"))
+    fn = cr.solve_path if spec["kind"] == "path" else cr.solve_traj
+
+    def step():
+        fn(robot, d["task"], d["useed"], H, weights, opts, dtype=torch.float32, spheres=d["spheres"], workspace=ws,
+           out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    status = out[2].cpu().numpy()
+    err = out[1].cpu().numpy()
+    unit = "paths/s" if spec["kind"] == "path" else "trajectories/s"
+    line = dict(metric=f"{spec['kind']} solves/sec (success %)", value=round(P / (ms * 1e-3), 2), unit=unit, n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
+                config=dict(workload=args.workload, segments=robot.n, problems=P, waypoints=H + 1, seeds=S,
+                            spheres=spec.get("M", 0), pts_per_seg=robot.pts_per_seg, k_init=spec["k_init"],
+                            k_final=spec["k_final"], n_final=spec["n_final"]),
+                success_rate=round(float((status == cr.SOLVED).mean()), 4),
+                status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+                max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)])
     print(json.dumps(line), flush=True)
 
 

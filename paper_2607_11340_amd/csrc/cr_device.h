@@ -751,6 +751,19 @@ CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T
 
 namespace crk {
 
+// Backbone point at arc fraction sg of a segment with bending coordinates (a, b),
+// s = a^2 + b^2, length L, whose base frame is (Rc, pc); rounded to T.
+template <typename TC, typename T>
+CR_HD void seg_point(const TC* Rc, const TC* pc, TC a, TC b, TC L, TC s, TC sg, T* out) {
+  ArcCoef<TC> ck = arc_coef<TC, false>(sg * sg * s);
+  const TC sL = sg * L;
+  TC dk[3] = {sL * ck.A * (sg * a), sL * ck.A * (sg * b), sL * ck.B}, x[3];
+  mv3(Rc, dk, x);
+  out[0] = (T)(pc[0] + x[0]);
+  out[1] = (T)(pc[1] + x[1]);
+  out[2] = (T)(pc[2] + x[2]);
+}
+
 template <int NS, typename T>
 struct Fwd {
   T W[2 * NS][3], Pd[2 * NS][3], pe[NS][3];  // twist columns and segment ends
@@ -791,63 +804,66 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
 #pragma unroll
       for (int c = 0; c < 3; ++c) f.F[i][c] = f.Mo[i][c] = T(0);
     }
-    // backbone points of this segment against every sphere (eq. 10)
+    // backbone points of this segment against every sphere (eq. 10).  Every point
+    // lies within L_i / 2 of the arc midpoint (arc length bounds the chord), so a
+    // sphere farther than L_i / 2 + R + r_i + margin from it is skipped for the
+    // whole segment without changing the cost.
     if (M > 0) {
       const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
       const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
       const TC sqc = (TC)w.sq_coll;
-      for (int k = 1; k <= K; ++k) {
-        const TC sg = TC(k) / TC(K);
-        ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
-        const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
-        TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
-        TC x[3];
-        mv3(Rc, dk, x);
-        x[0] += pc[0];
-        x[1] += pc[1];
-        x[2] += pc[2];
-        const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
-        const T rf = (T)(ri + marg);
-        TC fx[3] = {TC(0), TC(0), TC(0)};
-        bool any = false;
-        for (int m = 0; m < M; ++m) {
-          const T* sm = sph + m * ms;
-          const T e0 = xf[0] - sm[0], e1 = xf[1] - sm[cs], e2 = xf[2] - sm[2 * cs];
-          const T rq = (sm[3 * cs] + rf) * slack;
-          if (e0 * e0 + e1 * e1 + e2 * e2 < rq * rq) {
-            const TC d0 = x[0] - (TC)sm[0], d1 = x[1] - (TC)sm[cs], d2 = x[2] - (TC)sm[2 * cs];
-            const TC reach = (TC)sm[3 * cs] + ri + marg;
-            const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            const TC viol = reach - dist;  // margin - (dist - R - r)
-            if (viol > TC(0)) {
-              const TC rr = sqc * viol;
-              cost += (T)(TC(0.5) * rr * rr);
-              if (GRAD) {
-                // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
-                const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
-                fx[0] += sc * d0;
-                fx[1] += sc * d1;
-                fx[2] += dist > TC(0) ? sc * d2 : -sqc * rr;
-                any = true;
-              }
-            }
-          }
+      const T rf = (T)(ri + marg);
+      T xmf[3];
+      seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
+      const T half = T(0.5) * rb.L[i];
+      for (int m = 0; m < M; ++m) {
+        const T* sm = sph + m * ms;
+        {
+          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[cs], e2 = xmf[2] - sm[2 * cs];
+          const T rq = (sm[3 * cs] + rf + half) * T(1.0001);
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
         }
-        if (GRAD && any) {
-          const T ff[3] = {(T)fx[0], (T)fx[1], (T)fx[2]};
+        const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
+        const TC reach = (TC)sm[3 * cs] + ri + marg;
+        const T rq = (sm[3 * cs] + rf) * slack;
+        for (int k = 1; k <= K; ++k) {
+          const TC sg = TC(k) / TC(K);
+          ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
+          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+          TC x[3];
+          mv3(Rc, dk, x);
+          x[0] += pc[0];
+          x[1] += pc[1];
+          x[2] += pc[2];
+          const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+          {
+            const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
+            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+          }
+          const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const TC viol = reach - dist;  // margin - (dist - R - r)
+          if (!(viol > TC(0))) continue;
+          const TC rr = sqc * viol;
+          cost += (T)(TC(0.5) * rr * rr);
+          if (GRAD) {
+            // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
+            const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
+            const TC fx[3] = {sc * d0, sc * d1, dist > TC(0) ? sc * d2 : -sqc * rr};
 #pragma unroll
-          for (int c = 0; c < 3; ++c) f.F[i][c] += ff[c];
-          TC mx[3];
-          cross3(x, fx, mx);
+            for (int q = 0; q < 3; ++q) f.F[i][q] += (T)fx[q];
+            TC mx[3];
+            cross3(x, fx, mx);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) f.Mo[i][c] += (T)mx[c];
-          // own arc: x = pc + Rc d(sg a, sg b, sg L)
-          TC q[3];
-          mtv3(Rc, fx, q);
-          const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
-          const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
-          f.gz[2 * i] += (T)(sg * dot3(q, dda));
-          f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
+            for (int q = 0; q < 3; ++q) f.Mo[i][q] += (T)mx[q];
+            // own arc: x = pc + Rc d(sg a, sg b, sg L)
+            TC q[3];
+            mtv3(Rc, fx, q);
+            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+            f.gz[2 * i] += (T)(sg * dot3(q, dda));
+            f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
+          }
         }
       }
     }
@@ -1101,31 +1117,43 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
     const TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
     const TC s = ac * ac + bc * bc;
     if (M > 0) {
+      // clearance rows, with the segment-level sphere culling of config_forward
       const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
       const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
       const T rf = (T)(ri + marg);
-      for (int k = 1; k <= K; ++k) {
-        const TC sg = TC(k) / TC(K);
-        ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
-        const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
-        TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
-        TC x[3];
-        mv3(Rc, dk, x);
-        x[0] += pc[0];
-        x[1] += pc[1];
-        x[2] += pc[2];
-        const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
-        for (int m = 0; m < M; ++m) {
-          const T* sm = sph + m * ms;
-          const T e0 = xf[0] - sm[0], e1 = xf[1] - sm[cs], e2 = xf[2] - sm[2 * cs];
-          const T rq = (sm[3 * cs] + rf) * slack;
+      T xmf[3];
+      seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
+      const T half = T(0.5) * rb.L[i];
+      for (int m = 0; m < M; ++m) {
+        const T* sm = sph + m * ms;
+        {
+          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[cs], e2 = xmf[2] - sm[2 * cs];
+          const T rq = (sm[3 * cs] + rf + half) * T(1.0001);
           if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
-          const TC d0 = x[0] - (TC)sm[0], d1 = x[1] - (TC)sm[cs], d2 = x[2] - (TC)sm[2 * cs];
-          const TC reach = (TC)sm[3 * cs] + ri + marg;
+        }
+        const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
+        const TC reach = (TC)sm[3 * cs] + ri + marg;
+        const T rq = (sm[3 * cs] + rf) * slack;
+        for (int k = 1; k <= K; ++k) {
+          const TC sg = TC(k) / TC(K);
+          ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
+          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+          TC x[3];
+          mv3(Rc, dk, x);
+          x[0] += pc[0];
+          x[1] += pc[1];
+          x[2] += pc[2];
+          const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+          {
+            const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
+            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+          }
           const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
           const TC viol = reach - dist;
           if (!(viol > TC(0))) continue;
           const T rr = (T)((TC)w.sq_coll * viol);
+          const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
           // residual sq_coll (reach - |x - c|): row = -sq_coll n^T dx/dz
           T nvec[3];
           if (dist > TC(0)) {

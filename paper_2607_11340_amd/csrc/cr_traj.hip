@@ -7,15 +7,15 @@
 //                  and, through LDS, the smoothness and path-length couplings to
 //                  waypoints t-1 and t-2; writes the block rows of
 //                  H = J^T J (diagonal, first and second sub-diagonal blocks) and g.
-//   k_traj_solve   one lane per trajectory: damping, block Cholesky of the
+//   k_traj_solve   NZ lanes per trajectory, one per row of the 2n x 2n blocks,
+//                  several trajectories per wave: damping, block Cholesky of the
 //                  block-pentadiagonal H + lambda D (the exact banded factor),
 //                  forward and backward substitution, g.delta.
 //   k_traj_search  one workgroup per trajectory: backtracking line search; the
 //                  trial cost is block-reduced, so accept/reject is uniform per
 //                  workgroup; updates z and lambda.
-// Per trajectory and waypoint the workspace holds one record
-//   [ L_tt (packed, NP) | H_{t,t-1} -> L_{t,t-1} (NZ^2) | H_{t,t-2} -> L_{t,t-2} (NZ^2) | g (NZ) | y, delta (NZ) ]
-// and z is stored trajectory-major, waypoint, coordinate: [traj][t][k].
+// Per trajectory and waypoint the workspace holds one record (struct Rec) and z
+// is stored trajectory-major, waypoint, coordinate: [traj][t][k].
 #include <float.h>
 
 #include "cr_internal.h"
@@ -34,10 +34,16 @@ struct TrajArgs {
   int M, per_problem;
 };
 
+// Per-waypoint record of the normal equations, every block column-major: element
+// (row i, column j) of a block sits at column j * NZ + i, so the NZ lanes that own
+// the rows of one trajectory read a block column as NZ consecutive values.
+//   OH: H_tt (full, symmetric), overwritten by L_tt (lower)
+//   OB: H_{t,t-1}, overwritten by L_{t,t-1};  OC: H_{t,t-2}, overwritten by L_{t,t-2}
+//   OG: g_t;  OY: y_t, then delta_t
 template <int NS>
 struct Rec {
-  static constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
-  static constexpr int OL = 0, OB = NP, OC = NP + NZ * NZ, OG = NP + 2 * NZ * NZ, OY = OG + NZ;
+  static constexpr int NZ = 2 * NS;
+  static constexpr int OH = 0, OB = NZ * NZ, OC = 2 * NZ * NZ, OG = 3 * NZ * NZ, OY = OG + NZ;
   static constexpr int SIZE = OY + NZ;
 };
 
@@ -82,13 +88,12 @@ __device__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs
   T cst = T(0), cpen = T(0);
   if (act) {
     Fwd<NS, T> f;
-    cst = ta.M > 0 ? config_forward<NS, T, false, double>(rb, w, z, s_sph, ta.M, 4, 1, f)
-                   : config_forward<NS, T, false>(rb, w, z, s_sph, 0, 4, 1, f);
+    cst = config_forward<NS, T, false>(rb, w, z, s_sph, ta.M, 4, 1, f);
     if (pen && ta.M > 0) {
       WeightsT<T> wc = w;
       wc.sq_lim = wc.sq_curv = T(0);
       Fwd<NS, T> f2;
-      cpen = config_forward<NS, T, false, double>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
+      cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
     }
     if (ta.kind == CR_KIND_PATH) {
       T Tt[12], ft[3], tq[3];
@@ -201,8 +206,7 @@ __global__ void __launch_bounds__(256)
     T Tt[12];
     if (ta.kind == CR_KIND_PATH) load_pose(ta, p, t, Tt);
     const T* tp = ta.kind == CR_KIND_PATH ? Tt : nullptr;
-    cst = ta.M > 0 ? local_normal_eq<NS, T, double>(rb, w, z, s_sph, ta.M, 4, 1, tp, Hp, g, ptip, Jp)
-                   : local_normal_eq<NS, T, T>(rb, w, z, s_sph, 0, 4, 1, tp, Hp, g, ptip, Jp);
+    cst = local_normal_eq<NS, T, T>(rb, w, z, s_sph, ta.M, 4, 1, tp, Hp, g, ptip, Jp);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T u[3];
@@ -342,13 +346,12 @@ __global__ void __launch_bounds__(256)
     }
     T* rec = blk + (traj * Tn + t) * R::SIZE;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) rec[R::OL + k] = Hp[k];
+    for (int b = 0; b < NZ; ++b)
 #pragma unroll
-    for (int a = 0; a < NZ; ++a)
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) {
-        rec[R::OB + a * NZ + b] = Bm[a][b];
-        rec[R::OC + a * NZ + b] = Cm[a][b];
+      for (int a = 0; a < NZ; ++a) {
+        rec[R::OH + b * NZ + a] = a >= b ? Hp[tri(a, b)] : Hp[tri(b, a)];
+        rec[R::OB + b * NZ + a] = Bm[a][b];
+        rec[R::OC + b * NZ + a] = Cm[a][b];
       }
 #pragma unroll
     for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
@@ -360,168 +363,215 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Block Cholesky of the block-pentadiagonal H + lambda D, in place, one lane per
-// trajectory; then y = L^-1 (-g) and delta = L^-T y; writes g.delta.
+// Block Cholesky of the block-pentadiagonal H + lambda D, in place, then
+// y = L^-1 (-g), delta = L^-T y and g.delta.  NZ lanes own the rows of one
+// trajectory (row a on lane a); a 64-lane workgroup holds 64 / NZ trajectories.
+// The sequential chain over waypoints stays per trajectory; the last factors
+// L_{t-1,t-1}, L_{t-2,t-2}, L_{t-1,t-2} and y live in LDS so every lane can read
+// the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
 template <int NS, typename T>
 __global__ void __launch_bounds__(64)
     k_traj_solve(int64_t nt, int H, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
                  int32_t* __restrict__ chol_ok, T* __restrict__ gd_out) {
-  constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+  constexpr int NZ = 2 * NS, G = 64 / NZ;
+  constexpr int RS = NZ + (NZ & 1);  // LDS row stride
+  constexpr int GS = NZ * RS + 4;    // LDS group stride (breaks bank aliasing between groups)
   using R = Rec<NS>;
-  const int64_t traj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (traj >= nt) return;
-  if (failed[traj]) return;
+  __shared__ T sL[3][G * GS];     // L_tt of waypoints t mod 3 (row i at i * RS)
+  __shared__ T sD[3][G * RS];     // 1 / diag(L_tt)
+  __shared__ T sB[2][G * GS];     // L_{t,t-1} of waypoints t mod 2
+  __shared__ T sX[G * GS];        // rows of the block being formed (for the symmetric updates)
+  __shared__ T sY[3][G * RS];     // y_t, later delta_t, of waypoints t mod 3
+  const int lane = threadIdx.x;
+  const bool inw = lane < G * NZ;  // lane owns a row
+  const int g = inw ? lane / NZ : 0, a = inw ? lane - g * NZ : 0, base = g * NZ;
+  const int64_t traj = (int64_t)blockIdx.x * G + g;
+  const bool act = inw && traj < nt && !failed[traj];
   const int Tn = H + 1;
-  const T lm = lam[traj];
+  const T lm = act ? lam[traj] : T(0);
+  T* const recs = blk + (act ? traj : 0) * (int64_t)Tn * R::SIZE;
   bool ok = true;
   for (int t = 0; t < Tn; ++t) {
-    T* rec = blk + (traj * Tn + t) * R::SIZE;
-    T S[NP];
+    T* rec = recs + (int64_t)t * R::SIZE;
+    const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
+    const int b0 = t & 1, b1 = b0 ^ 1;
+    T S[NZ];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) S[k] = rec[R::OL + k];
+    for (int b = 0; b < NZ; ++b) S[b] = act ? rec[R::OH + b * NZ + a] : T(b == a);
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-      const T hj = S[tri(j, j)];
-      S[tri(j, j)] = hj + lm * (hj > T(1e-12) ? hj : T(1e-12));
-    }
-    T y[NZ];
+    for (int b = 0; b < NZ; ++b)
+      if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
+    T y = act ? -rec[R::OG + a] : T(0);
+    T Bw[NZ];
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) y[k] = -rec[R::OG + k];
+    for (int b = 0; b < NZ; ++b) Bw[b] = (act && t >= 1) ? rec[R::OB + b * NZ + a] : T(0);
     if (t >= 2) {
-      // L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T  (row by row: forward substitution)
-      const T* r2 = blk + (traj * Tn + t - 2) * R::SIZE;
-      const T* r1 = blk + (traj * Tn + t - 1) * R::SIZE;
+      // row a of L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T (forward substitution)
+      const T* L2 = &sL[s2][g * GS];
+      const T* D2 = &sD[s2][g * RS];
+      T x[NZ];
 #pragma unroll
-      for (int a = 0; a < NZ; ++a) {
-        T x[NZ];
+      for (int i = 0; i < NZ; ++i) {
+        T v = act ? rec[R::OC + i * NZ + a] : T(0);
 #pragma unroll
-        for (int i = 0; i < NZ; ++i) {
-          T v = rec[R::OC + a * NZ + i];
-#pragma unroll
-          for (int j = 0; j < i; ++j) v -= r2[R::OL + tri(i, j)] * x[j];
-          x[i] = v / r2[R::OL + tri(i, i)];
-        }
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) rec[R::OC + a * NZ + i] = x[i];
-        // contributions of this row: to S (row a) and to y
-        T ya = y[a];
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) ya -= x[i] * r2[R::OY + i];
-        y[a] = ya;
-        // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T (row a); L_{t-1,t-2} is row t-1's first sub-diagonal block
-#pragma unroll
-        for (int b = 0; b < NZ; ++b) {
-          T v = T(0);
-#pragma unroll
-          for (int i = 0; i < NZ; ++i) v += x[i] * r1[R::OB + b * NZ + i];
-          rec[R::OB + a * NZ + b] -= v;
-        }
+        for (int j = 0; j < i; ++j) v -= L2[i * RS + j] * x[j];
+        x[i] = v * D2[i];
       }
+      const T* Y2 = &sY[s2][g * RS];
+      const T* B1 = &sB[b1][g * GS];  // L_{t-1,t-2}
 #pragma unroll
-      for (int a = 0; a < NZ; ++a)
+      for (int i = 0; i < NZ; ++i) {
+        y -= x[i] * Y2[i];
+        if (act) rec[R::OC + i * NZ + a] = x[i];
+      }
+      // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          T v = T(0);
+      for (int b = 0; b < NZ; ++b) {
+        T v = T(0);
 #pragma unroll
-          for (int i = 0; i < NZ; ++i) v += rec[R::OC + a * NZ + i] * rec[R::OC + b * NZ + i];
-          S[tri(a, b)] -= v;
-        }
+        for (int i = 0; i < NZ; ++i) v += x[i] * B1[b * RS + i];
+        Bw[b] -= v;
+      }
+      if (inw) {
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) sX[g * GS + a * RS + i] = x[i];
+      }
+      __syncthreads();
+      // S -= L_{t,t-2} L_{t,t-2}^T (row a)
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) {
+        T v = T(0);
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) v += x[i] * sX[g * GS + b * RS + i];
+        S[b] -= v;
+      }
+      __syncthreads();
     }
     if (t >= 1) {
-      // L_{t,t-1} = (H_{t,t-1} - ...) L_{t-1,t-1}^-T
-      const T* r1 = blk + (traj * Tn + t - 1) * R::SIZE;
+      // row a of L_{t,t-1} = (H_{t,t-1} - ...) L_{t-1,t-1}^-T
+      const T* L1 = &sL[s1][g * GS];
+      const T* D1 = &sD[s1][g * RS];
+      T x[NZ];
 #pragma unroll
-      for (int a = 0; a < NZ; ++a) {
-        T x[NZ];
+      for (int i = 0; i < NZ; ++i) {
+        T v = Bw[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) v -= L1[i * RS + j] * x[j];
+        x[i] = v * D1[i];
+      }
+      const T* Y1 = &sY[s1][g * RS];
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) {
+        y -= x[i] * Y1[i];
+        if (act) rec[R::OB + i * NZ + a] = x[i];
+      }
+      if (inw) {
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-          T v = rec[R::OB + a * NZ + i];
-#pragma unroll
-          for (int j = 0; j < i; ++j) v -= r1[R::OL + tri(i, j)] * x[j];
-          x[i] = v / r1[R::OL + tri(i, i)];
+          sX[g * GS + a * RS + i] = x[i];
+          sB[b0][g * GS + a * RS + i] = x[i];
         }
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) rec[R::OB + a * NZ + i] = x[i];
-        T ya = y[a];
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) ya -= x[i] * r1[R::OY + i];
-        y[a] = ya;
       }
+      __syncthreads();
 #pragma unroll
-      for (int a = 0; a < NZ; ++a)
+      for (int b = 0; b < NZ; ++b) {
+        T v = T(0);
 #pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          T v = T(0);
-#pragma unroll
-          for (int i = 0; i < NZ; ++i) v += rec[R::OB + a * NZ + i] * rec[R::OB + b * NZ + i];
-          S[tri(a, b)] -= v;
-        }
+        for (int i = 0; i < NZ; ++i) v += x[i] * sX[g * GS + b * RS + i];
+        S[b] -= v;
+      }
     }
-    // L_tt L_tt^T = S;  y_t = L_tt^-1 (...)
+    // L_tt L_tt^T = S and y_t = L_tt^-1 y, column by column: in round j lane j
+    // finishes its pivot and y_j and publishes its row; rows below take column j.
+    T* Lt = &sL[s0][g * GS];
+    T* Dt = &sD[s0][g * RS];
+    T* Yt = &sY[s0][g * RS];
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
-      T dd = S[tri(j, j)];
+      if (a == j) {
+        T dd = S[j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) dd -= S[tri(j, k)] * S[tri(j, k)];
-      ok = ok && (dd > T(0));
-      const T ljj = tsqrt(dd > T(0) ? dd : T(1));
-      S[tri(j, j)] = ljj;
+        for (int k = 0; k < j; ++k) dd -= S[k] * S[k];
+        ok = ok && (dd > T(0));
+        const T ljj = tsqrt(dd > T(0) ? dd : T(1));
+        S[j] = ljj;
+        y = y / ljj;
+        if (inw) {
 #pragma unroll
-      for (int i = j + 1; i < NZ; ++i) {
-        T v = S[tri(i, j)];
+          for (int k = 0; k <= j; ++k) Lt[j * RS + k] = S[k];
+          Dt[j] = T(1) / ljj;
+          Yt[j] = y;
+        }
+      }
+      __syncthreads();
+      if (a > j) {
+        T v = S[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) v -= S[tri(i, k)] * S[tri(j, k)];
-        S[tri(i, j)] = v / ljj;
+        for (int k = 0; k < j; ++k) v -= S[k] * Lt[j * RS + k];
+        S[j] = v * Dt[j];
+        y -= S[j] * Yt[j];
       }
     }
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < NZ; ++i) {
-      T v = y[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= S[tri(i, k)] * y[k];
-      y[i] = v / S[tri(i, i)];
+      for (int b = 0; b < NZ; ++b) rec[R::OH + b * NZ + a] = b <= a ? S[b] : T(0);
+      rec[R::OY + a] = y;
     }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) rec[R::OL + k] = S[k];
-#pragma unroll
-    for (int k = 0; k < NZ; ++k) rec[R::OY + k] = y[k];
+    __syncthreads();
   }
   // backward: delta_t = L_tt^-T (y_t - L_{t+1,t}^T delta_{t+1} - L_{t+2,t}^T delta_{t+2})
   T gd = T(0);
   for (int t = Tn - 1; t >= 0; --t) {
-    T* rec = blk + (traj * Tn + t) * R::SIZE;
-    T x[NZ];
-#pragma unroll
-    for (int k = 0; k < NZ; ++k) x[k] = rec[R::OY + k];
+    T* rec = recs + (int64_t)t * R::SIZE;
+    const int s0 = t % 3, s1 = (t + 1) % 3, s2 = (t + 2) % 3;  // slots of t, t+1, t+2
+    T r = act ? rec[R::OY + a] : T(0);
     if (t + 1 < Tn) {
-      const T* q = blk + (traj * Tn + t + 1) * R::SIZE;
+      const T* q = rec + R::SIZE;
+      const T* d1 = &sY[s1][g * RS];
 #pragma unroll
-      for (int a = 0; a < NZ; ++a)
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) x[i] -= q[R::OB + a * NZ + i] * q[R::OY + a];
+      for (int b = 0; b < NZ; ++b) r -= (act ? q[R::OB + a * NZ + b] : T(0)) * d1[b];
     }
     if (t + 2 < Tn) {
-      const T* q = blk + (traj * Tn + t + 2) * R::SIZE;
+      const T* q = rec + 2 * R::SIZE;
+      const T* d2 = &sY[s2][g * RS];
 #pragma unroll
-      for (int a = 0; a < NZ; ++a)
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) x[i] -= q[R::OC + a * NZ + i] * q[R::OY + a];
+      for (int b = 0; b < NZ; ++b) r -= (act ? q[R::OC + a * NZ + b] : T(0)) * d2[b];
     }
+    // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
+    T Lc[NZ];
 #pragma unroll
-    for (int i = NZ - 1; i >= 0; --i) {
-      T v = x[i];
+    for (int k = 0; k < NZ; ++k) Lc[k] = act ? rec[R::OH + a * NZ + k] : T(k == a);
+    T d = T(0);
 #pragma unroll
-      for (int k = i + 1; k < NZ; ++k) v -= rec[R::OL + tri(k, i)] * x[k];
-      x[i] = v / rec[R::OL + tri(i, i)];
+    for (int k = NZ - 1; k >= 0; --k) {
+      T lkk = T(1);
+#pragma unroll
+      for (int q = 0; q < NZ; ++q)
+        if (q == a) lkk = Lc[q];
+      if (a == k) d = r / lkk;
+      const T dk = __shfl(d, base + k, 64);
+      if (a < k) r -= Lc[k] * dk;
     }
-#pragma unroll
-    for (int k = 0; k < NZ; ++k) {
-      rec[R::OY + k] = x[k];
-      gd += rec[R::OG + k] * x[k];
+    __syncthreads();
+    if (inw) sY[s0][g * RS + a] = d;
+    if (act) {
+      rec[R::OY + a] = d;
+      gd += rec[R::OG + a] * d;
     }
+    __syncthreads();
   }
-  chol_ok[traj] = ok ? 1 : 0;
-  gd_out[traj] = gd;
+  // per-trajectory reductions over the NZ row lanes
+  T gsum = T(0);
+  int okall = 1;
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    gsum += __shfl(gd, base + k, 64);
+    okall &= __shfl((int)ok, base + k, 64);
+  }
+  if (act && a == 0) {
+    chol_ok[traj] = okall;
+    gd_out[traj] = gsum;
+  }
 }
 
 template <int NS, typename T>
@@ -638,50 +688,74 @@ __global__ void k_fill(int64_t n, T* __restrict__ x, T v) {
   if (i < n) x[i] = v;
 }
 
-// Argmin over candidates per problem and the FP64 assessment of the winner.
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    v = MAX ? fmax(v, o) : fmin(v, o);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) s = MAX ? fmax(s, red[k]) : fmin(s, red[k]);
+  return s;
+}
+
+// Argmin over candidates per problem and the FP64 assessment of the winner: one
+// workgroup per problem, one lane per waypoint.
 template <int NS, typename TC>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
     k_traj_finalize(RobotT<double> rb, TrajArgs<double> ta, int nc, const int32_t* __restrict__ sel,
                     const TC* __restrict__ Zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
                     double* __restrict__ u_out, double* __restrict__ err_out, int32_t* __restrict__ status_out) {
   constexpr int NZ = 2 * NS;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double red[4];
+  __shared__ int s_best;
+  const int64_t p = blockIdx.x;
   const int64_t P = ta.P;
-  if (p >= P) return;
   const int Tn = ta.H + 1;
-  int best = -1, best_seed = 0;
-  double best_cost = 0.0;
-  for (int k = 0; k < nc; ++k) {
-    const int64_t tr = p * nc + k;
-    const int seed = sel ? sel[k * P + p] : k;
-    const double c = (double)costc[tr];
-    if (seed < 0 || failedc[tr] || !tfinite(c)) continue;
-    if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
-      best = k;
-      best_cost = c;
-      best_seed = seed;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int best = -1, best_seed = 0;
+    double best_cost = 0.0;
+    for (int k = 0; k < nc; ++k) {
+      const int64_t tr = p * nc + k;
+      const int seed = sel ? sel[k * P + p] : k;
+      const double c = (double)costc[tr];
+      if (seed < 0 || failedc[tr] || !tfinite(c)) continue;
+      if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
+        best = k;
+        best_cost = c;
+        best_seed = seed;
+      }
     }
+    s_best = best;
   }
+  __syncthreads();
+  const int best = s_best;
   const int64_t BU = P * Tn;
   if (best < 0) {
     const double nan = __builtin_nan("");
-    for (int t = 0; t < Tn; ++t)
-      for (int m = 0; m < 3 * NS; ++m) u_out[m * BU + p * Tn + t] = nan;
-    err_out[p] = err_out[P + p] = nan;
-    status_out[p] = CR_NONFINITE;
+    for (int m = 0; m < 3 * NS && t < Tn; ++m) u_out[m * BU + p * Tn + t] = nan;
+    if (t == 0) {
+      err_out[p] = err_out[P + p] = nan;
+      status_out[p] = CR_NONFINITE;
+    }
     return;
   }
   const int64_t tr = p * nc + best;
-  double pos = 0.0, rot = 0.0, viol = -DBL_MAX, thx = -DBL_MAX, gmin = DBL_MAX;
-  for (int t = 0; t < Tn; ++t) {
+  double pos = 0.0, rot = 0.0, viol = 0.0, thx = 0.0, gmin = DBL_MAX;
+  if (t < Tn) {
     double z[NZ];
 #pragma unroll
     for (int m = 0; m < NZ; ++m) z[m] = (double)Zc[(tr * Tn + t) * NZ + m];
-    double Rc[9], pc[3];
-    fk_tip<NS>(rb, z, Rc, pc);
-    bool check = ta.kind == CR_KIND_PATH || t == 0 || t == Tn - 1;
+    const bool check = ta.kind == CR_KIND_PATH || t == 0 || t == Tn - 1;
     if (check) {
-      double tt[12];
+      double Rc[9], pc[3], tt[12];
+      fk_tip<NS>(rb, z, Rc, pc);
       if (ta.kind == CR_KIND_PATH) {
         load_pose(ta, p, t, tt);
       } else {
@@ -699,13 +773,13 @@ __global__ void __launch_bounds__(64)
         }
       }
       double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
-      pos = fmax(pos, sqrt(dot3(dp, dp)));
+      pos = sqrt(dot3(dp, dp));
       double Re[9], te[3];
       relative_pose(Rc, pc, tt, Re, te);
       double v[3] = {0.5 * (Re[7] - Re[5]), 0.5 * (Re[2] - Re[6]), 0.5 * (Re[3] - Re[1])};
-      rot = fmax(rot, atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0)));
+      rot = atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0));
     }
-    // bounds and zero-sum output
+    // bounds, zero-sum output, clearance (margin 0) of every backbone point
     double Rp[9], pp[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? 1.0 : 0.0;
@@ -719,25 +793,29 @@ __global__ void __launch_bounds__(64)
         u_out[(3 * i + j) * BU + p * Tn + t] = u[j];
         viol = fmax(viol, fabs(u[j]) - rb.umaxd[i]);
       }
-      thx = fmax(thx, sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) - rb.theta_maxd);
-      // clearance (margin 0) of every backbone point
+      const double s = z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1];
+      thx = fmax(thx, sqrt(s) - rb.theta_maxd);
       if (ta.M > 0) {
-        const double s = z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1];
-        for (int k = 1; k <= rb.K; ++k) {
-          const double sg = (double)k / (double)rb.K;
-          ArcCoef<double> ck = arc_coef<double, false>(sg * sg * s);
-          double Rk[9], dk[3], x[3];
-          seg_R_d(sg * z[2 * i], sg * z[2 * i + 1], sg * rb.Ld[i], ck, Rk, dk);
-          mv3(Rp, dk, x);
-          for (int m = 0; m < ta.M; ++m) {
-            const int64_t col = (ta.per_problem ? p * ta.M : 0) + m;
-            const double d0 = pp[0] + x[0] - ta.sph[col], d1 = pp[1] + x[1] - ta.sph[ta.sld + col],
-                         d2 = pp[2] + x[2] - ta.sph[2 * ta.sld + col];
-            gmin = fmin(gmin, sqrt(d0 * d0 + d1 * d1 + d2 * d2) - ta.sph[3 * ta.sld + col] - rb.rd[i]);
+        // every point of the segment lies within L_i / 2 of its arc midpoint; only
+        // the sign of the smallest clearance is reported, so spheres that cannot
+        // reach the segment are skipped
+        double xm[3];
+        seg_point(Rp, pp, z[2 * i], z[2 * i + 1], rb.Ld[i], s, 0.5, xm);
+        for (int m = 0; m < ta.M; ++m) {
+          const int64_t col = (ta.per_problem ? p * ta.M : 0) + m;
+          const double cx = ta.sph[col], cy = ta.sph[ta.sld + col], cz = ta.sph[2 * ta.sld + col];
+          const double rs = ta.sph[3 * ta.sld + col];
+          const double e0 = xm[0] - cx, e1 = xm[1] - cy, e2 = xm[2] - cz;
+          if (sqrt(e0 * e0 + e1 * e1 + e2 * e2) - rs - rb.rd[i] - 0.5 * rb.Ld[i] > 0.0) continue;
+          for (int k = 1; k <= rb.K; ++k) {
+            double x[3];
+            seg_point(Rp, pp, z[2 * i], z[2 * i + 1], rb.Ld[i], s, (double)k / (double)rb.K, x);
+            const double d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+            gmin = fmin(gmin, sqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - rb.rd[i]);
           }
         }
       }
-      ArcCoef<double> c = arc_coef<double, false>(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]);
+      ArcCoef<double> c = arc_coef<double, false>(s);
       double Ri[9], di[3], q[3], Rn[9];
       seg_R_d(z[2 * i], z[2 * i + 1], rb.Ld[i], c, Ri, di);
       mv3(Rp, di, q);
@@ -749,14 +827,21 @@ __global__ void __launch_bounds__(64)
       for (int k = 0; k < 9; ++k) Rp[k] = Rn[k];
     }
   }
-  int32_t st = 0;
-  if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if (gmin < 0.0) st |= CR_COLLISION;
-  if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
-  if (st == 0) st = CR_SOLVED;
-  err_out[p] = pos;
-  err_out[P + p] = rot;
-  status_out[p] = st;
+  pos = block_reduce<true>(pos, red);
+  rot = block_reduce<true>(rot, red);
+  viol = block_reduce<true>(viol, red);
+  thx = block_reduce<true>(thx, red);
+  gmin = block_reduce<false>(gmin, red);
+  if (t == 0) {
+    int32_t st = 0;
+    if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
+    if (gmin < 0.0) st |= CR_COLLISION;
+    if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
+    if (st == 0) st = CR_SOLVED;
+    err_out[p] = pos;
+    err_out[P + p] = rot;
+    status_out[p] = st;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -774,7 +859,7 @@ struct TrajWs {
 
 static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype dt, char* base, TrajWs* w) {
   const size_t t1 = dt == CR_F64 ? 8 : 4;
-  const int NZ = 2 * ns, NP = NZ * (NZ + 1) / 2, REC = NP + 2 * NZ * NZ + 2 * NZ;
+  const int NZ = 2 * ns, REC = 3 * NZ * NZ + 2 * NZ;  // struct Rec
   const int64_t Tn = H + 1, n1 = P * S, n2 = P * (nf > 0 ? nf : 1);
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -832,11 +917,12 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   const int Tn = ta.H + 1;
   const int threads = ((Tn + 63) / 64) * 64;
   const size_t lds_b = traj_lds<NS, T>(ta.H, ta.M, true), lds_s = traj_lds<NS, T>(ta.H, ta.M, false);
+  constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL((k_traj_build<NS, T>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, c0,
                        failed);
-    hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + 63) / 64)), dim3(64), 0, st, nt, ta.H, blk, lam,
-                       failed, chol, gd);
+    hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, nt, ta.H, blk,
+                       lam, failed, chol, gd);
     hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
                        lam, c0, gd, chol, failed, trials);
   }
@@ -894,10 +980,10 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const cr_spheres* sp, i
     const size_t lds_e2 = traj_lds<NS, double>(H, M, false);
     hipLaunchKernelGGL((k_traj_eval<NS, double>), dim3((unsigned)n2), dim3(threads), lds_e2, st, rbd, wd, ta2,
                        (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2);
-    hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, rbd, tad, nf,
+    hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, nf,
                        ws.sel, (const double*)ws.Z2, (const double*)ws.cost2, ws.fail2, u_out, err_out, status_out);
   } else {
-    hipLaunchKernelGGL((k_traj_finalize<NS, T1>), dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, rbd, tad, S,
+    hipLaunchKernelGGL((k_traj_finalize<NS, T1>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, S,
                        (const int32_t*)nullptr, (const T1*)ws.Z1, (const T1*)ws.cost1, ws.fail1, u_out, err_out,
                        status_out);
   }

@@ -35,7 +35,9 @@ def case(oracle, kind, seed, n=3, H=9, P=3, S=2, M=0, K=4):
     else:
         ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
         task = ends
-        seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, Tn, b) for p in range(P)])
+        # bumped seeds only (the straight seed has zero acceleration)
+        seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S + 1, Tn, b, amp=0.8)[1:]
+                          for p in range(P)])
     sph = np.zeros((P, max(M, 1), 4))
     for p in range(P):
         _, _, pts = oracle.fk(ro, seeds[p, 0], points=True)
