@@ -826,43 +826,55 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
         const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
         const TC reach = (TC)sm[3 * cs] + ri + marg;
         const T rq = (sm[3 * cs] + rf) * slack;
-        for (int k = 1; k <= K; ++k) {
-          const TC sg = TC(k) / TC(K);
-          ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
-          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
-          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
-          TC x[3];
-          mv3(Rc, dk, x);
-          x[0] += pc[0];
-          x[1] += pc[1];
-          x[2] += pc[2];
-          const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+        // runs of at most 8 points, each skipped when the ball around its middle
+        // arc point (radius: half the run's arc length) misses the sphere
+        for (int k0 = 1; k0 <= K; k0 += 8) {
+          const int k1 = k0 + 7 < K ? k0 + 7 : K;
           {
-            const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
-            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+            T xr[3];
+            seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
+            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[cs], e2 = xr[2] - sm[2 * cs];
+            const T rr = (sm[3 * cs] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
-          const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
-          const TC viol = reach - dist;  // margin - (dist - R - r)
-          if (!(viol > TC(0))) continue;
-          const TC rr = sqc * viol;
-          cost += (T)(TC(0.5) * rr * rr);
-          if (GRAD) {
-            // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
-            const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
-            const TC fx[3] = {sc * d0, sc * d1, dist > TC(0) ? sc * d2 : -sqc * rr};
-#pragma unroll
-            for (int q = 0; q < 3; ++q) f.F[i][q] += (T)fx[q];
-            TC mx[3];
-            cross3(x, fx, mx);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) f.Mo[i][q] += (T)mx[q];
-            // own arc: x = pc + Rc d(sg a, sg b, sg L)
-            TC q[3];
-            mtv3(Rc, fx, q);
-            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
-            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
-            f.gz[2 * i] += (T)(sg * dot3(q, dda));
-            f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
+          for (int k = k0; k <= k1; ++k) {
+            const TC sg = TC(k) / TC(K);
+            ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
+            const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+            TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+            TC x[3];
+            mv3(Rc, dk, x);
+            x[0] += pc[0];
+            x[1] += pc[1];
+            x[2] += pc[2];
+            const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+            {
+              const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
+              if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+            }
+            const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const TC viol = reach - dist;  // margin - (dist - R - r)
+            if (!(viol > TC(0))) continue;
+            const TC rr = sqc * viol;
+            cost += (T)(TC(0.5) * rr * rr);
+            if (GRAD) {
+              // d(1/2 r^2)/dx = -sq_coll r n,  n = (x - c)/|x - c|  (+z when coincident)
+              const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
+              const TC fx[3] = {sc * d0, sc * d1, dist > TC(0) ? sc * d2 : -sqc * rr};
+  #pragma unroll
+              for (int q = 0; q < 3; ++q) f.F[i][q] += (T)fx[q];
+              TC mx[3];
+              cross3(x, fx, mx);
+  #pragma unroll
+              for (int q = 0; q < 3; ++q) f.Mo[i][q] += (T)mx[q];
+              // own arc: x = pc + Rc d(sg a, sg b, sg L)
+              TC q[3];
+              mtv3(Rc, fx, q);
+              const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+              const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+              f.gz[2 * i] += (T)(sg * dot3(q, dda));
+              f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
+            }
           }
         }
       }
@@ -1134,64 +1146,76 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
         const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
         const TC reach = (TC)sm[3 * cs] + ri + marg;
         const T rq = (sm[3 * cs] + rf) * slack;
-        for (int k = 1; k <= K; ++k) {
-          const TC sg = TC(k) / TC(K);
-          ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
-          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
-          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
-          TC x[3];
-          mv3(Rc, dk, x);
-          x[0] += pc[0];
-          x[1] += pc[1];
-          x[2] += pc[2];
-          const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+        // runs of at most 8 points, each skipped when the ball around its middle
+        // arc point (radius: half the run's arc length) misses the sphere
+        for (int k0 = 1; k0 <= K; k0 += 8) {
+          const int k1 = k0 + 7 < K ? k0 + 7 : K;
           {
-            const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
-            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
+            T xr[3];
+            seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
+            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[cs], e2 = xr[2] - sm[2 * cs];
+            const T rr = (sm[3 * cs] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
-          const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
-          const TC viol = reach - dist;
-          if (!(viol > TC(0))) continue;
-          const T rr = (T)((TC)w.sq_coll * viol);
-          const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
-          // residual sq_coll (reach - |x - c|): row = -sq_coll n^T dx/dz
-          T nvec[3];
-          if (dist > TC(0)) {
-            const TC id = TC(1) / dist;
-            nvec[0] = (T)(d0 * id);
-            nvec[1] = (T)(d1 * id);
-            nvec[2] = (T)(d2 * id);
-          } else {
-            nvec[0] = nvec[1] = T(0);
-            nvec[2] = T(1);
-          }
-          T row[NZ];
-#pragma unroll
-          for (int q = 0; q < NZ; ++q) row[q] = T(0);
-#pragma unroll
-          for (int j = 0; j < NS; ++j) {
-            if (j < i) {
-              T xm[3] = {xf[0] - pe[j][0], xf[1] - pe[j][1], xf[2] - pe[j][2]}, c3[3];
-              cross3(xm, nvec, c3);
-              row[2 * j] = -w.sq_coll * (dot3(W[2 * j], c3) + dot3(Pd[2 * j], nvec));
-              row[2 * j + 1] = -w.sq_coll * (dot3(W[2 * j + 1], c3) + dot3(Pd[2 * j + 1], nvec));
+          for (int k = k0; k <= k1; ++k) {
+            const TC sg = TC(k) / TC(K);
+            ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
+            const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+            TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+            TC x[3];
+            mv3(Rc, dk, x);
+            x[0] += pc[0];
+            x[1] += pc[1];
+            x[2] += pc[2];
+            const TC d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+            {
+              const T e0 = (T)d0, e1 = (T)d1, e2 = (T)d2;
+              if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
             }
-          }
-          {
-            TC nq[3] = {(TC)nvec[0], (TC)nvec[1], (TC)nvec[2]}, q[3];
-            mtv3(Rc, nq, q);
-            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
-            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
-            row[2 * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
-            row[2 * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
-          }
-          cost += T(0.5) * rr * rr;
-#pragma unroll
-          for (int k1 = 0; k1 < NZ; ++k1) {
-            if (k1 <= 2 * i + 1) {
-              g[k1] += row[k1] * rr;
-#pragma unroll
-              for (int k2 = 0; k2 <= k1; ++k2) Hp[tri(k1, k2)] += row[k1] * row[k2];
+            const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const TC viol = reach - dist;
+            if (!(viol > TC(0))) continue;
+            const T rr = (T)((TC)w.sq_coll * viol);
+            const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
+            // residual sq_coll (reach - |x - c|): row = -sq_coll n^T dx/dz
+            T nvec[3];
+            if (dist > TC(0)) {
+              const TC id = TC(1) / dist;
+              nvec[0] = (T)(d0 * id);
+              nvec[1] = (T)(d1 * id);
+              nvec[2] = (T)(d2 * id);
+            } else {
+              nvec[0] = nvec[1] = T(0);
+              nvec[2] = T(1);
+            }
+            T row[NZ];
+  #pragma unroll
+            for (int q = 0; q < NZ; ++q) row[q] = T(0);
+  #pragma unroll
+            for (int j = 0; j < NS; ++j) {
+              if (j < i) {
+                T xm[3] = {xf[0] - pe[j][0], xf[1] - pe[j][1], xf[2] - pe[j][2]}, c3[3];
+                cross3(xm, nvec, c3);
+                row[2 * j] = -w.sq_coll * (dot3(W[2 * j], c3) + dot3(Pd[2 * j], nvec));
+                row[2 * j + 1] = -w.sq_coll * (dot3(W[2 * j + 1], c3) + dot3(Pd[2 * j + 1], nvec));
+              }
+            }
+            {
+              TC nq[3] = {(TC)nvec[0], (TC)nvec[1], (TC)nvec[2]}, q[3];
+              mtv3(Rc, nq, q);
+              const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+              const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+              row[2 * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
+              row[2 * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
+            }
+            cost += T(0.5) * rr * rr;
+  #pragma unroll
+            for (int k1 = 0; k1 < NZ; ++k1) {
+              if (k1 <= 2 * i + 1) {
+                g[k1] += row[k1] * rr;
+  #pragma unroll
+                for (int k2 = 0; k2 <= k1; ++k2) Hp[tri(k1, k2)] += row[k1] * row[k2];
+              }
             }
           }
         }

@@ -75,25 +75,221 @@ __device__ __forceinline__ void load_pose(const TrajArgs<T>& ta, int64_t p, int 
   for (int c = 0; c < 12; ++c) Tt[c] = (T)ta.task[c * (ta.P * Tn) + p * Tn + t];
 }
 
+// Work list of the clearance term of one trajectory.  Every waypoint lane stores
+// its segment base frames and pushes the (waypoint, segment, sphere) triples that
+// pass the segment-ball test; then all lanes of the workgroup share the
+// (triple, backbone point) pairs, so a few colliding waypoints do not hold the
+// whole wave in their point loops.
+template <typename T>
+struct CollList {
+  static constexpr int FR = 17;
+  T* fr;      // [(t * NS + i) * FR]: base rotation (9), base position (3), a, b, arc midpoint (3)
+  int* list;  // packed triples (t << 12) | (i << 9) | m, one slice per wave
+  int* cnt;   // entries per wave (at most 4 waves)
+  int cap;    // 0: no list, each lane loops over its own points
+};
+
+// The list area follows the other LDS arrays: frames, then the counter and the
+// packed triples.
+template <int NS, typename T>
+__device__ __forceinline__ CollList<T> coll_list(T* area, int Tn, int cap) {
+  CollList<T> cl;
+  cl.fr = area;
+  cl.cnt = reinterpret_cast<int*>(area + Tn * NS * CollList<T>::FR);
+  cl.list = cl.cnt + 4;
+  cl.cap = cap;
+  return cl;
+}
+
+// Clearance residual of one backbone point x against sphere sm, squared / 2.
+template <typename T>
+__device__ __forceinline__ T point_sphere_cost(const T* x, const T* sm, T reach, T sqc) {
+  const T d0 = x[0] - sm[0], d1 = x[1] - sm[1], d2 = x[2] - sm[2];
+  const T q = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(q < reach * reach)) return T(0);
+  const T viol = reach - tsqrt(q);
+  if (!(viol > T(0))) return T(0);
+  const T rr = sqc * viol;
+  return T(0.5) * rr * rr;
+}
+
+// Lane t (waypoints within the horizon): base frame and arc midpoint of every
+// segment of waypoint t, into the list's frame area.
+template <int NS, typename T>
+__device__ __forceinline__ void coll_frames(const RobotT<T>& rb, const T* z, int t, const CollList<T>& cl) {
+  T Rc[9], pc[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
+  pc[0] = pc[1] = pc[2] = T(0);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const T a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
+    T* fr = cl.fr + (t * NS + i) * CollList<T>::FR;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fr[k] = Rc[k];
+    fr[9] = pc[0];
+    fr[10] = pc[1];
+    fr[11] = pc[2];
+    fr[12] = a;
+    fr[13] = b;
+    seg_point(Rc, pc, a, b, rb.L[i], s, T(0.5), fr + 14);
+    ArcCoef<T> c = arc_coef<T, false>(s);
+    T Ri[9], di[3], q[3], Rn[9];
+    seg_R_d(a, b, rb.L[i], c, Ri, di);
+    mv3(Rc, di, q);
+    pc[0] += q[0];
+    pc[1] += q[1];
+    pc[2] += q[2];
+    mm3(Rc, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+  }
+}
+
+template <int NS, typename T>
+__device__ __forceinline__ void seg_consts(const RobotT<T>& rb, int i, T& Li, T& ri) {
+  Li = rb.L[0];
+  ri = rb.r[0];
+#pragma unroll
+  for (int q = 1; q < NS; ++q)
+    if (q == i) {
+      Li = rb.L[q];
+      ri = rb.r[q];
+    }
+}
+
+// All lanes, after the frames are stored: segment-ball tests with one sphere per
+// lane (chunks of 64 spheres) against every (waypoint, segment).  Each wave owns a
+// slice of the list and takes its pairs t * NS + i in a strided order; hits are
+// placed with a ballot in (pair, sphere) order, so the list, and every sum over
+// it, is the same on every run.  Hits that do not fit are evaluated by their
+// lane; returns that cost.
+template <int NS, typename T>
+__device__ __forceinline__ T coll_enqueue(const RobotT<T>& rb, const WeightsT<T>& w, const T* s_sph, int M, int Tn,
+                                          const CollList<T>& cl) {
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6), nwv = (int)((blockDim.x + 63) >> 6);
+  const int capw = cl.cap / nwv;
+  int* wl = cl.list + wv * capw;
+  const int K = rb.K;
+  const T invK = T(1) / T(K);
+  const int npair = Tn * NS;
+  int used = 0;  // entries of this wave so far (uniform across the wave)
+  T cost = T(0);
+  for (int m0 = 0; m0 < M; m0 += 64) {
+    const int m = m0 + lane;
+    const bool has = m < M;
+    const T* sm = s_sph + 4 * (has ? m : 0);
+    const T c0 = sm[0], c1 = sm[1], c2 = sm[2], rs = sm[3];
+    for (int pr = wv; pr < npair; pr += nwv) {
+      const int t = pr / NS, i = pr - t * NS;
+      T Li, ri;
+      seg_consts<NS>(rb, i, Li, ri);
+      const T* fr = cl.fr + pr * CollList<T>::FR;
+      const T e0 = fr[14] - c0, e1 = fr[15] - c1, e2 = fr[16] - c2;
+      const T rq = (rs + ri + w.margin + T(0.5) * Li) * T(1.0001);
+      const bool hit = has && e0 * e0 + e1 * e1 + e2 * e2 < rq * rq;
+      const unsigned long long mask = __ballot(hit);
+      if (mask == 0ull) continue;
+      const int rank =
+          (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+      const int slot = used + rank;
+      used += __popcll(mask);
+      if (!hit) continue;
+      if (slot < capw) {
+        wl[slot] = (t << 12) | (i << 9) | m;
+      } else {
+        const T a = fr[12], b = fr[13];
+        for (int k = 1; k <= K; ++k) {
+          T x[3];
+          seg_point(fr, fr + 9, a, b, Li, a * a + b * b, T(k) * invK, x);
+          cost += point_sphere_cost(x, sm, rs + ri + w.margin, w.sq_coll);
+        }
+      }
+    }
+  }
+  if (lane == 0) cl.cnt[wv] = used < capw ? used : capw;
+  return cost;
+}
+
+// All lanes: every listed (waypoint, segment, sphere) triple, split into runs of
+// at most 8 backbone points; a run whose own ball (around its middle arc point)
+// misses the sphere is skipped.  Work items (triple, run) are strided over the
+// workgroup.
+template <int NS, typename T>
+__device__ __forceinline__ T coll_drain(const RobotT<T>& rb, const WeightsT<T>& w, const T* s_sph,
+                                        const CollList<T>& cl) {
+  const int K = rb.K, nth = (int)blockDim.x, nwv = (nth + 63) >> 6;
+  const int Q = (K + 7) >> 3;
+  const int capw = cl.cap / nwv;
+  const T invK = T(1) / T(K);
+  const int de = nth / Q, dq = nth - de * Q;
+  T cost = T(0);
+  for (int wv = 0; wv < nwv; ++wv) {
+    const int* wl = cl.list + wv * capw;
+    const int total = cl.cnt[wv] * Q;
+    int e = (int)threadIdx.x / Q, q = (int)threadIdx.x - e * Q;
+    for (int wi = (int)threadIdx.x; wi < total; wi += nth) {
+      const int code = wl[e];
+      const int t = code >> 12, i = (code >> 9) & 7, m = code & 511;
+      T Li, ri;
+      seg_consts<NS>(rb, i, Li, ri);
+      const T* fr = cl.fr + (t * NS + i) * CollList<T>::FR;
+      const T a = fr[12], b = fr[13], s = a * a + b * b;
+      const T* sm = s_sph + 4 * m;
+      const T reach = sm[3] + ri + w.margin;
+      const int k0 = 8 * q + 1, k1 = 8 * q + 8 < K ? 8 * q + 8 : K;
+      T xc[3];
+      seg_point(fr, fr + 9, a, b, Li, s, T(k0 + k1) * T(0.5) * invK, xc);
+      const T d0 = xc[0] - sm[0], d1 = xc[1] - sm[1], d2 = xc[2] - sm[2];
+      const T rq = (reach + T(k1 - k0) * T(0.5) * invK * Li) * T(1.0001);
+      if (d0 * d0 + d1 * d1 + d2 * d2 < rq * rq) {
+        for (int k = k0; k <= k1; ++k) {
+          T x[3];
+          seg_point(fr, fr + 9, a, b, Li, s, T(k) * invK, x);
+          cost += point_sphere_cost(x, sm, reach, w.sq_coll);
+        }
+      }
+      e += de;
+      q += dq;
+      if (q >= Q) {
+        q -= Q;
+        ++e;
+      }
+    }
+  }
+  return cost;
+}
+
 // Cost of one trajectory (value only), all lanes of the workgroup participate;
 // lane t evaluates waypoint t.  If pen != NULL the collision part alone is also
 // returned (every other weight zeroed).  s_u, s_p: LDS scratch of (H+1)*3n and
 // (H+1)*3 values.
 template <int NS, typename T>
-__device__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int64_t p, const T* z,
-                       const T* s_sph, T* s_u, T* s_p, T* s_red, T* pen) {
+__device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int64_t p, const T* z,
+                       const T* s_sph, T* s_u, T* s_p, T* s_red, T* pen, const CollList<T>& cl) {
   constexpr int NU = 3 * NS;
   const int t = threadIdx.x, H = ta.H;
   const bool act = t <= H;
+  const bool listed = cl.cap > 0 && ta.M > 0;
   T cst = T(0), cpen = T(0);
+  if (listed) {
+    if (act) coll_frames<NS>(rb, z, t, cl);
+    __syncthreads();
+    cpen = coll_enqueue<NS>(rb, w, s_sph, ta.M, H + 1, cl);
+    cst = cpen;
+  }
   if (act) {
     Fwd<NS, T> f;
-    cst = config_forward<NS, T, false>(rb, w, z, s_sph, ta.M, 4, 1, f);
-    if (pen && ta.M > 0) {
-      WeightsT<T> wc = w;
-      wc.sq_lim = wc.sq_curv = T(0);
-      Fwd<NS, T> f2;
-      cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
+    if (listed) {
+      cst += config_forward<NS, T, false>(rb, w, z, s_sph, 0, 4, 1, f);
+    } else {
+      cst = config_forward<NS, T, false>(rb, w, z, s_sph, ta.M, 4, 1, f);
+      if (pen && ta.M > 0) {
+        WeightsT<T> wc = w;
+        wc.sq_lim = wc.sq_curv = T(0);
+        Fwd<NS, T> f2;
+        cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
+      }
     }
     if (ta.kind == CR_KIND_PATH) {
       T Tt[12], ft[3], tq[3];
@@ -112,6 +308,11 @@ __device__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs
     s_p[3 * t + 2] = f.p[2];
   }
   __syncthreads();
+  if (listed) {
+    const T part = coll_drain<NS>(rb, w, s_sph, cl);
+    cst += part;
+    cpen += part;
+  }
   if (act) {
     const T idt = T(1) / w.dt, idt2 = idt * idt;
 #pragma unroll
@@ -579,7 +780,7 @@ __global__ void __launch_bounds__(256)
     k_traj_search(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                   const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                   const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, const int32_t* __restrict__ failed,
-                  int32_t* __restrict__ trials) {
+                  int32_t* __restrict__ trials, int list_cap) {
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -588,6 +789,7 @@ __global__ void __launch_bounds__(256)
   T* s_u = s_sph + 4 * ta.M;
   T* s_p = s_u + Tn * NU;
   T* s_red = s_p + Tn * 3;
+  const CollList<T> cl = coll_list<NS>(s_red + 8, Tn, list_cap);
   const int64_t traj = blockIdx.x;
   const int64_t p = traj / ta.per;
   if (failed[traj]) return;
@@ -613,7 +815,7 @@ __global__ void __launch_bounds__(256)
   for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
     for (int k = 0; k < NZ; ++k) zt[k] = act ? z[k] + alpha * dl[k] : T(0);
-    const T c = traj_cost<NS>(rb, w, ta, p, zt, s_sph, s_u, s_p, s_red, (T*)nullptr);
+    const T c = traj_cost<NS>(rb, w, ta, p, zt, s_sph, s_u, s_p, s_red, (T*)nullptr, cl);
     ++ntr;
     if (c <= c0 + T(1e-4) * alpha * gd) {
       acc = tr;
@@ -638,7 +840,7 @@ __global__ void __launch_bounds__(256)
 template <int NS, typename T>
 __global__ void __launch_bounds__(256)
     k_traj_eval(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, const T* __restrict__ Z, T* __restrict__ cost,
-                T* __restrict__ pen, int32_t* __restrict__ failed) {
+                T* __restrict__ pen, int32_t* __restrict__ failed, int list_cap) {
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int H = ta.H, Tn = H + 1;
@@ -646,6 +848,7 @@ __global__ void __launch_bounds__(256)
   T* s_u = s_sph + 4 * ta.M;
   T* s_p = s_u + Tn * NU;
   T* s_red = s_p + Tn * 3;
+  const CollList<T> cl = coll_list<NS>(s_red + 8, Tn, list_cap);
   const int64_t traj = blockIdx.x;
   const int64_t p = traj / ta.per;
   stage_spheres(ta, p, s_sph);
@@ -655,7 +858,7 @@ __global__ void __launch_bounds__(256)
   for (int k = 0; k < NZ; ++k) z[k] = t < Tn ? Z[(traj * Tn + t) * NZ + k] : T(0);
   __syncthreads();
   T pn;
-  const T c = traj_cost<NS>(rb, w, ta, p, z, s_sph, s_u, s_p, s_red, &pn);
+  const T c = traj_cost<NS>(rb, w, ta, p, z, s_sph, s_u, s_p, s_red, &pn, cl);
   if (threadIdx.x == 0) {
     cost[traj] = c;
     pen[traj] = pn;
@@ -904,6 +1107,27 @@ static size_t traj_lds(int H, int M, bool build) {
   return sizeof(T) * (size_t)(4 * M + Tn * 3 * NS + Tn * 3 + (build ? Tn * 3 * NZ : 0) + 8);
 }
 
+// Capacity of the clearance work list of the search / evaluation kernels (0: none),
+// sized so that their LDS stays within 48 KiB.
+template <int NS, typename T>
+static int traj_list_cap(int H, int M) {
+  if (M <= 0) return 0;
+  const int Tn = H + 1;
+  const size_t budget = 48 * 1024;
+  const size_t base = traj_lds<NS, T>(H, M, false) + sizeof(T) * (size_t)Tn * NS * CollList<T>::FR + 16;
+  if (base >= budget) return 0;
+  size_t cap = (size_t)Tn * NS * M < 2048 ? (size_t)Tn * NS * M : 2048;
+  if (cap > (budget - base) / 4) cap = (budget - base) / 4;
+  return cap >= 64 ? (int)cap : 0;
+}
+
+template <int NS, typename T>
+static size_t traj_lds_list(int H, int M, int cap) {
+  size_t b = traj_lds<NS, T>(H, M, false);
+  if (cap > 0) b += sizeof(T) * (size_t)(H + 1) * NS * CollList<T>::FR + 16 + 4 * (size_t)cap;
+  return b;
+}
+
 template <int NS>
 bool traj_lds_ok(int H, int M) {
   return traj_lds<NS, double>(H, M, true) <= 64 * 1024;
@@ -916,7 +1140,8 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
                             int32_t* trials, hipStream_t st) {
   const int Tn = ta.H + 1;
   const int threads = ((Tn + 63) / 64) * 64;
-  const size_t lds_b = traj_lds<NS, T>(ta.H, ta.M, true), lds_s = traj_lds<NS, T>(ta.H, ta.M, false);
+  const int cap = traj_list_cap<NS, T>(ta.H, ta.M);
+  const size_t lds_b = traj_lds<NS, T>(ta.H, ta.M, true), lds_s = traj_lds_list<NS, T>(ta.H, ta.M, cap);
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL((k_traj_build<NS, T>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, c0,
@@ -924,7 +1149,7 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
     hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, nt, ta.H, blk,
                        lam, failed, chol, gd);
     hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
-                       lam, c0, gd, chol, failed, trials);
+                       lam, c0, gd, chol, failed, trials, cap);
   }
   return check_hip(hipGetLastError(), "trajectory LM stage");
 }
@@ -955,10 +1180,11 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const cr_spheres* sp, i
   rc = traj_stage<NS, T1>(rb1, w1, ta1, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1, (T1*)ws.lam1, (T1*)ws.c01,
                           (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
   if (rc != CR_OK) return rc;
-  const size_t lds_e1 = traj_lds<NS, T1>(H, M, false);
+  const int cap1 = traj_list_cap<NS, T1>(H, M);
+  const size_t lds_e1 = traj_lds_list<NS, T1>(H, M, cap1);
   const int threads = ((Tn + 63) / 64) * 64;
   hipLaunchKernelGGL((k_traj_eval<NS, T1>), dim3((unsigned)n1), dim3(threads), lds_e1, st, rb1, w1, ta1,
-                     (const T1*)ws.Z1, (T1*)ws.cost1, (T1*)ws.pen1, ws.fail1);
+                     (const T1*)ws.Z1, (T1*)ws.cost1, (T1*)ws.pen1, ws.fail1, cap1);
   TrajArgs<double> tad{kind, H, P, S, task, ta1.sph, ta1.sld, M, ta1.per_problem};
   if (o.n_final > 0) {
     const int nf = o.n_final;
@@ -977,9 +1203,10 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const cr_spheres* sp, i
     rc = traj_stage<NS, double>(rbd, wd, ta2, lo2, n2, o.k_final, ws.Z2, ws.blk2, ws.lam2, ws.c02, ws.gd2, ws.chol2,
                                 ws.fail2, ws.trials2, st);
     if (rc != CR_OK) return rc;
-    const size_t lds_e2 = traj_lds<NS, double>(H, M, false);
+    const int cap2 = traj_list_cap<NS, double>(H, M);
+    const size_t lds_e2 = traj_lds_list<NS, double>(H, M, cap2);
     hipLaunchKernelGGL((k_traj_eval<NS, double>), dim3((unsigned)n2), dim3(threads), lds_e2, st, rbd, wd, ta2,
-                       (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2);
+                       (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2, cap2);
     hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, nf,
                        ws.sel, (const double*)ws.Z2, (const double*)ws.cost2, ws.fail2, u_out, err_out, status_out);
   } else {

@@ -21,7 +21,7 @@ def cr():
     return crsolver
 
 
-def case(oracle, kind, seed, n=3, H=9, P=3, S=2, M=0, K=4):
+def case(oracle, kind, seed, n=3, H=9, P=3, S=2, M=0, K=4, rad_range=(0.003, 0.008)):
     rng = np.random.default_rng(seed)
     L, r, b = [0.08] * n, [0.008] * n, 0.006
     ro = oracle.Robot(L=L, r=r, u_max=[0.8 * b] * n, pts_per_seg=K, theta_max=0.9)
@@ -45,7 +45,7 @@ def case(oracle, kind, seed, n=3, H=9, P=3, S=2, M=0, K=4):
             t, i, k = rng.integers(0, Tn), rng.integers(0, n), rng.integers(0, K)
             d = rng.normal(size=3)
             d /= np.linalg.norm(d)
-            rad = rng.uniform(0.003, 0.008)
+            rad = rng.uniform(*rad_range)
             sph[p, m, :3] = pts[t, i, k] + d * (rad + r[i] + rng.uniform(-1.5e-3, 5e-4))
             sph[p, m, 3] = rad
     return dict(kind=kind, n=n, L=L, r=r, b=b, K=K, H=H, P=P, S=S, M=M, ro=ro, W=W, task=task, seeds=seeds, sph=sph)
@@ -121,6 +121,23 @@ def test_fp64_lm_step_map_long_horizon(oracle, cr, kind):
             u1 = oracle.z_to_u(c["ro"], z1.reshape(c["H"] + 1, c["n"], 2))
             assert np.abs(u[0] - u1).max() <= 1e-9 * c["b"], it
         z, lam = z1, lam1
+
+
+@pytest.mark.parametrize("kind", ["path", "traj"])
+def test_fp64_lm_many_sphere_hits(oracle, cr, kind):
+    """64 large spheres around a 64-waypoint trajectory: far more (waypoint,
+    segment, sphere) candidates than the clearance work list holds, so both the
+    shared list and the per-lane overflow path take part; 2 FP64 LM iterations
+    still equal the oracle's."""
+    print(f"traj fp64 dense spheres kind={kind}", flush=True)
+    c = case(oracle, kind, 320, n=4, H=63, P=1, S=1, M=64, K=4, rad_range=(0.03, 0.06))
+    u, _, _ = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=2, k_final=0), "f64")
+    W = oracle.Weights(**c["W"])
+    pb = oracle_problem(oracle, c, 0)
+    z0 = oracle.u_to_z(c["ro"], c["seeds"][0, 0]).ravel()
+    zk, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, 2)
+    uk = oracle.z_to_u(c["ro"], zk.reshape(c["H"] + 1, c["n"], 2))
+    assert np.abs(u[0] - uk).max() <= 1e-9 * c["b"], np.abs(u[0] - uk).max()
 
 
 def test_path_two_stage_quality(oracle, cr):
