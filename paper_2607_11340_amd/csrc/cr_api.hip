@@ -198,6 +198,16 @@ cr_status cr_fk(const cr_robot* robot, int64_t B, const void* u, int64_t ld, voi
   return launch_fk(*robot, B, u, ld, arc, frames, pts, dtype, stream);
 }
 
+static cr_status check_spheres(const cr_spheres* spheres, int64_t P) {
+  if (!spheres || spheres->n_sph == 0) return CR_OK;
+  if (spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
+  if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
+  if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
+  const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
+  if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
+  return CR_OK;
+}
+
 size_t cr_solve_ik_workspace(const cr_robot* robot, int64_t P, int32_t S, const cr_opts* opts, cr_dtype dtype) {
   if (check_robot(robot) != CR_OK || check_opts(opts) != CR_OK || check_dtype(dtype) != CR_OK || P < 0 || S < 1)
     return 0;
@@ -215,7 +225,7 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   if (P * (int64_t)S > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "P*S too large");
   if (P == 0) return CR_OK;
   if (!T_target || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
-  if (spheres && spheres->n_sph > 0) return fail(CR_EUNSUPPORTED, "spheres in cr_solve_ik not built yet");
+  if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
   size_t need = ik_workspace_layout(*robot, P, S, *opts, dtype, nullptr, nullptr);
   void* mem = ws;
   if (ws) {
@@ -226,7 +236,8 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   }
   IkWorkspace w;
   ik_workspace_layout(*robot, P, S, *opts, dtype, (char*)mem, &w);
-  rc = launch_solve_ik(*robot, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
+  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  rc = launch_solve_ik(*robot, sp, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
                        (double*)u_out, (double*)err_out, status_out, w, dtype, stream);
   if (!ws) {
     cr_status rc2 = check_hip(hipFreeAsync(mem, stream), "hipFreeAsync(workspace)");
@@ -249,6 +260,7 @@ cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const v
   return launch_select(P, S, nz, z, e, pen, failed, n_final, dup_eps, idx_out, dtype, stream);
 }
 
+
 static cr_status check_traj_args(const cr_robot* robot, const cr_spheres* spheres, const cr_weights* weights,
                                  const cr_opts* opts, int64_t P, int32_t H, int32_t S, int kind, cr_dtype dtype) {
   cr_status rc;
@@ -258,14 +270,7 @@ static cr_status check_traj_args(const cr_robot* robot, const cr_spheres* sphere
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
   if (H < (kind == CR_KIND_TRAJ ? 1 : 0) || H > 255) return fail(CR_EINVAL, "H=%d out of range", H);
   if (P * (int64_t)S * (H + 1) > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "batch too large");
-  if (spheres && spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
-  if (spheres && spheres->n_sph > 0) {
-    if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
-    if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
-    const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
-    if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
-  }
-  return CR_OK;
+  return check_spheres(spheres, P);
 }
 
 static cr_status solve_traj_common(int kind, const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,

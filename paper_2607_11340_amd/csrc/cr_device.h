@@ -780,8 +780,8 @@ struct Fwd {
 // backbone-to-centre distances, and FP32 positions would set its error.  The pair
 // rejection test stays in T (with a relative slack); active pairs are re-measured
 // in TC.
-template <int NS, typename T, bool GRAD, typename TC = T>
-CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const T* sph, int M, int64_t ms,
+template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T>
+CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
                        int64_t cs, Fwd<NS, T>& f, const double* zd = nullptr) {
   T cost = T(0);
   TC Rc[9], pc[3];
@@ -817,15 +817,16 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
       seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
       const T half = T(0.5) * rb.L[i];
       for (int m = 0; m < M; ++m) {
-        const T* sm = sph + m * ms;
+        const TS* sp = sph + m * ms;
+        const T sm[4] = {(T)sp[0], (T)sp[cs], (T)sp[2 * cs], (T)sp[3 * cs]};
         {
-          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[cs], e2 = xmf[2] - sm[2 * cs];
-          const T rq = (sm[3 * cs] + rf + half) * T(1.0001);
+          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[1], e2 = xmf[2] - sm[2];
+          const T rq = (sm[3] + rf + half) * T(1.0001);
           if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
         }
-        const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
-        const TC reach = (TC)sm[3 * cs] + ri + marg;
-        const T rq = (sm[3 * cs] + rf) * slack;
+        const TC cx = (TC)sp[0], cy = (TC)sp[cs], cz = (TC)sp[2 * cs];
+        const TC reach = (TC)sp[3 * cs] + ri + marg;
+        const T rq = (sm[3] + rf) * slack;
         // runs of at most 8 points, each skipped when the ball around its middle
         // arc point (radius: half the run's arc length) misses the sphere
         for (int k0 = 1; k0 <= K; k0 += 8) {
@@ -833,8 +834,8 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
           {
             T xr[3];
             seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
-            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[cs], e2 = xr[2] - sm[2 * cs];
-            const T rr = (sm[3 * cs] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[1], e2 = xr[2] - sm[2];
+            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
             if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
           for (int k = k0; k <= k1; ++k) {
@@ -1107,8 +1108,8 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
 // tip position and its Jacobian.  Tt may be NULL (no pose rows).  TC is the
 // chain type (FP64 when spheres are present, as in config_forward).
-template <int NS, typename T, typename TC>
-CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const T* sph, int M, int64_t ms,
+template <int NS, typename T, typename TC, typename TS = T>
+CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
                         int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[2 * NS]) {
   constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
 #pragma unroll
@@ -1137,15 +1138,16 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
       seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
       const T half = T(0.5) * rb.L[i];
       for (int m = 0; m < M; ++m) {
-        const T* sm = sph + m * ms;
+        const TS* sp = sph + m * ms;
+        const T sm[4] = {(T)sp[0], (T)sp[cs], (T)sp[2 * cs], (T)sp[3 * cs]};
         {
-          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[cs], e2 = xmf[2] - sm[2 * cs];
-          const T rq = (sm[3 * cs] + rf + half) * T(1.0001);
+          const T e0 = xmf[0] - sm[0], e1 = xmf[1] - sm[1], e2 = xmf[2] - sm[2];
+          const T rq = (sm[3] + rf + half) * T(1.0001);
           if (!(e0 * e0 + e1 * e1 + e2 * e2 < rq * rq)) continue;
         }
-        const TC cx = (TC)sm[0], cy = (TC)sm[cs], cz = (TC)sm[2 * cs];
-        const TC reach = (TC)sm[3 * cs] + ri + marg;
-        const T rq = (sm[3 * cs] + rf) * slack;
+        const TC cx = (TC)sp[0], cy = (TC)sp[cs], cz = (TC)sp[2 * cs];
+        const TC reach = (TC)sp[3 * cs] + ri + marg;
+        const T rq = (sm[3] + rf) * slack;
         // runs of at most 8 points, each skipped when the ball around its middle
         // arc point (radius: half the run's arc length) misses the sphere
         for (int k0 = 1; k0 <= K; k0 += 8) {
@@ -1153,8 +1155,8 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
           {
             T xr[3];
             seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
-            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[cs], e2 = xr[2] - sm[2 * cs];
-            const T rr = (sm[3 * cs] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[1], e2 = xr[2] - sm[2];
+            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
             if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
           for (int k = k0; k <= k1; ++k) {
@@ -1280,6 +1282,69 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   if (Tt) cost += pose_rows<NZ>(w, Rt, pt, W, dp, Tt, Hp, g);
   bounds_normal_eq<NS, NZ>(rb, w, z, 0, Hp, g, cost);
   return cost;
+}
+
+// Penalised cost of one configuration against a target pose (eq. 8-10, 17):
+// pose, bounds and clearance against M spheres (sphere m, component c at
+// sph[m * ms + c * cs], stored as TS).
+template <int NS, typename T, typename TS>
+CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z, const TS* sph, int M, int64_t ms,
+                 int64_t cs) {
+  Fwd<NS, T> f;
+  T c = config_forward<NS, T, false, T, TS>(rb, w, z, sph, M, ms, cs, f);
+  T ft[3], tq[3];
+  return c + pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
+}
+
+// lm_ik with clearance rows: the same iteration, the generic per-configuration
+// normal equations and cost.
+template <int NS, typename T, typename TS>
+CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
+                  bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs) {
+  constexpr int NZ = 2 * NS;
+  constexpr int NP = NZ * (NZ + 1) / 2;
+  for (int it = 0; it < iters; ++it) {
+    T Hp[NP], g[NZ], dl[NZ], ptip[3], Jp[3][NZ];
+    const T c0 = local_normal_eq<NS, T, T, TS>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
+    if (!tfinite(c0)) {
+      failed = true;
+      break;
+    }
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      const T hj = Hp[tri(j, j)];
+      Hp[tri(j, j)] = hj + lam * (hj > T(1e-12) ? hj : T(1e-12));
+      dl[j] = -g[j];
+    }
+    if (!chol_solve<NZ>(Hp, dl)) {
+      lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
+      continue;
+    }
+    T gd = T(0);
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) gd += g[j] * dl[j];
+    T alpha = T(1);
+    int acc = -1;
+    T zt[NZ];
+    for (int tr = 0; tr < o.ls_max; ++tr) {
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
+      const T c = cfg_cost<NS, T, TS>(rb, w, Tt, zt, sph, M, ms, cs);
+      ++trials;
+      if (c <= c0 + T(1e-4) * alpha * gd) {
+        acc = tr;
+        break;
+      }
+      alpha *= T(0.5);
+    }
+    if (acc >= 0) {
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) z[j] = zt[j];
+      if (acc == 0) lam = lam / T(10) > o.lam_min ? lam / T(10) : o.lam_min;
+    } else {
+      lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
+    }
+  }
 }
 
 }  // namespace crk

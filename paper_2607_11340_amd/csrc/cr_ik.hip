@@ -52,6 +52,57 @@ __global__ void __launch_bounds__(256)
   trials_out[b] = trials;
 }
 
+// Spheres of a solve: sph[c * ld + m] (double), problem p owns columns
+// p * M .. p * M + M - 1 when per_problem.
+struct SphArgs {
+  const double* sph;
+  int64_t ld;
+  int M, per_problem;
+};
+
+// Stage 1 with clearance rows (eq. 10): one lane per seed as k_ik_stage1, the
+// generic per-configuration normal equations; spheres read from HBM (every lane
+// of a wave reads the same sphere: one broadcast load).
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_ik_stage1_sph(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
+                    const double* __restrict__ useed, int iters, T lam0, SphArgs sa, T* __restrict__ z_out,
+                    T* __restrict__ e_out, T* __restrict__ pen_out, T* __restrict__ cost_out,
+                    int32_t* __restrict__ failed_out, int32_t* __restrict__ trials_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t B = P * (int64_t)S;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int64_t p = b / S;
+  const double* sp = sa.sph + (sa.per_problem ? p * sa.M : 0);
+  T tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = (T)Tt[c * P + p];
+  T z[NZ];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    u_to_ab((T)useed[(3 * i) * B + b], (T)useed[(3 * i + 1) * B + b], (T)useed[(3 * i + 2) * B + b], rb.r[i],
+            &z[2 * i], &z[2 * i + 1]);
+  T lam = lam0;
+  bool failed = false;
+  int trials = 0;
+  lm_cfg<NS, T, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+  T e;
+  ik_cost<NS>(rb, w, tt, z, &e);
+  const T c = cfg_cost<NS, T, double>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+  WeightsT<T> wc = w;  // clearance part alone (SelectTop tie-break)
+  wc.w_pos = wc.w_rot = wc.sq_lim = wc.sq_curv = T(0);
+  const T pen = cfg_cost<NS, T, double>(rb, wc, tt, z, sp, sa.M, 1, sa.ld);
+  if (!tfinite(c) || !tfinite(e)) failed = true;
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
+  e_out[b] = e;
+  pen_out[b] = pen;
+  cost_out[b] = c;
+  failed_out[b] = failed ? 1 : 0;
+  trials_out[b] = trials;
+}
+
 // ---------------------------------------------------------------------------
 // SelectTop.  Keys (flag, e, index) are sorted ascending in LDS by a bitonic
 // network (flag 0 = valid, 1 = failed, 2 = padding); all keys are distinct, so
@@ -152,11 +203,11 @@ __global__ void __launch_bounds__(256)
 // Stage 2: FP64 refinement of the kept candidates, lambda restarted at lambda0.
 // ---------------------------------------------------------------------------
 
-template <int NS, typename T1>
+template <int NS, typename T1, bool SPH>
 __global__ void __launch_bounds__(256)
     k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
                 const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
-                int iters, double lam0, double* __restrict__ z2, double* __restrict__ cost2,
+                int iters, double lam0, SphArgs sa, double* __restrict__ z2, double* __restrict__ cost2,
                 int32_t* __restrict__ failed2) {
   constexpr int NZ = 2 * NS;
   const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
@@ -181,13 +232,60 @@ __global__ void __launch_bounds__(256)
   double lam = lam0;
   bool failed = false;
   int trials = 0;
-  lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
-  double c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
+  double c;
+  if (SPH) {
+    const double* sp = sa.sph + (sa.per_problem ? p * sa.M : 0);
+    lm_cfg<NS, double, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+    c = cfg_cost<NS, double, double>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+  } else {
+    lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+    c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
+  }
   if (!tfinite(c)) failed = true;
 #pragma unroll
   for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
   cost2[b] = c;
   failed2[b] = failed ? 1 : 0;
+}
+
+// True if some backbone point of z (FP64) lies inside an obstacle sphere
+// inflated by its segment's radius (clearance < 0, margin 0).  A sphere whose
+// distance to a segment's arc midpoint exceeds L_i / 2 + R + r_i cannot touch it.
+template <int NS>
+__device__ bool penetrates(const RobotT<double>& rb, const double* z, const double* sph, int M, int64_t ld) {
+  double Rp[9], pp[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  pp[0] = pp[1] = pp[2] = 0.0;
+  bool hit = false;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const double a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
+    double xm[3];
+    seg_point(Rp, pp, a, b, rb.Ld[i], s, 0.5, xm);
+    for (int m = 0; m < M && !hit; ++m) {
+      const double cx = sph[m], cy = sph[ld + m], cz = sph[2 * ld + m], rs = sph[3 * ld + m];
+      const double e0 = xm[0] - cx, e1 = xm[1] - cy, e2 = xm[2] - cz;
+      if (sqrt(e0 * e0 + e1 * e1 + e2 * e2) - rs - rb.rd[i] - 0.5 * rb.Ld[i] > 0.0) continue;
+      for (int k = 1; k <= rb.K; ++k) {
+        double x[3];
+        seg_point(Rp, pp, a, b, rb.Ld[i], s, (double)k / (double)rb.K, x);
+        const double d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+        if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - rb.rd[i] < 0.0) hit = true;
+      }
+    }
+    ArcCoef<double> c = arc_coef<double, false>(s);
+    double Ri[9], di[3], q[3], Rn[9];
+    seg_R_d(a, b, rb.Ld[i], c, Ri, di);
+    mv3(Rp, di, q);
+    pp[0] += q[0];
+    pp[1] += q[1];
+    pp[2] += q[2];
+    mm3(Rp, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rp[k] = Rn[k];
+  }
+  return hit;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +298,7 @@ template <int NS, typename TC>
 __global__ void __launch_bounds__(256)
     k_ik_finalize(RobotT<double> rb, int64_t P, int nc, const int32_t* __restrict__ sel,
                   const TC* __restrict__ zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
-                  const double* __restrict__ Tt, double* __restrict__ u_out, double* __restrict__ err_out,
+                  const double* __restrict__ Tt, SphArgs sa, double* __restrict__ u_out, double* __restrict__ err_out,
                   int32_t* __restrict__ status_out) {
   constexpr int NZ = 2 * NS;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,6 +353,7 @@ __global__ void __launch_bounds__(256)
   }
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
+  if (sa.M > 0 && penetrates<NS>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld)) st |= CR_COLLISION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
   if (st == 0) st = CR_SOLVED;
   err_out[p] = pos;
@@ -298,18 +397,26 @@ size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_op
 static int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 template <int NS, typename T>
-static cr_status run_ik(const cr_robot& rb0, int64_t P, const double* Tt, int32_t S, const double* useed,
-                        const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
-                        const IkWorkspace& ws, hipStream_t st) {
+static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, const double* Tt, int32_t S,
+                        const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
+                        int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
+  const SphArgs sa{sp ? (const double*)sp->sph : nullptr, sp ? sp->ld : 0, sp ? sp->n_sph : 0,
+                   sp ? sp->per_problem : 0};
   RobotT<T> rb = robot_to<T>(rb0);
   WeightsT<T> w = weights_to<T>(w0);
   LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
   const int64_t B = P * (int64_t)S;
   const bool timed = timer_on();
   if (timed) timer_begin_call(st);
-  hipLaunchKernelGGL((k_ik_stage1<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S, Tt,
-                     useed, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1,
-                     ws.trials1);
+  if (sa.M > 0) {
+    hipLaunchKernelGGL((k_ik_stage1_sph<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
+                       Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
+                       ws.failed1, ws.trials1);
+  } else {
+    hipLaunchKernelGGL((k_ik_stage1<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S, Tt,
+                       useed, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1,
+                       ws.trials1);
+  }
   cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1");
   if (rc != CR_OK) return rc;
   if (timed) timer_mark(0, st);
@@ -323,21 +430,26 @@ static cr_status run_ik(const cr_robot& rb0, int64_t P, const double* Tt, int32_
     WeightsT<double> wd = weights_to<double>(w0);
     LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
     const int64_t B2 = P * (int64_t)o.n_final;
-    hipLaunchKernelGGL((k_ik_stage2<NS, T>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, (int)S,
-                       (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, ws.z2, ws.cost2,
-                       ws.failed2);
+    if (sa.M > 0)
+      hipLaunchKernelGGL((k_ik_stage2<NS, T, true>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
+                         (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
+                         ws.cost2, ws.failed2);
+    else
+      hipLaunchKernelGGL((k_ik_stage2<NS, T, false>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
+                         (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
+                         ws.cost2, ws.failed2);
     rc = check_hip(hipGetLastError(), "k_ik_stage2");
     if (rc != CR_OK) return rc;
     if (timed) timer_mark(2, st);
     hipLaunchKernelGGL((k_ik_finalize<NS, double>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
-                       (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, u_out, err_out, status_out);
+                       (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, sa, u_out, err_out, status_out);
   } else {
     if (timed) {
       timer_mark(1, st);
       timer_mark(2, st);
     }
     hipLaunchKernelGGL((k_ik_finalize<NS, T>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
-                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, u_out,
+                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, sa, u_out,
                        err_out, status_out);
   }
   rc = check_hip(hipGetLastError(), "k_ik_finalize");
@@ -348,13 +460,13 @@ static cr_status run_ik(const cr_robot& rb0, int64_t P, const double* Tt, int32_
   return rc;
 }
 
-cr_status launch_solve_ik(const cr_robot& rb, int64_t P, const double* Tt, int32_t S, const double* useed,
-                          const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+cr_status launch_solve_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, const double* Tt, int32_t S,
+                          const double* useed, const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
                           int32_t* status_out, const IkWorkspace& ws, cr_dtype dtype, hipStream_t st) {
-#define CR_IK_CASE(N)                                                                                     \
-  case N:                                                                                                 \
-    return dtype == CR_F64 ? run_ik<N, double>(rb, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st) \
-                           : run_ik<N, float>(rb, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st);
+#define CR_IK_CASE(N)                                                                                            \
+  case N:                                                                                                        \
+    return dtype == CR_F64 ? run_ik<N, double>(rb, sp, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st) \
+                           : run_ik<N, float>(rb, sp, P, Tt, S, useed, w, o, u_out, err_out, status_out, ws, st);
   switch (rb.n_seg) {
     CR_IK_CASE(1)
     CR_IK_CASE(2)

@@ -35,9 +35,9 @@ struct IkWorkspace {
 size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_opts& o, cr_dtype dtype,
                            char* base, IkWorkspace* ws);
 
-cr_status launch_solve_ik(const cr_robot& rb, int64_t P, const double* Tt, int32_t S, const double* useed,
-                          const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
-                          int32_t* status_out, const IkWorkspace& ws, cr_dtype dtype, hipStream_t stream);
+cr_status launch_solve_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, const double* Tt, int32_t S,
+                          const double* useed, const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+                          int32_t* status_out, const IkWorkspace& ws, cr_dtype dtype, hipStream_t st);
 
 cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
                         const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out,

@@ -1,6 +1,6 @@
 """CPU checks of the C ABI: the library loads, exports every function that
 include/cr_solver.h declares, and rejects invalid arguments on the host before
-any device work (CR_EINVAL / CR_ENOMEM / CR_EUNSUPPORTED paths)."""
+any device work (CR_EINVAL / CR_ENOMEM paths)."""
 import ctypes as C
 import os
 import re
