@@ -118,21 +118,35 @@ __device__ __forceinline__ bool key_less(T ea, int fa, T eb, int fb) {
   return (fa & 0xffff) < (fb & 0xffff);
 }
 
-// Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zs_c].
+// Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zs_c] and
+// its keys sit at p * S + c; with rows != NULL problem p has its own candidate
+// count, key base and z layout (ragged batches, trajectories).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_select(int64_t P, int S, int Spad, int nz, const T* __restrict__ z, int64_t zs_m, int64_t zs_c,
+    k_select(int64_t P, int S0, int Spad0, int nz0, const T* __restrict__ z, int64_t zs_m, int64_t zs_c,
              const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final,
-             T dup_eps, int32_t* __restrict__ idx_out) {
+             T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
   extern __shared__ unsigned char smem[];
   T* se = reinterpret_cast<T*>(smem);
-  int* sf = reinterpret_cast<int*>(se + Spad);
-  unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad);
+  int* sf = reinterpret_cast<int*>(se + Spad0);
+  unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad0);
   const int64_t p = blockIdx.x;
+  int S = S0, nz = nz0, Spad = Spad0;
+  int64_t kb = p * S0, zb = p * S0 * zs_c, zc = zs_c;
+  if (rows) {
+    const SelRow r = rows[p];
+    S = r.S;
+    nz = r.nz;
+    kb = r.kbase;
+    zb = r.zbase;
+    zc = r.zsc;
+    Spad = 1;
+    while (Spad < S) Spad <<= 1;
+  }
   for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
     if (i < S) {
-      T ev = e[p * S + i];
-      int fl = (failed && failed[p * S + i]) || !tfinite(ev) ? 1 : 0;
+      T ev = e[kb + i];
+      int fl = (failed && failed[kb + i]) || !tfinite(ev) ? 1 : 0;
       se[i] = ev;
       sf[i] = (fl << 16) | i;
     } else {
@@ -173,14 +187,14 @@ __global__ void __launch_bounds__(256)
     for (int k = 0; k < nk && dup < 0; ++k) {
       T dmax = T(0);
       for (int m = 0; m < nz; ++m) {
-        T d = fabs(z[m * zs_m + (p * S + c) * zs_c] - z[m * zs_m + (p * S + kept[k]) * zs_c]);
+        T d = fabs(z[zb + m * zs_m + c * zc] - z[zb + m * zs_m + kept[k] * zc]);
         dmax = d > dmax ? d : dmax;
       }
       if (dmax <= dup_eps) dup = k;
     }
     if (dup < 0) {
       kept[nk++] = c;
-    } else if (pen[p * S + c] < pen[p * S + kept[dup]]) {
+    } else if (pen[kb + c] < pen[kb + kept[dup]]) {
       skipped[kept[dup]] = 1;
       kept[dup] = c;
     } else {
@@ -482,7 +496,7 @@ cr_status launch_solve_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, c
 
 cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
                                 const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
-                                int32_t* idx_out, cr_dtype dtype, hipStream_t st) {
+                                int32_t* idx_out, cr_dtype dtype, hipStream_t st, const SelRow* rows) {
   int Spad = 1;
   while (Spad < S) Spad <<= 1;
   const size_t tb = dtype == CR_F64 ? 8 : 4;
@@ -491,11 +505,11 @@ cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z,
   if (dtype == CR_F64)
     hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
                        (const double*)z, zs_m, zs_c, (const double*)e, (const double*)pen, failed, (int)n_final,
-                       dup_eps, idx_out);
+                       dup_eps, rows, idx_out);
   else
     hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
                        (const float*)z, zs_m, zs_c, (const float*)e, (const float*)pen, failed, (int)n_final,
-                       (float)dup_eps, idx_out);
+                       (float)dup_eps, rows, idx_out);
   return check_hip(hipGetLastError(), "k_select");
 }
 

@@ -8,6 +8,25 @@
 
 namespace crk {
 
+// Candidates of one SelectTop problem (ragged launches): S candidates with keys
+// at kbase + c, coordinate m of candidate c at z[zbase + m * zs_m + c * zsc].
+struct SelRow {
+  int32_t S, nz;
+  int64_t kbase, zbase, zsc;
+};
+
+// One row per problem of a path / trajectory launch (device memory).  Element
+// layouts: task row r, waypoint t at task + r * task_ld + t (PATH: 12 pose rows;
+// TRAJ: 6n rows of start then goal actuation, t = 0); seed row r, seed s,
+// waypoint t at seed + r * seed_ld + s * Tn + t; output row r, waypoint t at
+// out + r * out_ld + t; sphere m, component c at sph + c * sph_ld + m.
+struct TrajProb {
+  int32_t Tn, S, M, idx;    // waypoints, seeds, spheres, index of err / status
+  int64_t traj0, wp0, tn0;  // first stage-1 trajectory and waypoint configuration; waypoints of earlier problems
+  int64_t task, task_ld, seed, seed_ld, out, out_ld, sph, sph_ld;
+};
+
+
 // Records a message for cr_last_error() and returns the status.
 cr_status fail(cr_status s, const char* fmt, ...);
 cr_status check_hip(hipError_t e, const char* what);
@@ -45,8 +64,22 @@ cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const v
 
 cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
                                 const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
-                                int32_t* idx_out, cr_dtype dtype, hipStream_t st);
+                                int32_t* idx_out, cr_dtype dtype, hipStream_t st, const SelRow* rows = nullptr);
 
+// Totals of a path / trajectory launch: problems, stage-1 trajectories and
+// waypoint configurations, waypoints summed over problems, largest horizon + 1,
+// sphere count and seed count.
+struct TrajShape {
+  int64_t P, N1, W1, TnSum;
+  int Tmax, Mmax, Smax;
+};
+TrajShape traj_uniform_shape(int64_t P, int S, int H, int M);
+size_t traj_workspace_bytes(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dt);
+TrajProb* traj_table_slot(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dtype, void* wsmem);
+cr_status launch_traj_group(int kind, const cr_robot& rb, const TrajShape& sh, const TrajProb* tp, const double* task,
+                            const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
+                            double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
+                            cr_dtype dtype, hipStream_t st);
 size_t traj_workspace_bytes(const cr_robot& rb, int64_t P, int S, int H, const cr_opts& o, cr_dtype dt);
 cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
                             int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,

@@ -25,14 +25,44 @@ namespace crk {
 template <typename T>
 struct TrajArgs {
   int kind;                 // CR_KIND_PATH or CR_KIND_TRAJ
-  int H;                    // waypoints t = 0..H
-  int64_t P;                // problems
-  int per;                  // trajectories per problem in this launch
-  const double* task;       // PATH: poses [12][(H+1) P]; TRAJ: [6n][P]
-  const double* sph;        // spheres [4][sld] or NULL
-  int64_t sld;
-  int M, per_problem;
+  int64_t P;                // problems in the launch
+  int nf;                   // 0: stage 1, S of each problem's trajectories; > 0: nf per problem (stage 2)
+  int Tmax;                 // largest horizon + 1 of the launch
+  const TrajProb* tp;       // one row per problem
+  const double* task;       // PATH: reference poses; TRAJ: start and goal actuations (see TrajProb)
+  const double* sph;        // spheres (see TrajProb) or NULL
 };
+
+// What a workgroup (or lane group) needs of the trajectory it works on.
+struct TrajCtx {
+  TrajProb pr;
+  int64_t q;   // problem
+  int s;       // trajectory of the problem (seed, or stage-2 slot)
+  int64_t wp;  // first waypoint configuration of the trajectory in Z and the records
+};
+
+template <typename T>
+__device__ __forceinline__ TrajCtx traj_ctx(const TrajArgs<T>& ta, int64_t traj) {
+  TrajCtx cx;
+  if (ta.nf > 0) {
+    cx.q = traj / ta.nf;
+    cx.pr = ta.tp[cx.q];
+    cx.s = (int)(traj - cx.q * ta.nf);
+    cx.wp = ta.nf * cx.pr.tn0 + (int64_t)cx.s * cx.pr.Tn;
+  } else {
+    int64_t lo = 0, hi = ta.P - 1;  // last problem whose first trajectory is <= traj
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (ta.tp[mid].traj0 <= traj) lo = mid;
+      else hi = mid - 1;
+    }
+    cx.q = lo;
+    cx.pr = ta.tp[lo];
+    cx.s = (int)(traj - cx.pr.traj0);
+    cx.wp = cx.pr.wp0 + (int64_t)cx.s * cx.pr.Tn;
+  }
+  return cx;
+}
 
 // Per-waypoint record of the normal equations, every block column-major: element
 // (row i, column j) of a block sits at column j * NZ + i, so the NZ lanes that own
@@ -61,18 +91,26 @@ __device__ __forceinline__ T block_sum_all(T v, T* red) {
 }
 
 template <typename T>
-__device__ __forceinline__ void stage_spheres(const TrajArgs<T>& ta, int64_t p, T* s_sph) {
-  for (int i = threadIdx.x; i < 4 * ta.M; i += blockDim.x) {
+__device__ __forceinline__ void stage_spheres(const TrajArgs<T>& ta, const TrajCtx& cx, T* s_sph) {
+  for (int i = threadIdx.x; i < 4 * cx.pr.M; i += blockDim.x) {
     const int m = i >> 2, c = i & 3;
-    s_sph[i] = (T)ta.sph[c * ta.sld + (ta.per_problem ? p * ta.M : 0) + m];
+    s_sph[i] = (T)ta.sph[cx.pr.sph + c * cx.pr.sph_ld + m];
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void load_pose(const TrajArgs<T>& ta, int64_t p, int t, T* Tt) {
-  const int64_t Tn = ta.H + 1;
+__device__ __forceinline__ void load_pose(const TrajArgs<T>& ta, const TrajCtx& cx, int t, T* Tt) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) Tt[c] = (T)ta.task[c * (ta.P * Tn) + p * Tn + t];
+  for (int c = 0; c < 12; ++c) Tt[c] = (T)ta.task[cx.pr.task + c * cx.pr.task_ld + t];
+}
+
+// Bending coordinates of segment i of the start (end = 0) or goal (end = 1)
+// configuration of a trajectory problem.
+template <int NS, typename T, typename TR>
+__device__ __forceinline__ void load_end(const TrajArgs<T>& ta, const TrajCtx& cx, int end, int i, TR r, TR* za,
+                                         TR* zb) {
+  const double* u = ta.task + cx.pr.task + (int64_t)(end * 3 * NS + 3 * i) * cx.pr.task_ld;
+  u_to_ab((TR)u[0], (TR)u[cx.pr.task_ld], (TR)u[2 * cx.pr.task_ld], r, za, zb);
 }
 
 // Work list of the clearance term of one trajectory.  Every waypoint lane stores
@@ -265,17 +303,18 @@ __device__ __forceinline__ T coll_drain(const RobotT<T>& rb, const WeightsT<T>& 
 // returned (every other weight zeroed).  s_u, s_p: LDS scratch of (H+1)*3n and
 // (H+1)*3 values.
 template <int NS, typename T>
-__device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int64_t p, const T* z,
-                       const T* s_sph, T* s_u, T* s_p, T* s_red, T* pen, const CollList<T>& cl) {
+__device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta,
+                                       const TrajCtx& cx, const T* z, const T* s_sph, T* s_u, T* s_p, T* s_red, T* pen,
+                                       const CollList<T>& cl) {
   constexpr int NU = 3 * NS;
-  const int t = threadIdx.x, H = ta.H;
+  const int t = threadIdx.x, H = cx.pr.Tn - 1, M = cx.pr.M;
   const bool act = t <= H;
-  const bool listed = cl.cap > 0 && ta.M > 0;
+  const bool listed = cl.cap > 0 && M > 0;
   T cst = T(0), cpen = T(0);
   if (listed) {
     if (act) coll_frames<NS>(rb, z, t, cl);
     __syncthreads();
-    cpen = coll_enqueue<NS>(rb, w, s_sph, ta.M, H + 1, cl);
+    cpen = coll_enqueue<NS>(rb, w, s_sph, M, H + 1, cl);
     cst = cpen;
   }
   if (act) {
@@ -283,17 +322,17 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
     if (listed) {
       cst += config_forward<NS, T, false>(rb, w, z, s_sph, 0, 4, 1, f);
     } else {
-      cst = config_forward<NS, T, false>(rb, w, z, s_sph, ta.M, 4, 1, f);
-      if (pen && ta.M > 0) {
+      cst = config_forward<NS, T, false>(rb, w, z, s_sph, M, 4, 1, f);
+      if (pen && M > 0) {
         WeightsT<T> wc = w;
         wc.sq_lim = wc.sq_curv = T(0);
         Fwd<NS, T> f2;
-        cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, ta.M, 4, 1, f2);
+        cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, M, 4, 1, f2);
       }
     }
     if (ta.kind == CR_KIND_PATH) {
       T Tt[12], ft[3], tq[3];
-      load_pose(ta, p, t, Tt);
+      load_pose(ta, cx, t, Tt);
       cst += pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
     }
 #pragma unroll
@@ -345,12 +384,10 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
         }
       }
       if (t == 0 || t == H) {
-        const int off = t == 0 ? 0 : NU;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           T za, zb;
-          u_to_ab((T)ta.task[(off + 3 * i) * ta.P + p], (T)ta.task[(off + 3 * i + 1) * ta.P + p],
-                  (T)ta.task[(off + 3 * i + 2) * ta.P + p], rb.r[i], &za, &zb);
+          load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.r[i], &za, &zb);
           const T ra = w.sq_eq * (z[2 * i] - za), rb2 = w.sq_eq * (z[2 * i + 1] - zb);
           cst += T(0.5) * (ra * ra + rb2 * rb2);
         }
@@ -364,18 +401,21 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
 
 // ---------------------------------------------------------------------------
 
+// Stage-1 state from the seeds: one workgroup per trajectory, lane t = waypoint.
 template <int NS, typename T>
 __global__ void __launch_bounds__(256)
-    k_traj_init(int64_t nt, int Tn, const double* __restrict__ useed, const double* __restrict__ rr, T* __restrict__ Z) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t B = nt * Tn;
-  if (i >= B) return;
+    k_traj_init(RobotT<double> rbd, TrajArgs<T> ta, const double* __restrict__ useed, T* __restrict__ Z) {
+  const TrajCtx cx = traj_ctx(ta, blockIdx.x);
+  for (int t = threadIdx.x; t < cx.pr.Tn; t += blockDim.x) {
+    const double* u = useed + cx.pr.seed + (int64_t)cx.s * cx.pr.Tn + t;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    double a, b;
-    u_to_ab(useed[(3 * s) * B + i], useed[(3 * s + 1) * B + i], useed[(3 * s + 2) * B + i], rr[s], &a, &b);
-    Z[i * 2 * NS + 2 * s] = (T)a;
-    Z[i * 2 * NS + 2 * s + 1] = (T)b;
+    for (int i = 0; i < NS; ++i) {
+      double a, b;
+      u_to_ab(u[(3 * i) * cx.pr.seed_ld], u[(3 * i + 1) * cx.pr.seed_ld], u[(3 * i + 2) * cx.pr.seed_ld], rbd.rd[i], &a,
+              &b);
+      Z[(cx.wp + t) * 2 * NS + 2 * i] = (T)a;
+      Z[(cx.wp + t) * 2 * NS + 2 * i + 1] = (T)b;
+    }
   }
 }
 
@@ -386,16 +426,16 @@ __global__ void __launch_bounds__(256)
   constexpr int NZ = 2 * NS, NU = 3 * NS, NP = NZ * (NZ + 1) / 2;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int H = ta.H, Tn = H + 1;
+  const int64_t traj = blockIdx.x;
+  if (failed[traj]) return;  // uniform per workgroup
+  const TrajCtx cx = traj_ctx(ta, traj);
+  const int Tn = cx.pr.Tn, H = Tn - 1, M = cx.pr.M;
   T* s_sph = reinterpret_cast<T*>(smem_raw);
-  T* s_u = s_sph + 4 * ta.M;
+  T* s_u = s_sph + 4 * M;
   T* s_p = s_u + Tn * NU;
   T* s_jp = s_p + Tn * 3;
   T* s_red = s_jp + Tn * 3 * NZ;
-  const int64_t traj = blockIdx.x;
-  const int64_t p = traj / ta.per;
-  if (failed[traj]) return;  // uniform per workgroup
-  stage_spheres(ta, p, s_sph);
+  stage_spheres(ta, cx, s_sph);
   __syncthreads();
   const int t = threadIdx.x;
   const bool act = t < Tn;
@@ -403,11 +443,11 @@ __global__ void __launch_bounds__(256)
   T cst = T(0);
   if (act) {
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) z[k] = Z[(traj * Tn + t) * NZ + k];
+    for (int k = 0; k < NZ; ++k) z[k] = Z[(cx.wp + t) * NZ + k];
     T Tt[12];
-    if (ta.kind == CR_KIND_PATH) load_pose(ta, p, t, Tt);
+    if (ta.kind == CR_KIND_PATH) load_pose(ta, cx, t, Tt);
     const T* tp = ta.kind == CR_KIND_PATH ? Tt : nullptr;
-    cst = local_normal_eq<NS, T, T>(rb, w, z, s_sph, ta.M, 4, 1, tp, Hp, g, ptip, Jp);
+    cst = local_normal_eq<NS, T, T>(rb, w, z, s_sph, M, 4, 1, tp, Hp, g, ptip, Jp);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T u[3];
@@ -529,13 +569,11 @@ __global__ void __launch_bounds__(256)
       }
       // endpoint equalities, penalised (eq. 17)
       if (t == 0 || t == H) {
-        const int off = t == 0 ? 0 : NU;
         const T se2 = w.sq_eq * w.sq_eq;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           T za, zb;
-          u_to_ab((T)ta.task[(off + 3 * i) * ta.P + p], (T)ta.task[(off + 3 * i + 1) * ta.P + p],
-                  (T)ta.task[(off + 3 * i + 2) * ta.P + p], rb.r[i], &za, &zb);
+          load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.r[i], &za, &zb);
           const T ra = w.sq_eq * (z[2 * i] - za), rb2 = w.sq_eq * (z[2 * i + 1] - zb);
           cst += T(0.5) * (ra * ra + rb2 * rb2);
           g[2 * i] += w.sq_eq * ra;
@@ -545,7 +583,7 @@ __global__ void __launch_bounds__(256)
         }
       }
     }
-    T* rec = blk + (traj * Tn + t) * R::SIZE;
+    T* rec = blk + (cx.wp + t) * R::SIZE;
 #pragma unroll
     for (int b = 0; b < NZ; ++b)
 #pragma unroll
@@ -572,7 +610,7 @@ __global__ void __launch_bounds__(256)
 // the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
 template <int NS, typename T>
 __global__ void __launch_bounds__(64)
-    k_traj_solve(int64_t nt, int H, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
+    k_traj_solve(TrajArgs<T> ta, int64_t nt, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
                  int32_t* __restrict__ chol_ok, T* __restrict__ gd_out) {
   constexpr int NZ = 2 * NS, G = 64 / NZ;
   constexpr int RS = NZ + (NZ & 1);  // LDS row stride
@@ -588,24 +626,33 @@ __global__ void __launch_bounds__(64)
   const int g = inw ? lane / NZ : 0, a = inw ? lane - g * NZ : 0, base = g * NZ;
   const int64_t traj = (int64_t)blockIdx.x * G + g;
   const bool act = inw && traj < nt && !failed[traj];
-  const int Tn = H + 1;
+  int Tn = 0;
+  int64_t wp = 0;
+  if (act) {
+    const TrajCtx cx = traj_ctx(ta, traj);
+    Tn = cx.pr.Tn;
+    wp = cx.wp;
+  }
   const T lm = act ? lam[traj] : T(0);
-  T* const recs = blk + (act ? traj : 0) * (int64_t)Tn * R::SIZE;
+  T* const recs = blk + wp * R::SIZE;
   bool ok = true;
-  for (int t = 0; t < Tn; ++t) {
+  // every lane runs the longest horizon of the launch (workgroup-uniform barriers);
+  // a trajectory's lanes work only while t < its own horizon
+  for (int t = 0; t < ta.Tmax; ++t) {
+    const bool on = act && t < Tn;
     T* rec = recs + (int64_t)t * R::SIZE;
     const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
     const int b0 = t & 1, b1 = b0 ^ 1;
     T S[NZ];
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) S[b] = act ? rec[R::OH + b * NZ + a] : T(b == a);
+    for (int b = 0; b < NZ; ++b) S[b] = on ? rec[R::OH + b * NZ + a] : T(b == a);
 #pragma unroll
     for (int b = 0; b < NZ; ++b)
       if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
-    T y = act ? -rec[R::OG + a] : T(0);
+    T y = on ? -rec[R::OG + a] : T(0);
     T Bw[NZ];
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) Bw[b] = (act && t >= 1) ? rec[R::OB + b * NZ + a] : T(0);
+    for (int b = 0; b < NZ; ++b) Bw[b] = (on && t >= 1) ? rec[R::OB + b * NZ + a] : T(0);
     if (t >= 2) {
       // row a of L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T (forward substitution)
       const T* L2 = &sL[s2][g * GS];
@@ -613,7 +660,7 @@ __global__ void __launch_bounds__(64)
       T x[NZ];
 #pragma unroll
       for (int i = 0; i < NZ; ++i) {
-        T v = act ? rec[R::OC + i * NZ + a] : T(0);
+        T v = on ? rec[R::OC + i * NZ + a] : T(0);
 #pragma unroll
         for (int j = 0; j < i; ++j) v -= L2[i * RS + j] * x[j];
         x[i] = v * D2[i];
@@ -623,7 +670,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
       for (int i = 0; i < NZ; ++i) {
         y -= x[i] * Y2[i];
-        if (act) rec[R::OC + i * NZ + a] = x[i];
+        if (on) rec[R::OC + i * NZ + a] = x[i];
       }
       // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T
 #pragma unroll
@@ -664,7 +711,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
       for (int i = 0; i < NZ; ++i) {
         y -= x[i] * Y1[i];
-        if (act) rec[R::OB + i * NZ + a] = x[i];
+        if (on) rec[R::OB + i * NZ + a] = x[i];
       }
       if (inw) {
 #pragma unroll
@@ -693,7 +740,7 @@ __global__ void __launch_bounds__(64)
         T dd = S[j];
 #pragma unroll
         for (int k = 0; k < j; ++k) dd -= S[k] * S[k];
-        ok = ok && (dd > T(0));
+        ok = ok && (!on || dd > T(0));
         const T ljj = tsqrt(dd > T(0) ? dd : T(1));
         S[j] = ljj;
         y = y / ljj;
@@ -713,7 +760,7 @@ __global__ void __launch_bounds__(64)
         y -= S[j] * Yt[j];
       }
     }
-    if (act) {
+    if (on) {
 #pragma unroll
       for (int b = 0; b < NZ; ++b) rec[R::OH + b * NZ + a] = b <= a ? S[b] : T(0);
       rec[R::OY + a] = y;
@@ -722,26 +769,27 @@ __global__ void __launch_bounds__(64)
   }
   // backward: delta_t = L_tt^-T (y_t - L_{t+1,t}^T delta_{t+1} - L_{t+2,t}^T delta_{t+2})
   T gd = T(0);
-  for (int t = Tn - 1; t >= 0; --t) {
+  for (int t = ta.Tmax - 1; t >= 0; --t) {
+    const bool on = act && t < Tn;
     T* rec = recs + (int64_t)t * R::SIZE;
     const int s0 = t % 3, s1 = (t + 1) % 3, s2 = (t + 2) % 3;  // slots of t, t+1, t+2
-    T r = act ? rec[R::OY + a] : T(0);
+    T r = on ? rec[R::OY + a] : T(0);
     if (t + 1 < Tn) {
       const T* q = rec + R::SIZE;
       const T* d1 = &sY[s1][g * RS];
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= (act ? q[R::OB + a * NZ + b] : T(0)) * d1[b];
+      for (int b = 0; b < NZ; ++b) r -= (on ? q[R::OB + a * NZ + b] : T(0)) * d1[b];
     }
     if (t + 2 < Tn) {
       const T* q = rec + 2 * R::SIZE;
       const T* d2 = &sY[s2][g * RS];
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= (act ? q[R::OC + a * NZ + b] : T(0)) * d2[b];
+      for (int b = 0; b < NZ; ++b) r -= (on ? q[R::OC + a * NZ + b] : T(0)) * d2[b];
     }
     // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
     T Lc[NZ];
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) Lc[k] = act ? rec[R::OH + a * NZ + k] : T(k == a);
+    for (int k = 0; k < NZ; ++k) Lc[k] = on ? rec[R::OH + a * NZ + k] : T(k == a);
     T d = T(0);
 #pragma unroll
     for (int k = NZ - 1; k >= 0; --k) {
@@ -755,7 +803,7 @@ __global__ void __launch_bounds__(64)
     }
     __syncthreads();
     if (inw) sY[s0][g * RS + a] = d;
-    if (act) {
+    if (on) {
       rec[R::OY + a] = d;
       gd += rec[R::OG + a] * d;
     }
@@ -784,28 +832,28 @@ __global__ void __launch_bounds__(256)
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int H = ta.H, Tn = H + 1;
-  T* s_sph = reinterpret_cast<T*>(smem_raw);
-  T* s_u = s_sph + 4 * ta.M;
-  T* s_p = s_u + Tn * NU;
-  T* s_red = s_p + Tn * 3;
-  const CollList<T> cl = coll_list<NS>(s_red + 8, Tn, list_cap);
   const int64_t traj = blockIdx.x;
-  const int64_t p = traj / ta.per;
   if (failed[traj]) return;
   if (!chol_ok[traj]) {
     if (threadIdx.x == 0) lam[traj] = lam[traj] * T(10) < o.lam_max ? lam[traj] * T(10) : o.lam_max;
     return;
   }
-  stage_spheres(ta, p, s_sph);
+  const TrajCtx cx = traj_ctx(ta, traj);
+  const int Tn = cx.pr.Tn;
+  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_u = s_sph + 4 * cx.pr.M;
+  T* s_p = s_u + Tn * NU;
+  T* s_red = s_p + Tn * 3;
+  const CollList<T> cl = coll_list<NS>(s_red + 8, Tn, list_cap);
+  stage_spheres(ta, cx, s_sph);
   const int t = threadIdx.x;
   const bool act = t < Tn;
   T z[NZ], dl[NZ], zt[NZ];
   if (act) {
 #pragma unroll
     for (int k = 0; k < NZ; ++k) {
-      z[k] = Z[(traj * Tn + t) * NZ + k];
-      dl[k] = blk[(traj * Tn + t) * R::SIZE + R::OY + k];
+      z[k] = Z[(cx.wp + t) * NZ + k];
+      dl[k] = blk[(cx.wp + t) * R::SIZE + R::OY + k];
     }
   }
   __syncthreads();
@@ -815,7 +863,7 @@ __global__ void __launch_bounds__(256)
   for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
     for (int k = 0; k < NZ; ++k) zt[k] = act ? z[k] + alpha * dl[k] : T(0);
-    const T c = traj_cost<NS>(rb, w, ta, p, zt, s_sph, s_u, s_p, s_red, (T*)nullptr, cl);
+    const T c = traj_cost<NS>(rb, w, ta, cx, zt, s_sph, s_u, s_p, s_red, (T*)nullptr, cl);
     ++ntr;
     if (c <= c0 + T(1e-4) * alpha * gd) {
       acc = tr;
@@ -825,7 +873,7 @@ __global__ void __launch_bounds__(256)
   }
   if (acc >= 0 && act) {
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) Z[(traj * Tn + t) * NZ + k] = zt[k];
+    for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zt[k];
   }
   if (threadIdx.x == 0) {
     T l = lam[traj];
@@ -843,22 +891,22 @@ __global__ void __launch_bounds__(256)
                 T* __restrict__ pen, int32_t* __restrict__ failed, int list_cap) {
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int H = ta.H, Tn = H + 1;
+  const int64_t traj = blockIdx.x;
+  const TrajCtx cx = traj_ctx(ta, traj);
+  const int Tn = cx.pr.Tn;
   T* s_sph = reinterpret_cast<T*>(smem_raw);
-  T* s_u = s_sph + 4 * ta.M;
+  T* s_u = s_sph + 4 * cx.pr.M;
   T* s_p = s_u + Tn * NU;
   T* s_red = s_p + Tn * 3;
   const CollList<T> cl = coll_list<NS>(s_red + 8, Tn, list_cap);
-  const int64_t traj = blockIdx.x;
-  const int64_t p = traj / ta.per;
-  stage_spheres(ta, p, s_sph);
+  stage_spheres(ta, cx, s_sph);
   const int t = threadIdx.x;
   T z[NZ];
 #pragma unroll
-  for (int k = 0; k < NZ; ++k) z[k] = t < Tn ? Z[(traj * Tn + t) * NZ + k] : T(0);
+  for (int k = 0; k < NZ; ++k) z[k] = t < Tn ? Z[(cx.wp + t) * NZ + k] : T(0);
   __syncthreads();
   T pn;
-  const T c = traj_cost<NS>(rb, w, ta, p, z, s_sph, s_u, s_p, s_red, &pn, cl);
+  const T c = traj_cost<NS>(rb, w, ta, cx, z, s_sph, s_u, s_p, s_red, &pn, cl);
   if (threadIdx.x == 0) {
     cost[traj] = c;
     pen[traj] = pn;
@@ -866,23 +914,19 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Stage-2 candidates: copy the selected stage-1 trajectories (FP64 state).
+// Stage-2 candidates: copy the selected stage-1 trajectories (FP64 state); one
+// workgroup per stage-2 slot (problem q, slot k).
 template <int NS, typename T1>
-__global__ void __launch_bounds__(256)
-    k_traj_gather(int64_t P, int S, int nf, int Tn, const T1* __restrict__ Z1, const int32_t* __restrict__ sel,
+__global__ void __launch_bounds__(64)
+    k_traj_gather(TrajArgs<double> ta2, const T1* __restrict__ Z1, const int32_t* __restrict__ sel,
                   double* __restrict__ Z2, int32_t* __restrict__ failed2) {
   constexpr int NZ = 2 * NS;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P * nf * Tn) return;
-  const int64_t traj2 = i / Tn;
-  const int t = (int)(i % Tn);
-  const int64_t p = traj2 / nf;
-  const int k = (int)(traj2 % nf);
-  const int s = sel[k * P + p];
-  if (t == 0) failed2[traj2] = s < 0 ? 1 : 0;
-  const int64_t src = (p * S + (s < 0 ? 0 : s)) * Tn + t;
-#pragma unroll
-  for (int m = 0; m < NZ; ++m) Z2[(traj2 * Tn + t) * NZ + m] = (double)Z1[src * NZ + m];
+  const int64_t traj2 = blockIdx.x;
+  const TrajCtx cx = traj_ctx(ta2, traj2);
+  const int s = sel[(int64_t)cx.s * ta2.P + cx.q];
+  if (threadIdx.x == 0) failed2[traj2] = s < 0 ? 1 : 0;
+  const int64_t src = cx.pr.wp0 + (int64_t)(s < 0 ? 0 : s) * cx.pr.Tn;
+  for (int i = threadIdx.x; i < cx.pr.Tn * NZ; i += blockDim.x) Z2[cx.wp * NZ + i] = (double)Z1[src * NZ + i];
 }
 
 template <typename T>
@@ -911,21 +955,30 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
 // workgroup per problem, one lane per waypoint.
 template <int NS, typename TC>
 __global__ void __launch_bounds__(256)
-    k_traj_finalize(RobotT<double> rb, TrajArgs<double> ta, int nc, const int32_t* __restrict__ sel,
+    k_traj_finalize(RobotT<double> rb, TrajArgs<double> ta, int nf, const int32_t* __restrict__ sel,
                     const TC* __restrict__ Zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
-                    double* __restrict__ u_out, double* __restrict__ err_out, int32_t* __restrict__ status_out) {
+                    int64_t err_ld, double* __restrict__ u_out, double* __restrict__ err_out,
+                    int32_t* __restrict__ status_out) {
   constexpr int NZ = 2 * NS;
   __shared__ double red[4];
   __shared__ int s_best;
   const int64_t p = blockIdx.x;
   const int64_t P = ta.P;
-  const int Tn = ta.H + 1;
+  TrajCtx cx;
+  cx.q = p;
+  cx.pr = ta.tp[p];
+  cx.s = 0;
+  cx.wp = 0;
+  const int Tn = cx.pr.Tn;
+  const int nc = nf > 0 ? nf : cx.pr.S;
+  const int64_t c0 = nf > 0 ? p * nf : cx.pr.traj0;                  // first candidate's cost index
+  const int64_t w0 = nf > 0 ? nf * cx.pr.tn0 : cx.pr.wp0;            // first candidate's waypoint configuration
   const int t = threadIdx.x;
   if (t == 0) {
     int best = -1, best_seed = 0;
     double best_cost = 0.0;
     for (int k = 0; k < nc; ++k) {
-      const int64_t tr = p * nc + k;
+      const int64_t tr = c0 + k;
       const int seed = sel ? sel[k * P + p] : k;
       const double c = (double)costc[tr];
       if (seed < 0 || failedc[tr] || !tfinite(c)) continue;
@@ -939,35 +992,33 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   const int best = s_best;
-  const int64_t BU = P * Tn;
+  double* const uo = u_out + cx.pr.out;
+  const int64_t uld = cx.pr.out_ld, ei = cx.pr.idx;
   if (best < 0) {
     const double nan = __builtin_nan("");
-    for (int m = 0; m < 3 * NS && t < Tn; ++m) u_out[m * BU + p * Tn + t] = nan;
+    for (int m = 0; m < 3 * NS && t < Tn; ++m) uo[m * uld + t] = nan;
     if (t == 0) {
-      err_out[p] = err_out[P + p] = nan;
-      status_out[p] = CR_NONFINITE;
+      err_out[ei] = err_out[err_ld + ei] = nan;
+      status_out[ei] = CR_NONFINITE;
     }
     return;
   }
-  const int64_t tr = p * nc + best;
+  const int64_t wb = w0 + (int64_t)best * Tn;
   double pos = 0.0, rot = 0.0, viol = 0.0, thx = 0.0, gmin = DBL_MAX;
   if (t < Tn) {
     double z[NZ];
 #pragma unroll
-    for (int m = 0; m < NZ; ++m) z[m] = (double)Zc[(tr * Tn + t) * NZ + m];
+    for (int m = 0; m < NZ; ++m) z[m] = (double)Zc[(wb + t) * NZ + m];
     const bool check = ta.kind == CR_KIND_PATH || t == 0 || t == Tn - 1;
     if (check) {
       double Rc[9], pc[3], tt[12];
       fk_tip<NS>(rb, z, Rc, pc);
       if (ta.kind == CR_KIND_PATH) {
-        load_pose(ta, p, t, tt);
+        load_pose(ta, cx, t, tt);
       } else {
-        const int off = t == 0 ? 0 : 3 * NS;
         double ze[NZ];
 #pragma unroll
-        for (int i = 0; i < NS; ++i)
-          u_to_ab(ta.task[(off + 3 * i) * P + p], ta.task[(off + 3 * i + 1) * P + p], ta.task[(off + 3 * i + 2) * P + p],
-                  rb.rd[i], &ze[2 * i], &ze[2 * i + 1]);
+        for (int i = 0; i < NS; ++i) load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.rd[i], &ze[2 * i], &ze[2 * i + 1]);
         double Re2[9], pe2[3];
         fk_tip<NS>(rb, ze, Re2, pe2);
         for (int r = 0; r < 3; ++r) {
@@ -993,27 +1044,27 @@ __global__ void __launch_bounds__(256)
       ab_to_u(z[2 * i], z[2 * i + 1], rb.rd[i], u);
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        u_out[(3 * i + j) * BU + p * Tn + t] = u[j];
+        uo[(3 * i + j) * uld + t] = u[j];
         viol = fmax(viol, fabs(u[j]) - rb.umaxd[i]);
       }
       const double s = z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1];
       thx = fmax(thx, sqrt(s) - rb.theta_maxd);
-      if (ta.M > 0) {
+      if (cx.pr.M > 0) {
         // every point of the segment lies within L_i / 2 of its arc midpoint; only
         // the sign of the smallest clearance is reported, so spheres that cannot
         // reach the segment are skipped
         double xm[3];
         seg_point(Rp, pp, z[2 * i], z[2 * i + 1], rb.Ld[i], s, 0.5, xm);
-        for (int m = 0; m < ta.M; ++m) {
-          const int64_t col = (ta.per_problem ? p * ta.M : 0) + m;
-          const double cx = ta.sph[col], cy = ta.sph[ta.sld + col], cz = ta.sph[2 * ta.sld + col];
-          const double rs = ta.sph[3 * ta.sld + col];
-          const double e0 = xm[0] - cx, e1 = xm[1] - cy, e2 = xm[2] - cz;
+        const double* sp = ta.sph + cx.pr.sph;
+        const int64_t sld = cx.pr.sph_ld;
+        for (int m = 0; m < cx.pr.M; ++m) {
+          const double sx = sp[m], sy = sp[sld + m], sz = sp[2 * sld + m], rs = sp[3 * sld + m];
+          const double e0 = xm[0] - sx, e1 = xm[1] - sy, e2 = xm[2] - sz;
           if (sqrt(e0 * e0 + e1 * e1 + e2 * e2) - rs - rb.rd[i] - 0.5 * rb.Ld[i] > 0.0) continue;
           for (int k = 1; k <= rb.K; ++k) {
             double x[3];
             seg_point(Rp, pp, z[2 * i], z[2 * i + 1], rb.Ld[i], s, (double)k / (double)rb.K, x);
-            const double d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+            const double d0 = x[0] - sx, d1 = x[1] - sy, d2 = x[2] - sz;
             gmin = fmin(gmin, sqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - rb.rd[i]);
           }
         }
@@ -1041,9 +1092,9 @@ __global__ void __launch_bounds__(256)
     if (gmin < 0.0) st |= CR_COLLISION;
     if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
     if (st == 0) st = CR_SOLVED;
-    err_out[p] = pos;
-    err_out[P + p] = rot;
-    status_out[p] = st;
+    err_out[ei] = pos;
+    err_out[err_ld + ei] = rot;
+    status_out[ei] = st;
   }
 }
 
@@ -1056,14 +1107,19 @@ static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 struct TrajWs {
   void *Z1, *blk1, *lam1, *c01, *gd1, *cost1, *pen1;
   int32_t *chol1, *fail1, *trials1, *sel;
-  double *Z2, *blk2, *lam2, *c02, *gd2, *cost2, *pen2, *rd;
+  double *Z2, *blk2, *lam2, *c02, *gd2, *cost2, *pen2;
   int32_t *chol2, *fail2, *trials2;
+  TrajProb* tp;
+  SelRow* rows;
 };
 
-static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype dt, char* base, TrajWs* w) {
+// Workspace of one path / trajectory launch (struct TrajShape): stage-1 state for
+// every seed trajectory, stage-2 state for n_final trajectories per problem, the
+// problem table and the SelectTop rows.
+static size_t traj_ws_layout(int ns, const TrajShape& sh, int nf, cr_dtype dt, char* base, TrajWs* w) {
   const size_t t1 = dt == CR_F64 ? 8 : 4;
   const int NZ = 2 * ns, REC = 3 * NZ * NZ + 2 * NZ;  // struct Rec
-  const int64_t Tn = H + 1, n1 = P * S, n2 = P * (nf > 0 ? nf : 1);
+  const int64_t n1 = sh.N1, w1 = sh.W1, n2 = sh.P * (nf > 0 ? nf : 1), w2 = sh.TnSum * (nf > 0 ? nf : 1);
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t at = off;
@@ -1071,8 +1127,8 @@ static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype d
     return base ? (void*)(base + at) : nullptr;
   };
   TrajWs x{};
-  x.Z1 = take(t1 * n1 * Tn * NZ);
-  x.blk1 = take(t1 * n1 * Tn * REC);
+  x.Z1 = take(t1 * w1 * NZ);
+  x.blk1 = take(t1 * w1 * REC);
   x.lam1 = take(t1 * n1);
   x.c01 = take(t1 * n1);
   x.gd1 = take(t1 * n1);
@@ -1082,8 +1138,8 @@ static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype d
   x.fail1 = (int32_t*)take(4 * n1);
   x.trials1 = (int32_t*)take(4 * n1);
   x.sel = (int32_t*)take(4 * n2);
-  x.Z2 = (double*)take(8 * n2 * Tn * NZ);
-  x.blk2 = (double*)take(8 * n2 * Tn * REC);
+  x.Z2 = (double*)take(8 * w2 * NZ);
+  x.blk2 = (double*)take(8 * w2 * REC);
   x.lam2 = (double*)take(8 * n2);
   x.c02 = (double*)take(8 * n2);
   x.gd2 = (double*)take(8 * n2);
@@ -1092,29 +1148,84 @@ static size_t traj_ws_layout(int ns, int64_t P, int S, int H, int nf, cr_dtype d
   x.chol2 = (int32_t*)take(4 * n2);
   x.fail2 = (int32_t*)take(4 * n2);
   x.trials2 = (int32_t*)take(4 * n2);
-  x.rd = (double*)take(8 * CR_MAX_SEG);
+  x.tp = (TrajProb*)take(sizeof(TrajProb) * sh.P);
+  x.rows = (SelRow*)take(sizeof(SelRow) * sh.P);
   if (w) *w = x;
   return off;
 }
 
+TrajShape traj_uniform_shape(int64_t P, int S, int H, int M) {
+  TrajShape sh;
+  sh.P = P;
+  sh.N1 = P * S;
+  sh.W1 = P * S * (int64_t)(H + 1);
+  sh.TnSum = P * (int64_t)(H + 1);
+  sh.Tmax = H + 1;
+  sh.Mmax = M;
+  sh.Smax = S;
+  return sh;
+}
+
+size_t traj_workspace_bytes(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dt) {
+  return traj_ws_layout(rb.n_seg, sh, o.n_final, dt, nullptr, nullptr);
+}
+
 size_t traj_workspace_bytes(const cr_robot& rb, int64_t P, int S, int H, const cr_opts& o, cr_dtype dt) {
-  return traj_ws_layout(rb.n_seg, P, S, H, o.n_final, dt, nullptr, nullptr);
+  return traj_workspace_bytes(rb, traj_uniform_shape(P, S, H, 0), o, dt);
+}
+
+// Problem table of a uniform launch (every problem: S seeds, H + 1 waypoints, the
+// caller's SoA arrays of the single-problem entry points).
+__global__ void k_traj_table(int kind, int64_t P, int S, int Tn, int M, int per_problem, int64_t sph_ld,
+                             TrajProb* __restrict__ tp) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  TrajProb r;
+  r.Tn = Tn;
+  r.S = S;
+  r.M = M;
+  r.idx = (int32_t)q;
+  r.traj0 = q * S;
+  r.wp0 = q * S * (int64_t)Tn;
+  r.tn0 = q * Tn;
+  r.task = kind == CR_KIND_PATH ? q * Tn : q;
+  r.task_ld = kind == CR_KIND_PATH ? P * Tn : P;
+  r.seed = q * S * (int64_t)Tn;
+  r.seed_ld = P * S * (int64_t)Tn;
+  r.out = q * Tn;
+  r.out_ld = P * Tn;
+  r.sph = per_problem ? q * M : 0;
+  r.sph_ld = sph_ld;
+  tp[q] = r;
+}
+
+// SelectTop rows of a trajectory launch: candidates are whole stage-1 trajectories.
+__global__ void k_traj_selrows(int64_t P, int nz, const TrajProb* __restrict__ tp, SelRow* __restrict__ rows) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  const TrajProb r = tp[q];
+  SelRow s;
+  s.S = r.S;
+  s.nz = nz * r.Tn;
+  s.kbase = r.traj0;
+  s.zbase = r.wp0 * nz;
+  s.zsc = (int64_t)nz * r.Tn;
+  rows[q] = s;
 }
 
 template <int NS, typename T>
-static size_t traj_lds(int H, int M, bool build) {
-  const int Tn = H + 1, NZ = 2 * NS;
+static size_t traj_lds(int Tn, int M, bool build) {
+  const int NZ = 2 * NS;
   return sizeof(T) * (size_t)(4 * M + Tn * 3 * NS + Tn * 3 + (build ? Tn * 3 * NZ : 0) + 8);
 }
 
 // Capacity of the clearance work list of the search / evaluation kernels (0: none),
 // sized so that their LDS stays within 48 KiB.
 template <int NS, typename T>
-static int traj_list_cap(int H, int M) {
+static int traj_list_cap(int Tn, int M) {
   if (M <= 0) return 0;
-  const int Tn = H + 1;
   const size_t budget = 48 * 1024;
-  const size_t base = traj_lds<NS, T>(H, M, false) + sizeof(T) * (size_t)Tn * NS * CollList<T>::FR + 16;
+  const size_t base = traj_lds<NS, T>(Tn, M, false) + sizeof(T) * (size_t)Tn * NS * CollList<T>::FR + 16;
   if (base >= budget) return 0;
   size_t cap = (size_t)Tn * NS * M < 2048 ? (size_t)Tn * NS * M : 2048;
   if (cap > (budget - base) / 4) cap = (budget - base) / 4;
@@ -1122,112 +1233,113 @@ static int traj_list_cap(int H, int M) {
 }
 
 template <int NS, typename T>
-static size_t traj_lds_list(int H, int M, int cap) {
-  size_t b = traj_lds<NS, T>(H, M, false);
-  if (cap > 0) b += sizeof(T) * (size_t)(H + 1) * NS * CollList<T>::FR + 16 + 4 * (size_t)cap;
+static size_t traj_lds_list(int Tn, int M, int cap) {
+  size_t b = traj_lds<NS, T>(Tn, M, false);
+  if (cap > 0) b += sizeof(T) * (size_t)Tn * NS * CollList<T>::FR + 16 + 4 * (size_t)cap;
   return b;
 }
 
 template <int NS>
-bool traj_lds_ok(int H, int M) {
-  return traj_lds<NS, double>(H, M, true) <= 64 * 1024;
+bool traj_lds_ok(int Tmax, int Mmax) {
+  return traj_lds<NS, double>(Tmax, Mmax, true) <= 64 * 1024;
 }
 
-// One LM stage (k iterations) on nt trajectories in type T.
+static int threads_for(int Tn) { return ((Tn + 63) / 64) * 64; }
+
+// One LM stage (iters iterations) on the nt trajectories of ta, in type T.
 template <int NS, typename T>
-static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, const LMOpts<T>& lo,
-                            int64_t nt, int iters, T* Z, T* blk, T* lam, T* c0, T* gd, int32_t* chol, int32_t* failed,
-                            int32_t* trials, hipStream_t st) {
-  const int Tn = ta.H + 1;
-  const int threads = ((Tn + 63) / 64) * 64;
-  const int cap = traj_list_cap<NS, T>(ta.H, ta.M);
-  const size_t lds_b = traj_lds<NS, T>(ta.H, ta.M, true), lds_s = traj_lds_list<NS, T>(ta.H, ta.M, cap);
+static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int Mmax,
+                            const LMOpts<T>& lo, int64_t nt, int iters, T* Z, T* blk, T* lam, T* c0, T* gd,
+                            int32_t* chol, int32_t* failed, int32_t* trials, hipStream_t st) {
+  const int threads = threads_for(ta.Tmax);
+  const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax);
+  const size_t lds_b = traj_lds<NS, T>(ta.Tmax, Mmax, true), lds_s = traj_lds_list<NS, T>(ta.Tmax, Mmax, cap);
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   for (int it = 0; it < iters; ++it) {
     hipLaunchKernelGGL((k_traj_build<NS, T>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, c0,
                        failed);
-    hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, nt, ta.H, blk,
-                       lam, failed, chol, gd);
+    hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, ta, nt, blk, lam,
+                       failed, chol, gd);
     hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
                        lam, c0, gd, chol, failed, trials, cap);
   }
   return check_hip(hipGetLastError(), "trajectory LM stage");
 }
 
+// Two-stage solve of the problems in table tp (device), all of robot rb0 and
+// kind `kind`; sh describes the launch.  Outputs go where the table says; err and
+// status are indexed by the table's idx with leading dimension err_ld.
 template <int NS, typename T1>
-static cr_status run_traj(int kind, const cr_robot& rb0, const cr_spheres* sp, int64_t P, int H, const double* task, int S,
-                          const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
-                          int32_t* status_out, const TrajWs& ws, hipStream_t st) {
-  const int Tn = H + 1;
-  const int64_t n1 = P * (int64_t)S;
+static cr_status run_traj(int kind, const cr_robot& rb0, const TrajShape& sh, const TrajProb* tp, const double* task,
+                          const double* useed, const double* sph, const cr_weights& w0, const cr_opts& o,
+                          double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, const TrajWs& ws,
+                          hipStream_t st) {
+  const int64_t P = sh.P, n1 = sh.N1;
   RobotT<T1> rb1 = robot_to<T1>(rb0);
   WeightsT<T1> w1 = weights_to<T1>(w0);
   RobotT<double> rbd = robot_to<double>(rb0);
   WeightsT<double> wd = weights_to<double>(w0);
-  const int M = sp ? sp->n_sph : 0;
-  TrajArgs<T1> ta1{kind, H, P, S, task, M > 0 ? (const double*)sp->sph : nullptr, M > 0 ? sp->ld : 0, M,
-                   M > 0 ? sp->per_problem : 0};
-  cr_status rc = check_hip(hipMemcpyAsync(ws.rd, rbd.rd, sizeof(double) * CR_MAX_SEG, hipMemcpyHostToDevice, st),
-                           "copy robot radii");
-  if (rc != CR_OK) return rc;
-  hipLaunchKernelGGL((k_traj_init<NS, T1>), dim3((unsigned)((n1 * Tn + 255) / 256)), dim3(256), 0, st, n1, Tn, useed,
-                     (const double*)ws.rd, (T1*)ws.Z1);
+  TrajArgs<T1> ta1{kind, P, 0, sh.Tmax, tp, task, sph};
+  const int threads = threads_for(sh.Tmax);
+  hipLaunchKernelGGL((k_traj_init<NS, T1>), dim3((unsigned)n1), dim3(64), 0, st, rbd, ta1, useed, (T1*)ws.Z1);
   hipLaunchKernelGGL((k_fill<T1>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, (T1*)ws.lam1,
                      (T1)o.lambda0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.fail1, 0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.trials1, 0);
   LMOpts<T1> lo1{o.ls_max, (T1)o.lambda_min, (T1)o.lambda_max};
-  rc = traj_stage<NS, T1>(rb1, w1, ta1, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1, (T1*)ws.lam1, (T1*)ws.c01,
-                          (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
+  cr_status rc = traj_stage<NS, T1>(rb1, w1, ta1, sh.Mmax, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1,
+                                    (T1*)ws.lam1, (T1*)ws.c01, (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
   if (rc != CR_OK) return rc;
-  const int cap1 = traj_list_cap<NS, T1>(H, M);
-  const size_t lds_e1 = traj_lds_list<NS, T1>(H, M, cap1);
-  const int threads = ((Tn + 63) / 64) * 64;
+  const int cap1 = traj_list_cap<NS, T1>(sh.Tmax, sh.Mmax);
+  const size_t lds_e1 = traj_lds_list<NS, T1>(sh.Tmax, sh.Mmax, cap1);
   hipLaunchKernelGGL((k_traj_eval<NS, T1>), dim3((unsigned)n1), dim3(threads), lds_e1, st, rb1, w1, ta1,
                      (const T1*)ws.Z1, (T1*)ws.cost1, (T1*)ws.pen1, ws.fail1, cap1);
-  TrajArgs<double> tad{kind, H, P, S, task, ta1.sph, ta1.sld, M, ta1.per_problem};
+  TrajArgs<double> tad{kind, P, 0, sh.Tmax, tp, task, sph};
   if (o.n_final > 0) {
     const int nf = o.n_final;
     const int64_t n2 = P * (int64_t)nf;
     // SelectTop ranks path/trajectory candidates by their total cost
-    rc = launch_select_strided(P, S, 2 * NS * Tn, ws.Z1, 1, 2 * NS * Tn, ws.cost1, ws.pen1, ws.fail1, nf, o.dup_eps,
-                               ws.sel, sizeof(T1) == 8 ? CR_F64 : CR_F32, st);
+    hipLaunchKernelGGL(k_traj_selrows, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, 2 * NS, tp, ws.rows);
+    rc = launch_select_strided(P, sh.Smax, 0, ws.Z1, 1, 0, ws.cost1, ws.pen1, ws.fail1, nf, o.dup_eps, ws.sel,
+                               sizeof(T1) == 8 ? CR_F64 : CR_F32, st, ws.rows);
     if (rc != CR_OK) return rc;
-    hipLaunchKernelGGL((k_traj_gather<NS, T1>), dim3((unsigned)((n2 * Tn + 255) / 256)), dim3(256), 0, st, P, S, nf,
-                       Tn, (const T1*)ws.Z1, ws.sel, ws.Z2, ws.fail2);
+    TrajArgs<double> ta2 = tad;
+    ta2.nf = nf;
+    hipLaunchKernelGGL((k_traj_gather<NS, T1>), dim3((unsigned)n2), dim3(64), 0, st, ta2, (const T1*)ws.Z1, ws.sel,
+                       ws.Z2, ws.fail2);
     hipLaunchKernelGGL((k_fill<double>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, ws.lam2, o.lambda0);
     hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, n2, ws.trials2, 0);
-    TrajArgs<double> ta2 = tad;
-    ta2.per = nf;
     LMOpts<double> lo2{o.ls_max, o.lambda_min, o.lambda_max};
-    rc = traj_stage<NS, double>(rbd, wd, ta2, lo2, n2, o.k_final, ws.Z2, ws.blk2, ws.lam2, ws.c02, ws.gd2, ws.chol2,
-                                ws.fail2, ws.trials2, st);
+    rc = traj_stage<NS, double>(rbd, wd, ta2, sh.Mmax, lo2, n2, o.k_final, ws.Z2, ws.blk2, ws.lam2, ws.c02, ws.gd2,
+                                ws.chol2, ws.fail2, ws.trials2, st);
     if (rc != CR_OK) return rc;
-    const int cap2 = traj_list_cap<NS, double>(H, M);
-    const size_t lds_e2 = traj_lds_list<NS, double>(H, M, cap2);
+    const int cap2 = traj_list_cap<NS, double>(sh.Tmax, sh.Mmax);
+    const size_t lds_e2 = traj_lds_list<NS, double>(sh.Tmax, sh.Mmax, cap2);
     hipLaunchKernelGGL((k_traj_eval<NS, double>), dim3((unsigned)n2), dim3(threads), lds_e2, st, rbd, wd, ta2,
                        (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2, cap2);
-    hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, nf,
-                       ws.sel, (const double*)ws.Z2, (const double*)ws.cost2, ws.fail2, u_out, err_out, status_out);
+    hipLaunchKernelGGL((k_traj_finalize<NS, double>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, nf, ws.sel,
+                       (const double*)ws.Z2, (const double*)ws.cost2, ws.fail2, err_ld, u_out, err_out, status_out);
   } else {
-    hipLaunchKernelGGL((k_traj_finalize<NS, T1>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, S,
-                       (const int32_t*)nullptr, (const T1*)ws.Z1, (const T1*)ws.cost1, ws.fail1, u_out, err_out,
-                       status_out);
+    hipLaunchKernelGGL((k_traj_finalize<NS, T1>), dim3((unsigned)P), dim3(threads), 0, st, rbd, tad, 0,
+                       (const int32_t*)nullptr, (const T1*)ws.Z1, (const T1*)ws.cost1, ws.fail1, err_ld, u_out,
+                       err_out, status_out);
   }
   return check_hip(hipGetLastError(), "trajectory solve");
 }
 
-cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
-                            int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,
-                            double* err_out, int32_t* status_out, void* wsmem, cr_dtype dtype, hipStream_t st) {
+cr_status launch_traj_group(int kind, const cr_robot& rb, const TrajShape& sh, const TrajProb* tp, const double* task,
+                            const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
+                            double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
+                            cr_dtype dtype, hipStream_t st) {
   TrajWs ws;
-  traj_ws_layout(rb.n_seg, P, S, H, o.n_final, dtype, (char*)wsmem, &ws);
-#define CR_TRAJ_CASE(N)                                                                                            \
-  case N:                                                                                                          \
-    if (!traj_lds_ok<N>(H, sp ? sp->n_sph : 0)) return fail(CR_EINVAL, "horizon x spheres exceed 64 KiB of LDS"); \
-    return dtype == CR_F64                                                                                         \
-               ? run_traj<N, double>(kind, rb, sp, P, H, task, S, useed, w, o, u_out, err_out, status_out, ws, st) \
-               : run_traj<N, float>(kind, rb, sp, P, H, task, S, useed, w, o, u_out, err_out, status_out, ws, st);
+  traj_ws_layout(rb.n_seg, sh, o.n_final, dtype, (char*)wsmem, &ws);
+#define CR_TRAJ_CASE(N)                                                                                              \
+  case N:                                                                                                            \
+    if (!traj_lds_ok<N>(sh.Tmax, sh.Mmax)) return fail(CR_EINVAL, "horizon x spheres exceed 64 KiB of LDS");         \
+    return dtype == CR_F64 ? run_traj<N, double>(kind, rb, sh, tp, task, useed, sph, w, o, u_out, err_out, err_ld,   \
+                                                 status_out, ws, st)                                                 \
+                           : run_traj<N, float>(kind, rb, sh, tp, task, useed, sph, w, o, u_out, err_out, err_ld,    \
+                                                status_out, ws, st);
   switch (rb.n_seg) {
     CR_TRAJ_CASE(1)
     CR_TRAJ_CASE(2)
@@ -1239,6 +1351,24 @@ cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, 
       return fail(CR_EINVAL, "n_seg out of range");
   }
 #undef CR_TRAJ_CASE
+}
+
+TrajProb* traj_table_slot(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dtype, void* wsmem) {
+  TrajWs ws;
+  traj_ws_layout(rb.n_seg, sh, o.n_final, dtype, (char*)wsmem, &ws);
+  return ws.tp;
+}
+
+cr_status launch_solve_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
+                            int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,
+                            double* err_out, int32_t* status_out, void* wsmem, cr_dtype dtype, hipStream_t st) {
+  const int M = sp ? sp->n_sph : 0;
+  const TrajShape sh = traj_uniform_shape(P, S, H, M);
+  TrajProb* tp = traj_table_slot(rb, sh, o, dtype, wsmem);
+  hipLaunchKernelGGL(k_traj_table, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, kind, P, S, H + 1, M,
+                     sp ? sp->per_problem : 0, sp ? sp->ld : (int64_t)0, tp);
+  return launch_traj_group(kind, rb, sh, tp, task, useed, M > 0 ? (const double*)sp->sph : nullptr, w, o, u_out,
+                           err_out, P, status_out, wsmem, dtype, st);
 }
 
 }  // namespace crk
