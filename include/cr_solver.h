@@ -209,6 +209,60 @@ cr_status cr_solve_traj(const cr_robot* robot, const cr_spheres* spheres, int64_
 size_t cr_solve_traj_workspace(const cr_robot* robot, int64_t P, int32_t H, int32_t S,
                                const cr_opts* opts, cr_dtype dtype);
 
+/* ------------------------------------------------------------------------- */
+/* Uneven batches.                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* One problem of an uneven batch ([host] table).  Every problem has its own
+ * task kind, robot, horizon, seed count and spheres; its arrays are blocks at
+ * element offsets into the packed [device, double] arrays of the call:
+ *   task  IK: 12 values (3x4 row-major target pose, Sec. III-B);
+ *         PATH: [12][H+1] (row r, waypoint t at task_off + r*(H+1) + t);
+ *         TRAJ: [6n] (start then goal tendon displacements).
+ *   seeds [3n][S*(H+1)] (row r, seed s, waypoint t at seed_off + r*S*(H+1) + s*(H+1) + t).
+ *   spheres [4][n_sph] (component c of sphere m at sph_off + c*n_sph + m).
+ *   output [3n][H+1] (row r, waypoint t at out_off + r*(H+1) + t).
+ * Errors and status of problem i go to err_out[i], err_out[P + i], status_out[i]. */
+typedef struct {
+  int32_t kind;   /* cr_kind */
+  int32_t robot;  /* index into the robots array */
+  int32_t H;      /* IK: 0; PATH: 0..255; TRAJ: 1..255 */
+  int32_t S;      /* 1..4096 seeds */
+  int32_t n_sph;  /* 0..512 spheres */
+  int32_t pad;
+  int64_t task_off, seed_off, sph_off, out_off;
+} cr_problem;
+
+enum { CR_BATCH_GRAPH = 1 }; /* cr_solve_batch flags */
+
+/* Solves an uneven batch of P problems (Algorithm 1 for each, the same stages as
+ * cr_solve_ik / cr_solve_path / cr_solve_traj).  A native scheduler groups the
+ * problems by (kind, robot), orders each group longest-first by estimated work,
+ * uploads one problem table per group and launches every group's ragged solve;
+ * groups run concurrently on library-owned streams forked from `stream` and
+ * joined back into it.
+ *   robots [host] [n_robots]; probs [host] [P];
+ *   weights, opts [host] [3], indexed by cr_kind;
+ *   task, u_seed, sph, u_out [device, double] packed arrays (see cr_problem);
+ *   err_out [device, double] [2][P]; status_out [device, int32] [P];
+ *   ws/ws_bytes: at least cr_solve_batch_workspace() bytes (required with
+ *   CR_BATCH_GRAPH), or NULL/0 to let the library allocate stream-ordered.
+ * flags & CR_BATCH_GRAPH: the whole launch sequence is captured once into a
+ * hipGraph, cached by the call's arguments (table contents, pointers, options)
+ * and replayed on later identical calls.  The cache owns the graphs and their
+ * pinned table copies until the process ends.
+ * Errors: CR_EINVAL for a malformed table (kind, robot index, H, S, n_sph out of
+ * range, negative offsets); array extents cannot be checked and are the
+ * caller's responsibility.  Calls sharing a workspace must not overlap. */
+cr_status cr_solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
+                         const void* task, const void* u_seed, const void* sph, const cr_weights* weights,
+                         const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                         size_t ws_bytes, cr_dtype dtype, int32_t flags, hipStream_t stream);
+
+/* Workspace bytes of cr_solve_batch for this table (0 on invalid arguments). */
+size_t cr_solve_batch_workspace(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
+                                const cr_opts* opts, cr_dtype dtype);
+
 /* SelectTop of Algorithm 1 on given candidates, per problem: order by e
  * ascending (ties: lower index; failed candidates never kept), greedily keep
  * candidates, a candidate within dup_eps (infinity norm over nz coordinates) of

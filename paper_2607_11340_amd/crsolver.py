@@ -28,7 +28,7 @@ KIND = {"ik": 0, "path": 1, "traj": 2}
 SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_path", "cr_solve_traj",
-           "cr_solve_traj_workspace", "cr_select_top",
+           "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_select_top",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_status_string", "cr_last_error")
 
 
@@ -46,6 +46,12 @@ class _Robot(C.Structure):
 
 class _Spheres(C.Structure):
     _fields_ = [("n_sph", C.c_int32), ("per_problem", C.c_int32), ("sph", C.c_void_p), ("ld", C.c_int64)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("robot", C.c_int32), ("H", C.c_int32), ("S", C.c_int32),
+                ("n_sph", C.c_int32), ("pad", C.c_int32), ("task_off", C.c_int64), ("seed_off", C.c_int64),
+                ("sph_off", C.c_int64), ("out_off", C.c_int64)]
 
 
 class _Weights(C.Structure):
@@ -134,6 +140,10 @@ def _load():
     L.cr_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
     L.cr_solve_traj_workspace.argtypes = [R, i64, i32, i32, O, C.c_int]
     L.cr_solve_traj_workspace.restype = C.c_size_t
+    PR = C.POINTER(_Problem)
+    L.cr_solve_batch.argtypes = [R, i32, PR, i64, vp, vp, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, i32, vp]
+    L.cr_solve_batch_workspace.argtypes = [R, i32, PR, i64, O, C.c_int]
+    L.cr_solve_batch_workspace.restype = C.c_size_t
     L.cr_solve_ik_workspace.argtypes = [R, i64, i32, O, C.c_int]
     L.cr_solve_ik_workspace.restype = C.c_size_t
     L.cr_select_top.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, C.c_int, vp]
@@ -145,7 +155,7 @@ def _load():
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
-    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_path", "cr_solve_traj", "cr_select_top",
+    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_path", "cr_solve_traj", "cr_solve_batch", "cr_select_top",
                  "cr_timing_read", "cr_ik_flop_tally"):
         getattr(L, name).restype = C.c_int
     return L
@@ -302,6 +312,98 @@ def solve_traj(robot: Robot, u_start_goal: torch.Tensor, u_seed: torch.Tensor, H
     """Two-stage trajectory planning (eq. 11-15).  u_start_goal [6n, P] float64 (start then
     goal tendon displacements), u_seed as in solve_path.  err: largest endpoint error."""
     return _solve_traj("traj", robot, u_start_goal, u_seed, H, weights, opts, dtype, spheres, workspace, out)
+
+
+KIND = {"ik": 0, "path": 1, "traj": 2}
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """An uneven batch packed in the layout cr_solve_batch reads.  Each problem is
+    a dict: kind ('ik'|'path'|'traj'), robot (index), H, task (IK [3,4] pose;
+    PATH [H+1,3,4] poses; TRAJ (u_start [n,3], u_goal [n,3])), seeds
+    [S, H+1, n, 3] (IK: [S, n, 3]) and optionally spheres [M, 4]."""
+
+    def __init__(self, robots, problems):
+        import numpy as np
+        self.robots = list(robots)
+        P = len(problems)
+        self.table = (_Problem * max(P, 1))()
+        task, seed, sph = [], [], []
+        off = dict(task=0, seed=0, sph=0, out=0)
+        self.out_shape = []
+        for i, pb in enumerate(problems):
+            n = self.robots[pb["robot"]].n
+            kind = KIND[pb["kind"]]
+            H = int(pb.get("H", 0))
+            Tn = H + 1
+            if pb["kind"] == "ik":
+                t = np.asarray(pb["task"], dtype=np.float64).reshape(12)
+            elif pb["kind"] == "path":
+                t = np.asarray(pb["task"], dtype=np.float64).reshape(Tn, 12).T.reshape(-1)      # [12][Tn]
+            else:
+                us, ug = pb["task"]
+                t = np.concatenate([np.ravel(us), np.ravel(ug)]).astype(np.float64)
+            s = np.asarray(pb["seeds"], dtype=np.float64).reshape(-1, Tn, n * 3)             # [S, Tn, 3n]
+            S = s.shape[0]
+            s = s.reshape(S * Tn, 3 * n).T.reshape(-1)                                        # [3n][S*Tn]
+            m = np.zeros((0, 4)) if pb.get("spheres") is None else np.asarray(pb["spheres"], dtype=np.float64)
+            r = self.table[i]
+            r.kind, r.robot, r.H, r.S, r.n_sph, r.pad = kind, pb["robot"], H, S, len(m), 0
+            r.task_off, r.seed_off, r.sph_off, r.out_off = off["task"], off["seed"], off["sph"], off["out"]
+            task.append(t)
+            seed.append(s)
+            sph.append(m.T.reshape(-1))
+            off["task"] += t.size
+            off["seed"] += s.size
+            off["sph"] += m.size
+            off["out"] += 3 * n * Tn
+            self.out_shape.append((r.out_off, n, Tn, kind))
+        self.P = P
+        cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0)
+        self.task = cat(task)
+        self.seed = cat(seed)
+        self.sph = cat(sph)
+        self.n_out = off["out"]
+
+    def unpack(self, u_flat):
+        """Per-problem outputs [H+1, n, 3] (IK: [n, 3]) from the packed u_out."""
+        res = []
+        for (o, n, Tn, kind) in self.out_shape:
+            u = u_flat[o:o + 3 * n * Tn].reshape(3 * n, Tn).T.reshape(Tn, n, 3)
+            res.append(u[0] if kind == 0 else u)
+        return res
+
+
+def batch_workspace_bytes(batch: "Batch", opts, dtype) -> int:
+    rob = (_Robot * len(batch.robots))(*[r.c() for r in batch.robots])
+    oc = (_Opts * 3)(*[o.c() for o in opts])
+    return int(lib.cr_solve_batch_workspace(rob, len(batch.robots), batch.table, batch.P, oc, _dt(dtype)))
+
+
+def solve_batch(batch: "Batch", weights, opts, dtype=torch.float32, device="cuda", graph=False, workspace=None,
+                dev_arrays=None, out=None):
+    """cr_solve_batch on a packed Batch.  weights, opts: 3 each, indexed by kind
+    (ik, path, traj).  Returns (u_out flat [device], err [2, P], status [P])."""
+    if dev_arrays is None:
+        mk = lambda a: torch.tensor(a if a.size else [0.0], dtype=torch.float64, device=device)
+        dev_arrays = (mk(batch.task), mk(batch.seed), mk(batch.sph))
+    task, seed, sph = dev_arrays
+    if out is None:
+        out = (torch.empty(max(batch.n_out, 1), dtype=torch.float64, device=device),
+               torch.empty((2, max(batch.P, 1)), dtype=torch.float64, device=device),
+               torch.empty(max(batch.P, 1), dtype=torch.int32, device=device))
+    u, err, st = out
+    rob = (_Robot * len(batch.robots))(*[r.c() for r in batch.robots])
+    wc = (_Weights * 3)(*[w.c() for w in weights])
+    oc = (_Opts * 3)(*[o.c() for o in opts])
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    _check(lib.cr_solve_batch(rob, len(batch.robots), batch.table, batch.P, _ptr(task), _ptr(seed), _ptr(sph), wc, oc,
+                              _ptr(u), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype),
+                              BATCH_GRAPH if graph else 0, _stream(task)))
+    return u, err, st
 
 
 def select_top(z: torch.Tensor, e: torch.Tensor, pen: torch.Tensor, failed, P: int, S: int, n_final: int,

@@ -126,7 +126,7 @@ static void timer_release_all() {
   g_timer.calls.clear();
 }
 
-static cr_status check_robot(const cr_robot* rb) {
+cr_status check_robot(const cr_robot* rb) {
   if (!rb) return fail(CR_EINVAL, "robot is NULL");
   if (rb->n_seg < 1 || rb->n_seg > CR_MAX_SEG) return fail(CR_EINVAL, "n_seg=%d not in 1..%d", rb->n_seg, CR_MAX_SEG);
   if (rb->pts_per_seg < 1 || rb->pts_per_seg > 1024) return fail(CR_EINVAL, "pts_per_seg=%d not in 1..1024", rb->pts_per_seg);
@@ -139,12 +139,12 @@ static cr_status check_robot(const cr_robot* rb) {
   return CR_OK;
 }
 
-static cr_status check_dtype(cr_dtype d) {
+cr_status check_dtype(cr_dtype d) {
   if (d != CR_F32 && d != CR_F64) return fail(CR_EINVAL, "dtype %d invalid", (int)d);
   return CR_OK;
 }
 
-static cr_status check_opts(const cr_opts* o) {
+cr_status check_opts(const cr_opts* o) {
   if (!o) return fail(CR_EINVAL, "opts is NULL");
   if (o->n_final < 0 || o->n_final > 64) return fail(CR_EINVAL, "n_final=%d not in 0..64", o->n_final);
   if (o->k_init < 0 || o->k_final < 0) return fail(CR_EINVAL, "negative iteration count");
@@ -155,7 +155,7 @@ static cr_status check_opts(const cr_opts* o) {
   return CR_OK;
 }
 
-static cr_status check_weights(const cr_weights* w) {
+cr_status check_weights(const cr_weights* w) {
   if (!w) return fail(CR_EINVAL, "weights is NULL");
   const double v[] = {w->w_pos, w->w_rot, w->rho_lim, w->rho_curv, w->rho_coll, w->rho_eq, w->w_len, w->w_vel, w->w_acc};
   for (double x : v)
@@ -297,6 +297,19 @@ static cr_status solve_traj_common(int kind, const cr_robot* robot, const cr_sph
     if (rc == CR_OK) rc = rc2;
   }
   return rc;
+}
+
+cr_status cr_solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
+                         const void* task, const void* u_seed, const void* sph, const cr_weights* weights,
+                         const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                         size_t ws_bytes, cr_dtype dtype, int32_t flags, hipStream_t stream) {
+  return solve_batch(robots, n_robots, probs, P, task, u_seed, sph, weights, opts, u_out, err_out, status_out, ws,
+                     ws_bytes, dtype, flags, stream);
+}
+
+size_t cr_solve_batch_workspace(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
+                                const cr_opts* opts, cr_dtype dtype) {
+  return batch_workspace_bytes(robots, n_robots, probs, P, opts, dtype);
 }
 
 void cr_timing_enable(int32_t on) {

@@ -376,6 +376,196 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
+// Ragged launches (uneven batches): every problem has its own seed count,
+// sphere set and array offsets (struct IkProb); same per-seed iteration.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t ik_find(const IkProb* tp, int64_t P, int64_t b) {
+  int64_t lo = 0, hi = P - 1;  // last problem whose first seed is <= b
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tp[mid].seed0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_ik_stage1_rag(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
+                    const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
+                    int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
+                    T* __restrict__ cost_out, int32_t* __restrict__ failed_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const IkProb pr = tp[ik_find(tp, P, b)];
+  const int64_t s = b - pr.seed0;
+  T tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = (T)task[pr.task + c * pr.task_ld];
+  T z[NZ];
+  const double* u = useed + pr.seed + s;
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+    u_to_ab((T)u[(3 * i) * pr.seed_ld], (T)u[(3 * i + 1) * pr.seed_ld], (T)u[(3 * i + 2) * pr.seed_ld], rb.r[i],
+            &z[2 * i], &z[2 * i + 1]);
+  T lam = lam0;
+  bool failed = false;
+  int trials = 0;
+  T e, c, pen = T(0);
+  if (pr.M > 0) {
+    const double* sp = sph + pr.sph;
+    lm_cfg<NS, T, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, pr.M, 1, pr.sph_ld);
+    ik_cost<NS>(rb, w, tt, z, &e);
+    c = cfg_cost<NS, T, double>(rb, w, tt, z, sp, pr.M, 1, pr.sph_ld);
+    WeightsT<T> wc = w;
+    wc.w_pos = wc.w_rot = wc.sq_lim = wc.sq_curv = T(0);
+    pen = cfg_cost<NS, T, double>(rb, wc, tt, z, sp, pr.M, 1, pr.sph_ld);
+  } else {
+    lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+    c = ik_cost<NS>(rb, w, tt, z, &e);
+  }
+  if (!tfinite(c) || !tfinite(e)) failed = true;
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
+  e_out[b] = e;
+  pen_out[b] = pen;
+  cost_out[b] = c;
+  failed_out[b] = failed ? 1 : 0;
+}
+
+__global__ void k_ik_selrows(int64_t P, int nz, const IkProb* __restrict__ tp, SelRow* __restrict__ rows) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P) return;
+  SelRow r;
+  r.S = tp[q].S;
+  r.nz = nz;
+  r.kbase = tp[q].seed0;
+  r.zbase = tp[q].seed0;
+  r.zsc = 1;
+  rows[q] = r;
+}
+
+template <int NS, typename T1>
+__global__ void __launch_bounds__(256)
+    k_ik_stage2_rag(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int64_t B, int nf,
+                    const IkProb* __restrict__ tp, const double* __restrict__ task, const double* __restrict__ sph,
+                    const T1* __restrict__ z1, const int32_t* __restrict__ sel, int iters, double lam0,
+                    double* __restrict__ z2, double* __restrict__ cost2, int32_t* __restrict__ failed2) {
+  constexpr int NZ = 2 * NS;
+  const int64_t B2 = P * (int64_t)nf;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B2) return;
+  const int64_t p = b / nf;
+  const int k = (int)(b % nf);
+  const int s = sel[k * P + p];
+  if (s < 0) {
+#pragma unroll
+    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
+    cost2[b] = __builtin_nan("");
+    failed2[b] = 1;
+    return;
+  }
+  const IkProb pr = tp[p];
+  double tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = task[pr.task + c * pr.task_ld];
+  double z[NZ];
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z[m] = (double)z1[m * B + pr.seed0 + s];
+  double lam = lam0;
+  bool failed = false;
+  int trials = 0;
+  double c;
+  if (pr.M > 0) {
+    const double* sp = sph + pr.sph;
+    lm_cfg<NS, double, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, pr.M, 1, pr.sph_ld);
+    c = cfg_cost<NS, double, double>(rb, w, tt, z, sp, pr.M, 1, pr.sph_ld);
+  } else {
+    lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+    c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
+  }
+  if (!tfinite(c)) failed = true;
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
+  cost2[b] = c;
+  failed2[b] = failed ? 1 : 0;
+}
+
+// Argmin and FP64 assessment per problem.  Candidates: the nf stage-2 slots
+// (sel != NULL) or every stage-1 seed of the problem.
+template <int NS, typename TC>
+__global__ void __launch_bounds__(256)
+    k_ik_finalize_rag(RobotT<double> rb, int64_t P, int64_t Bc, int nf, const IkProb* __restrict__ tp,
+                      const int32_t* __restrict__ sel, const TC* __restrict__ zc, const TC* __restrict__ costc,
+                      const int32_t* __restrict__ failedc, const double* __restrict__ task,
+                      const double* __restrict__ sph, int64_t err_ld, double* __restrict__ u_out,
+                      double* __restrict__ err_out, int32_t* __restrict__ status_out) {
+  constexpr int NZ = 2 * NS;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const IkProb pr = tp[p];
+  const int nc = sel ? nf : pr.S;
+  const int64_t c0 = sel ? p * nf : pr.seed0;
+  int best = -1, best_seed = 0;
+  double best_cost = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    const int seed = sel ? sel[k * P + p] : k;
+    const double c = (double)costc[c0 + k];
+    if (seed < 0 || failedc[c0 + k] || !tfinite(c)) continue;
+    if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
+      best = k;
+      best_cost = c;
+      best_seed = seed;
+    }
+  }
+  double* uo = u_out + pr.out;
+  const int64_t ei = pr.idx;
+  if (best < 0) {
+    const double nan = __builtin_nan("");
+    for (int m = 0; m < 3 * NS; ++m) uo[m * pr.out_ld] = nan;
+    err_out[ei] = err_out[err_ld + ei] = nan;
+    status_out[ei] = CR_NONFINITE;
+    return;
+  }
+  double z[NZ];
+#pragma unroll
+  for (int m = 0; m < NZ; ++m) z[m] = (double)zc[m * Bc + c0 + best];
+  double tt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) tt[c] = task[pr.task + c * pr.task_ld];
+  double Rc[9], pc[3];
+  fk_tip<NS>(rb, z, Rc, pc);
+  double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
+  const double pos = sqrt(dot3(dp, dp));
+  double Re[9], te[3];
+  relative_pose(Rc, pc, tt, Re, te);
+  double v[3] = {0.5 * (Re[7] - Re[5]), 0.5 * (Re[2] - Re[6]), 0.5 * (Re[3] - Re[1])};
+  const double rot = atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0));
+  double viol = -DBL_MAX, thx = -DBL_MAX;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double u[3];
+    ab_to_u(z[2 * i], z[2 * i + 1], rb.rd[i], u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      uo[(3 * i + j) * pr.out_ld] = u[j];
+      viol = fmax(viol, fabs(u[j]) - rb.umaxd[i]);
+    }
+    thx = fmax(thx, sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) - rb.theta_maxd);
+  }
+  int32_t st = 0;
+  if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
+  if (pr.M > 0 && penetrates<NS>(rb, z, sph + pr.sph, pr.M, pr.sph_ld)) st |= CR_COLLISION;
+  if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
+  if (st == 0) st = CR_SOLVED;
+  err_out[ei] = pos;
+  err_out[err_ld + ei] = rot;
+  status_out[ei] = st;
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 
@@ -517,6 +707,110 @@ cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const v
                         const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out, cr_dtype dtype,
                         hipStream_t st) {
   return launch_select_strided(P, S, nz, z, P * (int64_t)S, 1, e, pen, failed, n_final, dup_eps, idx_out, dtype, st);
+}
+
+struct IkGroupWs {
+  void *z1, *e1, *pen1, *cost1;
+  int32_t *failed1, *sel;
+  double *z2, *cost2;
+  int32_t* failed2;
+  IkProb* tp;
+  SelRow* rows;
+};
+
+static size_t ik_group_layout(int ns, int64_t P, int64_t B, int nf, cr_dtype dtype, char* base, IkGroupWs* w) {
+  const size_t t1 = dtype == CR_F64 ? 8 : 4;
+  const int nz = 2 * ns;
+  const int64_t n2 = P * (nf > 0 ? nf : 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return base ? (void*)(base + at) : nullptr;
+  };
+  IkGroupWs x{};
+  x.z1 = take(t1 * nz * B);
+  x.e1 = take(t1 * B);
+  x.pen1 = take(t1 * B);
+  x.cost1 = take(t1 * B);
+  x.failed1 = (int32_t*)take(4 * B);
+  x.sel = (int32_t*)take(4 * n2);
+  x.z2 = (double*)take(8 * nz * n2);
+  x.cost2 = (double*)take(8 * n2);
+  x.failed2 = (int32_t*)take(4 * n2);
+  x.tp = (IkProb*)take(sizeof(IkProb) * P);
+  x.rows = (SelRow*)take(sizeof(SelRow) * P);
+  if (w) *w = x;
+  return off;
+}
+
+size_t ik_group_workspace_bytes(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o, cr_dtype dtype) {
+  return ik_group_layout(rb.n_seg, P, B, o.n_final, dtype, nullptr, nullptr);
+}
+
+IkProb* ik_table_slot(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o, cr_dtype dtype, void* wsmem) {
+  IkGroupWs w;
+  ik_group_layout(rb.n_seg, P, B, o.n_final, dtype, (char*)wsmem, &w);
+  return w.tp;
+}
+
+template <int NS, typename T>
+static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Smax, const IkProb* tp,
+                              const double* task, const double* useed, const double* sph, const cr_weights& w0,
+                              const cr_opts& o, double* u_out, double* err_out, int64_t err_ld, int32_t* status_out,
+                              const IkGroupWs& ws, hipStream_t st) {
+  RobotT<T> rb = robot_to<T>(rb0);
+  WeightsT<T> w = weights_to<T>(w0);
+  LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
+  RobotT<double> rbd = robot_to<double>(rb0);
+  hipLaunchKernelGGL((k_ik_stage1_rag<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B, tp, task,
+                     useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1);
+  cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_rag");
+  if (rc != CR_OK) return rc;
+  if (o.n_final > 0) {
+    const int nf = o.n_final;
+    hipLaunchKernelGGL(k_ik_selrows, dim3(blocks_for(P, 256)), dim3(256), 0, st, P, 2 * NS, tp, ws.rows);
+    rc = launch_select_strided(P, Smax, 2 * NS, ws.z1, B, 1, ws.e1, ws.pen1, ws.failed1, nf, o.dup_eps, ws.sel,
+                               sizeof(T) == 8 ? CR_F64 : CR_F32, st, ws.rows);
+    if (rc != CR_OK) return rc;
+    WeightsT<double> wd = weights_to<double>(w0);
+    LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
+    const int64_t B2 = P * (int64_t)nf;
+    hipLaunchKernelGGL((k_ik_stage2_rag<NS, T>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, B, nf,
+                       tp, task, sph, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, ws.z2, ws.cost2, ws.failed2);
+    hipLaunchKernelGGL((k_ik_finalize_rag<NS, double>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, B2, nf,
+                       tp, ws.sel, ws.z2, ws.cost2, ws.failed2, task, sph, err_ld, u_out, err_out, status_out);
+  } else {
+    hipLaunchKernelGGL((k_ik_finalize_rag<NS, T>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, B, 0, tp,
+                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, task, sph, err_ld,
+                       u_out, err_out, status_out);
+  }
+  return check_hip(hipGetLastError(), "ragged IK");
+}
+
+cr_status launch_ik_group(const cr_robot& rb, int64_t P, int64_t B, int Smax, const IkProb* tp, const double* task,
+                          const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
+                          double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
+                          cr_dtype dtype, hipStream_t st) {
+  IkGroupWs ws;
+  ik_group_layout(rb.n_seg, P, B, o.n_final, dtype, (char*)wsmem, &ws);
+#define CR_IKG_CASE(N)                                                                                         \
+  case N:                                                                                                      \
+    return dtype == CR_F64 ? run_ik_group<N, double>(rb, P, B, Smax, tp, task, useed, sph, w, o, u_out, err_out, \
+                                                     err_ld, status_out, ws, st)                               \
+                           : run_ik_group<N, float>(rb, P, B, Smax, tp, task, useed, sph, w, o, u_out, err_out,  \
+                                                    err_ld, status_out, ws, st);
+  switch (rb.n_seg) {
+    CR_IKG_CASE(1)
+    CR_IKG_CASE(2)
+    CR_IKG_CASE(3)
+    CR_IKG_CASE(4)
+    CR_IKG_CASE(5)
+    CR_IKG_CASE(6)
+    default:
+      return fail(CR_EINVAL, "n_seg out of range");
+  }
+#undef CR_IKG_CASE
 }
 
 }  // namespace crk

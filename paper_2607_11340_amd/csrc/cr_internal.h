@@ -28,6 +28,10 @@ struct TrajProb {
 
 
 // Records a message for cr_last_error() and returns the status.
+cr_status check_robot(const cr_robot* rb);
+cr_status check_dtype(cr_dtype d);
+cr_status check_opts(const cr_opts* o);
+cr_status check_weights(const cr_weights* w);
 cr_status fail(cr_status s, const char* fmt, ...);
 cr_status check_hip(hipError_t e, const char* what);
 
@@ -65,6 +69,28 @@ cr_status launch_select(int64_t P, int32_t S, int32_t nz, const void* z, const v
 cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
                                 const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
                                 int32_t* idx_out, cr_dtype dtype, hipStream_t st, const SelRow* rows = nullptr);
+
+// One row per problem of a ragged IK launch (device memory): pose element c
+// (3x4 row-major) at task + c * task_ld; seed row r, seed s at seed + r * seed_ld
+// + s; output row r at out + r * out_ld; sphere m, component c at sph + c * sph_ld
+// + m.  seed0 is the problem's first seed in the launch's stage-1 arrays.
+struct IkProb {
+  int32_t S, M, idx, pad;
+  int64_t seed0, task, task_ld, seed, seed_ld, out, out_ld, sph, sph_ld;
+};
+size_t ik_group_workspace_bytes(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o, cr_dtype dtype);
+IkProb* ik_table_slot(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o, cr_dtype dtype, void* wsmem);
+cr_status launch_ik_group(const cr_robot& rb, int64_t P, int64_t B, int Smax, const IkProb* tp, const double* task,
+                          const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
+                          double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
+                          cr_dtype dtype, hipStream_t st);
+
+size_t batch_workspace_bytes(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
+                             const cr_opts* opts, cr_dtype dtype);
+cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P, const void* task,
+                      const void* u_seed, const void* sph, const cr_weights* weights, const cr_opts* opts,
+                      void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, cr_dtype dtype,
+                      int32_t flags, hipStream_t stream);
 
 // Totals of a path / trajectory launch: problems, stage-1 trajectories and
 // waypoint configurations, waypoints summed over problems, largest horizon + 1,

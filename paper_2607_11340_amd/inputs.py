@@ -42,6 +42,50 @@ WORKLOADS = {
 }
 
 
+# Uneven batch: problem mix and ranges (robot geometry of path_4seg per segment;
+# iteration budgets of the IK / path / trajectory workloads).
+UNEVEN = dict(P=2048, frac=(0.60, 0.25, 0.15), n=(1, 6), H=(1, 64), S=(16, 512), M=(0, 64),
+              L=0.08, r=0.008, b=0.006, K=10, seed=BASE_SEED + 5)
+
+
+def uneven_problems(rng: np.random.Generator, P: int, spec: dict = None) -> list:
+    """Shapes and random draws of an uneven batch: per problem a dict with kind
+    ('ik' | 'path' | 'traj'), n, H (0 for IK), S, M and the actuations the caller
+    turns into tasks (IK: u_true [n,3]; PATH: u_ref [H+1,n,3]; TRAJ: u_start,
+    u_goal [n,3]), seeds [S, H+1, n, 3] and 4*M candidate spheres [4M, 4] (the
+    caller keeps the first M that clear its configurations).  Path seeds are the
+    reference plus N(0, 0.5 mm) per tendon; trajectory seeds are perturbed
+    straight lines."""
+    spec = spec or UNEVEN
+    b = spec["b"]
+    kinds = rng.choice(3, size=P, p=list(spec["frac"]))
+    out = []
+    for q in range(P):
+        kind = ("ik", "path", "traj")[kinds[q]]
+        n = int(rng.integers(spec["n"][0], spec["n"][1] + 1))
+        H = 0 if kind == "ik" else int(rng.integers(spec["H"][0], spec["H"][1] + 1))
+        S = int(rng.integers(spec["S"][0], spec["S"][1] + 1))
+        M = int(rng.integers(spec["M"][0], spec["M"][1] + 1))
+        Tn = H + 1
+        d = dict(kind=kind, n=n, H=H, S=S, M=M)
+        if kind == "ik":
+            d["u_true"] = uniform_actuation(rng, n, b, 1)[0]
+            d["seeds"] = uniform_actuation(rng, n, b, S).reshape(S, 1, n, 3)
+        elif kind == "path":
+            d["u_ref"] = smooth_actuation_paths(rng, n, b, 1, Tn)[0]
+            s = np.clip(d["u_ref"][None] + rng.normal(size=(S, Tn, n, 3)) * 5e-4, -b, b)
+            d["seeds"] = s - s.mean(axis=-1, keepdims=True)
+        else:
+            ends = uniform_actuation(rng, n, b, 2)
+            d["u_start"], d["u_goal"] = ends[0], ends[1]
+            d["seeds"] = perturbed_linear_paths(rng, ends[0], ends[1], S, Tn, b)
+        reach = n * spec["L"]
+        d["sphere_pool"] = spheres(rng, 4 * M, [-0.7 * reach, -0.7 * reach, 0.0], [0.7 * reach, 0.7 * reach, reach],
+                                   0.005, 0.02)
+        out.append(d)
+    return out
+
+
 def rng_for(name: str, salt: int = 0) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(WORKLOADS[name]["seed"] * 1000 + salt))
 

@@ -113,3 +113,39 @@ def test_select_top_rejects_bad_arguments_on_host(cr):
     assert L.cr_select_top(4, 8, 2, p, p, p, None, 65, 1e-3, p, 0, None) == cr.CR_EINVAL
     assert L.cr_select_top(4, 8, 2, p, p, p, None, 2, -1.0, p, 0, None) == cr.CR_EINVAL
     assert L.cr_select_top(4, 8, 2, p, None, p, None, 2, 1e-3, p, 0, None) == cr.CR_EINVAL
+
+
+def test_batch_table_validation_on_host(cr):
+    """cr_solve_batch rejects malformed tables before any device work; the
+    workspace query is host-only and grows with the table."""
+    L = cr.lib
+    rob = (cr._Robot * 2)(_robot(cr).c(), _robot(cr, L=[0.1], r=[0.01], u_max=[0.01]).c())
+    wc = (cr._Weights * 3)(*[cr.Weights().c()] * 3)
+    oc = (cr._Opts * 3)(*[cr.Opts().c()] * 3)
+    p = C.c_void_p(1)
+
+    def table(rows):
+        t = (cr._Problem * len(rows))()
+        for i, (kind, robot, H, S, M) in enumerate(rows):
+            t[i].kind, t[i].robot, t[i].H, t[i].S, t[i].n_sph = kind, robot, H, S, M
+        return t
+
+    good = [(0, 0, 0, 16, 0), (1, 1, 5, 8, 2), (2, 0, 3, 4, 0)]
+    for bad in ([(3, 0, 0, 16, 0)], [(0, 2, 0, 16, 0)], [(0, 0, 1, 16, 0)], [(2, 0, 0, 4, 0)], [(1, 0, 256, 4, 0)],
+                [(0, 0, 0, 0, 0)], [(0, 0, 0, 4097, 0)], [(0, 0, 0, 16, 513)], [(0, 0, 0, 16, -1)]):
+        t = table(good + bad)
+        rc = L.cr_solve_batch(rob, 2, t, len(good) + 1, p, p, p, wc, oc, p, p, p, None, 0, 0, 0, None)
+        assert rc == cr.CR_EINVAL, bad
+        assert L.cr_solve_batch_workspace(rob, 2, t, len(good) + 1, oc, 0) == 0
+    t = table(good)
+    t[0].task_off = -1
+    assert L.cr_solve_batch(rob, 2, t, 3, p, p, p, wc, oc, p, p, p, None, 0, 0, 0, None) == cr.CR_EINVAL
+    assert L.cr_solve_batch(rob, 0, table(good), 3, p, p, p, wc, oc, p, p, p, None, 0, 0, 0, None) == cr.CR_EINVAL
+    # graph mode needs a caller workspace
+    assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, None, 0, 0, 1, None) == cr.CR_EINVAL
+    # too small a workspace
+    assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, p, 16, 0, 0, None) == cr.CR_ENOMEM
+    a = L.cr_solve_batch_workspace(rob, 2, table(good), 3, oc, 0)
+    b = L.cr_solve_batch_workspace(rob, 2, table(good + good), 6, oc, 0)
+    c = L.cr_solve_batch_workspace(rob, 2, table(good), 3, oc, 1)
+    assert 0 < a < b and a < c
