@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "path_4seg", "traj_5seg"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "path_4seg", "traj_5seg", "uneven_batch"],
                     help="the headline IK workload, or one of the path / trajectory workloads")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -96,6 +96,8 @@ def main():
     from paper_2607_11340_amd import crsolver as cr
     from paper_2607_11340_amd import inputs as I
 
+    if args.workload == "uneven_batch":
+        return bench_uneven(args, cr, I, torch)
     if args.workload != WORKLOAD:
         return bench_trajectories(args, cr, I, torch)
     spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
@@ -273,6 +275,103 @@ def bench_trajectories(args, cr, I, torch):
                 success_rate=round(float((status == cr.SOLVED).mean()), 4),
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                 max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)])
+    print(json.dumps(line), flush=True)
+
+
+def uneven_inputs(cr, I, torch, P):
+    """The uneven batch: problem shapes and draws from the inputs recipe; tasks by
+    forward kinematics on the GPU; spheres kept only if they clear the problem's
+    target (IK), reference (path) or start and goal (trajectory) backbones by 2 mm."""
+    spec = I.UNEVEN
+    rng = np.random.Generator(np.random.PCG64(spec["seed"]))
+    probs = I.uneven_problems(rng, P)
+    L, r, b, K = spec["L"], spec["r"], spec["b"], spec["K"]
+    robots = [cr.Robot(L=[L] * n, r=[r] * n, u_max=[b] * n, pts_per_seg=K) for n in range(1, 7)]
+    dev = torch.device("cuda:0")
+    # forward kinematics of every task configuration, one call per segment count
+    cfg = {}
+    for n in range(1, 7):
+        rows = [(q, pb) for q, pb in enumerate(probs) if pb["n"] == n]
+        us, owners = [], []
+        for q, pb in rows:
+            u = pb["u_true"][None] if pb["kind"] == "ik" else (pb["u_ref"] if pb["kind"] == "path"
+                                                                else np.stack([pb["u_start"], pb["u_goal"]]))
+            us.append(u)
+            owners.append((q, len(u)))
+        if not us:
+            continue
+        U = np.concatenate(us).reshape(-1, 3 * n)
+        out = cr.fk(robots[n - 1], torch.tensor(U.T.copy(), device=dev), arc=False, frames=True, points=True)
+        fr = out["frames"][12 * (n - 1):12 * n].cpu().numpy().T            # [B, 12]
+        pts = out["pts"].cpu().numpy().T.reshape(len(U), n * K, 3)
+        at = 0
+        for q, m in owners:
+            cfg[q] = (fr[at:at + m], pts[at:at + m])
+            at += m
+    batch_probs, n_kept = [], 0
+    for q, pb in enumerate(probs):
+        n, Tn = pb["n"], pb["H"] + 1
+        fr, pts = cfg[q]
+        body = np.tile(np.repeat(np.full(n, r), K), len(pts))
+        P3 = pts.reshape(-1, 3)
+        pool = pb["sphere_pool"]
+        clear = (np.linalg.norm(P3[None] - pool[:, None, :3], axis=2) - pool[:, 3:4] - body[None]).min(axis=1) > 2e-3
+        sph = pool[clear][:pb["M"]]
+        n_kept += len(sph)
+        if pb["kind"] == "ik":
+            task = fr[0].reshape(3, 4)
+            seeds = pb["seeds"][:, 0]
+        elif pb["kind"] == "path":
+            task = fr.reshape(Tn, 3, 4)
+            seeds = pb["seeds"]
+        else:
+            task = (pb["u_start"], pb["u_goal"])
+            seeds = pb["seeds"]
+        batch_probs.append(dict(kind=pb["kind"], robot=n - 1, H=pb["H"], task=task, seeds=seeds,
+                                spheres=sph if len(sph) else None))
+    return cr.Batch(robots, batch_probs), probs, n_kept
+
+
+def bench_uneven(args, cr, I, torch):
+    P = I.UNEVEN["P"]
+    t0 = time.perf_counter()
+    batch, probs, n_sph = uneven_inputs(cr, I, torch, P)
+    print(f"bench: uneven batch built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    specs = [I.WORKLOADS[k] for k in ("ik_batched_3seg", "path_4seg", "traj_5seg")]
+    opts = [cr.Opts(n_final=s["n_final"], k_init=s["k_init"], k_final=s["k_final"]) for s in specs]
+    weights = [cr.Weights(), cr.Weights(**specs[1]["weights"]), cr.Weights()]
+    ws = torch.empty(cr.batch_workspace_bytes(batch, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    dev = tuple(torch.tensor(a if a.size else [0.0], dtype=torch.float64, device="cuda")
+                for a in (batch.task, batch.seed, batch.sph))
+    out = (torch.empty(batch.n_out, dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.int32, device="cuda"))
+
+    def step():
+        cr.solve_batch(batch, weights, opts, dtype=torch.float32, workspace=ws, dev_arrays=dev, graph=True, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    st = out[2].cpu().numpy()
+    kinds = np.array([("ik", "path", "traj").index(p["kind"]) for p in probs])
+    succ = {k: round(float((st[kinds == i] == cr.SOLVED).mean()), 4) for i, k in enumerate(("ik", "path", "traj"))}
+    line = dict(metric="uneven batch solves/sec (success %)", value=round(P / (ms * 1e-3), 2), unit="problems/s",
+                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
+                config=dict(workload="uneven_batch", problems=P, mix=dict(ik=int((kinds == 0).sum()),
+                                                                          path=int((kinds == 1).sum()),
+                                                                          traj=int((kinds == 2).sum())),
+                            segments="U{1..6}", horizons="U{1..64}", seeds="U{16..512}", spheres="U{0..64}",
+                            spheres_kept=n_sph, seeds_total=int(sum(p["S"] for p in probs)), graph=True),
+                success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ)
     print(json.dumps(line), flush=True)
 
 
