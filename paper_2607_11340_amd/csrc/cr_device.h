@@ -704,6 +704,7 @@ CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T
       dl[j] = -g[j];
     }
     if (!chol_solve<NZ>(Hp, dl)) {
+      if (!(lam < o.lam_max)) break;  // z and lambda would repeat: every later iteration is this one
       lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
       continue;
     }
@@ -729,6 +730,7 @@ CR_HD void lm_ik(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T
       for (int j = 0; j < NZ; ++j) z[j] = zt[j];
       if (acc == 0) lam = lam / T(10) > o.lam_min ? lam / T(10) : o.lam_min;
     } else {
+      if (!(lam < o.lam_max)) break;  // rejected at the largest damping: a fixed point of the iteration
       lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
     }
   }
@@ -1317,6 +1319,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
       dl[j] = -g[j];
     }
     if (!chol_solve<NZ>(Hp, dl)) {
+      if (!(lam < o.lam_max)) break;  // z and lambda would repeat: every later iteration is this one
       lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
       continue;
     }
@@ -1342,6 +1345,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
       for (int j = 0; j < NZ; ++j) z[j] = zt[j];
       if (acc == 0) lam = lam / T(10) > o.lam_min ? lam / T(10) : o.lam_min;
     } else {
+      if (!(lam < o.lam_max)) break;  // rejected at the largest damping: a fixed point of the iteration
       lam = lam * T(10) < o.lam_max ? lam * T(10) : o.lam_max;
     }
   }

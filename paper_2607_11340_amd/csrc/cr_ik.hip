@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(256)
   for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
     if (i < S) {
       T ev = e[kb + i];
-      int fl = (failed && failed[kb + i]) || !tfinite(ev) ? 1 : 0;
+      int fl = (failed && failed[kb + i] == 1) || !tfinite(ev) ? 1 : 0;
       se[i] = ev;
       sf[i] = (fl << 16) | i;
     } else {

@@ -15,7 +15,10 @@
 //                  trial cost is block-reduced, so accept/reject is uniform per
 //                  workgroup; updates z and lambda.
 // Per trajectory and waypoint the workspace holds one record (struct Rec) and z
-// is stored trajectory-major, waypoint, coordinate: [traj][t][k].
+// is stored trajectory-major, waypoint, coordinate: [traj][t][k].  A trajectory's
+// flag is 0 while it iterates, 1 once its cost is not finite (never selected) and
+// 2 once a step was rejected at the largest damping: z and lambda then repeat in
+// every later iteration, so its kernels skip it with the result unchanged.
 #include <float.h>
 
 #include "cr_internal.h"
@@ -827,7 +830,7 @@ template <int NS, typename T>
 __global__ void __launch_bounds__(256)
     k_traj_search(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                   const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
-                  const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, const int32_t* __restrict__ failed,
+                  const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
                   int32_t* __restrict__ trials, int list_cap) {
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   using R = Rec<NS>;
@@ -835,7 +838,11 @@ __global__ void __launch_bounds__(256)
   const int64_t traj = blockIdx.x;
   if (failed[traj]) return;
   if (!chol_ok[traj]) {
-    if (threadIdx.x == 0) lam[traj] = lam[traj] * T(10) < o.lam_max ? lam[traj] * T(10) : o.lam_max;
+    if (threadIdx.x == 0) {
+      const T l = lam[traj];
+      if (!(l < o.lam_max)) failed[traj] = 2;  // z and lambda would repeat from here on
+      else lam[traj] = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    }
     return;
   }
   const TrajCtx cx = traj_ctx(ta, traj);
@@ -878,7 +885,10 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) {
     T l = lam[traj];
     if (acc == 0) l = l / T(10) > o.lam_min ? l / T(10) : o.lam_min;
-    if (acc < 0) l = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    if (acc < 0) {
+      if (!(l < o.lam_max)) failed[traj] = 2;  // rejected at the largest damping: a fixed point
+      l = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    }
     lam[traj] = l;
     trials[traj] += ntr;
   }
@@ -981,7 +991,7 @@ __global__ void __launch_bounds__(256)
       const int64_t tr = c0 + k;
       const int seed = sel ? sel[k * P + p] : k;
       const double c = (double)costc[tr];
-      if (seed < 0 || failedc[tr] || !tfinite(c)) continue;
+      if (seed < 0 || failedc[tr] == 1 || !tfinite(c)) continue;
       if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
         best = k;
         best_cost = c;
