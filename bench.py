@@ -48,6 +48,17 @@ def parse():
     return ap.parse_args()
 
 
+def stage1_sources_hash():
+    """SHA-256 of the sources the stage-1 kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2607_11340_amd", "csrc")
+    for name in ("cr_device.h", "cr_ik.hip"):
+        with open(os.path.join(root, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def build_inputs(cr, I, torch):
     spec = I.WORKLOADS[WORKLOAD]
     n, P, S = len(spec["L"]), spec["P"], spec["S"]
@@ -162,7 +173,10 @@ def main():
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+            meas = json.load(f)
+        # counters describe the kernel built from these sources only
+        if meas.get("sources_sha256") == stage1_sources_hash():
+            traffic = meas.get("bytes_per_launch")
     roofline = dict(bound="alu", kernel="k_ik_stage1<3,float>", achieved=round(achieved, 3),
                     peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=traffic, launch_ms=round(stage_avg[0], 4),
