@@ -207,9 +207,10 @@ def main():
 def traj_inputs(name, cr, I, torch, O=None):
     """Seeded inputs of the path-following or trajectory workload (host arrays plus
     device tensors).  Path: smooth reference actuation paths, their FK poses as
-    reference, seeds = reference + N(0, 0.5 mm) per tendon.  Trajectory: uniform
-    start/goal actuations, perturbed straight-line seeds, spheres uniform in the
-    reachable box, rejected within 2 mm of the start or goal backbone."""
+    reference, uniform IK seeds per (seed, waypoint) for the exploration stage
+    (per-waypoint IK, then path assembly).  Trajectory: uniform start/goal
+    actuations, perturbed straight-line seeds, spheres uniform in the reachable
+    box, rejected within 2 mm of the start or goal backbone."""
     spec = I.WORKLOADS[name]
     n, P, S, H, b = len(spec["L"]), spec["P"], spec["S"], spec["H"], spec["b"]
     Tn = H + 1
@@ -222,8 +223,7 @@ def traj_inputs(name, cr, I, torch, O=None):
         uref = I.smooth_actuation_paths(rng, n, b, P, Tn)                    # [P, Tn, n, 3]
         fr = cr.fk(robot, torch.tensor(uref.reshape(P * Tn, -1).T.copy(), device=dev), arc=False)["frames"]
         out["task"] = fr[12 * (n - 1):12 * n].contiguous()                  # [12, Tn*P]
-        seeds = np.clip(uref[:, None] + rng.normal(size=(P, S, Tn, n, 3)) * 5e-4, -b, b)
-        seeds -= seeds.mean(axis=-1, keepdims=True)
+        seeds = I.uniform_actuation(rng, n, b, P * S * Tn).reshape(P, S, Tn, n, 3)
         out["spheres"] = None
     else:
         ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
@@ -254,7 +254,8 @@ def traj_inputs(name, cr, I, torch, O=None):
 def bench_trajectories(args, cr, I, torch):
     d = traj_inputs(args.workload, cr, I, torch)
     spec, robot, P, S, H = d["spec"], d["robot"], d["P"], d["S"], d["H"]
-    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"],
+                   k_seed=spec.get("k_seed", 0))
     weights = cr.Weights(**spec.get("weights", {}))
     ws = torch.empty(cr.traj_workspace_bytes(robot, P, H, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
     out = (torch.empty((3 * robot.n, (H + 1) * P), dtype=torch.float64, device="cuda"),
@@ -285,7 +286,7 @@ def bench_trajectories(args, cr, I, torch):
                 scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
                 config=dict(workload=args.workload, segments=robot.n, problems=P, waypoints=H + 1, seeds=S,
                             spheres=spec.get("M", 0), pts_per_seg=robot.pts_per_seg, k_init=spec["k_init"],
-                            k_final=spec["k_final"], n_final=spec["n_final"]),
+                            k_final=spec["k_final"], n_final=spec["n_final"], k_seed=spec.get("k_seed", 0)),
                 success_rate=round(float((status == cr.SOLVED).mean()), 4),
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                 max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)])
@@ -352,7 +353,8 @@ def bench_uneven(args, cr, I, torch):
     batch, probs, n_sph = uneven_inputs(cr, I, torch, P)
     print(f"bench: uneven batch built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     specs = [I.WORKLOADS[k] for k in ("ik_batched_3seg", "path_4seg", "traj_5seg")]
-    opts = [cr.Opts(n_final=s["n_final"], k_init=s["k_init"], k_final=s["k_final"]) for s in specs]
+    opts = [cr.Opts(n_final=s["n_final"], k_init=s["k_init"], k_final=s["k_final"], k_seed=s.get("k_seed", 0))
+            for s in specs]
     weights = [cr.Weights(), cr.Weights(**specs[1]["weights"]), cr.Weights()]
     ws = torch.empty(cr.batch_workspace_bytes(batch, opts, torch.float32), dtype=torch.uint8, device="cuda")
     dev = tuple(torch.tensor(a if a.size else [0.0], dtype=torch.float64, device="cuda")

@@ -113,6 +113,9 @@ typedef struct {
   int32_t fp64_refine;   /* 1: stage 2 in FP64 when stage 1 runs in FP32 */
   double lambda0, lambda_min, lambda_max;  /* LM damping: start, floor, ceiling */
   double dup_eps;        /* SelectTop near-duplicate radius (infinity norm, rad) */
+  int32_t k_seed;        /* path following: > 0 treats u_seed as per-waypoint IK seeds, runs this
+                            many plain IK iterations per (seed, waypoint) and assembles one path
+                            per seed from the waypoint solutions (Sec. IV-B); 0 = u_seed are paths */
 } cr_opts;
 
 /* ------------------------------------------------------------------------- */

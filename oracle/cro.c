@@ -996,6 +996,70 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
   return st;
 }
 
+/* Success test of one configuration against a pose (Sec. V-B reading): the
+ * assessment of a one-waypoint IK problem. */
+static int ik_ok(const cro_robot* rb, const cro_problem* pb, const double* T, const double* z) {
+  cro_problem one = *pb;
+  one.kind = CRO_IK;
+  one.H = 0;
+  one.task = T;
+  double err[2];
+  return assess(rb, &one, z, err) == CRO_SOLVED;
+}
+
+void cro_path_seeds(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
+                    const double* u_seed, int k, double* z_out) {
+  int n = rb->n_seg, nz = 2 * n, T = pb->H + 1;
+  double* cand = (double*)malloc(sizeof(double) * (size_t)S * T * nz);
+  int* ok = (int*)malloc(sizeof(int) * (size_t)S * T);
+  int* fin = (int*)malloc(sizeof(int) * (size_t)S * T);
+  cro_problem one = *pb;
+  one.kind = CRO_IK;
+  one.H = 0;
+  /* IK at every waypoint from every seed */
+  for (int t = 0; t < T; t++) {
+    one.task = pb->task + 12 * t;
+    for (int s = 0; s < S; s++) {
+      double* z = cand + ((size_t)t * S + s) * nz;
+      cro_u_to_z(rb, u_seed + ((size_t)s * T + t) * 3 * n, z);
+      double lam = o->lambda0;
+      int failed = cro_lm(rb, w, &one, o, z, &lam, k, NULL, NULL);
+      int finite = 1;
+      for (int q = 0; q < nz; q++)
+        if (!isfinite(z[q])) finite = 0;
+      fin[t * S + s] = finite && !failed;
+      ok[t * S + s] = fin[t * S + s] && ik_ok(rb, pb, one.task, z);
+    }
+  }
+  /* assemble one path per seed, nearest neighbour in the infinity norm */
+  for (int s = 0; s < S; s++) {
+    double* zp = z_out + (size_t)s * T * nz;
+    memcpy(zp, cand + (size_t)s * nz, sizeof(double) * nz);
+    for (int t = 1; t < T; t++) {
+      const double* prev = zp + (size_t)(t - 1) * nz;
+      int best = -1;
+      double bd = 0.0;
+      for (int pass = 0; pass < 2 && best < 0; pass++) {
+        for (int j = 0; j < S; j++) {
+          if (pass == 0 ? !ok[t * S + j] : !fin[t * S + j]) continue;
+          const double* zj = cand + ((size_t)t * S + j) * nz;
+          double d = 0.0;
+          for (int q = 0; q < nz; q++) d = fmax(d, fabs(zj[q] - prev[q]));
+          if (best < 0 || d < bd) {
+            best = j;
+            bd = d;
+          }
+        }
+      }
+      const double* src = best >= 0 ? cand + ((size_t)t * S + best) * nz : prev;
+      memcpy(zp + (size_t)t * nz, src, sizeof(double) * nz);
+    }
+  }
+  free(fin);
+  free(ok);
+  free(cand);
+}
+
 int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
               const double* u_seed, double* u_out, double* err_out, int32_t* status, int32_t* best_idx,
               double* best_cost) {
@@ -1009,8 +1073,10 @@ int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, 
   int32_t* failed = (int32_t*)malloc(sizeof(int32_t) * (size_t)S);
 
   /* stage 1: ParallelOptimize over every seed for k_init iterations */
+  if (pb->kind == CRO_PATH && o->k_seed > 0) cro_path_seeds(rb, w, pb, o, S, u_seed, o->k_seed, z);
   for (int s = 0; s < S; s++) {
-    for (int t = 0; t < T; t++) cro_u_to_z(rb, u_seed + (size_t)s * T * 3 * n + 3 * n * t, z + (size_t)s * N + nz * t);
+    if (!(pb->kind == CRO_PATH && o->k_seed > 0))
+      for (int t = 0; t < T; t++) cro_u_to_z(rb, u_seed + (size_t)s * T * 3 * n + 3 * n * t, z + (size_t)s * N + nz * t);
     lam[s] = o->lambda0;
     failed[s] = cro_lm(rb, w, pb, o, z + (size_t)s * N, &lam[s], o->k_init, &cost[s], NULL);
   }

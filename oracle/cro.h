@@ -56,6 +56,7 @@ typedef struct {
 typedef struct {
   int32_t n_final, k_init, k_final, ls_max;
   double lambda0, lambda_min, lambda_max, dup_eps;
+  int32_t k_seed; /* PATH: > 0 builds the path seeds by per-waypoint IK (cro_path_seeds) */
 } cro_opts;
 
 typedef struct {
@@ -107,6 +108,19 @@ int cro_chol_solve(int N, int bw, double* M, double* x);
 /* SelectTop of Algorithm 1: indices of n_final candidates out of S. */
 void cro_select_top(int S, int nz, const double* z, const double* e, const double* pen,
                     const int32_t* failed, int n_final, double dup_eps, int32_t* idx_out);
+
+/* Exploration stage of path following (Sec. IV-B): IK at every reference
+ * waypoint from every seed, then one path per seed assembled from the waypoint
+ * solutions.  u_seed[S][(H+1)*3n] are the IK seeds (seed s, waypoint t);
+ * k iterations of the plain method run per (s, t) against the waypoint's pose
+ * (with the problem's spheres).  Path s starts at the solution of seed s at
+ * waypoint 0; each later waypoint takes, among its S solutions that pass the
+ * success test (1 mm, 1 degree, bounds, no penetration), the one nearest in
+ * the infinity norm over z to the path's previous waypoint (ties: lower seed);
+ * if none passes, the nearest finite one; if none is finite, the previous
+ * waypoint's z again.  z_out[S][(H+1)*2n]. */
+void cro_path_seeds(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
+                    const double* u_seed, int k, double* z_out);
 
 /* Two-stage solve of one problem from S seeds u_seed[S][(H+1)*3n]
  * (Algorithm 1 for IK; the same template for PATH and TRAJ).

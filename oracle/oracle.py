@@ -54,7 +54,7 @@ class _Weights(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("n_final", C.c_int32), ("k_init", C.c_int32), ("k_final", C.c_int32),
                 ("ls_max", C.c_int32), ("lambda0", C.c_double), ("lambda_min", C.c_double),
-                ("lambda_max", C.c_double), ("dup_eps", C.c_double)]
+                ("lambda_max", C.c_double), ("dup_eps", C.c_double), ("k_seed", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -114,10 +114,11 @@ class Opts:
     lambda_min: float = 1e-12
     lambda_max: float = 1e12
     dup_eps: float = 1e-3
+    k_seed: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.n_final, self.k_init, self.k_final, self.ls_max, self.lambda0,
-                     self.lambda_min, self.lambda_max, self.dup_eps)
+                     self.lambda_min, self.lambda_max, self.dup_eps, self.k_seed)
 
 
 _lib = None
@@ -146,6 +147,8 @@ def lib():
         L.cro_chol_solve.restype = C.c_int
         L.cro_select_top.argtypes = [C.c_int, C.c_int, dp, dp, dp, ip, C.c_int, C.c_double, ip]
         L.cro_solve.argtypes = [R, W, P, O, C.c_int, dp, dp, dp, ip, ip, dp]
+        L.cro_path_seeds.argtypes = [R, W, P, O, C.c_int, dp, C.c_int, dp]
+        L.cro_path_seeds.restype = None
         L.cro_solve.restype = C.c_int
         _lib = L
     return _lib
@@ -302,6 +305,19 @@ def select_top(z, e, pen, failed, n_final: int, dup_eps: float = 1e-3):
     lib().cro_select_top(S, z2.shape[1], pz, pe, pp, pf, n_final, dup_eps,
                          out.ctypes.data_as(C.POINTER(C.c_int32)))
     return out
+
+
+def path_seeds(robot: Robot, weights: Weights, prob: Problem, opts: Opts, u_seed, k: int):
+    """Per-waypoint IK and path assembly (cro_path_seeds); u_seed [S, H+1, n, 3]
+    -> z [S, H+1, n, 2]."""
+    u_seed = np.asarray(u_seed, dtype=np.float64)
+    S = u_seed.shape[0]
+    us, pu = _d(u_seed)
+    z = np.empty((S, prob.H + 1, robot.n, 2))
+    rc, wc, oc = robot.c(), weights.c(), opts.c()
+    lib().cro_path_seeds(C.byref(rc), C.byref(wc), C.byref(prob.c), C.byref(oc), S, pu, int(k),
+                         z.ctypes.data_as(C.POINTER(C.c_double)))
+    return z
 
 
 def solve(robot: Robot, weights: Weights, prob: Problem, opts: Opts, u_seed):

@@ -63,7 +63,8 @@ class _Weights(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("n_final", C.c_int32), ("k_init", C.c_int32), ("k_final", C.c_int32),
                 ("ls_max", C.c_int32), ("fp64_refine", C.c_int32), ("lambda0", C.c_double),
-                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("dup_eps", C.c_double)]
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("dup_eps", C.c_double),
+                ("k_seed", C.c_int32)]
 
 
 @dataclass
@@ -121,10 +122,11 @@ class Opts:
     lambda_min: float = 1e-12
     lambda_max: float = 1e12
     dup_eps: float = 1e-3
+    k_seed: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.n_final, self.k_init, self.k_final, self.ls_max, self.fp64_refine,
-                     self.lambda0, self.lambda_min, self.lambda_max, self.dup_eps)
+                     self.lambda0, self.lambda_min, self.lambda_max, self.dup_eps, self.k_seed)
 
 
 def _load():

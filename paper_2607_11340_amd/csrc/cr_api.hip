@@ -147,7 +147,7 @@ cr_status check_dtype(cr_dtype d) {
 cr_status check_opts(const cr_opts* o) {
   if (!o) return fail(CR_EINVAL, "opts is NULL");
   if (o->n_final < 0 || o->n_final > 64) return fail(CR_EINVAL, "n_final=%d not in 0..64", o->n_final);
-  if (o->k_init < 0 || o->k_final < 0) return fail(CR_EINVAL, "negative iteration count");
+  if (o->k_init < 0 || o->k_final < 0 || o->k_seed < 0) return fail(CR_EINVAL, "negative iteration count");
   if (o->ls_max < 1 || o->ls_max > 8) return fail(CR_EINVAL, "ls_max=%d not in 1..8", o->ls_max);
   if (!(o->lambda0 > 0.0) || !(o->lambda_min > 0.0) || !(o->lambda_max >= o->lambda_min))
     return fail(CR_EINVAL, "invalid lambda bounds");

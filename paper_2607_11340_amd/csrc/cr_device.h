@@ -1351,4 +1351,72 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
   }
 }
 
+// True if some backbone point of z lies inside an obstacle sphere inflated by
+// its segment's radius (clearance < 0, margin 0); spheres are FP64, sphere m
+// component c at sph[c * ld + m].  A sphere whose distance to a segment's arc
+// midpoint exceeds L_i / 2 + R + r_i cannot touch the segment.
+template <int NS, typename T>
+CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M, int64_t ld) {
+  T Rp[9], pp[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? T(1) : T(0);
+  pp[0] = pp[1] = pp[2] = T(0);
+  bool hit = false;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const T a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
+    const T Li = rb.L[i], ri = rb.r[i];
+    T xm[3];
+    seg_point(Rp, pp, a, b, Li, s, T(0.5), xm);
+    for (int m = 0; m < M && !hit; ++m) {
+      const T cx = (T)sph[m], cy = (T)sph[ld + m], cz = (T)sph[2 * ld + m], rs = (T)sph[3 * ld + m];
+      const T e0 = xm[0] - cx, e1 = xm[1] - cy, e2 = xm[2] - cz;
+      if (tsqrt(e0 * e0 + e1 * e1 + e2 * e2) - rs - ri - T(0.5) * Li > T(0)) continue;
+      for (int k = 1; k <= rb.K; ++k) {
+        T x[3];
+        seg_point(Rp, pp, a, b, Li, s, T(k) / T(rb.K), x);
+        const T d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
+        if (tsqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - ri < T(0)) hit = true;
+      }
+    }
+    ArcCoef<T> c = arc_coef<T, false>(s);
+    T Ri[9], di[3], q[3], Rn[9];
+    seg_R_d(a, b, Li, c, Ri, di);
+    mv3(Rp, di, q);
+    pp[0] += q[0];
+    pp[1] += q[1];
+    pp[2] += q[2];
+    mm3(Rp, Ri, Rn);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rp[k] = Rn[k];
+  }
+  return hit;
+}
+
+// The success test of a configuration against a target pose Tt (3x4 row-major):
+// position within 1 mm, rotation within 1 degree, every tendon within its bound
+// (1e-6 m), every bending angle within theta_max and no penetration.
+template <int NS, typename T>
+CR_HD bool ik_success(const RobotT<T>& rb, const T* z, const T* Tt, const double* sph, int M, int64_t ld) {
+  T Rc[9], pc[3];
+  fk_tip<NS>(rb, z, Rc, pc);
+  const T dp[3] = {Tt[3] - pc[0], Tt[7] - pc[1], Tt[11] - pc[2]};
+  const T pos = tsqrt(dot3(dp, dp));
+  T Re[9], te[3];
+  relative_pose(Rc, pc, Tt, Re, te);
+  const T v[3] = {T(0.5) * (Re[7] - Re[5]), T(0.5) * (Re[2] - Re[6]), T(0.5) * (Re[3] - Re[1])};
+  const T rot = tatan2(tsqrt(dot3(v, v)), T(0.5) * (Re[0] + Re[4] + Re[8] - T(1)));
+  if (!(pos <= T(1e-3) && rot <= T(3.14159265358979323846 / 180.0))) return false;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    T u[3];
+    ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], u);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (fabs(u[j]) - rb.umax[i] > T(1e-6)) return false;
+    if (tsqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) > rb.theta_max) return false;
+  }
+  return !(M > 0 && penetrates<NS, T>(rb, z, sph, M, ld));
+}
+
 }  // namespace crk

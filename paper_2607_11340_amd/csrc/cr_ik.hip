@@ -262,45 +262,6 @@ __global__ void __launch_bounds__(256)
   failed2[b] = failed ? 1 : 0;
 }
 
-// True if some backbone point of z (FP64) lies inside an obstacle sphere
-// inflated by its segment's radius (clearance < 0, margin 0).  A sphere whose
-// distance to a segment's arc midpoint exceeds L_i / 2 + R + r_i cannot touch it.
-template <int NS>
-__device__ bool penetrates(const RobotT<double>& rb, const double* z, const double* sph, int M, int64_t ld) {
-  double Rp[9], pp[3];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? 1.0 : 0.0;
-  pp[0] = pp[1] = pp[2] = 0.0;
-  bool hit = false;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const double a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
-    double xm[3];
-    seg_point(Rp, pp, a, b, rb.Ld[i], s, 0.5, xm);
-    for (int m = 0; m < M && !hit; ++m) {
-      const double cx = sph[m], cy = sph[ld + m], cz = sph[2 * ld + m], rs = sph[3 * ld + m];
-      const double e0 = xm[0] - cx, e1 = xm[1] - cy, e2 = xm[2] - cz;
-      if (sqrt(e0 * e0 + e1 * e1 + e2 * e2) - rs - rb.rd[i] - 0.5 * rb.Ld[i] > 0.0) continue;
-      for (int k = 1; k <= rb.K; ++k) {
-        double x[3];
-        seg_point(Rp, pp, a, b, rb.Ld[i], s, (double)k / (double)rb.K, x);
-        const double d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
-        if (sqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - rb.rd[i] < 0.0) hit = true;
-      }
-    }
-    ArcCoef<double> c = arc_coef<double, false>(s);
-    double Ri[9], di[3], q[3], Rn[9];
-    seg_R_d(a, b, rb.Ld[i], c, Ri, di);
-    mv3(Rp, di, q);
-    pp[0] += q[0];
-    pp[1] += q[1];
-    pp[2] += q[2];
-    mm3(Rp, Ri, Rn);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rp[k] = Rn[k];
-  }
-  return hit;
-}
 
 // ---------------------------------------------------------------------------
 // Final argmin over candidates and FP64 assessment of the winner.
@@ -367,7 +328,7 @@ __global__ void __launch_bounds__(256)
   }
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if (sa.M > 0 && penetrates<NS>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld)) st |= CR_COLLISION;
+  if (sa.M > 0 && penetrates<NS, double>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld)) st |= CR_COLLISION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
   if (st == 0) st = CR_SOLVED;
   err_out[p] = pos;
@@ -557,7 +518,7 @@ __global__ void __launch_bounds__(256)
   }
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if (pr.M > 0 && penetrates<NS>(rb, z, sph + pr.sph, pr.M, pr.sph_ld)) st |= CR_COLLISION;
+  if (pr.M > 0 && penetrates<NS, double>(rb, z, sph + pr.sph, pr.M, pr.sph_ld)) st |= CR_COLLISION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
   if (st == 0) st = CR_SOLVED;
   err_out[ei] = pos;

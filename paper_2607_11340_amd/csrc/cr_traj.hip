@@ -404,6 +404,93 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
 
 // ---------------------------------------------------------------------------
 
+// Exploration stage of path following (Sec. IV-B): IK at every (seed, waypoint)
+// of stage 1 against that waypoint's reference pose, the plain method for
+// `iters` iterations (with the problem's spheres).  One workgroup per
+// trajectory, one lane per waypoint.  cand has the layout of Z; okf: 2 = passes
+// the success test, 1 = finite, 0 = not finite.
+template <int NS, typename T>
+__global__ void __launch_bounds__(64)
+    k_path_wp_ik(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, TrajArgs<T> ta, const double* __restrict__ useed,
+                 int iters, T lam0, T* __restrict__ cand, int32_t* __restrict__ okf) {
+  constexpr int NZ = 2 * NS;
+  const TrajCtx cx = traj_ctx(ta, blockIdx.x);
+  const int M = cx.pr.M;
+  const double* sp = M > 0 ? ta.sph + cx.pr.sph : nullptr;
+  for (int t = threadIdx.x; t < cx.pr.Tn; t += blockDim.x) {
+    T tt[12];
+    load_pose(ta, cx, t, tt);
+    const double* u = useed + cx.pr.seed + (int64_t)cx.s * cx.pr.Tn + t;
+    T z[NZ];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      u_to_ab((T)u[(3 * i) * cx.pr.seed_ld], (T)u[(3 * i + 1) * cx.pr.seed_ld], (T)u[(3 * i + 2) * cx.pr.seed_ld],
+              rb.r[i], &z[2 * i], &z[2 * i + 1]);
+    T lam = lam0;
+    bool failed = false;
+    int trials = 0;
+    if (M > 0) lm_cfg<NS, T, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, M, 1, cx.pr.sph_ld);
+    else lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
+    bool fin = !failed;
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      fin = fin && tfinite(z[k]);
+      cand[(cx.wp + t) * NZ + k] = z[k];
+    }
+    okf[cx.wp + t] = !fin ? 0 : (ik_success<NS, T>(rb, z, tt, sp, M, cx.pr.sph_ld) ? 2 : 1);
+  }
+}
+
+// Path assembly: path s starts at seed s's waypoint-0 solution; every later
+// waypoint takes, among the problem's S solutions there that pass the success
+// test, the nearest to the path's previous waypoint in the infinity norm over z
+// (ties: lower seed); if none passes, the nearest finite one; if none is finite,
+// the previous waypoint again.  One lane per trajectory.
+template <int NS, typename T>
+__global__ void __launch_bounds__(256)
+    k_path_chain(TrajArgs<T> ta, int64_t nt, const T* __restrict__ cand, const int32_t* __restrict__ okf,
+                 T* __restrict__ Z) {
+  constexpr int NZ = 2 * NS;
+  const int64_t traj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (traj >= nt) return;
+  const TrajCtx cx = traj_ctx(ta, traj);
+  const int Tn = cx.pr.Tn, S = cx.pr.S;
+  T prev[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    prev[k] = cand[cx.wp * NZ + k];
+    Z[cx.wp * NZ + k] = prev[k];
+  }
+  for (int t = 1; t < Tn; ++t) {
+    int best = -1;
+    T bd = T(0);
+    for (int pass = 0; pass < 2 && best < 0; ++pass) {
+      for (int j = 0; j < S; ++j) {
+        const int64_t at = cx.pr.wp0 + (int64_t)j * Tn + t;
+        const int f = okf[at];
+        if (pass == 0 ? f != 2 : f < 1) continue;
+        T d = T(0);
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+          const T e = fabs(cand[at * NZ + k] - prev[k]);
+          d = e > d ? e : d;
+        }
+        if (best < 0 || d < bd) {
+          best = j;
+          bd = d;
+        }
+      }
+    }
+    if (best >= 0) {
+      const int64_t at = cx.pr.wp0 + (int64_t)best * Tn + t;
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) prev[k] = cand[at * NZ + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = prev[k];
+  }
+}
+
 // Stage-1 state from the seeds: one workgroup per trajectory, lane t = waypoint.
 template <int NS, typename T>
 __global__ void __launch_bounds__(256)
@@ -1121,12 +1208,14 @@ struct TrajWs {
   int32_t *chol2, *fail2, *trials2;
   TrajProb* tp;
   SelRow* rows;
+  void* cand;       // path exploration: per-waypoint IK solutions (layout of Z1)
+  int32_t* okf;     // and their success flags
 };
 
 // Workspace of one path / trajectory launch (struct TrajShape): stage-1 state for
 // every seed trajectory, stage-2 state for n_final trajectories per problem, the
 // problem table and the SelectTop rows.
-static size_t traj_ws_layout(int ns, const TrajShape& sh, int nf, cr_dtype dt, char* base, TrajWs* w) {
+static size_t traj_ws_layout(int ns, const TrajShape& sh, int nf, int kseed, cr_dtype dt, char* base, TrajWs* w) {
   const size_t t1 = dt == CR_F64 ? 8 : 4;
   const int NZ = 2 * ns, REC = 3 * NZ * NZ + 2 * NZ;  // struct Rec
   const int64_t n1 = sh.N1, w1 = sh.W1, n2 = sh.P * (nf > 0 ? nf : 1), w2 = sh.TnSum * (nf > 0 ? nf : 1);
@@ -1160,6 +1249,10 @@ static size_t traj_ws_layout(int ns, const TrajShape& sh, int nf, cr_dtype dt, c
   x.trials2 = (int32_t*)take(4 * n2);
   x.tp = (TrajProb*)take(sizeof(TrajProb) * sh.P);
   x.rows = (SelRow*)take(sizeof(SelRow) * sh.P);
+  if (kseed > 0) {
+    x.cand = take(t1 * w1 * NZ);
+    x.okf = (int32_t*)take(4 * w1);
+  }
   if (w) *w = x;
   return off;
 }
@@ -1177,7 +1270,7 @@ TrajShape traj_uniform_shape(int64_t P, int S, int H, int M) {
 }
 
 size_t traj_workspace_bytes(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dt) {
-  return traj_ws_layout(rb.n_seg, sh, o.n_final, dt, nullptr, nullptr);
+  return traj_ws_layout(rb.n_seg, sh, o.n_final, o.k_seed, dt, nullptr, nullptr);
 }
 
 size_t traj_workspace_bytes(const cr_robot& rb, int64_t P, int S, int H, const cr_opts& o, cr_dtype dt) {
@@ -1291,12 +1384,19 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const TrajShape& sh, co
   WeightsT<double> wd = weights_to<double>(w0);
   TrajArgs<T1> ta1{kind, P, 0, sh.Tmax, tp, task, sph};
   const int threads = threads_for(sh.Tmax);
-  hipLaunchKernelGGL((k_traj_init<NS, T1>), dim3((unsigned)n1), dim3(64), 0, st, rbd, ta1, useed, (T1*)ws.Z1);
+  LMOpts<T1> lo1{o.ls_max, (T1)o.lambda_min, (T1)o.lambda_max};
+  if (kind == CR_KIND_PATH && o.k_seed > 0) {
+    hipLaunchKernelGGL((k_path_wp_ik<NS, T1>), dim3((unsigned)n1), dim3(64), 0, st, rb1, w1, lo1, ta1, useed, o.k_seed,
+                       (T1)o.lambda0, (T1*)ws.cand, ws.okf);
+    hipLaunchKernelGGL((k_path_chain<NS, T1>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, ta1, n1,
+                       (const T1*)ws.cand, (const int32_t*)ws.okf, (T1*)ws.Z1);
+  } else {
+    hipLaunchKernelGGL((k_traj_init<NS, T1>), dim3((unsigned)n1), dim3(64), 0, st, rbd, ta1, useed, (T1*)ws.Z1);
+  }
   hipLaunchKernelGGL((k_fill<T1>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, (T1*)ws.lam1,
                      (T1)o.lambda0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.fail1, 0);
   hipLaunchKernelGGL((k_fill<int32_t>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, n1, ws.trials1, 0);
-  LMOpts<T1> lo1{o.ls_max, (T1)o.lambda_min, (T1)o.lambda_max};
   cr_status rc = traj_stage<NS, T1>(rb1, w1, ta1, sh.Mmax, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1,
                                     (T1*)ws.lam1, (T1*)ws.c01, (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
   if (rc != CR_OK) return rc;
@@ -1342,7 +1442,7 @@ cr_status launch_traj_group(int kind, const cr_robot& rb, const TrajShape& sh, c
                             double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
                             cr_dtype dtype, hipStream_t st) {
   TrajWs ws;
-  traj_ws_layout(rb.n_seg, sh, o.n_final, dtype, (char*)wsmem, &ws);
+  traj_ws_layout(rb.n_seg, sh, o.n_final, o.k_seed, dtype, (char*)wsmem, &ws);
 #define CR_TRAJ_CASE(N)                                                                                              \
   case N:                                                                                                            \
     if (!traj_lds_ok<N>(sh.Tmax, sh.Mmax)) return fail(CR_EINVAL, "horizon x spheres exceed 64 KiB of LDS");         \
@@ -1365,7 +1465,7 @@ cr_status launch_traj_group(int kind, const cr_robot& rb, const TrajShape& sh, c
 
 TrajProb* traj_table_slot(const cr_robot& rb, const TrajShape& sh, const cr_opts& o, cr_dtype dtype, void* wsmem) {
   TrajWs ws;
-  traj_ws_layout(rb.n_seg, sh, o.n_final, dtype, (char*)wsmem, &ws);
+  traj_ws_layout(rb.n_seg, sh, o.n_final, o.k_seed, dtype, (char*)wsmem, &ws);
   return ws.tp;
 }
 

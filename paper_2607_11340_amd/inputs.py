@@ -34,7 +34,7 @@ WORKLOADS = {
         k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 2),
     "path_4seg": dict(
         kind="path", L=[0.08] * 4, r=[0.008] * 4, b=0.006, P=512, H=63, S=32,
-        k_init=100, k_final=20, n_final=4, K=10, dtype="f32", seed=BASE_SEED + 3,
+        k_init=100, k_final=20, n_final=4, K=10, dtype="f32", seed=BASE_SEED + 3, k_seed=30,
         weights=dict(w_vel=1e-2, w_acc=1e-2)),
     "traj_5seg": dict(
         kind="traj", L=[0.06] * 5, r=[0.006] * 5, b=0.006, P=256, H=31, S=64, M=64,
@@ -53,9 +53,9 @@ def uneven_problems(rng: np.random.Generator, P: int, spec: dict = None) -> list
     ('ik' | 'path' | 'traj'), n, H (0 for IK), S, M and the actuations the caller
     turns into tasks (IK: u_true [n,3]; PATH: u_ref [H+1,n,3]; TRAJ: u_start,
     u_goal [n,3]), seeds [S, H+1, n, 3] and 4*M candidate spheres [4M, 4] (the
-    caller keeps the first M that clear its configurations).  Path seeds are the
-    reference plus N(0, 0.5 mm) per tendon; trajectory seeds are perturbed
-    straight lines."""
+    caller keeps the first M that clear its configurations).  Path seeds are
+    uniform IK seeds per (seed, waypoint) for the exploration stage; trajectory
+    seeds are perturbed straight lines."""
     spec = spec or UNEVEN
     b = spec["b"]
     kinds = rng.choice(3, size=P, p=list(spec["frac"]))
@@ -73,8 +73,7 @@ def uneven_problems(rng: np.random.Generator, P: int, spec: dict = None) -> list
             d["seeds"] = uniform_actuation(rng, n, b, S).reshape(S, 1, n, 3)
         elif kind == "path":
             d["u_ref"] = smooth_actuation_paths(rng, n, b, 1, Tn)[0]
-            s = np.clip(d["u_ref"][None] + rng.normal(size=(S, Tn, n, 3)) * 5e-4, -b, b)
-            d["seeds"] = s - s.mean(axis=-1, keepdims=True)
+            d["seeds"] = uniform_actuation(rng, n, b, S * Tn).reshape(S, Tn, n, 3)
         else:
             ends = uniform_actuation(rng, n, b, 2)
             d["u_start"], d["u_goal"] = ends[0], ends[1]

@@ -193,3 +193,56 @@ def test_traj_two_stage_with_obstacles(oracle, cr):
         d = np.linalg.norm(pts.reshape(-1, 1, 3) - sph[p, None, :, :3], axis=2) - sph[p, None, :, 3] - 0.006
         assert d.min() >= 0.0
         assert np.abs(u[p]).max() <= b + 1e-6
+
+
+@pytest.mark.parametrize("k_init", [0, 2])
+def test_path_exploration_stage_fp64_matches_oracle(oracle, cr, k_init):
+    """Path following seeded by per-waypoint IK (Sec. IV-B): uniform IK seeds per
+    (seed, waypoint), 6 plain IK iterations each with spheres, paths assembled by
+    nearest successful solution, then k_init LM iterations over whole paths.  FP64:
+    answers, status and errors equal the oracle's."""
+    print(f"path exploration fp64 k_init={k_init}", flush=True)
+    rng = np.random.default_rng(330 + k_init)
+    n, H, P, S, M, K = 3, 7, 4, 5, 3, 4
+    L, r, b = [0.10, 0.08, 0.06], [0.010, 0.008, 0.006], 0.008
+    ro = oracle.Robot(L=L, r=r, u_max=[b] * n, pts_per_seg=K)
+    uref = I.smooth_actuation_paths(rng, n, b, P, H + 1)
+    _, fr = oracle.fk(ro, uref)
+    seeds = I.uniform_actuation(rng, n, b, P * S * (H + 1)).reshape(P, S, H + 1, n, 3)
+    sph = np.zeros((P, M, 4))
+    for p in range(P):
+        _, _, pts = oracle.fk(ro, uref[p], points=True)
+        for m in range(M):
+            t, i, k = rng.integers(0, H + 1), rng.integers(0, n), rng.integers(0, K)
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            rad = rng.uniform(0.003, 0.008)
+            sph[p, m, :3] = pts[t, i, k] + d * (rad + r[i] + rng.uniform(1e-3, 4e-3))
+            sph[p, m, 3] = rad
+    W = dict(w_vel=1e-2, w_acc=1e-2)
+    c = dict(kind="path", n=n, L=L, r=r, b=b, K=K, H=H, P=P, S=S, M=M, ro=ro, W=W, task=fr[:, :, -1], seeds=seeds,
+             sph=sph)
+    u, err, st = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=k_init, k_final=0, k_seed=6), "f64")
+    for p in range(P):
+        pb = oracle.Problem("path", fr[p, :, -1], H=H, spheres=sph[p])
+        ref = oracle.solve(ro, oracle.Weights(**W), pb, oracle.Opts(n_final=0, k_init=k_init, k_final=0, k_seed=6),
+                           seeds[p])
+        assert st[p] == ref["status"], (p, st[p], ref["status"])
+        assert np.abs(u[p] - ref["u"]).max() <= 1e-9 * b, (p, np.abs(u[p] - ref["u"]).max())
+
+
+def test_path_exploration_two_stage_quality(oracle, cr):
+    """The path workload's shape seeded the paper's way: 32 uniform IK seeds per
+    waypoint, 30 FP32 IK iterations, assembled paths, then 100 + 20 iterations."""
+    print("path exploration two-stage quality", flush=True)
+    spec = I.WORKLOADS["path_4seg"]
+    rng = I.rng_for("path_4seg", 2)
+    n, H, P, S = 4, spec["H"], 16, 32
+    ro = oracle.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n)
+    uref = I.smooth_actuation_paths(rng, n, spec["b"], P, H + 1)
+    _, fr = oracle.fk(ro, uref)
+    seeds = I.uniform_actuation(rng, n, spec["b"], P * S * (H + 1)).reshape(P, S, H + 1, n, 3)
+    c = dict(kind="path", n=n, L=spec["L"], r=spec["r"], b=spec["b"], K=10, H=H, P=P, S=S, M=0, ro=ro,
+             W=spec["weights"], task=fr[:, :, -1], seeds=seeds, sph=None)
+    u, err, st = gpu_solve(cr, c, cr.Opts(n_final=4, k_init=spec["k_init"], k_final=spec["k_final"], k_seed=30), "f32")
+    assert (st == cr.SOLVED).mean() >= 0.9, (st, err)
