@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tally-seeds", type=int, default=256)
+    ap.add_argument("--baseline-targets", type=int, default=16,
+                    help="targets timed with the plain per-problem FP32 solve (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (HBM counter calibration)")
     ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -72,6 +74,70 @@ def build_inputs(cr, I, torch):
     T = frames[12 * (n - 1):12 * n].contiguous()
     useed = torch.tensor(seeds.reshape(P * S, -1).T.copy(), device=dev)
     return spec, robot, u_true, seeds, T, useed
+
+
+def baseline_rate(cr, torch, robot, T, useed, spec, opts, weights, args, fused_rate):
+    """The plain per-problem FP32 GPU solve (cr_baseline_solve_ik) on the first
+    targets of the same workload: problems run one after another, so its rate on
+    a prefix is its rate on the batch."""
+    if args.baseline_targets <= 0:
+        return None
+    P, S = spec["P"], spec["S"]
+    p = min(args.baseline_targets, P)
+    Tp = T[:, :p].contiguous()
+    up = useed[:, :p * S].contiguous()
+    cr.baseline_solve_ik(robot, Tp, up, weights, opts)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, _, st = cr.baseline_solve_ik(robot, Tp, up, weights, opts)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rate = p / (ms * 1e-3)
+    return dict(value=round(rate, 2), unit="IK solves/s", targets=p, ms=round(ms, 2),
+                success_rate=round(float((st.cpu().numpy() == cr.SOLVED).mean()), 4),
+                speedup_of_fused=round(fused_rate / rate, 1),
+                kind="same Algorithm 1 and budgets, FP32, one problem at a time, separate kernels per step, "
+                     "forward-mode Jacobian")
+
+
+def fk_grad_rate(cr, I, torch, args):
+    """FK + cost + adjoint gradient evaluations per second on the path workload's
+    shape (512 paths x 32 seeds x 64 waypoints = 1,048,576 waypoint configurations
+    per call), forward and backward through the torch.autograd.Function, FP32."""
+    spec = I.WORKLOADS["path_4seg"]
+    n, P, S, H, b = len(spec["L"]), spec["P"], spec["S"], spec["H"], spec["b"]
+    Tn = H + 1
+    rng = I.rng_for("path_4seg", 7)
+    robot = cr.Robot(L=spec["L"], r=spec["r"], u_max=[b] * n)
+    uref = I.smooth_actuation_paths(rng, n, b, P, Tn)
+    dev = torch.device("cuda:0")
+    fr = cr.fk(robot, torch.tensor(uref.reshape(P * Tn, -1).T.copy(), device=dev), arc=False)["frames"]
+    task = fr[12 * (n - 1):12 * n].float().contiguous()
+    u = uref[:, None] + rng.normal(size=(P, S, Tn, n, 3)) * 5e-4
+    ut = torch.tensor(u.reshape(P * S * Tn, -1).T.copy(), device=dev, dtype=torch.float32)
+    pb = cr.CostProblem(robot, "path", P, S, H, task, cr.Weights(**spec["weights"]))
+    x = ut.clone().requires_grad_(True)
+
+    def once():
+        x.grad = None
+        cr.CostGrad.apply(x, pb).sum().backward()
+
+    for _ in range(2):
+        once()
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    evals = P * S * Tn
+    return dict(value=round(evals / (ms * 1e-3), 1), unit="FK+grad evals/s", ms_per_call=round(ms, 4),
+                workload="path_4seg shape: 512 x 32 x 64 waypoint configurations, forward + backward via CostGrad, f32")
 
 
 def cpu_baseline(spec, T_host, seeds, budget_s):
@@ -184,6 +250,9 @@ def main():
                     flops_per_normal_eq=tally[6], flops_per_cost_eval=tally[7],
                     trials_per_seed=round(tally[5], 2), tally_sample_seeds=len(pick))
 
+    fkg = fk_grad_rate(cr, I, torch, args)
+    b0 = baseline_rate(cr, torch, robot, T, useed, spec, opts, weights, args, P / (ms_per_step * 1e-3))
+
     base = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
@@ -200,7 +269,7 @@ def main():
         success_rate=round(success, 4), max_pos_err_solved_m=float(np.nanmax(np.where(status == cr.SOLVED, err[0], 0))),
         stage_ms=dict(stage1=round(stage_avg[0], 4), select=round(stage_avg[1], 4), stage2=round(stage_avg[2], 4),
                       finalize=round(stage_avg[3], 4)),
-        roofline=roofline, cpu_baseline=base)
+        fk_grad=fkg, plain_gpu_baseline=b0, roofline=roofline, cpu_baseline=base)
     print(json.dumps(line), flush=True)
 
 

@@ -279,6 +279,19 @@ cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const v
                         const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
                         int32_t* idx_out, cr_dtype dtype, hipStream_t stream);
 
+/* Comparison baseline: the plain per-problem FP32 IK solve the fused solver is
+ * measured against.  The same Algorithm 1, iteration counts and LM rules as
+ * cr_solve_ik, FP32 throughout (stage 2 included), run one problem after another
+ * with a separate kernel per step: residuals and Jacobian by forward-mode dual
+ * numbers (no adjoint), normal equations, damped Cholesky step, one kernel per
+ * line-search trial and one per accept test, SelectTop, argmin; every
+ * intermediate passes through HBM; no graph.  Arguments as cr_solve_ik (no
+ * spheres, dtype fixed to FP32); ws at least S * (3n + 2)(2n + 6) * 4 + 64 KiB
+ * bytes is always enough, or NULL/0 to let the library allocate. */
+cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_target, int32_t S,
+                               const void* u_seed, const cr_weights* weights, const cr_opts* opts, void* u_out,
+                               void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Instrumentation (benchmarks).                                               */
 /* ------------------------------------------------------------------------- */

@@ -92,6 +92,11 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
                       void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, cr_dtype dtype,
                       int32_t flags, hipStream_t stream);
 
+size_t b0_workspace_bytes(const cr_robot& rb, int S, const cr_opts& o);
+cr_status launch_b0_ik(const cr_robot& rb, int64_t P, const double* T, int S, const double* useed,
+                       const cr_weights& w, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
+                       void* wsmem, hipStream_t st);
+
 // Totals of a path / trajectory launch: problems, stage-1 trajectories and
 // waypoint configurations, waypoints summed over problems, largest horizon + 1,
 // sphere count and seed count.
