@@ -278,8 +278,10 @@ def traj_inputs(name, cr, I, torch, O=None):
     device tensors).  Path: smooth reference actuation paths, their FK poses as
     reference, uniform IK seeds per (seed, waypoint) for the exploration stage
     (per-waypoint IK, then path assembly).  Trajectory: uniform start/goal
-    actuations, perturbed straight-line seeds, spheres uniform in the reachable
-    box, rejected within 2 mm of the start or goal backbone."""
+    actuations with tip distance >= 0.1 of the robot length, perturbed
+    straight-line seeds, spheres with centres uniform in the bounding box of the
+    tips of 4096 uniform actuations, radii U[5, 20] mm, rejected if they come
+    within 1 mm of the start or goal backbone."""
     spec = I.WORKLOADS[name]
     n, P, S, H, b = len(spec["L"]), spec["P"], spec["S"], spec["H"], spec["b"]
     Tn = H + 1
@@ -295,7 +297,22 @@ def traj_inputs(name, cr, I, torch, O=None):
         seeds = I.uniform_actuation(rng, n, b, P * S * Tn).reshape(P, S, Tn, n, 3)
         out["spheres"] = None
     else:
-        ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
+        # start / goal pairs whose tips are at least 0.1 of the robot length apart
+        reach = float(sum(spec["L"]))
+        ends = np.zeros((P, 2, n, 3))
+        filled = 0
+        while filled < P:
+            cand = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
+            fr = cr.fk(robot, torch.tensor(cand.reshape(2 * P, -1).T.copy(), device=dev), arc=False)["frames"]
+            tips = fr[12 * (n - 1):12 * n].cpu().numpy().T.reshape(P, 2, 3, 4)[:, :, :, 3]
+            keep = cand[np.linalg.norm(tips[:, 0] - tips[:, 1], axis=1) >= 0.1 * reach]
+            take = min(len(keep), P - filled)
+            ends[filled:filled + take] = keep[:take]
+            filled += take
+        samp = I.uniform_actuation(rng, n, b, 4096)
+        fr = cr.fk(robot, torch.tensor(samp.reshape(4096, -1).T.copy(), device=dev), arc=False)["frames"]
+        tips = fr[12 * (n - 1):12 * n].cpu().numpy().T.reshape(4096, 3, 4)[:, :, 3]
+        lo, hi = tips.min(axis=0), tips.max(axis=0)
         seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, Tn, b) for p in range(P)])
         out["task"] = torch.tensor(np.concatenate([ends[:, 0].reshape(P, -1), ends[:, 1].reshape(P, -1)], 1).T.copy(),
                                    device=dev)
@@ -307,9 +324,9 @@ def traj_inputs(name, cr, I, torch, O=None):
         for p in range(P):
             m = 0
             while m < M:
-                cand = I.spheres(rng, 2 * M, [-0.2, -0.2, 0.0], [0.2, 0.2, 0.3], 0.005, 0.02)
+                cand = I.spheres(rng, 2 * M, lo, hi, 0.005, 0.02)
                 for s in cand:
-                    if m < M and (np.linalg.norm(pts[p] - s[:3], axis=1) - s[3] - body).min() > 2e-3:
+                    if m < M and (np.linalg.norm(pts[p] - s[:3], axis=1) - s[3] - body).min() > 1e-3:
                         sph[p, m] = s
                         m += 1
         out["spheres"] = (torch.tensor(np.ascontiguousarray(sph.reshape(P * M, 4).T), device=dev), True, M)
@@ -359,7 +376,42 @@ def bench_trajectories(args, cr, I, torch):
                 success_rate=round(float((status == cr.SOLVED).mean()), 4),
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                 max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)])
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def traj_cpu_baseline(d, spec, weights, opts, budget_s):
+    """The FP64 CPU oracle on whole problems of the same workload (path: all 32
+    seeds; trajectory: the first 4 of 64 seeds, the per-problem time scaled by
+    64 / 4, since stage 1 costs the same per seed and dominates)."""
+    from oracle import oracle as O
+    n, H, S = d["n"], d["H"], d["S"]
+    rb = O.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n, pts_per_seg=spec["K"])
+    W = O.Weights(**{k: getattr(weights, k) for k in ("w_pos", "w_rot", "rho_lim", "rho_curv", "rho_coll", "margin",
+                                                         "rho_eq", "w_len", "w_vel", "w_acc", "v_max", "a_max", "dt")})
+    oo = O.Opts(n_final=opts.n_final, k_init=opts.k_init, k_final=opts.k_final, k_seed=opts.k_seed)
+    s_used = S if spec["kind"] == "path" else 4
+    done, t0 = 0, time.perf_counter()
+    task_host = d["task"].cpu().numpy()
+    while True:
+        p = done
+        if spec["kind"] == "path":
+            T = task_host[:, p * (H + 1):(p + 1) * (H + 1)].T.reshape(H + 1, 3, 4)
+            pb = O.Problem("path", T, H=H)
+        else:
+            pb = O.Problem("traj", (d["ends"][p, 0], d["ends"][p, 1]), H=H, spheres=d["sph_host"][p])
+        O.solve(rb, W, pb, oo, d["seeds"][p, :s_used])
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or done >= d["P"]:
+            break
+    scale = S / s_used
+    return dict(value=round(done / (el * scale), 5), unit="paths/s" if spec["kind"] == "path" else "trajectories/s",
+                cores=1, kind="oracle",
+                sample=f"{done} problem(s) of the workload, {s_used} of {S} seeds each, full iteration budget, single "
+                       f"thread, {el:.1f} s" + (f"; time per problem scaled by {S}/{s_used}" if scale != 1 else ""))
 
 
 def uneven_inputs(cr, I, torch, P):
