@@ -1108,11 +1108,11 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 }
 
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
-// tip position and its Jacobian.  Tt may be NULL (no pose rows).  TC is the
+// tip position and its Jacobian.  Pose rows against Tt only if pose.  TC is the
 // chain type (FP64 when spheres are present, as in config_forward).
 template <int NS, typename T, typename TC, typename TS = T>
 CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
-                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[2 * NS]) {
+                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[2 * NS], bool pose = true) {
   constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
 #pragma unroll
   for (int k = 0; k < NP; ++k) Hp[k] = T(0);
@@ -1281,7 +1281,7 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   ptip[0] = pt[0];
   ptip[1] = pt[1];
   ptip[2] = pt[2];
-  if (Tt) cost += pose_rows<NZ>(w, Rt, pt, W, dp, Tt, Hp, g);
+  if (pose) cost += pose_rows<NZ>(w, Rt, pt, W, dp, Tt, Hp, g);
   bounds_normal_eq<NS, NZ>(rb, w, z, 0, Hp, g, cost);
   return cost;
 }

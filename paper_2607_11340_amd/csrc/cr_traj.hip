@@ -535,9 +535,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int k = 0; k < NZ; ++k) z[k] = Z[(cx.wp + t) * NZ + k];
     T Tt[12];
-    if (ta.kind == CR_KIND_PATH) load_pose(ta, cx, t, Tt);
-    const T* tp = ta.kind == CR_KIND_PATH ? Tt : nullptr;
-    cst = local_normal_eq<NS, T, T>(rb, w, z, s_sph, M, 4, 1, tp, Hp, g, ptip, Jp);
+    if (ta.kind == CR_KIND_PATH) {
+      load_pose(ta, cx, t, Tt);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) Tt[k] = T(0);
+    }
+    cst = local_normal_eq<NS, T, T>(rb, w, z, s_sph, M, 4, 1, Tt, Hp, g, ptip, Jp, ta.kind == CR_KIND_PATH);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T u[3];
@@ -554,11 +558,14 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   if (act) {
-    T Bm[NZ][NZ], Cm[NZ][NZ];
+    // The smoothness couplings of H_{t,t-1} and H_{t,t-2} act on each segment's
+    // own lifts, so they are 2x2 symmetric blocks on the diagonal: (aa, ab, bb)
+    // per segment.  The path-length coupling is added when the record is written.
+    T Bs[NS][3], Cs[NS][3];
 #pragma unroll
-    for (int a = 0; a < NZ; ++a)
+    for (int i = 0; i < NS; ++i)
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) Bm[a][b] = Cm[a][b] = T(0);
+      for (int k = 0; k < 3; ++k) Bs[i][k] = Cs[i][k] = T(0);
     const T idt = T(1) / w.dt, idt2 = idt * idt;
     // tendon velocity / acceleration smoothness and their hinges (linear in the lifts)
 #pragma unroll
@@ -577,11 +584,10 @@ __global__ void __launch_bounds__(256)
           Hp[tri(cb, ca)] += c1 * c1 * o01;
           Hp[tri(cb, cb)] += c1 * c1 * o11;
         };
-        auto add_off = [&](T (*X)[NZ], T c1c2) {  // coupling block entry c1 c2 lift^T lift
-          X[ca][ca] += c1c2 * o00;
-          X[ca][cb] += c1c2 * o01;
-          X[cb][ca] += c1c2 * o01;
-          X[cb][cb] += c1c2 * o11;
+        auto add_off = [&](T* X, T c1c2) {  // coupling block entry c1 c2 lift^T lift
+          X[0] += c1c2 * o00;
+          X[1] += c1c2 * o01;
+          X[2] += c1c2 * o11;
         };
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -592,14 +598,14 @@ __global__ void __launch_bounds__(256)
             const T cs = (k == 0 ? idt : -idt) * w.sq_vel;
             if (k == 0) cst += T(0.5) * rr * rr;
             add_self(cs, rr);
-            if (k == 0) add_off(Bm, cs * (-idt * w.sq_vel));
+            if (k == 0) add_off(Bs[i], cs * (-idt * w.sq_vel));
             if (w.has_vmax && fabs(v) > w.v_max) {
               const T sg = v < T(0) ? -w.sq_lim : w.sq_lim;
               const T hr = w.sq_lim * (fabs(v) - w.v_max);
               const T hs = sg * (k == 0 ? idt : -idt);
               if (k == 0) cst += T(0.5) * hr * hr;
               add_self(hs, hr);
-              if (k == 0) add_off(Bm, hs * (sg * -idt));
+              if (k == 0) add_off(Bs[i], hs * (sg * -idt));
             }
           }
         }
@@ -613,16 +619,16 @@ __global__ void __launch_bounds__(256)
             const T cs = cf[k] * idt2 * w.sq_acc;
             if (k == 0) cst += T(0.5) * rr * rr;
             add_self(cs, rr);
-            if (k <= 1) add_off(Bm, cs * cf[k + 1] * idt2 * w.sq_acc);
-            if (k == 0) add_off(Cm, cs * cf[2] * idt2 * w.sq_acc);
+            if (k <= 1) add_off(Bs[i], cs * cf[k + 1] * idt2 * w.sq_acc);
+            if (k == 0) add_off(Cs[i], cs * cf[2] * idt2 * w.sq_acc);
             if (w.has_amax && fabs(a) > w.a_max) {
               const T sg = a < T(0) ? -w.sq_lim : w.sq_lim;
               const T hr = w.sq_lim * (fabs(a) - w.a_max);
               const T hs = sg * cf[k] * idt2;
               if (k == 0) cst += T(0.5) * hr * hr;
               add_self(hs, hr);
-              if (k <= 1) add_off(Bm, hs * sg * cf[k + 1] * idt2);
-              if (k == 0) add_off(Cm, hs * sg * cf[2] * idt2);
+              if (k <= 1) add_off(Bs[i], hs * sg * cf[k + 1] * idt2);
+              if (k == 0) add_off(Cs[i], hs * sg * cf[2] * idt2);
             }
           }
         }
@@ -640,10 +646,6 @@ __global__ void __launch_bounds__(256)
           cst += T(0.5) * rr * rr;
           gr += w.sq_len * rr;
           sw += sl2;
-#pragma unroll
-          for (int a = 0; a < NZ; ++a)
-#pragma unroll
-            for (int b = 0; b < NZ; ++b) Bm[a][b] -= sl2 * Jp[c][a] * s_jp[((t - 1) * 3 + c) * NZ + b];
         }
         if (t + 1 <= H) {
           const T rr = w.sq_len * (s_p[3 * (t + 1) + c] - s_p[3 * t + c]);
@@ -674,14 +676,28 @@ __global__ void __launch_bounds__(256)
       }
     }
     T* rec = blk + (cx.wp + t) * R::SIZE;
+    const bool len = ta.kind == CR_KIND_TRAJ && t >= 1;
+    const T sl2 = w.sq_len * w.sq_len;
 #pragma unroll
-    for (int b = 0; b < NZ; ++b)
+    for (int b = 0; b < NZ; ++b) {
+      T jq[3] = {T(0), T(0), T(0)};  // column b of J_p at t - 1
+      if (len) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) jq[q] = s_jp[((t - 1) * 3 + q) * NZ + b];
+      }
 #pragma unroll
       for (int a = 0; a < NZ; ++a) {
+        T bv = T(0), cv = T(0);
+        if (a / 2 == b / 2) {
+          bv = Bs[a / 2][(a & 1) + (b & 1)];
+          cv = Cs[a / 2][(a & 1) + (b & 1)];
+        }
+        if (len) bv -= sl2 * (Jp[0][a] * jq[0] + Jp[1][a] * jq[1] + Jp[2][a] * jq[2]);
         rec[R::OH + b * NZ + a] = a >= b ? Hp[tri(a, b)] : Hp[tri(b, a)];
-        rec[R::OB + b * NZ + a] = Bm[a][b];
-        rec[R::OC + b * NZ + a] = Cm[a][b];
+        rec[R::OB + b * NZ + a] = bv;
+        rec[R::OC + b * NZ + a] = cv;
       }
+    }
 #pragma unroll
     for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
   }
