@@ -303,7 +303,7 @@ def _solve_traj(kind: str, robot: Robot, task: torch.Tensor, u_seed: torch.Tenso
     opts = opts or Opts(n_final=4, k_init=100, k_final=20)
     n, T = robot.n, H + 1
     P = task.shape[1] // (T if kind == "path" else 1)
-    S = u_seed.shape[1] // max(T * P, 1)
+    S = max(u_seed.shape[1] // max(T * P, 1), 1)
     if kind == "path":
         _need(task, (12, T * P), torch.float64, "T_ref")
     else:
