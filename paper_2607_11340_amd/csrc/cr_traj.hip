@@ -155,9 +155,10 @@ __device__ __forceinline__ T point_sphere_cost(const T* x, const T* sm, T reach,
 }
 
 // Lane t (waypoints within the horizon): base frame and arc midpoint of every
-// segment of waypoint t, into the list's frame area.
+// segment of waypoint t, into the list's frame area; the tip frame into Rt, pt.
 template <int NS, typename T>
-__device__ __forceinline__ void coll_frames(const RobotT<T>& rb, const T* z, int t, const CollList<T>& cl) {
+__device__ __forceinline__ void coll_frames(const RobotT<T>& rb, const T* z, int t, const CollList<T>& cl, T* Rt,
+                                            T* pt) {
   T Rc[9], pc[3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
@@ -185,6 +186,11 @@ __device__ __forceinline__ void coll_frames(const RobotT<T>& rb, const T* z, int
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
   }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rt[k] = Rc[k];
+  pt[0] = pc[0];
+  pt[1] = pc[1];
+  pt[2] = pc[2];
 }
 
 template <int NS, typename T>
@@ -221,29 +227,45 @@ __device__ __forceinline__ T coll_enqueue(const RobotT<T>& rb, const WeightsT<T>
     const bool has = m < M;
     const T* sm = s_sph + 4 * (has ? m : 0);
     const T c0 = sm[0], c1 = sm[1], c2 = sm[2], rs = sm[3];
-    for (int pr = wv; pr < npair; pr += nwv) {
-      const int t = pr / NS, i = pr - t * NS;
-      T Li, ri;
-      seg_consts<NS>(rb, i, Li, ri);
-      const T* fr = cl.fr + pr * CollList<T>::FR;
-      const T e0 = fr[14] - c0, e1 = fr[15] - c1, e2 = fr[16] - c2;
-      const T rq = (rs + ri + w.margin + T(0.5) * Li) * T(1.0001);
-      const bool hit = has && e0 * e0 + e1 * e1 + e2 * e2 < rq * rq;
-      const unsigned long long mask = __ballot(hit);
-      if (mask == 0ull) continue;
-      const int rank =
-          (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-      const int slot = used + rank;
-      used += __popcll(mask);
-      if (!hit) continue;
-      if (slot < capw) {
-        wl[slot] = (t << 12) | (i << 9) | m;
-      } else {
-        const T a = fr[12], b = fr[13];
-        for (int k = 1; k <= K; ++k) {
-          T x[3];
-          seg_point(fr, fr + 9, a, b, Li, a * a + b * b, T(k) * invK, x);
-          cost += point_sphere_cost(x, sm, rs + ri + w.margin, w.sq_coll);
+    // four (waypoint, segment) pairs per round: their midpoint loads are issued
+    // together before the ballots serialise the placement
+    for (int pr0 = wv; pr0 < npair; pr0 += 4 * nwv) {
+      bool hit[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int pr = pr0 + j * nwv;
+        const int prc = pr < npair ? pr : npair - 1;
+        const int i = prc % NS;
+        T Li, ri;
+        seg_consts<NS>(rb, i, Li, ri);
+        const T* fr = cl.fr + prc * CollList<T>::FR;
+        const T e0 = fr[14] - c0, e1 = fr[15] - c1, e2 = fr[16] - c2;
+        const T rq = (rs + ri + w.margin + T(0.5) * Li) * T(1.0001);
+        hit[j] = has && pr < npair && e0 * e0 + e1 * e1 + e2 * e2 < rq * rq;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned long long mask = __ballot(hit[j]);
+        if (mask == 0ull) continue;
+        const int pr = pr0 + j * nwv;
+        const int t = pr / NS, i = pr - t * NS;
+        const int rank =
+            (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        const int slot = used + rank;
+        used += __popcll(mask);
+        if (!hit[j]) continue;
+        if (slot < capw) {
+          wl[slot] = (t << 12) | (i << 9) | m;
+        } else {
+          T Li, ri;
+          seg_consts<NS>(rb, i, Li, ri);
+          const T* fr = cl.fr + pr * CollList<T>::FR;
+          const T a = fr[12], b = fr[13];
+          for (int k = 1; k <= K; ++k) {
+            T x[3];
+            seg_point(fr, fr + 9, a, b, Li, a * a + b * b, T(k) * invK, x);
+            cost += point_sphere_cost(x, sm, rs + ri + w.margin, w.sq_coll);
+          }
         }
       }
     }
@@ -314,29 +336,36 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
   const bool act = t <= H;
   const bool listed = cl.cap > 0 && M > 0;
   T cst = T(0), cpen = T(0);
+  T Rt[9], pt[3];  // tip frame of waypoint t
   if (listed) {
-    if (act) coll_frames<NS>(rb, z, t, cl);
+    if (act) coll_frames<NS>(rb, z, t, cl, Rt, pt);
     __syncthreads();
     cpen = coll_enqueue<NS>(rb, w, s_sph, M, H + 1, cl);
     cst = cpen;
   }
   if (act) {
-    Fwd<NS, T> f;
+    // bound hinges in the working precision, as in the normal equations
     if (listed) {
-      cst += config_forward<NS, T, false>(rb, w, z, s_sph, 0, 4, 1, f);
+      cst += bounds_cost<NS>(rb, w, z);
+    } else if (M == 0) {
+      fk_tip<NS>(rb, z, Rt, pt);
+      cst = bounds_cost<NS>(rb, w, z);
     } else {
-      cst = config_forward<NS, T, false>(rb, w, z, s_sph, M, 4, 1, f);
-      if (pen && M > 0) {
-        WeightsT<T> wc = w;
-        wc.sq_lim = wc.sq_curv = T(0);
-        Fwd<NS, T> f2;
-        cpen = config_forward<NS, T, false>(rb, wc, z, s_sph, M, 4, 1, f2);
-      }
+      Fwd<NS, T> f;
+      WeightsT<T> wb = w;  // clearance alone here; the bounds below
+      wb.sq_lim = wb.sq_curv = T(0);
+      cpen = config_forward<NS, T, false>(rb, wb, z, s_sph, M, 4, 1, f);
+      cst = cpen + bounds_cost<NS>(rb, w, z);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rt[k] = f.R[k];
+      pt[0] = f.p[0];
+      pt[1] = f.p[1];
+      pt[2] = f.p[2];
     }
     if (ta.kind == CR_KIND_PATH) {
       T Tt[12], ft[3], tq[3];
       load_pose(ta, cx, t, Tt);
-      cst += pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
+      cst += pose_term<T, false>(w, Rt, pt, Tt, ft, tq);
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
@@ -345,9 +374,9 @@ __device__ __forceinline__ T traj_cost(const RobotT<T>& rb, const WeightsT<T>& w
 #pragma unroll
       for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = u[j];
     }
-    s_p[3 * t] = f.p[0];
-    s_p[3 * t + 1] = f.p[1];
-    s_p[3 * t + 2] = f.p[2];
+    s_p[3 * t] = pt[0];
+    s_p[3 * t + 1] = pt[1];
+    s_p[3 * t + 2] = pt[2];
   }
   __syncthreads();
   if (listed) {
