@@ -123,12 +123,25 @@ __device__ __forceinline__ void load_end(const TrajArgs<T>& ta, const TrajCtx& c
 // whole wave in their point loops.
 template <typename T>
 struct CollList {
-  static constexpr int FR = 17;
-  T* fr;      // [(t * NS + i) * FR]: base rotation (9), base position (3), a, b, arc midpoint (3)
+  static constexpr int FR = 14;
+  T* fr;      // [(t * NS + i) * FR]: rows 0 and 1 of the base rotation (6), base position (3), a, b,
+              // arc midpoint (3); row 2 is their cross product
+  static constexpr int OP = 6, OA = 9, OM = 11;
   int* list;  // packed triples (t << 12) | (i << 9) | m, one slice per wave
   int* cnt;   // entries per wave (at most 4 waves)
   int cap;    // 0: no list, each lane loops over its own points
 };
+
+// Base rotation of a frame record: rows 0 and 1 as stored, row 2 = row 0 x row 1
+// (a rotation's rows form a right-handed orthonormal triple).
+template <typename T>
+__device__ __forceinline__ void frame_rot(const T* fr, T* R) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) R[k] = fr[k];
+  R[6] = R[1] * R[5] - R[2] * R[4];
+  R[7] = R[2] * R[3] - R[0] * R[5];
+  R[8] = R[0] * R[4] - R[1] * R[3];
+}
 
 // The list area follows the other LDS arrays: frames, then the counter and the
 // packed triples.
@@ -168,13 +181,13 @@ __device__ __forceinline__ void coll_frames(const RobotT<T>& rb, const T* z, int
     const T a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
     T* fr = cl.fr + (t * NS + i) * CollList<T>::FR;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) fr[k] = Rc[k];
-    fr[9] = pc[0];
-    fr[10] = pc[1];
-    fr[11] = pc[2];
-    fr[12] = a;
-    fr[13] = b;
-    seg_point(Rc, pc, a, b, rb.L[i], s, T(0.5), fr + 14);
+    for (int k = 0; k < 6; ++k) fr[k] = Rc[k];
+    fr[CollList<T>::OP] = pc[0];
+    fr[CollList<T>::OP + 1] = pc[1];
+    fr[CollList<T>::OP + 2] = pc[2];
+    fr[CollList<T>::OA] = a;
+    fr[CollList<T>::OA + 1] = b;
+    seg_point(Rc, pc, a, b, rb.L[i], s, T(0.5), fr + CollList<T>::OM);
     ArcCoef<T> c = arc_coef<T, false>(s);
     T Ri[9], di[3], q[3], Rn[9];
     seg_R_d(a, b, rb.L[i], c, Ri, di);
@@ -239,7 +252,8 @@ __device__ __forceinline__ T coll_enqueue(const RobotT<T>& rb, const WeightsT<T>
         T Li, ri;
         seg_consts<NS>(rb, i, Li, ri);
         const T* fr = cl.fr + prc * CollList<T>::FR;
-        const T e0 = fr[14] - c0, e1 = fr[15] - c1, e2 = fr[16] - c2;
+        const T* mid = fr + CollList<T>::OM;
+        const T e0 = mid[0] - c0, e1 = mid[1] - c1, e2 = mid[2] - c2;
         const T rq = (rs + ri + w.margin + T(0.5) * Li) * T(1.0001);
         hit[j] = has && pr < npair && e0 * e0 + e1 * e1 + e2 * e2 < rq * rq;
       }
@@ -260,10 +274,12 @@ __device__ __forceinline__ T coll_enqueue(const RobotT<T>& rb, const WeightsT<T>
           T Li, ri;
           seg_consts<NS>(rb, i, Li, ri);
           const T* fr = cl.fr + pr * CollList<T>::FR;
-          const T a = fr[12], b = fr[13];
+          const T a = fr[CollList<T>::OA], b = fr[CollList<T>::OA + 1];
+          T Rb[9];
+          frame_rot(fr, Rb);
           for (int k = 1; k <= K; ++k) {
             T x[3];
-            seg_point(fr, fr + 9, a, b, Li, a * a + b * b, T(k) * invK, x);
+            seg_point(Rb, fr + CollList<T>::OP, a, b, Li, a * a + b * b, T(k) * invK, x);
             cost += point_sphere_cost(x, sm, rs + ri + w.margin, w.sq_coll);
           }
         }
@@ -297,18 +313,21 @@ __device__ __forceinline__ T coll_drain(const RobotT<T>& rb, const WeightsT<T>& 
       T Li, ri;
       seg_consts<NS>(rb, i, Li, ri);
       const T* fr = cl.fr + (t * NS + i) * CollList<T>::FR;
-      const T a = fr[12], b = fr[13], s = a * a + b * b;
+      const T a = fr[CollList<T>::OA], b = fr[CollList<T>::OA + 1], s = a * a + b * b;
+      T Rb[9];
+      frame_rot(fr, Rb);
+      const T* pb = fr + CollList<T>::OP;
       const T* sm = s_sph + 4 * m;
       const T reach = sm[3] + ri + w.margin;
       const int k0 = 8 * q + 1, k1 = 8 * q + 8 < K ? 8 * q + 8 : K;
       T xc[3];
-      seg_point(fr, fr + 9, a, b, Li, s, T(k0 + k1) * T(0.5) * invK, xc);
+      seg_point(Rb, pb, a, b, Li, s, T(k0 + k1) * T(0.5) * invK, xc);
       const T d0 = xc[0] - sm[0], d1 = xc[1] - sm[1], d2 = xc[2] - sm[2];
       const T rq = (reach + T(k1 - k0) * T(0.5) * invK * Li) * T(1.0001);
       if (d0 * d0 + d1 * d1 + d2 * d2 < rq * rq) {
         for (int k = k0; k <= k1; ++k) {
           T x[3];
-          seg_point(fr, fr + 9, a, b, Li, s, T(k) * invK, x);
+          seg_point(Rb, pb, a, b, Li, s, T(k) * invK, x);
           cost += point_sphere_cost(x, sm, reach, w.sq_coll);
         }
       }
@@ -1002,7 +1021,20 @@ __global__ void __launch_bounds__(256)
   for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
     for (int k = 0; k < NZ; ++k) zt[k] = act ? z[k] + alpha * dl[k] : T(0);
-    const T c = traj_cost<NS>(rb, w, ta, cx, zt, s_sph, s_u, s_p, s_red, (T*)nullptr, cl);
+    // The cost's loads of the task, the spheres and the LDS arrays go through an
+    // offset that is zero but opaque to the compiler, fresh in every trial: it
+    // cannot hoist them out of the trial loop and keep their values in registers
+    // for all trials (that doubled this kernel's registers and halved its
+    // occupancy).  An integer offset keeps every pointer's address space known.
+    int z0 = 0;
+    asm volatile("" : "+s"(z0));
+    TrajArgs<T> tal = ta;
+    tal.task += z0;
+    CollList<T> cll = cl;
+    cll.fr += z0;
+    cll.list += z0;
+    cll.cnt += z0;
+    const T c = traj_cost<NS>(rb, w, tal, cx, zt, s_sph + z0, s_u + z0, s_p + z0, s_red + z0, (T*)nullptr, cll);
     ++ntr;
     if (c <= c0 + T(1e-4) * alpha * gd) {
       acc = tr;
@@ -1367,16 +1399,32 @@ static size_t traj_lds(int Tn, int M, bool build) {
   return sizeof(T) * (size_t)(4 * M + Tn * 3 * NS + Tn * 3 + (build ? Tn * 3 * NZ : 0) + 8);
 }
 
-// Capacity of the clearance work list of the search / evaluation kernels (0: none),
-// sized so that their LDS stays within 48 KiB.
+static int threads_for(int Tn) { return ((Tn + 63) / 64) * 64; }
+
+// Capacity of the clearance work list of the search / evaluation kernels (0: none)
+// for a launch of nt workgroups.  The list is sized to the LDS that each workgroup
+// may hold when the compute units keep the launch's workgroups resident together
+// (160 KiB / workgroups per CU), but never below 13 KiB per wave (about three
+// waves per SIMD, which the search kernel's registers allow anyway) nor above
+// 48 KiB; at least 128 entries per wave, at most 2048.  Listed triples beyond the
+// capacity are evaluated by the lane that found them.
 template <int NS, typename T>
-static int traj_list_cap(int Tn, int M) {
+static int traj_list_cap(int Tn, int M, int64_t nt) {
   if (M <= 0) return 0;
-  const size_t budget = 48 * 1024;
+  const size_t nwv = (size_t)threads_for(Tn) / 64;
   const size_t base = traj_lds<NS, T>(Tn, M, false) + sizeof(T) * (size_t)Tn * NS * CollList<T>::FR + 16;
-  if (base >= budget) return 0;
-  size_t cap = (size_t)Tn * NS * M < 2048 ? (size_t)Tn * NS * M : 2048;
-  if (cap > (budget - base) / 4) cap = (budget - base) / 4;
+  const size_t limit = 48 * 1024;
+  if (base + 64 * 4 > limit) return 0;
+  const size_t per_cu = nt > 256 ? (size_t)((nt + 255) / 256) : 1;
+  size_t budget = 160 * 1024 / per_cu;
+  if (budget < 13 * 1024 * nwv) budget = 13 * 1024 * nwv;
+  if (budget > limit) budget = limit;
+  size_t cap = budget > base ? (budget - base) / 4 : 0;
+  if (cap < 128 * nwv) cap = 128 * nwv;
+  if (cap > 2048) cap = 2048;
+  const size_t pairs = (size_t)Tn * NS * M;
+  if (cap > pairs) cap = pairs;
+  if (cap > (limit - base) / 4) cap = (limit - base) / 4;
   return cap >= 64 ? (int)cap : 0;
 }
 
@@ -1392,15 +1440,13 @@ bool traj_lds_ok(int Tmax, int Mmax) {
   return traj_lds<NS, double>(Tmax, Mmax, true) <= 64 * 1024;
 }
 
-static int threads_for(int Tn) { return ((Tn + 63) / 64) * 64; }
-
 // One LM stage (iters iterations) on the nt trajectories of ta, in type T.
 template <int NS, typename T>
 static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const TrajArgs<T>& ta, int Mmax,
                             const LMOpts<T>& lo, int64_t nt, int iters, T* Z, T* blk, T* lam, T* c0, T* gd,
                             int32_t* chol, int32_t* failed, int32_t* trials, hipStream_t st) {
   const int threads = threads_for(ta.Tmax);
-  const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax);
+  const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax, nt);
   const size_t lds_b = traj_lds<NS, T>(ta.Tmax, Mmax, true), lds_s = traj_lds_list<NS, T>(ta.Tmax, Mmax, cap);
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   for (int it = 0; it < iters; ++it) {
@@ -1445,7 +1491,7 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const TrajShape& sh, co
   cr_status rc = traj_stage<NS, T1>(rb1, w1, ta1, sh.Mmax, lo1, n1, o.k_init, (T1*)ws.Z1, (T1*)ws.blk1,
                                     (T1*)ws.lam1, (T1*)ws.c01, (T1*)ws.gd1, ws.chol1, ws.fail1, ws.trials1, st);
   if (rc != CR_OK) return rc;
-  const int cap1 = traj_list_cap<NS, T1>(sh.Tmax, sh.Mmax);
+  const int cap1 = traj_list_cap<NS, T1>(sh.Tmax, sh.Mmax, n1);
   const size_t lds_e1 = traj_lds_list<NS, T1>(sh.Tmax, sh.Mmax, cap1);
   hipLaunchKernelGGL((k_traj_eval<NS, T1>), dim3((unsigned)n1), dim3(threads), lds_e1, st, rb1, w1, ta1,
                      (const T1*)ws.Z1, (T1*)ws.cost1, (T1*)ws.pen1, ws.fail1, cap1);
@@ -1468,7 +1514,7 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const TrajShape& sh, co
     rc = traj_stage<NS, double>(rbd, wd, ta2, sh.Mmax, lo2, n2, o.k_final, ws.Z2, ws.blk2, ws.lam2, ws.c02, ws.gd2,
                                 ws.chol2, ws.fail2, ws.trials2, st);
     if (rc != CR_OK) return rc;
-    const int cap2 = traj_list_cap<NS, double>(sh.Tmax, sh.Mmax);
+    const int cap2 = traj_list_cap<NS, double>(sh.Tmax, sh.Mmax, n2);
     const size_t lds_e2 = traj_lds_list<NS, double>(sh.Tmax, sh.Mmax, cap2);
     hipLaunchKernelGGL((k_traj_eval<NS, double>), dim3((unsigned)n2), dim3(threads), lds_e2, st, rbd, wd, ta2,
                        (const double*)ws.Z2, ws.cost2, ws.pen2, ws.fail2, cap2);
