@@ -1,10 +1,12 @@
 // cr_tally.hip -- algorithmic operation counts of the IK stage-1 kernel.
 //
 // The stage-1 arithmetic in cr_device.h is templated on its scalar type.  Here
-// it is replayed on the host with CountT, a double that counts every floating
-// operation it performs, over a caller-given sample of seeds.  The counts are
-// therefore those of the kernel's own formulas (same branches, same line-search
-// trials up to FP32/FP64 rounding), not an estimate.  Counting rules:
+// it is replayed on the host with CountT, an FP32 value that counts every
+// floating operation it performs, over a caller-given sample of seeds.  The counts
+// are therefore those of the kernel's own formulas, taking the kernel's branches
+// and line-search trials in the kernel's precision (up to the rounding of fused
+// multiply-adds and of the host's math library), not an estimate.  The bound
+// hinges, which the kernel forms in FP64, are formed in FP64 here too.  Counting rules:
 // add, sub, mul = 1 each (a fused multiply-add counts as its mul and its add,
 // i.e. 2); div, sqrt and the transcendental calls (sin and cos of sincos count
 // 2, atan2 1) are tallied separately and count 1 flop each in the total.
@@ -20,10 +22,10 @@ struct OpCount {
 static thread_local OpCount g_ops;
 
 struct CountT {
-  double v;
-  CountT() : v(0.0) {}
-  CountT(double x) : v(x) {}
-  explicit operator double() const { return v; }
+  float v;
+  CountT() : v(0.0f) {}
+  CountT(double x) : v((float)x) {}
+  explicit operator double() const { return (double)v; }
 };
 inline CountT operator+(CountT a, CountT b) { g_ops.addmul += 1; return CountT(a.v + b.v); }
 inline CountT operator-(CountT a, CountT b) { g_ops.addmul += 1; return CountT(a.v - b.v); }
@@ -39,23 +41,23 @@ inline bool operator<=(CountT a, CountT b) { return a.v <= b.v; }
 inline bool operator>=(CountT a, CountT b) { return a.v >= b.v; }
 inline bool operator==(CountT a, CountT b) { return a.v == b.v; }
 inline bool operator!=(CountT a, CountT b) { return a.v != b.v; }
-inline CountT fabs(CountT a) { return CountT(::fabs(a.v)); }
+inline CountT fabs(CountT a) { return CountT(::fabsf(a.v)); }
 
 template <>
 CR_HD CountT tsqrt<CountT>(CountT x) {
   g_ops.sqrt += 1;
-  return CountT(::sqrt(x.v));
+  return CountT(::sqrtf(x.v));
 }
 template <>
 CR_HD CountT tatan2<CountT>(CountT y, CountT x) {
   g_ops.trans += 1;
-  return CountT(::atan2(y.v, x.v));
+  return CountT(::atan2f(y.v, x.v));
 }
 template <>
 CR_HD void tsincos<CountT>(CountT x, CountT* s, CountT* c) {
   g_ops.trans += 2;
-  *s = CountT(::sin(x.v));
-  *c = CountT(::cos(x.v));
+  *s = CountT(::sinf(x.v));
+  *c = CountT(::cosf(x.v));
 }
 template <>
 CR_HD bool tfinite<CountT>(CountT x) {
