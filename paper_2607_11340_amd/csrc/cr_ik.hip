@@ -106,7 +106,10 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // SelectTop.  Keys (flag, e, index) are sorted ascending in LDS by a bitonic
 // network (flag 0 = valid, 1 = failed, 2 = padding); all keys are distinct, so
-// the order equals a stable sort by (flag, e).  Thread 0 then walks the order.
+// the order equals a stable sort by (flag, e).  The first wave then walks the
+// order: each candidate is compared with every kept one at once, one lane per
+// (kept candidate, coordinate) pair, and the walk's decisions are uniform across
+// the wave.  The candidates' coordinates are staged in LDS when they fit.
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -118,18 +121,29 @@ __device__ __forceinline__ bool key_less(T ea, int fa, T eb, int fb) {
   return (fa & 0xffff) < (fb & 0xffff);
 }
 
-// Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zs_c] and
+// LDS of k_select for up to Spad candidates, with room to stage stage_nz
+// coordinates per candidate (0: coordinates are read from z).
+static inline size_t select_lds(int Spad, int stage_nz, size_t tb) {
+  size_t b = (size_t)Spad * (tb + 4) + (size_t)Spad;
+  b = (b + 7) & ~(size_t)7;
+  b += 64 * 4;
+  return b + (size_t)Spad * stage_nz * tb;
+}
+
+// Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zc] and
 // its keys sit at p * S + c; with rows != NULL problem p has its own candidate
 // count, key base and z layout (ragged batches, trajectories).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_select(int64_t P, int S0, int Spad0, int nz0, const T* __restrict__ z, int64_t zs_m, int64_t zs_c,
-             const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final,
-             T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
-  extern __shared__ unsigned char smem[];
+    k_select(int64_t P, int S0, int Spad0, int nz0, int stage_nz, const T* __restrict__ z, int64_t zs_m,
+             int64_t zs_c, const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed,
+             int n_final, T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
   T* se = reinterpret_cast<T*>(smem);
   int* sf = reinterpret_cast<int*>(se + Spad0);
   unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad0);
+  int* kept = reinterpret_cast<int*>(smem + ((((size_t)Spad0 * (sizeof(T) + 4) + Spad0) + 7) & ~(size_t)7));
+  T* sz = reinterpret_cast<T*>(kept + 64);
   const int64_t p = blockIdx.x;
   int S = S0, nz = nz0, Spad = Spad0;
   int64_t kb = p * S0, zb = p * S0 * zs_c, zc = zs_c;
@@ -143,6 +157,7 @@ __global__ void __launch_bounds__(256)
     Spad = 1;
     while (Spad < S) Spad <<= 1;
   }
+  const bool staged = nz <= stage_nz;
   for (int i = threadIdx.x; i < Spad; i += blockDim.x) {
     if (i < S) {
       T ev = e[kb + i];
@@ -154,6 +169,13 @@ __global__ void __launch_bounds__(256)
       sf[i] = (2 << 16) | i;
     }
     skipped[i] = 0;
+  }
+  if (staged) {
+    // consecutive threads read consecutive candidates of one coordinate
+    for (int i = threadIdx.x; i < S * nz; i += blockDim.x) {
+      const int m = i / S, c = i - m * S;
+      sz[c * nz + m] = z[zb + m * zs_m + c * zc];
+    }
   }
   __syncthreads();
   for (int k = 2; k <= Spad; k <<= 1) {
@@ -176,41 +198,66 @@ __global__ void __launch_bounds__(256)
       __syncthreads();
     }
   }
-  if (threadIdx.x != 0) return;
-  int kept[64];
+  if (threadIdx.x >= 64) return;
+  // One wave from here on.  Every lane takes the same decisions and writes the same
+  // values to the kept list and the skip flags, so the wave's in-order LDS accesses
+  // keep them consistent without a barrier.
+  const int lane = (int)threadIdx.x;
+  auto coord = [&](int c, int m) -> T { return staged ? sz[c * nz + m] : z[zb + m * zs_m + c * zc]; };
   int nk = 0;
   for (int q = 0; q < S && nk < n_final; ++q) {
-    int f = sf[q];
+    const int f = sf[q];
     if ((f >> 16) != 0) break;
-    int c = f & 0xffff;
-    int dup = -1;
-    for (int k = 0; k < nk && dup < 0; ++k) {
-      T dmax = T(0);
-      for (int m = 0; m < nz; ++m) {
-        T d = fabs(z[zb + m * zs_m + c * zc] - z[zb + m * zs_m + kept[k] * zc]);
-        dmax = d > dmax ? d : dmax;
+    const int c = f & 0xffff;
+    // bit k: some coordinate differs from kept candidate k by more than dup_eps
+    // (a NaN difference never counts, as in a running maximum that skips NaN)
+    unsigned long long kfar = 0ull;
+    const int np = nk * nz;
+    for (int base = 0; base < np; base += 64) {
+      const int pi = base + lane;
+      bool far = false;
+      if (pi < np) {
+        const int k = pi / nz, m = pi - k * nz;
+        far = fabs(coord(c, m) - coord(kept[k], m)) > dup_eps;
       }
-      if (dmax <= dup_eps) dup = k;
+      const unsigned long long fm = __ballot(far);
+      if (fm != 0ull) {
+        const int k0 = base / nz;
+        const int k1 = (base + 63) / nz < nk - 1 ? (base + 63) / nz : nk - 1;
+        for (int k = k0; k <= k1; ++k) {
+          const int lo = k * nz - base > 0 ? k * nz - base : 0;
+          const int hi = (k + 1) * nz - base < 64 ? (k + 1) * nz - base : 64;
+          const unsigned long long win = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+          if (fm & win) kfar |= 1ull << k;
+        }
+      }
     }
-    if (dup < 0) {
-      kept[nk++] = c;
-    } else if (pen[kb + c] < pen[kb + kept[dup]]) {
-      skipped[kept[dup]] = 1;
-      kept[dup] = c;
+    const unsigned long long near = ~kfar & (nk >= 64 ? ~0ull : ((1ull << nk) - 1ull));
+    if (near == 0ull) {
+      kept[nk] = c;
+      ++nk;
     } else {
-      skipped[c] = 1;
+      const int dup = __builtin_ctzll(near);  // the first kept candidate it duplicates
+      const int kd = kept[dup];
+      if (pen[kb + c] < pen[kb + kd]) {
+        skipped[kd] = 1;
+        kept[dup] = c;
+      } else {
+        skipped[c] = 1;
+      }
     }
   }
   for (int q = 0; q < S && nk < n_final; ++q) {
-    int f = sf[q];
+    const int f = sf[q];
     if ((f >> 16) != 0) break;
-    int c = f & 0xffff;
+    const int c = f & 0xffff;
     if (skipped[c]) {
-      kept[nk++] = c;
+      kept[nk] = c;
+      ++nk;
       skipped[c] = 0;
     }
   }
-  for (int k = 0; k < n_final; ++k) idx_out[k * P + p] = k < nk ? kept[k] : -1;
+  if (lane < n_final) idx_out[(int64_t)lane * P + p] = lane < nk ? kept[lane] : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -651,14 +698,17 @@ cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z,
   int Spad = 1;
   while (Spad < S) Spad <<= 1;
   const size_t tb = dtype == CR_F64 ? 8 : 4;
-  const size_t lds = Spad * (tb + 4) + Spad;
+  // stage the coordinates when every problem's fit in 32 KiB (nz == 0: per-row
+  // counts unknown here, read from z)
+  const int stage_nz = nz > 0 && (size_t)Spad * nz * tb <= 32 * 1024 ? nz : 0;
+  const size_t lds = select_lds(Spad, stage_nz, tb);
   if (P == 0) return CR_OK;
   if (dtype == CR_F64)
-    hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
+    hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_nz,
                        (const double*)z, zs_m, zs_c, (const double*)e, (const double*)pen, failed, (int)n_final,
                        dup_eps, rows, idx_out);
   else
-    hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz,
+    hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_nz,
                        (const float*)z, zs_m, zs_c, (const float*)e, (const float*)pen, failed, (int)n_final,
                        (float)dup_eps, rows, idx_out);
   return check_hip(hipGetLastError(), "k_select");

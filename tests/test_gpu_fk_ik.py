@@ -100,10 +100,16 @@ def test_select_top_parity(oracle, cr, dtype):
     rng = np.random.default_rng(31)
     td = torch.float64 if dtype == "f64" else torch.float32
     npd = np.float64 if dtype == "f64" else np.float32
-    for S, P, nf in [(1, 3, 2), (5, 7, 3), (64, 37, 8), (300, 11, 8), (2048, 2, 64)]:
-        nz = 4
+    for S, P, nf, nz in [(1, 3, 2, 4), (5, 7, 3, 4), (64, 37, 8, 4), (300, 11, 8, 4), (2048, 2, 64, 4),
+                         (64, 5, 8, 100), (40, 3, 16, 70)]:
         e = (rng.integers(0, 12, size=(P, S)) * 0.25).astype(npd)   # many exact ties
-        z = rng.integers(0, 4, size=(P, S, nz)).astype(npd) * npd(1e-3) * 0.9  # many near-duplicates
+        if nz <= 4:
+            z = rng.integers(0, 4, size=(P, S, nz)).astype(npd) * npd(1e-3) * 0.9  # many near-duplicates
+        else:
+            # long candidates (a kept one spans two 64-lane rounds): a few well separated
+            # base vectors plus noise below the duplicate tolerance
+            base = rng.integers(0, 4, size=(P, 3, nz)) * 3e-3
+            z = (base[:, rng.integers(0, 3, size=S)] + rng.uniform(-4e-4, 4e-4, (P, S, nz))).astype(npd)
         pen = rng.integers(0, 3, size=(P, S)).astype(npd)
         failed = (rng.random((P, S)) < 0.1).astype(np.int32)
         e[0, 0] = np.nan  # non-finite key counts as failed
