@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the compiler's own occupancy targets instead of the library's launch autotuning")
     ap.add_argument("--tally-seeds", type=int, default=256)
     ap.add_argument("--baseline-targets", type=int, default=16,
                     help="targets timed with the plain per-problem FP32 solve (0: skip)")
@@ -163,6 +165,18 @@ def cpu_baseline(spec, T_host, seeds, budget_s):
                        f"iterations, single thread, {el:.1f} s; {solved}/{done} solved")
 
 
+def autotune(args, cr, torch, call):
+    """The library's launch autotuning: one untimed call (call) times each tunable
+    kernel's occupancy variants -- identical results, different speed -- and caches
+    the fastest; the timed steps use the cached choices."""
+    if args.no_autotune:
+        return None
+    cr.autotune(True)
+    call()
+    torch.cuda.synchronize()
+    return cr.autotune_report()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -196,6 +210,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = autotune(args, cr, torch, step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -269,7 +284,7 @@ def main():
         success_rate=round(success, 4), max_pos_err_solved_m=float(np.nanmax(np.where(status == cr.SOLVED, err[0], 0))),
         stage_ms=dict(stage1=round(stage_avg[0], 4), select=round(stage_avg[1], 4), stage2=round(stage_avg[2], 4),
                       finalize=round(stage_avg[3], 4)),
-        fk_grad=fkg, plain_gpu_baseline=b0, roofline=roofline, cpu_baseline=base)
+        fk_grad=fkg, plain_gpu_baseline=b0, roofline=roofline, cpu_baseline=base, autotune=tuned)
     print(json.dumps(line), flush=True)
 
 
@@ -353,6 +368,7 @@ def bench_trajectories(args, cr, I, torch):
         fn(robot, d["task"], d["useed"], H, weights, opts, dtype=torch.float32, spheres=d["spheres"], workspace=ws,
            out=out)
 
+    tuned = autotune(args, cr, torch, step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -375,7 +391,8 @@ def bench_trajectories(args, cr, I, torch):
                             k_final=spec["k_final"], n_final=spec["n_final"], k_seed=spec.get("k_seed", 0)),
                 success_rate=round(float((status == cr.SOLVED).mean()), 4),
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
-                max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)])
+                max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)],
+                autotune=tuned)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)
@@ -483,9 +500,11 @@ def bench_uneven(args, cr, I, torch):
     out = (torch.empty(batch.n_out, dtype=torch.float64, device="cuda"),
            torch.empty((2, P), dtype=torch.float64, device="cuda"), torch.empty(P, dtype=torch.int32, device="cuda"))
 
-    def step():
-        cr.solve_batch(batch, weights, opts, dtype=torch.float32, workspace=ws, dev_arrays=dev, graph=True, out=out)
+    def step(graph=True):
+        cr.solve_batch(batch, weights, opts, dtype=torch.float32, workspace=ws, dev_arrays=dev, graph=graph, out=out)
 
+    # tuned eagerly: the graph captured by the first warm-up step then holds the chosen variants
+    tuned = autotune(args, cr, torch, lambda: step(graph=False))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -508,7 +527,7 @@ def bench_uneven(args, cr, I, torch):
                                                                           traj=int((kinds == 2).sum())),
                             segments="U{1..6}", horizons="U{1..64}", seeds="U{16..512}", spheres="U{0..64}",
                             spheres_kept=n_sph, seeds_total=int(sum(p["S"] for p in probs)), graph=True),
-                success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ)
+                success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ, autotune=tuned)
     print(json.dumps(line), flush=True)
 
 

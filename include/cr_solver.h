@@ -305,6 +305,34 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_t
 void cr_timing_enable(int32_t on);
 cr_status cr_timing_read(double* stage_ms, int64_t* n_calls);
 
+/* Launch autotuning of the uneven-batch scheduling (a library-owned cache per
+ * device).  The IK stage-1 kernels (uniform and table-driven) and the trajectory
+ * normal-equation kernel are each compiled for three occupancy targets (the
+ * minimum waves per SIMD their register allocation must allow).  The variants
+ * compute the same formulas, but the compiler may contract different products
+ * into fused multiply-adds under different register budgets, so FP32 results can
+ * differ between variants in the last bits; each variant is deterministic, and a
+ * cached choice reproduces the tuning call's results exactly.  While enabled, the
+ * first FP32 launch of a key (kernel, segments, launch size rounded up to a power
+ * of two, device) that is not being captured into a graph times each target once
+ * alone on the device (the call first waits for all queued device work, then
+ * synchronises on the timing events) and later launches of the key use the
+ * fastest.  Disabled (the default), or under capture with no
+ * cached choice, the compiler's own target runs.
+ *   cr_autotune_enable(on): switch tuning on or off (the cache is kept).
+ *   cr_autotune_clear():    forget every cached choice.
+ *   cr_autotune_force(v):   run variant v (0: the compiler's own target, 1 and 2:
+ *     the two tighter targets) for every tunable kernel, tuning or not; v < 0
+ *     returns to normal operation.
+ *   cr_autotune_report(buf, cap): text, one line per cached key (chosen target and
+ *     the milliseconds of each), written to buf [host] when buf != NULL, truncated
+ *     to cap - 1 bytes and NUL-terminated; returns the full length.
+ * Process-wide state, guarded by a mutex. */
+void cr_autotune_enable(int32_t on);
+void cr_autotune_clear(void);
+void cr_autotune_force(int32_t variant);
+int64_t cr_autotune_report(char* buf, int64_t cap);
+
 /* Algorithmic operation count of the IK stage-1 kernel, measured by replaying the
  * kernel's own arithmetic on the host with an op-counting scalar over n sample
  * seeds (k_init iterations plus the final evaluation each).

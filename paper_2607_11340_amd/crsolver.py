@@ -30,7 +30,8 @@ SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
            "cr_select_top",
-           "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_status_string", "cr_last_error")
+           "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_autotune_enable", "cr_autotune_clear", "cr_autotune_force",
+           "cr_autotune_report", "cr_status_string", "cr_last_error")
 
 
 class CRError(RuntimeError):
@@ -156,6 +157,14 @@ def _load():
     L.cr_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.cr_ik_flop_tally.argtypes = [R, W, O, i64, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]
+    L.cr_autotune_enable.argtypes = [i32]
+    L.cr_autotune_enable.restype = None
+    L.cr_autotune_force.argtypes = [i32]
+    L.cr_autotune_force.restype = None
+    L.cr_autotune_clear.argtypes = []
+    L.cr_autotune_clear.restype = None
+    L.cr_autotune_report.argtypes = [C.c_char_p, i64]
+    L.cr_autotune_report.restype = i64
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
@@ -500,3 +509,27 @@ class CostGrad(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         _, g = cost_grad(ctx.problem, u.detach(), grad=True, grad_scale=gcost.contiguous())
         return g, None
+
+
+def autotune(on: bool = True):
+    """Switch the library's launch autotuning on or off (cr_autotune_enable)."""
+    lib.cr_autotune_enable(1 if on else 0)
+
+
+def autotune_force(variant: int):
+    """Run the given launch variant of every tunable kernel; -1 returns to normal
+    operation (cr_autotune_force)."""
+    lib.cr_autotune_force(int(variant))
+
+
+def autotune_clear():
+    """Forget every cached autotuning choice (cr_autotune_clear)."""
+    lib.cr_autotune_clear()
+
+
+def autotune_report() -> list:
+    """The cached autotuning choices, one text line per key (cr_autotune_report)."""
+    n = lib.cr_autotune_report(None, 0)
+    buf = C.create_string_buffer(int(n) + 1)
+    lib.cr_autotune_report(buf, n + 1)
+    return [l for l in buf.value.decode().split("\n") if l]

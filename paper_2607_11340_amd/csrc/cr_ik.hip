@@ -17,8 +17,10 @@
 
 namespace crk {
 
-template <int NS, typename T>
-__global__ void __launch_bounds__(256)
+// OCC: the minimum waves per SIMD the register allocation must allow (1 = the
+// compiler's own choice); the autotuner picks among the compiled targets.
+template <int NS, typename T, int OCC = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     k_ik_stage1(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
                 const double* __restrict__ useed, int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out,
                 T* __restrict__ pen_out, T* __restrict__ cost_out, int32_t* __restrict__ failed_out,
@@ -398,8 +400,8 @@ __device__ __forceinline__ int64_t ik_find(const IkProb* tp, int64_t P, int64_t 
   return lo;
 }
 
-template <int NS, typename T>
-__global__ void __launch_bounds__(256)
+template <int NS, typename T, int OCC = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     k_ik_stage1_rag(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
                     const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
                     int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
@@ -625,9 +627,28 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
                        Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
                        ws.failed1, ws.trials1);
   } else {
-    hipLaunchKernelGGL((k_ik_stage1<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S, Tt,
-                       useed, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1,
-                       ws.trials1);
+    auto launch = [&](int v) {
+      const int occ = tune_occ(TK_IK_STAGE1, v);
+#define CR_S1(O)                                                                                                   \
+  hipLaunchKernelGGL((k_ik_stage1<NS, T, O>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S, Tt, \
+                     useed, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1,   \
+                     ws.trials1)
+      if constexpr (sizeof(T) == 4) {
+        if (occ == tune_occ(TK_IK_STAGE1, 1)) CR_S1(tune_occ(TK_IK_STAGE1, 1));
+        else if (occ == tune_occ(TK_IK_STAGE1, 2)) CR_S1(tune_occ(TK_IK_STAGE1, 2));
+        else CR_S1(1);
+      } else {
+        CR_S1(1);
+      }
+#undef CR_S1
+    };
+    int v = 0;
+    bool done = false;
+    if (sizeof(T) == 4) {
+      cr_status rt = tune_choose(TK_IK_STAGE1, NS, CR_F32, B, st, launch, &v, &done);
+      if (rt != CR_OK) return rt;
+    }
+    if (!done) launch(v);
   }
   cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1");
   if (rc != CR_OK) return rc;
@@ -774,8 +795,28 @@ static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Sma
   WeightsT<T> w = weights_to<T>(w0);
   LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
   RobotT<double> rbd = robot_to<double>(rb0);
-  hipLaunchKernelGGL((k_ik_stage1_rag<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B, tp, task,
-                     useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1, ws.failed1);
+  auto launch = [&](int v) {
+    const int occ = tune_occ(TK_IK_STAGE1_RAG, v);
+#define CR_S1R(O)                                                                                                 \
+  hipLaunchKernelGGL((k_ik_stage1_rag<NS, T, O>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B, tp, \
+                     task, useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,    \
+                     ws.failed1)
+    if constexpr (sizeof(T) == 4) {
+      if (occ == tune_occ(TK_IK_STAGE1_RAG, 1)) CR_S1R(tune_occ(TK_IK_STAGE1_RAG, 1));
+      else if (occ == tune_occ(TK_IK_STAGE1_RAG, 2)) CR_S1R(tune_occ(TK_IK_STAGE1_RAG, 2));
+      else CR_S1R(1);
+    } else {
+      CR_S1R(1);
+    }
+#undef CR_S1R
+  };
+  int v = 0;
+  bool done = false;
+  if (sizeof(T) == 4) {
+    cr_status rt = tune_choose(TK_IK_STAGE1_RAG, NS, CR_F32, B, st, launch, &v, &done);
+    if (rt != CR_OK) return rt;
+  }
+  if (!done) launch(v);
   cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_rag");
   if (rc != CR_OK) return rc;
   if (o.n_final > 0) {

@@ -35,6 +35,81 @@ cr_status check_weights(const cr_weights* w);
 cr_status fail(cr_status s, const char* fmt, ...);
 cr_status check_hip(hipError_t e, const char* what);
 
+// Launch-variant autotuning.  A tunable kernel is compiled once per occupancy
+// target (minimum waves per SIMD the register allocator must allow: more waves,
+// fewer registers, possibly spills).  The variants compute the same formulas; the
+// compiler may fuse different products into multiply-adds under different budgets,
+// so FP32 results can differ in the last bits between variants, while each variant
+// is deterministic.  With tuning enabled, the first launch of a key
+// (kernel, segments, dtype, launch size rounded to a power of two, device) on a
+// stream that is not being captured times every variant once with HIP events and
+// caches the fastest; only kernels that may run twice on the same data are tuned.
+// Tuning drains the device first (a device-wide synchronisation, once per key).
+enum TuneKernel { TK_IK_STAGE1 = 0, TK_IK_STAGE1_RAG = 1, TK_TRAJ_BUILD = 2, TK_COUNT = 3 };
+constexpr int TUNE_NV = 3;  // variants per kernel
+// occupancy target of variant v of kernel k (1 = the compiler's own choice)
+constexpr int tune_occ(int k, int v) {
+  return v == 0 ? 1 : (k == TK_TRAJ_BUILD ? (v == 1 ? 2 : 3) : (v == 1 ? 3 : 4));
+}
+bool tune_enabled();
+int tune_forced();  // -1, or the variant every tunable kernel runs
+bool stream_capturing(hipStream_t st);
+int tune_lookup(int kernel, int ns, int dtype, int64_t work);  // -1: not tuned yet
+void tune_store(int kernel, int ns, int dtype, int64_t work, int best, const float* ms);
+
+// The variant to launch for this key; times all variants (launch(v) enqueues
+// variant v on st) when the key is new and tuning may run, leaving the outputs of
+// the fastest variant (launched last, again, when it was not the last timed).
+// *done: the kernel has already run.  Errors of the timed launches are returned.
+template <typename F>
+cr_status tune_choose(int kernel, int ns, int dtype, int64_t work, hipStream_t st, F launch, int* variant,
+                      bool* done) {
+  *done = false;
+  *variant = 0;
+  const int forced = tune_forced();
+  if (forced >= 0) {
+    *variant = forced;
+    return CR_OK;
+  }
+  if (!tune_enabled()) return CR_OK;
+  const int v = tune_lookup(kernel, ns, dtype, work);
+  if (v >= 0) {
+    *variant = v;
+    return CR_OK;
+  }
+  if (stream_capturing(st)) return CR_OK;
+  hipEvent_t ev[TUNE_NV + 1];
+  int made = 0;
+  cr_status rc = CR_OK;
+  for (; made <= TUNE_NV && rc == CR_OK; ++made) rc = check_hip(hipEventCreate(&ev[made]), "hipEventCreate");
+  float ms[TUNE_NV] = {0.0f};
+  // the device is drained first, so that the variants run alone (work already
+  // queued on other streams, such as other groups of a batch, would skew them)
+  if (rc == CR_OK) rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  if (rc == CR_OK) {
+    launch(0);  // warm-up: first-use costs of the key's buffers and code
+    rc = check_hip(hipEventRecord(ev[0], st), "hipEventRecord");
+    for (int k = 0; k < TUNE_NV && rc == CR_OK; ++k) {
+      launch(k);
+      rc = check_hip(hipGetLastError(), "autotune launch");
+      if (rc == CR_OK) rc = check_hip(hipEventRecord(ev[k + 1], st), "hipEventRecord");
+    }
+    if (rc == CR_OK) rc = check_hip(hipEventSynchronize(ev[TUNE_NV]), "hipEventSynchronize");
+    for (int k = 0; k < TUNE_NV && rc == CR_OK; ++k)
+      rc = check_hip(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]), "hipEventElapsedTime");
+  }
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+  if (rc != CR_OK) return rc;
+  int best = 0;
+  for (int k = 1; k < TUNE_NV; ++k)
+    if (ms[k] < ms[best]) best = k;
+  tune_store(kernel, ns, dtype, work, best, ms);
+  *variant = best;
+  // the outputs must be the chosen variant's, as on every later call of the key
+  *done = best == TUNE_NV - 1;
+  return CR_OK;
+}
+
 template <typename T>
 RobotT<T> robot_to(const cr_robot& r);
 template <typename T>

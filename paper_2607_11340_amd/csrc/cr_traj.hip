@@ -557,8 +557,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <int NS, typename T>
-__global__ void __launch_bounds__(256)
+// OCC: the minimum waves per SIMD the register allocation must allow (1 = the
+// compiler's own choice); the autotuner picks among the compiled targets.
+template <int NS, typename T, int OCC = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     k_traj_build(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, const T* __restrict__ Z, T* __restrict__ blk,
                  T* __restrict__ cost0, int32_t* __restrict__ failed) {
   constexpr int NZ = 2 * NS, NU = 3 * NS, NP = NZ * (NZ + 1) / 2;
@@ -1449,9 +1451,30 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax, nt);
   const size_t lds_b = traj_lds<NS, T>(ta.Tmax, Mmax, true), lds_s = traj_lds_list<NS, T>(ta.Tmax, Mmax, cap);
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
+  // the normal-equation kernel rewrites the same records from the same z, so the
+  // autotuner may time its variants on the first iteration
+  auto build = [&](int v) {
+    const int occ = tune_occ(TK_TRAJ_BUILD, v);
+#define CR_TB(O)                                                                                           \
+  hipLaunchKernelGGL((k_traj_build<NS, T, O>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, \
+                     c0, failed)
+    if constexpr (sizeof(T) == 4) {
+      if (occ == tune_occ(TK_TRAJ_BUILD, 1)) CR_TB(tune_occ(TK_TRAJ_BUILD, 1));
+      else if (occ == tune_occ(TK_TRAJ_BUILD, 2)) CR_TB(tune_occ(TK_TRAJ_BUILD, 2));
+      else CR_TB(1);
+    } else {
+      CR_TB(1);
+    }
+#undef CR_TB
+  };
+  int vb = 0;
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_traj_build<NS, T>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, c0,
-                       failed);
+    bool done = false;
+    if (it == 0 && sizeof(T) == 4) {
+      cr_status rt = tune_choose(TK_TRAJ_BUILD, NS, CR_F32, nt * (int64_t)ta.Tmax, st, build, &vb, &done);
+      if (rt != CR_OK) return rt;
+    }
+    if (!done) build(vb);
     hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, ta, nt, blk, lam,
                        failed, chol, gd);
     hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,

@@ -1,0 +1,106 @@
+"""Launch autotuning (cr_autotune_*).  The stage-1 IK kernels and the trajectory
+normal-equation kernel are compiled for three occupancy targets.  Each variant is
+deterministic, and the call that tunes returns what later calls with the cached
+choice return, bit for bit.  Different variants may round differently in FP32
+(the compiler's contraction of products into fused multiply-adds can differ with
+the register budget), so across variants the solves must agree as solves: the
+same problems solved, and every solved answer within the success thresholds."""
+import numpy as np
+import pytest
+
+from paper_2607_11340_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture
+def cr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_11340_amd import crsolver
+    crsolver.autotune(False)
+    crsolver.autotune_force(-1)
+    crsolver.autotune_clear()
+    yield crsolver
+    crsolver.autotune(False)
+    crsolver.autotune_force(-1)
+    crsolver.autotune_clear()
+
+
+def run(solve):
+    out = [x.clone() for x in solve()]
+    torch.cuda.synchronize()
+    return out
+
+
+def check(cr, solve, max_status_changes=0):
+    ref = run(solve)                         # the compiler's own targets
+    for v in range(3):
+        cr.autotune_force(v)
+        a, b = run(solve), run(solve)
+        for x, y in zip(a, b):               # a fixed variant repeats exactly
+            assert torch.equal(x, y), v
+        st0, st = ref[2].cpu().numpy(), a[2].cpu().numpy()
+        assert int((st0 != st).sum()) <= max_status_changes, (v, st0, st)
+        err = a[1].cpu().numpy()
+        ok = st == cr.SOLVED
+        assert np.all(err[0][ok] <= 1e-3) and np.all(err[1][ok] <= np.deg2rad(1.0)), v
+        if v == 0:
+            for x, y in zip(a, ref):
+                assert torch.equal(x, y)
+    cr.autotune_force(-1)
+    cr.autotune(True)
+    tuned = run(solve)                       # this call times the variants
+    cached = run(solve)                      # the cached choice
+    for x, y in zip(tuned, cached):
+        assert torch.equal(x, y)
+
+
+def test_ik_stage1_variants(oracle, cr):
+    print("autotune ik stage 1", flush=True)
+    rng = np.random.default_rng(77)
+    L, r, b = [0.10, 0.08, 0.06], [0.010, 0.008, 0.006], 0.008
+    ro = oracle.Robot(L=L, r=r, u_max=[b] * 3)
+    rg = cr.Robot(L=L, r=r, u_max=[b] * 3)
+    P, S = 24, 64
+    _, fr = oracle.fk(ro, I.uniform_actuation(rng, 3, b, P))
+    T = torch.tensor(fr[:, -1].reshape(P, 12).T.copy(), device="cuda")
+    seeds = torch.tensor(I.uniform_actuation(rng, 3, b, P * S).reshape(P * S, 9).T.copy(), device="cuda")
+    opts = cr.Opts(n_final=4, k_init=40, k_final=10)
+    check(cr, lambda: cr.solve_ik(rg, T, seeds, cr.Weights(), opts, dtype=torch.float32))
+    rep = cr.autotune_report()
+    assert any("ik_stage1 n_seg 3 f32" in line for line in rep), rep
+
+
+def test_traj_build_variants(cr):
+    print("autotune trajectory build", flush=True)
+    rng = np.random.default_rng(78)
+    n, H, P, S, M, K = 4, 15, 6, 8, 6, 8
+    L, r, b = [0.08] * n, [0.008] * n, 0.006
+    rg = cr.Robot(L=L, r=r, u_max=[b] * n, pts_per_seg=K)
+    ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
+    seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, H + 1, b) for p in range(P)])
+    task = torch.tensor(np.concatenate([ends[:, 0].reshape(P, -1), ends[:, 1].reshape(P, -1)], 1).T.copy(),
+                        device="cuda")
+    us = torch.tensor(seeds.reshape(P * S * (H + 1), -1).T.copy(), device="cuda")
+    sph = np.concatenate([rng.uniform(-0.1, 0.1, (P * M, 2)), rng.uniform(0.05, 0.3, (P * M, 1)),
+                          rng.uniform(0.005, 0.02, (P * M, 1))], 1)
+    sp = (torch.tensor(np.ascontiguousarray(sph.T), device="cuda"), True, M)
+    opts = cr.Opts(n_final=2, k_init=12, k_final=3)
+    check(cr, lambda: cr.solve_traj(rg, task, us, H, cr.Weights(), opts, dtype=torch.float32, spheres=sp),
+          max_status_changes=1)
+    rep = cr.autotune_report()
+    assert any("traj_build n_seg 4 f32" in line for line in rep), rep
+
+
+def test_batch_variants(oracle, cr):
+    print("autotune uneven batch", flush=True)
+    from test_gpu_batch import mixed_problems, robots, weights3
+    _, rg = robots(oracle, cr)
+    batch = cr.Batch(rg, mixed_problems(oracle, 503))
+    opts = [cr.Opts(n_final=2, k_init=10, k_final=3)] * 3
+    check(cr, lambda: cr.solve_batch(batch, weights3(cr), opts, dtype=torch.float32), max_status_changes=1)
+    rep = cr.autotune_report()
+    assert any("ik_stage1_ragged" in line for line in rep), rep
+    assert any("traj_build" in line for line in rep), rep
