@@ -251,14 +251,16 @@ def main():
     flops_per_seed = tally[0]
     flops_launch = flops_per_seed * P * S
     achieved = flops_launch / (stage_avg[0] * 1e-3) / 1e12
+    occ = [l.split("occupancy ")[1].split()[0] for l in (tuned or []) if "ik_stage1 n_seg 3 f32" in l]
+    kname = "k_ik_stage1<3,float,%s>" % occ[0] if occ else "k_ik_stage1<3,float,1>"  # 1: the compiler's own target
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             meas = json.load(f)
-        # counters describe the kernel built from these sources only
-        if meas.get("sources_sha256") == stage1_sources_hash():
+        # counters describe the kernel variant built from these sources only
+        if meas.get("sources_sha256") == stage1_sources_hash() and meas.get("kernel") == kname:
             traffic = meas.get("bytes_per_launch")
-    roofline = dict(bound="alu", kernel="k_ik_stage1<3,float>", achieved=round(achieved, 3),
+    roofline = dict(bound="alu", kernel=kname, achieved=round(achieved, 3),
                     peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=traffic, launch_ms=round(stage_avg[0], 4),
                     flops_per_launch=flops_launch, flops_per_seed=round(flops_per_seed, 1),
