@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--baseline-problems", type=int, default=2,
+                    help="path / trajectory problems timed with the plain per-problem baseline (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the compiler's own occupancy targets instead of the library's launch autotuning")
     ap.add_argument("--tally-seeds", type=int, default=256)
@@ -163,6 +165,47 @@ def cpu_baseline(spec, T_host, seeds, budget_s):
     return dict(value=done / el, unit="IK solves/s", cores=1, kind="oracle",
                 sample=f"first {done} of {spec['P']} targets x {S} seeds, full {spec['k_init']}+{spec['k_final']} "
                        f"iterations, single thread, {el:.1f} s; {solved}/{done} solved")
+
+
+def traj_baseline_rate(cr, torch, d, spec, opts, weights, args, fused_rate):
+    """The plain per-problem FP32 path / trajectory solve (cr_baseline_solve_path /
+    _traj) on the first problems of the workload: problems run one after another,
+    so its rate on a prefix is its rate on the batch.  One problem is solved
+    first as a warm-up."""
+    if args.baseline_problems <= 0:
+        return None
+    robot, P, S, H = d["robot"], d["P"], d["S"], d["H"]
+    Tn, n = H + 1, robot.n
+    p = min(args.baseline_problems, P)
+    if spec["kind"] == "path":
+        task = d["task"][:, :p * Tn].contiguous()
+        fn = cr.baseline_solve_path
+    else:
+        task = d["task"][:, :p].contiguous()
+        fn = cr.baseline_solve_traj
+    useed = d["useed"][:, :p * S * Tn].contiguous()
+    sph = d["spheres"]
+    if sph is not None:
+        sph = (sph[0][:, :p * sph[2]].contiguous(), sph[1], sph[2])
+    b0_opts = cr.Opts(n_final=opts.n_final, k_init=opts.k_init, k_final=opts.k_final)  # no exploration stage
+    fn(robot, (task[:, :Tn] if spec["kind"] == "path" else task[:, :1]).contiguous(), useed[:, :S * Tn].contiguous(),
+       H, weights, b0_opts,
+       spheres=None if sph is None else (sph[0][:, :sph[2]].contiguous(), sph[1], sph[2]))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, _, st = fn(robot, task, useed, H, weights, b0_opts, spheres=sph)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rate = p / (ms * 1e-3)
+    return dict(value=round(rate, 3), unit=("paths/s" if spec["kind"] == "path" else "trajectories/s"), problems=p,
+                ms=round(ms, 1), success_rate=round(float((st.cpu().numpy() == cr.SOLVED).mean()), 4),
+                speedup_of_fused=round(fused_rate / rate, 1),
+                kind="same Algorithm 1 budgets and LM rules, FP32, one problem at a time, separate kernels per step, "
+                     "forward-mode Jacobian, every point-sphere pair, one thread per trajectory for the banded solve"
+                     + ("; without the per-waypoint exploration stage (its seeds are used as they are), so its "
+                        "success rate is not comparable" if spec["kind"] == "path" else ""))
 
 
 def autotune(args, cr, torch, call):
@@ -395,6 +438,8 @@ def bench_trajectories(args, cr, I, torch):
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                 max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)],
                 autotune=tuned)
+    print("bench: timing the plain per-problem baseline", file=sys.stderr, flush=True)
+    line["plain_gpu_baseline"] = traj_baseline_rate(cr, torch, d, spec, opts, weights, args, line["value"])
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)

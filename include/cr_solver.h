@@ -292,6 +292,28 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_t
                                const void* u_seed, const cr_weights* weights, const cr_opts* opts, void* u_out,
                                void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The plain per-problem FP32 comparison solve for path following and trajectory
+ * planning: Algorithm 1 with the iteration counts and LM rules of cr_solve_path /
+ * cr_solve_traj, but one problem at a time (its S trajectories), FP32 throughout
+ * (stage 2 included), a separate kernel per step with every intermediate in HBM,
+ * each waypoint's rows (pose, bounds, clearance of every backbone point against
+ * every sphere, no culls) differentiated by forward-mode dual numbers, the
+ * coupling rows assembled from the lifts' and tip positions' derivatives, and the
+ * block-banded normal equations factored by one thread per trajectory.  The final
+ * choice and its FP64 assessment are those of cr_solve_path / cr_solve_traj.
+ * Arguments, layouts and outputs as cr_solve_path / cr_solve_traj (no dtype;
+ * 1 <= S <= 4096).  ws: cr_baseline_traj_workspace() bytes, or NULL to allocate
+ * stream-ordered.  For timing against the fused solver; not used by it. */
+cr_status cr_baseline_solve_path(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                                 const void* T_ref, int32_t S, const void* u_seed, const cr_weights* weights,
+                                 const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+cr_status cr_baseline_solve_traj(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                                 const void* u_start_goal, int32_t S, const void* u_seed,
+                                 const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
+                                 int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t cr_baseline_traj_workspace(const cr_robot* robot, int32_t H, int32_t S, const cr_opts* opts);
+
 /* ------------------------------------------------------------------------- */
 /* Instrumentation (benchmarks).                                               */
 /* ------------------------------------------------------------------------- */

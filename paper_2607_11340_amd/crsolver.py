@@ -29,6 +29,7 @@ SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
+           "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_baseline_traj_workspace",
            "cr_select_top",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_autotune_enable", "cr_autotune_clear", "cr_autotune_force",
            "cr_autotune_report", "cr_status_string", "cr_last_error")
@@ -145,6 +146,10 @@ def _load():
     L.cr_solve_traj_workspace.argtypes = [R, i64, i32, i32, O, C.c_int]
     L.cr_solve_traj_workspace.restype = C.c_size_t
     L.cr_baseline_solve_ik.argtypes = [R, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
+    L.cr_baseline_solve_path.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
+    L.cr_baseline_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
+    L.cr_baseline_traj_workspace.argtypes = [R, i32, i32, O]
+    L.cr_baseline_traj_workspace.restype = C.c_size_t
     PR = C.POINTER(_Problem)
     L.cr_solve_batch.argtypes = [R, i32, PR, i64, vp, vp, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, i32, vp]
     L.cr_solve_batch_workspace.argtypes = [R, i32, PR, i64, O, C.c_int]
@@ -169,7 +174,7 @@ def _load():
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
     for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
-                 "cr_baseline_solve_ik", "cr_select_top",
+                 "cr_baseline_solve_ik", "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_select_top",
                  "cr_timing_read", "cr_ik_flop_tally"):
         getattr(L, name).restype = C.c_int
     return L
@@ -307,7 +312,7 @@ def traj_workspace_bytes(robot: Robot, P: int, H: int, S: int, opts: Opts, dtype
 
 
 def _solve_traj(kind: str, robot: Robot, task: torch.Tensor, u_seed: torch.Tensor, H: int, weights, opts, dtype,
-                spheres, workspace, out):
+                spheres, workspace, out, baseline=False):
     weights = weights or Weights()
     opts = opts or Opts(n_final=4, k_init=100, k_final=20)
     n, T = robot.n, H + 1
@@ -329,6 +334,11 @@ def _solve_traj(kind: str, robot: Robot, task: torch.Tensor, u_seed: torch.Tenso
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    if baseline:
+        fn = lib.cr_baseline_solve_path if kind == "path" else lib.cr_baseline_solve_traj
+        _check(fn(C.byref(rc), C.byref(sc), P, H, _ptr(task), S, _ptr(u_seed), C.byref(wc), C.byref(oc),
+                  _ptr(u_out), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _stream(task)))
+        return u_out, err, st
     fn = lib.cr_solve_path if kind == "path" else lib.cr_solve_traj
     _check(fn(C.byref(rc), C.byref(sc), P, H, _ptr(task), S, _ptr(u_seed), C.byref(wc), C.byref(oc), _ptr(u_out),
               _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype), _stream(task)))
@@ -350,7 +360,22 @@ def solve_traj(robot: Robot, u_start_goal: torch.Tensor, u_seed: torch.Tensor, H
     return _solve_traj("traj", robot, u_start_goal, u_seed, H, weights, opts, dtype, spheres, workspace, out)
 
 
-KIND = {"ik": 0, "path": 1, "traj": 2}
+def baseline_solve_path(robot: Robot, T_ref: torch.Tensor, u_seed: torch.Tensor, H: int, weights: Weights = None,
+                        opts: Opts = None, spheres=None, out=None):
+    """The plain per-problem FP32 comparison solve for path following
+    (cr_baseline_solve_path); arrays as solve_path."""
+    return _solve_traj("path", robot, T_ref, u_seed, H, weights, opts, torch.float32, spheres, None, out,
+                       baseline=True)
+
+
+def baseline_solve_traj(robot: Robot, u_start_goal: torch.Tensor, u_seed: torch.Tensor, H: int,
+                        weights: Weights = None, opts: Opts = None, spheres=None, out=None):
+    """The plain per-problem FP32 comparison solve for trajectories
+    (cr_baseline_solve_traj); arrays as solve_traj."""
+    return _solve_traj("traj", robot, u_start_goal, u_seed, H, weights, opts, torch.float32, spheres, None, out,
+                       baseline=True)
+
+
 BATCH_GRAPH = 1
 
 

@@ -338,6 +338,54 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_t
   return rc;
 }
 
+static cr_status baseline_traj_common(int kind, const cr_robot* robot, const cr_spheres* spheres, int64_t P,
+                                      int32_t H, const void* task, int32_t S, const void* u_seed,
+                                      const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
+                                      int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  cr_status rc = check_traj_args(robot, spheres, weights, opts, P, H, S, kind, CR_F32);
+  if (rc != CR_OK) return rc;
+  if (S > 4096) return fail(CR_EINVAL, "S=%d exceeds 4096", S);
+  if (P == 0) return CR_OK;
+  if (!task || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
+  const size_t need = b0_traj_workspace_bytes(*robot, S, H, *opts);
+  void* mem = ws;
+  if (ws) {
+    if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  } else {
+    rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
+    if (rc != CR_OK) return rc;
+  }
+  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  rc = launch_b0_traj(kind, *robot, sp, P, H, (const double*)task, S, (const double*)u_seed, *weights, *opts,
+                      (double*)u_out, (double*)err_out, status_out, mem, stream);
+  if (!ws) {
+    cr_status rc2 = check_hip(hipFreeAsync(mem, stream), "hipFreeAsync(workspace)");
+    if (rc == CR_OK) rc = rc2;
+  }
+  return rc;
+}
+
+cr_status cr_baseline_solve_path(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                                 const void* T_ref, int32_t S, const void* u_seed, const cr_weights* weights,
+                                 const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+  return baseline_traj_common(CR_KIND_PATH, robot, spheres, P, H, T_ref, S, u_seed, weights, opts, u_out, err_out,
+                              status_out, ws, ws_bytes, stream);
+}
+
+cr_status cr_baseline_solve_traj(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
+                                 const void* u_start_goal, int32_t S, const void* u_seed, const cr_weights* weights,
+                                 const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+  return baseline_traj_common(CR_KIND_TRAJ, robot, spheres, P, H, u_start_goal, S, u_seed, weights, opts, u_out,
+                              err_out, status_out, ws, ws_bytes, stream);
+}
+
+size_t cr_baseline_traj_workspace(const cr_robot* robot, int32_t H, int32_t S, const cr_opts* opts) {
+  if (check_robot(robot) != CR_OK || check_opts(opts) != CR_OK || S < 1 || S > 4096 || H < 0 || H > 255) return 0;
+  return b0_traj_workspace_bytes(*robot, S, H, *opts);
+}
+
 void cr_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_timer.mu);
   timer_release_all();

@@ -168,6 +168,16 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
                       int32_t flags, hipStream_t stream);
 
 size_t b0_workspace_bytes(const cr_robot& rb, int S, const cr_opts& o);
+size_t b0_traj_workspace_bytes(const cr_robot& rb, int S, int H, const cr_opts& o);
+cr_status launch_b0_traj(int kind, const cr_robot& rb, const cr_spheres* sp, int64_t P, int H, const double* task,
+                         int S, const double* useed, const cr_weights& w, const cr_opts& o, double* u_out,
+                         double* err_out, int32_t* status_out, void* wsmem, hipStream_t st);
+// FP64 assessment and argmin of one path / trajectory problem's FP32 candidates
+// (table row `row`, candidates local to it: nf kept ones with sel, or all S).
+cr_status launch_traj_assess_f32(int kind, const cr_robot& rb, const TrajProb* row, const double* task,
+                                 const double* sph, int Tn, int nf, const int32_t* sel, const float* Zc,
+                                 const float* costc, const int32_t* failedc, int64_t err_ld, double* u_out,
+                                 double* err_out, int32_t* status_out, hipStream_t st);
 cr_status launch_b0_ik(const cr_robot& rb, int64_t P, const double* T, int S, const double* useed,
                        const cr_weights& w, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
                        void* wsmem, hipStream_t st);

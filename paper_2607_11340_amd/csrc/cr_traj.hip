@@ -1551,6 +1551,31 @@ static cr_status run_traj(int kind, const cr_robot& rb0, const TrajShape& sh, co
   return check_hip(hipGetLastError(), "trajectory solve");
 }
 
+cr_status launch_traj_assess_f32(int kind, const cr_robot& rb0, const TrajProb* row, const double* task,
+                                 const double* sph, int Tn, int nf, const int32_t* sel, const float* Zc,
+                                 const float* costc, const int32_t* failedc, int64_t err_ld, double* u_out,
+                                 double* err_out, int32_t* status_out, hipStream_t st) {
+  const RobotT<double> rbd = robot_to<double>(rb0);
+  const TrajArgs<double> ta{kind, 1, 0, Tn, row, task, sph};
+#define CR_ASSESS_CASE(N)                                                                                          \
+  case N:                                                                                                          \
+    hipLaunchKernelGGL((k_traj_finalize<N, float>), dim3(1), dim3(threads_for(Tn)), 0, st, rbd, ta, nf, sel, Zc,   \
+                       costc, failedc, err_ld, u_out, err_out, status_out);                                        \
+    break;
+  switch (rb0.n_seg) {
+    CR_ASSESS_CASE(1)
+    CR_ASSESS_CASE(2)
+    CR_ASSESS_CASE(3)
+    CR_ASSESS_CASE(4)
+    CR_ASSESS_CASE(5)
+    CR_ASSESS_CASE(6)
+    default:
+      return fail(CR_EINVAL, "n_seg out of range");
+  }
+#undef CR_ASSESS_CASE
+  return check_hip(hipGetLastError(), "trajectory assessment");
+}
+
 cr_status launch_traj_group(int kind, const cr_robot& rb, const TrajShape& sh, const TrajProb* tp, const double* task,
                             const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
                             double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,

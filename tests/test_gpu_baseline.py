@@ -57,3 +57,78 @@ def test_baseline_two_stage_quality(oracle, cr):
     for p in range(24):
         pe = oracle.pose_error(ro, oracle.u_to_z(ro, u[p]), T[p])
         assert abs(err[p, 0] - pe[1]) < 1e-12 and abs(err[p, 1] - pe[2]) < 1e-9
+
+
+def _b0_traj(cr, c, opts):
+    """The plain path / trajectory baseline on a case of test_gpu_traj.case()."""
+    from test_gpu_traj import soa as _soa
+    n, P, S, H, M = c["n"], c["P"], c["S"], c["H"], c["M"]
+    rg = cr.Robot(L=c["L"], r=c["r"], u_max=list(c["ro"].u_max), pts_per_seg=c["K"], theta_max=c["ro"].theta_max)
+    if c["kind"] == "path":
+        task = torch.tensor(_soa(c["task"], 2), device="cuda")
+    else:
+        task = torch.tensor(np.concatenate([c["task"][:, 0].reshape(P, -1), c["task"][:, 1].reshape(P, -1)], 1).T.copy(),
+                            device="cuda")
+    us = torch.tensor(_soa(c["seeds"], 2), device="cuda")
+    sp = None
+    if M > 0:
+        sp = (torch.tensor(np.ascontiguousarray(c["sph"][:, :M].reshape(P * M, 4).T), device="cuda"), True, M)
+    fn = cr.baseline_solve_path if c["kind"] == "path" else cr.baseline_solve_traj
+    u, err, st = fn(rg, task, us, H, cr.Weights(**c["W"]), opts, spheres=sp)
+    torch.cuda.synchronize()
+    return aos(u.cpu().numpy(), (n, 3)).reshape(P, H + 1, n, 3), err.cpu().numpy().T, st.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["path", "traj"])
+@pytest.mark.parametrize("n,k", [(1, 1), (1, 2), (3, 1)])
+def test_baseline_traj_iterates(oracle, cr, kind, n, k):
+    """Plain method, one seed per problem, with clearance, bound and kinodynamic
+    hinges active: k FP32 iterations of the baseline equal the oracle's FP64
+    iterates to FP32 accuracy."""
+    print(f"baseline trajectory iterates kind={kind} n={n} k={k}", flush=True)
+    from test_gpu_traj import case, oracle_problem
+    c = case(oracle, kind, 700 + 10 * n + k, n=n, H=9, P=3, S=1, M=3)
+    u, _, _ = _b0_traj(cr, c, cr.Opts(n_final=0, k_init=k, k_final=0))
+    W = oracle.Weights(**c["W"])
+    worst = 0.0
+    for p in range(c["P"]):
+        pb = oracle_problem(oracle, c, p)
+        z0 = oracle.u_to_z(c["ro"], c["seeds"][p, 0]).ravel()
+        zk, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, k)
+        uk = oracle.z_to_u(c["ro"], zk.reshape(c["H"] + 1, c["n"], 2))
+        worst = max(worst, np.abs(u[p] - uk).max() / c["b"])
+    print(f"  max |u - u_oracle| / b = {worst:.3g}", flush=True)
+    assert worst <= 1e-4, worst
+
+
+def test_baseline_traj_quality(oracle, cr):
+    """Trajectories among spheres, two-stage settings, default weights: the
+    baseline solves the problems the fused FP32 solver solves (at most one fewer),
+    and what it reports for them is finite."""
+    print("baseline trajectory quality", flush=True)
+    from test_gpu_traj import case, gpu_solve
+    rng = np.random.default_rng(812)
+    n, H, P, S, M, K = 3, 11, 8, 8, 4, 8
+    L, r, b = [0.06] * n, [0.006] * n, 0.006
+    ro = oracle.Robot(L=L, r=r, u_max=[b] * n, pts_per_seg=K)
+    ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
+    seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, H + 1, b) for p in range(P)])
+    sph = np.zeros((P, M, 4))
+    for p in range(P):
+        _, _, pts = oracle.fk(ro, ends[p], points=True)
+        pts = pts.reshape(-1, 3)
+        m = 0
+        while m < M:  # spheres clear of the start and goal backbones
+            cand = np.concatenate([rng.uniform(-0.08, 0.08, 2), rng.uniform(0.02, 0.17, 1), rng.uniform(0.005, 0.015, 1)])
+            if (np.linalg.norm(pts - cand[:3], axis=1) - cand[3] - r[0]).min() > 1e-3:
+                sph[p, m] = cand
+                m += 1
+    c = dict(kind="traj", n=n, L=L, r=r, b=b, K=K, H=H, P=P, S=S, M=M, ro=ro, W={}, task=ends, seeds=seeds, sph=sph)
+    opts = cr.Opts(n_final=2, k_init=40, k_final=10)
+    _, _, st_f = gpu_solve(cr, c, opts, "f32")
+    u, err, st = _b0_traj(cr, c, opts)
+    print(f"  solved: fused {(st_f == cr.SOLVED).sum()}, baseline {(st == cr.SOLVED).sum()} of {P}", flush=True)
+    assert (st_f == cr.SOLVED).sum() >= P // 2, st_f
+    assert (st == cr.SOLVED).sum() >= (st_f == cr.SOLVED).sum() - 1, (st, st_f)
+    ok = st == cr.SOLVED
+    assert np.all(np.isfinite(u[ok])) and np.all(err[ok, 0] <= 1e-3)
