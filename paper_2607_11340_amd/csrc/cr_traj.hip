@@ -559,26 +559,38 @@ __global__ void __launch_bounds__(256)
 
 // OCC: the minimum waves per SIMD the register allocation must allow (1 = the
 // compiler's own choice); the autotuner picks among the compiled targets.
-template <int NS, typename T, int OCC = 1>
+template <int NS, typename T, int OCC = 1, int G = 1>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     k_traj_build(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, const T* __restrict__ Z, T* __restrict__ blk,
-                 T* __restrict__ cost0, int32_t* __restrict__ failed) {
+                 T* __restrict__ cost0, int32_t* __restrict__ failed, int64_t nt, int lds_per) {
   constexpr int NZ = 2 * NS, NU = 3 * NS, NP = NZ * (NZ + 1) / 2;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int64_t traj = blockIdx.x;
-  if (failed[traj]) return;  // uniform per workgroup
-  const TrajCtx cx = traj_ctx(ta, traj);
+  // G trajectories per workgroup (2 for horizons of at most 32 waypoints: one per
+  // half-wave), each with its own lds_per values of LDS
+  const int Tp = G == 1 ? (int)blockDim.x : 32;
+  const int sub = G == 1 ? 0 : (int)threadIdx.x / Tp;
+  const int t = (int)threadIdx.x - sub * Tp;
+  const int64_t traj = (int64_t)blockIdx.x * G + sub;
+  const bool live = traj < nt && !failed[traj];
+  if (G == 1 && !live) return;  // uniform per workgroup
+  TrajCtx cx;
+  cx.pr.Tn = 0;
+  cx.pr.M = 0;
+  cx.wp = 0;
+  if (live) cx = traj_ctx(ta, traj);
   const int Tn = cx.pr.Tn, H = Tn - 1, M = cx.pr.M;
-  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_sph = reinterpret_cast<T*>(smem_raw) + (size_t)sub * lds_per;
   T* s_u = s_sph + 4 * M;
   T* s_p = s_u + Tn * NU;
   T* s_jp = s_p + Tn * 3;
   T* s_red = s_jp + Tn * 3 * NZ;
-  stage_spheres(ta, cx, s_sph);
+  for (int i = t; i < 4 * M; i += Tp) {
+    const int m = i >> 2, c = i & 3;
+    s_sph[i] = (T)ta.sph[cx.pr.sph + c * cx.pr.sph_ld + m];
+  }
   __syncthreads();
-  const int t = threadIdx.x;
-  const bool act = t < Tn;
+  const bool act = live && t < Tn;
   T z[NZ], Hp[NP], g[NZ], ptip[3], Jp[3][NZ];
   T cst = T(0);
   if (act) {
@@ -751,8 +763,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 #pragma unroll
     for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
   }
-  const T total = block_sum_all(cst, s_red);
-  if (threadIdx.x == 0) {
+  T total;
+  if constexpr (G == 1) {
+    total = block_sum_all(cst, s_red);
+  } else {  // the trajectory's half-wave
+    total = cst;
+    for (int off = Tp >> 1; off > 0; off >>= 1) total += __shfl_xor(total, off, Tp);
+  }
+  if (live && t == 0) {
     cost0[traj] = total;
     if (!tfinite(total)) failed[traj] = 1;
   }
@@ -1450,14 +1468,22 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   const int threads = threads_for(ta.Tmax);
   const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax, nt);
   const size_t lds_b = traj_lds<NS, T>(ta.Tmax, Mmax, true), lds_s = traj_lds_list<NS, T>(ta.Tmax, Mmax, cap);
+  // two trajectories per normal-equation workgroup when both fit a half-wave
+  const int gb = ta.Tmax <= 32 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   // the normal-equation kernel rewrites the same records from the same z, so the
   // autotuner may time its variants on the first iteration
   auto build = [&](int v) {
     const int occ = tune_occ(TK_TRAJ_BUILD, v);
-#define CR_TB(O)                                                                                           \
-  hipLaunchKernelGGL((k_traj_build<NS, T, O>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z, blk, \
-                     c0, failed)
+#define CR_TB(O)                                                                                                   \
+  do {                                                                                                             \
+    if (gb == 2)                                                                                                   \
+      hipLaunchKernelGGL((k_traj_build<NS, T, O, 2>), dim3((unsigned)((nt + 1) / 2)), dim3(64), 2 * lds_b, st, rb, w, \
+                         ta, Z, blk, c0, failed, nt, (int)(lds_b / sizeof(T)));                                    \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_traj_build<NS, T, O, 1>), dim3((unsigned)nt), dim3(threads), lds_b, st, rb, w, ta, Z,  \
+                         blk, c0, failed, nt, (int)(lds_b / sizeof(T)));                                           \
+  } while (0)
     if constexpr (sizeof(T) == 4) {
       if (occ == tune_occ(TK_TRAJ_BUILD, 1)) CR_TB(tune_occ(TK_TRAJ_BUILD, 1));
       else if (occ == tune_occ(TK_TRAJ_BUILD, 2)) CR_TB(tune_occ(TK_TRAJ_BUILD, 2));
