@@ -1468,8 +1468,10 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   const int threads = threads_for(ta.Tmax);
   const int cap = traj_list_cap<NS, T>(ta.Tmax, Mmax, nt);
   const size_t lds_b = traj_lds<NS, T>(ta.Tmax, Mmax, true), lds_s = traj_lds_list<NS, T>(ta.Tmax, Mmax, cap);
-  // two trajectories per normal-equation workgroup when both fit a half-wave
-  const int gb = ta.Tmax <= 32 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
+  // two trajectories per normal-equation workgroup when both fit a half-wave and
+  // the launch is large enough to need several rounds of resident waves (small
+  // launches, such as the FP64 refinement, keep one wave per trajectory)
+  const int gb = ta.Tmax <= 32 && nt >= 4096 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
   constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
   // the normal-equation kernel rewrites the same records from the same z, so the
   // autotuner may time its variants on the first iteration
