@@ -123,10 +123,11 @@ __device__ __forceinline__ bool key_less(T ea, int fa, T eb, int fb) {
   return (fa & 0xffff) < (fb & 0xffff);
 }
 
-// LDS of k_select for up to Spad candidates, with room to stage stage_nz
-// coordinates per candidate (0: coordinates are read from z).
-static inline size_t select_lds(int Spad, int stage_nz, size_t tb) {
-  size_t b = (size_t)Spad * (tb + 4) + (size_t)Spad;
+// LDS of k_select for up to Spad candidates, with room to stage the penalties
+// (stage_pen) and stage_nz coordinates per candidate (0: coordinates are read
+// from z).
+static inline size_t select_lds(int Spad, int stage_pen, int stage_nz, size_t tb) {
+  size_t b = (size_t)Spad * ((stage_pen ? 2 : 1) * tb + 4) + (size_t)Spad;
   b = (b + 7) & ~(size_t)7;
   b += 64 * 4;
   return b + (size_t)Spad * stage_nz * tb;
@@ -137,14 +138,16 @@ static inline size_t select_lds(int Spad, int stage_nz, size_t tb) {
 // count, key base and z layout (ragged batches, trajectories).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_select(int64_t P, int S0, int Spad0, int nz0, int stage_nz, const T* __restrict__ z, int64_t zs_m,
+    k_select(int64_t P, int S0, int Spad0, int nz0, int stage_pen, int stage_nz, const T* __restrict__ z, int64_t zs_m,
              int64_t zs_c, const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed,
              int n_final, T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* se = reinterpret_cast<T*>(smem);
-  int* sf = reinterpret_cast<int*>(se + Spad0);
+  T* spen = se + Spad0;  // penalties for the duplicate rule, when staged
+  int* sf = reinterpret_cast<int*>(stage_pen ? spen + Spad0 : spen);
   unsigned char* skipped = reinterpret_cast<unsigned char*>(sf + Spad0);
-  int* kept = reinterpret_cast<int*>(smem + ((((size_t)Spad0 * (sizeof(T) + 4) + Spad0) + 7) & ~(size_t)7));
+  int* kept = reinterpret_cast<int*>(
+      smem + ((((size_t)Spad0 * ((stage_pen ? 2 : 1) * sizeof(T) + 4) + Spad0) + 7) & ~(size_t)7));
   T* sz = reinterpret_cast<T*>(kept + 64);
   const int64_t p = blockIdx.x;
   int S = S0, nz = nz0, Spad = Spad0;
@@ -165,6 +168,7 @@ __global__ void __launch_bounds__(256)
       T ev = e[kb + i];
       int fl = (failed && failed[kb + i] == 1) || !tfinite(ev) ? 1 : 0;
       se[i] = ev;
+      if (stage_pen) spen[i] = pen[kb + i];
       sf[i] = (fl << 16) | i;
     } else {
       se[i] = T(0);
@@ -206,58 +210,114 @@ __global__ void __launch_bounds__(256)
   // keep them consistent without a barrier.
   const int lane = (int)threadIdx.x;
   auto coord = [&](int c, int m) -> T { return staged ? sz[c * nz + m] : z[zb + m * zs_m + c * zc]; };
+  auto penalty = [&](int c) -> T { return stage_pen ? spen[c] : pen[kb + c]; };
   int nk = 0;
-  for (int q = 0; q < S && nk < n_final; ++q) {
-    const int f = sf[q];
-    if ((f >> 16) != 0) break;
-    const int c = f & 0xffff;
-    // bit k: some coordinate differs from kept candidate k by more than dup_eps
-    // (a NaN difference never counts, as in a running maximum that skips NaN)
-    unsigned long long kfar = 0ull;
-    const int np = nk * nz;
-    for (int base = 0; base < np; base += 64) {
-      const int pi = base + lane;
-      bool far = false;
-      if (pi < np) {
-        const int k = pi / nz, m = pi - k * nz;
-        far = fabs(coord(c, m) - coord(kept[k], m)) > dup_eps;
+  if (nz <= 16) {
+    // Short candidates: 64 candidates at a time, one per lane, each tested against
+    // the kept set; the decisions that change the kept set (a new distinct
+    // candidate, a duplicate with a lower penalty) are taken in order, and the
+    // lanes after each one are tested again, so every decision sees the kept set
+    // that the candidate-by-candidate rule would.
+    // A NaN difference never counts as far, as in a running maximum that skips NaN.
+    auto first_dup = [&](int c) -> int {
+      for (int k = 0; k < nk; ++k) {
+        const int ck = kept[k];
+        bool far = false;
+        for (int m = 0; m < nz; ++m) far = far || (fabs(coord(c, m) - coord(ck, m)) > dup_eps);
+        if (!far) return k;
       }
-      const unsigned long long fm = __ballot(far);
-      if (fm != 0ull) {
-        const int k0 = base / nz;
-        const int k1 = (base + 63) / nz < nk - 1 ? (base + 63) / nz : nk - 1;
-        for (int k = k0; k <= k1; ++k) {
-          const int lo = k * nz - base > 0 ? k * nz - base : 0;
-          const int hi = (k + 1) * nz - base < 64 ? (k + 1) * nz - base : 64;
-          const unsigned long long win = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
-          if (fm & win) kfar |= 1ull << k;
+      return -1;
+    };
+    bool last = false;
+    for (int base = 0; base < S && nk < n_final && !last; base += 64) {
+      const int q = base + lane;
+      const int f = q < S ? sf[q] : (2 << 16);
+      const bool valid = (f >> 16) == 0;  // the valid candidates are a prefix of the order
+      const int c = f & 0xffff;
+      last = __ballot(!valid) != 0ull;
+      int dup = valid ? first_dup(c) : -1;
+      int i = 0;  // first lane not decided yet
+      while (i < 64 && nk < n_final) {
+        const bool open = valid && lane >= i;
+        const bool ev = open && (dup < 0 || penalty(c) < penalty(kept[dup]));
+        const unsigned long long em = __ballot(ev);
+        if (em == 0ull) {
+          if (open) skipped[c] = 1;
+          break;
+        }
+        const int j = __builtin_ctzll(em);
+        if (open && lane < j) skipped[c] = 1;
+        const int cj = __shfl(c, j, 64), dj = __shfl(dup, j, 64);
+        if (dj < 0) {
+          kept[nk] = cj;
+          ++nk;
+        } else {
+          skipped[kept[dj]] = 1;
+          kept[dj] = cj;
+        }
+        i = j + 1;
+        if (valid && lane >= i) dup = first_dup(c);
+      }
+    }
+  } else {
+    // Long candidates (trajectories): one candidate at a time, all lanes comparing
+    // it with the kept ones, one lane per (kept candidate, coordinate) pair.
+    for (int q = 0; q < S && nk < n_final; ++q) {
+      const int f = sf[q];
+      if ((f >> 16) != 0) break;
+      const int c = f & 0xffff;
+      // bit k: some coordinate differs from kept candidate k by more than dup_eps
+      // (a NaN difference never counts, as in a running maximum that skips NaN)
+      unsigned long long kfar = 0ull;
+      const int np = nk * nz;
+      for (int base = 0; base < np; base += 64) {
+        const int pi = base + lane;
+        bool far = false;
+        if (pi < np) {
+          const int k = pi / nz, m = pi - k * nz;
+          far = fabs(coord(c, m) - coord(kept[k], m)) > dup_eps;
+        }
+        const unsigned long long fm = __ballot(far);
+        if (fm != 0ull) {
+          const int k0 = base / nz;
+          const int k1 = (base + 63) / nz < nk - 1 ? (base + 63) / nz : nk - 1;
+          for (int k = k0; k <= k1; ++k) {
+            const int lo = k * nz - base > 0 ? k * nz - base : 0;
+            const int hi = (k + 1) * nz - base < 64 ? (k + 1) * nz - base : 64;
+            const unsigned long long win = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+            if (fm & win) kfar |= 1ull << k;
+          }
+        }
+      }
+      const unsigned long long near = ~kfar & (nk >= 64 ? ~0ull : ((1ull << nk) - 1ull));
+      if (near == 0ull) {
+        kept[nk] = c;
+        ++nk;
+      } else {
+        const int dup = __builtin_ctzll(near);  // the first kept candidate it duplicates
+        const int kd = kept[dup];
+        if ((stage_pen ? spen[c] : pen[kb + c]) < (stage_pen ? spen[kd] : pen[kb + kd])) {
+          skipped[kd] = 1;
+          kept[dup] = c;
+        } else {
+          skipped[c] = 1;
         }
       }
     }
-    const unsigned long long near = ~kfar & (nk >= 64 ? ~0ull : ((1ull << nk) - 1ull));
-    if (near == 0ull) {
-      kept[nk] = c;
-      ++nk;
-    } else {
-      const int dup = __builtin_ctzll(near);  // the first kept candidate it duplicates
-      const int kd = kept[dup];
-      if (pen[kb + c] < pen[kb + kd]) {
-        skipped[kd] = 1;
-        kept[dup] = c;
-      } else {
-        skipped[c] = 1;
-      }
-    }
   }
-  for (int q = 0; q < S && nk < n_final; ++q) {
-    const int f = sf[q];
-    if ((f >> 16) != 0) break;
+  // Not enough distinct candidates: the skipped ones fill up the list in order.
+  for (int base = 0; base < S && nk < n_final; base += 64) {
+    const int q = base + lane;
+    const int f = q < S ? sf[q] : (2 << 16);
+    const bool valid = (f >> 16) == 0;
     const int c = f & 0xffff;
-    if (skipped[c]) {
-      kept[nk] = c;
-      ++nk;
-      skipped[c] = 0;
-    }
+    const bool take = valid && skipped[c];
+    const unsigned long long tm = __ballot(take);
+    const int rank =
+        (int)__builtin_amdgcn_mbcnt_hi((unsigned)(tm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)tm, 0u));
+    if (take && nk + rank < n_final) kept[nk + rank] = c;
+    nk = nk + __popcll(tm) < n_final ? nk + __popcll(tm) : n_final;
+    if (__ballot(!valid) != 0ull) break;
   }
   if (lane < n_final) idx_out[(int64_t)lane * P + p] = lane < nk ? kept[lane] : -1;
 }
@@ -721,16 +781,18 @@ cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z,
   const size_t tb = dtype == CR_F64 ? 8 : 4;
   // stage the coordinates when every problem's fit in 32 KiB (nz == 0: per-row
   // counts unknown here, read from z)
-  const int stage_nz = nz > 0 && (size_t)Spad * nz * tb <= 32 * 1024 ? nz : 0;
-  const size_t lds = select_lds(Spad, stage_nz, tb);
+  const int stage_pen = select_lds(Spad, 1, 0, tb) <= 64 * 1024 ? 1 : 0;
+  int stage_nz = nz > 0 && (size_t)Spad * nz * tb <= 32 * 1024 ? nz : 0;
+  if (select_lds(Spad, stage_pen, stage_nz, tb) > 64 * 1024) stage_nz = 0;
+  const size_t lds = select_lds(Spad, stage_pen, stage_nz, tb);
   if (P == 0) return CR_OK;
   if (dtype == CR_F64)
-    hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_nz,
-                       (const double*)z, zs_m, zs_c, (const double*)e, (const double*)pen, failed, (int)n_final,
+    hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_pen,
+                       stage_nz, (const double*)z, zs_m, zs_c, (const double*)e, (const double*)pen, failed, (int)n_final,
                        dup_eps, rows, idx_out);
   else
-    hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_nz,
-                       (const float*)z, zs_m, zs_c, (const float*)e, (const float*)pen, failed, (int)n_final,
+    hipLaunchKernelGGL((k_select<float>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_pen,
+                       stage_nz, (const float*)z, zs_m, zs_c, (const float*)e, (const float*)pen, failed, (int)n_final,
                        (float)dup_eps, rows, idx_out);
   return check_hip(hipGetLastError(), "k_select");
 }

@@ -100,7 +100,7 @@ def test_select_top_parity(oracle, cr, dtype):
     rng = np.random.default_rng(31)
     td = torch.float64 if dtype == "f64" else torch.float32
     npd = np.float64 if dtype == "f64" else np.float32
-    for S, P, nf, nz in [(1, 3, 2, 4), (5, 7, 3, 4), (64, 37, 8, 4), (300, 11, 8, 4), (2048, 2, 64, 4),
+    for S, P, nf, nz in [(1, 3, 2, 4), (5, 7, 3, 4), (64, 37, 8, 4), (300, 11, 8, 4), (2048, 2, 64, 4), (4096, 2, 8, 4),
                          (64, 5, 8, 100), (40, 3, 16, 70)]:
         e = (rng.integers(0, 12, size=(P, S)) * 0.25).astype(npd)   # many exact ties
         if nz <= 4:
