@@ -104,3 +104,29 @@ def test_batch_variants(oracle, cr):
     rep = cr.autotune_report()
     assert any("ik_stage1_ragged" in line for line in rep), rep
     assert any("traj_build" in line for line in rep), rep
+
+
+def test_graph_capture_with_empty_cache(oracle, cr):
+    """Tuning on but nothing cached when a batch graph is captured: nothing can be
+    timed under capture, so the graph holds the compiler's own variants; its
+    replays equal an eager run forced to them, and the cache stays empty."""
+    print("autotune under graph capture", flush=True)
+    from test_gpu_batch import mixed_problems, robots, weights3
+    _, rg = robots(oracle, cr)
+    batch = cr.Batch(rg, mixed_problems(oracle, 504))
+    opts = [cr.Opts(n_final=2, k_init=8, k_final=2)] * 3
+    W = weights3(cr)
+    ws = torch.empty(cr.batch_workspace_bytes(batch, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    dev = tuple(torch.tensor(a if a.size else [0.0], dtype=torch.float64, device="cuda")
+                for a in (batch.task, batch.seed, batch.sph))
+    cr.autotune_force(0)
+    ref = run(lambda: cr.solve_batch(batch, W, opts, dtype=torch.float32, workspace=ws, dev_arrays=dev))
+    cr.autotune_force(-1)
+    cr.autotune(True)
+    out = (torch.empty_like(ref[0]), torch.empty_like(ref[1]), torch.empty_like(ref[2]))
+    for rep in range(2):
+        cr.solve_batch(batch, W, opts, dtype=torch.float32, workspace=ws, dev_arrays=dev, graph=True, out=out)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), rep
+    assert cr.autotune_report() == []
