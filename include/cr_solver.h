@@ -288,9 +288,10 @@ cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const v
  * intermediate passes through HBM; no graph.  Arguments as cr_solve_ik (no
  * spheres, dtype fixed to FP32); ws at least S * (3n + 2)(2n + 6) * 4 + 64 KiB
  * bytes is always enough, or NULL/0 to let the library allocate. */
-cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_target, int32_t S,
-                               const void* u_seed, const cr_weights* weights, const cr_opts* opts, void* u_out,
-                               void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream);
+cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t P, const void* T_target,
+                               int32_t S, const void* u_seed, const cr_weights* weights, const cr_opts* opts,
+                               void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
 
 /* The plain per-problem FP32 comparison solve for path following and trajectory
  * planning: Algorithm 1 with the iteration counts and LM rules of cr_solve_path /

@@ -145,7 +145,7 @@ def _load():
     L.cr_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
     L.cr_solve_traj_workspace.argtypes = [R, i64, i32, i32, O, C.c_int]
     L.cr_solve_traj_workspace.restype = C.c_size_t
-    L.cr_baseline_solve_ik.argtypes = [R, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
+    L.cr_baseline_solve_ik.argtypes = [R, S, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
     L.cr_baseline_solve_path.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
     L.cr_baseline_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, vp]
     L.cr_baseline_traj_workspace.argtypes = [R, i32, i32, O]
@@ -285,9 +285,9 @@ def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights
 
 
 def baseline_solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,
-                      opts: Opts = None, out=None):
+                      opts: Opts = None, out=None, spheres=None):
     """The plain per-problem FP32 comparison solve (cr_baseline_solve_ik); arrays
-    as solve_ik."""
+    and spheres as solve_ik."""
     weights = weights or Weights()
     opts = opts or Opts()
     n, P = robot.n, T_target.shape[1]
@@ -301,8 +301,9 @@ def baseline_solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor
                torch.empty((P,), dtype=torch.int32, device=dev))
     u_out, err, st = out
     rc, wc, oc = robot.c(), weights.c(), opts.c()
-    _check(lib.cr_baseline_solve_ik(C.byref(rc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc), C.byref(oc),
-                                    _ptr(u_out), _ptr(err), _ptr(st), None, 0, _stream(T_target)))
+    sc = _spheres_c(spheres, torch.float64)
+    _check(lib.cr_baseline_solve_ik(C.byref(rc), C.byref(sc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc),
+                                    C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), None, 0, _stream(T_target)))
     return u_out, err, st
 
 

@@ -312,13 +312,15 @@ size_t cr_solve_batch_workspace(const cr_robot* robots, int32_t n_robots, const 
   return batch_workspace_bytes(robots, n_robots, probs, P, opts, dtype);
 }
 
-cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_target, int32_t S,
-                               const void* u_seed, const cr_weights* weights, const cr_opts* opts, void* u_out,
-                               void* err_out, int32_t* status_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t P, const void* T_target,
+                               int32_t S, const void* u_seed, const cr_weights* weights, const cr_opts* opts,
+                               void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
   cr_status rc;
   if ((rc = check_robot(robot)) != CR_OK || (rc = check_opts(opts)) != CR_OK || (rc = check_weights(weights)) != CR_OK)
     return rc;
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
+  if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
   if (P == 0) return CR_OK;
   if (!T_target || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
   const size_t need = b0_workspace_bytes(*robot, S, *opts);
@@ -329,8 +331,9 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, int64_t P, const void* T_t
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
     if (rc != CR_OK) return rc;
   }
-  rc = launch_b0_ik(*robot, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts, (double*)u_out,
-                    (double*)err_out, status_out, mem, stream);
+  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  rc = launch_b0_ik(*robot, sp, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
+                    (double*)u_out, (double*)err_out, status_out, mem, stream);
   if (!ws) {
     cr_status rc2 = check_hip(hipFreeAsync(mem, stream), "hipFreeAsync(workspace)");
     if (rc == CR_OK) rc = rc2;

@@ -385,7 +385,8 @@ __global__ void k_b0_target(const double* __restrict__ T, int64_t P, int64_t p, 
 template <int NS>
 __global__ void k_b0_finalize(RobotT<double> rb, int nc, const int32_t* __restrict__ sel, const float* __restrict__ zc,
                               const float* __restrict__ costc, const int32_t* __restrict__ flagc,
-                              const double* __restrict__ T, int64_t P, int64_t p, double* __restrict__ u_out,
+                              const double* __restrict__ T, int64_t P, int64_t p, const double* __restrict__ sph,
+                              int64_t sph_off, int64_t sph_ld, int M, double* __restrict__ u_out,
                               double* __restrict__ err_out, int32_t* __restrict__ status_out) {
   constexpr int NZ = 2 * NS;
   if (threadIdx.x != 0) return;
@@ -429,9 +430,149 @@ __global__ void k_b0_finalize(RobotT<double> rb, int nc, const int32_t* __restri
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
+  if (M > 0 && penetrates<NS, double>(rb, z, sph + sph_off, M, sph_ld)) st |= CR_COLLISION;
   err_out[p] = pos;
   err_out[P + p] = rot;
   status_out[p] = st == 0 ? CR_SOLVED : st;
+}
+
+// Cost rows of one waypoint configuration that involve it alone, in type D (float,
+// or a dual number carrying d/dz): pose (paths), bounds, clearance.  Calls
+// row(r, is_clearance) for every row; returns the lifts u [3n] and the tip position.
+template <int NS, typename D, typename F>
+__device__ void b0t_rows(const RobotT<D>& rb, const WeightsT<D>& w, int kind, const float* Tt, const double* sph,
+                         int64_t sph_off, int64_t sph_ld, int M, const D* z, D* u, D* ptip, F row) {
+  D Rc[9], pc[3];
+  for (int k = 0; k < 9; ++k) Rc[k] = D((k % 4 == 0) ? 1.0 : 0.0);
+  pc[0] = pc[1] = pc[2] = D(0.0);
+  const int K = rb.K;
+  for (int i = 0; i < NS; ++i) {
+    const D a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
+    for (int k = 1; k <= K && M > 0; ++k) {
+      D x[3];
+      seg_point(Rc, pc, a, b, rb.L[i], s, D((double)k / (double)K), x);
+      for (int m = 0; m < M; ++m) {
+        const float cx = (float)sph[sph_off + m], cy = (float)sph[sph_off + sph_ld + m];
+        const float cz = (float)sph[sph_off + 2 * sph_ld + m], rs = (float)sph[sph_off + 3 * sph_ld + m];
+        const float reach = rs + (float)rb.rd[i] + (float)w.margind;
+        const D d0 = x[0] - D(cx), d1 = x[1] - D(cy), d2 = x[2] - D(cz);
+        const D dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const D viol = D(reach) - dist;
+        if (viol > D(0.0)) row(w.sq_coll * viol, true);
+      }
+    }
+    ArcCoef<D> c = arc_coef<D, false>(s);
+    D Ri[9], di[3], q[3], Rn[9];
+    seg_R_d(a, b, rb.L[i], c, Ri, di);
+    mv3(Rc, di, q);
+    for (int k = 0; k < 3; ++k) pc[k] += q[k];
+    mm3(Rc, Ri, Rn);
+    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
+    ab_to_u(a, b, rb.r[i], u + 3 * i);
+    D ru[3], sg[3], rth;
+    bound_residuals<D, D>(rb, w, i, a, b, ru, sg, &rth);
+    for (int k = 0; k < 3; ++k) row(ru[k], false);
+    row(rth, false);
+  }
+  for (int k = 0; k < 3; ++k) ptip[k] = pc[k];
+  if (kind == CR_KIND_PATH) {
+    D Td[12], Re[9], te[3], om[3], rho[3], gam, dg;
+    for (int k = 0; k < 12; ++k) Td[k] = D(Tt[k]);
+    relative_pose(Rc, pc, Td, Re, te);
+    log_se3<D, false>(Re, te, om, rho, &gam, &dg);
+    for (int k = 0; k < 3; ++k) {
+      row(w.w_pos * rho[k], false);
+      row(w.w_rot * om[k], false);
+    }
+  }
+}
+
+// IK among spheres: the clearance rows vary in number (the active point-sphere
+// pairs), so J^T J and J^T r are accumulated as the dual-number rows are formed
+// (pose, bounds, clearance), and the cost with them.
+template <int NS>
+__global__ void k_b0_normal_sph(int S, RobotT<float> rb, WeightsT<float> w, const float* __restrict__ Tt,
+                                const double* __restrict__ sph, int64_t sph_off, int64_t sph_ld, int M,
+                                const float* __restrict__ z, float* __restrict__ Hp, float* __restrict__ g,
+                                float* __restrict__ c0, int32_t* __restrict__ flags) {
+  constexpr int NZ = 2 * NS, NU = 3 * NS, NP = NZ * (NZ + 1) / 2;
+  using D = Dual<NZ>;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || (flags[s] & 1)) return;
+  const RobotT<D> rd = robot_as<D>(rb);
+  const WeightsT<D> wd = weights_as<D>(w);
+  D zd[NZ], u[NU], pt[3];
+  for (int k = 0; k < NZ; ++k) {
+    zd[k] = D(z[k * S + s]);
+    zd[k].d[k] = 1.0f;
+  }
+  float tt[12];
+  for (int k = 0; k < 12; ++k) tt[k] = Tt[k];
+  float H[NP], gg[NZ], c = 0.0f;
+  for (int k = 0; k < NP; ++k) H[k] = 0.0f;
+  for (int k = 0; k < NZ; ++k) gg[k] = 0.0f;
+  b0t_rows<NS, D>(rd, wd, CR_KIND_PATH, tt, sph, sph_off, sph_ld, M, zd, u, pt, [&](const D& r, bool) {
+    c += 0.5f * r.v * r.v;
+    for (int a = 0; a < NZ; ++a) {
+      gg[a] += r.d[a] * r.v;
+      for (int b = 0; b <= a; ++b) H[tri(a, b)] += r.d[a] * r.d[b];
+    }
+  });
+  for (int k = 0; k < NP; ++k) Hp[k * S + s] = H[k];
+  for (int k = 0; k < NZ; ++k) g[k * S + s] = gg[k];
+  c0[s] = c;
+  if (!tfinite(c)) flags[s] |= 1;
+}
+
+// FP32 cost of the IK rows among spheres at z (pen: the clearance part).
+template <int NS>
+__device__ float b0_cost_sph(const RobotT<float>& rb, const WeightsT<float>& w, const float* tt, const double* sph,
+                             int64_t sph_off, int64_t sph_ld, int M, const float* z, float* pen) {
+  float u[3 * NS], pt[3], c = 0.0f, cp = 0.0f;
+  b0t_rows<NS, float>(rb, w, CR_KIND_PATH, tt, sph, sph_off, sph_ld, M, z, u, pt, [&](float r, bool coll) {
+    c += 0.5f * r * r;
+    if (coll) cp += 0.5f * r * r;
+  });
+  if (pen) *pen = cp;
+  return c;
+}
+
+template <int NS>
+__global__ void k_b0_trial_sph(int S, RobotT<float> rb, WeightsT<float> w, const float* __restrict__ Tt,
+                               const double* __restrict__ sph, int64_t sph_off, int64_t sph_ld, int M, float alpha,
+                               const float* __restrict__ z, const float* __restrict__ dl, float* __restrict__ zt,
+                               float* __restrict__ ct, const int32_t* __restrict__ flags) {
+  constexpr int NZ = 2 * NS;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || (flags[s] & 7)) return;
+  float tt[12], zz[NZ];
+  for (int k = 0; k < 12; ++k) tt[k] = Tt[k];
+  for (int k = 0; k < NZ; ++k) {
+    zz[k] = z[k * S + s] + alpha * dl[k * S + s];
+    zt[k * S + s] = zz[k];
+  }
+  ct[s] = b0_cost_sph<NS>(rb, w, tt, sph, sph_off, sph_ld, M, zz, nullptr);
+}
+
+// SelectTop keys among spheres: pose error, clearance penalty, cost.
+template <int NS>
+__global__ void k_b0_keys_sph(int S, RobotT<float> rb, WeightsT<float> w, const float* __restrict__ Tt,
+                              const double* __restrict__ sph, int64_t sph_off, int64_t sph_ld, int M,
+                              const float* __restrict__ z, float* __restrict__ e, float* __restrict__ pen,
+                              float* __restrict__ cost, int32_t* __restrict__ flags) {
+  constexpr int NZ = 2 * NS;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  float tt[12], zz[NZ];
+  for (int k = 0; k < 12; ++k) tt[k] = Tt[k];
+  for (int k = 0; k < NZ; ++k) zz[k] = z[k * S + s];
+  float ee, pn;
+  (void)ik_cost<NS>(rb, w, tt, zz, &ee);
+  const float c = b0_cost_sph<NS>(rb, w, tt, sph, sph_off, sph_ld, M, zz, &pn);
+  e[s] = ee;
+  pen[s] = pn;
+  cost[s] = c;
+  if (!tfinite(c) || !tfinite(ee)) flags[s] |= 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -480,18 +621,34 @@ size_t b0_workspace_bytes(const cr_robot& rb, int S, const cr_opts& o) {
   return b0_layout(rb.n_seg, S, o.n_final, nullptr, nullptr);
 }
 
+// Spheres of the problem being solved (M = 0: none).
+struct B0Sph {
+  const double* sph;
+  int64_t off, ld;
+  int M;
+};
+
 template <int NS>
 static cr_status b0_stage(const RobotT<float>& rb, const WeightsT<float>& w, const cr_opts& o, int S, int iters,
-                          const B0Ws& ws, float* z, hipStream_t st) {
+                          const B0Ws& ws, float* z, const B0Sph& sp, hipStream_t st) {
   const dim3 grid((S + 63) / 64), blk(64);
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL((k_b0_resjac<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, z, ws.r, ws.J, ws.c0, ws.flags);
-    hipLaunchKernelGGL((k_b0_normal<NS>), grid, blk, 0, st, S, ws.r, ws.J, ws.Hp, ws.g, ws.flags);
+    if (sp.M > 0) {
+      hipLaunchKernelGGL((k_b0_normal_sph<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, sp.sph, sp.off, sp.ld, sp.M, z,
+                         ws.Hp, ws.g, ws.c0, ws.flags);
+    } else {
+      hipLaunchKernelGGL((k_b0_resjac<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, z, ws.r, ws.J, ws.c0, ws.flags);
+      hipLaunchKernelGGL((k_b0_normal<NS>), grid, blk, 0, st, S, ws.r, ws.J, ws.Hp, ws.g, ws.flags);
+    }
     hipLaunchKernelGGL((k_b0_step<NS>), grid, blk, 0, st, S, ws.Hp, ws.g, ws.lam, ws.dl, ws.gd, ws.flags);
     float alpha = 1.0f;
     for (int tr = 0; tr < o.ls_max; ++tr) {
-      hipLaunchKernelGGL((k_b0_trial<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, alpha, z, ws.dl, ws.zt, ws.ct,
-                         ws.flags);
+      if (sp.M > 0)
+        hipLaunchKernelGGL((k_b0_trial_sph<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, sp.sph, sp.off, sp.ld, sp.M,
+                           alpha, z, ws.dl, ws.zt, ws.ct, ws.flags);
+      else
+        hipLaunchKernelGGL((k_b0_trial<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, alpha, z, ws.dl, ws.zt, ws.ct,
+                           ws.flags);
       hipLaunchKernelGGL((k_b0_accept<NS>), grid, blk, 0, st, S, tr, alpha, ws.c0, ws.gd, ws.ct, ws.zt, z, ws.acc,
                          ws.flags);
       alpha *= 0.5f;
@@ -503,9 +660,9 @@ static cr_status b0_stage(const RobotT<float>& rb, const WeightsT<float>& w, con
 }
 
 template <int NS>
-static cr_status b0_run(const cr_robot& rb0, int64_t P, const double* T, int S, const double* useed,
-                        const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
-                        const B0Ws& ws, hipStream_t st) {
+static cr_status b0_run(const cr_robot& rb0, const cr_spheres* spheres, int64_t P, const double* T, int S,
+                        const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
+                        int32_t* status_out, const B0Ws& ws, hipStream_t st) {
   const RobotT<float> rb = robot_to<float>(rb0);
   const WeightsT<float> w = weights_to<float>(w0);
   const RobotT<double> rbd = robot_to<double>(rb0);
@@ -513,13 +670,21 @@ static cr_status b0_run(const cr_robot& rb0, int64_t P, const double* T, int S, 
   const int nf = o.n_final;
   cr_status rc = CR_OK;
   for (int64_t p = 0; p < P && rc == CR_OK; ++p) {
+    B0Sph sp{nullptr, 0, 0, 0};
+    if (spheres && spheres->n_sph > 0)
+      sp = B0Sph{(const double*)spheres->sph, spheres->per_problem ? p * spheres->n_sph : 0, spheres->ld,
+                 spheres->n_sph};
     hipLaunchKernelGGL(k_b0_target, dim3(1), dim3(64), 0, st, T, P, p, ws.Tt);
     hipLaunchKernelGGL((k_b0_init<NS>), grid, blk, 0, st, S, P * (int64_t)S, p * (int64_t)S, useed, rb,
                        (float)o.lambda0, ws.z, ws.lam, ws.flags);
     hipLaunchKernelGGL(k_b0_fill, grid, blk, 0, st, S, ws.acc, -1);
-    rc = b0_stage<NS>(rb, w, o, S, o.k_init, ws, ws.z, st);
+    rc = b0_stage<NS>(rb, w, o, S, o.k_init, ws, ws.z, sp, st);
     if (rc != CR_OK) break;
-    hipLaunchKernelGGL((k_b0_keys<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, ws.z, ws.e, ws.pen, ws.cost, ws.flags);
+    if (sp.M > 0)
+      hipLaunchKernelGGL((k_b0_keys_sph<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, sp.sph, sp.off, sp.ld, sp.M, ws.z,
+                         ws.e, ws.pen, ws.cost, ws.flags);
+    else
+      hipLaunchKernelGGL((k_b0_keys<NS>), grid, blk, 0, st, S, rb, w, ws.Tt, ws.z, ws.e, ws.pen, ws.cost, ws.flags);
     if (nf > 0) {
       rc = launch_select(1, S, 2 * NS, ws.z, ws.e, ws.pen, ws.flags, nf, o.dup_eps, ws.sel, CR_F32, st);
       if (rc != CR_OK) break;
@@ -527,28 +692,33 @@ static cr_status b0_run(const cr_robot& rb0, int64_t P, const double* T, int S, 
       hipLaunchKernelGGL((k_b0_gather<NS>), g2, blk, 0, st, S, nf, ws.z, ws.sel, (float)o.lambda0, ws.z2, ws.lam,
                          ws.flags);
       hipLaunchKernelGGL(k_b0_fill, g2, blk, 0, st, nf, ws.acc, -1);
-      rc = b0_stage<NS>(rb, w, o, nf, o.k_final, ws, ws.z2, st);
+      rc = b0_stage<NS>(rb, w, o, nf, o.k_final, ws, ws.z2, sp, st);
       if (rc != CR_OK) break;
-      hipLaunchKernelGGL((k_b0_keys<NS>), g2, blk, 0, st, nf, rb, w, ws.Tt, ws.z2, ws.e, ws.pen, ws.cost, ws.flags);
+      if (sp.M > 0)
+        hipLaunchKernelGGL((k_b0_keys_sph<NS>), g2, blk, 0, st, nf, rb, w, ws.Tt, sp.sph, sp.off, sp.ld, sp.M, ws.z2,
+                           ws.e, ws.pen, ws.cost, ws.flags);
+      else
+        hipLaunchKernelGGL((k_b0_keys<NS>), g2, blk, 0, st, nf, rb, w, ws.Tt, ws.z2, ws.e, ws.pen, ws.cost,
+                           ws.flags);
       hipLaunchKernelGGL((k_b0_finalize<NS>), dim3(1), dim3(64), 0, st, rbd, nf, ws.sel, ws.z2, ws.cost, ws.flags, T,
-                         P, p, u_out, err_out, status_out);
+                         P, p, sp.sph, sp.off, sp.ld, sp.M, u_out, err_out, status_out);
     } else {
       hipLaunchKernelGGL((k_b0_finalize<NS>), dim3(1), dim3(64), 0, st, rbd, S, (const int32_t*)nullptr, ws.z,
-                         ws.cost, ws.flags, T, P, p, u_out, err_out, status_out);
+                         ws.cost, ws.flags, T, P, p, sp.sph, sp.off, sp.ld, sp.M, u_out, err_out, status_out);
     }
     rc = check_hip(hipGetLastError(), "baseline solve");
   }
   return rc;
 }
 
-cr_status launch_b0_ik(const cr_robot& rb, int64_t P, const double* T, int S, const double* useed,
-                       const cr_weights& w, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
-                       void* wsmem, hipStream_t st) {
+cr_status launch_b0_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, const double* T, int S,
+                       const double* useed, const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+                       int32_t* status_out, void* wsmem, hipStream_t st) {
   B0Ws ws;
   b0_layout(rb.n_seg, S, o.n_final, (char*)wsmem, &ws);
 #define CR_B0_CASE(N) \
   case N:             \
-    return b0_run<N>(rb, P, T, S, useed, w, o, u_out, err_out, status_out, ws, st);
+    return b0_run<N>(rb, sp, P, T, S, useed, w, o, u_out, err_out, status_out, ws, st);
   switch (rb.n_seg) {
     CR_B0_CASE(1)
     CR_B0_CASE(2)
@@ -632,57 +802,6 @@ __global__ void k_b0t_init(const TrajProb* __restrict__ row, const double* __res
 // Reference pose of waypoint t (paths), 12 values.
 __device__ inline void b0t_pose(const TrajProb& pr, const double* task, int t, float* Tt) {
   for (int c = 0; c < 12; ++c) Tt[c] = (float)task[pr.task + c * pr.task_ld + t];
-}
-
-// Cost rows of one waypoint configuration that involve it alone, in type D (float,
-// or a dual number carrying d/dz): pose (paths), bounds, clearance.  Calls
-// row(r, is_clearance) for every row; returns the lifts u [3n] and the tip position.
-template <int NS, typename D, typename F>
-__device__ void b0t_rows(const RobotT<D>& rb, const WeightsT<D>& w, int kind, const float* Tt, const double* sph,
-                         int64_t sph_off, int64_t sph_ld, int M, const D* z, D* u, D* ptip, F row) {
-  D Rc[9], pc[3];
-  for (int k = 0; k < 9; ++k) Rc[k] = D((k % 4 == 0) ? 1.0 : 0.0);
-  pc[0] = pc[1] = pc[2] = D(0.0);
-  const int K = rb.K;
-  for (int i = 0; i < NS; ++i) {
-    const D a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
-    for (int k = 1; k <= K && M > 0; ++k) {
-      D x[3];
-      seg_point(Rc, pc, a, b, rb.L[i], s, D((double)k / (double)K), x);
-      for (int m = 0; m < M; ++m) {
-        const float cx = (float)sph[sph_off + m], cy = (float)sph[sph_off + sph_ld + m];
-        const float cz = (float)sph[sph_off + 2 * sph_ld + m], rs = (float)sph[sph_off + 3 * sph_ld + m];
-        const float reach = rs + (float)rb.rd[i] + (float)w.margind;
-        const D d0 = x[0] - D(cx), d1 = x[1] - D(cy), d2 = x[2] - D(cz);
-        const D dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const D viol = D(reach) - dist;
-        if (viol > D(0.0)) row(w.sq_coll * viol, true);
-      }
-    }
-    ArcCoef<D> c = arc_coef<D, false>(s);
-    D Ri[9], di[3], q[3], Rn[9];
-    seg_R_d(a, b, rb.L[i], c, Ri, di);
-    mv3(Rc, di, q);
-    for (int k = 0; k < 3; ++k) pc[k] += q[k];
-    mm3(Rc, Ri, Rn);
-    for (int k = 0; k < 9; ++k) Rc[k] = Rn[k];
-    ab_to_u(a, b, rb.r[i], u + 3 * i);
-    D ru[3], sg[3], rth;
-    bound_residuals<D, D>(rb, w, i, a, b, ru, sg, &rth);
-    for (int k = 0; k < 3; ++k) row(ru[k], false);
-    row(rth, false);
-  }
-  for (int k = 0; k < 3; ++k) ptip[k] = pc[k];
-  if (kind == CR_KIND_PATH) {
-    D Td[12], Re[9], te[3], om[3], rho[3], gam, dg;
-    for (int k = 0; k < 12; ++k) Td[k] = D(Tt[k]);
-    relative_pose(Rc, pc, Td, Re, te);
-    log_se3<D, false>(Re, te, om, rho, &gam, &dg);
-    for (int k = 0; k < 3; ++k) {
-      row(w.w_pos * rho[k], false);
-      row(w.w_rot * om[k], false);
-    }
-  }
 }
 
 // Each waypoint's own rows by forward-mode dual numbers: H_tt, g_t, its cost, and

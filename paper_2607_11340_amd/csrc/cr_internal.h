@@ -178,9 +178,9 @@ cr_status launch_traj_assess_f32(int kind, const cr_robot& rb, const TrajProb* r
                                  const double* sph, int Tn, int nf, const int32_t* sel, const float* Zc,
                                  const float* costc, const int32_t* failedc, int64_t err_ld, double* u_out,
                                  double* err_out, int32_t* status_out, hipStream_t st);
-cr_status launch_b0_ik(const cr_robot& rb, int64_t P, const double* T, int S, const double* useed,
-                       const cr_weights& w, const cr_opts& o, double* u_out, double* err_out, int32_t* status_out,
-                       void* wsmem, hipStream_t st);
+cr_status launch_b0_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, const double* T, int S,
+                       const double* useed, const cr_weights& w, const cr_opts& o, double* u_out, double* err_out,
+                       int32_t* status_out, void* wsmem, hipStream_t st);
 
 // Totals of a path / trajectory launch: problems, stage-1 trajectories and
 // waypoint configurations, waypoints summed over problems, largest horizon + 1,

@@ -132,3 +132,55 @@ def test_baseline_traj_quality(oracle, cr):
     assert (st == cr.SOLVED).sum() >= (st_f == cr.SOLVED).sum() - 1, (st, st_f)
     ok = st == cr.SOLVED
     assert np.all(np.isfinite(u[ok])) and np.all(err[ok, 0] <= 1e-3)
+
+
+def _b0_sph(cr, ro, T, seeds, sph, opts):
+    P, S, M = seeds.shape[0], seeds.shape[1], sph.shape[1]
+    rg = cr.Robot(L=list(ro.L), r=list(ro.r), u_max=list(ro.u_max), pts_per_seg=ro.pts_per_seg)
+    sp = (torch.tensor(np.ascontiguousarray(sph.reshape(P * M, 4).T), device="cuda"), True, M)
+    u, err, st = cr.baseline_solve_ik(rg, torch.tensor(soa(T, 2), device="cuda"),
+                                      torch.tensor(soa(seeds, 2), device="cuda"), cr.Weights(), opts, spheres=sp)
+    torch.cuda.synchronize()
+    return aos(u.cpu().numpy(), (ro.n, 3)), err.cpu().numpy().T, st.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_baseline_ik_spheres_iterates(oracle, cr, k):
+    """IK among spheres in contact with the seeds' backbones: k FP32 iterations of
+    the baseline (clearance rows by dual numbers) equal the oracle's FP64 iterates
+    to FP32 accuracy.  The baseline forms the clearance residual, reach minus
+    distance, in FP32: for violations near 1e-4 m at coordinates near 0.2 m that
+    difference alone carries a relative error near 1e-4 (FP32 epsilon 6e-8 times
+    0.2 / 1e-4), which the steps of two iterations compound; hence 5e-4 of the
+    bound here (the fused FP32 kernels form it in FP64)."""
+    print(f"baseline ik spheres iterates k={k}", flush=True)
+    from test_gpu_ik_spheres import B3, sphere_case
+    ro, T, seeds, sph = sphere_case(oracle, 450 + k, P=16, S=1, M=6)
+    u, _, _ = _b0_sph(cr, ro, T, seeds, sph, cr.Opts(n_final=0, k_init=k, k_final=0))
+    worst = 0.0
+    for p in range(16):
+        pb = oracle.Problem("ik", T[p], spheres=sph[p])
+        z0 = oracle.u_to_z(ro, seeds[p, 0]).ravel()
+        zk, _, _, _, _ = oracle.lm(ro, oracle.Weights(), pb, oracle.Opts(), z0, 1e-3, k)
+        uk = oracle.z_to_u(ro, zk.reshape(3, 2))
+        worst = max(worst, np.abs(u[p] - uk).max() / B3)
+    print(f"  max |u - u_oracle| / b = {worst:.3g}", flush=True)
+    assert worst <= 5e-4, worst
+
+
+def test_baseline_ik_spheres_status(oracle, cr):
+    """From seeds that penetrate spheres, a short plain solve: the baseline's status
+    bits (collision included) and errors are the oracle's assessment of the
+    configuration it returns, and some answers still collide."""
+    print("baseline ik spheres status", flush=True)
+    from test_gpu_ik_spheres import sphere_case
+    ro, T, seeds, sph = sphere_case(oracle, 460, P=24, S=3, M=8, off=(-4e-3, -1e-3))
+    u, err, st = _b0_sph(cr, ro, T, seeds, sph, cr.Opts(n_final=0, k_init=2, k_final=0))
+    n_coll = 0
+    for p in range(24):
+        ref = oracle.solve(ro, oracle.Weights(), oracle.Problem("ik", T[p], spheres=sph[p]),
+                           oracle.Opts(n_final=0, k_init=0, k_final=0), u[p][None])
+        assert st[p] == ref["status"], (p, st[p], ref["status"])
+        assert abs(err[p, 0] - ref["err"][0]) <= 1e-9 * max(ref["err"][0], 0.1)
+        n_coll += bool(st[p] & cr.COLLISION)
+    assert n_coll >= 3, n_coll
