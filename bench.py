@@ -529,13 +529,69 @@ def uneven_inputs(cr, I, torch, P):
             seeds = pb["seeds"]
         batch_probs.append(dict(kind=pb["kind"], robot=n - 1, H=pb["H"], task=task, seeds=seeds,
                                 spheres=sph if len(sph) else None))
-    return cr.Batch(robots, batch_probs), probs, n_kept
+    return cr.Batch(robots, batch_probs), probs, n_kept, (robots, batch_probs)
+
+
+def uneven_baseline_estimate(cr, torch, singles, weights, opts, args, fused_rate):
+    """The plain per-problem FP32 solves (cr_baseline_solve_ik / _path / _traj) on
+    the first problems of each kind in batch order, each with its own robot,
+    horizon, seeds and spheres; the batch's time is estimated as the sum over kinds
+    of (problems of that kind) x (mean sampled time)."""
+    k = args.baseline_problems
+    if k <= 0:
+        return None
+    robots, probs = singles
+    dev = torch.device("cuda:0")
+    times, counts, sampled = {}, {}, {}
+    for pb in probs:
+        counts[pb["kind"]] = counts.get(pb["kind"], 0) + 1
+    for kind in ("ik", "path", "traj"):
+        picks = [pb for pb in probs if pb["kind"] == kind][:k]
+        ts = []
+        for pb in picks:
+            rb = robots[pb["robot"]]
+            n, H = rb.n, pb["H"]
+            Tn, S = H + 1, pb["seeds"].shape[0]
+            sph = pb["spheres"]
+            sp = None if sph is None else (torch.tensor(np.ascontiguousarray(sph.T), device=dev), False, len(sph))
+            wk, ok = weights[("ik", "path", "traj").index(kind)], opts[("ik", "path", "traj").index(kind)]
+            b0o = cr.Opts(n_final=ok.n_final, k_init=ok.k_init, k_final=ok.k_final)
+            if kind == "ik":
+                T = torch.tensor(np.asarray(pb["task"]).reshape(12, 1), device=dev)
+                us = torch.tensor(pb["seeds"].reshape(S, 3 * n).T.copy(), device=dev)
+                call = lambda: cr.baseline_solve_ik(rb, T, us, wk, b0o, spheres=sp)
+            else:
+                us = torch.tensor(pb["seeds"].reshape(S * Tn, 3 * n).T.copy(), device=dev)
+                if kind == "path":
+                    task = torch.tensor(np.asarray(pb["task"]).reshape(Tn, 12).T.copy(), device=dev)
+                    call = lambda: cr.baseline_solve_path(rb, task, us, H, wk, b0o, spheres=sp)
+                else:
+                    ends = np.concatenate([np.ravel(pb["task"][0]), np.ravel(pb["task"][1])]).reshape(-1, 1)
+                    task = torch.tensor(ends, device=dev)
+                    call = lambda: cr.baseline_solve_traj(rb, task, us, H, wk, b0o, spheres=sp)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        if ts:
+            times[kind] = sum(ts) / len(ts)
+            sampled[kind] = len(ts)
+    total_ms = sum(counts[kd] * times[kd] for kd in times)
+    rate = sum(counts[kd] for kd in times) / (total_ms * 1e-3)
+    return dict(value=round(rate, 3), unit="problems/s", estimate=True,
+                mean_ms_per_problem={kd: round(v, 1) for kd, v in times.items()}, sampled=sampled, counts=counts,
+                speedup_of_fused=round(fused_rate / rate, 1),
+                kind="plain per-problem FP32 solves of each kind, timed on the first problems of that kind, scaled "
+                     "by the kind's count; path problems without the per-waypoint exploration stage")
 
 
 def bench_uneven(args, cr, I, torch):
     P = I.UNEVEN["P"]
     t0 = time.perf_counter()
-    batch, probs, n_sph = uneven_inputs(cr, I, torch, P)
+    batch, probs, n_sph, singles = uneven_inputs(cr, I, torch, P)
     print(f"bench: uneven batch built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     specs = [I.WORKLOADS[k] for k in ("ik_batched_3seg", "path_4seg", "traj_5seg")]
     opts = [cr.Opts(n_final=s["n_final"], k_init=s["k_init"], k_final=s["k_final"], k_seed=s.get("k_seed", 0))
@@ -575,6 +631,8 @@ def bench_uneven(args, cr, I, torch):
                             segments="U{1..6}", horizons="U{1..64}", seeds="U{16..512}", spheres="U{0..64}",
                             spheres_kept=n_sph, seeds_total=int(sum(p["S"] for p in probs)), graph=True),
                 success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ, autotune=tuned)
+    print("bench: timing the plain per-problem baseline on a per-kind sample", file=sys.stderr, flush=True)
+    line["plain_gpu_baseline"] = uneven_baseline_estimate(cr, torch, singles, weights, opts, args, line["value"])
     print(json.dumps(line), flush=True)
 
 
