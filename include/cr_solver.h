@@ -164,8 +164,9 @@ cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* sp
  *   u_out    [device, double] [3n][P]   zero-sum tendon displacements of q*
  *   err_out  [device, double] [2][P]    position error (m), rotation error (rad)
  *   status_out [device, int32] [P]      status bits
- *   ws/ws_bytes [device] scratch of at least cr_solve_ik_workspace() bytes, or
- *   NULL/0 to let the library allocate and free it stream-ordered.
+ *   ws/ws_bytes [device] scratch of at least cr_solve_ik_workspace() bytes,
+ *   256-byte aligned (CR_EINVAL otherwise; hipMalloc's blocks are), or NULL/0
+ *   to let the library allocate and free it stream-ordered.
  * Calls that share one workspace must not overlap. */
 cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t P,
                       const void* T_target, int32_t S, const void* u_seed,
@@ -248,8 +249,9 @@ enum { CR_BATCH_GRAPH = 1 }; /* cr_solve_batch flags */
  *   weights, opts [host] [3], indexed by cr_kind;
  *   task, u_seed, sph, u_out [device, double] packed arrays (see cr_problem);
  *   err_out [device, double] [2][P]; status_out [device, int32] [P];
- *   ws/ws_bytes: at least cr_solve_batch_workspace() bytes (required with
- *   CR_BATCH_GRAPH), or NULL/0 to let the library allocate stream-ordered.
+ *   ws/ws_bytes: at least cr_solve_batch_workspace() bytes, 256-byte aligned
+ *   (required with CR_BATCH_GRAPH), or NULL/0 to let the library allocate
+ *   stream-ordered.
  * flags & CR_BATCH_GRAPH: the whole launch sequence is captured once into a
  * hipGraph, cached by the call's arguments (table contents, pointers, options)
  * and replayed on later identical calls.  The cache owns the graphs and their
@@ -285,9 +287,9 @@ cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const v
  * with a separate kernel per step: residuals and Jacobian by forward-mode dual
  * numbers (no adjoint), normal equations, damped Cholesky step, one kernel per
  * line-search trial and one per accept test, SelectTop, argmin; every
- * intermediate passes through HBM; no graph.  Arguments as cr_solve_ik (no
- * spheres, dtype fixed to FP32); ws at least S * (3n + 2)(2n + 6) * 4 + 64 KiB
- * bytes is always enough, or NULL/0 to let the library allocate. */
+ * intermediate passes through HBM; no graph.  Arguments as cr_solve_ik (dtype
+ * fixed to FP32); ws (256-byte aligned) at least S * (3n + 2)(2n + 6) * 4 +
+ * 64 KiB bytes is always enough, or NULL/0 to let the library allocate. */
 cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t P, const void* T_target,
                                int32_t S, const void* u_seed, const cr_weights* weights, const cr_opts* opts,
                                void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes,
@@ -303,8 +305,8 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres,
  * block-banded normal equations factored by one thread per trajectory.  The final
  * choice and its FP64 assessment are those of cr_solve_path / cr_solve_traj.
  * Arguments, layouts and outputs as cr_solve_path / cr_solve_traj (no dtype;
- * 1 <= S <= 4096).  ws: cr_baseline_traj_workspace() bytes, or NULL to allocate
- * stream-ordered.  For timing against the fused solver; not used by it. */
+ * 1 <= S <= 4096).  ws: cr_baseline_traj_workspace() bytes, 256-byte aligned,
+ * or NULL to allocate stream-ordered.  For timing against the fused solver; not used by it. */
 cr_status cr_baseline_solve_path(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t H,
                                  const void* T_ref, int32_t S, const void* u_seed, const cr_weights* weights,
                                  const cr_opts* opts, void* u_out, void* err_out, int32_t* status_out, void* ws,

@@ -229,6 +229,7 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   size_t need = ik_workspace_layout(*robot, P, S, *opts, dtype, nullptr, nullptr);
   void* mem = ws;
   if (ws) {
+    if ((uintptr_t)ws % 256) return fail(CR_EINVAL, "workspace %p is not 256-byte aligned", ws);
     if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   } else {
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
@@ -284,6 +285,7 @@ static cr_status solve_traj_common(int kind, const cr_robot* robot, const cr_sph
   const size_t need = traj_workspace_bytes(*robot, P, S, H, *opts, dtype);
   void* mem = ws;
   if (ws) {
+    if ((uintptr_t)ws % 256) return fail(CR_EINVAL, "workspace %p is not 256-byte aligned", ws);
     if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   } else {
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
@@ -326,6 +328,7 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres,
   const size_t need = b0_workspace_bytes(*robot, S, *opts);
   void* mem = ws;
   if (ws) {
+    if ((uintptr_t)ws % 256) return fail(CR_EINVAL, "workspace %p is not 256-byte aligned", ws);
     if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   } else {
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
@@ -353,6 +356,7 @@ static cr_status baseline_traj_common(int kind, const cr_robot* robot, const cr_
   const size_t need = b0_traj_workspace_bytes(*robot, S, H, *opts);
   void* mem = ws;
   if (ws) {
+    if ((uintptr_t)ws % 256) return fail(CR_EINVAL, "workspace %p is not 256-byte aligned", ws);
     if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   } else {
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");

@@ -376,6 +376,7 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
   const size_t need = plan.ws_bytes > 0 ? plan.ws_bytes : 256;
   void* mem = ws;
   if (ws) {
+    if ((uintptr_t)ws % 256) return fail(CR_EINVAL, "workspace %p is not 256-byte aligned", ws);
     if (ws_bytes < need) return fail(CR_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
   } else {
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");

@@ -782,6 +782,36 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // The sequential chain over waypoints stays per trajectory; the last factors
 // L_{t-1,t-1}, L_{t-2,t-2}, L_{t-1,t-2} and y live in LDS so every lane can read
 // the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
+// NZ consecutive values of a record (16-byte aligned records; an offset that is a
+// multiple of NZ) with 16- or 8-byte loads.
+template <int NZ, typename T>
+__device__ __forceinline__ void load_run(const T* p, T* out) {
+  if constexpr (sizeof(T) == 4 && NZ % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+      out[k + 2] = v.z;
+      out[k + 3] = v.w;
+    }
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) {
+      const float2 v = *reinterpret_cast<const float2*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+    }
+  }
+}
+
 template <int NS, typename T>
 __global__ void __launch_bounds__(64)
     k_traj_solve(TrajArgs<T> ta, int64_t nt, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
@@ -817,9 +847,13 @@ __global__ void __launch_bounds__(64)
     T* rec = recs + (int64_t)t * R::SIZE;
     const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
     const int b0 = t & 1, b1 = b0 ^ 1;
-    T S[NZ];
+    T S[NZ];  // row a of H_tt, read as its column a (the block is stored exactly symmetric)
+    if (on) {
+      load_run<NZ>(rec + R::OH + a * NZ, S);
+    } else {
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) S[b] = on ? rec[R::OH + b * NZ + a] : T(b == a);
+      for (int b = 0; b < NZ; ++b) S[b] = T(b == a);
+    }
 #pragma unroll
     for (int b = 0; b < NZ; ++b)
       if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
@@ -948,22 +982,28 @@ __global__ void __launch_bounds__(64)
     T* rec = recs + (int64_t)t * R::SIZE;
     const int s0 = t % 3, s1 = (t + 1) % 3, s2 = (t + 2) % 3;  // slots of t, t+1, t+2
     T r = on ? rec[R::OY + a] : T(0);
-    if (t + 1 < Tn) {
-      const T* q = rec + R::SIZE;
+    if (t + 1 < Tn && on) {
       const T* d1 = &sY[s1][g * RS];
+      T q[NZ];
+      load_run<NZ>(rec + R::SIZE + R::OB + a * NZ, q);
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= (on ? q[R::OB + a * NZ + b] : T(0)) * d1[b];
+      for (int b = 0; b < NZ; ++b) r -= q[b] * d1[b];
     }
-    if (t + 2 < Tn) {
-      const T* q = rec + 2 * R::SIZE;
+    if (t + 2 < Tn && on) {
       const T* d2 = &sY[s2][g * RS];
+      T q[NZ];
+      load_run<NZ>(rec + 2 * R::SIZE + R::OC + a * NZ, q);
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= (on ? q[R::OC + a * NZ + b] : T(0)) * d2[b];
+      for (int b = 0; b < NZ; ++b) r -= q[b] * d2[b];
     }
     // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
     T Lc[NZ];
+    if (on) {
+      load_run<NZ>(rec + R::OH + a * NZ, Lc);
+    } else {
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) Lc[k] = on ? rec[R::OH + a * NZ + k] : T(k == a);
+      for (int k = 0; k < NZ; ++k) Lc[k] = T(k == a);
+    }
     T d = T(0);
 #pragma unroll
     for (int k = NZ - 1; k >= 0; --k) {

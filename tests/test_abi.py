@@ -92,7 +92,9 @@ def test_solve_ik_rejects_bad_arguments_on_host(cr):
     oc = cr.Opts().c()
     need = L.cr_solve_ik_workspace(C.byref(rb), 4, 8, C.byref(oc), 0)
     assert need > 0
-    assert call(ws=p, ws_bytes=need - 1) == cr.CR_ENOMEM
+    assert call(ws=C.c_void_p(4096), ws_bytes=need - 1) == cr.CR_ENOMEM
+    assert call(ws=C.c_void_p(4096 + 16), ws_bytes=need) == cr.CR_EINVAL  # not 256-byte aligned
+    assert "aligned" in L.cr_last_error().decode()
 
 
 def test_workspace_size_scales(cr):
@@ -144,7 +146,10 @@ def test_batch_table_validation_on_host(cr):
     # graph mode needs a caller workspace
     assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, None, 0, 0, 1, None) == cr.CR_EINVAL
     # too small a workspace
-    assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, p, 16, 0, 0, None) == cr.CR_ENOMEM
+    w4k = C.c_void_p(4096)
+    assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, w4k, 16, 0, 0, None) == cr.CR_ENOMEM
+    # a misaligned workspace
+    assert L.cr_solve_batch(rob, 2, table(good), 3, p, p, p, wc, oc, p, p, p, p, 1 << 30, 0, 0, None) == cr.CR_EINVAL
     a = L.cr_solve_batch_workspace(rob, 2, table(good), 3, oc, 0)
     b = L.cr_solve_batch_workspace(rob, 2, table(good + good), 6, oc, 0)
     c = L.cr_solve_batch_workspace(rob, 2, table(good), 3, oc, 1)
