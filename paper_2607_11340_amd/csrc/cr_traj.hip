@@ -67,11 +67,14 @@ __device__ __forceinline__ TrajCtx traj_ctx(const TrajArgs<T>& ta, int64_t traj)
   return cx;
 }
 
-// Per-waypoint record of the normal equations, every block column-major: element
-// (row i, column j) of a block sits at column j * NZ + i, so the NZ lanes that own
-// the rows of one trajectory read a block column as NZ consecutive values.
-//   OH: H_tt (full, symmetric), overwritten by L_tt (lower)
-//   OB: H_{t,t-1}, overwritten by L_{t,t-1};  OC: H_{t,t-2}, overwritten by L_{t,t-2}
+// Per-waypoint record of the normal equations.  The solve keeps row a of every
+// block on lane a, so blocks are laid out for the accesses that dominate it:
+//   OH: H_tt (full, symmetric; row a read as column a), overwritten by L_tt
+//       column-major (element (i, j) at j * NZ + i: the backward pass reads a
+//       column of L_tt as NZ consecutive values)
+//   OB: H_{t,t-1}, overwritten by L_{t,t-1};  OC: H_{t,t-2}, overwritten by
+//       L_{t,t-2}; both row-major (element (i, j) at i * NZ + j: the forward pass
+//       reads and writes a row per lane as NZ consecutive values)
 //   OG: g_t;  OY: y_t, then delta_t
 template <int NS>
 struct Rec {
@@ -79,6 +82,51 @@ struct Rec {
   static constexpr int OH = 0, OB = NZ * NZ, OC = 2 * NZ * NZ, OG = 3 * NZ * NZ, OY = OG + NZ;
   static constexpr int SIZE = OY + NZ;
 };
+
+// NZ consecutive values of a record (16-byte aligned records; an offset that is a
+// multiple of NZ) with 16- or 8-byte loads and stores.
+template <int NZ, typename T>
+__device__ __forceinline__ void load_run(const T* p, T* out) {
+  if constexpr (sizeof(T) == 4 && NZ % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+      out[k + 2] = v.z;
+      out[k + 3] = v.w;
+    }
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) {
+      const float2 v = *reinterpret_cast<const float2*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(p + k);
+      out[k] = v.x;
+      out[k + 1] = v.y;
+    }
+  }
+}
+
+template <int NZ, typename T>
+__device__ __forceinline__ void store_run(const T* v, T* p) {
+  if constexpr (sizeof(T) == 4 && NZ % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 4)
+      *reinterpret_cast<float4*>(p + k) = make_float4(v[k], v[k + 1], v[k + 2], v[k + 3]);
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) *reinterpret_cast<float2*>(p + k) = make_float2(v[k], v[k + 1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NZ; k += 2) *reinterpret_cast<double2*>(p + k) = make_double2(v[k], v[k + 1]);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T block_sum_all(T v, T* red) {
@@ -742,23 +790,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     const T sl2 = w.sq_len * w.sq_len;
 #pragma unroll
     for (int b = 0; b < NZ; ++b) {
-      T jq[3] = {T(0), T(0), T(0)};  // column b of J_p at t - 1
-      if (len) {
+      T hc[NZ];  // column b of H_tt
 #pragma unroll
-        for (int q = 0; q < 3; ++q) jq[q] = s_jp[((t - 1) * 3 + q) * NZ + b];
-      }
+      for (int a = 0; a < NZ; ++a) hc[a] = a >= b ? Hp[tri(a, b)] : Hp[tri(b, a)];
+      store_run<NZ>(hc, rec + R::OH + b * NZ);
+    }
+    T jq[3][NZ] = {};  // J_p at t - 1
+    if (len) {
 #pragma unroll
-      for (int a = 0; a < NZ; ++a) {
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) jq[q][b] = s_jp[((t - 1) * 3 + q) * NZ + b];
+    }
+#pragma unroll
+    for (int a = 0; a < NZ; ++a) {
+      T brow[NZ], crow[NZ];  // row a of H_{t,t-1} and of H_{t,t-2}
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) {
         T bv = T(0), cv = T(0);
         if (a / 2 == b / 2) {
           bv = Bs[a / 2][(a & 1) + (b & 1)];
           cv = Cs[a / 2][(a & 1) + (b & 1)];
         }
-        if (len) bv -= sl2 * (Jp[0][a] * jq[0] + Jp[1][a] * jq[1] + Jp[2][a] * jq[2]);
-        rec[R::OH + b * NZ + a] = a >= b ? Hp[tri(a, b)] : Hp[tri(b, a)];
-        rec[R::OB + b * NZ + a] = bv;
-        rec[R::OC + b * NZ + a] = cv;
+        if (len) bv -= sl2 * (Jp[0][a] * jq[0][b] + Jp[1][a] * jq[1][b] + Jp[2][a] * jq[2][b]);
+        brow[b] = bv;
+        crow[b] = cv;
       }
+      store_run<NZ>(brow, rec + R::OB + a * NZ);
+      store_run<NZ>(crow, rec + R::OC + a * NZ);
     }
 #pragma unroll
     for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
@@ -782,36 +841,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // The sequential chain over waypoints stays per trajectory; the last factors
 // L_{t-1,t-1}, L_{t-2,t-2}, L_{t-1,t-2} and y live in LDS so every lane can read
 // the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
-// NZ consecutive values of a record (16-byte aligned records; an offset that is a
-// multiple of NZ) with 16- or 8-byte loads.
-template <int NZ, typename T>
-__device__ __forceinline__ void load_run(const T* p, T* out) {
-  if constexpr (sizeof(T) == 4 && NZ % 4 == 0) {
-#pragma unroll
-    for (int k = 0; k < NZ; k += 4) {
-      const float4 v = *reinterpret_cast<const float4*>(p + k);
-      out[k] = v.x;
-      out[k + 1] = v.y;
-      out[k + 2] = v.z;
-      out[k + 3] = v.w;
-    }
-  } else if constexpr (sizeof(T) == 4) {
-#pragma unroll
-    for (int k = 0; k < NZ; k += 2) {
-      const float2 v = *reinterpret_cast<const float2*>(p + k);
-      out[k] = v.x;
-      out[k + 1] = v.y;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < NZ; k += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(p + k);
-      out[k] = v.x;
-      out[k + 1] = v.y;
-    }
-  }
-}
-
 template <int NS, typename T>
 __global__ void __launch_bounds__(64)
     k_traj_solve(TrajArgs<T> ta, int64_t nt, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
@@ -858,17 +887,27 @@ __global__ void __launch_bounds__(64)
     for (int b = 0; b < NZ; ++b)
       if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
     T y = on ? -rec[R::OG + a] : T(0);
-    T Bw[NZ];
+    T Bw[NZ];  // row a of H_{t,t-1}
+    if (on && t >= 1) {
+      load_run<NZ>(rec + R::OB + a * NZ, Bw);
+    } else {
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) Bw[b] = (on && t >= 1) ? rec[R::OB + b * NZ + a] : T(0);
+      for (int b = 0; b < NZ; ++b) Bw[b] = T(0);
+    }
     if (t >= 2) {
       // row a of L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T (forward substitution)
       const T* L2 = &sL[s2][g * GS];
       const T* D2 = &sD[s2][g * RS];
-      T x[NZ];
+      T x[NZ];  // row a of H_{t,t-2}, then of L_{t,t-2}
+      if (on) {
+        load_run<NZ>(rec + R::OC + a * NZ, x);
+      } else {
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) x[i] = T(0);
+      }
 #pragma unroll
       for (int i = 0; i < NZ; ++i) {
-        T v = on ? rec[R::OC + i * NZ + a] : T(0);
+        T v = x[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) v -= L2[i * RS + j] * x[j];
         x[i] = v * D2[i];
@@ -876,10 +915,8 @@ __global__ void __launch_bounds__(64)
       const T* Y2 = &sY[s2][g * RS];
       const T* B1 = &sB[b1][g * GS];  // L_{t-1,t-2}
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        y -= x[i] * Y2[i];
-        if (on) rec[R::OC + i * NZ + a] = x[i];
-      }
+      for (int i = 0; i < NZ; ++i) y -= x[i] * Y2[i];
+      if (on) store_run<NZ>(x, rec + R::OC + a * NZ);
       // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T
 #pragma unroll
       for (int b = 0; b < NZ; ++b) {
@@ -917,10 +954,8 @@ __global__ void __launch_bounds__(64)
       }
       const T* Y1 = &sY[s1][g * RS];
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        y -= x[i] * Y1[i];
-        if (on) rec[R::OB + i * NZ + a] = x[i];
-      }
+      for (int i = 0; i < NZ; ++i) y -= x[i] * Y1[i];
+      if (on) store_run<NZ>(x, rec + R::OB + a * NZ);
       if (inw) {
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
@@ -982,19 +1017,18 @@ __global__ void __launch_bounds__(64)
     T* rec = recs + (int64_t)t * R::SIZE;
     const int s0 = t % 3, s1 = (t + 1) % 3, s2 = (t + 2) % 3;  // slots of t, t+1, t+2
     T r = on ? rec[R::OY + a] : T(0);
+    // column a of L_{t+1,t} and of L_{t+2,t} (their rows are stored contiguously)
     if (t + 1 < Tn && on) {
+      const T* q = rec + R::SIZE + R::OB + a;
       const T* d1 = &sY[s1][g * RS];
-      T q[NZ];
-      load_run<NZ>(rec + R::SIZE + R::OB + a * NZ, q);
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= q[b] * d1[b];
+      for (int b = 0; b < NZ; ++b) r -= q[b * NZ] * d1[b];
     }
     if (t + 2 < Tn && on) {
+      const T* q = rec + 2 * R::SIZE + R::OC + a;
       const T* d2 = &sY[s2][g * RS];
-      T q[NZ];
-      load_run<NZ>(rec + 2 * R::SIZE + R::OC + a * NZ, q);
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= q[b] * d2[b];
+      for (int b = 0; b < NZ; ++b) r -= q[b * NZ] * d2[b];
     }
     // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
     T Lc[NZ];
