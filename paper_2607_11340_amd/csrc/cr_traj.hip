@@ -841,6 +841,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // The sequential chain over waypoints stays per trajectory; the last factors
 // L_{t-1,t-1}, L_{t-2,t-2}, L_{t-1,t-2} and y live in LDS so every lane can read
 // the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
+// The diagonal block is factored by rounds over its columns in FP64 (one LDS
+// exchange per column); in FP32 the whole block fits the registers of every row
+// lane, so it is exchanged once and factored redundantly by each lane.
 template <int NS, typename T>
 __global__ void __launch_bounds__(64)
     k_traj_solve(TrajArgs<T> ta, int64_t nt, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
@@ -972,41 +975,99 @@ __global__ void __launch_bounds__(64)
         S[b] -= v;
       }
     }
-    // L_tt L_tt^T = S and y_t = L_tt^-1 y, column by column: in round j lane j
-    // finishes its pivot and y_j and publishes its row; rows below take column j.
     T* Lt = &sL[s0][g * GS];
     T* Dt = &sD[s0][g * RS];
     T* Yt = &sY[s0][g * RS];
+    if constexpr (sizeof(T) == 4) {
+      // L_tt L_tt^T = S and y_t = L_tt^-1 y in one exchange: the rows of S and y go
+      // to LDS (the slot of waypoint t - 3, no longer read), every lane of the
+      // trajectory factors the whole block in registers with the same arithmetic,
+      // and the first lane publishes the factor for the rows and later waypoints.
+      if (inw) {
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) {
-      if (a == j) {
-        T dd = S[j];
+        for (int b = 0; b < NZ; ++b) Lt[a * RS + b] = S[b];
+        Yt[a] = y;
+      }
+      __syncthreads();
+      T L[NZ * (NZ + 1) / 2], yv[NZ], dv[NZ];
 #pragma unroll
-        for (int k = 0; k < j; ++k) dd -= S[k] * S[k];
+      for (int i = 0; i < NZ; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) L[tri(i, j)] = Lt[i * RS + j];
+        yv[i] = Yt[i];
+      }
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        T dd = L[tri(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) dd -= L[tri(j, k)] * L[tri(j, k)];
         ok = ok && (!on || dd > T(0));
         const T ljj = tsqrt(dd > T(0) ? dd : T(1));
-        S[j] = ljj;
-        y = y / ljj;
-        if (inw) {
+        L[tri(j, j)] = ljj;
+        yv[j] = yv[j] / ljj;
+        dv[j] = T(1) / ljj;
 #pragma unroll
-          for (int k = 0; k <= j; ++k) Lt[j * RS + k] = S[k];
-          Dt[j] = T(1) / ljj;
-          Yt[j] = y;
+        for (int i = j + 1; i < NZ; ++i) {
+          T v = L[tri(i, j)];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= L[tri(i, k)] * L[tri(j, k)];
+          L[tri(i, j)] = v * dv[j];
+          yv[i] -= L[tri(i, j)] * yv[j];
         }
       }
       __syncthreads();
-      if (a > j) {
-        T v = S[j];
+      if (inw && a == 0) {
 #pragma unroll
-        for (int k = 0; k < j; ++k) v -= S[k] * Lt[j * RS + k];
-        S[j] = v * Dt[j];
-        y -= S[j] * Yt[j];
+        for (int i = 0; i < NZ; ++i) {
+#pragma unroll
+          for (int j = 0; j <= i; ++j) Lt[i * RS + j] = L[tri(i, j)];
+          Dt[i] = dv[i];
+          Yt[i] = yv[i];
+        }
       }
-    }
-    if (on) {
+      __syncthreads();
+      y = Yt[a];
+      if (on) {
+        T col[NZ];  // column a of L_tt
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) rec[R::OH + b * NZ + a] = b <= a ? S[b] : T(0);
-      rec[R::OY + a] = y;
+        for (int k = 0; k < NZ; ++k) col[k] = k >= a ? Lt[k * RS + a] : T(0);
+        store_run<NZ>(col, rec + R::OH + a * NZ);
+        rec[R::OY + a] = y;
+      }
+    } else {
+      // L_tt L_tt^T = S and y_t = L_tt^-1 y, column by column: in round j lane j
+      // finishes its pivot and y_j and publishes its row; rows below take column j.
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        if (a == j) {
+          T dd = S[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) dd -= S[k] * S[k];
+          ok = ok && (!on || dd > T(0));
+          const T ljj = tsqrt(dd > T(0) ? dd : T(1));
+          S[j] = ljj;
+          y = y / ljj;
+          if (inw) {
+#pragma unroll
+            for (int k = 0; k <= j; ++k) Lt[j * RS + k] = S[k];
+            Dt[j] = T(1) / ljj;
+            Yt[j] = y;
+          }
+        }
+        __syncthreads();
+        if (a > j) {
+          T v = S[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= S[k] * Lt[j * RS + k];
+          S[j] = v * Dt[j];
+          y -= S[j] * Yt[j];
+        }
+      }
+      if (on) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) rec[R::OH + b * NZ + a] = b <= a ? S[b] : T(0);
+        rec[R::OY + a] = y;
+      }
     }
     __syncthreads();
   }

@@ -103,6 +103,36 @@ def test_fp64_lm_iterates_match_oracle(oracle, cr, kind, k):
 
 
 @pytest.mark.parametrize("kind", ["path", "traj"])
+@pytest.mark.parametrize("n", [3, 4])
+def test_fp32_lm_step_matches_oracle(oracle, cr, kind, n):
+    """One FP32 LM iteration over whole trajectories (FP32 normal equations and
+    block Cholesky, every block factored in registers) against the oracle's FP64
+    iteration from the same seed.  Tolerance: the step is the solution of the
+    damped normal equations, so its FP32 error is about cond * NZ * 6e-8 of its
+    size; with the Marquardt damping of the first iteration (lambda = 1e-3
+    relative) cond stays below 1e3 here, giving 5e-4 of the largest change."""
+    print(f"traj fp32 step kind={kind} n={n}", flush=True)
+    c = case(oracle, kind, 330 + n, n=n, H=12, P=4, S=1, M=2)
+    u, err, st = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=1, k_final=0), "f32")
+    W = oracle.Weights(**c["W"])
+    moved = 0
+    for p in range(c["P"]):
+        pb = oracle_problem(oracle, c, p)
+        z0 = oracle.u_to_z(c["ro"], c["seeds"][p, 0]).ravel()
+        z1, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, 1)
+        u1 = oracle.z_to_u(c["ro"], z1.reshape(c["H"] + 1, c["n"], 2))
+        step = np.abs(u1 - c["seeds"][p, 0]).max()
+        dev = np.abs(u[p] - u1).max()
+        print(f"  p={p} step={step:.3e} dev={dev:.3e}", flush=True)
+        if step > 1e-9:  # accepted step
+            moved += 1
+            assert dev <= 5e-4 * step + 1e-7 * c["b"], (p, dev, step)
+        else:  # rejected by the line search: the seed comes back (FP32 round trip z <-> u)
+            assert dev <= 1e-5 * c["b"], (p, dev)
+    assert moved >= c["P"] - 1, moved
+
+
+@pytest.mark.parametrize("kind", ["path", "traj"])
 def test_fp64_lm_step_map_long_horizon(oracle, cr, kind):
     """4-segment robot, 32 waypoints, spheres: one GPU FP64 LM step from the oracle's
     own iterate equals one oracle step, at several points of a 12-iteration run."""
