@@ -223,8 +223,9 @@ def autotune(args, cr, torch, call):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(problems are independent, see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported (problems are "
+              f"independent: several GPUs would each run one process on their share of the batch)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2607_11340_amd import crsolver as cr

@@ -44,7 +44,7 @@ typedef enum {
   CR_EINVAL = 1,        /* invalid argument; nothing was launched */
   CR_ENOMEM = 2,        /* workspace too small or allocation failed */
   CR_EDEVICE = 3,       /* a HIP call failed */
-  CR_EUNSUPPORTED = 4   /* valid request this build does not implement */
+  CR_EUNSUPPORTED = 4   /* valid request the library does not implement */
 } cr_status;
 
 /* Floating-point type of a call's arrays and arithmetic. */
