@@ -81,6 +81,10 @@ struct Rec {
   static constexpr int NZ = 2 * NS;
   static constexpr int OH = 0, OB = NZ * NZ, OC = 2 * NZ * NZ, OG = 3 * NZ * NZ, OY = OG + NZ;
   static constexpr int SIZE = OY + NZ;
+  // with a 256-byte aligned workspace every record and block starts on a 16-byte
+  // boundary in FP32 and FP64 (SIZE = 4 NS (3 NS + 1)); a row of a block is
+  // 16-byte aligned when NZ is a multiple of 4 or in FP64, else 8-byte aligned
+  static_assert(SIZE % 4 == 0 && OB % 4 == 0 && OC % 4 == 0, "record blocks must be 16-byte aligned");
 };
 
 // NZ consecutive values of a record (16-byte aligned records; an offset that is a
