@@ -876,16 +876,50 @@ __global__ void __launch_bounds__(64)
   const T lm = act ? lam[traj] : T(0);
   T* const recs = blk + wp * R::SIZE;
   bool ok = true;
+  // FP32 rows of the next waypoint's blocks are loaded while the current one is
+  // factored (the chain over waypoints is latency-bound)
+  constexpr bool PF = sizeof(T) == 4 && NZ <= 10;
+  T pH[NZ], pB[NZ], pC[NZ], pG = T(0);
+  if constexpr (PF) {
+    if (act && 0 < Tn) {
+      load_run<NZ>(recs + R::OH + a * NZ, pH);
+      load_run<NZ>(recs + R::OB + a * NZ, pB);
+      load_run<NZ>(recs + R::OC + a * NZ, pC);
+      pG = recs[R::OG + a];
+    }
+  }
   // every lane runs the longest horizon of the launch (workgroup-uniform barriers);
   // a trajectory's lanes work only while t < its own horizon
   for (int t = 0; t < ta.Tmax; ++t) {
     const bool on = act && t < Tn;
     T* rec = recs + (int64_t)t * R::SIZE;
+    T cH[NZ], cB[NZ], cC[NZ], cG = T(0);
+    if constexpr (PF) {
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) {
+        cH[k] = pH[k];
+        cB[k] = pB[k];
+        cC[k] = pC[k];
+      }
+      cG = pG;
+      if (act && t + 1 < Tn) {
+        const T* nx = rec + R::SIZE;
+        load_run<NZ>(nx + R::OH + a * NZ, pH);
+        load_run<NZ>(nx + R::OB + a * NZ, pB);
+        load_run<NZ>(nx + R::OC + a * NZ, pC);
+        pG = nx[R::OG + a];
+      }
+    }
     const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
     const int b0 = t & 1, b1 = b0 ^ 1;
     T S[NZ];  // row a of H_tt, read as its column a (the block is stored exactly symmetric)
     if (on) {
-      load_run<NZ>(rec + R::OH + a * NZ, S);
+      if constexpr (PF) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) S[b] = cH[b];
+      } else {
+        load_run<NZ>(rec + R::OH + a * NZ, S);
+      }
     } else {
 #pragma unroll
       for (int b = 0; b < NZ; ++b) S[b] = T(b == a);
@@ -893,10 +927,15 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int b = 0; b < NZ; ++b)
       if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
-    T y = on ? -rec[R::OG + a] : T(0);
+    T y = on ? -(PF ? cG : rec[R::OG + a]) : T(0);
     T Bw[NZ];  // row a of H_{t,t-1}
     if (on && t >= 1) {
-      load_run<NZ>(rec + R::OB + a * NZ, Bw);
+      if constexpr (PF) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) Bw[b] = cB[b];
+      } else {
+        load_run<NZ>(rec + R::OB + a * NZ, Bw);
+      }
     } else {
 #pragma unroll
       for (int b = 0; b < NZ; ++b) Bw[b] = T(0);
@@ -907,7 +946,12 @@ __global__ void __launch_bounds__(64)
       const T* D2 = &sD[s2][g * RS];
       T x[NZ];  // row a of H_{t,t-2}, then of L_{t,t-2}
       if (on) {
-        load_run<NZ>(rec + R::OC + a * NZ, x);
+        if constexpr (PF) {
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) x[i] = cC[i];
+        } else {
+          load_run<NZ>(rec + R::OC + a * NZ, x);
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < NZ; ++i) x[i] = T(0);
