@@ -178,6 +178,28 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
 size_t cr_solve_ik_workspace(const cr_robot* robot, int64_t P, int32_t S, const cr_opts* opts,
                              cr_dtype dtype);
 
+/* Bytes of the static scratch buffer of cr_solve_ik_static on each GPU (64 MiB). */
+#define CR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* cr_solve_ik for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as cr_solve_ik, with the same arguments except the workspace: its scratch
+ * is a static device buffer of CR_STATIC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); its first call on a device
+ * looks up that device's buffer address, with that device current.  Runs on the
+ * current device; `stream` must belong to it.  The caller still owns T_target,
+ * u_seed, u_out, err_out and status_out.
+ * Every call on a GPU shares that GPU's buffer: calls that overlap on one GPU
+ * (concurrent streams or host threads) race and must be serialised by the caller.
+ * Errors: as cr_solve_ik, and CR_ENOMEM (nothing launched) when
+ * cr_solve_ik_workspace() of these shapes exceeds CR_STATIC_SCRATCH_BYTES (the
+ * 3-segment, 4096 x 256-seed, N_final = 8 FP32 solve needs 48 MB). */
+cr_status cr_solve_ik_static(const cr_robot* robot, const cr_spheres* spheres, int64_t P,
+                             const void* T_target, int32_t S, const void* u_seed,
+                             const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
+                             int32_t* status_out, cr_dtype dtype, hipStream_t stream);
+
 /* Path following (eq. 16 with the trajectory constraints of eq. 12-15) for P
  * problems of H+1 waypoints, two-stage as in Algorithm 1 (Sec. IV-B): stage 1
  * runs k_init LM iterations over whole trajectories (block-pentadiagonal normal

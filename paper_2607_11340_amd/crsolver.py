@@ -27,7 +27,7 @@ F32, F64 = 0, 1
 KIND = {"ik": 0, "path": 1, "traj": 2}
 SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 
-EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_path", "cr_solve_traj",
+EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
            "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_baseline_traj_workspace",
            "cr_select_top",
@@ -141,6 +141,7 @@ def _load():
     L.cr_fk.argtypes = [R, i64, vp, i64, vp, vp, vp, C.c_int, vp]
     L.cr_cost_grad.argtypes = [i32, R, S, W, i64, i32, i32, vp, vp, vp, vp, vp, C.c_int, vp]
     L.cr_solve_ik.argtypes = [R, S, i64, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
+    L.cr_solve_ik_static.argtypes = [R, S, i64, vp, i32, vp, W, O, vp, vp, vp, C.c_int, vp]
     L.cr_solve_path.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
     L.cr_solve_traj.argtypes = [R, S, i64, i32, vp, i32, vp, W, O, vp, vp, vp, vp, C.c_size_t, C.c_int, vp]
     L.cr_solve_traj_workspace.argtypes = [R, i64, i32, i32, O, C.c_int]
@@ -173,7 +174,7 @@ def _load():
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
-    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
+    for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
                  "cr_baseline_solve_ik", "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_select_top",
                  "cr_timing_read", "cr_ik_flop_tally"):
         getattr(L, name).restype = C.c_int
@@ -281,6 +282,35 @@ def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights
     _check(lib.cr_solve_ik(C.byref(rc), C.byref(sc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc),
                            C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype),
                            _stream(T_target)))
+    return u_out, err, st
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_ik_static(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,
+                    opts: Opts = None, dtype=torch.float32, spheres=None, out=None):
+    """solve_ik through cr_solve_ik_static: no workspace and no device allocation
+    inside the call (its scratch is the library's static per-GPU buffer).  `out`
+    (u, err, status) must be given by callers that cannot allocate; when None,
+    this wrapper allocates the outputs before the call."""
+    weights = weights or Weights()
+    opts = opts or Opts()
+    n = robot.n
+    P = T_target.shape[1]
+    S = u_seed.shape[1] // max(P, 1)
+    _need(T_target, (12, P), torch.float64, "T_target")
+    _need(u_seed, (3 * n, S * P), torch.float64, "u_seed")
+    dev = T_target.device
+    if out is None:
+        out = (torch.empty((3 * n, P), dtype=torch.float64, device=dev),
+               torch.empty((2, P), dtype=torch.float64, device=dev),
+               torch.empty((P,), dtype=torch.int32, device=dev))
+    u_out, err, st = out
+    rc, wc, oc = robot.c(), weights.c(), opts.c()
+    sc = _spheres_c(spheres, torch.float64)
+    _check(lib.cr_solve_ik_static(C.byref(rc), C.byref(sc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc),
+                                  C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), _dt(dtype), _stream(T_target)))
     return u_out, err, st
 
 

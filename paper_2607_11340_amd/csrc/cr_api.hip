@@ -165,6 +165,16 @@ cr_status check_weights(const cr_weights* w) {
   return CR_OK;
 }
 
+cr_status check_spheres(const cr_spheres* spheres, int64_t P) {
+  if (!spheres || spheres->n_sph == 0) return CR_OK;
+  if (spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
+  if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
+  if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
+  const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
+  if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
+  return CR_OK;
+}
+
 }  // namespace crk
 
 using namespace crk;
@@ -198,15 +208,6 @@ cr_status cr_fk(const cr_robot* robot, int64_t B, const void* u, int64_t ld, voi
   return launch_fk(*robot, B, u, ld, arc, frames, pts, dtype, stream);
 }
 
-static cr_status check_spheres(const cr_spheres* spheres, int64_t P) {
-  if (!spheres || spheres->n_sph == 0) return CR_OK;
-  if (spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
-  if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
-  if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
-  const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
-  if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
-  return CR_OK;
-}
 
 size_t cr_solve_ik_workspace(const cr_robot* robot, int64_t P, int32_t S, const cr_opts* opts, cr_dtype dtype) {
   if (check_robot(robot) != CR_OK || check_opts(opts) != CR_OK || check_dtype(dtype) != CR_OK || P < 0 || S < 1)
