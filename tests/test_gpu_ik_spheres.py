@@ -122,7 +122,8 @@ def test_ik_spheres_two_stage_quality(oracle, cr):
     opts = cr.Opts(n_final=8, k_init=150, k_final=50)
     u, err, st = gpu_solve(cr, ro, T, seeds, sph, opts, "f32")
     solved = st == cr.SOLVED
-    assert solved.mean() >= 0.9, (solved.mean(), np.unique(st, return_counts=True))
+    print(f"  success {solved.mean():.3f}", flush=True)
+    assert solved.mean() >= 0.95, (solved.mean(), np.unique(st, return_counts=True))
     for p in np.nonzero(solved)[0]:
         _, _, pts = oracle.fk(ro, u[p], points=True)
         body = np.repeat(np.asarray(R3), K)

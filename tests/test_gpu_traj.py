@@ -103,7 +103,7 @@ def test_fp64_lm_iterates_match_oracle(oracle, cr, kind, k):
 
 
 @pytest.mark.parametrize("kind", ["path", "traj"])
-@pytest.mark.parametrize("n", [3, 4])
+@pytest.mark.parametrize("n", [3, 4, 5, 6])
 def test_fp32_lm_step_matches_oracle(oracle, cr, kind, n):
     """One FP32 LM iteration over whole trajectories (FP32 normal equations and
     block Cholesky, every block factored in registers) against the oracle's FP64
@@ -194,10 +194,14 @@ def test_path_two_stage_quality(oracle, cr):
 def test_traj_two_stage_with_obstacles(oracle, cr):
     """Trajectory planning among spheres (5 segments, 32 waypoints): the returned
     trajectories reach both endpoints, respect the bounds and are collision free
-    according to the oracle's own geometry."""
+    according to the oracle's own geometry.  Where spheres squeeze a trajectory
+    against the tendon bounds, the penalised cost (eq. 17, equal weights 1e6 on both
+    hinges) settles where the two hinge gradients balance, a few micrometres past
+    the bound: such answers are flagged CR_LIMIT_VIOLATION (tolerance 1e-6 m) and are
+    the only failures allowed; about one problem in twelve of this shape ends so."""
     print("traj two-stage obstacles", flush=True)
     rng = np.random.default_rng(44)
-    n, H, P, S, K, M = 5, 31, 6, 8, 8, 8
+    n, H, P, S, K, M = 5, 31, 40, 8, 8, 8
     L, r, b = [0.06] * n, [0.006] * n, 0.006
     ro = oracle.Robot(L=L, r=r, u_max=[b] * n, pts_per_seg=K)
     ends = I.uniform_actuation(rng, n, b, 2 * P).reshape(P, 2, n, 3)
@@ -216,8 +220,13 @@ def test_traj_two_stage_with_obstacles(oracle, cr):
                 m += 1
     c = dict(kind="traj", n=n, L=L, r=r, b=b, K=K, H=H, P=P, S=S, M=M, ro=ro, W=dict(), task=ends, seeds=seeds,
              sph=sph)
-    u, err, st = gpu_solve(cr, c, cr.Opts(n_final=4, k_init=60, k_final=20), "f32")
-    assert (st == cr.SOLVED).mean() >= 5 / 6, (st, err)
+    u, err, st = gpu_solve(cr, c, cr.Opts(n_final=4, k_init=80, k_final=20), "f32")
+    over = np.abs(u).reshape(P, -1).max(axis=1) - b
+    print(f"  success {(st == cr.SOLVED).mean():.3f}, tendon overshoot of the others "
+          f"{over[st != cr.SOLVED]}", flush=True)
+    assert (st == cr.SOLVED).mean() >= 0.85, (st, err)
+    assert set(st[st != cr.SOLVED]) <= {cr.LIMIT_VIOLATION}, st
+    assert over.max() <= 5e-5, over.max()          # under 1 % of the 6 mm bound
     for p in np.nonzero(st == cr.SOLVED)[0]:
         _, _, pts = oracle.fk(ro, u[p], points=True)
         d = np.linalg.norm(pts.reshape(-1, 1, 3) - sph[p, None, :, :3], axis=2) - sph[p, None, :, 3] - 0.006
@@ -267,7 +276,7 @@ def test_path_exploration_two_stage_quality(oracle, cr):
     print("path exploration two-stage quality", flush=True)
     spec = I.WORKLOADS["path_4seg"]
     rng = I.rng_for("path_4seg", 2)
-    n, H, P, S = 4, spec["H"], 16, 32
+    n, H, P, S = 4, spec["H"], 40, 32
     ro = oracle.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n)
     uref = I.smooth_actuation_paths(rng, n, spec["b"], P, H + 1)
     _, fr = oracle.fk(ro, uref)
@@ -275,4 +284,5 @@ def test_path_exploration_two_stage_quality(oracle, cr):
     c = dict(kind="path", n=n, L=spec["L"], r=spec["r"], b=spec["b"], K=10, H=H, P=P, S=S, M=0, ro=ro,
              W=spec["weights"], task=fr[:, :, -1], seeds=seeds, sph=None)
     u, err, st = gpu_solve(cr, c, cr.Opts(n_final=4, k_init=spec["k_init"], k_final=spec["k_final"], k_seed=30), "f32")
-    assert (st == cr.SOLVED).mean() >= 0.9, (st, err)
+    print(f"  success {(st == cr.SOLVED).mean():.3f}", flush=True)
+    assert (st == cr.SOLVED).mean() >= 0.95, (st, err)
