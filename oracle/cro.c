@@ -267,30 +267,52 @@ static dual fam_gamma(dual q) {
 
 static double alpha_j(int j) { return 2.0 * PI * (double)j / 3.0; }
 
+int cro_ncoord(const cro_robot* rb) { return rb->extensible ? 3 : 2; }
+
 /* eq. (4) minus L_i:  u_ij = -r_c theta_i cos(alpha_j - phi_i) = -r_c (a cos alpha_j + b sin alpha_j).
  * Three tendons at 0, 120, 240 degrees are orthogonal in the sense
  * sum_j cos^2 = sum_j sin^2 = 3/2, sum_j cos sin = sum_j cos = sum_j sin = 0, so
  * projecting u on cos/sin inverts eq. (4) and ignores the common mode. */
 void cro_u_to_z(const cro_robot* rb, const double* u, double* z) {
+  int c = cro_ncoord(rb);
   for (int i = 0; i < rb->n_seg; i++) {
     double pc = 0.0, ps = 0.0;
     for (int j = 0; j < 3; j++) {
       pc += u[3 * i + j] * cos(alpha_j(j));
       ps += u[3 * i + j] * sin(alpha_j(j));
     }
-    z[2 * i] = -pc / (1.5 * rb->r[i]);
-    z[2 * i + 1] = -ps / (1.5 * rb->r[i]);
+    z[c * i] = -pc / (1.5 * rb->r[i]);
+    z[c * i + 1] = -ps / (1.5 * rb->r[i]);
+    /* extensible: the common mode is the change of the segment's length (the mean of
+     * eq. 4 over the three tendons is L_i) */
+    if (c == 3) z[c * i + 2] = (u[3 * i] + u[3 * i + 1] + u[3 * i + 2]) / 3.0;
   }
 }
 
 void cro_z_to_u(const cro_robot* rb, const double* z, double* u) {
+  int c = cro_ncoord(rb);
   for (int i = 0; i < rb->n_seg; i++)
-    for (int j = 0; j < 3; j++)
-      u[3 * i + j] = -rb->r[i] * (z[2 * i] * cos(alpha_j(j)) + z[2 * i + 1] * sin(alpha_j(j)));
+    for (int j = 0; j < 3; j++) {
+      u[3 * i + j] = -rb->r[i] * (z[c * i] * cos(alpha_j(j)) + z[c * i + 1] * sin(alpha_j(j)));
+      if (c == 3) u[3 * i + j] += z[c * i + 2];
+    }
 }
 
+/* bending part of tendon j of segment i (zero-sum over j) */
+static dual bend_dual(const cro_robot* rb, const dual* z, int i, int j) {
+  int c = cro_ncoord(rb);
+  return dscale(-rb->r[i], dadd(dscale(cos(alpha_j(j)), z[c * i]), dscale(sin(alpha_j(j)), z[c * i + 1])));
+}
+
+/* whole displacement of tendon j of segment i: bending part plus extension */
 static dual lift_dual(const cro_robot* rb, const dual* z, int i, int j) {
-  return dscale(-rb->r[i], dadd(dscale(cos(alpha_j(j)), z[2 * i]), dscale(sin(alpha_j(j)), z[2 * i + 1])));
+  dual u = bend_dual(rb, z, i, j);
+  return cro_ncoord(rb) == 3 ? dadd(u, z[3 * i + 2]) : u;
+}
+
+/* length of segment i */
+static dual seg_len(const cro_robot* rb, const dual* z, int i) {
+  return cro_ncoord(rb) == 3 ? dshift(z[3 * i + 2], rb->L[i]) : dcon(rb->L[i]);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -326,19 +348,20 @@ static void fk_chain(const cro_robot* rb, const dual* z, dual (*Rf)[9], dual (*p
   dual R[9], p[3];
   for (int k = 0; k < 9; k++) R[k] = dcon((k % 4 == 0) ? 1.0 : 0.0);
   for (int k = 0; k < 3; k++) p[k] = dcon(0.0);
-  int K = rb->pts_per_seg;
+  int K = rb->pts_per_seg, zc = cro_ncoord(rb);
   for (int i = 0; i < rb->n_seg; i++) {
+    dual Li = seg_len(rb, z, i);
     if (pts) {
       for (int k = 1; k <= K; k++) {
         double sg = (double)k / (double)K;
         dual Rk[9], dk[3], q[3];
-        arc_transform(dscale(sg, z[2 * i]), dscale(sg, z[2 * i + 1]), dcon(sg * rb->L[i]), Rk, dk);
+        arc_transform(dscale(sg, z[zc * i]), dscale(sg, z[zc * i + 1]), dscale(sg, Li), Rk, dk);
         mat_vec(R, dk, q);
         for (int c = 0; c < 3; c++) pts[i * K + k - 1][c] = dadd(p[c], q[c]);
       }
     }
     dual Ri[9], di[3], q[3], Rn[9];
-    arc_transform(z[2 * i], z[2 * i + 1], dcon(rb->L[i]), Ri, di);
+    arc_transform(z[zc * i], z[zc * i + 1], Li, Ri, di);
     mat_vec(R, di, q);
     for (int c = 0; c < 3; c++) p[c] = dadd(p[c], q[c]);
     mat_mul(R, Ri, Rn);
@@ -349,22 +372,23 @@ static void fk_chain(const cro_robot* rb, const dual* z, dual (*Rf)[9], dual (*p
 }
 
 int cro_fk(const cro_robot* rb, const double* u, double* arc, double* frames, double* pts) {
-  int n = rb->n_seg, K = rb->pts_per_seg;
+  int n = rb->n_seg, K = rb->pts_per_seg, zc = cro_ncoord(rb);
   double zz[CRO_MAX_DIR];
   dual z[CRO_MAX_DIR], Rf[CRO_MAX_SEG][9], pf[CRO_MAX_SEG][3];
   nd = 0;
   cro_u_to_z(rb, u, zz);
-  for (int k = 0; k < 2 * n; k++) z[k] = dcon(zz[k]);
+  for (int k = 0; k < zc * n; k++) z[k] = dcon(zz[k]);
   dual(*P)[3] = NULL;
   if (pts && K > 0) P = (dual(*)[3])malloc(sizeof(dual[3]) * (size_t)(n * K));
   fk_chain(rb, z, Rf, pf, P);
   for (int i = 0; i < n; i++) {
-    double a = zz[2 * i], b = zz[2 * i + 1], th = sqrt(a * a + b * b);
+    double a = zz[zc * i], b = zz[zc * i + 1], th = sqrt(a * a + b * b);
     double ph = (th > 0.0) ? atan2(b, a) : 0.0;
     if (ph < 0.0) ph += 2.0 * PI;
-    arc[3 * i] = th / rb->L[i];
+    double Li = seg_len(rb, z, i).v;
+    arc[3 * i] = th / Li;
     arc[3 * i + 1] = ph;
-    arc[3 * i + 2] = rb->L[i];
+    arc[3 * i + 2] = Li;
     if (frames) {
       for (int r = 0; r < 3; r++) {
         for (int c = 0; c < 3; c++) frames[12 * i + 4 * r + c] = Rf[i][3 * r + c].v;
@@ -589,7 +613,7 @@ enum { T_TASK = 1, T_LIMITS = 2, T_COLL = 4, T_SMOOTH = 8, T_LEN = 16, T_ENDS = 
 
 static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
                          const double* z, sink* s, int terms) {
-  int n = rb->n_seg, nz = 2 * n, H = pb->H, K = rb->pts_per_seg;
+  int n = rb->n_seg, zc = cro_ncoord(rb), nz = zc * n, H = pb->H, K = rb->pts_per_seg;
   int derive = (s->g || s->Hm || s->J);
   nd = derive ? nz : 0;
   s->cost = 0.0;
@@ -622,20 +646,28 @@ static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_pr
         emit_lin(s, w->w_rot, 1, &tm);
       }
     }
-    /* actuation bounds, eq. (9): |u_ij| <= u_max_i */
+    /* actuation bounds, eq. (9): |u_ij| <= u_max_i on the bending part of each tendon */
     for (int i = 0; i < n && (terms & T_LIMITS); i++)
       for (int j = 0; j < 3; j++) {
-        term tm = {t, 1.0, &W->u[3 * i + j]};
+        dual ub = bend_dual(rb, W->z, i, j);
+        term tm = {t, 1.0, &ub};
         emit_hinge(s, sq_lim, rb->u_max[i], 1, &tm);
       }
     /* bending bound, eq. (9): theta_i <= theta_max */
     for (int i = 0; i < n && (terms & T_LIMITS); i++) {
-      double th = sqrt(z[t * nz + 2 * i] * z[t * nz + 2 * i] + z[t * nz + 2 * i + 1] * z[t * nz + 2 * i + 1]);
+      double th = sqrt(z[t * nz + zc * i] * z[t * nz + zc * i] + z[t * nz + zc * i + 1] * z[t * nz + zc * i + 1]);
       if (th - rb->theta_max > 0.0) {
-        dual thd = dsqrt(dadd(dmul(W->z[2 * i], W->z[2 * i]), dmul(W->z[2 * i + 1], W->z[2 * i + 1])));
+        dual thd = dsqrt(dadd(dmul(W->z[zc * i], W->z[zc * i]), dmul(W->z[zc * i + 1], W->z[zc * i + 1])));
         term tm = {t, 1.0, &thd};
         emit_hinge(s, sq_curv, rb->theta_max, 1, &tm);
       }
+    }
+    /* length bounds of extensible segments, eq. (9): L_min_i <= L_i <= L_max_i, one
+     * hinge on the distance from the interval's centre beyond its half width */
+    for (int i = 0; i < n && zc == 3 && (terms & T_LIMITS); i++) {
+      dual off = dshift(seg_len(rb, W->z, i), -0.5 * (rb->L_min[i] + rb->L_max[i]));
+      term tm = {t, 1.0, &off};
+      emit_hinge(s, sq_lim, 0.5 * (rb->L_max[i] - rb->L_min[i]), 1, &tm);
     }
     /* obstacle clearance, eq. (10) */
     if (pts && (terms & T_COLL)) collision_rows(rb, w, pb, t, pts, s);
@@ -700,7 +732,7 @@ static sink make_sink(int nz, int N) {
 
 double cro_cost(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const double* u,
                 double* grad_u) {
-  int n = rb->n_seg, nz = 2 * n, T = pb->H + 1, N = T * nz;
+  int n = rb->n_seg, zc = cro_ncoord(rb), nz = zc * n, T = pb->H + 1, N = T * nz;
   double* z = (double*)malloc(sizeof(double) * (size_t)N);
   for (int t = 0; t < T; t++) cro_u_to_z(rb, u + 3 * n * t, z + nz * t);
   sink s = make_sink(nz, N);
@@ -711,13 +743,16 @@ double cro_cost(const cro_robot* rb, const cro_weights* w, const cro_problem* pb
   }
   double c = eval_cost(rb, w, pb, z, &s);
   if (grad_u) {
-    /* chain rule through z(u) of cro_u_to_z: dz_{2i}/du_ij = -cos(alpha_j)/(1.5 r_i), ... */
+    /* chain rule through z(u) of cro_u_to_z: da_i/du_ij = -cos(alpha_j)/(1.5 r_i),
+     * db_i/du_ij = -sin(alpha_j)/(1.5 r_i), de_i/du_ij = 1/3 */
     for (int t = 0; t < T; t++)
       for (int i = 0; i < n; i++)
-        for (int j = 0; j < 3; j++)
+        for (int j = 0; j < 3; j++) {
           grad_u[t * 3 * n + 3 * i + j] =
-              -(gz[t * nz + 2 * i] * cos(alpha_j(j)) + gz[t * nz + 2 * i + 1] * sin(alpha_j(j))) /
+              -(gz[t * nz + zc * i] * cos(alpha_j(j)) + gz[t * nz + zc * i + 1] * sin(alpha_j(j))) /
               (1.5 * rb->r[i]);
+          if (zc == 3) grad_u[t * 3 * n + 3 * i + j] += gz[t * nz + zc * i + 2] / 3.0;
+        }
     free(gz);
   }
   free(z);
@@ -726,7 +761,7 @@ double cro_cost(const cro_robot* rb, const cro_weights* w, const cro_problem* pb
 
 int cro_residuals(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const double* z,
                   double* r, double* J, int cap_rows) {
-  int nz = 2 * rb->n_seg, N = (pb->H + 1) * nz;
+  int nz = cro_ncoord(rb) * rb->n_seg, N = (pb->H + 1) * nz;
   sink s = make_sink(nz, N);
   s.r = r;
   s.J = J;
@@ -740,7 +775,7 @@ void cro_pose_error(const cro_robot* rb, const double* z, const double* T, doubl
   int n = rb->n_seg;
   nd = 0;
   dual zd[ND], Rf[CRO_MAX_SEG][9], pf[CRO_MAX_SEG][3], rho[3], om[3];
-  for (int k = 0; k < 2 * n; k++) zd[k] = dcon(z[k]);
+  for (int k = 0; k < cro_ncoord(rb) * n; k++) zd[k] = dcon(z[k]);
   fk_chain(rb, zd, Rf, pf, NULL);
   pose_log(Rf[n - 1], pf[n - 1], T, rho, om);
   double e2 = 0.0;
@@ -813,7 +848,7 @@ static int band_of(const cro_problem* pb, int nz) {
 
 int cro_lm(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o,
            double* z, double* lambda, int iters, double* cost_out, int* trials_out) {
-  int nz = 2 * rb->n_seg, N = (pb->H + 1) * nz, bw = band_of(pb, nz);
+  int nz = cro_ncoord(rb) * rb->n_seg, N = (pb->H + 1) * nz, bw = band_of(pb, nz);
   double* Hm = (double*)malloc(sizeof(double) * (size_t)N * N);
   double* g = (double*)malloc(sizeof(double) * (size_t)N);
   double* dlt = (double*)malloc(sizeof(double) * (size_t)N);
@@ -943,7 +978,7 @@ void cro_select_top(int S, int nz, const double* z, const double* e, const doubl
 
 /* Success / status of a solution z (Sec. V-B, with 1 mm / 1 degree thresholds). */
 static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* z, double* err) {
-  int n = rb->n_seg, nz = 2 * n, T = pb->H + 1, K = rb->pts_per_seg;
+  int n = rb->n_seg, zc = cro_ncoord(rb), nz = zc * n, T = pb->H + 1, K = rb->pts_per_seg;
   double pos = 0.0, rot = 0.0, viol = 0.0, thx = 0.0, gmin = INFINITY;
   int finite = 1;
   for (int t = 0; t < T; t++) {
@@ -966,8 +1001,14 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
     double u[3 * CRO_MAX_SEG];
     cro_z_to_u(rb, zt, u);
     for (int i = 0; i < n; i++) {
-      for (int j = 0; j < 3; j++) viol = fmax(viol, fabs(u[3 * i + j]) - rb->u_max[i]);
-      double th = sqrt(zt[2 * i] * zt[2 * i] + zt[2 * i + 1] * zt[2 * i + 1]);
+      /* tendon bound on the bending part; extensible segments: length within bounds */
+      double e = zc == 3 ? zt[zc * i + 2] : 0.0;
+      for (int j = 0; j < 3; j++) viol = fmax(viol, fabs(u[3 * i + j] - e) - rb->u_max[i]);
+      if (zc == 3) {
+        viol = fmax(viol, rb->L_min[i] - (rb->L[i] + e));
+        viol = fmax(viol, (rb->L[i] + e) - rb->L_max[i]);
+      }
+      double th = sqrt(zt[zc * i] * zt[zc * i] + zt[zc * i + 1] * zt[zc * i + 1]);
       thx = fmax(thx, th - rb->theta_max);
     }
     if (pb->n_sph > 0 && K > 0) {
@@ -1009,7 +1050,7 @@ static int ik_ok(const cro_robot* rb, const cro_problem* pb, const double* T, co
 
 void cro_path_seeds(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
                     const double* u_seed, int k, double* z_out) {
-  int n = rb->n_seg, nz = 2 * n, T = pb->H + 1;
+  int n = rb->n_seg, nz = cro_ncoord(rb) * n, T = pb->H + 1;
   double* cand = (double*)malloc(sizeof(double) * (size_t)S * T * nz);
   int* ok = (int*)malloc(sizeof(int) * (size_t)S * T);
   int* fin = (int*)malloc(sizeof(int) * (size_t)S * T);
@@ -1063,7 +1104,7 @@ void cro_path_seeds(const cro_robot* rb, const cro_weights* w, const cro_problem
 int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
               const double* u_seed, double* u_out, double* err_out, int32_t* status, int32_t* best_idx,
               double* best_cost) {
-  int n = rb->n_seg, nz = 2 * n, T = pb->H + 1, N = T * nz;
+  int n = rb->n_seg, nz = cro_ncoord(rb) * n, T = pb->H + 1, N = T * nz;
   if (n < 1 || n > CRO_MAX_SEG || S < 1 || pb->H < 0 || (pb->kind == CRO_IK && pb->H != 0) ||
       (pb->kind == CRO_TRAJ && pb->H < 1))
     return -1;

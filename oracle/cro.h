@@ -10,8 +10,10 @@
  *   u    tendon displacements of one configuration, u[3*i + j] = length change of
  *        tendon j (at angle alpha_j = 2*pi*j/3) in segment i relative to L_i
  *        (Sec. III-B, eq. 4).
- *   z    bending coordinates of one configuration, z[2*i] = a_i = theta_i cos phi_i,
- *        z[2*i+1] = b_i = theta_i sin phi_i (the iterate of the solver).
+ *   z    coordinates of one configuration (the iterate of the solver), c per
+ *        segment: z[c*i] = a_i = theta_i cos phi_i, z[c*i+1] = b_i = theta_i sin phi_i,
+ *        and for extensible robots (c = 3) z[3*i+2] = e_i = mean_j u_ij, the change
+ *        of the segment's length (L_i = L[i] + e_i); c = 2 otherwise.
  *   T    a pose as 12 doubles, 3x4 row-major [R | p].
  * A trajectory (kinds PATH/TRAJ) stores H+1 configurations back to back.
  */
@@ -20,7 +22,7 @@
 #include <stdint.h>
 
 #define CRO_MAX_SEG 6
-#define CRO_MAX_DIR (2 * CRO_MAX_SEG)
+#define CRO_MAX_DIR (3 * CRO_MAX_SEG)
 
 enum { CRO_IK = 0, CRO_PATH = 1, CRO_TRAJ = 2 };
 enum {
@@ -38,6 +40,11 @@ typedef struct {
   double r[CRO_MAX_SEG];     /* tendon routing radius r_c of each segment, m */
   double u_max[CRO_MAX_SEG]; /* bound on |tendon displacement|, m */
   double theta_max;          /* bound on each bending angle theta_i, rad */
+  int32_t extensible;        /* 0: inextensible, the common mode of a segment's tendons is
+                                ignored (eq. 4 with L fixed); 1: the common mode is the
+                                segment's extension, L_i = L[i] + mean_j u_ij (Sec. V-B) */
+  double L_min[CRO_MAX_SEG]; /* extensible: bounds on each segment length (eq. 9), m */
+  double L_max[CRO_MAX_SEG];
 } cro_robot;
 
 typedef struct {
@@ -71,7 +78,11 @@ typedef struct {
 extern "C" {
 #endif
 
-/* tendon displacements -> bending coordinates, and the zero-sum lift back */
+/* coordinates per segment: 3 for extensible robots, else 2 */
+int cro_ncoord(const cro_robot* rb);
+
+/* tendon displacements -> coordinates z, and the lift back (zero-sum per segment
+ * when inextensible; with mean e_i when extensible) */
 void cro_u_to_z(const cro_robot* rb, const double* u, double* z);
 void cro_z_to_u(const cro_robot* rb, const double* z, double* u);
 
@@ -86,7 +97,7 @@ int cro_fk(const cro_robot* rb, const double* u, double* arc, double* frames, do
 double cro_cost(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
                 const double* u, double* grad_u);
 
-/* Residual vector r and dense Jacobian J = dr/dz ([m][(H+1)*2n]) at z.
+/* Residual vector r and dense Jacobian J = dr/dz ([m][(H+1)*c*n]) at z.
  * Returns the number of residual rows m, or -1 if it would exceed cap_rows. */
 int cro_residuals(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
                   const double* z, double* r, double* J, int cap_rows);
@@ -118,7 +129,7 @@ void cro_select_top(int S, int nz, const double* z, const double* e, const doubl
  * success test (1 mm, 1 degree, bounds, no penetration), the one nearest in
  * the infinity norm over z to the path's previous waypoint (ties: lower seed);
  * if none passes, the nearest finite one; if none is finite, the previous
- * waypoint's z again.  z_out[S][(H+1)*2n]. */
+ * waypoint's z again.  z_out[S][(H+1)*c*n]. */
 void cro_path_seeds(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, const cro_opts* o, int S,
                     const double* u_seed, int k, double* z_out);
 

@@ -7,7 +7,8 @@ with the GPU library (``paper_2607_11340_amd``) and never imports it.
 
 Arrays are numpy float64, item-major:
   u  [..., n, 3]   tendon displacements (Sec. III-B, eq. 4 minus L_i)
-  z  [..., n, 2]   bending coordinates (a, b) = theta (cos phi, sin phi)
+  z  [..., n, c]   coordinates: bending (a, b) = theta (cos phi, sin phi), and for
+                   extensible robots (c = 3) the extension e = mean tendon displacement
   T  [..., 3, 4]   pose [R | p]
 """
 from __future__ import annotations
@@ -42,7 +43,8 @@ def build(force: bool = True) -> str:
 class _Robot(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("pts_per_seg", C.c_int32),
                 ("L", C.c_double * MAX_SEG), ("r", C.c_double * MAX_SEG),
-                ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double)]
+                ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double),
+                ("extensible", C.c_int32), ("L_min", C.c_double * MAX_SEG), ("L_max", C.c_double * MAX_SEG)]
 
 
 class _Weights(C.Structure):
@@ -69,10 +71,21 @@ class Robot:
     u_max: list
     pts_per_seg: int = 10
     theta_max: float = np.pi
+    L_min: list = None     # extensible robots: bounds on each segment length (m);
+    L_max: list = None     # both given <=> the segment lengths are decision variables
 
     @property
     def n(self) -> int:
         return len(self.L)
+
+    @property
+    def extensible(self) -> bool:
+        return self.L_min is not None and self.L_max is not None
+
+    @property
+    def nc(self) -> int:
+        """coordinates per segment"""
+        return 3 if self.extensible else 2
 
     def c(self) -> _Robot:
         s = _Robot()
@@ -81,6 +94,10 @@ class Robot:
         for i in range(self.n):
             s.L[i], s.r[i], s.u_max[i] = self.L[i], self.r[i], self.u_max[i]
         s.theta_max = self.theta_max
+        s.extensible = 1 if self.extensible else 0
+        if self.extensible:
+            for i in range(self.n):
+                s.L_min[i], s.L_max[i] = self.L_min[i], self.L_max[i]
         return s
 
 
@@ -183,19 +200,20 @@ class Problem:
 def u_to_z(robot: Robot, u):
     u = np.asarray(u, dtype=np.float64)
     flat = u.reshape(-1, robot.n * 3)
-    out = np.empty((flat.shape[0], robot.n * 2))
+    nc = robot.nc
+    out = np.empty((flat.shape[0], robot.n * nc))
     rc = robot.c()
     for k in range(flat.shape[0]):
         a, pa = _d(flat[k])
-        o = np.empty(robot.n * 2)
+        o = np.empty(robot.n * nc)
         lib().cro_u_to_z(C.byref(rc), pa, o.ctypes.data_as(C.POINTER(C.c_double)))
         out[k] = o
-    return out.reshape(u.shape[:-2] + (robot.n, 2))
+    return out.reshape(u.shape[:-2] + (robot.n, nc))
 
 
 def z_to_u(robot: Robot, z):
     z = np.asarray(z, dtype=np.float64)
-    flat = z.reshape(-1, robot.n * 2)
+    flat = z.reshape(-1, robot.n * robot.nc)
     out = np.empty((flat.shape[0], robot.n * 3))
     rc = robot.c()
     for k in range(flat.shape[0]):
@@ -261,7 +279,7 @@ def residuals(robot: Robot, weights: Weights, prob: Problem, z, cap: int = 20000
 
 
 def pose_error(robot: Robot, z, T):
-    """(e, position error, rotation angle) of z [n, 2] against T [3, 4] (eq. 18)."""
+    """(e, position error, rotation angle) of z [n, c] against T [3, 4] (eq. 18)."""
     z, pz = _d(z)
     T, pT = _d(T)
     out = np.empty(3)
@@ -309,11 +327,11 @@ def select_top(z, e, pen, failed, n_final: int, dup_eps: float = 1e-3):
 
 def path_seeds(robot: Robot, weights: Weights, prob: Problem, opts: Opts, u_seed, k: int):
     """Per-waypoint IK and path assembly (cro_path_seeds); u_seed [S, H+1, n, 3]
-    -> z [S, H+1, n, 2]."""
+    -> z [S, H+1, n, c]."""
     u_seed = np.asarray(u_seed, dtype=np.float64)
     S = u_seed.shape[0]
     us, pu = _d(u_seed)
-    z = np.empty((S, prob.H + 1, robot.n, 2))
+    z = np.empty((S, prob.H + 1, robot.n, robot.nc))
     rc, wc, oc = robot.c(), weights.c(), opts.c()
     lib().cro_path_seeds(C.byref(rc), C.byref(wc), C.byref(prob.c), C.byref(oc), S, pu, int(k),
                          z.ctypes.data_as(C.POINTER(C.c_double)))
