@@ -77,6 +77,15 @@ typedef struct {
   double r[CR_MAX_SEG];       /* tendon routing radius r_c (m), > 0; also the body radius */
   double u_max[CR_MAX_SEG];   /* bound on |u| of each tendon of the segment (m), > 0 */
   double theta_max;           /* bound on each bending angle (rad), default pi */
+  int32_t extensible;         /* 0: inextensible segments, the common mode of each segment's
+                                 three tendons is ignored (eq. 4 with L fixed).  1: extensible
+                                 segments (the extendable robots of Sec. V-B): the common mode
+                                 mean_j u_ij is the change of the segment's length,
+                                 L_i = L[i] + mean_j u_ij, bounded by [L_min, L_max] (eq. 9);
+                                 u_max then bounds the bending part u_ij - mean_j u_ij.
+                                 Supported by cr_fk, cr_cost_grad (IK) and cr_solve_ik. */
+  double L_min[CR_MAX_SEG];   /* extensible: segment length bounds (m), 0 < L_min <= L <= L_max */
+  double L_max[CR_MAX_SEG];
 } cr_robot;
 
 /* Spherical obstacles.  [host] struct, `sph` is [device] in the call's dtype for
@@ -390,6 +399,16 @@ int64_t cr_autotune_report(char* buf, int64_t cap);
  *   transcendental count 1.  Runs on the calling thread; no device work. */
 cr_status cr_ik_flop_tally(const cr_robot* robot, const cr_weights* weights, const cr_opts* opts, int64_t n,
                            const double* T_target, const double* u_seed, double* out);
+
+/* Calibration of the vector-ALU accounting: launches `blocks` workgroups of 256
+ * lanes, each lane running `iters` rounds over 16 independent chains of one
+ * instruction per chain and round: kind 0 v_fma_f32, 1 v_rcp_f32, 2 v_fma_f32 on
+ * every chain plus v_rcp_f32 on every fourth, 3 v_fma_f64.  The known instruction
+ * count per wave (16 or 20 per round) against the measured duration gives the
+ * issue rate the SIMDs reach, and against the SQ_INSTS_VALU* counters what those
+ * count.  out [device] receives blocks * 256 floats.  CR_EINVAL for kind not in
+ * 0..3, blocks not in 1..2^20, iters < 1 or out == NULL. */
+cr_status cr_calib_valu(int32_t kind, int64_t blocks, int32_t iters, float* out, hipStream_t stream);
 
 /* Text for a status code, and the thread's last error message. */
 const char* cr_status_string(cr_status s);

@@ -30,7 +30,7 @@ SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
            "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_baseline_traj_workspace",
-           "cr_select_top",
+           "cr_select_top", "cr_calib_valu",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_autotune_enable", "cr_autotune_clear", "cr_autotune_force",
            "cr_autotune_report", "cr_status_string", "cr_last_error")
 
@@ -44,7 +44,8 @@ class CRError(RuntimeError):
 class _Robot(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("pts_per_seg", C.c_int32),
                 ("L", C.c_double * MAX_SEG), ("r", C.c_double * MAX_SEG),
-                ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double)]
+                ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double),
+                ("extensible", C.c_int32), ("L_min", C.c_double * MAX_SEG), ("L_max", C.c_double * MAX_SEG)]
 
 
 class _Spheres(C.Structure):
@@ -78,10 +79,21 @@ class Robot:
     u_max: list
     pts_per_seg: int = 10
     theta_max: float = math.pi
+    L_min: list = None   # extensible segments: length bounds (m); both given <=> the
+    L_max: list = None   # common mode of each segment's tendons is its extension
 
     @property
     def n(self) -> int:
         return len(self.L)
+
+    @property
+    def extensible(self) -> bool:
+        return self.L_min is not None and self.L_max is not None
+
+    @property
+    def nc(self) -> int:
+        """coordinates per segment in the solver (a, b and, if extensible, e)"""
+        return 3 if self.extensible else 2
 
     def c(self) -> _Robot:
         s = _Robot()
@@ -89,6 +101,10 @@ class Robot:
         for i in range(self.n):
             s.L[i], s.r[i], s.u_max[i] = self.L[i], self.r[i], self.u_max[i]
         s.theta_max = self.theta_max
+        if self.extensible:
+            s.extensible = 1
+            for i in range(self.n):
+                s.L_min[i], s.L_max[i] = self.L_min[i], self.L_max[i]
         return s
 
 
@@ -158,6 +174,7 @@ def _load():
     L.cr_solve_ik_workspace.argtypes = [R, i64, i32, O, C.c_int]
     L.cr_solve_ik_workspace.restype = C.c_size_t
     L.cr_select_top.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, C.c_double, vp, C.c_int, vp]
+    L.cr_calib_valu.argtypes = [i32, i64, i32, vp, vp]
     L.cr_timing_enable.argtypes = [i32]
     L.cr_timing_enable.restype = None
     L.cr_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -176,7 +193,7 @@ def _load():
     L.cr_last_error.restype = C.c_char_p
     for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
                  "cr_baseline_solve_ik", "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_select_top",
-                 "cr_timing_read", "cr_ik_flop_tally"):
+                 "cr_timing_read", "cr_ik_flop_tally", "cr_calib_valu"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -565,6 +582,13 @@ class CostGrad(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         _, g = cost_grad(ctx.problem, u.detach(), grad=True, grad_scale=gcost.contiguous())
         return g, None
+
+
+def calib_valu(kind: int, blocks: int, iters: int, out: torch.Tensor):
+    """One launch of the vector-ALU calibration loop `kind` (cr_calib_valu);
+    out: float32 CUDA tensor of blocks * 256 elements."""
+    _need(out, (blocks * 256,), torch.float32, "out")
+    _check(lib.cr_calib_valu(int(kind), int(blocks), int(iters), _ptr(out), _stream(out)))
 
 
 def autotune(on: bool = True):

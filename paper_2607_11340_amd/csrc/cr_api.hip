@@ -43,6 +43,14 @@ RobotT<T> robot_to(const cr_robot& r) {
     o.umaxd[i] = i < r.n_seg ? r.u_max[i] : 0.0;
   }
   o.theta_maxd = r.theta_max;
+  o.ext = r.extensible ? 1 : 0;
+  for (int i = 0; i < CR_MAX_SEG; ++i) {
+    const bool on = r.extensible && i < r.n_seg;
+    o.Lmidd[i] = on ? 0.5 * (r.L_min[i] + r.L_max[i]) : 0.0;
+    o.Lhalfd[i] = on ? 0.5 * (r.L_max[i] - r.L_min[i]) : 0.0;
+    o.Lmid[i] = (T)o.Lmidd[i];
+    o.Lhalf[i] = (T)o.Lhalfd[i];
+  }
   return o;
 }
 template RobotT<float> robot_to<float>(const cr_robot&);
@@ -136,6 +144,16 @@ cr_status check_robot(const cr_robot* rb) {
     if (!(rb->u_max[i] > 0.0)) return fail(CR_EINVAL, "u_max[%d] must be > 0", i);
   }
   if (!(rb->theta_max > 0.0)) return fail(CR_EINVAL, "theta_max must be > 0");
+  if (rb->extensible != 0 && rb->extensible != 1) return fail(CR_EINVAL, "extensible must be 0 or 1");
+  for (int i = 0; rb->extensible && i < rb->n_seg; ++i)
+    if (!(rb->L_min[i] > 0.0) || !(rb->L_min[i] <= rb->L[i]) || !(rb->L[i] <= rb->L_max[i]) || !isfinite(rb->L_max[i]))
+      return fail(CR_EINVAL, "extensible segment %d needs 0 < L_min <= L <= L_max (finite)", i);
+  return CR_OK;
+}
+
+cr_status check_inextensible(const cr_robot* rb, const char* what) {
+  if (rb && rb->extensible) return fail(CR_EUNSUPPORTED, "%s: extensible segments are supported by cr_fk, "
+                                                          "cr_cost_grad (IK) and cr_solve_ik only", what);
   return CR_OK;
 }
 
@@ -267,7 +285,7 @@ static cr_status check_traj_args(const cr_robot* robot, const cr_spheres* sphere
                                  const cr_opts* opts, int64_t P, int32_t H, int32_t S, int kind, cr_dtype dtype) {
   cr_status rc;
   if ((rc = check_robot(robot)) != CR_OK || (rc = check_dtype(dtype)) != CR_OK || (rc = check_opts(opts)) != CR_OK ||
-      (rc = check_weights(weights)) != CR_OK)
+      (rc = check_weights(weights)) != CR_OK || (rc = check_inextensible(robot, "path / trajectory solve")) != CR_OK)
     return rc;
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
   if (H < (kind == CR_KIND_TRAJ ? 1 : 0) || H > 255) return fail(CR_EINVAL, "H=%d out of range", H);
@@ -320,7 +338,8 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres,
                                void* u_out, void* err_out, int32_t* status_out, void* ws, size_t ws_bytes,
                                hipStream_t stream) {
   cr_status rc;
-  if ((rc = check_robot(robot)) != CR_OK || (rc = check_opts(opts)) != CR_OK || (rc = check_weights(weights)) != CR_OK)
+  if ((rc = check_robot(robot)) != CR_OK || (rc = check_opts(opts)) != CR_OK || (rc = check_weights(weights)) != CR_OK ||
+      (rc = check_inextensible(robot, "cr_baseline_solve_ik")) != CR_OK)
     return rc;
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
   if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
@@ -423,7 +442,8 @@ cr_status cr_timing_read(double* stage_ms, int64_t* n_calls) {
 cr_status cr_ik_flop_tally(const cr_robot* robot, const cr_weights* weights, const cr_opts* opts, int64_t n,
                            const double* T_target, const double* u_seed, double* out) {
   cr_status rc;
-  if ((rc = check_robot(robot)) != CR_OK || (rc = check_opts(opts)) != CR_OK || (rc = check_weights(weights)) != CR_OK)
+  if ((rc = check_robot(robot)) != CR_OK || (rc = check_opts(opts)) != CR_OK || (rc = check_weights(weights)) != CR_OK ||
+      (rc = check_inextensible(robot, "cr_ik_flop_tally")) != CR_OK)
     return rc;
   if (n < 1 || !T_target || !u_seed || !out) return fail(CR_EINVAL, "need n >= 1 and non-NULL host arrays");
   return tally_ik_dispatch(*robot, *weights, *opts, n, T_target, u_seed, out);
@@ -461,6 +481,8 @@ cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* sp
     return rc;
   if (kind != CR_KIND_IK && kind != CR_KIND_PATH && kind != CR_KIND_TRAJ) return fail(CR_EINVAL, "kind %d invalid", kind);
   if (kind == CR_KIND_IK && H != 0) return fail(CR_EINVAL, "IK needs H = 0");
+  if (kind != CR_KIND_IK && (rc = check_inextensible(robot, "cr_cost_grad for paths and trajectories")) != CR_OK)
+    return rc;
   if (kind == CR_KIND_TRAJ && H < 1) return fail(CR_EINVAL, "TRAJ needs H >= 1");
   if (H < 0 || H > 255) return fail(CR_EINVAL, "H=%d not in 0..255", H);
   if (P < 0 || S < 1) return fail(CR_EINVAL, "need P >= 0 and S >= 1");

@@ -44,6 +44,7 @@ cr_status check_table(const cr_robot* robots, int32_t n_robots, const cr_problem
   if (!robots || n_robots < 1) return fail(CR_EINVAL, "need at least one robot");
   for (int r = 0; r < n_robots; ++r) {
     cr_status rc = check_robot(&robots[r]);
+    if (rc == CR_OK) rc = check_inextensible(&robots[r], "cr_solve_batch");
     if (rc != CR_OK) return rc;
   }
   if (!opts) return fail(CR_EINVAL, "opts is NULL");

@@ -26,12 +26,13 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return s;
 }
 
-template <int NS, typename T, bool GRAD>
+// EXT: extensible segments, the third coordinate e_i = mean_j u_ij per segment.
+template <int NS, typename T, bool GRAD, bool EXT = false>
 __global__ void __launch_bounds__(256)
     k_cost_ik(RobotT<T> rb, WeightsT<T> w, int64_t P, int S, const T* __restrict__ task, const T* __restrict__ sph,
               int64_t sld, int M, int per_problem, const T* __restrict__ u, T* __restrict__ cost, T* __restrict__ grad,
               const T* __restrict__ gscale) {
-  constexpr int NZ = 2 * NS;
+  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
   const int64_t B = P * (int64_t)S;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -40,31 +41,36 @@ __global__ void __launch_bounds__(256)
   double zd[NZ];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    u_to_ab((double)u[(3 * i) * B + b], (double)u[(3 * i + 1) * B + b], (double)u[(3 * i + 2) * B + b], rb.rd[i],
-            &zd[2 * i], &zd[2 * i + 1]);
-    z[2 * i] = (T)zd[2 * i];
-    z[2 * i + 1] = (T)zd[2 * i + 1];
+    const double u0 = (double)u[(3 * i) * B + b], u1 = (double)u[(3 * i + 1) * B + b],
+                 u2 = (double)u[(3 * i + 2) * B + b];
+    u_to_ab(u0, u1, u2, rb.rd[i], &zd[NC * i], &zd[NC * i + 1]);
+    if constexpr (EXT) zd[NC * i + 2] = (u0 + u1 + u2) * (1.0 / 3.0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) z[NC * i + c] = (T)zd[NC * i + c];
   }
   T tt[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) tt[c] = task[c * P + p];
-  Fwd<NS, T> f;
+  Fwd<NS, T, EXT> f;
   const T* sp = sph ? sph + (per_problem ? p * M : 0) : nullptr;
-  T c = (sph && M > 0) ? config_forward<NS, T, GRAD, double>(rb, w, z, sp, M, 1, sld, f, zd)
-                        : config_forward<NS, T, GRAD>(rb, w, z, sp, 0, 1, sld, f, zd);
+  T c = (sph && M > 0) ? config_forward<NS, T, GRAD, double, T, EXT>(rb, w, z, sp, M, 1, sld, f, zd)
+                        : config_forward<NS, T, GRAD, T, T, EXT>(rb, w, z, sp, 0, 1, sld, f, zd);
   T ft[3] = {T(0), T(0), T(0)}, tq[3] = {T(0), T(0), T(0)};
   c += pose_term<T, GRAD>(w, f.R, f.p, tt, ft, tq);
   cost[b] = c;
   if (GRAD) {
     T gz[NZ];
-    config_reverse<NS>(f, ft, tq, gz);
+    config_reverse<NS, T, EXT>(f, ft, tq, gz);
     const T sc = gscale ? gscale[b] : T(1);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T gu[3];
-      gz_to_gu(gz[2 * i], gz[2 * i + 1], rb.r[i], gu);
+      gz_to_gu(gz[NC * i], gz[NC * i + 1], rb.r[i], gu);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) grad[(3 * i + j) * B + b] = sc * gu[j];
+      for (int j = 0; j < 3; ++j) {
+        if constexpr (EXT) gu[j] += gz[NC * i + 2] * T(1.0 / 3.0);  // de_i / du_ij = 1/3
+        grad[(3 * i + j) * B + b] = sc * gu[j];
+      }
     }
   }
 }
@@ -244,12 +250,17 @@ static cr_status run_cost(int kind, const cr_robot& rb0, const cr_spheres* sp, c
   if (B == 0) return CR_OK;
   if (kind == CR_KIND_IK) {
     const unsigned nb = (unsigned)((B + 255) / 256);
-    if (grad)
-      hipLaunchKernelGGL((k_cost_ik<NS, T, true>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld,
-                         M, ppb, (const T*)u, (T*)cost, (T*)grad, (const T*)gscale);
-    else
-      hipLaunchKernelGGL((k_cost_ik<NS, T, false>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld,
-                         M, ppb, (const T*)u, (T*)cost, (T*)nullptr, (const T*)nullptr);
+#define CR_COST_IK(G, E)                                                                                          \
+  hipLaunchKernelGGL((k_cost_ik<NS, T, G, E>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld, M, \
+                     ppb, (const T*)u, (T*)cost, G ? (T*)grad : (T*)nullptr, G ? (const T*)gscale : (const T*)nullptr)
+    if (rb0.extensible) {
+      if (grad) CR_COST_IK(true, true);
+      else CR_COST_IK(false, true);
+    } else {
+      if (grad) CR_COST_IK(true, false);
+      else CR_COST_IK(false, false);
+    }
+#undef CR_COST_IK
     return check_hip(hipGetLastError(), "k_cost_ik");
   }
   const int Tn = H + 1;

@@ -5,7 +5,11 @@
 //
 // Coordinates: each segment i is described by its bending coordinates
 // (a_i, b_i) = theta_i (cos phi_i, sin phi_i) (Sec. III-A, q = (theta, phi, L) with
-// L fixed); tendon displacements u map to them linearly through eq. (4).
+// L fixed); tendon displacements u map to them linearly through eq. (4).  Robots
+// with extensible segments (the extendable robots of Sec. V-B) carry a third
+// coordinate per segment, the extension e_i = mean_j u_ij, with L_i = L[i] + e_i;
+// the functions of the generic per-configuration path take EXT for them (NC = 3
+// coordinates per segment, stored a, b, e).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,6 +36,10 @@ struct RobotT {
   // difference of nearly equal numbers, so it is formed in FP64 whatever the
   // kernel's type.
   double Ld[CR_MAX_SEG], rd[CR_MAX_SEG], umaxd[CR_MAX_SEG], theta_maxd;
+  // extensible segments: centre and half width of each length interval (eq. 9)
+  int ext;
+  T Lmid[CR_MAX_SEG], Lhalf[CR_MAX_SEG];
+  double Lmidd[CR_MAX_SEG], Lhalfd[CR_MAX_SEG];
 };
 
 template <typename T>
@@ -315,18 +323,26 @@ CR_HD void seg_R_d(T a, T b, T L, const ArcCoef<T>& c, T* R, T* d) {
   d[2] = L * c.B;
 }
 
+// Length of segment i at coordinates z (NC per segment).
+template <bool EXT, typename T>
+CR_HD T seg_len(const RobotT<T>& rb, const T* z, int i) {
+  if constexpr (EXT) return rb.L[i] + z[3 * i + 2];
+  else return rb.L[i];
+}
+
 // Value-only chain of NS segments: tip rotation Rc and position pc.
-template <int NS, typename T>
+template <int NS, typename T, bool EXT = false>
 CR_HD void fk_tip(const RobotT<T>& rb, const T* z, T* Rc, T* pc) {
+  constexpr int NC = EXT ? 3 : 2;
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? T(1) : T(0);
   pc[0] = pc[1] = pc[2] = T(0);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    T a = z[2 * i], b = z[2 * i + 1];
+    T a = z[NC * i], b = z[NC * i + 1];
     ArcCoef<T> c = arc_coef<T, false>(a * a + b * b);
     T Ri[9], di[3], q[3], Rn[9];
-    seg_R_d(a, b, rb.L[i], c, Ri, di);
+    seg_R_d(a, b, seg_len<EXT>(rb, z, i), c, Ri, di);
     mv3(Rc, di, q);
     pc[0] += q[0];
     pc[1] += q[1];
@@ -443,14 +459,33 @@ CR_HD void bound_residuals(const RobotT<T>& rb, const WeightsT<T>& w, int i, TH 
   *rth = s > thmax * thmax ? (TH)w.sq_curv * (tsqrt(s) - thmax) : TH(0);
 }
 
-template <int NS, typename T>
+// Length hinge of an extensible segment (eq. 9, L_min <= L_i <= L_max):
+// sq_lim max(0, |L_i - mid| - half) with L_i = L[i] + e; *sgn = sign(L_i - mid).
+template <typename TH, typename T>
+CR_HD TH length_residual(const RobotT<T>& rb, const WeightsT<T>& w, int i, TH e, TH* sgn) {
+  const TH L0 = sizeof(TH) == 8 ? (TH)rb.Ld[i] : (TH)rb.L[i];
+  const TH mid = sizeof(TH) == 8 ? (TH)rb.Lmidd[i] : (TH)rb.Lmid[i];
+  const TH half = sizeof(TH) == 8 ? (TH)rb.Lhalfd[i] : (TH)rb.Lhalf[i];
+  const TH off = (L0 + e) - mid;
+  *sgn = off < TH(0) ? TH(-1) : TH(1);
+  const TH viol = fabs(off) - half;
+  return viol > TH(0) ? (TH)w.sq_lim * viol : TH(0);
+}
+
+template <int NS, typename T, bool EXT = false>
 CR_HD T bounds_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* z) {
+  constexpr int NC = EXT ? 3 : 2;
   T c = T(0);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     T ru[3], sg[3], rth;
-    bound_residuals<T>(rb, w, i, z[2 * i], z[2 * i + 1], ru, sg, &rth);
+    bound_residuals<T>(rb, w, i, z[NC * i], z[NC * i + 1], ru, sg, &rth);
     c += T(0.5) * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
+    if constexpr (EXT) {
+      T se;
+      const T rl = length_residual<T>(rb, w, i, z[NC * i + 2], &se);
+      c += T(0.5) * rl * rl;
+    }
   }
   return c;
 }
@@ -460,14 +495,26 @@ __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j
 
 // Adds the bound rows to cost, g = J^T r and H = J^T J (packed lower) for one configuration.
 // `off` is the column offset of this configuration's (a, b) block.
-template <int NS, int NZT, typename T>
+template <int NS, int NZT, typename T, bool EXT = false>
 CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, int off, T* Hp, T* g, T& cost) {
+  constexpr int NC = EXT ? 3 : 2;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const T a = z[2 * i], b = z[2 * i + 1];
+    const T a = z[NC * i], b = z[NC * i + 1];
     T ru[3], sg[3], rth;
     bound_residuals<T>(rb, w, i, a, b, ru, sg, &rth);
-    const int ca = off + 2 * i, cb = off + 2 * i + 1;
+    const int ca = off + NC * i, cb = off + NC * i + 1;
+    if constexpr (EXT) {
+      T se;
+      const T rl = length_residual<T>(rb, w, i, z[NC * i + 2], &se);
+      if (rl > T(0)) {
+        const int ce = off + NC * i + 2;
+        const T je = se * w.sq_lim;
+        cost += T(0.5) * rl * rl;
+        g[ce] += je * rl;
+        Hp[tri(ce, ce)] += je * je;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (ru[j] > T(0)) {
@@ -501,16 +548,16 @@ CR_HD void bounds_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* 
 // ---------------------------------------------------------------------------
 
 // Pose part: returns 1/2 |(w_pos rho, w_rot w)|^2; optionally the unweighted |log|.
-template <int NS, typename T>
+template <int NS, typename T, bool EXT = false>
 CR_HD T ik_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z,
                                      T* e_out) {
   T Rc[9], pc[3], Re[9], te[3], om[3], rho[3], gam, dg;
-  fk_tip<NS>(rb, z, Rc, pc);
+  fk_tip<NS, T, EXT>(rb, z, Rc, pc);
   relative_pose(Rc, pc, Tt, Re, te);
   log_se3<T, false>(Re, te, om, rho, &gam, &dg);
   T r2 = w.w_pos * w.w_pos * dot3(rho, rho) + w.w_rot * w.w_rot * dot3(om, om);
   if (e_out) *e_out = tsqrt(dot3(rho, rho) + dot3(om, om));
-  return T(0.5) * r2 + bounds_cost<NS>(rb, w, z);
+  return T(0.5) * r2 + bounds_cost<NS, T, EXT>(rb, w, z);
 }
 
 // Normal equations H = J^T J (packed lower, 2NS x 2NS), g = J^T r and cost at z.
@@ -766,12 +813,13 @@ CR_HD void seg_point(const TC* Rc, const TC* pc, TC a, TC b, TC L, TC s, TC sg, 
   out[2] = (T)(pc[2] + x[2]);
 }
 
-template <int NS, typename T>
+template <int NS, typename T, bool EXT = false>
 struct Fwd {
-  T W[2 * NS][3], Pd[2 * NS][3], pe[NS][3];  // twist columns and segment ends
-  T R[9], p[3];                              // tip frame
-  T F[NS][3], Mo[NS][3];                     // force and moment about the origin from points of segment i
-  T gz[2 * NS];                              // direct gradient terms (own arc, bounds)
+  static constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
+  T W[NZ][3], Pd[NZ][3], pe[NS][3];  // twist columns and segment ends
+  T R[9], p[3];                      // tip frame
+  T F[NS][3], Mo[NS][3];             // force and moment about the origin from points of segment i
+  T gz[NZ];                          // direct gradient terms (own arc, bounds)
 };
 
 // Sphere m, component c (cx, cy, cz, radius) is read as sph[m * ms + c * cs].
@@ -782,9 +830,10 @@ struct Fwd {
 // backbone-to-centre distances, and FP32 positions would set its error.  The pair
 // rejection test stays in T (with a relative slack); active pairs are re-measured
 // in TC.
-template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T>
+template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T, bool EXT = false>
 CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
-                       int64_t cs, Fwd<NS, T>& f, const double* zd = nullptr) {
+                       int64_t cs, Fwd<NS, T, EXT>& f, const double* zd = nullptr) {
+  constexpr int NC = EXT ? 3 : 2;
   T cost = T(0);
   TC Rc[9], pc[3];
 #pragma unroll
@@ -792,15 +841,16 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
   pc[0] = pc[1] = pc[2] = TC(0);
   if (GRAD) {
 #pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) f.gz[k] = T(0);
+    for (int k = 0; k < NC * NS; ++k) f.gz[k] = T(0);
   }
   const int K = rb.K;
   const T slack = sizeof(T) < sizeof(TC) ? T(1.0001) : T(1);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const T a = z[2 * i], b = z[2 * i + 1];
-    const TC ac = zd ? (TC)zd[2 * i] : (TC)a, bc = zd ? (TC)zd[2 * i + 1] : (TC)b;
-    const TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    const T a = z[NC * i], b = z[NC * i + 1];
+    const TC ac = zd ? (TC)zd[NC * i] : (TC)a, bc = zd ? (TC)zd[NC * i + 1] : (TC)b;
+    TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    if constexpr (EXT) Lc += zd ? (TC)zd[NC * i + 2] : (TC)z[NC * i + 2];
     const TC s = ac * ac + bc * bc;
     if (GRAD) {
 #pragma unroll
@@ -817,7 +867,8 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
       const T rf = (T)(ri + marg);
       T xmf[3];
       seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
-      const T half = T(0.5) * rb.L[i];
+      const T Lf = (T)Lc;
+      const T half = T(0.5) * Lf;
       for (int m = 0; m < M; ++m) {
         const TS* sp = sph + m * ms;
         const T sm[4] = {(T)sp[0], (T)sp[cs], (T)sp[2 * cs], (T)sp[3 * cs]};
@@ -837,7 +888,7 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
             T xr[3];
             seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
             const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[1], e2 = xr[2] - sm[2];
-            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * Lf) * T(1.0001);
             if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
           for (int k = k0; k <= k1; ++k) {
@@ -875,8 +926,13 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
               mtv3(Rc, fx, q);
               const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
               const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
-              f.gz[2 * i] += (T)(sg * dot3(q, dda));
-              f.gz[2 * i + 1] += (T)(sg * dot3(q, ddb));
+              f.gz[NC * i] += (T)(sg * dot3(q, dda));
+              f.gz[NC * i + 1] += (T)(sg * dot3(q, ddb));
+              if constexpr (EXT) {
+                // the point moves with the length: dx/de = Rc sg (A sa, A sb, B)
+                const TC dde[3] = {sg * ck.A * sa, sg * ck.A * sb, sg * ck.B};
+                f.gz[NC * i + 2] += (T)dot3(q, dde);
+              }
             }
           }
         }
@@ -893,16 +949,26 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
       TC t0[3];
       mv3(Rc, wa, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) f.W[2 * i][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) f.W[NC * i][q] = (T)t0[q];
       mv3(Rc, wb, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) f.W[2 * i + 1][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) f.W[NC * i + 1][q] = (T)t0[q];
       mv3(Rc, dda, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) f.Pd[2 * i][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) f.Pd[NC * i][q] = (T)t0[q];
       mv3(Rc, ddb, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) f.Pd[2 * i + 1][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) f.Pd[NC * i + 1][q] = (T)t0[q];
+      if constexpr (EXT) {
+        // the extension moves the segment's end along d_i / L_i and does not rotate it
+        const TC dde[3] = {c.A * ac, c.A * bc, c.B};
+        mv3(Rc, dde, t0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          f.W[NC * i + 2][q] = T(0);
+          f.Pd[NC * i + 2][q] = (T)t0[q];
+        }
+      }
     }
     TC q[3], Rn[9];
     mv3(Rc, di, q);
@@ -920,7 +986,7 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
     // bounds (eq. 9): tendon hinges and bending hinge, violations formed in FP64
     {
       double ru[3], sg[3], rth;
-      const double ad = zd ? zd[2 * i] : (double)a, bd = zd ? zd[2 * i + 1] : (double)b;
+      const double ad = zd ? zd[NC * i] : (double)a, bd = zd ? zd[NC * i + 1] : (double)b;
       bound_residuals<double>(rb, w, i, ad, bd, ru, sg, &rth);
       double cb = 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
       cost += (T)cb;
@@ -940,8 +1006,15 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
           ga += (double)w.sq_curv * ad / th * rth;
           gb += (double)w.sq_curv * bd / th * rth;
         }
-        f.gz[2 * i] += (T)ga;
-        f.gz[2 * i + 1] += (T)gb;
+        f.gz[NC * i] += (T)ga;
+        f.gz[NC * i + 1] += (T)gb;
+      }
+      if constexpr (EXT) {
+        double se;
+        const double ed = zd ? zd[NC * i + 2] : (double)z[NC * i + 2];
+        const double rl = length_residual<double>(rb, w, i, ed, &se);
+        cost += (T)(0.5 * rl * rl);
+        if (GRAD && rl > 0.0) f.gz[NC * i + 2] += (T)(se * (double)w.sq_lim * rl);
       }
     }
   }
@@ -1003,8 +1076,9 @@ CR_HD T pose_term(const WeightsT<T>& w, const T* R, const T* p, const T* Tt, T* 
 
 // Reverse sweep: gz += contributions of the tip wrench (f_tip, tau_tip) and of
 // the per-segment point forces recorded in the forward pass.
-template <int NS, typename T>
-CR_HD void config_reverse(const Fwd<NS, T>& f, const T* f_tip, const T* tau_tip, T* gz) {
+template <int NS, typename T, bool EXT = false>
+CR_HD void config_reverse(const Fwd<NS, T, EXT>& f, const T* f_tip, const T* tau_tip, T* gz) {
+  constexpr int NC = EXT ? 3 : 2;
   T Fd[3] = {f_tip[0], f_tip[1], f_tip[2]};
   T Md[3];
   cross3(f.p, f_tip, Md);
@@ -1018,8 +1092,9 @@ CR_HD void config_reverse(const Fwd<NS, T>& f, const T* f_tip, const T* tau_tip,
     mom[0] = Md[0] - pf[0];
     mom[1] = Md[1] - pf[1];
     mom[2] = Md[2] - pf[2];
-    gz[2 * j] = f.gz[2 * j] + dot3(f.W[2 * j], mom) + dot3(f.Pd[2 * j], Fd);
-    gz[2 * j + 1] = f.gz[2 * j + 1] + dot3(f.W[2 * j + 1], mom) + dot3(f.Pd[2 * j + 1], Fd);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      gz[NC * j + c] = f.gz[NC * j + c] + dot3(f.W[NC * j + c], mom) + dot3(f.Pd[NC * j + c], Fd);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       Fd[c] += f.F[j][c];
@@ -1110,10 +1185,10 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
 // tip position and its Jacobian.  Pose rows against Tt only if pose.  TC is the
 // chain type (FP64 when spheres are present, as in config_forward).
-template <int NS, typename T, typename TC, typename TS = T>
+template <int NS, typename T, typename TC, typename TS = T, bool EXT = false>
 CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
-                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[2 * NS], bool pose = true) {
-  constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[(EXT ? 3 : 2) * NS], bool pose = true) {
+  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS, NP = NZ * (NZ + 1) / 2;
 #pragma unroll
   for (int k = 0; k < NP; ++k) Hp[k] = T(0);
 #pragma unroll
@@ -1128,8 +1203,9 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   const T slack = sizeof(T) < sizeof(TC) ? T(1.0001) : T(1);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const TC ac = (TC)z[2 * i], bc = (TC)z[2 * i + 1];
-    const TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    const TC ac = (TC)z[NC * i], bc = (TC)z[NC * i + 1];
+    TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
+    if constexpr (EXT) Lc += (TC)z[NC * i + 2];
     const TC s = ac * ac + bc * bc;
     if (M > 0) {
       // clearance rows, with the segment-level sphere culling of config_forward
@@ -1138,7 +1214,8 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
       const T rf = (T)(ri + marg);
       T xmf[3];
       seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xmf);
-      const T half = T(0.5) * rb.L[i];
+      const T Lf = (T)Lc;
+      const T half = T(0.5) * Lf;
       for (int m = 0; m < M; ++m) {
         const TS* sp = sph + m * ms;
         const T sm[4] = {(T)sp[0], (T)sp[cs], (T)sp[2 * cs], (T)sp[3 * cs]};
@@ -1158,7 +1235,7 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
             T xr[3];
             seg_point(Rc, pc, ac, bc, Lc, s, TC(k0 + k1) * TC(0.5) / TC(K), xr);
             const T e0 = xr[0] - sm[0], e1 = xr[1] - sm[1], e2 = xr[2] - sm[2];
-            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * rb.L[i]) * T(1.0001);
+            const T rr = (sm[3] + rf + T(k1 - k0) * T(0.5) / T(K) * Lf) * T(1.0001);
             if (!(e0 * e0 + e1 * e1 + e2 * e2 < rr * rr)) continue;
           }
           for (int k = k0; k <= k1; ++k) {
@@ -1200,8 +1277,9 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
               if (j < i) {
                 T xm[3] = {xf[0] - pe[j][0], xf[1] - pe[j][1], xf[2] - pe[j][2]}, c3[3];
                 cross3(xm, nvec, c3);
-                row[2 * j] = -w.sq_coll * (dot3(W[2 * j], c3) + dot3(Pd[2 * j], nvec));
-                row[2 * j + 1] = -w.sq_coll * (dot3(W[2 * j + 1], c3) + dot3(Pd[2 * j + 1], nvec));
+  #pragma unroll
+                for (int c = 0; c < NC; ++c)
+                  row[NC * j + c] = -w.sq_coll * (dot3(W[NC * j + c], c3) + dot3(Pd[NC * j + c], nvec));
               }
             }
             {
@@ -1209,13 +1287,17 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
               mtv3(Rc, nq, q);
               const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
               const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
-              row[2 * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
-              row[2 * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
+              row[NC * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
+              row[NC * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
+              if constexpr (EXT) {
+                const TC dde[3] = {sg * ck.A * sa, sg * ck.A * sb, sg * ck.B};
+                row[NC * i + 2] = (T)(-(TC)w.sq_coll * dot3(q, dde));
+              }
             }
             cost += T(0.5) * rr * rr;
   #pragma unroll
             for (int k1 = 0; k1 < NZ; ++k1) {
-              if (k1 <= 2 * i + 1) {
+              if (k1 <= NC * i + NC - 1) {
                 g[k1] += row[k1] * rr;
   #pragma unroll
                 for (int k2 = 0; k2 <= k1; ++k2) Hp[tri(k1, k2)] += row[k1] * row[k2];
@@ -1236,16 +1318,25 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
       TC t0[3];
       mv3(Rc, wa, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) W[2 * i][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) W[NC * i][q] = (T)t0[q];
       mv3(Rc, wb, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) W[2 * i + 1][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) W[NC * i + 1][q] = (T)t0[q];
       mv3(Rc, dda, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Pd[2 * i][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) Pd[NC * i][q] = (T)t0[q];
       mv3(Rc, ddb, t0);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) Pd[2 * i + 1][q] = (T)t0[q];
+      for (int q = 0; q < 3; ++q) Pd[NC * i + 1][q] = (T)t0[q];
+      if constexpr (EXT) {
+        const TC dde[3] = {c.A * ac, c.A * bc, c.B};
+        mv3(Rc, dde, t0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          W[NC * i + 2][q] = T(0);
+          Pd[NC * i + 2][q] = (T)t0[q];
+        }
+      }
     }
     TC q[3], Rn[9];
     mv3(Rc, di, q);
@@ -1269,7 +1360,7 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   T dp[NZ][3];
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
-    const int j = k / 2;
+    const int j = k / NC;
     T rel[3] = {pt[0] - pe[j][0], pt[1] - pe[j][1], pt[2] - pe[j][2]}, c3[3];
     cross3(W[k], rel, c3);
 #pragma unroll
@@ -1282,32 +1373,32 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   ptip[1] = pt[1];
   ptip[2] = pt[2];
   if (pose) cost += pose_rows<NZ>(w, Rt, pt, W, dp, Tt, Hp, g);
-  bounds_normal_eq<NS, NZ>(rb, w, z, 0, Hp, g, cost);
+  bounds_normal_eq<NS, NZ, T, EXT>(rb, w, z, 0, Hp, g, cost);
   return cost;
 }
 
 // Penalised cost of one configuration against a target pose (eq. 8-10, 17):
 // pose, bounds and clearance against M spheres (sphere m, component c at
 // sph[m * ms + c * cs], stored as TS).
-template <int NS, typename T, typename TS>
+template <int NS, typename T, typename TS, bool EXT = false>
 CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z, const TS* sph, int M, int64_t ms,
                  int64_t cs) {
-  Fwd<NS, T> f;
-  T c = config_forward<NS, T, false, T, TS>(rb, w, z, sph, M, ms, cs, f);
+  Fwd<NS, T, EXT> f;
+  T c = config_forward<NS, T, false, T, TS, EXT>(rb, w, z, sph, M, ms, cs, f);
   T ft[3], tq[3];
   return c + pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
 }
 
 // lm_ik with clearance rows: the same iteration, the generic per-configuration
 // normal equations and cost.
-template <int NS, typename T, typename TS>
+template <int NS, typename T, typename TS, bool EXT = false>
 CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
                   bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs) {
-  constexpr int NZ = 2 * NS;
+  constexpr int NZ = (EXT ? 3 : 2) * NS;
   constexpr int NP = NZ * (NZ + 1) / 2;
   for (int it = 0; it < iters; ++it) {
     T Hp[NP], g[NZ], dl[NZ], ptip[3], Jp[3][NZ];
-    const T c0 = local_normal_eq<NS, T, T, TS>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
+    const T c0 = local_normal_eq<NS, T, T, TS, EXT>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
     if (!tfinite(c0)) {
       failed = true;
       break;
@@ -1332,7 +1423,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
     for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
       for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
-      const T c = cfg_cost<NS, T, TS>(rb, w, Tt, zt, sph, M, ms, cs);
+      const T c = cfg_cost<NS, T, TS, EXT>(rb, w, Tt, zt, sph, M, ms, cs);
       ++trials;
       if (c <= c0 + T(1e-4) * alpha * gd) {
         acc = tr;
@@ -1355,8 +1446,9 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
 // its segment's radius (clearance < 0, margin 0); spheres are FP64, sphere m
 // component c at sph[c * ld + m].  A sphere whose distance to a segment's arc
 // midpoint exceeds L_i / 2 + R + r_i cannot touch the segment.
-template <int NS, typename T>
+template <int NS, typename T, bool EXT = false>
 CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M, int64_t ld) {
+  constexpr int NC = EXT ? 3 : 2;
   T Rp[9], pp[3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? T(1) : T(0);
@@ -1364,8 +1456,8 @@ CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M,
   bool hit = false;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const T a = z[2 * i], b = z[2 * i + 1], s = a * a + b * b;
-    const T Li = rb.L[i], ri = rb.r[i];
+    const T a = z[NC * i], b = z[NC * i + 1], s = a * a + b * b;
+    const T Li = seg_len<EXT>(rb, z, i), ri = rb.r[i];
     T xm[3];
     seg_point(Rp, pp, a, b, Li, s, T(0.5), xm);
     for (int m = 0; m < M && !hit; ++m) {

@@ -38,22 +38,25 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     T a, bb;
-    u_to_ab(u[(3 * i) * ld + b], u[(3 * i + 1) * ld + b], u[(3 * i + 2) * ld + b], rb.r[i], &a, &bb);
+    const T u0 = u[(3 * i) * ld + b], u1 = u[(3 * i + 1) * ld + b], u2 = u[(3 * i + 2) * ld + b];
+    u_to_ab(u0, u1, u2, rb.r[i], &a, &bb);
+    // extensible segments: the common mode of the three tendons is the change of length
+    const T Li = rb.ext ? rb.L[i] + (u0 + u1 + u2) * T(1.0 / 3.0) : rb.L[i];
     T s = a * a + bb * bb;
     if (arc) {
       T th = tsqrt(s);
       T ph = th > T(0) ? tatan2(bb, a) : T(0);
       if (ph < T(0)) ph += T(6.28318530717958647692);
-      arc[(3 * i) * ld + b] = th / rb.L[i];
+      arc[(3 * i) * ld + b] = th / Li;
       arc[(3 * i + 1) * ld + b] = ph;
-      arc[(3 * i + 2) * ld + b] = rb.L[i];
+      arc[(3 * i + 2) * ld + b] = Li;
     }
     if (pts) {
       for (int k = 1; k <= K; ++k) {
         T sg = T(k) / T(K);
         ArcCoef<T> ck = arc_coef<T, false>(sg * sg * s);
         T Rk[9], dk[3], q[3];
-        seg_R_d(sg * a, sg * bb, sg * rb.L[i], ck, Rk, dk);
+        seg_R_d(sg * a, sg * bb, sg * Li, ck, Rk, dk);
         mv3(Rc, dk, q);
         const int64_t c0 = 3 * (i * K + k - 1);
         pts[c0 * ld + b] = pc[0] + q[0];
@@ -63,7 +66,7 @@ __global__ void __launch_bounds__(256)
     }
     ArcCoef<T> c = arc_coef<T, false>(s);
     T Ri[9], di[3], q[3], Rn[9];
-    seg_R_d(a, bb, rb.L[i], c, Ri, di);
+    seg_R_d(a, bb, Li, c, Ri, di);
     mv3(Rc, di, q);
     pc[0] += q[0];
     pc[1] += q[1];

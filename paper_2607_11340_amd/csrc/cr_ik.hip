@@ -64,37 +64,41 @@ struct SphArgs {
 
 // Stage 1 with clearance rows (eq. 10): one lane per seed as k_ik_stage1, the
 // generic per-configuration normal equations; spheres read from HBM (every lane
-// of a wave reads the same sphere: one broadcast load).
-template <int NS, typename T>
+// of a wave reads the same sphere: one broadcast load).  Also the stage 1 of
+// extensible robots (EXT: three coordinates a, b, e per segment), with or
+// without spheres (sa.M may be 0).
+template <int NS, typename T, bool EXT = false>
 __global__ void __launch_bounds__(256)
     k_ik_stage1_sph(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
                     const double* __restrict__ useed, int iters, T lam0, SphArgs sa, T* __restrict__ z_out,
                     T* __restrict__ e_out, T* __restrict__ pen_out, T* __restrict__ cost_out,
                     int32_t* __restrict__ failed_out, int32_t* __restrict__ trials_out) {
-  constexpr int NZ = 2 * NS;
+  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
   const int64_t B = P * (int64_t)S;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int64_t p = b / S;
-  const double* sp = sa.sph + (sa.per_problem ? p * sa.M : 0);
+  const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
   T tt[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) tt[c] = (T)Tt[c * P + p];
   T z[NZ];
 #pragma unroll
-  for (int i = 0; i < NS; ++i)
-    u_to_ab((T)useed[(3 * i) * B + b], (T)useed[(3 * i + 1) * B + b], (T)useed[(3 * i + 2) * B + b], rb.r[i],
-            &z[2 * i], &z[2 * i + 1]);
+  for (int i = 0; i < NS; ++i) {
+    const T u0 = (T)useed[(3 * i) * B + b], u1 = (T)useed[(3 * i + 1) * B + b], u2 = (T)useed[(3 * i + 2) * B + b];
+    u_to_ab(u0, u1, u2, rb.r[i], &z[NC * i], &z[NC * i + 1]);
+    if constexpr (EXT) z[NC * i + 2] = (u0 + u1 + u2) * T(1.0 / 3.0);
+  }
   T lam = lam0;
   bool failed = false;
   int trials = 0;
-  lm_cfg<NS, T, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+  lm_cfg<NS, T, double, EXT>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
   T e;
-  ik_cost<NS>(rb, w, tt, z, &e);
-  const T c = cfg_cost<NS, T, double>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+  ik_cost<NS, T, EXT>(rb, w, tt, z, &e);
+  const T c = cfg_cost<NS, T, double, EXT>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
   WeightsT<T> wc = w;  // clearance part alone (SelectTop tie-break)
   wc.w_pos = wc.w_rot = wc.sq_lim = wc.sq_curv = T(0);
-  const T pen = cfg_cost<NS, T, double>(rb, wc, tt, z, sp, sa.M, 1, sa.ld);
+  const T pen = sa.M > 0 ? cfg_cost<NS, T, double, EXT>(rb, wc, tt, z, sp, sa.M, 1, sa.ld) : T(0);
   if (!tfinite(c) || !tfinite(e)) failed = true;
 #pragma unroll
   for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
@@ -326,13 +330,13 @@ __global__ void __launch_bounds__(256)
 // Stage 2: FP64 refinement of the kept candidates, lambda restarted at lambda0.
 // ---------------------------------------------------------------------------
 
-template <int NS, typename T1, bool SPH>
+template <int NS, typename T1, bool SPH, bool EXT = false>
 __global__ void __launch_bounds__(256)
     k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
                 const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
                 int iters, double lam0, SphArgs sa, double* __restrict__ z2, double* __restrict__ cost2,
                 int32_t* __restrict__ failed2) {
-  constexpr int NZ = 2 * NS;
+  constexpr int NZ = (EXT ? 3 : 2) * NS;
   const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B2) return;
@@ -356,10 +360,10 @@ __global__ void __launch_bounds__(256)
   bool failed = false;
   int trials = 0;
   double c;
-  if (SPH) {
-    const double* sp = sa.sph + (sa.per_problem ? p * sa.M : 0);
-    lm_cfg<NS, double, double>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
-    c = cfg_cost<NS, double, double>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+  if (SPH || EXT) {
+    const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
+    lm_cfg<NS, double, double, EXT>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+    c = cfg_cost<NS, double, double, EXT>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
   } else {
     lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
     c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
@@ -378,13 +382,13 @@ __global__ void __launch_bounds__(256)
 // or all S stage-1 seeds (seed index k).
 // ---------------------------------------------------------------------------
 
-template <int NS, typename TC>
+template <int NS, typename TC, bool EXT = false>
 __global__ void __launch_bounds__(256)
     k_ik_finalize(RobotT<double> rb, int64_t P, int nc, const int32_t* __restrict__ sel,
                   const TC* __restrict__ zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
                   const double* __restrict__ Tt, SphArgs sa, double* __restrict__ u_out, double* __restrict__ err_out,
                   int32_t* __restrict__ status_out) {
-  constexpr int NZ = 2 * NS;
+  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   const int64_t Bc = P * (int64_t)nc;
@@ -416,7 +420,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int c = 0; c < 12; ++c) tt[c] = Tt[c * P + p];
   double Rc[9], pc[3];
-  fk_tip<NS>(rb, z, Rc, pc);
+  fk_tip<NS, double, EXT>(rb, z, Rc, pc);
   double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
   double pos = sqrt(dot3(dp, dp));
   double Re[9], te[3];
@@ -427,17 +431,23 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     double u[3];
-    ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], u);
+    ab_to_u(z[NC * i], z[NC * i + 1], rb.r[i], u);
+    // extensible: the output carries the extension as the common mode; the tendon
+    // bound applies to the bending part, the length to its interval
+    const double e = EXT ? z[NC * i + 2] : 0.0;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      u_out[(3 * i + j) * P + p] = u[j];
+      u_out[(3 * i + j) * P + p] = u[j] + e;
       viol = fmax(viol, fabs(u[j]) - rb.umax[i]);
     }
-    thx = fmax(thx, sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]) - rb.theta_max);
+    if (EXT) viol = fmax(viol, fabs((rb.Ld[i] + e) - rb.Lmidd[i]) - rb.Lhalfd[i]);
+    thx = fmax(thx, sqrt(z[NC * i] * z[NC * i] + z[NC * i + 1] * z[NC * i + 1]) - rb.theta_max);
   }
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if (sa.M > 0 && penetrates<NS, double>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld)) st |= CR_COLLISION;
+  if (sa.M > 0 &&
+      penetrates<NS, double, EXT>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld))
+    st |= CR_COLLISION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
   if (st == 0) st = CR_SOLVED;
   err_out[p] = pos;
@@ -645,7 +655,7 @@ size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_op
                            char* base, IkWorkspace* ws) {
   const size_t t1 = dtype == CR_F64 ? 8 : 4;
   const int64_t B = P * (int64_t)S;
-  const int nz = 2 * rb.n_seg;
+  const int nz = (rb.extensible ? 3 : 2) * rb.n_seg;
   const int nf = o.n_final > 0 ? o.n_final : 0;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -670,12 +680,66 @@ size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_op
 
 static int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Algorithm 1 for robots with extensible segments: three coordinates per segment
+// (bending a, b and extension e); every stage runs the generic per-configuration
+// path (clearance rows when spheres are given).
+template <int NS, typename T>
+static cr_status run_ik_ext(const cr_robot& rb0, const SphArgs& sa, int64_t P, const double* Tt, int32_t S,
+                            const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out,
+                            double* err_out, int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
+  RobotT<T> rb = robot_to<T>(rb0);
+  WeightsT<T> w = weights_to<T>(w0);
+  LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
+  const int64_t B = P * (int64_t)S;
+  const bool timed = timer_on();
+  if (timed) timer_begin_call(st);
+  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, true>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
+                     Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
+                     ws.failed1, ws.trials1);
+  cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_sph");
+  if (rc != CR_OK) return rc;
+  if (timed) timer_mark(0, st);
+  RobotT<double> rbd = robot_to<double>(rb0);
+  if (o.n_final > 0) {
+    rc = launch_select(P, S, 3 * NS, ws.z1, ws.e1, ws.pen1, ws.failed1, o.n_final, o.dup_eps, ws.sel,
+                       sizeof(T) == 8 ? CR_F64 : CR_F32, st);
+    if (rc != CR_OK) return rc;
+    if (timed) timer_mark(1, st);
+    WeightsT<double> wd = weights_to<double>(w0);
+    LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
+    const int64_t B2 = P * (int64_t)o.n_final;
+    hipLaunchKernelGGL((k_ik_stage2<NS, T, true, true>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
+                       (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, ws.cost2,
+                       ws.failed2);
+    rc = check_hip(hipGetLastError(), "k_ik_stage2");
+    if (rc != CR_OK) return rc;
+    if (timed) timer_mark(2, st);
+    hipLaunchKernelGGL((k_ik_finalize<NS, double, true>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
+                       (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, sa, u_out, err_out, status_out);
+  } else {
+    if (timed) {
+      timer_mark(1, st);
+      timer_mark(2, st);
+    }
+    hipLaunchKernelGGL((k_ik_finalize<NS, T, true>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
+                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, sa, u_out,
+                       err_out, status_out);
+  }
+  rc = check_hip(hipGetLastError(), "k_ik_finalize");
+  if (timed) {
+    timer_mark(3, st);
+    timer_end_call();
+  }
+  return rc;
+}
+
 template <int NS, typename T>
 static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, const double* Tt, int32_t S,
                         const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
                         int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
   const SphArgs sa{sp ? (const double*)sp->sph : nullptr, sp ? sp->ld : 0, sp ? sp->n_sph : 0,
                    sp ? sp->per_problem : 0};
+  if (rb0.extensible) return run_ik_ext<NS, T>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
   RobotT<T> rb = robot_to<T>(rb0);
   WeightsT<T> w = weights_to<T>(w0);
   LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};

@@ -39,7 +39,33 @@ WORKLOADS = {
     "traj_5seg": dict(
         kind="traj", L=[0.06] * 5, r=[0.006] * 5, b=0.006, P=256, H=31, S=64, M=64,
         k_init=80, k_final=20, n_final=4, K=64, dtype="f32", seed=BASE_SEED + 4),
+    # extendable robot among obstacles (Sec. V-B, the extendable row of Table II):
+    # segment lengths free within [0.5, 1.5] of nominal, a 3 x 3 x 3 lattice of
+    # spheres (radius 0.2 of a segment length, the paper's ratio) with seeded
+    # jitter, targets kept only if their configuration clears the lattice
+    "ik_ext_4seg": dict(
+        kind="ik", L=[0.08] * 4, r=[0.008] * 4, b=0.006, L_min=[0.04] * 4, L_max=[0.12] * 4, P=1024, S=128,
+        k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 6,
+        lattice=dict(xy=(-0.15, 0.0, 0.15), z=(0.10, 0.22, 0.34), radius=0.016, jitter=0.01)),
 }
+
+
+def extended_actuation(rng: np.random.Generator, n: int, b, e_lo, e_hi, count: int) -> np.ndarray:
+    """`count` actuations [count, n, 3] of extensible segments: a uniform zero-sum
+    bending part (as uniform_actuation) plus a common mode U[e_lo, e_hi] per segment
+    (the change of the segment's length)."""
+    e_lo = np.broadcast_to(np.asarray(e_lo, dtype=np.float64), (n,))
+    e_hi = np.broadcast_to(np.asarray(e_hi, dtype=np.float64), (n,))
+    bend = uniform_actuation(rng, n, b, count)
+    return bend + rng.uniform(e_lo, e_hi, size=(count, n))[:, :, None]
+
+
+def sphere_lattice(rng: np.random.Generator, xy, z, radius: float, jitter: float) -> np.ndarray:
+    """A len(xy) x len(xy) x len(z) lattice of spheres [N, 4], each centre moved by
+    U[-jitter, jitter] per axis."""
+    c = np.array([[x, y, zz] for x in xy for y in xy for zz in z], dtype=np.float64)
+    c = c + rng.uniform(-jitter, jitter, size=c.shape)
+    return np.concatenate([c, np.full((len(c), 1), radius)], axis=1)
 
 
 # Uneven batch: problem mix and ranges (robot geometry of path_4seg per segment;

@@ -1,0 +1,185 @@
+"""Extensible segments on the GPU (the extendable robots of Sec. V-B; segment
+lengths are decision variables within the bounds of eq. 9) against the CPU
+oracle: forward kinematics (FP64 1e-9, FP32 1e-5 normwise), cost and adjoint
+gradient with every hinge active, with and without spheres (FP64 1e-9, FP32
+1e-5), FP64 LM iterates (1e-9), the FP64 two-stage solve (Algorithm 1, short
+budgets: answers, status and errors equal the oracle's) and the FP32 two-stage
+solve's quality on a 4-segment extendable robot among spheres."""
+import numpy as np
+import pytest
+
+from helpers import aos, normwise_rel, soa
+from paper_2607_11340_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GEOM = dict(L=[0.08, 0.07, 0.06, 0.05], r=[0.008, 0.007, 0.006, 0.005], b=0.006,
+            L_min=[0.04, 0.035, 0.03, 0.025], L_max=[0.12, 0.105, 0.09, 0.075])
+
+
+@pytest.fixture(scope="module")
+def cr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_11340_amd import crsolver
+    return crsolver
+
+
+def _robots(oracle, cr, n, K=6, **over):
+    g = {**GEOM, **over}
+    kw = dict(L=g["L"][:n], r=g["r"][:n], u_max=[g["b"]] * n, pts_per_seg=K, L_min=g["L_min"][:n],
+              L_max=g["L_max"][:n], theta_max=over.get("theta_max", np.pi))
+    return oracle.Robot(**kw), cr.Robot(**kw)
+
+
+def ext_actuation(rng, n, b, count, e_lo=-0.02, e_hi=0.02):
+    """Uniform bending actuations plus a common mode (the extension) per segment."""
+    return I.uniform_actuation(rng, n, b, count) + rng.uniform(e_lo, e_hi, size=(count, n, 1))
+
+
+@pytest.mark.parametrize("n", [1, 3, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ext_fk_parity(oracle, cr, n, dtype):
+    print(f"extensible fk n={n} {dtype}", flush=True)
+    rng = np.random.default_rng(800 + n)
+    ro, rg = _robots(oracle, cr, n, K=5)
+    u = ext_actuation(rng, n, GEOM["b"], 555)
+    arc_o, fr_o, pts_o = oracle.fk(ro, u, points=True)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    out = cr.fk(rg, torch.tensor(soa(u, 2), dtype=td, device="cuda"), points=True)
+    fr = aos(out["frames"].double().cpu().numpy(), (n, 3, 4))
+    pts = aos(out["pts"].double().cpu().numpy(), (n, 5, 3))
+    arc = aos(out["arc"].double().cpu().numpy(), (n, 3))
+    tol = 1e-9 if dtype == "f64" else 1e-5
+    assert normwise_rel(fr, fr_o) < tol and normwise_rel(pts, pts_o) < tol
+    assert normwise_rel(arc[..., 2], arc_o[..., 2]) < tol   # segment lengths L + e
+    assert normwise_rel(arc[..., 0], arc_o[..., 0]) < tol   # curvatures theta / (L + e)
+
+
+def _cost_case(oracle, cr, seed, M):
+    rng = np.random.default_rng(seed)
+    n, P, S, K = 3, 23, 9, 6
+    ro, rg = _robots(oracle, cr, n, K=K, theta_max=0.6, b=0.004, L_max=[0.085, 0.075, 0.064, 0.05])
+    ut = ext_actuation(rng, n, 0.004, P, -0.005, 0.005)
+    _, fr = oracle.fk(ro, ut)
+    u = ext_actuation(rng, n, 0.006, P * S, -0.01, 0.02).reshape(P, S, n, 3)
+    sph = np.zeros((P, max(M, 1), 4))
+    for p in range(P):
+        _, _, pts = oracle.fk(ro, u[p, 0], points=True)
+        for m in range(M):
+            i, k = rng.integers(0, n), rng.integers(0, K)
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            rad = rng.uniform(0.004, 0.01)
+            sph[p, m, :3] = pts[i, k] + d * (rad + ro.r[i] + rng.uniform(-2e-3, 1e-3))
+            sph[p, m, 3] = rad
+    return ro, rg, fr[:, -1], u, sph
+
+
+@pytest.mark.parametrize("M", [0, 5])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ext_cost_grad_parity(oracle, cr, M, dtype):
+    print(f"extensible cost_grad M={M} {dtype}", flush=True)
+    ro, rg, T, u, sph = _cost_case(oracle, cr, 810 + M, M)
+    P, S, n = u.shape[:3]
+    if dtype == "f32":
+        u, T, sph = (x.astype(np.float32).astype(np.float64) for x in (u, T, sph))
+    W = oracle.Weights()
+    co = np.zeros((P, S))
+    go = np.zeros_like(u)
+    for p in range(P):
+        pb = oracle.Problem("ik", T[p], spheres=sph[p, :M] if M else None)
+        for s in range(S):
+            co[p, s], go[p, s] = oracle.cost(ro, W, pb, u[p, s], grad=True)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    sp = (torch.tensor(np.ascontiguousarray(sph[:, :max(M, 1)].reshape(-1, 4).T), device="cuda", dtype=td), True, M) \
+        if M else None
+    pbg = cr.CostProblem(rg, "ik", P, S, 0, torch.tensor(soa(T, 2), device="cuda", dtype=td), cr.Weights(), sp)
+    cost, g = cr.cost_grad(pbg, torch.tensor(soa(u[:, :, None], 2), device="cuda", dtype=td))
+    torch.cuda.synchronize()
+    cg = cost.double().cpu().numpy().reshape(P, S)
+    gg = aos(g.double().cpu().numpy(), (n, 3)).reshape(P, S, n, 3)
+    tol = 1e-9 if dtype == "f64" else 1e-5
+    assert co.min() > 0
+    assert (np.abs(cg - co) / co).max() < tol
+    worst = max(normwise_rel(gg[p, s], go[p, s]) for p in range(P) for s in range(S))
+    print(f"  max per-seed grad rel {worst:.2e}", flush=True)
+    assert worst < tol
+    # the gradient is not blind to the common mode any more
+    assert np.abs(go.sum(axis=3)).max() > 1e-6 * np.abs(go).max()
+
+
+def _ik(cr, rg, T, seeds, opts, dtype, sph=None):
+    P = T.shape[0]
+    sp = None
+    if sph is not None:
+        M = sph.shape[1]
+        sp = (torch.tensor(np.ascontiguousarray(sph.reshape(P * M, 4).T), device="cuda"), True, M)
+    u, err, st = cr.solve_ik(rg, torch.tensor(soa(T, 2), device="cuda"), torch.tensor(soa(seeds, 2), device="cuda"),
+                             cr.Weights(), opts, dtype=dtype, spheres=sp)
+    torch.cuda.synchronize()
+    return aos(u.cpu().numpy(), (rg.n, 3)), err.cpu().numpy().T, st.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("M", [0, 4])
+def test_ext_fp64_lm_iterates_match(oracle, cr, k, M):
+    print(f"extensible fp64 iterates k={k} M={M}", flush=True)
+    ro, rg, T, u, sph = _cost_case(oracle, cr, 820 + k + M, M)
+    P = T.shape[0]
+    seeds = u[:, :1]
+    ug, _, _ = _ik(cr, rg, T, seeds, cr.Opts(n_final=0, k_init=k, k_final=0), "f64", sph[:, :M] if M else None)
+    for p in range(P):
+        pb = oracle.Problem("ik", T[p], spheres=sph[p, :M] if M else None)
+        z0 = oracle.u_to_z(ro, seeds[p, 0]).ravel()
+        zk, _, _, _, _ = oracle.lm(ro, oracle.Weights(), pb, oracle.Opts(), z0, 1e-3, k)
+        uk = oracle.z_to_u(ro, zk.reshape(3, 3))
+        assert np.abs(ug[p] - uk).max() <= 1e-9 * 0.02, (p, np.abs(ug[p] - uk).max())
+
+
+def test_ext_two_stage_fp64_matches_oracle_solve(oracle, cr):
+    print("extensible two-stage fp64", flush=True)
+    ro, rg, T, u, sph = _cost_case(oracle, cr, 830, 4)
+    opts = dict(n_final=3, k_init=4, k_final=3)
+    ug, err, st = _ik(cr, rg, T, u, cr.Opts(**opts), "f64", sph[:, :4])
+    for p in range(T.shape[0]):
+        ref = oracle.solve(ro, oracle.Weights(), oracle.Problem("ik", T[p], spheres=sph[p, :4]), oracle.Opts(**opts),
+                           u[p])
+        assert st[p] == ref["status"], (p, st[p], ref["status"])
+        assert np.abs(ug[p] - ref["u"]).max() <= 1e-9 * 0.02, (p, np.abs(ug[p] - ref["u"]).max())
+        assert np.allclose(err[p], ref["err"], rtol=1e-9, atol=1e-13)
+
+
+def test_ext_two_stage_quality_among_spheres(oracle, cr):
+    """4-segment extendable robot (lengths within [0.5, 1.5] of nominal), targets from
+    FK of uniform bending and extension, 12 spheres per problem kept 3 mm clear of
+    the target configuration: FP32 stage 1 + FP64 stage 2 solves >= 95 %, and every
+    solved answer is inside the length bounds and collision free (oracle geometry)."""
+    print("extensible two-stage quality", flush=True)
+    rng = np.random.default_rng(840)
+    n, P, S, M, K = 4, 160, 64, 12, 6
+    ro, rg = _robots(oracle, cr, n, K=K)
+    ut = ext_actuation(rng, n, GEOM["b"], P, -0.015, 0.015)
+    _, fr, pts_t = oracle.fk(ro, ut, points=True)
+    seeds = ext_actuation(rng, n, GEOM["b"], P * S, -0.02, 0.02).reshape(P, S, n, 3)
+    body = np.repeat(np.asarray(GEOM["r"][:n]), K)
+    sph = np.zeros((P, M, 4))
+    for p in range(P):
+        m = 0
+        while m < M:
+            c = np.concatenate([rng.uniform([-0.2, -0.2, 0.0], [0.2, 0.2, 0.3]), rng.uniform([0.005], [0.02])])
+            if (np.linalg.norm(pts_t[p].reshape(-1, 3) - c[:3], axis=1) - c[3] - body).min() > 3e-3:
+                sph[p, m] = c
+                m += 1
+    ug, err, st = _ik(cr, rg, fr[:, -1], seeds, cr.Opts(n_final=8, k_init=150, k_final=50), "f32", sph)
+    solved = st == cr.SOLVED
+    print(f"  success {solved.mean():.3f}", flush=True)
+    assert solved.mean() >= 0.95, np.unique(st, return_counts=True)
+    for p in np.nonzero(solved)[0]:
+        arc, _, pts = oracle.fk(ro, ug[p], points=True)
+        assert ((arc[:, 2] >= np.array(GEOM["L_min"][:n]) - 1e-6) & (arc[:, 2] <= np.array(GEOM["L_max"][:n]) + 1e-6)).all()
+        g = np.linalg.norm(pts.reshape(-1, 1, 3) - sph[p, None, :, :3], axis=2) - sph[p, None, :, 3] - body[:, None]
+        assert g.min() >= 0.0
+        pe = oracle.pose_error(ro, oracle.u_to_z(ro, ug[p]), fr[p, -1])
+        assert pe[1] <= 1e-3 and pe[2] <= np.pi / 180
