@@ -608,6 +608,36 @@ static void collision_rows(const cro_robot* rb, const cro_weights* w, const cro_
     }
 }
 
+/* Self-contact rows of one waypoint (eq. 10): every pair of backbone points p, q
+ * of segments i and j >= i + 2, gap = |p - q| - r_i - r_j,
+ * r = sqrt(rho_coll) max(0, margin - gap). */
+static void self_rows(const cro_robot* rb, const cro_weights* w, int t, dual (*pts)[3], sink* s) {
+  int n = rb->n_seg, K = rb->pts_per_seg;
+  double sq = sqrt(w->rho_coll);
+  for (int i = 0; i < n; i++)
+    for (int j = i + 2; j < n; j++)
+      for (int k = 0; k < K; k++)
+        for (int l = 0; l < K; l++) {
+          dual* P = pts[i * K + k];
+          dual* Q = pts[j * K + l];
+          double dx = Q[0].v - P[0].v, dy = Q[1].v - P[1].v, dz = Q[2].v - P[2].v;
+          double dist = sqrt(dx * dx + dy * dy + dz * dz);
+          double gap = dist - rb->r[i] - rb->r[j];
+          if (!(w->margin - gap > 0.0)) continue;
+          dual ddist;
+          if (dist > 0.0) {
+            dual q[3] = {dsub(Q[0], P[0]), dsub(Q[1], P[1]), dsub(Q[2], P[2])};
+            ddist = dsqrt(dot3(q, q));
+          } else { /* coincident: take the +z direction */
+            ddist = dsub(Q[2], P[2]);
+            ddist.v = 0.0;
+          }
+          dual viol = dsub(dcon(w->margin + rb->r[i] + rb->r[j]), ddist);
+          term tm = {t, 1.0, &viol};
+          emit_lin(s, sq, 1, &tm);
+        }
+}
+
 /* groups of cost terms, so that the collision penalty alone can be evaluated */
 enum { T_TASK = 1, T_LIMITS = 2, T_COLL = 4, T_SMOOTH = 8, T_LEN = 16, T_ENDS = 32, T_ALL = 63 };
 
@@ -620,7 +650,7 @@ static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_pr
   s->rows = 0;
   waypoint* wp = (waypoint*)malloc(sizeof(waypoint) * (size_t)(H + 1));
   dual(*pts)[3] = NULL;
-  if (pb->n_sph > 0 && K > 0) pts = (dual(*)[3])malloc(sizeof(dual[3]) * (size_t)(n * K));
+  if ((pb->n_sph > 0 || rb->self_collision) && K > 0) pts = (dual(*)[3])malloc(sizeof(dual[3]) * (size_t)(n * K));
   double sq_lim = sqrt(w->rho_lim), sq_curv = sqrt(w->rho_curv);
 
   for (int t = 0; t <= H; t++) {
@@ -669,8 +699,9 @@ static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_pr
       term tm = {t, 1.0, &off};
       emit_hinge(s, sq_lim, 0.5 * (rb->L_max[i] - rb->L_min[i]), 1, &tm);
     }
-    /* obstacle clearance, eq. (10) */
-    if (pts && (terms & T_COLL)) collision_rows(rb, w, pb, t, pts, s);
+    /* obstacle clearance and self contact, eq. (10) */
+    if (pts && pb->n_sph > 0 && (terms & T_COLL)) collision_rows(rb, w, pb, t, pts, s);
+    if (pts && rb->self_collision && (terms & T_COLL)) self_rows(rb, w, t, pts, s);
   }
 
   if (pb->kind != CRO_IK && (terms & T_SMOOTH)) {
@@ -1011,7 +1042,7 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
       double th = sqrt(zt[zc * i] * zt[zc * i] + zt[zc * i + 1] * zt[zc * i + 1]);
       thx = fmax(thx, th - rb->theta_max);
     }
-    if (pb->n_sph > 0 && K > 0) {
+    if ((pb->n_sph > 0 || rb->self_collision) && K > 0) {
       double* P = (double*)malloc(sizeof(double) * 3 * (size_t)(n * K));
       double arc[3 * CRO_MAX_SEG];
       cro_fk(rb, u, arc, NULL, P);
@@ -1023,6 +1054,16 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
             double dx = q[0] - S[0], dy = q[1] - S[1], dzz = q[2] - S[2];
             gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - S[3] - rb->r[i]);
           }
+      /* self contact between non-adjacent segments */
+      for (int i = 0; i < n && rb->self_collision; i++)
+        for (int j = i + 2; j < n; j++)
+          for (int k = 0; k < K; k++)
+            for (int l = 0; l < K; l++) {
+              const double* p = P + 3 * (i * K + k);
+              const double* q = P + 3 * (j * K + l);
+              double dx = q[0] - p[0], dy = q[1] - p[1], dzz = q[2] - p[2];
+              gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - rb->r[i] - rb->r[j]);
+            }
       free(P);
     }
   }

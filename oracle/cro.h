@@ -45,6 +45,9 @@ typedef struct {
                                 segment's extension, L_i = L[i] + mean_j u_ij (Sec. V-B) */
   double L_min[CRO_MAX_SEG]; /* extensible: bounds on each segment length (eq. 9), m */
   double L_max[CRO_MAX_SEG];
+  int32_t self_collision;    /* 1: backbone points of non-adjacent segments (|i - j| >= 2)
+                                must keep r_i + r_j apart (eq. 10, self contact), with the
+                                clearance penalty and margin of the obstacles */
 } cro_robot;
 
 typedef struct {
