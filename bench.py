@@ -28,41 +28,37 @@ import numpy as np
 
 WORKLOAD = "ik_batched_3seg"
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CUs, 2.4 GHz)
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "path_4seg", "traj_5seg", "uneven_batch"],
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "ik_ext_4seg", "path_4seg", "traj_5seg", "uneven_batch"],
                     help="the headline IK workload, or one of the path / trajectory workloads")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the path, trajectory and uneven-batch summaries of the headline line")
+    ap.add_argument("--sub-steps", type=int, default=3, help="timed steps of each summarised workload")
     ap.add_argument("--baseline-problems", type=int, default=2,
                     help="path / trajectory problems timed with the plain per-problem baseline (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the compiler's own occupancy targets instead of the library's launch autotuning")
+    ap.add_argument("--force-variant", type=int, default=-1,
+                    help="run occupancy variant 0, 1 or 2 of every tunable kernel (counter runs per variant)")
     ap.add_argument("--tally-seeds", type=int, default=256)
     ap.add_argument("--baseline-targets", type=int, default=16,
                     help="targets timed with the plain per-problem FP32 solve (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (HBM counter calibration)")
-    ap.add_argument("--traffic-json", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                                                           "ik_stage1_traffic.json"))
+    ap.add_argument("--calib", action="store_true",
+                    help="time the vector-ALU calibration loops (known instruction counts) and exit")
     return ap.parse_args()
-
-
-def stage1_sources_hash():
-    """SHA-256 of the sources the stage-1 kernel is built from."""
-    import hashlib
-    h = hashlib.sha256()
-    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2607_11340_amd", "csrc")
-    for name in ("cr_device.h", "cr_ik.hip"):
-        with open(os.path.join(root, name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
 
 
 def build_inputs(cr, I, torch):
@@ -106,6 +102,51 @@ def baseline_rate(cr, torch, robot, T, useed, spec, opts, weights, args, fused_r
                      "forward-mode Jacobian")
 
 
+def plain_method(cr, torch, robot, T, useed, spec, weights, fused_rate, fused_success):
+    """The plain method on the same batch (no SelectTop, no stage 2: every seed
+    runs the whole iteration budget, k_init + k_final, in FP32, then the argmin),
+    the ablation of Table I's row without the beam search."""
+    P, S = spec["P"], spec["S"]
+    opts = cr.Opts(n_final=0, k_init=spec["k_init"] + spec["k_final"], k_final=0)
+    res = {}
+
+    def step():
+        res["out"] = cr.solve_ik(robot, T, useed, weights, opts, dtype=torch.float32)
+
+    step()
+    per_step, _ = step_times(torch, step, 3)
+    ms = float(np.median(per_step))
+    st = res["out"][2].cpu().numpy()
+    return dict(value=round(P / (ms * 1e-3), 1), unit="IK solves/s", ms_per_step=round(ms, 4),
+                success_rate=round(float((st == cr.SOLVED).mean()), 4), k_init=opts.k_init,
+                two_stage=dict(value=round(fused_rate, 1), success_rate=round(fused_success, 4)),
+                kind="stage 1 only over the whole budget, then the argmin (no SelectTop, no FP64 stage 2)")
+
+
+def oracle_reassessment(spec, T34, u, err, status):
+    """Every returned answer re-assessed by the FP64 CPU oracle (a zero-iteration
+    plain solve from the answer itself returns the oracle's own status bits and
+    errors): the largest difference from the device's FP64 errors and the success
+    rate as the oracle judges it."""
+    from oracle import oracle as O
+    n = len(spec["L"])
+    rb = O.Robot(L=spec["L"], r=spec["r"], u_max=[spec["b"]] * n)
+    W, opts = O.Weights(), O.Opts(n_final=0, k_init=0, k_final=0)
+    P = len(u)
+    t0 = time.perf_counter()
+    st_o = np.zeros(P, dtype=np.int64)
+    err_o = np.zeros((P, 2))
+    for p in range(P):
+        res = O.solve(rb, W, O.Problem("ik", T34[p]), opts, u[p][None])
+        st_o[p], err_o[p] = res["status"], res["err"]
+    return dict(answers=P, seconds=round(time.perf_counter() - t0, 2),
+                max_abs_diff_pos_err_m=float(np.abs(err_o[:, 0] - err[0]).max()),
+                max_abs_diff_rot_err_rad=float(np.abs(err_o[:, 1] - err[1]).max()),
+                status_agreement=round(float((st_o == status).mean()), 6),
+                oracle_success_rate=round(float((st_o == O.SOLVED).mean()), 6),
+                max_oracle_pos_err_solved_m=float(np.max(np.where(st_o == O.SOLVED, err_o[:, 0], 0.0))))
+
+
 def fk_grad_rate(cr, I, torch, args):
     """FK + cost + adjoint gradient evaluations per second on the path workload's
     shape (512 paths x 32 seeds x 64 waypoints = 1,048,576 waypoint configurations
@@ -140,8 +181,22 @@ def fk_grad_rate(cr, I, torch, args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     evals = P * S * Tn
-    return dict(value=round(evals / (ms * 1e-3), 1), unit="FK+grad evals/s", ms_per_call=round(ms, 4),
-                workload="path_4seg shape: 512 x 32 x 64 waypoint configurations, forward + backward via CostGrad, f32")
+    # algorithmic HBM bytes of one forward + backward: u in (3n FP32 per configuration,
+    # read by both passes), the poses (12 FP32 per problem waypoint), the cost and the
+    # upstream gradient per seed, the gradient out (3n FP32 per configuration)
+    alg_bytes = 4 * (2 * 3 * n * evals + 12 * P * Tn + 2 * P * S + 3 * n * evals)
+    out = dict(value=round(evals / (ms * 1e-3), 1), unit="FK+grad evals/s", ms_per_call=round(ms, 4),
+               workload="path_4seg shape: 512 x 32 x 64 waypoint configurations, forward + backward via CostGrad, f32",
+               hbm_bytes_per_call=alg_bytes,
+               hbm_frac=round(alg_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    meas = stored_counters("fk_grad")
+    if meas and meas.get("valu_f32_flops_per_call"):
+        f = meas["valu_f32_flops_per_call"]
+        out["counter_f32_flops_per_call"] = f
+        out["valu_frac"] = round(f / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)
+        if meas.get("hbm_bytes_per_call"):
+            out["counter_hbm_bytes_per_call"] = meas["hbm_bytes_per_call"]
+    return out
 
 
 def cpu_baseline(spec, T_host, seeds, budget_s):
@@ -164,7 +219,7 @@ def cpu_baseline(spec, T_host, seeds, budget_s):
             break
     return dict(value=done / el, unit="IK solves/s", cores=1, kind="oracle",
                 sample=f"first {done} of {spec['P']} targets x {S} seeds, full {spec['k_init']}+{spec['k_final']} "
-                       f"iterations, single thread, {el:.1f} s; {solved}/{done} solved")
+                       f"iterations, single thread, {el:.1f} s; {solved}/{done} solved", host=host_info())
 
 
 def traj_baseline_rate(cr, torch, d, spec, opts, weights, args, fused_rate):
@@ -208,16 +263,107 @@ def traj_baseline_rate(cr, torch, d, spec, opts, weights, args, fused_rate):
                         "success rate is not comparable" if spec["kind"] == "path" else ""))
 
 
+STAGE1_OCC = {0: 1, 1: 3, 2: 4}   # occupancy target of each IK stage-1 variant (1: the compiler's own)
+
+
 def autotune(args, cr, torch, call):
     """The library's launch autotuning: one untimed call (call) times each tunable
     kernel's occupancy variants -- identical results, different speed -- and caches
     the fastest; the timed steps use the cached choices."""
+    if args.force_variant >= 0:
+        cr.autotune_force(args.force_variant)
+        return [f"forced variant {args.force_variant}"]
     if args.no_autotune:
         return None
     cr.autotune(True)
     call()
     torch.cuda.synchronize()
     return cr.autotune_report()
+
+
+def bench_calib(cr, torch):
+    """Issue rate of known vector-ALU loops (cr_calib_valu): FMA, RCP, FMA + RCP,
+    FP64 FMA, ADD, MUL, FMA over 32 chains, and the stage-1 FMA : MUL : ADD mix.  Rates are per CU and cycle at the 2.4 GHz peak
+    clock; under rocprofv3 the same launches give the SQ_INSTS_VALU* counts."""
+    blocks, iters = 8192, 2048
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    res = {}
+    names = ("fma_f32", "rcp_f32", "fma_f32+rcp_f32", "fma_f64", "add_f32", "mul_f32", "fma_f32_32chains",
+             "fma10_mul4_add2_f32", "fma_f32_lanes0-31", "fma_f32_lanes0-15")
+    for kind, per_round in ((0, 16), (1, 16), (2, 20), (3, 16), (4, 16), (5, 16), (6, 32), (7, 16), (8, 16), (9, 16)):
+        cr.calib_valu(kind, blocks, iters, out)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cr.calib_valu(kind, blocks, iters, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = float(np.median(ms))
+        winst = blocks * 4 * iters * per_round
+        res[names[kind]] = dict(
+            ms=round(t, 4), wave_instructions=winst,
+            per_cu_cycle_at_2400mhz=round(winst / (t * 1e-3) / (256 * 2.4e9), 4))
+    print(json.dumps(dict(calib_valu=res, blocks=blocks, iters=iters)), flush=True)
+
+
+def step_times(torch, step, k):
+    """Runs k steps, each bracketed by HIP events on the current stream, inside one
+    synchronised bracket; returns (per-step ms list, bracket ms)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    b0.record()
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    b1.record()
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in evs], b0.elapsed_time(b1)
+
+
+def host_info():
+    """Cores this process may use and the CPU model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=len(os.sched_getaffinity(0)), cpu_count=os.cpu_count(), cpu_model=model)
+
+
+COUNTERS_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "counters.json")
+
+
+def sources_hash():
+    """SHA-256 over the solver's kernel sources (the calibration loops excluded)."""
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2607_11340_amd", "csrc")
+    for name in sorted(os.listdir(root)):
+        if name.endswith((".hip", ".h")) and name != "cr_calib.hip":
+            with open(os.path.join(root, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def stored_counters(workload):
+    """rocprofv3 counter values stored for a workload (profiles/counters.json), or
+    None when they were taken on other kernel sources than these."""
+    if not os.path.exists(COUNTERS_JSON):
+        return None
+    with open(COUNTERS_JSON) as f:
+        meas = json.load(f)
+    if meas.get("sources_sha256") != sources_hash():
+        return None
+    return meas.get("workloads", {}).get(workload)
 
 
 def main():
@@ -231,8 +377,13 @@ def main():
     from paper_2607_11340_amd import crsolver as cr
     from paper_2607_11340_amd import inputs as I
 
+    if args.calib:
+        return bench_calib(cr, torch)
     if args.workload == "uneven_batch":
         return bench_uneven(args, cr, I, torch)
+    if args.workload == "ik_ext_4seg":
+        print(json.dumps(run_ik_ext(args, cr, I, torch, args.steps, args.warmup)), flush=True)
+        return
     if args.workload != WORKLOAD:
         return bench_trajectories(args, cr, I, torch)
     spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
@@ -261,25 +412,19 @@ def main():
     print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
     cr.lib.cr_timing_enable(1)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
+    per_step, total_ms = step_times(torch, step, args.steps)
     stage_ms = (C.c_double * 4)()
     ncalls = C.c_int64(0)
     cr._check(cr.lib.cr_timing_read(stage_ms, C.byref(ncalls)))
     cr.lib.cr_timing_enable(0)
-    ms_per_step = total_ms / args.steps
+    ms_per_step = float(np.median(per_step))
     stage_avg = [stage_ms[k] / max(ncalls.value, 1) for k in range(4)]
     status = out[2].cpu().numpy()
     err = out[1].cpu().numpy()
+    u_host = out[0].cpu().numpy().T.reshape(P, robot.n, 3)
     success = float((status == cr.SOLVED).mean())
-    print(f"bench: {args.steps} steps, {ms_per_step:.3f} ms/step, stages {['%.3f' % s for s in stage_avg]} ms, "
-          f"success {success:.4f}", file=sys.stderr, flush=True)
+    print(f"bench: {args.steps} steps, median {ms_per_step:.3f} ms/step, stages {['%.3f' % s for s in stage_avg]} "
+          f"ms, success {success:.4f}", file=sys.stderr, flush=True)
 
     # algorithmic flops of the stage-1 kernel from the library's op tally over a seed sample
     T_host = T.cpu().numpy().T.copy()                       # [P, 12]
@@ -296,41 +441,68 @@ def main():
     flops_launch = flops_per_seed * P * S
     achieved = flops_launch / (stage_avg[0] * 1e-3) / 1e12
     occ = [l.split("occupancy ")[1].split()[0] for l in (tuned or []) if "ik_stage1 n_seg 3 f32" in l]
+    if args.force_variant >= 0:
+        occ = [str(STAGE1_OCC[args.force_variant])]
     kname = "k_ik_stage1<3,float,%s>" % occ[0] if occ else "k_ik_stage1<3,float,1>"  # 1: the compiler's own target
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            meas = json.load(f)
-        # counters describe the kernel variant built from these sources only
-        if meas.get("sources_sha256") == stage1_sources_hash() and meas.get("kernel") == kname:
-            traffic = meas.get("bytes_per_launch")
+    meas = stored_counters(WORKLOAD) or {}
+    kmeas = meas.get(kname, {})
+    traffic = kmeas.get("hbm_bytes_per_launch")
+    # the build's survey estimate of about 3 kflop per FP32 seed-iteration, for comparison
+    survey_flops = 3.0e3 * P * S * spec["k_init"]
     roofline = dict(bound="alu", kernel=kname, achieved=round(achieved, 3),
                     peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=traffic, launch_ms=round(stage_avg[0], 4),
                     flops_per_launch=flops_launch, flops_per_seed=round(flops_per_seed, 1),
+                    flops_per_seed_iteration=round(flops_per_seed / spec["k_init"], 1),
                     flops_per_normal_eq=tally[6], flops_per_cost_eval=tally[7],
-                    trials_per_seed=round(tally[5], 2), tally_sample_seeds=len(pick))
+                    trials_per_seed=round(tally[5], 2), tally_sample_seeds=len(pick),
+                    frac_at_3kflop_per_seed_iteration=round(survey_flops / (stage_avg[0] * 1e-3) / 1e12
+                                                            / FP32_VECTOR_PEAK_TFLOPS, 4))
+    if kmeas:
+        cf = kmeas.get("valu_f32_flops_per_launch")
+        if cf:
+            roofline["counter_f32_flops_per_launch"] = cf
+            roofline["counter_frac"] = round(cf / (stage_avg[0] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)
+        if traffic:
+            roofline["hbm_frac"] = round(traffic / (stage_avg[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)
+    s2name = "k_ik_stage2<3,float,false>"
+    if s2name in meas and meas[s2name].get("valu_f64_flops_per_launch"):
+        f64 = meas[s2name]["valu_f64_flops_per_launch"]
+        roofline["stage2_fp64"] = dict(kernel=s2name, counter_f64_flops_per_launch=f64, launch_ms=round(stage_avg[2], 4),
+                                       frac_of_fp64_peak=round(f64 / (stage_avg[2] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4))
 
+    plain = plain_method(cr, torch, robot, T, useed, spec, weights, P / (ms_per_step * 1e-3), success)
     fkg = fk_grad_rate(cr, I, torch, args)
     b0 = baseline_rate(cr, torch, robot, T, useed, spec, opts, weights, args, P / (ms_per_step * 1e-3))
+    del ws
+    torch.cuda.empty_cache()
+    subs = {}
+    if not args.headline_only:
+        for name in ("ik_ext_4seg", "path_4seg", "traj_5seg", "uneven_batch"):
+            print(f"bench: workload {name}", file=sys.stderr, flush=True)
+            subs[name] = sub_workload(name, args, cr, I, torch)
+            torch.cuda.empty_cache()
 
     base = None
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        print("bench: timing the CPU oracle and re-assessing every answer with it", file=sys.stderr, flush=True)
         T34 = T_host.reshape(P, 3, 4)
         base = cpu_baseline(spec, T34, seeds, args.cpu_seconds)
+        base["reassessment"] = oracle_reassessment(spec, T34, u_host, err, status)
 
     line = dict(
         metric="IK solves/sec at <=1 mm/1 deg (success %); FK+grad evals/sec; %FP32 VALU peak",
         value=round(P / (ms_per_step * 1e-3), 1), unit="IK solves/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), ms_per_step_mean=round(total_ms / args.steps, 4),
+        ms_per_step_range=[round(min(per_step), 4), round(max(per_step), 4)], higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
         config=dict(workload=WORKLOAD, segments=len(spec["L"]), targets=P, seeds_per_target=S,
                     k_init=spec["k_init"], k_final=spec["k_final"], n_final=spec["n_final"]),
         success_rate=round(success, 4), max_pos_err_solved_m=float(np.nanmax(np.where(status == cr.SOLVED, err[0], 0))),
         stage_ms=dict(stage1=round(stage_avg[0], 4), select=round(stage_avg[1], 4), stage2=round(stage_avg[2], 4),
                       finalize=round(stage_avg[3], 4)),
-        fk_grad=fkg, plain_gpu_baseline=b0, roofline=roofline, cpu_baseline=base, autotune=tuned)
+        plain_method=plain, fk_grad=fkg, workloads=subs, plain_gpu_baseline=b0, roofline=roofline,
+        cpu_baseline=base, autotune=tuned, host=host_info())
     print(json.dumps(line), flush=True)
 
 
@@ -399,7 +571,11 @@ def traj_inputs(name, cr, I, torch, O=None):
 
 
 def bench_trajectories(args, cr, I, torch):
-    d = traj_inputs(args.workload, cr, I, torch)
+    print(json.dumps(run_trajectories(args.workload, args, cr, I, torch, args.steps, args.warmup, True)), flush=True)
+
+
+def run_trajectories(name, args, cr, I, torch, steps, warmup, extras):
+    d = traj_inputs(name, cr, I, torch)
     spec, robot, P, S, H = d["spec"], d["robot"], d["P"], d["S"], d["H"]
     opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"],
                    k_seed=spec.get("k_seed", 0))
@@ -415,36 +591,120 @@ def bench_trajectories(args, cr, I, torch):
            out=out)
 
     tuned = autotune(args, cr, torch, step)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    print(f"bench: warmup done ({warmup} steps)", file=sys.stderr, flush=True)
+    per_step, total = step_times(torch, step, steps)
+    ms = float(np.median(per_step))
     status = out[2].cpu().numpy()
     err = out[1].cpu().numpy()
     unit = "paths/s" if spec["kind"] == "path" else "trajectories/s"
     line = dict(metric=f"{spec['kind']} solves/sec (success %)", value=round(P / (ms * 1e-3), 2), unit=unit, n_gpus=1,
-                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True,
+                steps=steps, warmup=warmup, ms_per_step=round(ms, 4), ms_per_step_mean=round(total / steps, 4),
+                higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
-                config=dict(workload=args.workload, segments=robot.n, problems=P, waypoints=H + 1, seeds=S,
+                config=dict(workload=name, segments=robot.n, problems=P, waypoints=H + 1, seeds=S,
                             spheres=spec.get("M", 0), pts_per_seg=robot.pts_per_seg, k_init=spec["k_init"],
                             k_final=spec["k_final"], n_final=spec["n_final"], k_seed=spec.get("k_seed", 0)),
                 success_rate=round(float((status == cr.SOLVED).mean()), 4),
                 status_counts={int(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                 max_err_solved=[float(np.max(np.where(status == cr.SOLVED, err[k], 0))) for k in range(2)],
                 autotune=tuned)
-    print("bench: timing the plain per-problem baseline", file=sys.stderr, flush=True)
-    line["plain_gpu_baseline"] = traj_baseline_rate(cr, torch, d, spec, opts, weights, args, line["value"])
-    if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    line.update(counter_roofline(name, ms))
+    if extras:
+        print("bench: timing the plain per-problem baseline", file=sys.stderr, flush=True)
+        line["plain_gpu_baseline"] = traj_baseline_rate(cr, torch, d, spec, opts, weights, args, line["value"])
+        if not args.no_cpu_baseline:
+            print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+            line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)
+    return line
+
+
+def counter_roofline(name, ms):
+    """Vector-ALU rate of a whole step from stored rocprofv3 op counters (FP32 and
+    FP64 flops per step, masked lanes included) over this run's step time."""
+    meas = stored_counters(name)
+    if not meas:
+        return dict(counter_roofline=None)
+    f32, f64 = meas.get("valu_f32_flops_per_step", 0.0), meas.get("valu_f64_flops_per_step", 0.0)
+    return dict(counter_roofline=dict(
+        bound="alu", unit="TFLOP/s", f32_flops_per_step=f32, f64_flops_per_step=f64,
+        f32_achieved=round(f32 / (ms * 1e-3) / 1e12, 3), frac_fp32=round(f32 / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+        frac_fp64=round(f64 / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 4),
+        dominant_kernel=meas.get("dominant_kernel"), source=meas.get("source")))
+
+
+def run_ik_ext(args, cr, I, torch, steps, warmup):
+    """Two-stage IK of a 4-segment robot with extensible segments (lengths free in
+    [0.5, 1.5] of nominal) among a jittered 3 x 3 x 3 sphere lattice: targets from
+    forward kinematics of uniform bending and extension, kept only when their
+    backbone clears every sphere by 2 mm; uniform seeds of bending and extension."""
+    name = "ik_ext_4seg"
+    spec = I.WORKLOADS[name]
+    n, P, S, b, K = len(spec["L"]), spec["P"], spec["S"], spec["b"], spec["K"]
+    rng = I.rng_for(name)
+    robot = cr.Robot(L=spec["L"], r=spec["r"], u_max=[b] * n, pts_per_seg=K, L_min=spec["L_min"], L_max=spec["L_max"])
+    lat = spec["lattice"]
+    sph = I.sphere_lattice(rng, lat["xy"], lat["z"], lat["radius"], lat["jitter"])
+    e_lo = [lo - L for lo, L in zip(spec["L_min"], spec["L"])]
+    e_hi = [hi - L for hi, L in zip(spec["L_max"], spec["L"])]
+    dev = torch.device("cuda:0")
+    body = np.repeat(np.asarray(spec["r"]), K)
+    keep = []
+    while sum(len(k) for k in keep) < P:
+        cand = I.extended_actuation(rng, n, b, [0.75 * e for e in e_lo], [0.75 * e for e in e_hi], 2 * P)
+        out = cr.fk(robot, torch.tensor(cand.reshape(2 * P, -1).T.copy(), device=dev), arc=False, points=True)
+        pts = out["pts"].cpu().numpy().T.reshape(2 * P, n * K, 3)
+        gap = (np.linalg.norm(pts[:, :, None, :] - sph[None, None, :, :3], axis=3) - sph[None, None, :, 3]
+               - body[None, :, None]).min(axis=(1, 2))
+        keep.append(cand[gap > 2e-3])
+    u_true = np.concatenate(keep)[:P]
+    fr = cr.fk(robot, torch.tensor(u_true.reshape(P, -1).T.copy(), device=dev), arc=False)["frames"]
+    T = fr[12 * (n - 1):12 * n].contiguous()
+    seeds = I.extended_actuation(rng, n, b, e_lo, e_hi, P * S)
+    useed = torch.tensor(seeds.reshape(P * S, -1).T.copy(), device=dev)
+    sp = (torch.tensor(np.ascontiguousarray(sph.T), device=dev), False, len(sph))
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    weights = cr.Weights()
+    ws = torch.empty(cr.ik_workspace_bytes(robot, P, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    out = (torch.empty((3 * n, P), dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"),
+           torch.empty((P,), dtype=torch.int32, device="cuda"))
+
+    def step():
+        cr.solve_ik(robot, T, useed, weights, opts, dtype=torch.float32, spheres=sp, workspace=ws, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    per_step, total = step_times(torch, step, steps)
+    ms = float(np.median(per_step))
+    st = out[2].cpu().numpy()
+    line = dict(metric="extendable IK solves/sec (success %)", value=round(P / (ms * 1e-3), 1), unit="IK solves/s",
+                n_gpus=1, steps=steps, warmup=warmup, ms_per_step=round(ms, 4), ms_per_step_mean=round(total / steps, 4),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64",
+                data="synthetic",
+                config=dict(workload=name, segments=n, targets=P, seeds_per_target=S, spheres=len(sph),
+                            length_bounds=[spec["L_min"][0], spec["L_max"][0]], k_init=spec["k_init"],
+                            k_final=spec["k_final"], n_final=spec["n_final"]),
+                success_rate=round(float((st == cr.SOLVED).mean()), 4),
+                status_counts={int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))})
+    line.update(counter_roofline(name, ms))
+    return line
+
+
+def sub_workload(name, args, cr, I, torch):
+    """A compact line of one of the other workloads for the headline JSON."""
+    if name == "ik_ext_4seg":
+        ln = run_ik_ext(args, cr, I, torch, args.sub_steps, 1)
+    elif name == "uneven_batch":
+        ln = run_uneven(args, cr, I, torch, args.sub_steps, 1, False)
+    else:
+        ln = run_trajectories(name, args, cr, I, torch, args.sub_steps, 1, False)
+    keep = ("value", "unit", "ms_per_step", "ms_per_step_mean", "steps", "success_rate", "success_by_kind",
+            "status_counts", "config", "counter_roofline", "autotune")
+    return {k: ln[k] for k in keep if k in ln}
 
 
 def traj_cpu_baseline(d, spec, weights, opts, budget_s):
@@ -590,6 +850,10 @@ def uneven_baseline_estimate(cr, torch, singles, weights, opts, args, fused_rate
 
 
 def bench_uneven(args, cr, I, torch):
+    print(json.dumps(run_uneven(args, cr, I, torch, args.steps, args.warmup, True)), flush=True)
+
+
+def run_uneven(args, cr, I, torch, steps, warmup, extras):
     P = I.UNEVEN["P"]
     t0 = time.perf_counter()
     batch, probs, n_sph, singles = uneven_inputs(cr, I, torch, P)
@@ -609,22 +873,18 @@ def bench_uneven(args, cr, I, torch):
 
     # tuned eagerly: the graph captured by the first warm-up step then holds the chosen variants
     tuned = autotune(args, cr, torch, lambda: step(graph=False))
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    print(f"bench: warmup done ({warmup} steps)", file=sys.stderr, flush=True)
+    per_step, total = step_times(torch, step, steps)
+    ms = float(np.median(per_step))
     st = out[2].cpu().numpy()
     kinds = np.array([("ik", "path", "traj").index(p["kind"]) for p in probs])
     succ = {k: round(float((st[kinds == i] == cr.SOLVED).mean()), 4) for i, k in enumerate(("ik", "path", "traj"))}
     line = dict(metric="uneven batch solves/sec (success %)", value=round(P / (ms * 1e-3), 2), unit="problems/s",
-                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
+                n_gpus=1, steps=steps, warmup=warmup, ms_per_step=round(ms, 3), ms_per_step_mean=round(total / steps, 3),
+                higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
                 config=dict(workload="uneven_batch", problems=P, mix=dict(ik=int((kinds == 0).sum()),
                                                                           path=int((kinds == 1).sum()),
@@ -632,9 +892,11 @@ def bench_uneven(args, cr, I, torch):
                             segments="U{1..6}", horizons="U{1..64}", seeds="U{16..512}", spheres="U{0..64}",
                             spheres_kept=n_sph, seeds_total=int(sum(p["S"] for p in probs)), graph=True),
                 success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ, autotune=tuned)
-    print("bench: timing the plain per-problem baseline on a per-kind sample", file=sys.stderr, flush=True)
-    line["plain_gpu_baseline"] = uneven_baseline_estimate(cr, torch, singles, weights, opts, args, line["value"])
-    print(json.dumps(line), flush=True)
+    line.update(counter_roofline("uneven_batch", ms))
+    if extras:
+        print("bench: timing the plain per-problem baseline on a per-kind sample", file=sys.stderr, flush=True)
+        line["plain_gpu_baseline"] = uneven_baseline_estimate(cr, torch, singles, weights, opts, args, line["value"])
+    return line
 
 
 if __name__ == "__main__":

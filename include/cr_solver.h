@@ -401,13 +401,16 @@ cr_status cr_ik_flop_tally(const cr_robot* robot, const cr_weights* weights, con
                            const double* T_target, const double* u_seed, double* out);
 
 /* Calibration of the vector-ALU accounting: launches `blocks` workgroups of 256
- * lanes, each lane running `iters` rounds over 16 independent chains of one
- * instruction per chain and round: kind 0 v_fma_f32, 1 v_rcp_f32, 2 v_fma_f32 on
- * every chain plus v_rcp_f32 on every fourth, 3 v_fma_f64.  The known instruction
- * count per wave (16 or 20 per round) against the measured duration gives the
- * issue rate the SIMDs reach, and against the SQ_INSTS_VALU* counters what those
- * count.  out [device] receives blocks * 256 floats.  CR_EINVAL for kind not in
- * 0..3, blocks not in 1..2^20, iters < 1 or out == NULL. */
+ * lanes, each lane running `iters` rounds over independent chains of one
+ * instruction per chain and round: kind 0 v_fma_f32 (16 chains), 1 v_rcp_f32,
+ * 2 v_fma_f32 on every chain plus v_rcp_f32 on every fourth, 3 v_fma_f64,
+ * 4 v_add_f32, 5 v_mul_f32, 6 v_fma_f32 over 32 chains, 7 ten v_fma_f32, four
+ * v_mul_f32 and two v_add_f32 per round, 8 and 9 as 0 with only the first 32 or
+ * 16 lanes of every wave active.  The known instruction count per wave
+ * against the measured duration gives the issue rate the SIMDs reach, and against
+ * the SQ_INSTS_VALU* counters what those count.  out [device] receives blocks *
+ * 256 floats.  CR_EINVAL for kind not in 0..9, blocks not in 1..2^20, iters < 1
+ * or out == NULL. */
 cr_status cr_calib_valu(int32_t kind, int64_t blocks, int32_t iters, float* out, hipStream_t stream);
 
 /* Text for a status code, and the thread's last error message. */
