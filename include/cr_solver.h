@@ -86,6 +86,12 @@ typedef struct {
                                  Supported by cr_fk, cr_cost_grad (IK) and cr_solve_ik. */
   double L_min[CR_MAX_SEG];   /* extensible: segment length bounds (m), 0 < L_min <= L <= L_max */
   double L_max[CR_MAX_SEG];
+  int32_t self_collision;     /* 1: contact between the robot's own non-adjacent segments
+                                 (|i - j| >= 2) counts as collision (eq. 10): backbone points
+                                 keep r_i + r_j apart, with the clearance penalty and margin
+                                 of the obstacles; the status gets CR_COLLISION.  Supported by
+                                 cr_cost_grad (IK) and cr_solve_ik (n_seg >= 3; fewer segments
+                                 have no such pair). */
 } cr_robot;
 
 /* Spherical obstacles.  [host] struct, `sph` is [device] in the call's dtype for

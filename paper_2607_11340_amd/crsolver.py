@@ -45,7 +45,8 @@ class _Robot(C.Structure):
     _fields_ = [("n_seg", C.c_int32), ("pts_per_seg", C.c_int32),
                 ("L", C.c_double * MAX_SEG), ("r", C.c_double * MAX_SEG),
                 ("u_max", C.c_double * MAX_SEG), ("theta_max", C.c_double),
-                ("extensible", C.c_int32), ("L_min", C.c_double * MAX_SEG), ("L_max", C.c_double * MAX_SEG)]
+                ("extensible", C.c_int32), ("L_min", C.c_double * MAX_SEG), ("L_max", C.c_double * MAX_SEG),
+                ("self_collision", C.c_int32)]
 
 
 class _Spheres(C.Structure):
@@ -81,6 +82,7 @@ class Robot:
     theta_max: float = math.pi
     L_min: list = None   # extensible segments: length bounds (m); both given <=> the
     L_max: list = None   # common mode of each segment's tendons is its extension
+    self_collision: bool = False   # contact between non-adjacent segments counts (eq. 10)
 
     @property
     def n(self) -> int:
@@ -105,6 +107,7 @@ class Robot:
             s.extensible = 1
             for i in range(self.n):
                 s.L_min[i], s.L_max[i] = self.L_min[i], self.L_max[i]
+        s.self_collision = 1 if self.self_collision else 0
         return s
 
 

@@ -44,6 +44,7 @@ RobotT<T> robot_to(const cr_robot& r) {
   }
   o.theta_maxd = r.theta_max;
   o.ext = r.extensible ? 1 : 0;
+  o.self = r.self_collision ? 1 : 0;
   for (int i = 0; i < CR_MAX_SEG; ++i) {
     const bool on = r.extensible && i < r.n_seg;
     o.Lmidd[i] = on ? 0.5 * (r.L_min[i] + r.L_max[i]) : 0.0;
@@ -145,6 +146,7 @@ cr_status check_robot(const cr_robot* rb) {
   }
   if (!(rb->theta_max > 0.0)) return fail(CR_EINVAL, "theta_max must be > 0");
   if (rb->extensible != 0 && rb->extensible != 1) return fail(CR_EINVAL, "extensible must be 0 or 1");
+  if (rb->self_collision != 0 && rb->self_collision != 1) return fail(CR_EINVAL, "self_collision must be 0 or 1");
   for (int i = 0; rb->extensible && i < rb->n_seg; ++i)
     if (!(rb->L_min[i] > 0.0) || !(rb->L_min[i] <= rb->L[i]) || !(rb->L[i] <= rb->L_max[i]) || !isfinite(rb->L_max[i]))
       return fail(CR_EINVAL, "extensible segment %d needs 0 < L_min <= L <= L_max (finite)", i);
@@ -154,6 +156,8 @@ cr_status check_robot(const cr_robot* rb) {
 cr_status check_inextensible(const cr_robot* rb, const char* what) {
   if (rb && rb->extensible) return fail(CR_EUNSUPPORTED, "%s: extensible segments are supported by cr_fk, "
                                                           "cr_cost_grad (IK) and cr_solve_ik only", what);
+  if (rb && rb->self_collision && rb->n_seg >= 3)
+    return fail(CR_EUNSUPPORTED, "%s: self contact is supported by cr_cost_grad (IK) and cr_solve_ik only", what);
   return CR_OK;
 }
 

@@ -27,7 +27,7 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 }
 
 // EXT: extensible segments, the third coordinate e_i = mean_j u_ij per segment.
-template <int NS, typename T, bool GRAD, bool EXT = false>
+template <int NS, typename T, bool GRAD, bool EXT = false, bool SELF = false>
 __global__ void __launch_bounds__(256)
     k_cost_ik(RobotT<T> rb, WeightsT<T> w, int64_t P, int S, const T* __restrict__ task, const T* __restrict__ sph,
               int64_t sld, int M, int per_problem, const T* __restrict__ u, T* __restrict__ cost, T* __restrict__ grad,
@@ -53,8 +53,9 @@ __global__ void __launch_bounds__(256)
   for (int c = 0; c < 12; ++c) tt[c] = task[c * P + p];
   Fwd<NS, T, EXT> f;
   const T* sp = sph ? sph + (per_problem ? p * M : 0) : nullptr;
-  T c = (sph && M > 0) ? config_forward<NS, T, GRAD, double, T, EXT>(rb, w, z, sp, M, 1, sld, f, zd)
-                        : config_forward<NS, T, GRAD, T, T, EXT>(rb, w, z, sp, 0, 1, sld, f, zd);
+  // clearance (spheres, self contact) is formed on an FP64 chain (see cr_cost_grad)
+  T c = ((sph && M > 0) || SELF) ? config_forward<NS, T, GRAD, double, T, EXT, SELF>(rb, w, z, sp, M, 1, sld, f, zd)
+                                 : config_forward<NS, T, GRAD, T, T, EXT, SELF>(rb, w, z, sp, 0, 1, sld, f, zd);
   T ft[3] = {T(0), T(0), T(0)}, tq[3] = {T(0), T(0), T(0)};
   c += pose_term<T, GRAD>(w, f.R, f.p, tt, ft, tq);
   cost[b] = c;
@@ -250,16 +251,22 @@ static cr_status run_cost(int kind, const cr_robot& rb0, const cr_spheres* sp, c
   if (B == 0) return CR_OK;
   if (kind == CR_KIND_IK) {
     const unsigned nb = (unsigned)((B + 255) / 256);
-#define CR_COST_IK(G, E)                                                                                          \
-  hipLaunchKernelGGL((k_cost_ik<NS, T, G, E>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld, M, \
-                     ppb, (const T*)u, (T*)cost, G ? (T*)grad : (T*)nullptr, G ? (const T*)gscale : (const T*)nullptr)
-    if (rb0.extensible) {
-      if (grad) CR_COST_IK(true, true);
-      else CR_COST_IK(false, true);
-    } else {
-      if (grad) CR_COST_IK(true, false);
-      else CR_COST_IK(false, false);
-    }
+#define CR_COST_IK(G, E, SF)                                                                                     \
+  hipLaunchKernelGGL((k_cost_ik<NS, T, G, E, SF>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld, \
+                     M, ppb, (const T*)u, (T*)cost, G ? (T*)grad : (T*)nullptr, G ? (const T*)gscale : (const T*)nullptr)
+#define CR_COST_IK2(E, SF)       \
+  do {                           \
+    if (grad)                    \
+      CR_COST_IK(true, E, SF);   \
+    else                         \
+      CR_COST_IK(false, E, SF);  \
+  } while (0)
+    const bool self = rb0.self_collision && NS >= 3;
+    if (rb0.extensible && self) CR_COST_IK2(true, true);
+    else if (rb0.extensible) CR_COST_IK2(true, false);
+    else if (self) CR_COST_IK2(false, true);
+    else CR_COST_IK2(false, false);
+#undef CR_COST_IK2
 #undef CR_COST_IK
     return check_hip(hipGetLastError(), "k_cost_ik");
   }

@@ -38,6 +38,7 @@ struct RobotT {
   double Ld[CR_MAX_SEG], rd[CR_MAX_SEG], umaxd[CR_MAX_SEG], theta_maxd;
   // extensible segments: centre and half width of each length interval (eq. 9)
   int ext;
+  int self;  // 1: contact between non-adjacent segments counts as collision (eq. 10)
   T Lmid[CR_MAX_SEG], Lhalf[CR_MAX_SEG];
   double Lmidd[CR_MAX_SEG], Lhalfd[CR_MAX_SEG];
 };
@@ -830,12 +831,109 @@ struct Fwd {
 // backbone-to-centre distances, and FP32 positions would set its error.  The pair
 // rejection test stays in T (with a relative slack); active pairs are re-measured
 // in TC.
-template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T, bool EXT = false>
+// Self contact (eq. 10) of the points of segment j against those of every
+// segment m <= j - 2: residual sq_coll max(0, margin + r_j + r_m - |q - p|) per
+// pair of points q (segment j) and p (segment m).  Segment m's base frame is
+// (Rb[m], pb[m]) and sb[m] = (a, b, L).  With GRAD the pair's force acts on q and,
+// opposite, on p: recorded as point forces of both segments (swept back by
+// config_reverse) plus their own-arc terms.  Every point lies within L / 2 of its
+// segment's arc midpoint, so a segment pair whose midpoints are farther apart than
+// (L_j + L_m) / 2 + the reach is skipped whole.
+template <int NS, typename T, bool GRAD, typename TC, bool EXT>
+CR_HD T self_contact(const RobotT<T>& rb, const WeightsT<T>& w, int j, const TC (*Rb)[9], const TC (*pb)[3],
+                     const TC (*sb)[3], Fwd<NS, T, EXT>& f) {
+  constexpr int NC = EXT ? 3 : 2;
+  T cost = T(0);
+  const int K = rb.K;
+  const TC rj = sizeof(TC) == 8 ? (TC)rb.rd[j] : (TC)rb.r[j];
+  const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
+  const TC sqc = (TC)w.sq_coll;
+  const TC aj = sb[j][0], bj = sb[j][1], Lj = sb[j][2], sj = aj * aj + bj * bj;
+  TC midj[3];
+  seg_point(Rb[j], pb[j], aj, bj, Lj, sj, TC(0.5), midj);
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    if (m + 2 > j) continue;
+    const TC am = sb[m][0], bm = sb[m][1], Lm = sb[m][2], sm = am * am + bm * bm;
+    const TC rm = sizeof(TC) == 8 ? (TC)rb.rd[m] : (TC)rb.r[m];
+    const TC reach = rj + rm + marg;
+    {
+      TC midm[3];
+      seg_point(Rb[m], pb[m], am, bm, Lm, sm, TC(0.5), midm);
+      const TC e0 = midj[0] - midm[0], e1 = midj[1] - midm[1], e2 = midj[2] - midm[2];
+      const TC lim = (TC(0.5) * (Lj + Lm) + reach) * TC(1.0001);
+      if (!(e0 * e0 + e1 * e1 + e2 * e2 < lim * lim)) continue;
+    }
+    for (int l = 1; l <= K; ++l) {
+      const TC sq = TC(l) / TC(K);
+      ArcCoef<TC> cq = arc_coef<TC, GRAD>(sq * sq * sj);
+      const TC qa = sq * aj, qb = sq * bj, qL = sq * Lj;
+      TC dq[3] = {qL * cq.A * qa, qL * cq.A * qb, qL * cq.B}, q[3];
+      mv3(Rb[j], dq, q);
+      q[0] += pb[j][0];
+      q[1] += pb[j][1];
+      q[2] += pb[j][2];
+      for (int k = 1; k <= K; ++k) {
+        const TC sp = TC(k) / TC(K);
+        ArcCoef<TC> cp = arc_coef<TC, GRAD>(sp * sp * sm);
+        const TC pa = sp * am, pbb = sp * bm, pL = sp * Lm;
+        TC dp[3] = {pL * cp.A * pa, pL * cp.A * pbb, pL * cp.B}, pt[3];
+        mv3(Rb[m], dp, pt);
+        pt[0] += pb[m][0];
+        pt[1] += pb[m][1];
+        pt[2] += pb[m][2];
+        const TC d0 = q[0] - pt[0], d1 = q[1] - pt[1], d2 = q[2] - pt[2];
+        const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const TC viol = reach - dist;
+        if (!(viol > TC(0))) continue;
+        const TC rr = sqc * viol;
+        cost += (T)(TC(0.5) * rr * rr);
+        if (GRAD) {
+          // d(1/2 r^2)/dq = -sq_coll r n, n = (q - p)/|q - p| (+z when coincident); -that on p
+          const TC sc = dist > TC(0) ? -sqc * rr / dist : TC(0);
+          const TC fq[3] = {sc * d0, sc * d1, dist > TC(0) ? sc * d2 : -sqc * rr};
+          TC mq[3], mp[3], qq[3], qp[3];
+          cross3(q, fq, mq);
+          cross3(pt, fq, mp);
+          mtv3(Rb[j], fq, qq);
+          mtv3(Rb[m], fq, qp);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            f.F[j][c] += (T)fq[c];
+            f.Mo[j][c] += (T)mq[c];
+            f.F[m][c] -= (T)fq[c];
+            f.Mo[m][c] -= (T)mp[c];
+          }
+          const TC daq[3] = {qL * (cq.A + TC(2) * qa * qa * cq.Ap), qL * TC(2) * qa * qb * cq.Ap, qL * TC(2) * qa * cq.Bp};
+          const TC dbq[3] = {qL * TC(2) * qa * qb * cq.Ap, qL * (cq.A + TC(2) * qb * qb * cq.Ap), qL * TC(2) * qb * cq.Bp};
+          const TC dap[3] = {pL * (cp.A + TC(2) * pa * pa * cp.Ap), pL * TC(2) * pa * pbb * cp.Ap, pL * TC(2) * pa * cp.Bp};
+          const TC dbp[3] = {pL * TC(2) * pa * pbb * cp.Ap, pL * (cp.A + TC(2) * pbb * pbb * cp.Ap), pL * TC(2) * pbb * cp.Bp};
+          f.gz[NC * j] += (T)(sq * dot3(qq, daq));
+          f.gz[NC * j + 1] += (T)(sq * dot3(qq, dbq));
+          f.gz[NC * m] -= (T)(sp * dot3(qp, dap));
+          f.gz[NC * m + 1] -= (T)(sp * dot3(qp, dbp));
+          if constexpr (EXT) {
+            const TC deq[3] = {sq * cq.A * qa, sq * cq.A * qb, sq * cq.B};
+            const TC dep[3] = {sp * cp.A * pa, sp * cp.A * pbb, sp * cp.B};
+            f.gz[NC * j + 2] += (T)dot3(qq, deq);
+            f.gz[NC * m + 2] -= (T)dot3(qp, dep);
+          }
+        }
+      }
+    }
+  }
+  return cost;
+}
+
+template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T, bool EXT = false, bool SELF = false>
 CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
                        int64_t cs, Fwd<NS, T, EXT>& f, const double* zd = nullptr) {
   constexpr int NC = EXT ? 3 : 2;
   T cost = T(0);
   TC Rc[9], pc[3];
+  // self contact: base frame, bending and length of every segment, for the points
+  // of segments two or more behind the current one
+  TC Rb[SELF ? NS : 1][9], pb[SELF ? NS : 1][3], sb[SELF ? NS : 1][3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? TC(1) : TC(0);
   pc[0] = pc[1] = pc[2] = TC(0);
@@ -855,6 +953,16 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
     if (GRAD) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) f.F[i][c] = f.Mo[i][c] = T(0);
+    }
+    if constexpr (SELF) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rb[i][k] = Rc[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pb[i][k] = pc[k];
+      sb[i][0] = ac;
+      sb[i][1] = bc;
+      sb[i][2] = Lc;
+      cost += self_contact<NS, T, GRAD, TC, EXT>(rb, w, i, Rb, pb, sb, f);
     }
     // backbone points of this segment against every sphere (eq. 10).  Every point
     // lies within L_i / 2 of the arc midpoint (arc length bounds the chord), so a
@@ -1185,7 +1293,7 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
 // tip position and its Jacobian.  Pose rows against Tt only if pose.  TC is the
 // chain type (FP64 when spheres are present, as in config_forward).
-template <int NS, typename T, typename TC, typename TS = T, bool EXT = false>
+template <int NS, typename T, typename TC, typename TS = T, bool EXT = false, bool SELF = false>
 CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
                         int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[(EXT ? 3 : 2) * NS], bool pose = true) {
   constexpr int NC = EXT ? 3 : 2, NZ = NC * NS, NP = NZ * (NZ + 1) / 2;
@@ -1199,6 +1307,7 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
   for (int k = 0; k < 9; ++k) Rc[k] = (k % 4 == 0) ? TC(1) : TC(0);
   pc[0] = pc[1] = pc[2] = TC(0);
   T W[NZ][3], Pd[NZ][3], pe[NS][3];
+  TC Rb[SELF ? NS : 1][9], pbs[SELF ? NS : 1][3];  // base frames (self contact)
   const int K = rb.K;
   const T slack = sizeof(T) < sizeof(TC) ? T(1.0001) : T(1);
 #pragma unroll
@@ -1207,6 +1316,114 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
     TC Lc = sizeof(TC) == 8 ? (TC)rb.Ld[i] : (TC)rb.L[i];
     if constexpr (EXT) Lc += (TC)z[NC * i + 2];
     const TC s = ac * ac + bc * bc;
+    if constexpr (SELF) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rb[i][k] = Rc[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pbs[i][k] = pc[k];
+      // self-contact rows (eq. 10): points q of this segment against points p of every
+      // segment m <= i - 2; both move rigidly with the segments before m, so only the
+      // columns of segments m..i enter the row
+#pragma unroll
+      for (int m = 0; m < NS; ++m) {
+        if (m + 2 > i) continue;
+        const TC am = (TC)z[NC * m], bm = (TC)z[NC * m + 1], sm = am * am + bm * bm;
+        TC Lm = sizeof(TC) == 8 ? (TC)rb.Ld[m] : (TC)rb.L[m];
+        if constexpr (EXT) Lm += (TC)z[NC * m + 2];
+        const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
+        const TC rm = sizeof(TC) == 8 ? (TC)rb.rd[m] : (TC)rb.r[m];
+        const TC reach = ri + rm + (sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin);
+        {
+          TC mi[3], mm[3];
+          seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), mi);
+          seg_point(Rb[m], pbs[m], am, bm, Lm, sm, TC(0.5), mm);
+          const TC e0 = mi[0] - mm[0], e1 = mi[1] - mm[1], e2 = mi[2] - mm[2];
+          const TC lim = (TC(0.5) * (Lc + Lm) + reach) * TC(1.0001);
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < lim * lim)) continue;
+        }
+        for (int l = 1; l <= K; ++l) {
+          const TC sq = TC(l) / TC(K);
+          ArcCoef<TC> cq = arc_coef<TC, true>(sq * sq * s);
+          const TC qa = sq * ac, qb = sq * bc, qL = sq * Lc;
+          TC dq[3] = {qL * cq.A * qa, qL * cq.A * qb, qL * cq.B}, q[3];
+          mv3(Rc, dq, q);
+          q[0] += pc[0];
+          q[1] += pc[1];
+          q[2] += pc[2];
+          for (int k = 1; k <= K; ++k) {
+            const TC sp = TC(k) / TC(K);
+            ArcCoef<TC> cp = arc_coef<TC, true>(sp * sp * sm);
+            const TC pa = sp * am, pbb = sp * bm, pL = sp * Lm;
+            TC dp[3] = {pL * cp.A * pa, pL * cp.A * pbb, pL * cp.B}, pt[3];
+            mv3(Rb[m], dp, pt);
+            pt[0] += pbs[m][0];
+            pt[1] += pbs[m][1];
+            pt[2] += pbs[m][2];
+            const TC d0 = q[0] - pt[0], d1 = q[1] - pt[1], d2 = q[2] - pt[2];
+            const TC dist = tsqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            const TC viol = reach - dist;
+            if (!(viol > TC(0))) continue;
+            const T rr = (T)((TC)w.sq_coll * viol);
+            TC nv[3];
+            if (dist > TC(0)) {
+              const TC id = TC(1) / dist;
+              nv[0] = d0 * id;
+              nv[1] = d1 * id;
+              nv[2] = d2 * id;
+            } else {
+              nv[0] = nv[1] = TC(0);
+              nv[2] = TC(1);
+            }
+            const T nf[3] = {(T)nv[0], (T)nv[1], (T)nv[2]}, qf[3] = {(T)q[0], (T)q[1], (T)q[2]};
+            T row[NZ];
+#pragma unroll
+            for (int c = 0; c < NZ; ++c) row[c] = T(0);
+            // segments m .. i-1: q moves rigidly with them (q distal to their ends)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) {
+              if (c >= m && c < i) {
+                T xm[3] = {qf[0] - pe[c][0], qf[1] - pe[c][1], qf[2] - pe[c][2]}, c3[3];
+                cross3(xm, nf, c3);
+#pragma unroll
+                for (int e = 0; e < NC; ++e)
+                  row[NC * c + e] = -w.sq_coll * (dot3(W[NC * c + e], c3) + dot3(Pd[NC * c + e], nf));
+              }
+            }
+            // own arcs: q within segment i (+), p within segment m (-)
+            {
+              TC qq[3], qp[3];
+              mtv3(Rc, nv, qq);
+              mtv3(Rb[m], nv, qp);
+              const TC daq[3] = {qL * (cq.A + TC(2) * qa * qa * cq.Ap), qL * TC(2) * qa * qb * cq.Ap, qL * TC(2) * qa * cq.Bp};
+              const TC dbq[3] = {qL * TC(2) * qa * qb * cq.Ap, qL * (cq.A + TC(2) * qb * qb * cq.Ap), qL * TC(2) * qb * cq.Bp};
+              const TC dap[3] = {pL * (cp.A + TC(2) * pa * pa * cp.Ap), pL * TC(2) * pa * pbb * cp.Ap, pL * TC(2) * pa * cp.Bp};
+              const TC dbp[3] = {pL * TC(2) * pa * pbb * cp.Ap, pL * (cp.A + TC(2) * pbb * pbb * cp.Ap), pL * TC(2) * pbb * cp.Bp};
+              const TC sqc = (TC)w.sq_coll;
+              row[NC * i] = (T)(-sqc * sq * dot3(qq, daq));
+              row[NC * i + 1] = (T)(-sqc * sq * dot3(qq, dbq));
+              row[NC * m] += (T)(sqc * sp * dot3(qp, dap));
+              row[NC * m + 1] += (T)(sqc * sp * dot3(qp, dbp));
+              if constexpr (EXT) {
+                const TC deq[3] = {sq * cq.A * qa, sq * cq.A * qb, sq * cq.B};
+                const TC dep[3] = {sp * cp.A * pa, sp * cp.A * pbb, sp * cp.B};
+                row[NC * i + 2] = (T)(-sqc * dot3(qq, deq));
+                row[NC * m + 2] += (T)(sqc * dot3(qp, dep));
+              }
+            }
+            cost += T(0.5) * rr * rr;
+#pragma unroll
+            for (int k1 = 0; k1 < NZ; ++k1) {
+              if (k1 >= NC * m && k1 <= NC * i + NC - 1) {
+                g[k1] += row[k1] * rr;
+#pragma unroll
+                for (int k2 = 0; k2 <= k1; ++k2)
+                  if (k2 >= NC * m) Hp[tri(k1, k2)] += row[k1] * row[k2];
+              }
+            }
+          }
+        }
+      }
+    }
     if (M > 0) {
       // clearance rows, with the segment-level sphere culling of config_forward
       const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
@@ -1380,25 +1597,25 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
 // Penalised cost of one configuration against a target pose (eq. 8-10, 17):
 // pose, bounds and clearance against M spheres (sphere m, component c at
 // sph[m * ms + c * cs], stored as TS).
-template <int NS, typename T, typename TS, bool EXT = false>
+template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false>
 CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z, const TS* sph, int M, int64_t ms,
                  int64_t cs) {
   Fwd<NS, T, EXT> f;
-  T c = config_forward<NS, T, false, T, TS, EXT>(rb, w, z, sph, M, ms, cs, f);
+  T c = config_forward<NS, T, false, T, TS, EXT, SELF>(rb, w, z, sph, M, ms, cs, f);
   T ft[3], tq[3];
   return c + pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
 }
 
 // lm_ik with clearance rows: the same iteration, the generic per-configuration
 // normal equations and cost.
-template <int NS, typename T, typename TS, bool EXT = false>
+template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false>
 CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
                   bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs) {
   constexpr int NZ = (EXT ? 3 : 2) * NS;
   constexpr int NP = NZ * (NZ + 1) / 2;
   for (int it = 0; it < iters; ++it) {
     T Hp[NP], g[NZ], dl[NZ], ptip[3], Jp[3][NZ];
-    const T c0 = local_normal_eq<NS, T, T, TS, EXT>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
+    const T c0 = local_normal_eq<NS, T, T, TS, EXT, SELF>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
     if (!tfinite(c0)) {
       failed = true;
       break;
@@ -1423,7 +1640,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
     for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
       for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
-      const T c = cfg_cost<NS, T, TS, EXT>(rb, w, Tt, zt, sph, M, ms, cs);
+      const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
       ++trials;
       if (c <= c0 + T(1e-4) * alpha * gd) {
         acc = tr;
@@ -1446,7 +1663,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
 // its segment's radius (clearance < 0, margin 0); spheres are FP64, sphere m
 // component c at sph[c * ld + m].  A sphere whose distance to a segment's arc
 // midpoint exceeds L_i / 2 + R + r_i cannot touch the segment.
-template <int NS, typename T, bool EXT = false>
+template <int NS, typename T, bool EXT = false, bool SELF = false>
 CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M, int64_t ld) {
   constexpr int NC = EXT ? 3 : 2;
   T Rp[9], pp[3];
@@ -1454,10 +1671,33 @@ CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M,
   for (int k = 0; k < 9; ++k) Rp[k] = (k % 4 == 0) ? T(1) : T(0);
   pp[0] = pp[1] = pp[2] = T(0);
   bool hit = false;
+  T Rb[SELF ? NS : 1][9], pb[SELF ? NS : 1][3];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const T a = z[NC * i], b = z[NC * i + 1], s = a * a + b * b;
     const T Li = seg_len<EXT>(rb, z, i), ri = rb.r[i];
+    if constexpr (SELF) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rb[i][k] = Rp[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pb[i][k] = pp[k];
+      // points of segment i against points of every segment m <= i - 2 (margin 0)
+#pragma unroll
+      for (int m = 0; m < NS; ++m) {
+        if (m + 2 > i || hit) continue;
+        const T am = z[NC * m], bm = z[NC * m + 1], sm = am * am + bm * bm, Lm = seg_len<EXT>(rb, z, m);
+        for (int k = 1; k <= rb.K && !hit; ++k) {
+          T q[3];
+          seg_point(Rp, pp, a, b, Li, s, T(k) / T(rb.K), q);
+          for (int l = 1; l <= rb.K; ++l) {
+            T pm[3];
+            seg_point(Rb[m], pb[m], am, bm, Lm, sm, T(l) / T(rb.K), pm);
+            const T d0 = q[0] - pm[0], d1 = q[1] - pm[1], d2 = q[2] - pm[2];
+            if (tsqrt(d0 * d0 + d1 * d1 + d2 * d2) - ri - rb.r[m] < T(0)) hit = true;
+          }
+        }
+      }
+    }
     T xm[3];
     seg_point(Rp, pp, a, b, Li, s, T(0.5), xm);
     for (int m = 0; m < M && !hit; ++m) {

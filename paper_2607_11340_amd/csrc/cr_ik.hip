@@ -11,11 +11,24 @@
 //
 // All per-seed state stays in VGPRs for the whole iteration loop; HBM sees the
 // seeds once and the per-seed summaries once.
-#include <float.h>
-
-#include "cr_internal.h"
+#include "cr_ik_gen.h"
 
 namespace crk {
+
+CR_IK_GEN_EXTERN(true, false, 1)
+CR_IK_GEN_EXTERN(true, false, 2)
+CR_IK_GEN_EXTERN(true, false, 3)
+CR_IK_GEN_EXTERN(true, false, 4)
+CR_IK_GEN_EXTERN(true, false, 5)
+CR_IK_GEN_EXTERN(true, false, 6)
+CR_IK_GEN_EXTERN(false, true, 3)
+CR_IK_GEN_EXTERN(true, true, 3)
+CR_IK_GEN_EXTERN(false, true, 4)
+CR_IK_GEN_EXTERN(true, true, 4)
+CR_IK_GEN_EXTERN(false, true, 5)
+CR_IK_GEN_EXTERN(true, true, 5)
+CR_IK_GEN_EXTERN(false, true, 6)
+CR_IK_GEN_EXTERN(true, true, 6)
 
 // OCC: the minimum waves per SIMD the register allocation must allow (1 = the
 // compiler's own choice); the autotuner picks among the compiled targets.
@@ -49,61 +62,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
   for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
   e_out[b] = e;
   pen_out[b] = T(0);
-  cost_out[b] = c;
-  failed_out[b] = failed ? 1 : 0;
-  trials_out[b] = trials;
-}
-
-// Spheres of a solve: sph[c * ld + m] (double), problem p owns columns
-// p * M .. p * M + M - 1 when per_problem.
-struct SphArgs {
-  const double* sph;
-  int64_t ld;
-  int M, per_problem;
-};
-
-// Stage 1 with clearance rows (eq. 10): one lane per seed as k_ik_stage1, the
-// generic per-configuration normal equations; spheres read from HBM (every lane
-// of a wave reads the same sphere: one broadcast load).  Also the stage 1 of
-// extensible robots (EXT: three coordinates a, b, e per segment), with or
-// without spheres (sa.M may be 0).
-template <int NS, typename T, bool EXT = false>
-__global__ void __launch_bounds__(256)
-    k_ik_stage1_sph(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
-                    const double* __restrict__ useed, int iters, T lam0, SphArgs sa, T* __restrict__ z_out,
-                    T* __restrict__ e_out, T* __restrict__ pen_out, T* __restrict__ cost_out,
-                    int32_t* __restrict__ failed_out, int32_t* __restrict__ trials_out) {
-  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
-  const int64_t B = P * (int64_t)S;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const int64_t p = b / S;
-  const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
-  T tt[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) tt[c] = (T)Tt[c * P + p];
-  T z[NZ];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const T u0 = (T)useed[(3 * i) * B + b], u1 = (T)useed[(3 * i + 1) * B + b], u2 = (T)useed[(3 * i + 2) * B + b];
-    u_to_ab(u0, u1, u2, rb.r[i], &z[NC * i], &z[NC * i + 1]);
-    if constexpr (EXT) z[NC * i + 2] = (u0 + u1 + u2) * T(1.0 / 3.0);
-  }
-  T lam = lam0;
-  bool failed = false;
-  int trials = 0;
-  lm_cfg<NS, T, double, EXT>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
-  T e;
-  ik_cost<NS, T, EXT>(rb, w, tt, z, &e);
-  const T c = cfg_cost<NS, T, double, EXT>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
-  WeightsT<T> wc = w;  // clearance part alone (SelectTop tie-break)
-  wc.w_pos = wc.w_rot = wc.sq_lim = wc.sq_curv = T(0);
-  const T pen = sa.M > 0 ? cfg_cost<NS, T, double, EXT>(rb, wc, tt, z, sp, sa.M, 1, sa.ld) : T(0);
-  if (!tfinite(c) || !tfinite(e)) failed = true;
-#pragma unroll
-  for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
-  e_out[b] = e;
-  pen_out[b] = pen;
   cost_out[b] = c;
   failed_out[b] = failed ? 1 : 0;
   trials_out[b] = trials;
@@ -326,28 +284,41 @@ __global__ void __launch_bounds__(256)
   if (lane < n_final) idx_out[(int64_t)lane * P + p] = lane < nk ? kept[lane] : -1;
 }
 
-// ---------------------------------------------------------------------------
-// Stage 2: FP64 refinement of the kept candidates, lambda restarted at lambda0.
-// ---------------------------------------------------------------------------
+// Stage 2 for robots without clearance rows, G lanes per kept candidate (G = 1, 2
+// or 4).  One lane per candidate leaves SIMDs idle when the candidates are few
+// (32,768 candidates are 512 waves for 1024 SIMDs), and a wave with half its lanes
+// active issues no faster than a full one.  Here the G lanes of a group carry the
+// same candidate: each forms the same normal equations and step (identical inputs
+// and instructions, so identical values), and the line search evaluates G step
+// lengths at once, lane q taking alpha = 2^-(G r + q) in round r; the accepted
+// step is the first that passes in the sequential order, found with a ballot over
+// the group.  Decisions and iterates are those of lm_ik.
+// lanes of one wave per SIMD over the whole chip: 256 CUs x 4 SIMDs x 64 lanes
+constexpr int64_t kStage2Lanes = 256 * 4 * 64;
 
-template <int NS, typename T1, bool SPH, bool EXT = false>
+template <int NS, typename T1, int G>
 __global__ void __launch_bounds__(256)
-    k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
-                const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
-                int iters, double lam0, SphArgs sa, double* __restrict__ z2, double* __restrict__ cost2,
-                int32_t* __restrict__ failed2) {
-  constexpr int NZ = (EXT ? 3 : 2) * NS;
+    k_ik_stage2_grp(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
+                    const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
+                    int iters, double lam0, double* __restrict__ z2, double* __restrict__ cost2,
+                    int32_t* __restrict__ failed2) {
+  static_assert(G == 1 || G == 2 || G == 4, "group of 1, 2 or 4 lanes");
+  constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
   const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B2) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = t / G;
+  const int q = (int)(t % G);
+  if (b >= B2) return;  // the whole group leaves together
   const int64_t p = b / nf;
   const int k = (int)(b % nf);
   const int s = sel[k * P + p];
   if (s < 0) {
+    if (q == 0) {
 #pragma unroll
-    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
-    cost2[b] = __builtin_nan("");
-    failed2[b] = 1;
+      for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
+      cost2[b] = __builtin_nan("");
+      failed2[b] = 1;
+    }
     return;
   }
   double tt[12];
@@ -358,101 +329,62 @@ __global__ void __launch_bounds__(256)
   for (int m = 0; m < NZ; ++m) z[m] = (double)z1[m * B1 + p * S + s];
   double lam = lam0;
   bool failed = false;
-  int trials = 0;
-  double c;
-  if (SPH || EXT) {
-    const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
-    lm_cfg<NS, double, double, EXT>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
-    c = cfg_cost<NS, double, double, EXT>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
-  } else {
-    lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
-    c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
+  const int lane = threadIdx.x & 63, base = lane & ~(G - 1);
+  const int rounds = (o.ls_max + G - 1) / G;
+  for (int it = 0; it < iters; ++it) {
+    double Hp[NP], g[NZ], dl[NZ];
+    const double c0 = ik_normal_eq<NS>(rb, w, tt, z, Hp, g);
+    if (!tfinite(c0)) {
+      failed = true;
+      break;
+    }
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      const double hj = Hp[tri(j, j)];
+      Hp[tri(j, j)] = hj + lam * (hj > 1e-12 ? hj : 1e-12);
+      dl[j] = -g[j];
+    }
+    if (!chol_solve<NZ>(Hp, dl)) {
+      if (!(lam < o.lam_max)) break;
+      lam = lam * 10.0 < o.lam_max ? lam * 10.0 : o.lam_max;
+      continue;
+    }
+    double gd = 0.0;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) gd += g[j] * dl[j];
+    int acc = -1;
+    for (int r = 0; r < rounds && acc < 0; ++r) {
+      const int tr = G * r + q;
+      bool ok = false;
+      if (tr < o.ls_max) {
+        const double alpha = ldexp(1.0, -tr);
+        double zt[NZ];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
+        const double c = ik_cost<NS>(rb, w, tt, zt, (double*)nullptr);
+        ok = c <= c0 + 1e-4 * alpha * gd;
+      }
+      const unsigned grp = (unsigned)((__ballot(ok) >> base) & ((1ull << G) - 1));
+      if (grp) acc = G * r + __builtin_ctz(grp);
+    }
+    if (acc >= 0) {
+      const double alpha = ldexp(1.0, -acc);
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) z[j] = z[j] + alpha * dl[j];
+      if (acc == 0) lam = lam / 10.0 > o.lam_min ? lam / 10.0 : o.lam_min;
+    } else {
+      if (!(lam < o.lam_max)) break;
+      lam = lam * 10.0 < o.lam_max ? lam * 10.0 : o.lam_max;
+    }
   }
+  const double c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
   if (!tfinite(c)) failed = true;
+  if (q == 0) {
 #pragma unroll
-  for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
-  cost2[b] = c;
-  failed2[b] = failed ? 1 : 0;
-}
-
-
-// ---------------------------------------------------------------------------
-// Final argmin over candidates and FP64 assessment of the winner.
-// Candidates are either the nf stage-2 slots (sel != NULL: seed index sel[k])
-// or all S stage-1 seeds (seed index k).
-// ---------------------------------------------------------------------------
-
-template <int NS, typename TC, bool EXT = false>
-__global__ void __launch_bounds__(256)
-    k_ik_finalize(RobotT<double> rb, int64_t P, int nc, const int32_t* __restrict__ sel,
-                  const TC* __restrict__ zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
-                  const double* __restrict__ Tt, SphArgs sa, double* __restrict__ u_out, double* __restrict__ err_out,
-                  int32_t* __restrict__ status_out) {
-  constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const int64_t Bc = P * (int64_t)nc;
-  int best = -1, best_seed = 0;
-  double best_cost = 0.0;
-  for (int k = 0; k < nc; ++k) {
-    const int64_t col = p * nc + k;
-    int seed = sel ? sel[k * P + p] : k;
-    double c = (double)costc[col];
-    if (seed < 0 || failedc[col] || !tfinite(c)) continue;
-    if (best < 0 || c < best_cost || (c == best_cost && seed < best_seed)) {
-      best = k;
-      best_cost = c;
-      best_seed = seed;
-    }
+    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
+    cost2[b] = c;
+    failed2[b] = failed ? 1 : 0;
   }
-  if (best < 0) {
-    const double nan = __builtin_nan("");
-    for (int m = 0; m < 3 * NS; ++m) u_out[m * P + p] = nan;
-    err_out[p] = nan;
-    err_out[P + p] = nan;
-    status_out[p] = CR_NONFINITE;
-    return;
-  }
-  double z[NZ];
-#pragma unroll
-  for (int m = 0; m < NZ; ++m) z[m] = (double)zc[m * Bc + p * nc + best];
-  double tt[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) tt[c] = Tt[c * P + p];
-  double Rc[9], pc[3];
-  fk_tip<NS, double, EXT>(rb, z, Rc, pc);
-  double dp[3] = {tt[3] - pc[0], tt[7] - pc[1], tt[11] - pc[2]};
-  double pos = sqrt(dot3(dp, dp));
-  double Re[9], te[3];
-  relative_pose(Rc, pc, tt, Re, te);
-  double v[3] = {0.5 * (Re[7] - Re[5]), 0.5 * (Re[2] - Re[6]), 0.5 * (Re[3] - Re[1])};
-  double rot = atan2(sqrt(dot3(v, v)), 0.5 * (Re[0] + Re[4] + Re[8] - 1.0));
-  double viol = -DBL_MAX, thx = -DBL_MAX;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    double u[3];
-    ab_to_u(z[NC * i], z[NC * i + 1], rb.r[i], u);
-    // extensible: the output carries the extension as the common mode; the tendon
-    // bound applies to the bending part, the length to its interval
-    const double e = EXT ? z[NC * i + 2] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      u_out[(3 * i + j) * P + p] = u[j] + e;
-      viol = fmax(viol, fabs(u[j]) - rb.umax[i]);
-    }
-    if (EXT) viol = fmax(viol, fabs((rb.Ld[i] + e) - rb.Lmidd[i]) - rb.Lhalfd[i]);
-    thx = fmax(thx, sqrt(z[NC * i] * z[NC * i] + z[NC * i + 1] * z[NC * i + 1]) - rb.theta_max);
-  }
-  int32_t st = 0;
-  if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if (sa.M > 0 &&
-      penetrates<NS, double, EXT>(rb, z, sa.sph + (sa.per_problem ? p * sa.M : 0), sa.M, sa.ld))
-    st |= CR_COLLISION;
-  if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
-  if (st == 0) st = CR_SOLVED;
-  err_out[p] = pos;
-  err_out[P + p] = rot;
-  status_out[p] = st;
 }
 
 // ---------------------------------------------------------------------------
@@ -678,60 +610,6 @@ size_t ik_workspace_layout(const cr_robot& rb, int64_t P, int32_t S, const cr_op
   return off;
 }
 
-static int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
-
-// Algorithm 1 for robots with extensible segments: three coordinates per segment
-// (bending a, b and extension e); every stage runs the generic per-configuration
-// path (clearance rows when spheres are given).
-template <int NS, typename T>
-static cr_status run_ik_ext(const cr_robot& rb0, const SphArgs& sa, int64_t P, const double* Tt, int32_t S,
-                            const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out,
-                            double* err_out, int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
-  RobotT<T> rb = robot_to<T>(rb0);
-  WeightsT<T> w = weights_to<T>(w0);
-  LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
-  const int64_t B = P * (int64_t)S;
-  const bool timed = timer_on();
-  if (timed) timer_begin_call(st);
-  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, true>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
-                     Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
-                     ws.failed1, ws.trials1);
-  cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_sph");
-  if (rc != CR_OK) return rc;
-  if (timed) timer_mark(0, st);
-  RobotT<double> rbd = robot_to<double>(rb0);
-  if (o.n_final > 0) {
-    rc = launch_select(P, S, 3 * NS, ws.z1, ws.e1, ws.pen1, ws.failed1, o.n_final, o.dup_eps, ws.sel,
-                       sizeof(T) == 8 ? CR_F64 : CR_F32, st);
-    if (rc != CR_OK) return rc;
-    if (timed) timer_mark(1, st);
-    WeightsT<double> wd = weights_to<double>(w0);
-    LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
-    const int64_t B2 = P * (int64_t)o.n_final;
-    hipLaunchKernelGGL((k_ik_stage2<NS, T, true, true>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
-                       (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, ws.cost2,
-                       ws.failed2);
-    rc = check_hip(hipGetLastError(), "k_ik_stage2");
-    if (rc != CR_OK) return rc;
-    if (timed) timer_mark(2, st);
-    hipLaunchKernelGGL((k_ik_finalize<NS, double, true>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
-                       (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, sa, u_out, err_out, status_out);
-  } else {
-    if (timed) {
-      timer_mark(1, st);
-      timer_mark(2, st);
-    }
-    hipLaunchKernelGGL((k_ik_finalize<NS, T, true>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
-                       (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, sa, u_out,
-                       err_out, status_out);
-  }
-  rc = check_hip(hipGetLastError(), "k_ik_finalize");
-  if (timed) {
-    timer_mark(3, st);
-    timer_end_call();
-  }
-  return rc;
-}
 
 template <int NS, typename T>
 static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, const double* Tt, int32_t S,
@@ -739,7 +617,14 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
                         int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
   const SphArgs sa{sp ? (const double*)sp->sph : nullptr, sp ? sp->ld : 0, sp ? sp->n_sph : 0,
                    sp ? sp->per_problem : 0};
-  if (rb0.extensible) return run_ik_ext<NS, T>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
+  if constexpr (NS >= 3) {  // fewer than three segments have no non-adjacent pair
+    if (rb0.self_collision && rb0.extensible)
+      return run_ik_gen<NS, T, true, true>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
+    if (rb0.self_collision)
+      return run_ik_gen<NS, T, false, true>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
+  }
+  if (rb0.extensible)
+    return run_ik_gen<NS, T, true, false>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
   RobotT<T> rb = robot_to<T>(rb0);
   WeightsT<T> w = weights_to<T>(w0);
   LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
@@ -791,10 +676,19 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
       hipLaunchKernelGGL((k_ik_stage2<NS, T, true>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
                          (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
                          ws.cost2, ws.failed2);
-    else
-      hipLaunchKernelGGL((k_ik_stage2<NS, T, false>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
-                         (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
-                         ws.cost2, ws.failed2);
+    else {
+      // lanes per candidate: fill the 1024 SIMDs with one wave each where the
+      // candidates allow, at most four
+      const int g = B2 * 4 <= kStage2Lanes ? 4 : (B2 * 2 <= kStage2Lanes ? 2 : 1);
+#define CR_S2G(G)                                                                                                \
+  hipLaunchKernelGGL((k_ik_stage2_grp<NS, T, G>), dim3(blocks_for(G * B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, \
+                     (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, ws.z2, ws.cost2,   \
+                     ws.failed2)
+      if (g == 4) CR_S2G(4);
+      else if (g == 2) CR_S2G(2);
+      else CR_S2G(1);
+#undef CR_S2G
+    }
     rc = check_hip(hipGetLastError(), "k_ik_stage2");
     if (rc != CR_OK) return rc;
     if (timed) timer_mark(2, st);

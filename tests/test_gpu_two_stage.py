@@ -76,6 +76,28 @@ def test_ik_two_stage_fp64_matches_oracle_solve(oracle, cr, n, P, S, nf, k1, k2)
     assert refined == P
 
 
+@pytest.mark.parametrize("P,group", [(2050, 2), (4100, 1)])
+def test_ik_two_stage_fp64_lane_groups_match_oracle(oracle, cr, P, group):
+    """Stage 2 of robots without clearance rows runs G lanes per kept candidate, G
+    set by the candidate count (4 up to 16,384, 2 up to 32,768, else 1; the small
+    cases above take 4); the lanes evaluate G line-search step lengths at once and
+    must take the sequential search's decisions.  Launches of the two larger
+    shapes, checked against the oracle's two-stage driver on sampled problems."""
+    print(f"ik two-stage fp64 lane group {group}: P={P}", flush=True)
+    spec = I.WORKLOADS["ik_batched_3seg"]
+    n, b, S, nf = 3, spec["b"], 3, 8
+    rng = np.random.default_rng(560 + group)
+    ro = oracle.Robot(L=spec["L"], r=spec["r"], u_max=[b] * n)
+    u_true = I.uniform_actuation(rng, n, b, P)
+    _, fr = oracle.fk(ro, u_true)
+    seeds = I.uniform_actuation(rng, n, b, P * S).reshape(P, S, n, 3)
+    # nf > S: every seed is kept, the surplus slots are empty (-1)
+    u, err, st = _ik_solve(cr, ro, fr[:, -1], seeds, cr.Opts(n_final=nf, k_init=3, k_final=6))
+    opts_o = oracle.Opts(n_final=nf, k_init=3, k_final=6)
+    for p in rng.choice(P, size=12, replace=False):
+        _check(oracle, ro, {}, oracle.Problem("ik", fr[p, -1]), seeds[p], opts_o, u[p], err[p], st[p], b, p)
+
+
 def test_ik_spheres_two_stage_fp64_matches_oracle_solve(oracle, cr):
     """Collision-aware IK: seeds next to spheres, so SelectTop's collision-penalty
     tie rule and the clearance rows of both stages take part."""
