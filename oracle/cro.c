@@ -1007,6 +1007,39 @@ void cro_select_top(int S, int nz, const double* z, const double* e, const doubl
   free(ord);
 }
 
+/* Smallest clearance of configuration u[3n] (eq. 10 with margin 0): over every
+ * backbone point and sphere |p - c| - R - r_i and, with self contact, over every
+ * pair of points of non-adjacent segments |p - q| - r_i - r_j.  INFINITY when
+ * there is nothing to clear. */
+static double contact_gap(const cro_robot* rb, const double* sph, int n_sph, const double* u) {
+  int n = rb->n_seg, K = rb->pts_per_seg;
+  double gmin = INFINITY;
+  if ((n_sph <= 0 && !rb->self_collision) || K <= 0) return gmin;
+  double* P = (double*)malloc(sizeof(double) * 3 * (size_t)(n * K));
+  double arc[3 * CRO_MAX_SEG];
+  cro_fk(rb, u, arc, NULL, P);
+  for (int i = 0; i < n; i++)
+    for (int k = 0; k < K; k++)
+      for (int m = 0; m < n_sph; m++) {
+        const double* S = sph + 4 * m;
+        const double* q = P + 3 * (i * K + k);
+        double dx = q[0] - S[0], dy = q[1] - S[1], dzz = q[2] - S[2];
+        gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - S[3] - rb->r[i]);
+      }
+  /* self contact between non-adjacent segments */
+  for (int i = 0; i < n && rb->self_collision; i++)
+    for (int j = i + 2; j < n; j++)
+      for (int k = 0; k < K; k++)
+        for (int l = 0; l < K; l++) {
+          const double* p = P + 3 * (i * K + k);
+          const double* q = P + 3 * (j * K + l);
+          double dx = q[0] - p[0], dy = q[1] - p[1], dzz = q[2] - p[2];
+          gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - rb->r[i] - rb->r[j]);
+        }
+  free(P);
+  return gmin;
+}
+
 /* Success / status of a solution z (Sec. V-B, with 1 mm / 1 degree thresholds). */
 static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* z, double* err) {
   int n = rb->n_seg, zc = cro_ncoord(rb), nz = zc * n, T = pb->H + 1, K = rb->pts_per_seg;
@@ -1042,30 +1075,7 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
       double th = sqrt(zt[zc * i] * zt[zc * i] + zt[zc * i + 1] * zt[zc * i + 1]);
       thx = fmax(thx, th - rb->theta_max);
     }
-    if ((pb->n_sph > 0 || rb->self_collision) && K > 0) {
-      double* P = (double*)malloc(sizeof(double) * 3 * (size_t)(n * K));
-      double arc[3 * CRO_MAX_SEG];
-      cro_fk(rb, u, arc, NULL, P);
-      for (int i = 0; i < n; i++)
-        for (int k = 0; k < K; k++)
-          for (int m = 0; m < pb->n_sph; m++) {
-            const double* S = pb->sph + 4 * m;
-            const double* q = P + 3 * (i * K + k);
-            double dx = q[0] - S[0], dy = q[1] - S[1], dzz = q[2] - S[2];
-            gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - S[3] - rb->r[i]);
-          }
-      /* self contact between non-adjacent segments */
-      for (int i = 0; i < n && rb->self_collision; i++)
-        for (int j = i + 2; j < n; j++)
-          for (int k = 0; k < K; k++)
-            for (int l = 0; l < K; l++) {
-              const double* p = P + 3 * (i * K + k);
-              const double* q = P + 3 * (j * K + l);
-              double dx = q[0] - p[0], dy = q[1] - p[1], dzz = q[2] - p[2];
-              gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - rb->r[i] - rb->r[j]);
-            }
-      free(P);
-    }
+    gmin = fmin(gmin, contact_gap(rb, pb->sph, pb->n_sph, u));
   }
   err[0] = pos;
   err[1] = rot;
@@ -1224,4 +1234,94 @@ int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, 
   free(lam);
   free(z);
   return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* SampleSeeds (Algorithm 1; Sec. IV-B: seeds inside the bounds, seeds that    */
+/* collide at once are drawn again).                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds; each multiplies words 0 and 2 by the
+ * round multipliers into 128-bit products and mixes the high halves with the
+ * other words and the key, the key advancing by the two Weyl increments
+ * between rounds. */
+void cro_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; round++) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)M0 * c0, p1 = (unsigned __int128)M1 * c2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0, hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* uniform j of the stream of (problem p, seed s, attempt a): word j mod 4 of
+ * Philox4x64-10 at counter (j div 4, a, s, p), its top 53 bits scaled to [0, 1) */
+static double seed_uniform(const uint64_t key[2], int64_t p, int32_t s, int32_t a, int64_t j) {
+  uint64_t ctr[4] = {(uint64_t)(j >> 2), (uint64_t)a, (uint64_t)s, (uint64_t)p}, out[4];
+  cro_philox4x64(ctr, key, out);
+  return (double)(out[j & 3] >> 11) * 0x1.0p-53;
+}
+
+int32_t cro_sample_seed(const cro_robot* rb, const double* sph, int n_sph, const uint64_t key[2], int64_t p,
+                        int32_t s, int32_t max_attempts, double* u) {
+  int n = rb->n_seg;
+  int32_t a = 0;
+  for (;; a++) {
+    int64_t j = 0;
+    for (int i = 0; i < n; i++) {
+      const double b = rb->u_max[i];
+      double ub[3] = {0.0, 0.0, 0.0}, worst = 0.0;
+      int ok = 0;
+      for (int tries = 0; tries < CRO_SEED_TRIPLES && !ok; tries++) {
+        double x[3];
+        for (int k = 0; k < 3; k++) x[k] = b * (2.0 * seed_uniform(key, p, s, a, j++) - 1.0);
+        const double mean = (x[0] + x[1] + x[2]) / 3.0;
+        worst = 0.0;
+        for (int k = 0; k < 3; k++) {
+          ub[k] = x[k] - mean;
+          worst = fmax(worst, fabs(ub[k]));
+        }
+        /* bending angle of the zero-sum part: |(a, b)| of eq. (4) inverted */
+        double pc = 0.0, ps = 0.0;
+        for (int k = 0; k < 3; k++) {
+          pc += ub[k] * cos(alpha_j(k));
+          ps += ub[k] * sin(alpha_j(k));
+        }
+        const double th = sqrt(pc * pc + ps * ps) / (1.5 * rb->r[i]);
+        ok = worst <= b && th <= rb->theta_max;
+      }
+      if (!ok) {
+        /* no triple inside the bounds: the last one scaled onto them */
+        double pc = 0.0, ps = 0.0;
+        for (int k = 0; k < 3; k++) {
+          pc += ub[k] * cos(alpha_j(k));
+          ps += ub[k] * sin(alpha_j(k));
+        }
+        const double th = sqrt(pc * pc + ps * ps) / (1.5 * rb->r[i]);
+        double f = fmin(worst > 0.0 ? b / worst : 1.0, th > 0.0 ? rb->theta_max / th : 1.0);
+        for (int k = 0; k < 3; k++) ub[k] *= f;
+      }
+      /* extensible: the extension drawn within the length bounds of eq. (9) */
+      double e = 0.0;
+      if (rb->extensible)
+        e = (rb->L_min[i] - rb->L[i]) + (rb->L_max[i] - rb->L_min[i]) * seed_uniform(key, p, s, a, j++);
+      for (int k = 0; k < 3; k++) u[3 * i + k] = ub[k] + e;
+    }
+    if (a + 1 >= max_attempts || !(contact_gap(rb, sph, n_sph, u) < 0.0)) break;
+  }
+  return contact_gap(rb, sph, n_sph, u) < 0.0 ? -(a + 1) : a + 1;
 }

@@ -144,6 +144,27 @@ int cro_solve(const cro_robot* rb, const cro_weights* w, const cro_problem* pb,
               const cro_opts* o, int S, const double* u_seed, double* u_out,
               double* err_out, int32_t* status, int32_t* best_idx, double* best_cost);
 
+/* Philox4x64-10 counter-based generator (Salmon et al., SC 2011): out = the
+ * four 64-bit words for counter ctr under key. */
+void cro_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Triples drawn per segment before the bound is enforced by scaling. */
+#define CRO_SEED_TRIPLES 32
+
+/* SampleSeeds of Algorithm 1 for seed s of problem p (Sec. IV-B: inside the
+ * bounds, seeds that collide at once are discarded).  Attempt a = 0, 1, ...
+ * reads the uniform stream U_j = word j mod 4 of Philox4x64-10 at counter
+ * (j div 4, a, s, p) under key, top 53 bits times 2^-53.  Per segment, in
+ * order: triples x = u_max (2 U - 1) minus their mean until the zero-sum triple
+ * has max |x| <= u_max and bending angle <= theta_max (at most CRO_SEED_TRIPLES
+ * triples, else the last one scaled onto the bounds); extensible robots then take
+ * the extension e = L_min - L + (L_max - L_min) U and every tendon adds e.  The
+ * attempt is kept if it clears the spheres and, with self contact, the robot
+ * itself (margin 0), or if it is attempt max_attempts - 1.  u[3n] receives the
+ * seed; returns the number of attempts used, negated if the seed still collides. */
+int32_t cro_sample_seed(const cro_robot* rb, const double* sph, int n_sph, const uint64_t key[2], int64_t p,
+                        int32_t s, int32_t max_attempts, double* u);
+
 #ifdef __cplusplus
 }
 #endif

@@ -170,6 +170,11 @@ def lib():
         L.cro_path_seeds.argtypes = [R, W, P, O, C.c_int, dp, C.c_int, dp]
         L.cro_path_seeds.restype = None
         L.cro_solve.restype = C.c_int
+        u64p = C.POINTER(C.c_uint64)
+        L.cro_philox4x64.argtypes = [u64p, u64p, u64p]
+        L.cro_philox4x64.restype = None
+        L.cro_sample_seed.argtypes = [R, dp, C.c_int, u64p, C.c_int64, C.c_int32, C.c_int32, dp]
+        L.cro_sample_seed.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -362,3 +367,37 @@ def solve(robot: Robot, weights: Weights, prob: Problem, opts: Opts, u_seed):
         raise ValueError("bad solve arguments")
     shape = (robot.n, 3) if prob.kind == "ik" else (T, robot.n, 3)
     return dict(u=u_out.reshape(shape), err=err, status=st.value, best=best.value, cost=bc.value)
+
+
+def philox4x64(ctr, key):
+    """Philox4x64-10 block: four uint64 words for counter ctr[4] under key[2]."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    u64p = C.POINTER(C.c_uint64)
+    lib().cro_philox4x64(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p), out.ctypes.data_as(u64p))
+    return out
+
+
+def sample_seeds(robot: Robot, P: int, S: int, key, max_attempts: int = 8, spheres=None):
+    """SampleSeeds (Algorithm 1) for P problems x S seeds: u [P, S, n, 3] and the
+    attempts per seed [P, S] (negative: still colliding after max_attempts).
+    spheres: None, [M, 4] shared, or [P, M, 4] per problem."""
+    n = robot.n
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    u64p = C.POINTER(C.c_uint64)
+    rc = robot.c()
+    u = np.zeros((P, S, n, 3))
+    tries = np.zeros((P, S), dtype=np.int32)
+    for p in range(P):
+        sp = None if spheres is None else np.asarray(spheres, dtype=np.float64)
+        if sp is not None and sp.ndim == 3:
+            sp = sp[p]
+        M = 0 if sp is None else len(sp)
+        sarr, sptr = _d(sp if M else np.zeros((1, 4)))
+        for s in range(S):
+            out, po = _d(np.zeros(3 * n))
+            tries[p, s] = lib().cro_sample_seed(C.byref(rc), sptr, M, k.ctypes.data_as(u64p), p, s,
+                                                int(max_attempts), po)
+            u[p, s] = out.reshape(n, 3)
+    return u, tries
