@@ -161,7 +161,11 @@ cr_status cr_fk(const cr_robot* robot, int64_t B, const void* u, int64_t ld, voi
  *         because the cost ignores each segment's common mode).
  *   grad_scale [device] [S*P] or NULL: grad of seed p*S + s is multiplied by
  *         grad_scale[p*S + s] (the upstream gradient of a backward pass).
- * All arrays, spheres included, are in `dtype`.  The gradient is formed by an
+ * All arrays, spheres included, are in `dtype`, and so is every step: with
+ * CR_F32 the tendon map, the chained transforms, the backbone points, every
+ * residual (pose, bounds, clearance, smoothness, endpoints) and the adjoint sweep
+ * run in FP32 (a clearance hinge then carries the FP32 error of the point
+ * positions, about 8 n 2^-24 sum(L) metres).  The gradient is formed by an
  * adjoint sweep over recomputed segment transforms (no stored Jacobian).
  * Errors: CR_EINVAL for bad shapes (H != 0 for IK, H < 1 for TRAJ, H > 255,
  * more than 512 spheres). */
@@ -170,10 +174,34 @@ cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* sp
                        const void* task, const void* u, void* cost, void* grad,
                        const void* grad_scale, cr_dtype dtype, hipStream_t stream);
 
+/* SampleSeeds of Algorithm 1 (Sec. IV-B: initial configurations inside the
+ * bounds; those that collide at once are discarded and drawn again), on the
+ * device from a counter-based generator, so seeds need no host transfer.
+ *   u_out [device, double] [3n][S*P], column p*S + s (the u_seed layout of the
+ *         solve calls); attempts_out [device, int32] [S*P] or NULL.
+ * Seed s of problem p reads the uniform stream U_j = word j mod 4 of
+ * Philox4x64-10 (Salmon et al., SC 2011) at counter (j div 4, a, s, p) under key
+ * (key0, key1), top 53 bits times 2^-53, for attempt a = 0, 1, ...: per segment,
+ * triples x = u_max (2 U - 1) minus their mean until the zero-sum triple has
+ * max |x| <= u_max and bending angle <= theta_max (at most 32 triples, else the
+ * last one scaled onto the bounds); extensible robots then take the extension
+ * L_min - L + (L_max - L_min) U, added to all three tendons.  An attempt is kept
+ * if the configuration clears the spheres of problem p (and, with
+ * self_collision, the robot itself) with margin 0 in FP64, or if it is attempt
+ * max_attempts - 1.  attempts_out = attempts used, negated for a seed that still
+ * collides.  A seed depends only on (key, p, s), not on P or S.  Spheres are
+ * double, as for the solve calls.
+ * Errors: CR_EINVAL for bad shapes or max_attempts outside 1..64. */
+cr_status cr_sample_seeds(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t S,
+                          uint64_t key0, uint64_t key1, int32_t max_attempts, double* u_out,
+                          int32_t* attempts_out, hipStream_t stream);
+
 /* Two-stage inverse kinematics, Algorithm 1: stage 1 runs k_init LM iterations
  * on every seed in `dtype`; SelectTop keeps n_final per problem; stage 2 runs
  * k_final LM iterations on those (in FP64 if fp64_refine or dtype is CR_F64);
- * the answer is the argmin of the final cost (ties: lowest seed index).
+ * the answer is the argmin of the final cost (ties: lowest seed index).  Stage 1
+ * runs wholly in `dtype`, clearance and self-contact rows included; with CR_F32,
+ * FP64 arithmetic is confined to stage 2 and to the assessment of the answer.
  *   T_target [device, double] [12][P];  u_seed [device, double] [3n][S*P],
  *   column p*S + s.
  *   u_out    [device, double] [3n][P]   zero-sum tendon displacements of q*
@@ -376,16 +404,21 @@ cr_status cr_timing_read(double* stage_ms, int64_t* n_calls);
  * differ between variants in the last bits; each variant is deterministic, and a
  * cached choice reproduces the tuning call's results exactly.  While enabled, the
  * first FP32 launch of a key (kernel, segments, launch size rounded up to a power
- * of two, device) that is not being captured into a graph times each target once
- * alone on the device (the call first waits for all queued device work, then
- * synchronises on the timing events) and later launches of the key use the
- * fastest.  Disabled (the default), or under capture with no
- * cached choice, the compiler's own target runs.
+ * of two, device) that is not being captured into a graph times each target three
+ * times alone on the device (the call first waits for all queued device work, then
+ * synchronises on the timing events) and later launches of the key use the one
+ * with the shortest time.  Disabled (the default), or under capture with no
+ * cached choice, the compiler's own target runs.  The FP64 IK stage 2 of robots
+ * without clearance rows is tuned the same way over its lanes per kept candidate
+ * (1, 2 or 4: the lanes of a candidate try that many line-search step lengths at
+ * once and take the sequential search's choice, so its results do not depend on
+ * the variant; FP32 and FP64 stage 1 alike); untuned, it takes the width that
+ * gives each of the chip's 1024 SIMDs at most one wave.
  *   cr_autotune_enable(on): switch tuning on or off (the cache is kept).
  *   cr_autotune_clear():    forget every cached choice.
  *   cr_autotune_force(v):   run variant v (0: the compiler's own target, 1 and 2:
- *     the two tighter targets) for every tunable kernel, tuning or not; v < 0
- *     returns to normal operation.
+ *     the two tighter targets; IK stage 2: 2^v lanes per candidate) for every
+ *     tunable kernel, tuning or not; v < 0 returns to normal operation.
  *   cr_autotune_report(buf, cap): text, one line per cached key (chosen target and
  *     the milliseconds of each), written to buf [host] when buf != NULL, truncated
  *     to cap - 1 bytes and NUL-terminated; returns the full length.

@@ -30,7 +30,7 @@ SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
            "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_baseline_traj_workspace",
-           "cr_select_top", "cr_calib_valu",
+           "cr_select_top", "cr_sample_seeds", "cr_calib_valu",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_autotune_enable", "cr_autotune_clear", "cr_autotune_force",
            "cr_autotune_report", "cr_status_string", "cr_last_error")
 
@@ -191,12 +191,13 @@ def _load():
     L.cr_autotune_clear.restype = None
     L.cr_autotune_report.argtypes = [C.c_char_p, i64]
     L.cr_autotune_report.restype = i64
+    L.cr_sample_seeds.argtypes = [R, S, i64, i32, C.c_uint64, C.c_uint64, i32, vp, vp, vp]
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
     for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
                  "cr_baseline_solve_ik", "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_select_top",
-                 "cr_timing_read", "cr_ik_flop_tally", "cr_calib_valu"):
+                 "cr_sample_seeds", "cr_timing_read", "cr_ik_flop_tally", "cr_calib_valu"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -274,6 +275,23 @@ def fk(robot: Robot, u: torch.Tensor, arc=True, frames=True, points=False):
 def ik_workspace_bytes(robot: Robot, P: int, S: int, opts: Opts, dtype) -> int:
     rc, oc = robot.c(), opts.c()
     return int(lib.cr_solve_ik_workspace(C.byref(rc), P, S, C.byref(oc), _dt(dtype)))
+
+
+def sample_seeds(robot: Robot, P: int, S: int, key=(0, 0), max_attempts: int = 8, spheres=None,
+                 device="cuda"):
+    """SampleSeeds of Algorithm 1 on the device (cr_sample_seeds): S seeds for each
+    of P problems inside the bounds, colliding ones drawn again up to max_attempts
+    times.  key: two 64-bit integers; spheres as for solve_ik (float64).  Returns
+    (u_seed [3n, S*P] float64, column p*S + s; attempts [S*P] int32, negative for
+    a seed that still collides)."""
+    u = torch.empty((3 * robot.n, S * P), dtype=torch.float64, device=device)
+    att = torch.empty((S * P,), dtype=torch.int32, device=device)
+    sp = _spheres_c(spheres, torch.float64)
+    rc = robot.c()
+    _check(lib.cr_sample_seeds(C.byref(rc), C.byref(sp), P, S,
+                               int(key[0]) & (2 ** 64 - 1), int(key[1]) & (2 ** 64 - 1), max_attempts, _ptr(u),
+                               _ptr(att), _stream(u)))
+    return u, att
 
 
 def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,

@@ -270,6 +270,20 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   return rc;
 }
 
+cr_status cr_sample_seeds(const cr_robot* robot, const cr_spheres* spheres, int64_t P, int32_t S, uint64_t key0,
+                          uint64_t key1, int32_t max_attempts, double* u_out, int32_t* attempts_out,
+                          hipStream_t stream) {
+  cr_status rc;
+  if ((rc = check_robot(robot)) != CR_OK) return rc;
+  if (P < 0 || S < 1) return fail(CR_EINVAL, "need P >= 0 and S >= 1");
+  if (P > ((int64_t)1 << 40) / S) return fail(CR_EINVAL, "P * S too large");
+  if (max_attempts < 1 || max_attempts > 64) return fail(CR_EINVAL, "max_attempts=%d not in 1..64", max_attempts);
+  if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
+  if (P == 0) return CR_OK;
+  if (!u_out) return fail(CR_EINVAL, "u_out is NULL");
+  return launch_sample_seeds(*robot, spheres, P, S, key0, key1, max_attempts, u_out, attempts_out, stream);
+}
+
 cr_status cr_select_top(int64_t P, int32_t S, int32_t nz, const void* z, const void* e, const void* pen,
                         const int32_t* failed, int32_t n_final, double dup_eps, int32_t* idx_out, cr_dtype dtype,
                         hipStream_t stream) {

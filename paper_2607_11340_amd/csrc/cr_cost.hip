@@ -38,24 +38,18 @@ __global__ void __launch_bounds__(256)
   if (b >= B) return;
   const int64_t p = b / S;
   T z[NZ];
-  double zd[NZ];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const double u0 = (double)u[(3 * i) * B + b], u1 = (double)u[(3 * i + 1) * B + b],
-                 u2 = (double)u[(3 * i + 2) * B + b];
-    u_to_ab(u0, u1, u2, rb.rd[i], &zd[NC * i], &zd[NC * i + 1]);
-    if constexpr (EXT) zd[NC * i + 2] = (u0 + u1 + u2) * (1.0 / 3.0);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) z[NC * i + c] = (T)zd[NC * i + c];
+    const T u0 = u[(3 * i) * B + b], u1 = u[(3 * i + 1) * B + b], u2 = u[(3 * i + 2) * B + b];
+    u_to_ab(u0, u1, u2, rb.r[i], &z[NC * i], &z[NC * i + 1]);
+    if constexpr (EXT) z[NC * i + 2] = (u0 + u1 + u2) * T(1.0 / 3.0);
   }
   T tt[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) tt[c] = task[c * P + p];
   Fwd<NS, T, EXT> f;
   const T* sp = sph ? sph + (per_problem ? p * M : 0) : nullptr;
-  // clearance (spheres, self contact) is formed on an FP64 chain (see cr_cost_grad)
-  T c = ((sph && M > 0) || SELF) ? config_forward<NS, T, GRAD, double, T, EXT, SELF>(rb, w, z, sp, M, 1, sld, f, zd)
-                                 : config_forward<NS, T, GRAD, T, T, EXT, SELF>(rb, w, z, sp, 0, 1, sld, f, zd);
+  T c = config_forward<NS, T, GRAD, T, T, EXT, SELF>(rb, w, z, sp, (sph && M > 0) ? M : 0, 1, sld, f);
   T ft[3] = {T(0), T(0), T(0)}, tq[3] = {T(0), T(0), T(0)};
   c += pose_term<T, GRAD>(w, f.R, f.p, tt, ft, tq);
   cost[b] = c;
@@ -83,8 +77,8 @@ __global__ void __launch_bounds__(256)
                 T* __restrict__ cost, T* __restrict__ grad, const T* __restrict__ gscale) {
   constexpr int NZ = 2 * NS, NU = 3 * NS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* s_u = reinterpret_cast<double*>(smem_raw);  // zero-sum tendon displacements, FP64
-  T* s_sph = reinterpret_cast<T*>(s_u + (H + 1) * NU);
+  T* s_u = reinterpret_cast<T*>(smem_raw);  // zero-sum tendon displacements
+  T* s_sph = s_u + (H + 1) * NU;
   T* s_p = s_sph + 4 * M;
   T* s_red = s_p + (H + 1) * 3;
   const int Tn = H + 1;
@@ -99,7 +93,6 @@ __global__ void __launch_bounds__(256)
   const bool act = t < Tn;
   const int64_t col = traj * Tn + t;
   T z[NZ];
-  double zd[NZ];
   Fwd<NS, T> f;
   T cst = T(0);
   T ft[3] = {T(0), T(0), T(0)}, tq[3] = {T(0), T(0), T(0)};
@@ -107,17 +100,14 @@ __global__ void __launch_bounds__(256)
   if (act) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      u_to_ab((double)u[(3 * i) * B + col], (double)u[(3 * i + 1) * B + col], (double)u[(3 * i + 2) * B + col],
-              rb.rd[i], &zd[2 * i], &zd[2 * i + 1]);
-      z[2 * i] = (T)zd[2 * i];
-      z[2 * i + 1] = (T)zd[2 * i + 1];
-      double ub[3];
-      ab_to_u(zd[2 * i], zd[2 * i + 1], rb.rd[i], ub);
+      u_to_ab(u[(3 * i) * B + col], u[(3 * i + 1) * B + col], u[(3 * i + 2) * B + col], rb.r[i], &z[2 * i],
+              &z[2 * i + 1]);
+      T ub[3];
+      ab_to_u(z[2 * i], z[2 * i + 1], rb.r[i], ub);
 #pragma unroll
       for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = ub[j];
     }
-    cst = M > 0 ? config_forward<NS, T, GRAD, double>(rb, w, z, s_sph, M, 4, 1, f, zd)
-                : config_forward<NS, T, GRAD>(rb, w, z, s_sph, 0, 4, 1, f, zd);
+    cst = config_forward<NS, T, GRAD>(rb, w, z, s_sph, M, 4, 1, f);
     if (kind == CR_KIND_PATH) {
       T tt[12];
       const int64_t tc = p * Tn + t;
@@ -131,12 +121,12 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   if (act) {
-    const double idt = 1.0 / (double)w.dt, idt2 = idt * idt;
-    const double sqv = (double)w.sq_vel, sqa = (double)w.sq_acc, sql = (double)w.sq_lim;
-    double gu[NU];
-    double cs = 0.0;
+    const T idt = T(1) / w.dt, idt2 = idt * idt;
+    const T sqv = w.sq_vel, sqa = w.sq_acc, sql = w.sq_lim;
+    T gu[NU];
+    T cs = T(0);
 #pragma unroll
-    for (int m = 0; m < NU; ++m) gu[m] = 0.0;
+    for (int m = 0; m < NU; ++m) gu[m] = T(0);
     // tendon velocity and acceleration (finite differences, Sec. IV-A): residual tau is
     // owned by lane tau for the cost; lane t gathers d/du_t from tau = t, t+1 (, t+2).
 #pragma unroll
@@ -145,17 +135,17 @@ __global__ void __launch_bounds__(256)
       for (int k = 0; k < 2; ++k) {
         const int tau = t + k;
         if (tau >= 1 && tau <= H) {
-          const double v = (s_u[tau * NU + m] - s_u[(tau - 1) * NU + m]) * idt;
-          const double dv = k == 0 ? idt : -idt;
-          const double rr = sqv * v;
-          if (k == 0) cs += 0.5 * rr * rr;
+          const T v = (s_u[tau * NU + m] - s_u[(tau - 1) * NU + m]) * idt;
+          const T dv = k == 0 ? idt : -idt;
+          const T rr = sqv * v;
+          if (k == 0) cs += T(0.5) * rr * rr;
           if (GRAD) gu[m] += rr * sqv * dv;
           if (w.has_vmax) {
-            const double viol = fabs(v) - (double)w.v_max;
-            if (viol > 0.0) {
-              const double hr = sql * viol;
-              if (k == 0) cs += 0.5 * hr * hr;
-              if (GRAD) gu[m] += hr * (v < 0.0 ? -sql : sql) * dv;
+            const T viol = fabs(v) - w.v_max;
+            if (viol > T(0)) {
+              const T hr = sql * viol;
+              if (k == 0) cs += T(0.5) * hr * hr;
+              if (GRAD) gu[m] += hr * (v < T(0) ? -sql : sql) * dv;
             }
           }
         }
@@ -164,23 +154,23 @@ __global__ void __launch_bounds__(256)
       for (int k = 0; k < 3; ++k) {
         const int tau = t + k;
         if (tau >= 2 && tau <= H) {
-          const double a = (s_u[tau * NU + m] - 2.0 * s_u[(tau - 1) * NU + m] + s_u[(tau - 2) * NU + m]) * idt2;
-          const double da = k == 1 ? -2.0 * idt2 : idt2;
-          const double rr = sqa * a;
-          if (k == 0) cs += 0.5 * rr * rr;
+          const T a = (s_u[tau * NU + m] - T(2) * s_u[(tau - 1) * NU + m] + s_u[(tau - 2) * NU + m]) * idt2;
+          const T da = k == 1 ? T(-2) * idt2 : idt2;
+          const T rr = sqa * a;
+          if (k == 0) cs += T(0.5) * rr * rr;
           if (GRAD) gu[m] += rr * sqa * da;
           if (w.has_amax) {
-            const double viol = fabs(a) - (double)w.a_max;
-            if (viol > 0.0) {
-              const double hr = sql * viol;
-              if (k == 0) cs += 0.5 * hr * hr;
-              if (GRAD) gu[m] += hr * (a < 0.0 ? -sql : sql) * da;
+            const T viol = fabs(a) - w.a_max;
+            if (viol > T(0)) {
+              const T hr = sql * viol;
+              if (k == 0) cs += T(0.5) * hr * hr;
+              if (GRAD) gu[m] += hr * (a < T(0) ? -sql : sql) * da;
             }
           }
         }
       }
     }
-    cst += (T)cs;
+    cst += cs;
     T gze[NZ];
 #pragma unroll
     for (int k = 0; k < NZ; ++k) gze[k] = T(0);
@@ -200,14 +190,14 @@ __global__ void __launch_bounds__(256)
         const int off = t == 0 ? 0 : NU;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-          double za, zb;
-          u_to_ab((double)task[(off + 3 * i) * P + p], (double)task[(off + 3 * i + 1) * P + p],
-                  (double)task[(off + 3 * i + 2) * P + p], rb.rd[i], &za, &zb);
-          const double sqe = (double)w.sq_eq;
-          const double ra = sqe * (zd[2 * i] - za), rb2 = sqe * (zd[2 * i + 1] - zb);
-          cst += (T)(0.5 * (ra * ra + rb2 * rb2));
-          gze[2 * i] += (T)(sqe * ra);
-          gze[2 * i + 1] += (T)(sqe * rb2);
+          T za, zb;
+          u_to_ab(task[(off + 3 * i) * P + p], task[(off + 3 * i + 1) * P + p], task[(off + 3 * i + 2) * P + p],
+                  rb.r[i], &za, &zb);
+          const T sqe = w.sq_eq;
+          const T ra = sqe * (z[2 * i] - za), rb2 = sqe * (z[2 * i + 1] - zb);
+          cst += T(0.5) * (ra * ra + rb2 * rb2);
+          gze[2 * i] += sqe * ra;
+          gze[2 * i + 1] += sqe * rb2;
         }
       }
     }
@@ -217,15 +207,15 @@ __global__ void __launch_bounds__(256)
       const T sc = gscale ? gscale[traj] : T(1);
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        double sa = 0.0, sb = 0.0;
+        T sa = T(0), sb = T(0);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          double ja, jb;
-          lift_row(j, rb.rd[i], &ja, &jb);
+          T ja, jb;
+          lift_row(j, rb.r[i], &ja, &jb);
           sa += gu[3 * i + j] * ja;
           sb += gu[3 * i + j] * jb;
         }
-        const T ga = gz[2 * i] + gze[2 * i] + (T)sa, gb = gz[2 * i + 1] + gze[2 * i + 1] + (T)sb;
+        const T ga = gz[2 * i] + gze[2 * i] + sa, gb = gz[2 * i + 1] + gze[2 * i + 1] + sb;
         T go[3];
         gz_to_gu(ga, gb, rb.r[i], go);
 #pragma unroll
@@ -272,7 +262,7 @@ static cr_status run_cost(int kind, const cr_robot& rb0, const cr_spheres* sp, c
   }
   const int Tn = H + 1;
   const int threads = ((Tn + 63) / 64) * 64;
-  const size_t lds = sizeof(double) * (size_t)(Tn * 3 * NS) + sizeof(T) * (size_t)(4 * M + Tn * 3 + 8);
+  const size_t lds = sizeof(T) * (size_t)(Tn * 3 * NS + 4 * M + Tn * 3 + 8);
   if (grad)
     hipLaunchKernelGGL((k_cost_traj<NS, T, true>), dim3((unsigned)B), dim3(threads), lds, st, rb, w, kind, P, S, H,
                        (const T*)task, sph, sld, M, ppb, (const T*)u, (T*)cost, (T*)grad, (const T*)gscale);

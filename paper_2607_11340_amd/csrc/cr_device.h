@@ -32,9 +32,7 @@ struct RobotT {
   int n, K;
   T L[CR_MAX_SEG], r[CR_MAX_SEG], umax[CR_MAX_SEG];
   T theta_max;
-  // FP64 copies for the bound and clearance hinges: a violation |u| - u_max is a
-  // difference of nearly equal numbers, so it is formed in FP64 whatever the
-  // kernel's type.
+  // FP64 copies of the geometry for the FP64 chains (stage 2, assessment)
   double Ld[CR_MAX_SEG], rd[CR_MAX_SEG], umaxd[CR_MAX_SEG], theta_maxd;
   // extensible segments: centre and half width of each length interval (eq. 9)
   int ext;
@@ -437,11 +435,10 @@ CR_HD void relative_pose(const T* R, const T* p, const T* Tt, T* Re, T* te) {
 // Bound penalties shared by every task (eq. 9): tendon hinge and bending hinge.
 // ---------------------------------------------------------------------------
 
-// One segment's bound residuals in FP64 from its bending coordinates (eq. 9):
+// One segment's bound residuals from its bending coordinates (eq. 9):
 // tendon hinges sq_lim max(0, |u_j| - u_max) and the bending hinge
 // sq_curv max(0, theta - theta_max).  ru[j] / rth are 0 when inactive.
-// TH is the type the violations are formed in: FP64 where gradients are
-// reported (cost/gradient kernel), the kernel's own type inside the solver loop.
+// TH is the type the violations are formed in (the kernel's chain type).
 template <typename TH, typename T>
 CR_HD void bound_residuals(const RobotT<T>& rb, const WeightsT<T>& w, int i, TH a, TH b, TH* ru, TH* sgn, TH* rth) {
   const TH r = sizeof(TH) == 8 ? (TH)rb.rd[i] : (TH)rb.r[i];
@@ -824,12 +821,13 @@ struct Fwd {
 };
 
 // Sphere m, component c (cx, cy, cz, radius) is read as sph[m * ms + c * cs].
-// zd (2NS, FP64) or NULL: the bending coordinates in FP64 (z is their rounding to
-// T) for the bound hinges; when NULL the hinges use z widened to FP64.
-// TC is the type of the chained transforms and backbone points.  With spheres the
-// FP32 kernels chain in FP64: a clearance violation is a small difference of
-// backbone-to-centre distances, and FP32 positions would set its error.  The pair
-// rejection test stays in T (with a relative slack); active pairs are re-measured
+// zd (NC NS, FP64) or NULL: the coordinates in FP64 when the caller has them (z
+// is their rounding to T); a TC chain starts from them.
+// TC is the type of the chained transforms, the backbone points and the bound
+// hinges.  Every kernel chains in its own type (FP32 kernels in FP32: a clearance
+// violation then carries the FP32 error of the point positions, about
+// 8 n u32 sum(L), which the FP32 parity tests allow for).  The pair rejection test
+// runs in T (with a relative slack when TC is wider); active pairs are measured
 // in TC.
 // Self contact (eq. 10) of the points of segment j against those of every
 // segment m <= j - 2: residual sq_coll max(0, margin + r_j + r_m - |q - p|) per
@@ -1091,38 +1089,38 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
       f.pe[i][1] = (T)pc[1];
       f.pe[i][2] = (T)pc[2];
     }
-    // bounds (eq. 9): tendon hinges and bending hinge, violations formed in FP64
+    // bounds (eq. 9): tendon hinges and bending hinge, in the chain's type
     {
-      double ru[3], sg[3], rth;
-      const double ad = zd ? zd[NC * i] : (double)a, bd = zd ? zd[NC * i + 1] : (double)b;
-      bound_residuals<double>(rb, w, i, ad, bd, ru, sg, &rth);
-      double cb = 0.5 * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
+      TC ru[3], sg[3], rth;
+      bound_residuals<TC>(rb, w, i, ac, bc, ru, sg, &rth);
+      const TC cb = TC(0.5) * (ru[0] * ru[0] + ru[1] * ru[1] + ru[2] * ru[2] + rth * rth);
       cost += (T)cb;
       if (GRAD) {
-        double ga = 0.0, gb = 0.0;
+        TC ga = TC(0), gb = TC(0);
+        const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          if (ru[j] > 0.0) {
-            double ja, jb;
-            lift_row(j, rb.rd[i], &ja, &jb);
-            ga += sg[j] * (double)w.sq_lim * ja * ru[j];
-            gb += sg[j] * (double)w.sq_lim * jb * ru[j];
+          if (ru[j] > TC(0)) {
+            TC ja, jb;
+            lift_row(j, ri, &ja, &jb);
+            ga += sg[j] * (TC)w.sq_lim * ja * ru[j];
+            gb += sg[j] * (TC)w.sq_lim * jb * ru[j];
           }
         }
-        if (rth > 0.0) {
-          const double th = sqrt(ad * ad + bd * bd);
-          ga += (double)w.sq_curv * ad / th * rth;
-          gb += (double)w.sq_curv * bd / th * rth;
+        if (rth > TC(0)) {
+          const TC ith = trcp(tsqrt(s));
+          ga += (TC)w.sq_curv * ac * ith * rth;
+          gb += (TC)w.sq_curv * bc * ith * rth;
         }
         f.gz[NC * i] += (T)ga;
         f.gz[NC * i + 1] += (T)gb;
       }
       if constexpr (EXT) {
-        double se;
-        const double ed = zd ? zd[NC * i + 2] : (double)z[NC * i + 2];
-        const double rl = length_residual<double>(rb, w, i, ed, &se);
-        cost += (T)(0.5 * rl * rl);
-        if (GRAD && rl > 0.0) f.gz[NC * i + 2] += (T)(se * (double)w.sq_lim * rl);
+        TC se;
+        const TC ed = zd ? (TC)zd[NC * i + 2] : (TC)z[NC * i + 2];
+        const TC rl = length_residual<TC>(rb, w, i, ed, &se);
+        cost += (T)(TC(0.5) * rl * rl);
+        if (GRAD && rl > TC(0)) f.gz[NC * i + 2] += (T)(se * (TC)w.sq_lim * rl);
       }
     }
   }
@@ -1292,7 +1290,7 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
 // tip position and its Jacobian.  Pose rows against Tt only if pose.  TC is the
-// chain type (FP64 when spheres are present, as in config_forward).
+// chain type (as in config_forward).
 template <int NS, typename T, typename TC, typename TS = T, bool EXT = false, bool SELF = false>
 CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
                         int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[(EXT ? 3 : 2) * NS], bool pose = true) {

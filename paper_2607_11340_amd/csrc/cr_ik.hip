@@ -677,17 +677,29 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
                          (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
                          ws.cost2, ws.failed2);
     else {
-      // lanes per candidate: fill the 1024 SIMDs with one wave each where the
-      // candidates allow, at most four
-      const int g = B2 * 4 <= kStage2Lanes ? 4 : (B2 * 2 <= kStage2Lanes ? 2 : 1);
+      auto launch2 = [&](int g) {
 #define CR_S2G(G)                                                                                                \
   hipLaunchKernelGGL((k_ik_stage2_grp<NS, T, G>), dim3(blocks_for(G * B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, \
                      (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, ws.z2, ws.cost2,   \
                      ws.failed2)
-      if (g == 4) CR_S2G(4);
-      else if (g == 2) CR_S2G(2);
-      else CR_S2G(1);
+        if (g == 4) CR_S2G(4);
+        else if (g == 2) CR_S2G(2);
+        else CR_S2G(1);
 #undef CR_S2G
+      };
+      // lanes per candidate: untuned, fill the 1024 SIMDs with one wave each where
+      // the candidates allow, at most four
+      int g = B2 * 4 <= kStage2Lanes ? 4 : (B2 * 2 <= kStage2Lanes ? 2 : 1);
+      bool done = false;
+      if (tune_enabled() || tune_forced() >= 0) {
+        int v = 0;
+        rc = tune_choose(TK_IK_STAGE2, NS, sizeof(T) == 8 ? CR_F64 : CR_F32, B2, st,
+                         [&](int vv) { launch2(tune_occ(TK_IK_STAGE2, vv)); }, &v, &done);
+        if (rc != CR_OK) return rc;
+        if (!done && (tune_forced() >= 0 || tune_lookup(TK_IK_STAGE2, NS, sizeof(T) == 8 ? CR_F64 : CR_F32, B2) >= 0))
+          g = tune_occ(TK_IK_STAGE2, v);
+      }
+      if (!done) launch2(g);
     }
     rc = check_hip(hipGetLastError(), "k_ik_stage2");
     if (rc != CR_OK) return rc;

@@ -46,12 +46,20 @@ cr_status check_hip(hipError_t e, const char* what);
 // (kernel, segments, dtype, launch size rounded to a power of two, device) on a
 // stream that is not being captured times every variant once with HIP events and
 // caches the fastest; only kernels that may run twice on the same data are tuned.
-// Tuning drains the device first (a device-wide synchronisation, once per key).
-enum TuneKernel { TK_IK_STAGE1 = 0, TK_IK_STAGE1_RAG = 1, TK_TRAJ_BUILD = 2, TK_COUNT = 3 };
-constexpr int TUNE_NV = 3;  // variants per kernel
-// occupancy target of variant v of kernel k (1 = the compiler's own choice)
+// Each variant is timed TUNE_ROUNDS times (rounds over all variants, so that clock
+// and cache drift spread evenly) and its shortest time counts, which keeps the
+// choice stable between runs and machines.  Tuning drains the device first (a
+// device-wide synchronisation, once per key).
+// The FP64 IK stage 2 is tuned over its lanes per kept candidate instead (1, 2 or
+// 4; every width takes the same decisions, so its outputs do not depend on the
+// variant); untuned, it takes the width that gives every SIMD one wave.
+enum TuneKernel { TK_IK_STAGE1 = 0, TK_IK_STAGE1_RAG = 1, TK_TRAJ_BUILD = 2, TK_IK_STAGE2 = 3, TK_COUNT = 4 };
+constexpr int TUNE_NV = 3;      // variants per kernel
+constexpr int TUNE_ROUNDS = 3;  // timings per variant
+// parameter of variant v of kernel k: the occupancy target (1 = the compiler's
+// own choice), or for TK_IK_STAGE2 the lanes per candidate
 constexpr int tune_occ(int k, int v) {
-  return v == 0 ? 1 : (k == TK_TRAJ_BUILD ? (v == 1 ? 2 : 3) : (v == 1 ? 3 : 4));
+  return k == TK_IK_STAGE2 ? 1 << v : v == 0 ? 1 : (k == TK_TRAJ_BUILD ? (v == 1 ? 2 : 3) : (v == 1 ? 3 : 4));
 }
 bool tune_enabled();
 int tune_forced();  // -1, or the variant every tunable kernel runs
@@ -88,8 +96,8 @@ cr_status tune_choose(int kernel, int ns, int dtype, int64_t work, hipStream_t s
   // the device is drained first, so that the variants run alone (work already
   // queued on other streams, such as other groups of a batch, would skew them)
   if (rc == CR_OK) rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
-  if (rc == CR_OK) {
-    launch(0);  // warm-up: first-use costs of the key's buffers and code
+  if (rc == CR_OK) launch(0);  // warm-up: first-use costs of the key's buffers and code
+  for (int round = 0; round < TUNE_ROUNDS && rc == CR_OK; ++round) {
     rc = check_hip(hipEventRecord(ev[0], st), "hipEventRecord");
     for (int k = 0; k < TUNE_NV && rc == CR_OK; ++k) {
       launch(k);
@@ -97,8 +105,11 @@ cr_status tune_choose(int kernel, int ns, int dtype, int64_t work, hipStream_t s
       if (rc == CR_OK) rc = check_hip(hipEventRecord(ev[k + 1], st), "hipEventRecord");
     }
     if (rc == CR_OK) rc = check_hip(hipEventSynchronize(ev[TUNE_NV]), "hipEventSynchronize");
-    for (int k = 0; k < TUNE_NV && rc == CR_OK; ++k)
-      rc = check_hip(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]), "hipEventElapsedTime");
+    for (int k = 0; k < TUNE_NV && rc == CR_OK; ++k) {
+      float t = 0.0f;
+      rc = check_hip(hipEventElapsedTime(&t, ev[k], ev[k + 1]), "hipEventElapsedTime");
+      if (rc == CR_OK && (round == 0 || t < ms[k])) ms[k] = t;
+    }
   }
   for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
   if (rc != CR_OK) return rc;
@@ -116,6 +127,13 @@ template <typename T>
 RobotT<T> robot_to(const cr_robot& r);
 template <typename T>
 WeightsT<T> weights_to(const cr_weights& w);
+
+// SampleSeeds: zero-sum triples drawn per segment before the bounds are enforced
+// by scaling
+constexpr int kSeedTriples = 32;
+cr_status launch_sample_seeds(const cr_robot& rb, const cr_spheres* sp, int64_t P, int32_t S, uint64_t k0,
+                              uint64_t k1, int32_t max_attempts, double* u_out, int32_t* attempts_out,
+                              hipStream_t st);
 
 cr_status launch_fk(const cr_robot& rb, int64_t B, const void* u, int64_t ld, void* arc, void* frames,
                     void* pts, cr_dtype dtype, hipStream_t stream);

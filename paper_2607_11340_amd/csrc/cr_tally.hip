@@ -5,8 +5,7 @@
 // floating operation it performs, over a caller-given sample of seeds.  The counts
 // are therefore those of the kernel's own formulas, taking the kernel's branches
 // and line-search trials in the kernel's precision (up to the rounding of fused
-// multiply-adds and of the host's math library), not an estimate.  The bound
-// hinges, which the kernel forms in FP64, are formed in FP64 here too.  Counting rules:
+// multiply-adds and of the host's math library), not an estimate.  Counting rules:
 // add, sub, mul = 1 each (a fused multiply-add counts as its mul and its add,
 // i.e. 2); div, sqrt and the transcendental calls (sin and cos of sincos count
 // 2, atan2 1) are tallied separately and count 1 flop each in the total.

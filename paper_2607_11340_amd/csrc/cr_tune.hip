@@ -41,6 +41,7 @@ const char* kernel_name(int k) {
     case TK_IK_STAGE1: return "ik_stage1";
     case TK_IK_STAGE1_RAG: return "ik_stage1_ragged";
     case TK_TRAJ_BUILD: return "traj_build";
+    case TK_IK_STAGE2: return "ik_stage2";
   }
   return "?";
 }
@@ -106,12 +107,14 @@ int64_t cr_autotune_report(char* buf, int64_t cap) {
       const TuneKey& k = kv.first;
       const TuneEntry& e = kv.second;
       const int kern = std::get<1>(k);
-      std::snprintf(line, sizeof line, "device %d %s n_seg %d %s work<=2^%d: occupancy %d (ms", std::get<0>(k),
+      const bool lanes = kern == TK_IK_STAGE2;
+      std::snprintf(line, sizeof line, "device %d %s n_seg %d %s work<=2^%d: %s %d (ms", std::get<0>(k),
                     kernel_name(kern), std::get<2>(k), std::get<3>(k) == CR_F64 ? "f64" : "f32", std::get<4>(k),
-                    tune_occ(kern, e.best));
+                    lanes ? "lanes per candidate" : "occupancy", tune_occ(kern, e.best));
       s += line;
       for (int v = 0; v < TUNE_NV; ++v) {
-        std::snprintf(line, sizeof line, "%s occ%d %.4f", v ? "," : "", tune_occ(kern, v), e.ms[v]);
+        std::snprintf(line, sizeof line, "%s %s%d %.4f", v ? "," : "", lanes ? "lanes" : "occ", tune_occ(kern, v),
+                      e.ms[v]);
         s += line;
       }
       s += ")\n";

@@ -41,3 +41,121 @@ def ik_workload(O, spec_name, P=None, S=None, salt=0):
 
 def normwise_rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+U32 = 2.0 ** -24   # FP32 unit roundoff
+
+
+def _points_and_jacobian(O, ro, u, h=1e-7):
+    """Backbone points [n, K, 3] of one configuration u [n, 3], their arc lengths
+    and d(points)/du [n, K, 3, 3n] by central differences of the oracle's FK."""
+    n = ro.n
+    arc, _, pts = O.fk(ro, u, points=True)
+    du = np.zeros((2 * 3 * n, n, 3))
+    for j in range(3 * n):
+        du[2 * j].flat[j] = h
+        du[2 * j + 1].flat[j] = -h
+    _, _, pp = O.fk(ro, u[None] + du, points=True)
+    J = np.stack([(pp[2 * j] - pp[2 * j + 1]) / (2 * h) for j in range(3 * n)], axis=-1)
+    return pts, arc[:, 2], J
+
+
+def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=False):
+    """Absolute allowance (cost, gradient norm) for the FP32 rounding of the hinge
+    residuals of one seed, u [n, 3] or [T, n, 3] (a trajectory), sph [M, 4] or None.
+
+    A hinge r = sq max(0, v - v_max) (sq = sqrt(rho)) is a difference of nearly
+    equal numbers, so its FP32 error is set by the absolute error dv of v, not by
+    the size of r.  It moves 1/2 r^2 by at most r sq dv and the gradient r sq dv/du
+    by sq^2 dv |dv/du| + r sq |dv/du| 4 u32 (the FP32 derivative carries a few
+    roundings).  Per kind of v, with u32 = 2^-24:
+      * contact (eq. 10): v = distance from a backbone point to a sphere centre or,
+        with self contact, to a point of a non-adjacent segment.  An FP32 kernel
+        places a point through n chained segment transforms, every entry a few
+        roundings of numbers of size <= 1 scaled by lengths, so the point errs by at
+        most dp = 8 n u32 sum(L); dv <= dp + u32 (|p| + |c| + |p - c|) (2 dp for a
+        pair of points); |dv/du| <= ||dp/du||_2 (Frobenius norm of the oracle's
+        point Jacobian by central differences), and the unit normal turns by
+        dv / |p - c|, adding sq^2 h dv / |p - c| |dp/du|;
+      * tendon bound (eq. 9): v = |u_ij| of the lifted zero-sum displacement,
+        dv <= 8 u32 (|u_ij| + u_max), |dv/du| <= 1;
+      * bending bound: v = theta_i, dv <= 8 u32 theta_i, |dv/du| <= 1 / r_i;
+      * length bound (extensible): v = |L_i + e_i - mid|, dv <= 4 u32 (L_i + |e_i| +
+        mid + half), |dv/du| = 1 / sqrt(3);
+      * kinodynamic (trajectories, kinodynamic=True): tendon velocity and
+        acceleration finite differences of the lifted displacements, quadratic and
+        hinged, dv <= 16 u32 max|u| / dt (velocity), 32 u32 max|u| / dt^2
+        (acceleration), |dv/du| <= 2 / dt, resp. 2.45 / dt^2.
+    Pose residuals are not cancellations at these inputs and stay within the
+    relative 1e-5 the tests add."""
+    u = np.asarray(u, dtype=np.float64)
+    us = u[None] if u.ndim == 2 else u
+    n = ro.n
+    sq_coll, sq_lim, sq_curv = np.sqrt(W.rho_coll), np.sqrt(W.rho_lim), np.sqrt(W.rho_curv)
+    margin = W.margin
+    rad = np.repeat(np.asarray(ro.r, dtype=np.float64), ro.pts_per_seg)
+    seg = np.repeat(np.arange(n), ro.pts_per_seg)
+    umax = np.asarray(ro.u_max, dtype=np.float64)
+    acc = [0.0, 0.0]
+
+    def hinge(r, sq, dv, gv):
+        """adds the allowance of active hinges r = sq (v - v_max) > 0"""
+        acc[0] += float(np.sum(r * sq * dv))
+        acc[1] += float(np.sum(sq * sq * dv * gv + r * sq * gv * 4 * U32))
+
+    ubar = []
+    for ut in us:
+        z = O.u_to_z(ro, ut).reshape(n, ro.nc)
+        ub = ut - (z[:, 2:3] if ro.extensible else ut.mean(axis=1, keepdims=True))
+        ubar.append(ub)
+        # bounds (eq. 9)
+        viol = np.abs(ub) - umax[:, None]
+        act = viol > 0
+        hinge(sq_lim * viol[act], sq_lim, (8 * U32 * (np.abs(ub) + umax[:, None]))[act], 1.0)
+        th = np.hypot(z[:, 0], z[:, 1])
+        act = th > ro.theta_max
+        hinge(sq_curv * (th - ro.theta_max)[act], sq_curv, 8 * U32 * th[act], (1.0 / np.asarray(ro.r))[act])
+        if ro.extensible:
+            L0, e = np.asarray(ro.L), z[:, 2]
+            mid = 0.5 * (np.asarray(ro.L_min) + np.asarray(ro.L_max))
+            half = 0.5 * (np.asarray(ro.L_max) - np.asarray(ro.L_min))
+            v = np.abs(L0 + e - mid) - half
+            act = v > 0
+            hinge(sq_lim * v[act], sq_lim, (4 * U32 * (L0 + np.abs(e) + mid + half))[act], 1 / np.sqrt(3))
+        # contact (eq. 10)
+        if (sph is not None and len(sph)) or self_contact:
+            pts, lens, J = _points_and_jacobian(O, ro, ut)
+            p = pts.reshape(-1, 3)
+            Jp = J.reshape(-1, 3, 3 * n)
+            dp = 8 * n * U32 * lens.sum()
+            jn = np.linalg.norm(Jp, axis=(1, 2))
+            if sph is not None and len(sph):
+                d = np.linalg.norm(p[:, None] - sph[None, :, :3], axis=2)
+                h = margin - (d - sph[None, :, 3] - rad[:, None])
+                act = h > 0
+                dv = dp + U32 * (np.linalg.norm(p, axis=1)[:, None] + np.linalg.norm(sph[:, :3], axis=1)[None] + d)
+                gv = np.broadcast_to(jn[:, None], h.shape)[act]
+                hinge(sq_coll * h[act], sq_coll, dv[act], gv * (1 + h[act] / d[act]))
+            if self_contact:
+                far = seg[:, None] >= seg[None, :] + 2
+                d = np.linalg.norm(p[:, None] - p[None], axis=2)
+                h = margin - (d - rad[:, None] - rad[None])
+                act = far & (h > 0)
+                pn = np.linalg.norm(p, axis=1)
+                dv = 2 * dp + U32 * (pn[:, None] + pn[None] + d)
+                a, b = np.nonzero(act)
+                gv = np.linalg.norm(Jp[a] - Jp[b], axis=(1, 2))
+                hinge(sq_coll * h[act], sq_coll, dv[act], gv * (1 + h[act] / d[act]))
+    if kinodynamic and len(us) > 1:
+        ub = np.stack(ubar)
+        big = np.abs(ub).max()
+        dt = W.dt
+        for order, dv, gv, wq, lim in ((1, 16 * U32 * big / dt, 2 / dt, np.sqrt(W.w_vel), W.v_max),
+                                       (2, 32 * U32 * big / dt ** 2, 2.45 / dt ** 2, np.sqrt(W.w_acc), W.a_max)):
+            v = np.diff(ub, n=order, axis=0) / dt ** order
+            hinge(wq * np.abs(v), wq, dv, gv)                   # quadratic smoothness (a hinge at 0)
+            if np.isfinite(lim):
+                viol = np.abs(v) - lim
+                act = viol > 0
+                hinge(sq_lim * viol[act], sq_lim, dv, gv)
+    return acc[0], acc[1]

@@ -1,13 +1,16 @@
 """GPU parity of the penalised cost (eq. 17) and its adjoint gradient against the
 CPU oracle, for the three task kinds, with bound hinges, clearance hinges and
 kinodynamic hinges active.  FP64 within 1e-9 relative, FP32 within 1e-5
-relative (normwise per seed, oracle evaluated at the FP32-rounded inputs).
+relative (normwise per seed, oracle evaluated at the FP32-rounded inputs) plus the
+derived allowance for the FP32 rounding of active hinges (helpers.fp32_hinge_slack:
+a hinge is a small difference of nearly equal FP32 numbers, such as distances
+formed from FP32 point positions).
 Also: central finite differences on the GPU cost and torch gradcheck through
 the autograd Function."""
 import numpy as np
 import pytest
 
-from helpers import aos, normwise_rel, robots, soa
+from helpers import aos, fp32_hinge_slack, normwise_rel, robots, soa
 from paper_2607_11340_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -110,14 +113,25 @@ def test_cost_grad_parity(oracle, cr, kind, dtype):
         u, task, sph = (x.astype(np.float32).astype(np.float64) for x in (u, task, sph))
     co, go = oracle_eval(oracle, c, u, task, sph)
     cg, gg, _, _ = gpu_eval(cr, c, u, task, sph, dtype)
+    P, S = c["P"], c["S"]
     tol = 1e-9 if dtype == "f64" else 1e-5
     # the case must exercise the penalties it claims to
     assert co.min() > 0
-    rel_c = np.abs(cg - co) / np.abs(co)
-    assert rel_c.max() < tol, rel_c.max()
-    worst = max(normwise_rel(gg[p, s], go[p, s]) for p in range(c["P"]) for s in range(c["S"]))
-    print(f"  max cost rel {rel_c.max():.2e}, max per-seed grad rel {worst:.2e}", flush=True)
-    assert worst < tol
+    gn = np.array([[np.linalg.norm(go[p, s]) for s in range(S)] for p in range(P)])
+    eg = np.array([[np.linalg.norm(gg[p, s] - go[p, s]) for s in range(S)] for p in range(P)])
+    ec = np.abs(cg - co)
+    slack = np.zeros((P, S, 2))
+    if dtype == "f32":
+        W = oracle.Weights(**c["w"])
+        for p in range(P):
+            for s in range(S):
+                slack[p, s] = fp32_hinge_slack(oracle, c["ro"], W, u[p, s, 0] if kind == "ik" else u[p, s], sph[p],
+                                               kinodynamic=kind != "ik")
+    print(f"  max cost rel {(ec / co).max():.2e}, max per-seed grad rel {(eg / gn).max():.2e}; "
+          f"max error over allowance: cost {(ec / (tol * co + slack[..., 0])).max():.3f}, "
+          f"grad {(eg / (tol * gn + slack[..., 1])).max():.3f}", flush=True)
+    assert (ec <= tol * co + slack[..., 0]).all()
+    assert (eg <= tol * gn + slack[..., 1]).all()
     # the cost-only kernel returns the same cost up to rounding
     cg2, _, _, _ = gpu_eval(cr, c, u, task, sph, dtype, grad=False)
     assert (np.abs(cg2 - cg) / np.abs(cg)).max() < (1e-13 if dtype == "f64" else 1e-6)

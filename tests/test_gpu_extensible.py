@@ -2,13 +2,14 @@
 lengths are decision variables within the bounds of eq. 9) against the CPU
 oracle: forward kinematics (FP64 1e-9, FP32 1e-5 normwise), cost and adjoint
 gradient with every hinge active, with and without spheres (FP64 1e-9, FP32
-1e-5), FP64 LM iterates (1e-9), the FP64 two-stage solve (Algorithm 1, short
+1e-5 plus the derived allowance for FP32 hinge residuals,
+helpers.fp32_hinge_slack), FP64 LM iterates (1e-9), the FP64 two-stage solve (Algorithm 1, short
 budgets: answers, status and errors equal the oracle's) and the FP32 two-stage
 solve's quality on a 4-segment extendable robot among spheres."""
 import numpy as np
 import pytest
 
-from helpers import aos, normwise_rel, soa
+from helpers import aos, fp32_hinge_slack, normwise_rel, soa
 from paper_2607_11340_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -102,10 +103,17 @@ def test_ext_cost_grad_parity(oracle, cr, M, dtype):
     gg = aos(g.double().cpu().numpy(), (n, 3)).reshape(P, S, n, 3)
     tol = 1e-9 if dtype == "f64" else 1e-5
     assert co.min() > 0
-    assert (np.abs(cg - co) / co).max() < tol
-    worst = max(normwise_rel(gg[p, s], go[p, s]) for p in range(P) for s in range(S))
-    print(f"  max per-seed grad rel {worst:.2e}", flush=True)
-    assert worst < tol
+    slack = np.zeros((P, S, 2))
+    if dtype == "f32":          # FP32 hinges (helpers.fp32_hinge_slack)
+        for p in range(P):
+            for s in range(S):
+                slack[p, s] = fp32_hinge_slack(oracle, ro, W, u[p, s], sph[p, :M] if M else None)
+    gn = np.array([[np.linalg.norm(go[p, s]) for s in range(S)] for p in range(P)])
+    eg = np.array([[np.linalg.norm(gg[p, s] - go[p, s]) for s in range(S)] for p in range(P)])
+    ec = np.abs(cg - co)
+    print(f"  max cost rel {(ec / co).max():.2e}, max per-seed grad rel {(eg / gn).max():.2e}", flush=True)
+    assert (ec <= tol * co + slack[..., 0]).all()
+    assert (eg <= tol * gn + slack[..., 1]).all()
     # the gradient is not blind to the common mode any more
     assert np.abs(go.sum(axis=3)).max() > 1e-6 * np.abs(go).max()
 
