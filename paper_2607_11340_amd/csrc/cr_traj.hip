@@ -1050,10 +1050,13 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
         for (int k = 0; k < j; ++k) dd -= L[tri(j, k)] * L[tri(j, k)];
         ok = ok && (!on || dd > T(0));
-        const T ljj = tsqrt(dd > T(0) ? dd : T(1));
+        // hardware square root and reciprocal (1 ulp each; dd > 0 is normal here or
+        // replaced by 1), then products: the IEEE-exact forms cost about ten
+        // instructions each and this block is factored on every row lane
+        const T ljj = __builtin_amdgcn_sqrtf(dd > T(0) ? dd : T(1));
         L[tri(j, j)] = ljj;
-        yv[j] = yv[j] / ljj;
-        dv[j] = T(1) / ljj;
+        dv[j] = __builtin_amdgcn_rcpf(ljj);
+        yv[j] = yv[j] * dv[j];
 #pragma unroll
         for (int i = j + 1; i < NZ; ++i) {
           T v = L[tri(i, j)];
@@ -1148,13 +1151,14 @@ __global__ void __launch_bounds__(64)
       for (int k = 0; k < NZ; ++k) Lc[k] = T(k == a);
     }
     T d = T(0);
+    T laa = T(1);  // this lane's pivot L[a][a], inverted once
+#pragma unroll
+    for (int q = 0; q < NZ; ++q)
+      if (q == a) laa = Lc[q];
+    const T ilaa = trcp(laa);
 #pragma unroll
     for (int k = NZ - 1; k >= 0; --k) {
-      T lkk = T(1);
-#pragma unroll
-      for (int q = 0; q < NZ; ++q)
-        if (q == a) lkk = Lc[q];
-      if (a == k) d = r / lkk;
+      if (a == k) d = r * ilaa;
       const T dk = __shfl(d, base + k, 64);
       if (a < k) r -= Lc[k] * dk;
     }
@@ -1180,8 +1184,10 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// FP32 five segments: 170 VGPRs by the compiler's own choice, two waves per SIMD;
+// held to three (168 VGPRs), as the register budget just allows
 template <int NS, typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NS == 5 ? 3 : 1)))
     k_traj_search(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                   const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                   const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
