@@ -67,24 +67,44 @@ __device__ __forceinline__ TrajCtx traj_ctx(const TrajArgs<T>& ta, int64_t traj)
   return cx;
 }
 
-// Per-waypoint record of the normal equations.  The solve keeps row a of every
-// block on lane a, so blocks are laid out for the accesses that dominate it:
-//   OH: H_tt (full, symmetric; row a read as column a), overwritten by L_tt
-//       column-major (element (i, j) at j * NZ + i: the backward pass reads a
-//       column of L_tt as NZ consecutive values)
-//   OB: H_{t,t-1}, overwritten by L_{t,t-1};  OC: H_{t,t-2}, overwritten by
-//       L_{t,t-2}; both row-major (element (i, j) at i * NZ + j: the forward pass
-//       reads and writes a row per lane as NZ consecutive values)
-//   OG: g_t;  OY: y_t, then delta_t
+// Per-waypoint record of the normal equations and of their factor.  The block
+// solve streams these records through HBM twice per LM iteration, so the build
+// stores only what is not zero or repeated, and the solve keeps row a of every
+// block on lane a.  Inputs, written by the build and read once by the forward
+// pass:
+//   OHI: H_tt, lower triangle packed by rows (element (i, j), j <= i, at
+//        i (i + 1) / 2 + j; the upper triangle is never read)
+//   OBS, OCS: the smoothness couplings, 2 x 2 symmetric blocks on the diagonal,
+//        (aa, ab, bb) per segment: H_{t,t-2} is exactly that, and so is H_{t,t-1}
+//        for path following
+//   OB:  trajectories only: H_{t,t-1} in full (the tip path-length term couples
+//        every coordinate of t with every one of t - 1), row-major
+//   OG:  g_t
+// Factor, written by the forward pass and read by the backward pass:
+//   OL:  L_tt, lower triangle packed by columns (column j from
+//        j NZ - j (j - 1) / 2, rows j .. NZ - 1: the backward pass reads a column
+//        per lane)
+//   OB, OC: L_{t,t-1}, L_{t,t-2}, row-major (element (i, j) at i NZ + j: the
+//        forward pass writes a row per lane as NZ consecutive values)
+//   OY:  y_t, then delta_t
+__host__ __device__ constexpr int rec_up4(int x) { return (x + 3) & ~3; }
+__host__ __device__ constexpr int rec_size(int ns) {
+  return 2 * rec_up4(2 * ns * (2 * ns + 1) / 2) + 2 * (2 * ns) * (2 * ns) + 2 * rec_up4(2 * ns) + 2 * rec_up4(3 * ns);
+}
 template <int NS>
 struct Rec {
-  static constexpr int NZ = 2 * NS;
-  static constexpr int OH = 0, OB = NZ * NZ, OC = 2 * NZ * NZ, OG = 3 * NZ * NZ, OY = OG + NZ;
-  static constexpr int SIZE = OY + NZ;
+  static constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
+  static constexpr int OL = 0, OB = rec_up4(NP), OC = OB + NZ * NZ, OY = OC + NZ * NZ, OG = OY + rec_up4(NZ),
+                       OHI = OG + rec_up4(NZ), OBS = OHI + rec_up4(NP), OCS = OBS + rec_up4(3 * NS),
+                       SIZE = OCS + rec_up4(3 * NS);
   // with a 256-byte aligned workspace every record and block starts on a 16-byte
-  // boundary in FP32 and FP64 (SIZE = 4 NS (3 NS + 1)); a row of a block is
-  // 16-byte aligned when NZ is a multiple of 4 or in FP64, else 8-byte aligned
-  static_assert(SIZE % 4 == 0 && OB % 4 == 0 && OC % 4 == 0, "record blocks must be 16-byte aligned");
+  // boundary in FP32 and FP64; a row of OB / OC is 16-byte aligned when NZ is a
+  // multiple of 4 or in FP64, else 8-byte aligned
+  static_assert(SIZE % 4 == 0 && OB % 4 == 0 && OC % 4 == 0 && OY % 4 == 0 && OG % 4 == 0,
+                "record blocks must be 16-byte aligned");
+  static_assert(SIZE == rec_size(NS), "rec_size must follow the layout");
+  // first value of column j of L_tt in OL
+  static __device__ __forceinline__ int lcol(int j) { return j * NZ - j * (j - 1) / 2; }
 };
 
 // NZ consecutive values of a record (16-byte aligned records; an offset that is a
@@ -790,38 +810,38 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
       }
     }
     T* rec = blk + (cx.wp + t) * R::SIZE;
-    const bool len = ta.kind == CR_KIND_TRAJ && t >= 1;
-    const T sl2 = w.sq_len * w.sq_len;
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) {
-      T hc[NZ];  // column b of H_tt
+    for (int k = 0; k < NP; ++k) rec[R::OHI + k] = Hp[k];  // lower triangle, packed by rows
 #pragma unroll
-      for (int a = 0; a < NZ; ++a) hc[a] = a >= b ? Hp[tri(a, b)] : Hp[tri(b, a)];
-      store_run<NZ>(hc, rec + R::OH + b * NZ);
-    }
-    T jq[3][NZ] = {};  // J_p at t - 1
-    if (len) {
+    for (int i = 0; i < NS; ++i)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int b = 0; b < NZ; ++b) jq[q][b] = s_jp[((t - 1) * 3 + q) * NZ + b];
-    }
-#pragma unroll
-    for (int a = 0; a < NZ; ++a) {
-      T brow[NZ], crow[NZ];  // row a of H_{t,t-1} and of H_{t,t-2}
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) {
-        T bv = T(0), cv = T(0);
-        if (a / 2 == b / 2) {
-          bv = Bs[a / 2][(a & 1) + (b & 1)];
-          cv = Cs[a / 2][(a & 1) + (b & 1)];
-        }
-        if (len) bv -= sl2 * (Jp[0][a] * jq[0][b] + Jp[1][a] * jq[1][b] + Jp[2][a] * jq[2][b]);
-        brow[b] = bv;
-        crow[b] = cv;
+      for (int k = 0; k < 3; ++k) {
+        rec[R::OBS + 3 * i + k] = Bs[i][k];
+        rec[R::OCS + 3 * i + k] = Cs[i][k];
       }
-      store_run<NZ>(brow, rec + R::OB + a * NZ);
-      store_run<NZ>(crow, rec + R::OC + a * NZ);
+    if (ta.kind == CR_KIND_TRAJ) {
+      // H_{t,t-1} in full: the smoothness blocks minus the path-length coupling
+      // sq_len^2 J_p(t)^T J_p(t-1)
+      const bool len = t >= 1;
+      const T sl2 = w.sq_len * w.sq_len;
+      T jq[3][NZ] = {};  // J_p at t - 1
+      if (len) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int b = 0; b < NZ; ++b) jq[q][b] = s_jp[((t - 1) * 3 + q) * NZ + b];
+      }
+#pragma unroll
+      for (int a = 0; a < NZ; ++a) {
+        T brow[NZ];  // row a of H_{t,t-1}
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) {
+          T bv = a / 2 == b / 2 ? Bs[a / 2][(a & 1) + (b & 1)] : T(0);
+          if (len) bv -= sl2 * (Jp[0][a] * jq[0][b] + Jp[1][a] * jq[1][b] + Jp[2][a] * jq[2][b]);
+          brow[b] = bv;
+        }
+        store_run<NZ>(brow, rec + R::OB + a * NZ);
+      }
     }
 #pragma unroll
     for (int k = 0; k < NZ; ++k) rec[R::OG + k] = g[k];
@@ -876,17 +896,32 @@ __global__ void __launch_bounds__(64)
   const T lm = act ? lam[traj] : T(0);
   T* const recs = blk + wp * R::SIZE;
   bool ok = true;
+  // row a of the input blocks of a record: H_tt (lower part, b <= a; the rest
+  // is never read), H_{t,t-1} (in full for trajectories, else from the segment's
+  // 2 x 2 block) and H_{t,t-2} (from the segment's 2 x 2 block), and g_a
+  const bool dense_b = ta.kind == CR_KIND_TRAJ;
+  const int sa = 3 * (a >> 1) + (a & 1);  // row a of the segment's (aa, ab, bb)
+  auto load_inputs = [&](const T* r, T* h, T* bw, T* c, T& gv) {
+#pragma unroll
+    for (int b = 0; b < NZ; ++b) h[b] = b <= a ? r[R::OHI + a * (a + 1) / 2 + b] : T(0);
+    if (dense_b) {
+      load_run<NZ>(r + R::OB + a * NZ, bw);
+    } else {
+      const T b0 = r[R::OBS + sa], b1 = r[R::OBS + sa + 1];
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) bw[b] = b == (a & ~1) ? b0 : (b == (a | 1) ? b1 : T(0));
+    }
+    const T c0 = r[R::OCS + sa], c1 = r[R::OCS + sa + 1];
+#pragma unroll
+    for (int b = 0; b < NZ; ++b) c[b] = b == (a & ~1) ? c0 : (b == (a | 1) ? c1 : T(0));
+    gv = r[R::OG + a];
+  };
   // FP32 rows of the next waypoint's blocks are loaded while the current one is
   // factored (the chain over waypoints is latency-bound)
   constexpr bool PF = sizeof(T) == 4 && NZ <= 10;
   T pH[NZ], pB[NZ], pC[NZ], pG = T(0);
   if constexpr (PF) {
-    if (act && 0 < Tn) {
-      load_run<NZ>(recs + R::OH + a * NZ, pH);
-      load_run<NZ>(recs + R::OB + a * NZ, pB);
-      load_run<NZ>(recs + R::OC + a * NZ, pC);
-      pG = recs[R::OG + a];
-    }
+    if (act && 0 < Tn) load_inputs(recs, pH, pB, pC, pG);
   }
   // every lane runs the longest horizon of the launch (workgroup-uniform barriers);
   // a trajectory's lanes work only while t < its own horizon
@@ -902,24 +937,16 @@ __global__ void __launch_bounds__(64)
         cC[k] = pC[k];
       }
       cG = pG;
-      if (act && t + 1 < Tn) {
-        const T* nx = rec + R::SIZE;
-        load_run<NZ>(nx + R::OH + a * NZ, pH);
-        load_run<NZ>(nx + R::OB + a * NZ, pB);
-        load_run<NZ>(nx + R::OC + a * NZ, pC);
-        pG = nx[R::OG + a];
-      }
+      if (act && t + 1 < Tn) load_inputs(rec + R::SIZE, pH, pB, pC, pG);
+    } else {
+      if (on) load_inputs(rec, cH, cB, cC, cG);
     }
     const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
     const int b0 = t & 1, b1 = b0 ^ 1;
-    T S[NZ];  // row a of H_tt, read as its column a (the block is stored exactly symmetric)
+    T S[NZ];  // row a of H_tt, lower part (b <= a)
     if (on) {
-      if constexpr (PF) {
 #pragma unroll
-        for (int b = 0; b < NZ; ++b) S[b] = cH[b];
-      } else {
-        load_run<NZ>(rec + R::OH + a * NZ, S);
-      }
+      for (int b = 0; b < NZ; ++b) S[b] = cH[b];
     } else {
 #pragma unroll
       for (int b = 0; b < NZ; ++b) S[b] = T(b == a);
@@ -927,15 +954,11 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int b = 0; b < NZ; ++b)
       if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
-    T y = on ? -(PF ? cG : rec[R::OG + a]) : T(0);
+    T y = on ? -cG : T(0);
     T Bw[NZ];  // row a of H_{t,t-1}
     if (on && t >= 1) {
-      if constexpr (PF) {
 #pragma unroll
-        for (int b = 0; b < NZ; ++b) Bw[b] = cB[b];
-      } else {
-        load_run<NZ>(rec + R::OB + a * NZ, Bw);
-      }
+      for (int b = 0; b < NZ; ++b) Bw[b] = cB[b];
     } else {
 #pragma unroll
       for (int b = 0; b < NZ; ++b) Bw[b] = T(0);
@@ -946,12 +969,8 @@ __global__ void __launch_bounds__(64)
       const T* D2 = &sD[s2][g * RS];
       T x[NZ];  // row a of H_{t,t-2}, then of L_{t,t-2}
       if (on) {
-        if constexpr (PF) {
 #pragma unroll
-          for (int i = 0; i < NZ; ++i) x[i] = cC[i];
-        } else {
-          load_run<NZ>(rec + R::OC + a * NZ, x);
-        }
+        for (int i = 0; i < NZ; ++i) x[i] = cC[i];
       } else {
 #pragma unroll
         for (int i = 0; i < NZ; ++i) x[i] = T(0);
@@ -1079,10 +1098,10 @@ __global__ void __launch_bounds__(64)
       __syncthreads();
       y = Yt[a];
       if (on) {
-        T col[NZ];  // column a of L_tt
+        // column a of L_tt, rows a .. NZ - 1
 #pragma unroll
-        for (int k = 0; k < NZ; ++k) col[k] = k >= a ? Lt[k * RS + a] : T(0);
-        store_run<NZ>(col, rec + R::OH + a * NZ);
+        for (int k = 0; k < NZ; ++k)
+          if (k >= a) rec[R::OL + R::lcol(a) + k - a] = Lt[k * RS + a];
         rec[R::OY + a] = y;
       }
     } else {
@@ -1116,7 +1135,8 @@ __global__ void __launch_bounds__(64)
       }
       if (on) {
 #pragma unroll
-        for (int b = 0; b < NZ; ++b) rec[R::OH + b * NZ + a] = b <= a ? S[b] : T(0);
+        for (int b = 0; b < NZ; ++b)
+          if (b <= a) rec[R::OL + R::lcol(b) + a - b] = S[b];  // row a of L_tt
         rec[R::OY + a] = y;
       }
     }
@@ -1145,7 +1165,8 @@ __global__ void __launch_bounds__(64)
     // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
     T Lc[NZ];
     if (on) {
-      load_run<NZ>(rec + R::OH + a * NZ, Lc);
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) Lc[k] = k >= a ? rec[R::OL + R::lcol(a) + k - a] : T(0);
     } else {
 #pragma unroll
       for (int k = 0; k < NZ; ++k) Lc[k] = T(k == a);
@@ -1503,7 +1524,7 @@ struct TrajWs {
 // problem table and the SelectTop rows.
 static size_t traj_ws_layout(int ns, const TrajShape& sh, int nf, int kseed, cr_dtype dt, char* base, TrajWs* w) {
   const size_t t1 = dt == CR_F64 ? 8 : 4;
-  const int NZ = 2 * ns, REC = 3 * NZ * NZ + 2 * NZ;  // struct Rec
+  const int NZ = 2 * ns, REC = rec_size(ns);  // struct Rec
   const int64_t n1 = sh.N1, w1 = sh.W1, n2 = sh.P * (nf > 0 ? nf : 1), w2 = sh.TnSum * (nf > 0 ? nf : 1);
   size_t off = 0;
   auto take = [&](size_t b) {
