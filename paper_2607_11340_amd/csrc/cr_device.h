@@ -1606,7 +1606,11 @@ CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T
 
 // lm_ik with clearance rows: the same iteration, the generic per-configuration
 // normal equations and cost.
-template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false>
+// G > 1 (device only): the G lanes of an aligned lane group carry the same
+// configuration and try G step lengths of the line search at once, lane q taking
+// 2^-(G r + q) in round r; a ballot over the group takes the first accepted one,
+// the sequential search's choice, so the iterates do not depend on G.
+template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false, int G = 1>
 CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
                   bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs) {
   constexpr int NZ = (EXT ? 3 : 2) * NS;
@@ -1635,16 +1639,41 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
     T alpha = T(1);
     int acc = -1;
     T zt[NZ];
-    for (int tr = 0; tr < o.ls_max; ++tr) {
+    if constexpr (G == 1) {
+      for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
-      for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
-      const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
-      ++trials;
-      if (c <= c0 + T(1e-4) * alpha * gd) {
-        acc = tr;
-        break;
+        for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
+        const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
+        ++trials;
+        if (c <= c0 + T(1e-4) * alpha * gd) {
+          acc = tr;
+          break;
+        }
+        alpha *= T(0.5);
       }
-      alpha *= T(0.5);
+    } else {
+#if defined(__HIP_DEVICE_COMPILE__)
+      const int lane = threadIdx.x & 63, base = lane & ~(G - 1), q = lane & (G - 1);
+      for (int r = 0; r * G < o.ls_max && acc < 0; ++r) {
+        const int tr = G * r + q;
+        bool ok = false;
+        if (tr < o.ls_max) {
+          const T at = ldexp(T(1), -tr);
+#pragma unroll
+          for (int j = 0; j < NZ; ++j) zt[j] = z[j] + at * dl[j];
+          const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
+          ok = c <= c0 + T(1e-4) * at * gd;
+        }
+        ++trials;
+        const unsigned grp = (unsigned)((__ballot(ok) >> base) & ((1ull << G) - 1));
+        if (grp) acc = G * r + __builtin_ctz(grp);
+      }
+      if (acc >= 0) {
+        alpha = ldexp(T(1), -acc);
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
+      }
+#endif
     }
     if (acc >= 0) {
 #pragma unroll

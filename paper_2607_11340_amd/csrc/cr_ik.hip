@@ -672,11 +672,17 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
     WeightsT<double> wd = weights_to<double>(w0);
     LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
     const int64_t B2 = P * (int64_t)o.n_final;
-    if (sa.M > 0)
-      hipLaunchKernelGGL((k_ik_stage2<NS, T, true>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
-                         (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2,
-                         ws.cost2, ws.failed2);
-    else {
+    if (sa.M > 0) {
+      const int g2 = stage2_cfg_lanes(B2);
+#define CR_S2C(GL)                                                                                                    \
+  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, false, false, GL>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, \
+                     rbd, wd, lod, P, (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa,  \
+                     ws.z2, ws.cost2, ws.failed2)
+      if (g2 == 4) CR_S2C(4);
+      else if (g2 == 2) CR_S2C(2);
+      else CR_S2C(1);
+#undef CR_S2C
+    } else {
       auto launch2 = [&](int g) {
 #define CR_S2G(G)                                                                                                \
   hipLaunchKernelGGL((k_ik_stage2_grp<NS, T, G>), dim3(blocks_for(G * B2, 256)), dim3(256), 0, st, rbd, wd, lod, P, \

@@ -72,7 +72,9 @@ __global__ void __launch_bounds__(256)
 // Stage 2: FP64 refinement of the kept candidates, lambda restarted at lambda0.
 // ---------------------------------------------------------------------------
 
-template <int NS, typename T1, bool SPH, bool EXT = false, bool SELF = false>
+// G lanes per candidate (1, 2 or 4) try the line-search step lengths in
+// parallel (lm_cfg); the group leaves together and its first lane writes.
+template <int NS, typename T1, bool SPH, bool EXT = false, bool SELF = false, int G = 1>
 __global__ void __launch_bounds__(256)
     k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
                 const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
@@ -80,16 +82,20 @@ __global__ void __launch_bounds__(256)
                 int32_t* __restrict__ failed2) {
   constexpr int NZ = (EXT ? 3 : 2) * NS;
   const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = tg / G;
+  const bool lead = tg % G == 0;
   if (b >= B2) return;
   const int64_t p = b / nf;
   const int k = (int)(b % nf);
   const int s = sel[k * P + p];
   if (s < 0) {
+    if (lead) {
 #pragma unroll
-    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
-    cost2[b] = __builtin_nan("");
-    failed2[b] = 1;
+      for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = 0.0;
+      cost2[b] = __builtin_nan("");
+      failed2[b] = 1;
+    }
     return;
   }
   double tt[12];
@@ -104,17 +110,26 @@ __global__ void __launch_bounds__(256)
   double c;
   if (SPH || EXT || SELF) {
     const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
-    lm_cfg<NS, double, double, EXT, SELF>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+    lm_cfg<NS, double, double, EXT, SELF, G>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
     c = cfg_cost<NS, double, double, EXT, SELF>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
   } else {
     lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
     c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
   }
   if (!tfinite(c)) failed = true;
+  if (lead) {
 #pragma unroll
-  for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
-  cost2[b] = c;
-  failed2[b] = failed ? 1 : 0;
+    for (int m = 0; m < NZ; ++m) z2[m * B2 + b] = z[m];
+    cost2[b] = c;
+    failed2[b] = failed ? 1 : 0;
+  }
+}
+
+// lanes per stage-2 candidate with clearance rows: one wave per SIMD at most
+// (256 CUs x 4 SIMDs x 64 lanes), at most four
+static inline int stage2_cfg_lanes(int64_t B2) {
+  constexpr int64_t kLanes = 256 * 4 * 64;
+  return B2 * 4 <= kLanes ? 4 : (B2 * 2 <= kLanes ? 2 : 1);
 }
 
 
@@ -227,9 +242,15 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
     WeightsT<double> wd = weights_to<double>(w0);
     LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
     const int64_t B2 = P * (int64_t)o.n_final;
-    hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF>), dim3(blocks_for(B2, 256)), dim3(256), 0, st, rbd, wd, lod, P,
-                       (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, ws.cost2,
-                       ws.failed2);
+    const int g2 = stage2_cfg_lanes(B2);
+#define CR_S2C(GL)                                                                                                  \
+  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF, GL>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, rbd, \
+                     wd, lod, P, (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, \
+                     ws.cost2, ws.failed2)
+    if (g2 == 4) CR_S2C(4);
+    else if (g2 == 2) CR_S2C(2);
+    else CR_S2C(1);
+#undef CR_S2C
     rc = check_hip(hipGetLastError(), "k_ik_stage2");
     if (rc != CR_OK) return rc;
     if (timed) timer_mark(2, st);
