@@ -608,6 +608,49 @@ static void collision_rows(const cro_robot* rb, const cro_weights* w, const cro_
     }
 }
 
+/* Signed distance of point x to convex polytope j in half-space form: the largest
+ * of n_f.x - d_f over its planes (exact inside the polytope and in the region of
+ * each face outside it; below the distance near edges and corners outside).
+ * *arg receives the plane of the first largest value. */
+static double poly_sd(const cro_problem* pb, int j, const double* x, int* arg) {
+  double s = -INFINITY;
+  int a = 0;
+  for (int f = 0; f < pb->n_planes; f++) {
+    const double* P = pb->planes + 4 * ((size_t)j * pb->n_planes + f);
+    double v = P[0] * x[0] + P[1] * x[1] + P[2] * x[2] - P[3];
+    if (v > s) {
+      s = v;
+      a = f;
+    }
+  }
+  if (arg) *arg = a;
+  return s;
+}
+
+/* Polytope rows of one waypoint (convex obstacles, eq. 10 with the signed
+ * distance above): gap = sd(p) - r_i, r = sqrt(rho_coll) max(0, margin - gap),
+ * differentiated through the plane that attains the distance. */
+static void polytope_rows(const cro_robot* rb, const cro_weights* w, const cro_problem* pb, int t,
+                          dual (*pts)[3], sink* s) {
+  int n = rb->n_seg, K = rb->pts_per_seg;
+  double sq = sqrt(w->rho_coll);
+  for (int i = 0; i < n; i++)
+    for (int k = 0; k < K; k++) {
+      dual* P = pts[i * K + k];
+      double x[3] = {P[0].v, P[1].v, P[2].v};
+      for (int j = 0; j < pb->n_poly; j++) {
+        int f;
+        double gap = poly_sd(pb, j, x, &f) - rb->r[i];
+        if (!(w->margin - gap > 0.0)) continue;
+        const double* Q = pb->planes + 4 * ((size_t)j * pb->n_planes + f);
+        dual sd = dshift(dadd(dadd(dscale(Q[0], P[0]), dscale(Q[1], P[1])), dscale(Q[2], P[2])), -Q[3]);
+        dual viol = dsub(dcon(w->margin + rb->r[i]), sd);
+        term tm = {t, 1.0, &viol};
+        emit_lin(s, sq, 1, &tm);
+      }
+    }
+}
+
 /* Self-contact rows of one waypoint (eq. 10): every pair of backbone points p, q
  * of segments i and j >= i + 2, gap = |p - q| - r_i - r_j,
  * r = sqrt(rho_coll) max(0, margin - gap). */
@@ -650,7 +693,8 @@ static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_pr
   s->rows = 0;
   waypoint* wp = (waypoint*)malloc(sizeof(waypoint) * (size_t)(H + 1));
   dual(*pts)[3] = NULL;
-  if ((pb->n_sph > 0 || rb->self_collision) && K > 0) pts = (dual(*)[3])malloc(sizeof(dual[3]) * (size_t)(n * K));
+  if ((pb->n_sph > 0 || pb->n_poly > 0 || rb->self_collision) && K > 0)
+    pts = (dual(*)[3])malloc(sizeof(dual[3]) * (size_t)(n * K));
   double sq_lim = sqrt(w->rho_lim), sq_curv = sqrt(w->rho_curv);
 
   for (int t = 0; t <= H; t++) {
@@ -701,6 +745,7 @@ static double eval_terms(const cro_robot* rb, const cro_weights* w, const cro_pr
     }
     /* obstacle clearance and self contact, eq. (10) */
     if (pts && pb->n_sph > 0 && (terms & T_COLL)) collision_rows(rb, w, pb, t, pts, s);
+    if (pts && pb->n_poly > 0 && (terms & T_COLL)) polytope_rows(rb, w, pb, t, pts, s);
     if (pts && rb->self_collision && (terms & T_COLL)) self_rows(rb, w, t, pts, s);
   }
 
@@ -1011,10 +1056,12 @@ void cro_select_top(int S, int nz, const double* z, const double* e, const doubl
  * backbone point and sphere |p - c| - R - r_i and, with self contact, over every
  * pair of points of non-adjacent segments |p - q| - r_i - r_j.  INFINITY when
  * there is nothing to clear. */
-static double contact_gap(const cro_robot* rb, const double* sph, int n_sph, const double* u) {
+static double contact_gap(const cro_robot* rb, const double* sph, int n_sph, const double* u,
+                          const cro_problem* poly) {
   int n = rb->n_seg, K = rb->pts_per_seg;
   double gmin = INFINITY;
-  if ((n_sph <= 0 && !rb->self_collision) || K <= 0) return gmin;
+  int npoly = poly ? poly->n_poly : 0;
+  if ((n_sph <= 0 && npoly <= 0 && !rb->self_collision) || K <= 0) return gmin;
   double* P = (double*)malloc(sizeof(double) * 3 * (size_t)(n * K));
   double arc[3 * CRO_MAX_SEG];
   cro_fk(rb, u, arc, NULL, P);
@@ -1026,6 +1073,10 @@ static double contact_gap(const cro_robot* rb, const double* sph, int n_sph, con
         double dx = q[0] - S[0], dy = q[1] - S[1], dzz = q[2] - S[2];
         gmin = fmin(gmin, sqrt(dx * dx + dy * dy + dzz * dzz) - S[3] - rb->r[i]);
       }
+  /* convex polytopes: signed distance minus the body radius */
+  for (int i = 0; i < n; i++)
+    for (int k = 0; k < K; k++)
+      for (int j = 0; j < npoly; j++) gmin = fmin(gmin, poly_sd(poly, j, P + 3 * (i * K + k), NULL) - rb->r[i]);
   /* self contact between non-adjacent segments */
   for (int i = 0; i < n && rb->self_collision; i++)
     for (int j = i + 2; j < n; j++)
@@ -1075,7 +1126,7 @@ static int32_t assess(const cro_robot* rb, const cro_problem* pb, const double* 
       double th = sqrt(zt[zc * i] * zt[zc * i] + zt[zc * i + 1] * zt[zc * i + 1]);
       thx = fmax(thx, th - rb->theta_max);
     }
-    gmin = fmin(gmin, contact_gap(rb, pb->sph, pb->n_sph, u));
+    gmin = fmin(gmin, contact_gap(rb, pb->sph, pb->n_sph, u, pb));
   }
   err[0] = pos;
   err[1] = rot;
@@ -1321,7 +1372,7 @@ int32_t cro_sample_seed(const cro_robot* rb, const double* sph, int n_sph, const
         e = (rb->L_min[i] - rb->L[i]) + (rb->L_max[i] - rb->L_min[i]) * seed_uniform(key, p, s, a, j++);
       for (int k = 0; k < 3; k++) u[3 * i + k] = ub[k] + e;
     }
-    if (a + 1 >= max_attempts || !(contact_gap(rb, sph, n_sph, u) < 0.0)) break;
+    if (a + 1 >= max_attempts || !(contact_gap(rb, sph, n_sph, u, NULL) < 0.0)) break;
   }
-  return contact_gap(rb, sph, n_sph, u) < 0.0 ? -(a + 1) : a + 1;
+  return contact_gap(rb, sph, n_sph, u, NULL) < 0.0 ? -(a + 1) : a + 1;
 }

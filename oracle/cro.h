@@ -75,6 +75,11 @@ typedef struct {
   const double* task;    /* IK: T[12]; PATH: T[(H+1)*12]; TRAJ: u_start[3n], u_goal[3n] */
   int32_t n_sph;         /* number of spheres */
   const double* sph;     /* [n_sph][4]: cx, cy, cz, radius */
+  int32_t n_poly;        /* number of convex polytopes (IK only) */
+  int32_t n_planes;      /* planes per polytope */
+  const double* planes;  /* [n_poly][n_planes][4]: unit normal n and offset d of the
+                            half-space n.x <= d; a polytope is the intersection of its
+                            half-spaces (unused planes: n = 0, d large) */
 } cro_problem;
 
 #ifdef __cplusplus

@@ -62,7 +62,8 @@ class _Opts(C.Structure):
 
 class _Problem(C.Structure):
     _fields_ = [("kind", C.c_int32), ("H", C.c_int32), ("task", C.POINTER(C.c_double)),
-                ("n_sph", C.c_int32), ("sph", C.POINTER(C.c_double))]
+                ("n_sph", C.c_int32), ("sph", C.POINTER(C.c_double)),
+                ("n_poly", C.c_int32), ("n_planes", C.c_int32), ("planes", C.POINTER(C.c_double))]
 
 
 @dataclass
@@ -193,7 +194,9 @@ class Problem:
     """One task instance: kind 'ik' (task T[3,4]), 'path' (T[H+1,3,4]) or
     'traj' (u_start[n,3], u_goal[n,3]); optional spheres [M,4]."""
 
-    def __init__(self, kind: str, task, H: int = 0, spheres=None):
+    def __init__(self, kind: str, task, H: int = 0, spheres=None, polytopes=None):
+        """polytopes: None or [n_poly, n_planes, 4] half-spaces (unit normal, offset)
+        n.x <= d of convex obstacles."""
         self.kind, self.H = kind, int(H)
         if kind == "traj":
             us, ug = task
@@ -202,7 +205,9 @@ class Problem:
             self._task, p = _d(np.ravel(task))
         sph = np.zeros((0, 4)) if spheres is None else np.asarray(spheres, dtype=np.float64).reshape(-1, 4)
         self._sph, sp = _d(sph if len(sph) else np.zeros((1, 4)))
-        self.c = _Problem(KIND[kind], self.H, p, len(sph), sp)
+        pl = np.zeros((0, 1, 4)) if polytopes is None else np.asarray(polytopes, dtype=np.float64)
+        self._pl, pp = _d(pl if pl.size else np.zeros((1, 1, 4)))
+        self.c = _Problem(KIND[kind], self.H, p, len(sph), sp, len(pl), pl.shape[1] if len(pl) else 0, pp)
 
 
 def u_to_z(robot: Robot, u):
