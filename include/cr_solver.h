@@ -94,16 +94,34 @@ typedef struct {
                                  have no such pair). */
 } cr_robot;
 
-/* Spherical obstacles.  [host] struct, `sph` is [device] in the call's dtype for
- * cr_cost_grad and double for the solve calls: sph[c * ld + m], c = cx, cy, cz, radius.
- * per_problem = 0: one set of n_sph spheres shared by all problems;
- * per_problem = 1: problem p owns spheres m = p * n_sph .. p * n_sph + n_sph - 1. */
+/* Obstacles.  [host] struct; the arrays are [device], in the call's dtype for
+ * cr_cost_grad and double for the solve calls.
+ * Spheres: sph[c * ld + m], c = cx, cy, cz, radius.
+ * Convex polytopes (the convex pieces of Sec. V's obstacle model, in half-space
+ * form; IK only: cr_cost_grad with kind IK, cr_solve_ik, cr_solve_ik_static):
+ *   polytope j is the intersection of n_planes half-spaces n . x <= d; plane f of
+ *   polytope j has components c = nx, ny, nz, d at planes[c * plane_ld + j *
+ *   n_planes + f] (unit normals; an unused plane is n = 0 with a large d).  A
+ *   backbone point x of segment i clears it when sd(x) - r_i >= 0 with the signed
+ *   distance sd(x) = max_f (n_f . x - d_f) (exact inside and in the region of each
+ *   face outside; below the distance near edges and corners outside); the
+ *   clearance hinge of eq. (10) uses margin - (sd(x) - r_i).  Not supported with
+ *   extensible segments or self contact (CR_EINVAL).
+ * per_problem = 0: one set of obstacles shared by all problems;
+ * per_problem = 1: problem p owns spheres m = p * n_sph .. p * n_sph + n_sph - 1
+ *   and polytopes p * n_poly .. p * n_poly + n_poly - 1.
+ * Zero-initialise the struct: n_sph = n_poly = 0 means no obstacles. */
 typedef struct {
   int32_t n_sph;
   int32_t per_problem;
   const void* sph;
   int64_t ld;
-} cr_spheres;
+  int32_t n_poly;      /* polytopes per problem (or shared), 0..256 */
+  int32_t n_planes;    /* planes per polytope, 1..32 */
+  const void* planes;
+  int64_t plane_ld;
+} cr_obstacles;
+typedef cr_obstacles cr_spheres;
 
 /* Weights of the penalised cost, eq. (17).  [host] */
 typedef struct {

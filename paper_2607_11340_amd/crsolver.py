@@ -50,7 +50,8 @@ class _Robot(C.Structure):
 
 
 class _Spheres(C.Structure):
-    _fields_ = [("n_sph", C.c_int32), ("per_problem", C.c_int32), ("sph", C.c_void_p), ("ld", C.c_int64)]
+    _fields_ = [("n_sph", C.c_int32), ("per_problem", C.c_int32), ("sph", C.c_void_p), ("ld", C.c_int64),
+                ("n_poly", C.c_int32), ("n_planes", C.c_int32), ("planes", C.c_void_p), ("plane_ld", C.c_int64)]
 
 
 class _Problem(C.Structure):
@@ -241,14 +242,30 @@ def _need(t, shape, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _spheres_c(spheres, dtype) -> _Spheres:
-    """spheres: None, or (tensor [4, M] shared) or (tensor [4, M*P], per_problem=True)."""
-    if spheres is None:
-        return _Spheres(0, 0, None, 0)
-    t, per_problem, M = spheres
-    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.shape[0] != 4:
-        raise ValueError("spheres must be a contiguous CUDA tensor [4, ld] of the call's dtype")
-    return _Spheres(int(M), 1 if per_problem else 0, C.c_void_p(t.data_ptr()), int(t.shape[1]))
+def _spheres_c(spheres, dtype, polytopes=None) -> _Spheres:
+    """spheres: None, or (tensor [4, M] shared) or (tensor [4, M*P], per_problem=True).
+    polytopes (convex obstacles, IK only): None, or (tensor [4, ld], per_problem,
+    n_poly, n_planes): plane f of polytope j at column j*n_planes + f (+ p*n_poly*
+    n_planes per problem), rows nx, ny, nz, d of the half-space n.x <= d."""
+    out = _Spheres(0, 0, None, 0, 0, 0, None, 0)
+    pp = None
+    if spheres is not None:
+        t, per_problem, M = spheres
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.shape[0] != 4:
+            raise ValueError("spheres must be a contiguous CUDA tensor [4, ld] of the call's dtype")
+        out.n_sph, out.sph, out.ld = int(M), C.c_void_p(t.data_ptr()), int(t.shape[1])
+        pp = bool(per_problem)
+    if polytopes is not None:
+        t, per_problem, n_poly, n_planes = polytopes
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.shape[0] != 4:
+            raise ValueError("polytopes must be a contiguous CUDA tensor [4, ld] of the call's dtype")
+        if pp is not None and pp != bool(per_problem):
+            raise ValueError("spheres and polytopes must agree on per_problem")
+        out.n_poly, out.n_planes = int(n_poly), int(n_planes)
+        out.planes, out.plane_ld = C.c_void_p(t.data_ptr()), int(t.shape[1])
+        pp = bool(per_problem)
+    out.per_problem = 1 if pp else 0
+    return out
 
 
 def fk(robot: Robot, u: torch.Tensor, arc=True, frames=True, points=False):
@@ -295,7 +312,8 @@ def sample_seeds(robot: Robot, P: int, S: int, key=(0, 0), max_attempts: int = 8
 
 
 def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,
-             opts: Opts = None, dtype=torch.float32, spheres=None, workspace: torch.Tensor = None, out=None):
+             opts: Opts = None, dtype=torch.float32, spheres=None, workspace: torch.Tensor = None, out=None,
+             polytopes=None):
     """Two-stage IK (Algorithm 1).  T_target [12, P] float64, u_seed [3n, S*P] float64
     (column p*S + s).  `dtype` is the stage-1 precision.  Returns (u [3n, P],
     err [2, P] (position m, rotation rad), status [P] int32)."""
@@ -313,7 +331,7 @@ def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights
                torch.empty((P,), dtype=torch.int32, device=dev))
     u_out, err, st = out
     rc, wc, oc = robot.c(), weights.c(), opts.c()
-    sc = _spheres_c(spheres, torch.float64)
+    sc = _spheres_c(spheres, torch.float64, polytopes)
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
@@ -327,7 +345,7 @@ STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def solve_ik_static(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,
-                    opts: Opts = None, dtype=torch.float32, spheres=None, out=None):
+                    opts: Opts = None, dtype=torch.float32, spheres=None, out=None, polytopes=None):
     """solve_ik through cr_solve_ik_static: no workspace and no device allocation
     inside the call (its scratch is the library's static per-GPU buffer).  `out`
     (u, err, status) must be given by callers that cannot allocate; when None,
@@ -346,7 +364,7 @@ def solve_ik_static(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, 
                torch.empty((P,), dtype=torch.int32, device=dev))
     u_out, err, st = out
     rc, wc, oc = robot.c(), weights.c(), opts.c()
-    sc = _spheres_c(spheres, torch.float64)
+    sc = _spheres_c(spheres, torch.float64, polytopes)
     _check(lib.cr_solve_ik_static(C.byref(rc), C.byref(sc), P, _ptr(T_target), S, _ptr(u_seed), C.byref(wc),
                                   C.byref(oc), _ptr(u_out), _ptr(err), _ptr(st), _dt(dtype), _stream(T_target)))
     return u_out, err, st
@@ -557,7 +575,8 @@ def select_top(z: torch.Tensor, e: torch.Tensor, pen: torch.Tensor, failed, P: i
 class CostProblem:
     """A batch of P problems x S seeds x (H+1) waypoints for cr_cost_grad.
     task: IK [12, P] poses; PATH [12, (H+1)*P] reference poses (column p*(H+1)+t);
-    TRAJ [6n, P] (u_start then u_goal).  spheres: None or (tensor [4, ld], per_problem, M)."""
+    TRAJ [6n, P] (u_start then u_goal).  spheres: None or (tensor [4, ld], per_problem, M).
+    polytopes (IK only): None or (tensor [4, ld], per_problem, n_poly, n_planes)."""
     robot: Robot
     kind: str
     P: int
@@ -566,6 +585,7 @@ class CostProblem:
     task: torch.Tensor
     weights: Weights = field(default_factory=Weights)
     spheres: tuple = None
+    polytopes: tuple = None
 
 
 def cost_grad(pb: CostProblem, u: torch.Tensor, grad: bool = True, grad_scale: torch.Tensor = None):
@@ -581,7 +601,7 @@ def cost_grad(pb: CostProblem, u: torch.Tensor, grad: bool = True, grad_scale: t
     if grad_scale is not None:
         _need(grad_scale, (pb.S * pb.P,), u.dtype, "grad_scale")
     rc, wc = pb.robot.c(), pb.weights.c()
-    sc = _spheres_c(pb.spheres, u.dtype)
+    sc = _spheres_c(pb.spheres, u.dtype, pb.polytopes)
     _check(lib.cr_cost_grad(KIND[pb.kind], C.byref(rc), C.byref(sc), C.byref(wc), pb.P, pb.H, pb.S,
                             _ptr(pb.task), _ptr(u), _ptr(cost), _ptr(g), _ptr(grad_scale), dt, _stream(u)))
     return (cost, g) if grad else cost

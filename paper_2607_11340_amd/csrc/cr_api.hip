@@ -188,12 +188,30 @@ cr_status check_weights(const cr_weights* w) {
 }
 
 cr_status check_spheres(const cr_spheres* spheres, int64_t P) {
-  if (!spheres || spheres->n_sph == 0) return CR_OK;
+  if (!spheres) return CR_OK;
+  if (spheres->n_poly != 0) {
+    if (spheres->n_poly < 0 || spheres->n_poly > 256) return fail(CR_EINVAL, "n_poly=%d not in 0..256", spheres->n_poly);
+    if (spheres->n_planes < 1 || spheres->n_planes > 32)
+      return fail(CR_EINVAL, "n_planes=%d not in 1..32", spheres->n_planes);
+    if (!spheres->planes) return fail(CR_EINVAL, "obstacles->planes is NULL");
+    const int64_t per = (int64_t)spheres->n_poly * spheres->n_planes;
+    if (spheres->plane_ld < (spheres->per_problem ? per * P : per)) return fail(CR_EINVAL, "obstacles->plane_ld too small");
+  }
+  if (spheres->n_sph == 0) return CR_OK;
   if (spheres->n_sph < 0) return fail(CR_EINVAL, "n_sph < 0");
   if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
   if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
   const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
   if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld too small");
+  return CR_OK;
+}
+
+// convex polytopes: IK only, inextensible robots without self contact
+cr_status check_poly_ok(const cr_obstacles* obst, const cr_robot* rb, bool ik, const char* who) {
+  if (!obst || obst->n_poly == 0) return CR_OK;
+  if (!ik) return fail(CR_EINVAL, "%s: convex polytopes are supported for IK only", who);
+  if (rb && (rb->extensible || rb->self_collision))
+    return fail(CR_EINVAL, "%s: convex polytopes are not supported with extensible segments or self contact", who);
   return CR_OK;
 }
 
@@ -248,7 +266,8 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   if (P * (int64_t)S > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "P*S too large");
   if (P == 0) return CR_OK;
   if (!T_target || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
-  if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
+  if ((rc = check_spheres(spheres, P)) != CR_OK || (rc = check_poly_ok(spheres, robot, true, "cr_solve_ik")) != CR_OK)
+    return rc;
   size_t need = ik_workspace_layout(*robot, P, S, *opts, dtype, nullptr, nullptr);
   void* mem = ws;
   if (ws) {
@@ -260,7 +279,7 @@ cr_status cr_solve_ik(const cr_robot* robot, const cr_spheres* spheres, int64_t 
   }
   IkWorkspace w;
   ik_workspace_layout(*robot, P, S, *opts, dtype, (char*)mem, &w);
-  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  const cr_spheres* sp = (spheres && (spheres->n_sph > 0 || spheres->n_poly > 0)) ? spheres : nullptr;
   rc = launch_solve_ik(*robot, sp, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
                        (double*)u_out, (double*)err_out, status_out, w, dtype, stream);
   if (!ws) {
@@ -279,6 +298,7 @@ cr_status cr_sample_seeds(const cr_robot* robot, const cr_spheres* spheres, int6
   if (P > ((int64_t)1 << 40) / S) return fail(CR_EINVAL, "P * S too large");
   if (max_attempts < 1 || max_attempts > 64) return fail(CR_EINVAL, "max_attempts=%d not in 1..64", max_attempts);
   if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
+  if (spheres && spheres->n_poly) return fail(CR_EINVAL, "cr_sample_seeds: convex polytopes are not supported");
   if (P == 0) return CR_OK;
   if (!u_out) return fail(CR_EINVAL, "u_out is NULL");
   return launch_sample_seeds(*robot, spheres, P, S, key0, key1, max_attempts, u_out, attempts_out, stream);
@@ -307,6 +327,7 @@ static cr_status check_traj_args(const cr_robot* robot, const cr_spheres* sphere
     return rc;
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
   if (H < (kind == CR_KIND_TRAJ ? 1 : 0) || H > 255) return fail(CR_EINVAL, "H=%d out of range", H);
+  if (spheres && spheres->n_poly) return fail(CR_EINVAL, "paths and trajectories: convex polytopes are not supported");
   if (P * (int64_t)S * (H + 1) > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "batch too large");
   return check_spheres(spheres, P);
 }
@@ -328,7 +349,7 @@ static cr_status solve_traj_common(int kind, const cr_robot* robot, const cr_sph
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
     if (rc != CR_OK) return rc;
   }
-  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  const cr_spheres* sp = (spheres && (spheres->n_sph > 0 || spheres->n_poly > 0)) ? spheres : nullptr;
   rc = launch_solve_traj(kind, *robot, sp, P, H, (const double*)task, S, (const double*)u_seed, *weights, *opts,
                          (double*)u_out, (double*)err_out, status_out, mem, dtype, stream);
   if (!ws) {
@@ -361,6 +382,7 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres,
     return rc;
   if (P < 0 || S < 1 || S > 4096) return fail(CR_EINVAL, "need P >= 0 and 1 <= S <= 4096");
   if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
+  if (spheres && spheres->n_poly) return fail(CR_EINVAL, "cr_baseline_solve_ik: convex polytopes are not supported");
   if (P == 0) return CR_OK;
   if (!T_target || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
   const size_t need = b0_workspace_bytes(*robot, S, *opts);
@@ -372,7 +394,7 @@ cr_status cr_baseline_solve_ik(const cr_robot* robot, const cr_spheres* spheres,
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
     if (rc != CR_OK) return rc;
   }
-  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  const cr_spheres* sp = (spheres && (spheres->n_sph > 0 || spheres->n_poly > 0)) ? spheres : nullptr;
   rc = launch_b0_ik(*robot, sp, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
                     (double*)u_out, (double*)err_out, status_out, mem, stream);
   if (!ws) {
@@ -400,7 +422,7 @@ static cr_status baseline_traj_common(int kind, const cr_robot* robot, const cr_
     rc = check_hip(hipMallocAsync(&mem, need, stream), "hipMallocAsync(workspace)");
     if (rc != CR_OK) return rc;
   }
-  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  const cr_spheres* sp = (spheres && (spheres->n_sph > 0 || spheres->n_poly > 0)) ? spheres : nullptr;
   rc = launch_b0_traj(kind, *robot, sp, P, H, (const double*)task, S, (const double*)u_seed, *weights, *opts,
                       (double*)u_out, (double*)err_out, status_out, mem, stream);
   if (!ws) {
@@ -507,14 +529,9 @@ cr_status cr_cost_grad(int32_t kind, const cr_robot* robot, const cr_spheres* sp
   if (P * (int64_t)S * (H + 1) > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "batch too large");
   if (P == 0) return CR_OK;
   if (!task || !u || !cost) return fail(CR_EINVAL, "NULL array argument");
-  if (spheres && spheres->n_sph > 0) {
-    if (spheres->n_sph > 512) return fail(CR_EINVAL, "n_sph=%d exceeds 512", spheres->n_sph);
-    if (!spheres->sph) return fail(CR_EINVAL, "spheres->sph is NULL");
-    const int64_t need = spheres->per_problem ? (int64_t)spheres->n_sph * P : spheres->n_sph;
-    if (spheres->ld < need) return fail(CR_EINVAL, "spheres->ld=%lld < %lld", (long long)spheres->ld, (long long)need);
-  } else if (spheres && spheres->n_sph < 0) {
-    return fail(CR_EINVAL, "n_sph < 0");
-  }
+  if ((rc = check_spheres(spheres, P)) != CR_OK ||
+      (rc = check_poly_ok(spheres, robot, kind == CR_KIND_IK, "cr_cost_grad")) != CR_OK)
+    return rc;
   return launch_cost_grad(kind, *robot, spheres, *weights, P, H, S, task, u, cost, grad, grad_scale, dtype, stream);
 }
 

@@ -27,11 +27,12 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 }
 
 // EXT: extensible segments, the third coordinate e_i = mean_j u_ij per segment.
-template <int NS, typename T, bool GRAD, bool EXT = false, bool SELF = false>
+// POLY: convex polytopes (pl, NPO polytopes of F planes per problem or shared).
+template <int NS, typename T, bool GRAD, bool EXT = false, bool SELF = false, bool POLY = false>
 __global__ void __launch_bounds__(256)
     k_cost_ik(RobotT<T> rb, WeightsT<T> w, int64_t P, int S, const T* __restrict__ task, const T* __restrict__ sph,
               int64_t sld, int M, int per_problem, const T* __restrict__ u, T* __restrict__ cost, T* __restrict__ grad,
-              const T* __restrict__ gscale) {
+              const T* __restrict__ gscale, const T* __restrict__ pl, int64_t pld, int NPO, int F) {
   constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
   const int64_t B = P * (int64_t)S;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,7 +50,8 @@ __global__ void __launch_bounds__(256)
   for (int c = 0; c < 12; ++c) tt[c] = task[c * P + p];
   Fwd<NS, T, EXT> f;
   const T* sp = sph ? sph + (per_problem ? p * M : 0) : nullptr;
-  T c = config_forward<NS, T, GRAD, T, T, EXT, SELF>(rb, w, z, sp, (sph && M > 0) ? M : 0, 1, sld, f);
+  const PolyArgs<T> po{NPO > 0 ? pl + (per_problem ? p * NPO * F : 0) : nullptr, pld, NPO, F};
+  T c = config_forward<NS, T, GRAD, T, T, EXT, SELF, POLY>(rb, w, z, sp, (sph && M > 0) ? M : 0, 1, sld, f, nullptr, po);
   T ft[3] = {T(0), T(0), T(0)}, tq[3] = {T(0), T(0), T(0)};
   c += pose_term<T, GRAD>(w, f.R, f.p, tt, ft, tq);
   cost[b] = c;
@@ -236,23 +238,31 @@ static cr_status run_cost(int kind, const cr_robot& rb0, const cr_spheres* sp, c
   const int M = sp ? sp->n_sph : 0;
   const T* sph = M > 0 ? (const T*)sp->sph : nullptr;
   const int64_t sld = M > 0 ? sp->ld : 0;
-  const int ppb = M > 0 ? sp->per_problem : 0;
+  const int NPO = sp ? sp->n_poly : 0;
+  const int ppb = (M > 0 || NPO > 0) ? sp->per_problem : 0;
+  const T* pl = NPO > 0 ? (const T*)sp->planes : nullptr;
+  const int64_t pld = NPO > 0 ? sp->plane_ld : 0;
+  const int F = NPO > 0 ? sp->n_planes : 0;
   const int64_t B = P * (int64_t)S;
   if (B == 0) return CR_OK;
   if (kind == CR_KIND_IK) {
     const unsigned nb = (unsigned)((B + 255) / 256);
-#define CR_COST_IK(G, E, SF)                                                                                     \
-  hipLaunchKernelGGL((k_cost_ik<NS, T, G, E, SF>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, sld, \
-                     M, ppb, (const T*)u, (T*)cost, G ? (T*)grad : (T*)nullptr, G ? (const T*)gscale : (const T*)nullptr)
-#define CR_COST_IK2(E, SF)       \
-  do {                           \
-    if (grad)                    \
-      CR_COST_IK(true, E, SF);   \
-    else                         \
-      CR_COST_IK(false, E, SF);  \
+#define CR_COST_IK(G, E, SF, PO)                                                                                   \
+  hipLaunchKernelGGL((k_cost_ik<NS, T, G, E, SF, PO>), dim3(nb), dim3(256), 0, st, rb, w, P, S, (const T*)task, sph, \
+                     sld, M, ppb, (const T*)u, (T*)cost, G ? (T*)grad : (T*)nullptr,                                 \
+                     G ? (const T*)gscale : (const T*)nullptr, pl, pld, NPO, F)
+#define CR_COST_IK2(E, SF)              \
+  do {                                  \
+    if (grad)                           \
+      CR_COST_IK(true, E, SF, false);   \
+    else                                \
+      CR_COST_IK(false, E, SF, false);  \
   } while (0)
     const bool self = rb0.self_collision && NS >= 3;
-    if (rb0.extensible && self) CR_COST_IK2(true, true);
+    if (NPO > 0) {  // convex polytopes: inextensible robots without self contact
+      if (grad) CR_COST_IK(true, false, false, true);
+      else CR_COST_IK(false, false, false, true);
+    } else if (rb0.extensible && self) CR_COST_IK2(true, true);
     else if (rb0.extensible) CR_COST_IK2(true, false);
     else if (self) CR_COST_IK2(false, true);
     else CR_COST_IK2(false, false);

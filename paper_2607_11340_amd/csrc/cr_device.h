@@ -820,6 +820,37 @@ struct Fwd {
   T gz[NZ];                          // direct gradient terms (own arc, bounds)
 };
 
+// Convex polytopes in half-space form (convex obstacles): polytope j of a problem
+// is the intersection of its F half-spaces n.x <= d, plane f of polytope j with
+// component c (nx, ny, nz, d; unit normals) at pl[c * ld + j * F + f].  Signed
+// distance sd(x) = max_f (n_f . x - d_f): exact inside the polytope and in the
+// region of each face outside it, below the distance near edges and corners
+// outside; it is 1-Lipschitz (unit normals).  Unused planes are n = 0, d large.
+template <typename TS>
+struct PolyArgs {
+  const TS* pl;
+  int64_t ld;
+  int NP, F;
+};
+
+// sd of x to polytope j; *arg = the plane of the first largest value
+template <typename TC, typename TS>
+CR_HD TC poly_sd(const PolyArgs<TS>& po, int j, const TC* x, int* arg) {
+  TC s = TC(0);
+  int a = 0;
+  for (int f = 0; f < po.F; ++f) {
+    const int64_t col = (int64_t)j * po.F + f;
+    const TC v = (TC)po.pl[col] * x[0] + (TC)po.pl[po.ld + col] * x[1] + (TC)po.pl[2 * po.ld + col] * x[2] -
+                 (TC)po.pl[3 * po.ld + col];
+    if (f == 0 || v > s) {
+      s = v;
+      a = f;
+    }
+  }
+  if (arg) *arg = a;
+  return s;
+}
+
 // Sphere m, component c (cx, cy, cz, radius) is read as sph[m * ms + c * cs].
 // zd (NC NS, FP64) or NULL: the coordinates in FP64 when the caller has them (z
 // is their rounding to T); a TC chain starts from them.
@@ -923,9 +954,12 @@ CR_HD T self_contact(const RobotT<T>& rb, const WeightsT<T>& w, int j, const TC 
   return cost;
 }
 
-template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T, bool EXT = false, bool SELF = false>
+// POLY: clearance rows against the convex polytopes of po as well.
+template <int NS, typename T, bool GRAD, typename TC = T, typename TS = T, bool EXT = false, bool SELF = false,
+          bool POLY = false>
 CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
-                       int64_t cs, Fwd<NS, T, EXT>& f, const double* zd = nullptr) {
+                       int64_t cs, Fwd<NS, T, EXT>& f, const double* zd = nullptr,
+                       const PolyArgs<TS>& po = PolyArgs<TS>{nullptr, 0, 0, 0}) {
   constexpr int NC = EXT ? 3 : 2;
   T cost = T(0);
   TC Rc[9], pc[3];
@@ -1039,6 +1073,57 @@ CR_HD T config_forward(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, co
                 const TC dde[3] = {sg * ck.A * sa, sg * ck.A * sb, sg * ck.B};
                 f.gz[NC * i + 2] += (T)dot3(q, dde);
               }
+            }
+          }
+        }
+      }
+    }
+    if constexpr (POLY) {
+      // backbone points of this segment against every convex polytope: sd is
+      // 1-Lipschitz and every point lies within L_i / 2 of the arc midpoint, so a
+      // polytope farther than L_i / 2 + r_i + margin from it is skipped
+      const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
+      const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
+      const TC sqc = (TC)w.sq_coll;
+      TC xm[3];
+      seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xm);
+      for (int jp = 0; jp < po.NP; ++jp) {
+        if (poly_sd<TC>(po, jp, xm, (int*)nullptr) - TC(0.5) * Lc - ri - marg > TC(1e-6)) continue;
+        for (int k = 1; k <= K; ++k) {
+          const TC sg = TC(k) / TC(K);
+          ArcCoef<TC> ck = arc_coef<TC, GRAD>(sg * sg * s);
+          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+          TC x[3];
+          mv3(Rc, dk, x);
+          x[0] += pc[0];
+          x[1] += pc[1];
+          x[2] += pc[2];
+          int fa;
+          const TC viol = marg + ri - poly_sd<TC>(po, jp, x, &fa);
+          if (!(viol > TC(0))) continue;
+          const TC rr = sqc * viol;
+          cost += (T)(TC(0.5) * rr * rr);
+          if (GRAD) {
+            // d(1/2 r^2)/dx = -sq_coll r n_f of the plane that attains sd
+            const int64_t col = (int64_t)jp * po.F + fa;
+            const TC sc = -sqc * rr;
+            const TC fx[3] = {sc * (TC)po.pl[col], sc * (TC)po.pl[po.ld + col], sc * (TC)po.pl[2 * po.ld + col]};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) f.F[i][q] += (T)fx[q];
+            TC mx[3];
+            cross3(x, fx, mx);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) f.Mo[i][q] += (T)mx[q];
+            TC q[3];
+            mtv3(Rc, fx, q);
+            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+            f.gz[NC * i] += (T)(sg * dot3(q, dda));
+            f.gz[NC * i + 1] += (T)(sg * dot3(q, ddb));
+            if constexpr (EXT) {
+              const TC dde[3] = {sg * ck.A * sa, sg * ck.A * sb, sg * ck.B};
+              f.gz[NC * i + 2] += (T)dot3(q, dde);
             }
           }
         }
@@ -1291,9 +1376,10 @@ CR_HD T pose_rows(const WeightsT<T>& w, const T* Rc, const T* pc, T (*W)[3], T (
 // Hp (packed lower, 2NS), g are overwritten.  ptip[3] and Jp[3][2NS] receive the
 // tip position and its Jacobian.  Pose rows against Tt only if pose.  TC is the
 // chain type (as in config_forward).
-template <int NS, typename T, typename TC, typename TS = T, bool EXT = false, bool SELF = false>
+template <int NS, typename T, typename TC, typename TS = T, bool EXT = false, bool SELF = false, bool POLY = false>
 CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, const TS* sph, int M, int64_t ms,
-                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[(EXT ? 3 : 2) * NS], bool pose = true) {
+                        int64_t cs, const T* Tt, T* Hp, T* g, T* ptip, T (*Jp)[(EXT ? 3 : 2) * NS], bool pose = true,
+                        const PolyArgs<TS>& po = PolyArgs<TS>{nullptr, 0, 0, 0}) {
   constexpr int NC = EXT ? 3 : 2, NZ = NC * NS, NP = NZ * (NZ + 1) / 2;
 #pragma unroll
   for (int k = 0; k < NP; ++k) Hp[k] = T(0);
@@ -1522,6 +1608,70 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
         }
       }
     }
+    if constexpr (POLY) {
+      // convex-polytope rows (culling as in config_forward): residual
+      // sq_coll (margin + r_i - sd(x)), row = -sq_coll n_f^T dx/dz
+      const TC ri = sizeof(TC) == 8 ? (TC)rb.rd[i] : (TC)rb.r[i];
+      const TC marg = sizeof(TC) == 8 ? (TC)w.margind : (TC)w.margin;
+      TC xm[3];
+      seg_point(Rc, pc, ac, bc, Lc, s, TC(0.5), xm);
+      for (int jp = 0; jp < po.NP; ++jp) {
+        if (poly_sd<TC>(po, jp, xm, (int*)nullptr) - TC(0.5) * Lc - ri - marg > TC(1e-6)) continue;
+        for (int k = 1; k <= K; ++k) {
+          const TC sg = TC(k) / TC(K);
+          ArcCoef<TC> ck = arc_coef<TC, true>(sg * sg * s);
+          const TC sa = sg * ac, sb = sg * bc, sL = sg * Lc;
+          TC dk[3] = {sL * ck.A * sa, sL * ck.A * sb, sL * ck.B};
+          TC x[3];
+          mv3(Rc, dk, x);
+          x[0] += pc[0];
+          x[1] += pc[1];
+          x[2] += pc[2];
+          int fa;
+          const TC viol = marg + ri - poly_sd<TC>(po, jp, x, &fa);
+          if (!(viol > TC(0))) continue;
+          const T rr = (T)((TC)w.sq_coll * viol);
+          const T xf[3] = {(T)x[0], (T)x[1], (T)x[2]};
+          const int64_t col = (int64_t)jp * po.F + fa;
+          // sd grows along the plane normal: the residual falls along it
+          T nvec[3] = {(T)po.pl[col], (T)po.pl[po.ld + col], (T)po.pl[2 * po.ld + col]};
+          T row[NZ];
+#pragma unroll
+          for (int q = 0; q < NZ; ++q) row[q] = T(0);
+#pragma unroll
+          for (int j = 0; j < NS; ++j) {
+            if (j < i) {
+              T xmj[3] = {xf[0] - pe[j][0], xf[1] - pe[j][1], xf[2] - pe[j][2]}, c3[3];
+              cross3(xmj, nvec, c3);
+#pragma unroll
+              for (int c = 0; c < NC; ++c)
+                row[NC * j + c] = -w.sq_coll * (dot3(W[NC * j + c], c3) + dot3(Pd[NC * j + c], nvec));
+            }
+          }
+          {
+            TC nq[3] = {(TC)nvec[0], (TC)nvec[1], (TC)nvec[2]}, q[3];
+            mtv3(Rc, nq, q);
+            const TC dda[3] = {sL * (ck.A + TC(2) * sa * sa * ck.Ap), sL * TC(2) * sa * sb * ck.Ap, sL * TC(2) * sa * ck.Bp};
+            const TC ddb[3] = {sL * TC(2) * sa * sb * ck.Ap, sL * (ck.A + TC(2) * sb * sb * ck.Ap), sL * TC(2) * sb * ck.Bp};
+            row[NC * i] = (T)(-(TC)w.sq_coll * sg * dot3(q, dda));
+            row[NC * i + 1] = (T)(-(TC)w.sq_coll * sg * dot3(q, ddb));
+            if constexpr (EXT) {
+              const TC dde[3] = {sg * ck.A * sa, sg * ck.A * sb, sg * ck.B};
+              row[NC * i + 2] = (T)(-(TC)w.sq_coll * dot3(q, dde));
+            }
+          }
+          cost += T(0.5) * rr * rr;
+#pragma unroll
+          for (int k1 = 0; k1 < NZ; ++k1) {
+            if (k1 <= NC * i + NC - 1) {
+              g[k1] += row[k1] * rr;
+#pragma unroll
+              for (int k2 = 0; k2 <= k1; ++k2) Hp[tri(k1, k2)] += row[k1] * row[k2];
+            }
+          }
+        }
+      }
+    }
     ArcCoef<TC> c = arc_coef<TC, true>(s);
     TC Ri[9], di[3];
     seg_R_d(ac, bc, Lc, c, Ri, di);
@@ -1595,11 +1745,11 @@ CR_HD T local_normal_eq(const RobotT<T>& rb, const WeightsT<T>& w, const T* z, c
 // Penalised cost of one configuration against a target pose (eq. 8-10, 17):
 // pose, bounds and clearance against M spheres (sphere m, component c at
 // sph[m * ms + c * cs], stored as TS).
-template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false>
+template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false, bool POLY = false>
 CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T* z, const TS* sph, int M, int64_t ms,
-                 int64_t cs) {
+                 int64_t cs, const PolyArgs<TS>& po = PolyArgs<TS>{nullptr, 0, 0, 0}) {
   Fwd<NS, T, EXT> f;
-  T c = config_forward<NS, T, false, T, TS, EXT, SELF>(rb, w, z, sph, M, ms, cs, f);
+  T c = config_forward<NS, T, false, T, TS, EXT, SELF, POLY>(rb, w, z, sph, M, ms, cs, f, nullptr, po);
   T ft[3], tq[3];
   return c + pose_term<T, false>(w, f.R, f.p, Tt, ft, tq);
 }
@@ -1610,14 +1760,15 @@ CR_HD T cfg_cost(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, const T
 // configuration and try G step lengths of the line search at once, lane q taking
 // 2^-(G r + q) in round r; a ballot over the group takes the first accepted one,
 // the sequential search's choice, so the iterates do not depend on G.
-template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false, int G = 1>
+template <int NS, typename T, typename TS, bool EXT = false, bool SELF = false, int G = 1, bool POLY = false>
 CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, T& lam, int iters, const LMOpts<T>& o,
-                  bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs) {
+                  bool& failed, int& trials, const TS* sph, int M, int64_t ms, int64_t cs,
+                  const PolyArgs<TS>& po = PolyArgs<TS>{nullptr, 0, 0, 0}) {
   constexpr int NZ = (EXT ? 3 : 2) * NS;
   constexpr int NP = NZ * (NZ + 1) / 2;
   for (int it = 0; it < iters; ++it) {
     T Hp[NP], g[NZ], dl[NZ], ptip[3], Jp[3][NZ];
-    const T c0 = local_normal_eq<NS, T, T, TS, EXT, SELF>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp);
+    const T c0 = local_normal_eq<NS, T, T, TS, EXT, SELF, POLY>(rb, w, z, sph, M, ms, cs, Tt, Hp, g, ptip, Jp, true, po);
     if (!tfinite(c0)) {
       failed = true;
       break;
@@ -1643,7 +1794,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
       for (int tr = 0; tr < o.ls_max; ++tr) {
 #pragma unroll
         for (int j = 0; j < NZ; ++j) zt[j] = z[j] + alpha * dl[j];
-        const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
+        const T c = cfg_cost<NS, T, TS, EXT, SELF, POLY>(rb, w, Tt, zt, sph, M, ms, cs, po);
         ++trials;
         if (c <= c0 + T(1e-4) * alpha * gd) {
           acc = tr;
@@ -1661,7 +1812,7 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
           const T at = ldexp(T(1), -tr);
 #pragma unroll
           for (int j = 0; j < NZ; ++j) zt[j] = z[j] + at * dl[j];
-          const T c = cfg_cost<NS, T, TS, EXT, SELF>(rb, w, Tt, zt, sph, M, ms, cs);
+          const T c = cfg_cost<NS, T, TS, EXT, SELF, POLY>(rb, w, Tt, zt, sph, M, ms, cs, po);
           ok = c <= c0 + T(1e-4) * at * gd;
         }
         ++trials;
@@ -1690,8 +1841,9 @@ CR_HD void lm_cfg(const RobotT<T>& rb, const WeightsT<T>& w, const T* Tt, T* z, 
 // its segment's radius (clearance < 0, margin 0); spheres are FP64, sphere m
 // component c at sph[c * ld + m].  A sphere whose distance to a segment's arc
 // midpoint exceeds L_i / 2 + R + r_i cannot touch the segment.
-template <int NS, typename T, bool EXT = false, bool SELF = false>
-CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M, int64_t ld) {
+template <int NS, typename T, bool EXT = false, bool SELF = false, bool POLY = false>
+CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M, int64_t ld,
+                      const PolyArgs<double>& po = PolyArgs<double>{nullptr, 0, 0, 0}) {
   constexpr int NC = EXT ? 3 : 2;
   T Rp[9], pp[3];
 #pragma unroll
@@ -1736,6 +1888,16 @@ CR_HD bool penetrates(const RobotT<T>& rb, const T* z, const double* sph, int M,
         seg_point(Rp, pp, a, b, Li, s, T(k) / T(rb.K), x);
         const T d0 = x[0] - cx, d1 = x[1] - cy, d2 = x[2] - cz;
         if (tsqrt(d0 * d0 + d1 * d1 + d2 * d2) - rs - ri < T(0)) hit = true;
+      }
+    }
+    if constexpr (POLY) {
+      for (int jp = 0; jp < po.NP && !hit; ++jp) {
+        if (poly_sd<T>(po, jp, xm, (int*)nullptr) - ri - T(0.5) * Li > T(0)) continue;
+        for (int k = 1; k <= rb.K; ++k) {
+          T x[3];
+          seg_point(Rp, pp, a, b, Li, s, T(k) / T(rb.K), x);
+          if (poly_sd<T>(po, jp, x, (int*)nullptr) - ri < T(0)) hit = true;
+        }
       }
     }
     ArcCoef<T> c = arc_coef<T, false>(s);

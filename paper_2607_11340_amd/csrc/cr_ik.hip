@@ -15,6 +15,12 @@
 
 namespace crk {
 
+CR_IK_GEN_EXTERN_POLY(1)
+CR_IK_GEN_EXTERN_POLY(2)
+CR_IK_GEN_EXTERN_POLY(3)
+CR_IK_GEN_EXTERN_POLY(4)
+CR_IK_GEN_EXTERN_POLY(5)
+CR_IK_GEN_EXTERN_POLY(6)
 CR_IK_GEN_EXTERN(true, false, 1)
 CR_IK_GEN_EXTERN(true, false, 2)
 CR_IK_GEN_EXTERN(true, false, 3)
@@ -616,7 +622,12 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
                         const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out, double* err_out,
                         int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
   const SphArgs sa{sp ? (const double*)sp->sph : nullptr, sp ? sp->ld : 0, sp ? sp->n_sph : 0,
-                   sp ? sp->per_problem : 0};
+                   sp ? sp->per_problem : 0, sp ? (const double*)sp->planes : nullptr, sp ? sp->plane_ld : 0,
+                   sp ? sp->n_poly : 0, sp ? sp->n_planes : 0};
+  // convex polytopes: the generic path with polytope rows (inextensible robots
+  // without self contact; the API refuses the other combinations)
+  if (sa.NPO > 0)
+    return run_ik_gen<NS, T, false, false, true>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);
   if constexpr (NS >= 3) {  // fewer than three segments have no non-adjacent pair
     if (rb0.self_collision && rb0.extensible)
       return run_ik_gen<NS, T, true, true>(rb0, sa, P, Tt, S, useed, w0, o, u_out, err_out, status_out, ws, st);

@@ -19,14 +19,24 @@ struct SphArgs {
   const double* sph;
   int64_t ld;
   int M, per_problem;
+  // convex polytopes (half-space form, see PolyArgs), per problem when per_problem
+  const double* pl;
+  int64_t pld;
+  int NPO, F;
 };
+
+// the polytopes of problem p
+__device__ __forceinline__ PolyArgs<double> poly_of(const SphArgs& sa, int64_t p) {
+  return PolyArgs<double>{sa.NPO > 0 ? sa.pl + (sa.per_problem ? p * sa.NPO * sa.F : 0) : nullptr, sa.pld, sa.NPO,
+                          sa.F};
+}
 
 // Stage 1 with clearance rows (eq. 10): one lane per seed as k_ik_stage1, the
 // generic per-configuration normal equations; spheres read from HBM (every lane
 // of a wave reads the same sphere: one broadcast load).  Also the stage 1 of
 // extensible robots (EXT: three coordinates a, b, e per segment), with or
 // without spheres (sa.M may be 0).
-template <int NS, typename T, bool EXT = false, bool SELF = false>
+template <int NS, typename T, bool EXT = false, bool SELF = false, bool POLY = false>
 __global__ void __launch_bounds__(256)
     k_ik_stage1_sph(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int S, const double* __restrict__ Tt,
                     const double* __restrict__ useed, int iters, T lam0, SphArgs sa, T* __restrict__ z_out,
@@ -51,13 +61,15 @@ __global__ void __launch_bounds__(256)
   T lam = lam0;
   bool failed = false;
   int trials = 0;
-  lm_cfg<NS, T, double, EXT, SELF>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
+  const PolyArgs<double> po = poly_of(sa, p);
+  lm_cfg<NS, T, double, EXT, SELF, 1, POLY>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld, po);
   T e;
   ik_cost<NS, T, EXT>(rb, w, tt, z, &e);
-  const T c = cfg_cost<NS, T, double, EXT, SELF>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+  const T c = cfg_cost<NS, T, double, EXT, SELF, POLY>(rb, w, tt, z, sp, sa.M, 1, sa.ld, po);
   WeightsT<T> wc = w;  // clearance part alone (SelectTop tie-break)
   wc.w_pos = wc.w_rot = wc.sq_lim = wc.sq_curv = T(0);
-  const T pen = (sa.M > 0 || SELF) ? cfg_cost<NS, T, double, EXT, SELF>(rb, wc, tt, z, sp, sa.M, 1, sa.ld) : T(0);
+  const T pen = (sa.M > 0 || SELF || POLY) ? cfg_cost<NS, T, double, EXT, SELF, POLY>(rb, wc, tt, z, sp, sa.M, 1, sa.ld, po)
+                                           : T(0);
   if (!tfinite(c) || !tfinite(e)) failed = true;
 #pragma unroll
   for (int k = 0; k < NZ; ++k) z_out[k * B + b] = z[k];
@@ -74,7 +86,7 @@ __global__ void __launch_bounds__(256)
 
 // G lanes per candidate (1, 2 or 4) try the line-search step lengths in
 // parallel (lm_cfg); the group leaves together and its first lane writes.
-template <int NS, typename T1, bool SPH, bool EXT = false, bool SELF = false, int G = 1>
+template <int NS, typename T1, bool SPH, bool EXT = false, bool SELF = false, int G = 1, bool POLY = false>
 __global__ void __launch_bounds__(256)
     k_ik_stage2(RobotT<double> rb, WeightsT<double> w, LMOpts<double> o, int64_t P, int S, int nf,
                 const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
@@ -110,8 +122,9 @@ __global__ void __launch_bounds__(256)
   double c;
   if (SPH || EXT || SELF) {
     const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
-    lm_cfg<NS, double, double, EXT, SELF, G>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld);
-    c = cfg_cost<NS, double, double, EXT, SELF>(rb, w, tt, z, sp, sa.M, 1, sa.ld);
+    const PolyArgs<double> po = poly_of(sa, p);
+    lm_cfg<NS, double, double, EXT, SELF, G, POLY>(rb, w, tt, z, lam, iters, o, failed, trials, sp, sa.M, 1, sa.ld, po);
+    c = cfg_cost<NS, double, double, EXT, SELF, POLY>(rb, w, tt, z, sp, sa.M, 1, sa.ld, po);
   } else {
     lm_ik<NS>(rb, w, tt, z, lam, iters, o, failed, trials);
     c = ik_cost<NS>(rb, w, tt, z, (double*)nullptr);
@@ -139,7 +152,7 @@ static inline int stage2_cfg_lanes(int64_t B2) {
 // or all S stage-1 seeds (seed index k).
 // ---------------------------------------------------------------------------
 
-template <int NS, typename TC, bool EXT = false, bool SELF = false>
+template <int NS, typename TC, bool EXT = false, bool SELF = false, bool POLY = false>
 __global__ void __launch_bounds__(256)
     k_ik_finalize(RobotT<double> rb, int64_t P, int nc, const int32_t* __restrict__ sel,
                   const TC* __restrict__ zc, const TC* __restrict__ costc, const int32_t* __restrict__ failedc,
@@ -202,9 +215,9 @@ __global__ void __launch_bounds__(256)
   }
   int32_t st = 0;
   if (viol > 1e-6 || thx > 0.0) st |= CR_LIMIT_VIOLATION;
-  if ((sa.M > 0 || SELF) &&
-      penetrates<NS, double, EXT, SELF>(rb, z, sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr, sa.M,
-                                        sa.ld))
+  if ((sa.M > 0 || SELF || POLY) &&
+      penetrates<NS, double, EXT, SELF, POLY>(rb, z, sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr, sa.M,
+                                              sa.ld, poly_of(sa, p)))
     st |= CR_COLLISION;
   if (!(pos <= 1e-3 && rot <= 3.14159265358979323846 / 180.0)) st |= CR_NOT_CONVERGED;
   if (st == 0) st = CR_SOLVED;
@@ -217,7 +230,7 @@ __global__ void __launch_bounds__(256)
 // segment, bending a, b and extension e) or with self contact (SELF: eq. 10 between
 // non-adjacent segments); every stage runs the generic per-configuration path
 // (clearance rows when spheres are given).
-template <int NS, typename T, bool EXT, bool SELF>
+template <int NS, typename T, bool EXT, bool SELF, bool POLY = false>
 cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const double* Tt, int32_t S,
                             const double* useed, const cr_weights& w0, const cr_opts& o, double* u_out,
                             double* err_out, int32_t* status_out, const IkWorkspace& ws, hipStream_t st) {
@@ -227,7 +240,7 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
   const int64_t B = P * (int64_t)S;
   const bool timed = timer_on();
   if (timed) timer_begin_call(st);
-  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, EXT, SELF>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
+  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, EXT, SELF, POLY>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
                      Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
                      ws.failed1, ws.trials1);
   cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_sph");
@@ -244,7 +257,7 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
     const int64_t B2 = P * (int64_t)o.n_final;
     const int g2 = stage2_cfg_lanes(B2);
 #define CR_S2C(GL)                                                                                                  \
-  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF, GL>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, rbd, \
+  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF, GL, POLY>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, rbd, \
                      wd, lod, P, (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, \
                      ws.cost2, ws.failed2)
     if (g2 == 4) CR_S2C(4);
@@ -254,14 +267,14 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
     rc = check_hip(hipGetLastError(), "k_ik_stage2");
     if (rc != CR_OK) return rc;
     if (timed) timer_mark(2, st);
-    hipLaunchKernelGGL((k_ik_finalize<NS, double, EXT, SELF>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
+    hipLaunchKernelGGL((k_ik_finalize<NS, double, EXT, SELF, POLY>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P,
                        (int)o.n_final, ws.sel, ws.z2, ws.cost2, ws.failed2, Tt, sa, u_out, err_out, status_out);
   } else {
     if (timed) {
       timer_mark(1, st);
       timer_mark(2, st);
     }
-    hipLaunchKernelGGL((k_ik_finalize<NS, T, EXT, SELF>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
+    hipLaunchKernelGGL((k_ik_finalize<NS, T, EXT, SELF, POLY>), dim3(blocks_for(P, 256)), dim3(256), 0, st, rbd, P, (int)S,
                        (const int32_t*)nullptr, (const T*)ws.z1, (const T*)ws.cost1, ws.failed1, Tt, sa, u_out,
                        err_out, status_out);
   }
@@ -280,6 +293,26 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
   template cr_status run_ik_gen<NS, double, EXT, SELF>(const cr_robot&, const SphArgs&, int64_t, const double*,   \
                                                         int32_t, const double*, const cr_weights&, const cr_opts&, \
                                                         double*, double*, int32_t*, const IkWorkspace&, hipStream_t);
+#define CR_IK_GEN_INST_POLY(NS)                                                                                    \
+  template cr_status run_ik_gen<NS, float, false, false, true>(const cr_robot&, const SphArgs&, int64_t,           \
+                                                               const double*, int32_t, const double*,              \
+                                                               const cr_weights&, const cr_opts&, double*, double*, \
+                                                               int32_t*, const IkWorkspace&, hipStream_t);          \
+  template cr_status run_ik_gen<NS, double, false, false, true>(const cr_robot&, const SphArgs&, int64_t,          \
+                                                                const double*, int32_t, const double*,             \
+                                                                const cr_weights&, const cr_opts&, double*,         \
+                                                                double*, int32_t*, const IkWorkspace&, hipStream_t);
+#define CR_IK_GEN_EXTERN_POLY(NS)                                                                                  \
+  extern template cr_status run_ik_gen<NS, float, false, false, true>(const cr_robot&, const SphArgs&, int64_t,    \
+                                                                      const double*, int32_t, const double*,       \
+                                                                      const cr_weights&, const cr_opts&, double*,   \
+                                                                      double*, int32_t*, const IkWorkspace&,        \
+                                                                      hipStream_t);                                 \
+  extern template cr_status run_ik_gen<NS, double, false, false, true>(const cr_robot&, const SphArgs&, int64_t,   \
+                                                                       const double*, int32_t, const double*,      \
+                                                                       const cr_weights&, const cr_opts&, double*,  \
+                                                                       double*, int32_t*, const IkWorkspace&,       \
+                                                                       hipStream_t);
 #define CR_IK_GEN_EXTERN(EXT, SELF, NS)                                                                            \
   extern template cr_status run_ik_gen<NS, float, EXT, SELF>(const cr_robot&, const SphArgs&, int64_t,            \
                                                               const double*, int32_t, const double*,              \

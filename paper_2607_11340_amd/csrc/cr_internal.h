@@ -33,6 +33,7 @@ cr_status check_dtype(cr_dtype d);
 cr_status check_opts(const cr_opts* o);
 cr_status check_weights(const cr_weights* w);
 cr_status check_spheres(const cr_spheres* spheres, int64_t P);
+cr_status check_poly_ok(const cr_obstacles* obst, const cr_robot* rb, bool ik, const char* who);
 cr_status check_inextensible(const cr_robot* rb, const char* what);  // CR_EUNSUPPORTED for extensible robots
 cr_status fail(cr_status s, const char* fmt, ...);
 cr_status check_hip(hipError_t e, const char* what);

@@ -58,7 +58,9 @@ extern "C" cr_status cr_solve_ik_static(const cr_robot* robot, const cr_spheres*
   if (P * (int64_t)S > ((int64_t)1 << 31) - 1) return fail(CR_EINVAL, "P*S too large");
   if (P == 0) return CR_OK;
   if (!T_target || !u_seed || !u_out || !err_out || !status_out) return fail(CR_EINVAL, "NULL array argument");
-  if ((rc = check_spheres(spheres, P)) != CR_OK) return rc;
+  if ((rc = check_spheres(spheres, P)) != CR_OK ||
+      (rc = check_poly_ok(spheres, robot, true, "cr_solve_ik_static")) != CR_OK)
+    return rc;
   const size_t need = ik_workspace_layout(*robot, P, S, *opts, dtype, nullptr, nullptr);
   if (need > (size_t)CR_STATIC_SCRATCH_BYTES)
     return fail(CR_ENOMEM, "these shapes need %zu bytes of scratch, more than the static %zu bytes (use cr_solve_ik)",
@@ -67,7 +69,7 @@ extern "C" cr_status cr_solve_ik_static(const cr_robot* robot, const cr_spheres*
   if ((rc = scratch_address(&mem)) != CR_OK) return rc;
   IkWorkspace w;
   ik_workspace_layout(*robot, P, S, *opts, dtype, (char*)mem, &w);
-  const cr_spheres* sp = (spheres && spheres->n_sph > 0) ? spheres : nullptr;
+  const cr_spheres* sp = (spheres && (spheres->n_sph > 0 || spheres->n_poly > 0)) ? spheres : nullptr;
   return launch_solve_ik(*robot, sp, P, (const double*)T_target, S, (const double*)u_seed, *weights, *opts,
                          (double*)u_out, (double*)err_out, status_out, w, dtype, stream);
 }

@@ -60,7 +60,7 @@ def _points_and_jacobian(O, ro, u, h=1e-7):
     return pts, arc[:, 2], J
 
 
-def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=False):
+def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=False, poly=None):
     """Absolute allowance (cost, gradient norm) for the FP32 rounding of the hinge
     residuals of one seed, u [n, 3] or [T, n, 3] (a trajectory), sph [M, 4] or None.
 
@@ -77,6 +77,8 @@ def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=Fals
         pair of points); |dv/du| <= ||dp/du||_2 (Frobenius norm of the oracle's
         point Jacobian by central differences), and the unit normal turns by
         dv / |p - c|, adding sq^2 h dv / |p - c| |dp/du|;
+      * convex polytopes (poly [n_poly, n_planes, 4]): v = sd(x) = max_f (n_f . x -
+        d_f), dv <= dp + 2 u32 (|x| + |d_f|), |dv/du| <= ||dp/du||_2;
       * tendon bound (eq. 9): v = |u_ij| of the lifted zero-sum displacement,
         dv <= 8 u32 (|u_ij| + u_max), |dv/du| <= 1;
       * bending bound: v = theta_i, dv <= 8 u32 theta_i, |dv/du| <= 1 / r_i;
@@ -123,7 +125,7 @@ def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=Fals
             act = v > 0
             hinge(sq_lim * v[act], sq_lim, (4 * U32 * (L0 + np.abs(e) + mid + half))[act], 1 / np.sqrt(3))
         # contact (eq. 10)
-        if (sph is not None and len(sph)) or self_contact:
+        if (sph is not None and len(sph)) or self_contact or poly is not None:
             pts, lens, J = _points_and_jacobian(O, ro, ut)
             p = pts.reshape(-1, 3)
             Jp = J.reshape(-1, 3, 3 * n)
@@ -136,6 +138,15 @@ def fp32_hinge_slack(O, ro, W, u, sph=None, self_contact=False, kinodynamic=Fals
                 dv = dp + U32 * (np.linalg.norm(p, axis=1)[:, None] + np.linalg.norm(sph[:, :3], axis=1)[None] + d)
                 gv = np.broadcast_to(jn[:, None], h.shape)[act]
                 hinge(sq_coll * h[act], sq_coll, dv[act], gv * (1 + h[act] / d[act]))
+            if poly is not None:
+                for pl in poly:
+                    v = p @ pl[:, :3].T - pl[None, :, 3]                 # [points, planes]
+                    sd = v.max(axis=1)
+                    fa = v.argmax(axis=1)
+                    h = margin - (sd - rad)
+                    act = h > 0
+                    dv = dp + 2 * U32 * (np.linalg.norm(p, axis=1) + np.abs(pl[fa, 3]))
+                    hinge(sq_coll * h[act], sq_coll, dv[act], jn[act])
             if self_contact:
                 far = seg[:, None] >= seg[None, :] + 2
                 d = np.linalg.norm(p[:, None] - p[None], axis=2)
