@@ -36,7 +36,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "ik_ext_4seg", "path_4seg", "traj_5seg", "uneven_batch"],
+                    choices=[WORKLOAD, "ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "uneven_batch"],
                     help="the headline IK workload, or one of the path / trajectory workloads")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -384,6 +384,9 @@ def main():
     if args.workload == "ik_ext_4seg":
         print(json.dumps(run_ik_ext(args, cr, I, torch, args.steps, args.warmup)), flush=True)
         return
+    if args.workload == "ik_box_3seg":
+        print(json.dumps(run_ik_box(args, cr, I, torch, args.steps, args.warmup)), flush=True)
+        return
     if args.workload != WORKLOAD:
         return bench_trajectories(args, cr, I, torch)
     spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
@@ -478,7 +481,7 @@ def main():
     torch.cuda.empty_cache()
     subs = {}
     if not args.headline_only:
-        for name in ("ik_ext_4seg", "path_4seg", "traj_5seg", "uneven_batch"):
+        for name in ("ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "uneven_batch"):
             print(f"bench: workload {name}", file=sys.stderr, flush=True)
             subs[name] = sub_workload(name, args, cr, I, torch)
             torch.cuda.empty_cache()
@@ -694,10 +697,72 @@ def run_ik_ext(args, cr, I, torch, steps, warmup):
     return line
 
 
+def run_ik_box(args, cr, I, torch, steps, warmup):
+    """Two-stage IK of the 3-segment robot among 12 oriented boxes per problem
+    (convex obstacles in half-space form): targets from forward kinematics of
+    uniform actuations; boxes drawn per problem and kept only when the target's
+    backbone clears them by 3 mm; uniform seeds."""
+    name = "ik_box_3seg"
+    spec = I.WORKLOADS[name]
+    n, P, S, b, K = len(spec["L"]), spec["P"], spec["S"], spec["b"], spec["K"]
+    bx = spec["boxes"]
+    rng = I.rng_for(name)
+    robot = cr.Robot(L=spec["L"], r=spec["r"], u_max=[b] * n, pts_per_seg=K)
+    dev = torch.device("cuda:0")
+    u_true = I.uniform_actuation(rng, n, b, P)
+    out = cr.fk(robot, torch.tensor(u_true.reshape(P, -1).T.copy(), device=dev), arc=False, points=True)
+    pts = out["pts"].cpu().numpy().T.reshape(P, n * K, 3)
+    T = out["frames"][12 * (n - 1):12 * n].contiguous()
+    body = np.repeat(np.asarray(spec["r"]), K)
+    planes = np.zeros((P, bx["count"], 6, 4))
+    for p in range(P):
+        j = 0
+        while j < bx["count"]:
+            c, h, R = I.random_boxes(rng, 4 * bx["count"], bx["lo"], bx["hi"], bx["half_lo"], bx["half_hi"])
+            for q in range(len(c)):
+                pl = I.box_halfspaces(c[q], h[q], R[q])
+                sd = (pts[p] @ pl[:, :3].T - pl[None, :, 3]).max(axis=1)
+                if (sd - body).min() > bx["clear"] and j < bx["count"]:
+                    planes[p, j] = pl
+                    j += 1
+    seeds = I.uniform_actuation(rng, n, b, P * S)
+    useed = torch.tensor(seeds.reshape(P * S, -1).T.copy(), device=dev)
+    po = (torch.tensor(np.ascontiguousarray(planes.reshape(-1, 4).T), device=dev), True, bx["count"], 6)
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    weights = cr.Weights()
+    ws = torch.empty(cr.ik_workspace_bytes(robot, P, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    res = (torch.empty((3 * n, P), dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"),
+           torch.empty((P,), dtype=torch.int32, device="cuda"))
+
+    def step():
+        cr.solve_ik(robot, T, useed, weights, opts, dtype=torch.float32, workspace=ws, out=res, polytopes=po)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    per_step, total = step_times(torch, step, steps)
+    ms = float(np.median(per_step))
+    st = res[2].cpu().numpy()
+    line = dict(metric="IK among convex obstacles solves/sec (success %)", value=round(P / (ms * 1e-3), 1),
+                unit="IK solves/s", n_gpus=1, steps=steps, warmup=warmup, ms_per_step=round(ms, 4),
+                ms_per_step_mean=round(total / steps, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", refine_dtype="f64", data="synthetic",
+                config=dict(workload=name, segments=n, targets=P, seeds_per_target=S, boxes=bx["count"],
+                            planes_per_box=6, k_init=spec["k_init"], k_final=spec["k_final"],
+                            n_final=spec["n_final"]),
+                success_rate=round(float((st == cr.SOLVED).mean()), 4),
+                status_counts={int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))})
+    line.update(counter_roofline(name, ms))
+    return line
+
+
 def sub_workload(name, args, cr, I, torch):
     """A compact line of one of the other workloads for the headline JSON."""
     if name == "ik_ext_4seg":
         ln = run_ik_ext(args, cr, I, torch, args.sub_steps, 1)
+    elif name == "ik_box_3seg":
+        ln = run_ik_box(args, cr, I, torch, args.sub_steps, 1)
     elif name == "uneven_batch":
         ln = run_uneven(args, cr, I, torch, args.sub_steps, 1, False)
     else:

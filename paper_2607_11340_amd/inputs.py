@@ -47,7 +47,37 @@ WORKLOADS = {
         kind="ik", L=[0.08] * 4, r=[0.008] * 4, b=0.006, L_min=[0.04] * 4, L_max=[0.12] * 4, P=1024, S=128,
         k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 6,
         lattice=dict(xy=(-0.15, 0.0, 0.15), z=(0.10, 0.22, 0.34), radius=0.016, jitter=0.01)),
+    # the 3-segment robot among convex obstacles (the convex pieces of Sec. V's
+    # scenes; synthetic boxes stand in for its shelves and cabinets): 12 oriented
+    # boxes per problem, half extents U[1, 5] cm, centres in the workspace box,
+    # kept only if they clear the target configuration by 3 mm
+    "ik_box_3seg": dict(
+        kind="ik", L=[0.10, 0.08, 0.06], r=[0.010, 0.008, 0.006], b=0.008, P=1024, S=128,
+        k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 7,
+        boxes=dict(count=12, lo=(-0.2, -0.2, 0.0), hi=(0.2, 0.2, 0.3), half_lo=0.01, half_hi=0.05, clear=3e-3)),
 }
+
+
+def random_boxes(rng: np.random.Generator, count: int, lo, hi, half_lo: float, half_hi: float):
+    """`count` oriented boxes: centres [count, 3] uniform in [lo, hi], half extents
+    [count, 3] uniform in [half_lo, half_hi], rotations [count, 3, 3] (the Q of a
+    QR factorisation of a Gaussian matrix, columns the box axes)."""
+    c = rng.uniform(np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64), size=(count, 3))
+    h = rng.uniform(half_lo, half_hi, size=(count, 3))
+    R = np.stack([np.linalg.qr(rng.normal(size=(3, 3)))[0] for _ in range(count)])
+    return c, h, R
+
+
+def box_halfspaces(c, h, R) -> np.ndarray:
+    """The six half-spaces n.x <= d of a box (centre c, half extents h, axes the
+    columns of R) as rows (nx, ny, nz, d)."""
+    out = np.empty((6, 4))
+    for k in range(3):
+        for q, sgn in enumerate((1.0, -1.0)):
+            n = sgn * R[:, k]
+            out[2 * k + q, :3] = n
+            out[2 * k + q, 3] = n @ c + h[k]
+    return out
 
 
 def extended_actuation(rng: np.random.Generator, n: int, b, e_lo, e_hi, count: int) -> np.ndarray:
