@@ -1327,6 +1327,10 @@ static double seed_uniform(const uint64_t key[2], int64_t p, int32_t s, int32_t 
   return (double)(out[j & 3] >> 11) * 0x1.0p-53;
 }
 
+double cro_contact_gap(const cro_robot* rb, const double* sph, int n_sph, const double* u) {
+  return contact_gap(rb, sph, n_sph, u, NULL);
+}
+
 int32_t cro_sample_seed(const cro_robot* rb, const double* sph, int n_sph, const uint64_t key[2], int64_t p,
                         int32_t s, int32_t max_attempts, double* u) {
   int n = rb->n_seg;

@@ -170,6 +170,12 @@ void cro_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4
 int32_t cro_sample_seed(const cro_robot* rb, const double* sph, int n_sph, const uint64_t key[2], int64_t p,
                         int32_t s, int32_t max_attempts, double* u);
 
+/* Smallest clearance of configuration u[3n] against spheres sph[n_sph][4]
+ * (x, y, z, radius) and, with self contact, the robot itself (eq. 10 with
+ * margin 0): negative iff the configuration collides; INFINITY when there is
+ * nothing to clear. */
+double cro_contact_gap(const cro_robot* rb, const double* sph, int n_sph, const double* u);
+
 #ifdef __cplusplus
 }
 #endif

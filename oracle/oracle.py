@@ -14,6 +14,7 @@ Arrays are numpy float64, item-major:
 from __future__ import annotations
 
 import ctypes as C
+import heapq
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -176,6 +177,8 @@ def lib():
         L.cro_philox4x64.restype = None
         L.cro_sample_seed.argtypes = [R, dp, C.c_int, u64p, C.c_int64, C.c_int32, C.c_int32, dp]
         L.cro_sample_seed.restype = C.c_int32
+        L.cro_contact_gap.argtypes = [R, dp, C.c_int, dp]
+        L.cro_contact_gap.restype = C.c_double
         _lib = L
     return _lib
 
@@ -406,3 +409,224 @@ def sample_seeds(robot: Robot, P: int, S: int, key, max_attempts: int = 8, spher
                                                 int(max_attempts), po)
             u[p, s] = out.reshape(n, 3)
     return u, tries
+
+
+# ---------------------------------------------------------------------------
+# PRM exploration stage of trajectory planning (Algorithm 2; Sec. IV-B).
+#
+# Readings, where the algorithm leaves the details open:
+#  * configurations are tendon displacements u (3n numbers, zero-sum per
+#    segment); the distance of two configurations is the Euclidean norm of their
+#    difference, its square summed in component order;
+#  * ParallelSample(N): node j of problem p is SampleSeeds' draw (key, p, j);
+#    a node that still collides after max_attempts is discarded (kept in the
+#    arrays, flagged by its negative attempt count);
+#  * a straight motion from a to b is free iff each of its n_check interior
+#    configurations a + t_m (b - a), t_m = m / (n_check + 1), m = 1..n_check,
+#    clears the scene (SampleSeeds' test, margin 0); a roadmap motion starts at
+#    the lower-indexed node, a query motion at the query configuration;
+#  * ParallelConnect(V, k): each kept node lists its k nearest kept nodes
+#    (ties to the lower index); the graph is undirected, {i, j} is an edge when
+#    either lists the other with a free motion, weighted by their distance;
+#  * ConnectToRoadmap(q): the k nearest kept nodes of q joined by free motions;
+#    the direct start-goal motion is an edge too when it is free;
+#  * Dijkstra: nodes 0..N-1 are the roadmap, N the start and N+1 the goal; nodes
+#    settle in order of (distance, index), a relaxation needs a strictly
+#    smaller distance, and the search ends when the goal settles;
+#  * ResampleLinear(Q_path, H): waypoint t lies at arc length s_m t / H along the
+#    path's polyline (s_i = distance of the i-th path node from the start), by
+#    linear interpolation in the first segment whose end reaches it; waypoint 0
+#    is the start and waypoint H the goal;
+#  * start and goal not connected: the straight line between them;
+#  * seeds for ParallelOptimize: seed 0 is Q'; seed s >= 1 adds the caller's
+#    perturbation of that seed and scales each (waypoint, segment) back into
+#    |u| <= u_max.
+# ---------------------------------------------------------------------------
+PRM_NONE = -(2 ** 31)
+
+
+def config_gap(robot: Robot, u, spheres=None) -> float:
+    """Smallest clearance of one configuration u [n, 3] (negative: collides)."""
+    sph = np.zeros((0, 4)) if spheres is None else np.asarray(spheres, dtype=np.float64).reshape(-1, 4)
+    sarr, sp = _d(sph if len(sph) else np.zeros((1, 4)))
+    ua, up = _d(np.ravel(u))
+    rc = robot.c()
+    return float(lib().cro_contact_gap(C.byref(rc), sp, len(sph), up))
+
+
+def dist2(a, b):
+    """Squared distance of configurations a [..., 3n] and b [..., 3n], summed in
+    component order (broadcasting over leading axes)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    out = np.zeros(np.broadcast_shapes(a.shape[:-1], b.shape[:-1]))
+    for c in range(a.shape[-1]):
+        d = a[..., c] - b[..., c]
+        out = out + d * d
+    return out
+
+
+def motion_gap(robot: Robot, ua, ub, n_check: int, spheres=None) -> float:
+    """Smallest clearance over the interior configurations of the straight motion
+    ua -> ub ([3n] each); INFINITY when n_check is 0 or nothing is in the way."""
+    ua = np.ravel(np.asarray(ua, dtype=np.float64))
+    ub = np.ravel(np.asarray(ub, dtype=np.float64))
+    g = np.inf
+    for m in range(1, n_check + 1):
+        t = m / (n_check + 1)
+        g = min(g, config_gap(robot, ua + t * (ub - ua), spheres))
+    return g
+
+
+def prm_roadmap(robot: Robot, p: int, N: int, k: int, n_check: int, key, max_attempts: int = 8, spheres=None):
+    """ParallelSample(N) and ParallelConnect(V, k) for problem p's scene.
+
+    Returns dict with
+      nodes [N, n, 3], attempts [N] (negative: discarded),
+      nbr [N, k] int: slot c of node i holds j (free motion), -1 - j (the motion
+        collides) or PRM_NONE (fewer than k kept neighbours, or i discarded),
+      gap [N, k]: smallest clearance over the slot's motion (INFINITY if none),
+      adj: list of N sorted neighbour lists of the undirected graph,
+      adj_w: their weights (distances)."""
+    n = robot.n
+    kk = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    u64p = C.POINTER(C.c_uint64)
+    rc = robot.c()
+    sph = None if spheres is None else np.asarray(spheres, dtype=np.float64).reshape(-1, 4)
+    M = 0 if sph is None else len(sph)
+    sarr, sptr = _d(sph if M else np.zeros((1, 4)))
+    nodes = np.zeros((N, 3 * n))
+    att = np.zeros(N, dtype=np.int64)
+    for j in range(N):
+        out, po = _d(np.zeros(3 * n))
+        att[j] = lib().cro_sample_seed(C.byref(rc), sptr, M, kk.ctypes.data_as(u64p), p, j, int(max_attempts), po)
+        nodes[j] = out
+    kept = att > 0
+    nbr = np.full((N, k), PRM_NONE, dtype=np.int64)
+    gap = np.full((N, k), np.inf)
+    for i in range(N):
+        if not kept[i]:
+            continue
+        d2 = dist2(nodes[i][None], nodes)
+        order = [j for j in np.lexsort((np.arange(N), d2)) if j != i and kept[j]][:k]
+        for c, j in enumerate(order):
+            a, b = min(i, j), max(i, j)
+            g = motion_gap(robot, nodes[a], nodes[b], n_check, sph)
+            gap[i, c] = g
+            nbr[i, c] = j if not g < 0.0 else -1 - j
+    nb = [set() for _ in range(N)]
+    for i in range(N):
+        for j in nbr[i]:
+            if j >= 0:
+                nb[i].add(int(j))
+                nb[int(j)].add(i)
+    adj = [sorted(s) for s in nb]
+    adj_w = [[float(np.sqrt(dist2(nodes[i], nodes[j]))) for j in adj[i]] for i in range(N)]
+    return dict(nodes=nodes.reshape(N, n, 3), attempts=att, nbr=nbr, gap=gap, adj=adj, adj_w=adj_w)
+
+
+def resample_linear(path_u, s, H: int):
+    """ResampleLinear: H + 1 waypoints [H+1, 3n] at equal arc length along the
+    polyline through path_u [m+1, 3n] whose cumulative lengths are s [m+1]."""
+    path_u = np.asarray(path_u, dtype=np.float64)
+    m = len(path_u) - 1
+    out = np.empty((H + 1, path_u.shape[1]))
+    out[0] = path_u[0]
+    out[H] = path_u[m]
+    for t in range(1, H):
+        sig = s[m] * t / H
+        i = 1
+        while i < m and not sig <= s[i]:
+            i += 1
+        den = s[i] - s[i - 1]
+        lam = (sig - s[i - 1]) / den if den != 0.0 else 0.0
+        out[t] = path_u[i - 1] + lam * (path_u[i] - path_u[i - 1])
+    return out
+
+
+def prm_query(robot: Robot, rm: dict, k: int, n_check: int, u_start, u_goal, H: int, S: int = 1, bumps=None,
+              spheres=None, linear: bool = False):
+    """ConnectToRoadmap, Dijkstra and ResampleLinear for one query on roadmap rm
+    (as prm_roadmap returns), then the S seeds of ParallelOptimize.
+
+    bumps: None or [S, H+1, n, 3] perturbations (seed 0's is ignored).
+    linear: skip the roadmap (the straight-line initializer).
+    Returns dict with path (node indices, start N ... goal N+1), n_path (roadmap
+    nodes on the path; -1: not connected, straight line), seeds [S, H+1, n, 3],
+    the connections of both ends (start_nbr/goal_nbr: j or -1 - j as nbr) with
+    their clearances, and the direct motion's clearance."""
+    n = robot.n
+    sph = None if spheres is None else np.asarray(spheres, dtype=np.float64).reshape(-1, 4)
+    qs = np.ravel(np.asarray(u_start, dtype=np.float64))
+    qg = np.ravel(np.asarray(u_goal, dtype=np.float64))
+    out = dict()
+    if linear:
+        path, n_path, pts, s = [None, None], 0, np.stack([qs, qg]), np.array([0.0, np.sqrt(dist2(qs, qg))])
+    else:
+        nodes = rm["nodes"].reshape(-1, 3 * n)
+        N = len(nodes)
+        kept = rm["attempts"] > 0
+        ends = []
+        for q in (qs, qg):
+            d2 = dist2(q[None], nodes)
+            order = [j for j in np.lexsort((np.arange(N), d2)) if kept[j]][:k]
+            lst = []
+            for j in order:
+                g = motion_gap(robot, q, nodes[j], n_check, sph)
+                lst.append((int(j), g, float(np.sqrt(d2[j]))))
+            ends.append(lst)
+        g_direct = motion_gap(robot, qs, qg, n_check, sph)
+        out.update(start_nbr=[j if not g < 0.0 else -1 - j for j, g, _ in ends[0]],
+                   goal_nbr=[j if not g < 0.0 else -1 - j for j, g, _ in ends[1]],
+                   start_gap=[g for _, g, _ in ends[0]], goal_gap=[g for _, g, _ in ends[1]], direct_gap=g_direct)
+        S_, G_ = N, N + 1
+        nb = [list(zip(rm["adj"][i], rm["adj_w"][i])) for i in range(N)] + [[], []]
+        for j, g, w in ends[0]:
+            if not g < 0.0:
+                nb[S_].append((j, w))
+        for j, g, w in ends[1]:
+            if not g < 0.0:
+                nb[j].append((G_, w))
+        if not g_direct < 0.0:
+            nb[S_].append((G_, float(np.sqrt(dist2(qs, qg)))))
+        dist = np.full(N + 2, np.inf)
+        pred = np.full(N + 2, -1)
+        done = np.zeros(N + 2, dtype=bool)
+        dist[S_] = 0.0
+        heap = [(0.0, S_)]
+        while heap:
+            dv, v = heapq.heappop(heap)
+            if done[v]:
+                continue
+            done[v] = True
+            if v == G_:
+                break
+            for w_, wt in nb[v]:
+                cand = dv + wt
+                if not done[w_] and cand < dist[w_]:
+                    dist[w_] = cand
+                    pred[w_] = v
+                    heapq.heappush(heap, (cand, w_))
+        if done[G_]:
+            path = [G_]
+            while path[-1] != S_:
+                path.append(int(pred[path[-1]]))
+            path = path[::-1]
+            n_path = len(path) - 2
+            allu = np.concatenate([nodes, qs[None], qg[None]])
+            pts, s = allu[path], dist[path]
+        else:
+            path, n_path = [S_, G_], -1
+            pts, s = np.stack([qs, qg]), np.array([0.0, np.sqrt(dist2(qs, qg))])
+    Q = resample_linear(pts, s, H)
+    seeds = np.repeat(Q[None], S, axis=0)
+    if bumps is not None:
+        bumps = np.asarray(bumps, dtype=np.float64).reshape(S, H + 1, 3 * n)
+        umax = np.asarray(robot.u_max[:n], dtype=np.float64)
+        for q in range(1, S):
+            x = (Q + bumps[q]).reshape(H + 1, n, 3)
+            peak = np.abs(x).max(axis=2)
+            scale = np.minimum(1.0, umax[None, :] / np.maximum(peak, 1e-300))
+            seeds[q] = (x * scale[:, :, None]).reshape(H + 1, 3 * n)
+    out.update(path=path, n_path=n_path, seeds=seeds.reshape(S, H + 1, n, 3))
+    return out

@@ -181,24 +181,36 @@ def smooth_actuation_paths(rng: np.random.Generator, n: int, b, count: int, T: i
     return out
 
 
-def perturbed_linear_paths(rng: np.random.Generator, u_start: np.ndarray, u_goal: np.ndarray,
-                           count: int, T: int, b, amp: float = 0.5) -> np.ndarray:
-    """Trajectory seeds [count, T, n, 3] between u_start and u_goal ([n, 3] each):
-    seed 0 is the straight interpolation (the linear initializer of Sec. V-C),
-    the others add two half-sine bumps per tendon of amplitude U[-amp, amp] * b,
-    made zero-sum and scaled per waypoint back inside |u| <= b."""
-    n = u_start.shape[0]
+def path_bumps(rng: np.random.Generator, n: int, count: int, T: int, b, amp: float = 0.5) -> np.ndarray:
+    """Perturbations [count, T, n, 3] of trajectory seeds: bump 0 is zero, the
+    others are two half-sine bumps per tendon of amplitude U[-amp, amp] * b over
+    the horizon, made zero-sum per segment."""
     b = np.broadcast_to(np.asarray(b, dtype=np.float64), (n,))
     s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
-    lin = (1.0 - s)[:, None, None] * u_start[None] + s[:, None, None] * u_goal[None]
-    out = np.repeat(lin[None], count, axis=0)
+    out = np.zeros((count, T, n, 3))
     for q in range(1, count):
         bump = np.zeros((T, n, 3))
         for k in (1, 2):
             c = rng.uniform(-amp, amp, size=(n, 3)) * b[:, None]
             bump += np.sin(np.pi * k * s)[:, None, None] * c[None]
         bump -= bump.mean(axis=2, keepdims=True)
-        x = out[q] + bump
+        out[q] = bump
+    return out
+
+
+def perturbed_linear_paths(rng: np.random.Generator, u_start: np.ndarray, u_goal: np.ndarray,
+                           count: int, T: int, b, amp: float = 0.5) -> np.ndarray:
+    """Trajectory seeds [count, T, n, 3] between u_start and u_goal ([n, 3] each):
+    seed 0 is the straight interpolation (the linear initializer of Sec. V-C),
+    the others add path_bumps and are scaled per waypoint back inside |u| <= b."""
+    n = u_start.shape[0]
+    bumps = path_bumps(rng, n, count, T, b, amp)
+    b = np.broadcast_to(np.asarray(b, dtype=np.float64), (n,))
+    s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
+    lin = (1.0 - s)[:, None, None] * u_start[None] + s[:, None, None] * u_goal[None]
+    out = np.repeat(lin[None], count, axis=0)
+    for q in range(1, count):
+        x = out[q] + bumps[q]
         peak = np.abs(x).max(axis=2)  # [T, n]
         scale = np.minimum(1.0, b[None, :] / np.maximum(peak, 1e-300))
         out[q] = x * scale[:, :, None]
