@@ -297,6 +297,91 @@ size_t cr_solve_traj_workspace(const cr_robot* robot, int64_t P, int32_t H, int3
                                const cr_opts* opts, cr_dtype dtype);
 
 /* ------------------------------------------------------------------------- */
+/* Exploration stage of trajectory planning: probabilistic roadmap (PRM),      */
+/* Algorithm 2.                                                                */
+/* ------------------------------------------------------------------------- */
+
+/* Roadmap and query parameters.  [host] */
+typedef struct {
+  int32_t n_nodes;       /* N roadmap samples per problem (ParallelSample), 1..2048 */
+  int32_t k;             /* neighbours per node (ParallelConnect) and per query end
+                            (ConnectToRoadmap), 1..32 */
+  int32_t n_check;       /* interior configurations checked per straight motion, 0..64 */
+  int32_t max_attempts;  /* SampleSeeds attempts per node, 1..64 */
+  uint64_t key0, key1;   /* Philox key of the node draws */
+} cr_prm_opts;
+
+/* A neighbour-list slot without a neighbour. */
+#define CR_PRM_NONE INT32_MIN
+
+/* Offline roadmap of every problem's scene (Algorithm 2, ParallelSample and
+ * ParallelConnect).  Configurations are tendon displacements u (3n numbers);
+ * the distance of two is the Euclidean norm of their difference.  For P
+ * problems, each with its own spheres (per_problem) or the shared ones:
+ *  - node j of problem p is cr_sample_seeds' seed (key, p, j) with max_attempts;
+ *    a node that still collides is discarded (attempts < 0);
+ *  - every kept node lists its k nearest kept nodes (ties: lower index); the
+ *    straight motion a -> b from the lower-indexed node is checked at the
+ *    n_check configurations a + t_m (b - a), t_m = m / (n_check + 1),
+ *    m = 1..n_check, with SampleSeeds' FP64 collision test (margin 0), endpoints
+ *    not rechecked;
+ *  - the roadmap is the undirected graph in which {i, j} is an edge when either
+ *    lists the other with a free motion, weighted by their distance.
+ * Outputs [device], B = N * P, column p * N + j:
+ *   nodes    [3n][B] double    node configurations (zero-sum per segment)
+ *   attempts [B] int32         SampleSeeds attempts, negative: node discarded
+ *   nbr      [k][B] int32      slot s of node j at nbr[s * B + p * N + j]: the s-th
+ *                              nearest kept node i (free motion), -1 - i (the motion
+ *                              collides) or CR_PRM_NONE
+ *   adj_off  [(N+1)*P] int32   CSR offsets of problem p at adj_off[p * (N + 1) + v],
+ *                              relative to the problem's block
+ *   adj      [2kN*P] int32     neighbours of node v of problem p at
+ *                              adj[p * 2kN + adj_off[..v] .. p * 2kN + adj_off[..v+1]],
+ *                              sorted by index
+ *   adj_w    [2kN*P] double    the matching edge lengths
+ * Distances and interpolations are formed with correctly rounded FP64 operations
+ * in component order, without contraction.  Inextensible robots without self
+ * contact and spheres only (the trajectory solve's scope).
+ * Errors: CR_EINVAL for parameters outside the ranges above, P > 65535, polytopes;
+ * CR_EUNSUPPORTED for extensible robots or self contact. */
+cr_status cr_prm_build(const cr_robot* robot, const cr_spheres* spheres, int64_t P, const cr_prm_opts* prm,
+                       double* nodes, int32_t* attempts, int32_t* nbr, int32_t* adj_off, int32_t* adj,
+                       double* adj_w, hipStream_t stream);
+
+/* Online queries (Algorithm 2, ConnectToRoadmap, Dijkstra, ResampleLinear): one
+ * (start, goal) pair per problem on that problem's roadmap (cr_prm_build's
+ * arrays, same P and prm), giving S initial trajectories of H+1 waypoints for
+ * cr_solve_traj.
+ *  - each end is joined to its k nearest kept nodes by the motions that pass the
+ *    check above (starting at the end); the direct start-goal motion is an edge
+ *    too when it passes;
+ *  - Dijkstra over roadmap nodes 0..N-1, start N and goal N+1 settles nodes in
+ *    order of (distance, index), relaxes on strict improvement and stops when
+ *    the goal settles;
+ *  - ResampleLinear: waypoint t (0 < t < H) lies at arc length s_m t / H along the
+ *    path's polyline (s_i = the distance of the i-th path node), linearly
+ *    interpolated in the first segment that reaches it; waypoint 0 is the start,
+ *    H the goal; start and goal not connected: the straight line;
+ *  - seed 0 is that trajectory; seed s >= 1 adds bump[.][column of s] (if bump is
+ *    not NULL) and scales each (waypoint, segment) by min(1, u_max / max_j |u_j|).
+ * linear = 1 skips the roadmap (the roadmap arrays may be NULL): the straight line
+ * with the same perturbations (the linear initializer of Sec. V-C).
+ *   u_start_goal [device, double] [6n][P]: start (c < 3n) then goal
+ *   bump         [device, double] [3n][(H+1)*S*P] or NULL
+ *   u_seed_out   [device, double] [3n][(H+1)*S*P], column (p*S + s)*(H+1) + t,
+ *                the layout of cr_solve_traj's u_seed
+ *   n_path_out   [device, int32] [P]: roadmap nodes on the path, -1 when start and
+ *                goal are not connected (0 also for the direct motion and linear)
+ *   path_out     [device, int32] [N+2][P] or NULL: node t of problem p's path at
+ *                t * P + p (N = start, N + 1 = goal), -1 after the goal
+ * Errors: as cr_prm_build, and CR_EINVAL for H outside 1..255 or S outside 1..4096. */
+cr_status cr_prm_query(const cr_robot* robot, const cr_spheres* spheres, int64_t P, const cr_prm_opts* prm,
+                       const double* nodes, const int32_t* attempts, const int32_t* adj_off, const int32_t* adj,
+                       const double* adj_w, const double* u_start_goal, int32_t H, int32_t S, const double* bump,
+                       int32_t linear, double* u_seed_out, int32_t* n_path_out, int32_t* path_out,
+                       hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Uneven batches.                                                             */
 /* ------------------------------------------------------------------------- */
 

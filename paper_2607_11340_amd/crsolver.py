@@ -30,7 +30,7 @@ SOLVED, LIMIT_VIOLATION, COLLISION, NONFINITE, NOT_CONVERGED = 1, 2, 4, 8, 16
 EXPORTS = ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_workspace", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj",
            "cr_solve_traj_workspace", "cr_solve_batch", "cr_solve_batch_workspace", "cr_baseline_solve_ik",
            "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_baseline_traj_workspace",
-           "cr_select_top", "cr_sample_seeds", "cr_calib_valu",
+           "cr_select_top", "cr_sample_seeds", "cr_prm_build", "cr_prm_query", "cr_calib_valu",
            "cr_timing_enable", "cr_timing_read", "cr_ik_flop_tally", "cr_autotune_enable", "cr_autotune_clear", "cr_autotune_force",
            "cr_autotune_report", "cr_status_string", "cr_last_error")
 
@@ -52,6 +52,14 @@ class _Robot(C.Structure):
 class _Spheres(C.Structure):
     _fields_ = [("n_sph", C.c_int32), ("per_problem", C.c_int32), ("sph", C.c_void_p), ("ld", C.c_int64),
                 ("n_poly", C.c_int32), ("n_planes", C.c_int32), ("planes", C.c_void_p), ("plane_ld", C.c_int64)]
+
+
+class _PrmOpts(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("k", C.c_int32), ("n_check", C.c_int32), ("max_attempts", C.c_int32),
+                ("key0", C.c_uint64), ("key1", C.c_uint64)]
+
+
+PRM_NONE = -(2 ** 31)
 
 
 class _Problem(C.Structure):
@@ -193,12 +201,15 @@ def _load():
     L.cr_autotune_report.argtypes = [C.c_char_p, i64]
     L.cr_autotune_report.restype = i64
     L.cr_sample_seeds.argtypes = [R, S, i64, i32, C.c_uint64, C.c_uint64, i32, vp, vp, vp]
+    PO = C.POINTER(_PrmOpts)
+    L.cr_prm_build.argtypes = [R, S, i64, PO, vp, vp, vp, vp, vp, vp, vp]
+    L.cr_prm_query.argtypes = [R, S, i64, PO, vp, vp, vp, vp, vp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
     L.cr_status_string.argtypes = [C.c_int]
     L.cr_status_string.restype = C.c_char_p
     L.cr_last_error.restype = C.c_char_p
     for name in ("cr_fk", "cr_cost_grad", "cr_solve_ik", "cr_solve_ik_static", "cr_solve_path", "cr_solve_traj", "cr_solve_batch",
                  "cr_baseline_solve_ik", "cr_baseline_solve_path", "cr_baseline_solve_traj", "cr_select_top",
-                 "cr_sample_seeds", "cr_timing_read", "cr_ik_flop_tally", "cr_calib_valu"):
+                 "cr_sample_seeds", "cr_prm_build", "cr_prm_query", "cr_timing_read", "cr_ik_flop_tally", "cr_calib_valu"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -309,6 +320,73 @@ def sample_seeds(robot: Robot, P: int, S: int, key=(0, 0), max_attempts: int = 8
                                int(key[0]) & (2 ** 64 - 1), int(key[1]) & (2 ** 64 - 1), max_attempts, _ptr(u),
                                _ptr(att), _stream(u)))
     return u, att
+
+
+@dataclass
+class PrmOpts:
+    """Roadmap and query parameters of the PRM exploration stage (Algorithm 2)."""
+    n_nodes: int = 1024
+    k: int = 10
+    n_check: int = 8
+    max_attempts: int = 8
+    key: tuple = (0, 0)
+
+    def c(self) -> _PrmOpts:
+        return _PrmOpts(self.n_nodes, self.k, self.n_check, self.max_attempts, int(self.key[0]) & (2 ** 64 - 1),
+                        int(self.key[1]) & (2 ** 64 - 1))
+
+
+def prm_build(robot: Robot, P: int, prm: PrmOpts, spheres=None, device="cuda"):
+    """Offline roadmaps of P scenes (cr_prm_build).  spheres as for solve_traj
+    (float64).  Returns a dict of device tensors: nodes [3n, N*P] float64,
+    attempts [N*P], nbr [k, N*P], adj_off [(N+1)*P], adj [2kN*P] int32 and
+    adj_w [2kN*P] float64."""
+    n, N, k = robot.n, prm.n_nodes, prm.k
+    B = N * P
+    out = dict(nodes=torch.empty((3 * n, B), dtype=torch.float64, device=device),
+               attempts=torch.empty((B,), dtype=torch.int32, device=device),
+               nbr=torch.empty((k, B), dtype=torch.int32, device=device),
+               adj_off=torch.empty(((N + 1) * P,), dtype=torch.int32, device=device),
+               adj=torch.empty((2 * k * B,), dtype=torch.int32, device=device),
+               adj_w=torch.empty((2 * k * B,), dtype=torch.float64, device=device))
+    rc, pc = robot.c(), prm.c()
+    sp = _spheres_c(spheres, torch.float64)
+    t = out["nodes"]
+    _check(lib.cr_prm_build(C.byref(rc), C.byref(sp), P, C.byref(pc), _ptr(t), _ptr(out["attempts"]),
+                            _ptr(out["nbr"]), _ptr(out["adj_off"]), _ptr(out["adj"]), _ptr(out["adj_w"]), _stream(t)))
+    return out
+
+
+def prm_query(robot: Robot, prm: PrmOpts, u_start_goal: torch.Tensor, H: int, S: int, roadmap: dict = None,
+              bump: torch.Tensor = None, linear: bool = False, spheres=None, out=None, path: bool = False):
+    """Online queries (cr_prm_query): u_start_goal [6n, P] float64 on the roadmaps
+    of prm_build (None with linear=True).  bump: None or [3n, (H+1)*S*P] float64.
+    Returns (u_seed [3n, (H+1)*S*P] float64, n_path [P] int32, path [N+2, P] int32
+    or None)."""
+    n = robot.n
+    P = u_start_goal.shape[1]
+    _need(u_start_goal, (6 * n, P), torch.float64, "u_start_goal")
+    cols = (H + 1) * S * P
+    if bump is not None:
+        _need(bump, (3 * n, cols), torch.float64, "bump")
+    dev = u_start_goal.device
+    if out is None:
+        out = (torch.empty((3 * n, cols), dtype=torch.float64, device=dev),
+               torch.empty((P,), dtype=torch.int32, device=dev))
+    useed, npath = out
+    pth = torch.empty((prm.n_nodes + 2, P), dtype=torch.int32, device=dev) if path else None
+    rm = roadmap or {}
+    if not linear:
+        N, k = prm.n_nodes, prm.k
+        _need(rm["nodes"], (3 * n, N * P), torch.float64, "nodes")
+        _need(rm["adj"], (2 * k * N * P,), torch.int32, "adj")
+    rc, pc = robot.c(), prm.c()
+    sp = _spheres_c(spheres, torch.float64)
+    _check(lib.cr_prm_query(C.byref(rc), C.byref(sp), P, C.byref(pc), _ptr(rm.get("nodes")), _ptr(rm.get("attempts")),
+                            _ptr(rm.get("adj_off")), _ptr(rm.get("adj")), _ptr(rm.get("adj_w")), _ptr(u_start_goal),
+                            H, S, _ptr(bump), 1 if linear else 0, _ptr(useed), _ptr(npath), _ptr(pth),
+                            _stream(u_start_goal)))
+    return useed, npath, pth
 
 
 def solve_ik(robot: Robot, T_target: torch.Tensor, u_seed: torch.Tensor, weights: Weights = None,

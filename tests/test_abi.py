@@ -154,3 +154,30 @@ def test_batch_table_validation_on_host(cr):
     b = L.cr_solve_batch_workspace(rob, 2, table(good + good), 6, oc, 0)
     c = L.cr_solve_batch_workspace(rob, 2, table(good), 3, oc, 1)
     assert 0 < a < b and a < c
+
+
+def test_prm_rejects_bad_arguments_on_host(cr):
+    L = cr.lib
+    rb = _robot(cr).c()
+    sp = cr._Spheres()
+    fake = C.c_void_p(256)
+    for bad in (dict(n_nodes=0), dict(n_nodes=4096), dict(k=0), dict(k=33), dict(n_check=65), dict(max_attempts=0)):
+        o = cr.PrmOpts(**{**dict(n_nodes=64, k=4, n_check=2), **bad}).c()
+        assert L.cr_prm_build(C.byref(rb), C.byref(sp), 4, C.byref(o), fake, fake, fake, fake, fake, fake,
+                              None) == cr.CR_EINVAL
+    o = cr.PrmOpts(n_nodes=64, k=4, n_check=2).c()
+    assert L.cr_prm_build(C.byref(rb), C.byref(sp), 70000, C.byref(o), fake, fake, fake, fake, fake, fake,
+                          None) == cr.CR_EINVAL
+    assert L.cr_prm_build(C.byref(rb), C.byref(sp), 4, C.byref(o), None, fake, fake, fake, fake, fake,
+                          None) == cr.CR_EINVAL
+    ext = _robot(cr, L_min=[0.05, 0.04, 0.03], L_max=[0.12, 0.1, 0.08]).c()
+    assert L.cr_prm_build(C.byref(ext), C.byref(sp), 4, C.byref(o), fake, fake, fake, fake, fake, fake,
+                          None) == cr.CR_EUNSUPPORTED
+    for H, S in ((0, 4), (256, 4), (8, 0), (8, 4097)):
+        assert L.cr_prm_query(C.byref(rb), C.byref(sp), 4, C.byref(o), fake, fake, fake, fake, fake, fake, H, S, None,
+                              0, fake, fake, None, None) == cr.CR_EINVAL
+    # the roadmap may be missing only for the straight-line initializer
+    assert L.cr_prm_query(C.byref(rb), C.byref(sp), 4, C.byref(o), None, None, None, None, None, fake, 8, 4, None, 0,
+                          fake, fake, None, None) == cr.CR_EINVAL
+    assert L.cr_prm_query(C.byref(rb), C.byref(sp), 4, C.byref(o), None, None, None, None, None, fake, 8, 4, None, 2,
+                          fake, fake, None, None) == cr.CR_EINVAL
