@@ -36,7 +36,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "uneven_batch"],
+                    choices=[WORKLOAD, "ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "traj_prm_5seg",
+                             "uneven_batch"],
                     help="the headline IK workload, or one of the path / trajectory workloads")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -387,6 +388,9 @@ def main():
     if args.workload == "ik_box_3seg":
         print(json.dumps(run_ik_box(args, cr, I, torch, args.steps, args.warmup)), flush=True)
         return
+    if args.workload == "traj_prm_5seg":
+        print(json.dumps(run_traj_prm(args, cr, I, torch, args.steps, args.warmup)), flush=True)
+        return
     if args.workload != WORKLOAD:
         return bench_trajectories(args, cr, I, torch)
     spec, robot, u_true, seeds, T, useed = build_inputs(cr, I, torch)
@@ -481,7 +485,7 @@ def main():
     torch.cuda.empty_cache()
     subs = {}
     if not args.headline_only:
-        for name in ("ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "uneven_batch"):
+        for name in ("ik_ext_4seg", "ik_box_3seg", "path_4seg", "traj_5seg", "traj_prm_5seg", "uneven_batch"):
             print(f"bench: workload {name}", file=sys.stderr, flush=True)
             subs[name] = sub_workload(name, args, cr, I, torch)
             torch.cuda.empty_cache()
@@ -549,18 +553,34 @@ def traj_inputs(name, cr, I, torch, O=None):
         fr = cr.fk(robot, torch.tensor(samp.reshape(4096, -1).T.copy(), device=dev), arc=False)["frames"]
         tips = fr[12 * (n - 1):12 * n].cpu().numpy().T.reshape(4096, 3, 4)[:, :, 3]
         lo, hi = tips.min(axis=0), tips.max(axis=0)
-        seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, Tn, b) for p in range(P)])
+        if "prm" in spec:   # the seeds' perturbations, applied by the initializer on the device
+            bumps = np.stack([I.path_bumps(rng, n, S, Tn, b) for p in range(P)])
+            out["bump"] = torch.tensor(bumps.reshape(P * S * Tn, -1).T.copy(), device=dev)
+            seeds = None
+        else:
+            seeds = np.stack([I.perturbed_linear_paths(rng, ends[p, 0], ends[p, 1], S, Tn, b) for p in range(P)])
         out["task"] = torch.tensor(np.concatenate([ends[:, 0].reshape(P, -1), ends[:, 1].reshape(P, -1)], 1).T.copy(),
                                    device=dev)
         M = spec["M"]
-        pts = cr.fk(robot, torch.tensor(ends.reshape(2 * P, -1).T.copy(), device=dev), arc=False, frames=False,
-                    points=True)["pts"].cpu().numpy().T.reshape(P, 2 * n * K, 3)
+
+        def points(u):
+            res = cr.fk(robot, torch.tensor(u.reshape(len(u), -1).T.copy(), device=dev), arc=False, frames=False,
+                        points=True)["pts"].cpu().numpy().T
+            return res.reshape(len(u), n * K, 3)
+
+        pts = points(ends.reshape(2 * P, n, 3)).reshape(P, 2 * n * K, 3)
         sph = np.zeros((P, M, 4))
         body = np.tile(np.repeat(np.asarray(spec["r"]), K), 2)
+        nb = spec.get("blockers", 0)
+        have = np.zeros(P, dtype=int)
+        if nb:
+            sph[:, :nb], have = I.line_blockers(rng, ends, nb, *spec.get("sph_r", (0.005, 0.02)), points,
+                                                np.repeat(np.asarray(spec["r"]), K))
+            out["blockers"] = have
         for p in range(P):
-            m = 0
+            m = int(have[p])
             while m < M:
-                cand = I.spheres(rng, 2 * M, lo, hi, 0.005, 0.02)
+                cand = I.spheres(rng, 2 * M, lo, hi, *spec.get("sph_r", (0.005, 0.02)))
                 for s in cand:
                     if m < M and (np.linalg.norm(pts[p] - s[:3], axis=1) - s[3] - body).min() > 1e-3:
                         sph[p, m] = s
@@ -569,7 +589,8 @@ def traj_inputs(name, cr, I, torch, O=None):
         out["sph_host"] = sph
         out["ends"] = ends
     out["seeds"] = seeds
-    out["useed"] = torch.tensor(seeds.reshape(P * S * Tn, -1).T.copy(), device=dev)
+    if seeds is not None:
+        out["useed"] = torch.tensor(seeds.reshape(P * S * Tn, -1).T.copy(), device=dev)
     return out
 
 
@@ -621,6 +642,95 @@ def run_trajectories(name, args, cr, I, torch, steps, warmup, extras):
         if not args.no_cpu_baseline:
             print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
             line["cpu_baseline"] = traj_cpu_baseline(d, spec, weights, opts, args.cpu_seconds)
+    return line
+
+
+def event_ms(torch, fn, reps):
+    """Median duration (ms) of fn() over reps runs, HIP events on the current stream."""
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def run_traj_prm(args, cr, I, torch, steps, warmup):
+    """Trajectory planning with the PRM initializer (Algorithm 2) against the
+    straight-line initializer on the same scenes, seeds' perturbations and solve:
+    one step = the online query on every problem (ConnectToRoadmap, Dijkstra,
+    ResampleLinear, seeds) plus the two-stage solve.  The roadmaps are built once
+    (offline) and timed on their own."""
+    name = "traj_prm_5seg"
+    d = traj_inputs(name, cr, I, torch)
+    spec, robot, P, S, H = d["spec"], d["robot"], d["P"], d["S"], d["H"]
+    pr = spec["prm"]
+    prm = cr.PrmOpts(n_nodes=pr["n_nodes"], k=pr["k"], n_check=pr["n_check"], max_attempts=pr["max_attempts"],
+                     key=(spec["seed"], 2))
+    rm = cr.prm_build(robot, P, prm, spheres=d["spheres"])
+    torch.cuda.synchronize()
+    build_ms = event_ms(torch, lambda: cr.prm_build(robot, P, prm, spheres=d["spheres"]), 3)
+    att = rm["attempts"].cpu().numpy()
+    nbr = rm["nbr"].cpu().numpy()
+    opts = cr.Opts(n_final=spec["n_final"], k_init=spec["k_init"], k_final=spec["k_final"])
+    weights = cr.Weights(**spec.get("weights", {}))
+    ws = torch.empty(cr.traj_workspace_bytes(robot, P, H, S, opts, torch.float32), dtype=torch.uint8, device="cuda")
+    out = (torch.empty((3 * robot.n, (H + 1) * P), dtype=torch.float64, device="cuda"),
+           torch.empty((2, P), dtype=torch.float64, device="cuda"),
+           torch.empty((P,), dtype=torch.int32, device="cuda"))
+    qout = (torch.empty((3 * robot.n, (H + 1) * S * P), dtype=torch.float64, device="cuda"),
+            torch.empty((P,), dtype=torch.int32, device="cuda"))
+
+    def query(linear):
+        cr.prm_query(robot, prm, d["task"], H, S, roadmap=rm, bump=d["bump"], linear=linear, spheres=d["spheres"],
+                     out=qout)
+
+    def step(linear=False):
+        query(linear)
+        cr.solve_traj(robot, d["task"], qout[0], H, weights, opts, dtype=torch.float32, spheres=d["spheres"],
+                      workspace=ws, out=out)
+
+    tuned = autotune(args, cr, torch, step)
+    res = {}
+    for linear in (False, True):
+        for _ in range(warmup):
+            step(linear)
+        torch.cuda.synchronize()
+        per_step, total = step_times(torch, lambda: step(linear), steps)
+        st = out[2].cpu().numpy()
+        npath = qout[1].cpu().numpy()
+        ms = float(np.median(per_step))
+        res[linear] = dict(value=round(P / (ms * 1e-3), 2), unit="trajectories/s", ms_per_step=round(ms, 4),
+                           ms_per_step_mean=round(total / steps, 4),
+                           success_rate=round(float((st == cr.SOLVED).mean()), 4),
+                           status_counts={int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+                           query_ms=round(event_ms(torch, lambda: query(linear), 3), 4))
+        if not linear:
+            res[linear]["paths"] = dict(connected=round(float((npath >= 0).mean()), 4),
+                                        detour=round(float((npath > 0).mean()), 4),
+                                        mean_roadmap_nodes=round(float(npath[npath >= 0].mean()), 2)
+                                        if (npath >= 0).any() else None)
+        print(f"bench: {name} {'linear' if linear else 'prm'} {res[linear]}", file=sys.stderr, flush=True)
+    line = dict(metric="trajectory solves/sec with the PRM initializer (success %)", value=res[False]["value"],
+                unit="trajectories/s", n_gpus=1, steps=steps, warmup=warmup, ms_per_step=res[False]["ms_per_step"],
+                ms_per_step_mean=res[False]["ms_per_step_mean"], higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32", refine_dtype="f64", data="synthetic",
+                config=dict(workload=name, segments=robot.n, problems=P, waypoints=H + 1, seeds=S,
+                            spheres=spec["M"], blockers=spec["blockers"],
+                            blockers_mean=round(float(d["blockers"].mean()), 3), pts_per_seg=robot.pts_per_seg,
+                            k_init=spec["k_init"], k_final=spec["k_final"], n_final=spec["n_final"], prm=pr),
+                success_rate=res[False]["success_rate"], status_counts=res[False]["status_counts"],
+                initializer="prm", query=dict(ms=res[False]["query_ms"], **res[False]["paths"]),
+                linear_initializer={k: v for k, v in res[True].items() if k != "query_ms"} | dict(
+                    query_ms=res[True]["query_ms"]),
+                roadmap=dict(build_ms=round(build_ms, 3), nodes=P * prm.n_nodes,
+                             kept_nodes=int((att > 0).sum()),
+                             free_motions=int((nbr >= 0).sum()),
+                             colliding_motions=int(((nbr < 0) & (nbr != cr.PRM_NONE)).sum())),
+                autotune=tuned)
     return line
 
 
@@ -765,10 +875,13 @@ def sub_workload(name, args, cr, I, torch):
         ln = run_ik_box(args, cr, I, torch, args.sub_steps, 1)
     elif name == "uneven_batch":
         ln = run_uneven(args, cr, I, torch, args.sub_steps, 1, False)
+    elif name == "traj_prm_5seg":
+        ln = run_traj_prm(args, cr, I, torch, args.sub_steps, 1)
     else:
         ln = run_trajectories(name, args, cr, I, torch, args.sub_steps, 1, False)
     keep = ("value", "unit", "ms_per_step", "ms_per_step_mean", "steps", "success_rate", "success_by_kind",
-            "status_counts", "config", "counter_roofline", "autotune")
+            "status_counts", "config", "counter_roofline", "autotune", "initializer", "linear_initializer", "roadmap",
+            "query")
     return {k: ln[k] for k in keep if k in ln}
 
 

@@ -39,6 +39,17 @@ WORKLOADS = {
     "traj_5seg": dict(
         kind="traj", L=[0.06] * 5, r=[0.006] * 5, b=0.006, P=256, H=31, S=64, M=64,
         k_init=80, k_final=20, n_final=4, K=64, dtype="f32", seed=BASE_SEED + 4),
+    # the trajectory workload with the PRM initializer of Algorithm 2 (Sec. V-C
+    # compares it with the straight line): the same robot, horizon and seeds in
+    # a random scene shaped like the paper's (27 spheres of radius 0.05 to 0.10
+    # of the workspace's side: 25 to 50 mm for the ~0.5 m box of this robot's
+    # tips); up to 8 of them sit on backbone points of the straight start-goal
+    # motion; roadmaps of 1024 nodes with 10 neighbours, motions checked at 8
+    # interior configurations
+    "traj_prm_5seg": dict(
+        kind="traj", L=[0.06] * 5, r=[0.006] * 5, b=0.006, P=256, H=31, S=64, M=27,
+        k_init=80, k_final=20, n_final=4, K=64, dtype="f32", seed=BASE_SEED + 8, blockers=8, sph_r=(0.025, 0.05),
+        prm=dict(n_nodes=1024, k=10, n_check=8, max_attempts=8)),
     # extendable robot among obstacles (Sec. V-B, the extendable row of Table II):
     # segment lengths free within [0.5, 1.5] of nominal, a 3 x 3 x 3 lattice of
     # spheres (radius 0.2 of a segment length, the paper's ratio) with seeded
@@ -56,6 +67,43 @@ WORKLOADS = {
         k_init=150, k_final=50, n_final=8, K=10, dtype="f32", seed=BASE_SEED + 7,
         boxes=dict(count=12, lo=(-0.2, -0.2, 0.0), hi=(0.2, 0.2, 0.3), half_lo=0.01, half_hi=0.05, clear=3e-3)),
 }
+
+
+def line_blockers(rng: np.random.Generator, ends: np.ndarray, count: int, r_lo: float, r_hi: float, points,
+                  body: np.ndarray, clear: float = 1e-3, rounds: int = 16):
+    """Spheres [P, count, 4] in the way of each problem's straight motion between
+    ends[p, 0] and ends[p, 1] ([P, 2, n, 3] actuations): a candidate is centred on
+    a backbone point of the distal half of the configuration (1 - s) u_start +
+    s u_goal, s ~ U[0.25, 0.75], radius U[r_lo, r_hi], and kept if it clears the
+    start and goal backbones by `clear`; after `rounds` rounds of 4 * count
+    candidates a problem keeps the blockers it has (start and goal too close for
+    more).  points(u [B, n, 3]) -> [B, Q, 3] gives the caller's backbone points (Q
+    per configuration, radii body [Q]).  Returns the spheres (rows past a
+    problem's count are zero) and the count per problem [P]."""
+    P = ends.shape[0]
+    end_pts = points(ends.reshape((2 * P,) + ends.shape[2:])).reshape(P, -1, 3)
+    out = np.zeros((P, count, 4))
+    have = np.zeros(P, dtype=int)
+    for _ in range(rounds):
+        if (have >= count).all():
+            break
+        todo = np.flatnonzero(have < count)
+        m = 4 * count
+        s = rng.uniform(0.25, 0.75, size=(len(todo), m))
+        u = (1.0 - s)[:, :, None, None] * ends[todo, 0][:, None] + s[:, :, None, None] * ends[todo, 1][:, None]
+        pts = points(u.reshape((-1,) + ends.shape[2:])).reshape(len(todo), m, -1, 3)
+        Q = pts.shape[2]
+        idx = rng.integers(Q // 2, Q, size=(len(todo), m))
+        rad = rng.uniform(r_lo, r_hi, size=(len(todo), m))
+        for a, p in enumerate(todo):
+            for c in range(m):
+                if have[p] >= count:
+                    break
+                cen = pts[a, c, idx[a, c]]
+                if (np.linalg.norm(end_pts[p] - cen, axis=1) - rad[a, c] - np.tile(body, 2)).min() > clear:
+                    out[p, have[p]] = [*cen, rad[a, c]]
+                    have[p] += 1
+    return out, have
 
 
 def random_boxes(rng: np.random.Generator, count: int, lo, hi, half_lo: float, half_hi: float):

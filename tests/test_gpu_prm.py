@@ -176,3 +176,71 @@ def test_prm_seeds_feed_the_trajectory_solve(oracle, cr):
                            oracle.Opts(n_final=2, k_init=3, k_final=2), q["seeds"])
         assert st[p] == res["status"], p
         assert np.abs(u[p] - res["u"]).max() <= 1e-9 * CASE["b"], p
+
+
+def test_full_size_sampled(oracle, cr):
+    """The PRM trajectory workload's roadmap shape (256 scenes of 27 spheres, up to
+    8 of them on the straight start-goal motion; 1024 nodes, 10 neighbours, 8
+    checks per motion; 5 segments, 64 points each) in one launch; the oracle
+    checks problem 0 whole (roadmap and query) and 64 sampled nodes of problem
+    255 (neighbour lists and motion verdicts)."""
+    spec = I.WORKLOADS["traj_prm_5seg"]
+    n, K, P, M, H, S = len(spec["L"]), spec["K"], spec["P"], spec["M"], spec["H"], 4
+    pr = spec["prm"]
+    ro, rg = _robots(oracle, cr, spec["L"], spec["r"], spec["b"], K)
+    rng = np.random.default_rng(2607)
+    ends = I.uniform_actuation(rng, n, spec["b"], 2 * P).reshape(P, 2, n, 3)
+
+    def points(u):
+        return np.stack([oracle.fk(ro, x, points=True)[2].reshape(-1, 3) for x in u])
+
+    sph = np.zeros((P, M, 4))
+    nb, (r_lo, r_hi) = spec["blockers"], spec["sph_r"]
+    sph[:, :nb], have = I.line_blockers(rng, ends, nb, r_lo, r_hi, points, np.repeat(spec["r"], K))
+    rest = np.concatenate([rng.uniform([-0.25, -0.25, -0.04], [0.25, 0.25, 0.3], size=(P, M, 3)),
+                           rng.uniform(r_lo, r_hi, size=(P, M, 1))], axis=2)
+    for p in range(P):
+        sph[p, have[p]:] = rest[p, :M - have[p]]
+    sp = (torch.tensor(np.ascontiguousarray(sph.reshape(P * M, 4).T), device="cuda"), True, M)
+    key = (spec["seed"], 2)
+    prm = cr.PrmOpts(n_nodes=pr["n_nodes"], k=pr["k"], n_check=pr["n_check"], max_attempts=pr["max_attempts"], key=key)
+    print("prm full size: build", flush=True)
+    rm_g = cr.prm_build(rg, P, prm, spheres=sp)
+    usg = torch.tensor(ends.reshape(P, 6 * n).T.copy(), device="cuda")
+    bumps = I.path_bumps(rng, n, S * P, H + 1, spec["b"]).reshape(P, S, H + 1, n, 3)
+    bump_g = torch.tensor(bumps.reshape(P * S * (H + 1), 3 * n).T.copy(), device="cuda")
+    print("prm full size: query", flush=True)
+    useed, npath, path = cr.prm_query(rg, prm, usg, H, S, roadmap=rm_g, bump=bump_g, spheres=sp, path=True)
+    torch.cuda.synchronize()
+    N, k = pr["n_nodes"], pr["k"]
+    first = dict(nodes=rm_g["nodes"][:, :N], attempts=rm_g["attempts"][:N], nbr=rm_g["nbr"][:, :N],
+                 adj_off=rm_g["adj_off"][:N + 1], adj=rm_g["adj"][:2 * k * N], adj_w=rm_g["adj_w"][:2 * k * N])
+    rms = _compare_roadmap(oracle, ro, first, 1, N, k, pr["n_check"], key, pr["max_attempts"], sph[:1], False)
+    q = oracle.prm_query(ro, rms[0], k, pr["n_check"], ends[0, 0], ends[0, 1], H, S=S, bumps=bumps[0], spheres=sph[0])
+    assert npath.cpu().numpy()[0] == q["n_path"]
+    useed = aos(useed.cpu().numpy(), (n, 3)).reshape(P, S, H + 1, n, 3)
+    assert np.abs(useed[0] - q["seeds"]).max() <= 1e-14
+    assert list(path.cpu().numpy()[:len(q["path"]), 0]) == list(q["path"])
+    print(f"  problem 0: n_path {q['n_path']}", flush=True)
+    # problem P - 1: nodes, the k nearest nodes and the motion verdicts of 64
+    # sampled nodes (the oracle's lists without checks, then the sampled checks)
+    p = P - 1
+    ref = oracle.prm_roadmap(ro, p, N, k, 0, key, max_attempts=pr["max_attempts"], spheres=sph[p])
+    u_o = ref["nodes"].reshape(N, 3 * n)
+    nodes_g = aos(rm_g["nodes"].cpu().numpy(), (n, 3)).reshape(P, N, 3 * n)[p]
+    att_g = rm_g["attempts"].cpu().numpy().reshape(P, N)[p]
+    nbr_g = rm_g["nbr"].cpu().numpy().reshape(k, P, N)[:, p].T
+    assert np.array_equal(att_g, ref["attempts"])
+    assert np.abs(nodes_g - u_o).max() <= 8 * np.spacing(spec["b"])
+    kept = np.flatnonzero(ref["attempts"] > 0)
+    checked = 0
+    for i in np.random.default_rng(3).choice(kept, size=min(64, len(kept)), replace=False):
+        for c, j in enumerate(ref["nbr"][i]):
+            if j == oracle.PRM_NONE:
+                assert nbr_g[i, c] == j
+                continue
+            g = oracle.motion_gap(ro, u_o[min(i, j)], u_o[max(i, j)], pr["n_check"], sph[p])
+            want = j if not g < 0 else -1 - j
+            assert nbr_g[i, c] == want or abs(g) <= 1e-12, (i, c, nbr_g[i, c], want, g)
+            checked += 1
+    assert checked >= 64 * k // 2
