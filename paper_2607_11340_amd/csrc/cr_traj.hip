@@ -84,23 +84,26 @@ __device__ __forceinline__ TrajCtx traj_ctx(const TrajArgs<T>& ta, int64_t traj)
 //   OL:  L_tt, lower triangle packed by columns (column j from
 //        j NZ - j (j - 1) / 2, rows j .. NZ - 1: the backward pass reads a column
 //        per lane)
-//   OB, OC: L_{t,t-1}, L_{t,t-2}, row-major (element (i, j) at i NZ + j: the
-//        forward pass writes a row per lane as NZ consecutive values)
+//   OB:  L_{t,t-1}, row-major (element (i, j) at i NZ + j: the forward pass
+//        writes a row per lane as NZ consecutive values)
 //   OY:  y_t, then delta_t
+// L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T is not stored: the backward pass forms
+// L_{t,t-2}^T delta_t as L_{t-2,t-2}^-1 (H_{t,t-2}^T delta_t) from the segment
+// blocks, a triangular solve instead of a block read and write through HBM.
 __host__ __device__ constexpr int rec_up4(int x) { return (x + 3) & ~3; }
 __host__ __device__ constexpr int rec_size(int ns) {
-  return 2 * rec_up4(2 * ns * (2 * ns + 1) / 2) + 2 * (2 * ns) * (2 * ns) + 2 * rec_up4(2 * ns) + 2 * rec_up4(3 * ns);
+  return 2 * rec_up4(2 * ns * (2 * ns + 1) / 2) + (2 * ns) * (2 * ns) + 2 * rec_up4(2 * ns) + 2 * rec_up4(3 * ns);
 }
 template <int NS>
 struct Rec {
   static constexpr int NZ = 2 * NS, NP = NZ * (NZ + 1) / 2;
-  static constexpr int OL = 0, OB = rec_up4(NP), OC = OB + NZ * NZ, OY = OC + NZ * NZ, OG = OY + rec_up4(NZ),
+  static constexpr int OL = 0, OB = rec_up4(NP), OY = OB + NZ * NZ, OG = OY + rec_up4(NZ),
                        OHI = OG + rec_up4(NZ), OBS = OHI + rec_up4(NP), OCS = OBS + rec_up4(3 * NS),
                        SIZE = OCS + rec_up4(3 * NS);
   // with a 256-byte aligned workspace every record and block starts on a 16-byte
-  // boundary in FP32 and FP64; a row of OB / OC is 16-byte aligned when NZ is a
+  // boundary in FP32 and FP64; a row of OB is 16-byte aligned when NZ is a
   // multiple of 4 or in FP64, else 8-byte aligned
-  static_assert(SIZE % 4 == 0 && OB % 4 == 0 && OC % 4 == 0 && OY % 4 == 0 && OG % 4 == 0,
+  static_assert(SIZE % 4 == 0 && OB % 4 == 0 && OY % 4 == 0 && OG % 4 == 0,
                 "record blocks must be 16-byte aligned");
   static_assert(SIZE == rec_size(NS), "rec_size must follow the layout");
   // first value of column j of L_tt in OL
@@ -860,31 +863,46 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 }
 
 // Block Cholesky of the block-pentadiagonal H + lambda D, in place, then
-// y = L^-1 (-g), delta = L^-T y and g.delta.  NZ lanes own the rows of one
-// trajectory (row a on lane a); a 64-lane workgroup holds 64 / NZ trajectories.
-// The sequential chain over waypoints stays per trajectory; the last factors
-// L_{t-1,t-1}, L_{t-2,t-2}, L_{t-1,t-2} and y live in LDS so every lane can read
-// the rows it needs.  Rows are exchanged only within a wave (workgroup = one wave).
-// The diagonal block is factored by rounds over its columns in FP64 (one LDS
-// exchange per column); in FP32 the whole block fits the registers of every row
-// lane, so it is exchanged once and factored redundantly by each lane.
+// y = L^-1 (-g), delta = L^-T y and g.delta, from both ends of the trajectory at
+// once.  2 NZ lanes own one trajectory: the top group (row a on lane a) factors
+// waypoints 0 .. m-1 forward, the bottom group factors waypoints Tn-1 .. m+2 in
+// reverse order (the same recurrences on the reversed matrix, whose couplings are
+// the transposed blocks), then eliminates its part from the two middle waypoints
+// m, m+1 (their Schur complement), and the top group factors those two last.  The
+// backward substitution starts at the middle and runs outward on both groups.
+// For Tn < 4 the top group does everything.  The sequential chain is thus about
+// Tn / 2 + 4 steps instead of Tn, on twice the lanes.
+// Storage of the factor (records of the workspace): the top group stores row a of
+// L_tt and L_{t,t-1} in record t (OL, OB); the bottom group, whose chain
+// predecessors of waypoint r are r+1 and r+2, stores row a of its coupling block
+// to r+1 in record r+1 (OB), so that each of its backward steps finds that
+// coupling in its own record and no input is overwritten before it is read.  The
+// couplings two apart are formed again from the segment blocks in the backward
+// pass.  The last factors, y and delta of each group are
+// in LDS (diagonal factors packed by rows); the middle downdates go from the
+// bottom group to the top group through the bottom group's free LDS slots.
+// Rows are exchanged only within a wave (workgroup = one wave).  In FP32 the
+// diagonal block is exchanged once and factored redundantly by each row lane; in
+// FP64 it is factored by rounds over its columns (one LDS exchange per column).
 template <int NS, typename T>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (NS <= 4 ? 4 : (NS == 5 ? 3 : 1)) : 1)))
     k_traj_solve(TrajArgs<T> ta, int64_t nt, T* __restrict__ blk, const T* __restrict__ lam, const int32_t* __restrict__ failed,
                  int32_t* __restrict__ chol_ok, T* __restrict__ gd_out) {
-  constexpr int NZ = 2 * NS, G = 64 / NZ;
+  constexpr int NZ = 2 * NS, G2 = 64 / (2 * NZ), NG = 2 * G2, NP = NZ * (NZ + 1) / 2;
   constexpr int RS = NZ + (NZ & 1);  // LDS row stride
-  constexpr int GS = NZ * RS + 4;    // LDS group stride (breaks bank aliasing between groups)
+  constexpr int GS = NZ * RS + 4;    // LDS stride of a full block (breaks bank aliasing between groups)
+  constexpr int PS = NP + 4;         // LDS stride of a packed triangle
   using R = Rec<NS>;
-  __shared__ T sL[3][G * GS];     // L_tt of waypoints t mod 3 (row i at i * RS)
-  __shared__ T sD[3][G * RS];     // 1 / diag(L_tt)
-  __shared__ T sB[2][G * GS];     // L_{t,t-1} of waypoints t mod 2
-  __shared__ T sX[G * GS];        // rows of the block being formed (for the symmetric updates)
-  __shared__ T sY[3][G * RS];     // y_t, later delta_t, of waypoints t mod 3
+  __shared__ T sL[3][NG * PS];     // L_pp of chain positions p mod 3, packed by rows
+  __shared__ T sD[3][NG * RS];     // 1 / diag(L_pp)
+  __shared__ T sB[NG * GS];        // coupling of the last position to the one before it
+  __shared__ T sX[NG * GS];        // rows of the coupling being formed (for the symmetric updates)
+  __shared__ T sY[3][NG * RS];     // y_p, later delta, of positions p mod 3
   const int lane = threadIdx.x;
-  const bool inw = lane < G * NZ;  // lane owns a row
-  const int g = inw ? lane / NZ : 0, a = inw ? lane - g * NZ : 0, base = g * NZ;
-  const int64_t traj = (int64_t)blockIdx.x * G + g;
+  const bool inw = lane < NG * NZ;  // lane owns a row
+  const int gg = inw ? lane / NZ : 0, a = inw ? lane - gg * NZ : 0, base = gg * NZ;
+  const int half = gg & 1, j2 = gg >> 1, pg = gg ^ 1;  // 0: top, 1: bottom; partner group
+  const int64_t traj = (int64_t)blockIdx.x * G2 + j2;
   const bool act = inw && traj < nt && !failed[traj];
   int Tn = 0;
   int64_t wp = 0;
@@ -893,176 +911,193 @@ __global__ void __launch_bounds__(64)
     Tn = cx.pr.Tn;
     wp = cx.wp;
   }
+  // chain geometry: the bottom group factors nbot waypoints, the top group m
+  // before the middle pair (nbot = 0: the top group alone, all Tn)
+  const int nbot = Tn >= 4 ? (Tn - 1) / 2 : 0;
+  const int m = Tn >= 4 ? (Tn - 2) / 2 : Tn;
+  const int ntop = Tn - nbot;
+  const int nfull = half ? nbot : m;  // full steps of this group in the first phase
+  const int Tm = ta.Tmax;
+  const int K1 = Tm >= 4 ? max((Tm - 1) / 2, min(Tm, 3)) : Tm;  // first-phase steps of the launch
   const T lm = act ? lam[traj] : T(0);
   T* const recs = blk + wp * R::SIZE;
   bool ok = true;
-  // row a of the input blocks of a record: H_tt (lower part, b <= a; the rest
-  // is never read), H_{t,t-1} (in full for trajectories, else from the segment's
-  // 2 x 2 block) and H_{t,t-2} (from the segment's 2 x 2 block), and g_a
   const bool dense_b = ta.kind == CR_KIND_TRAJ;
   const int sa = 3 * (a >> 1) + (a & 1);  // row a of the segment's (aa, ab, bb)
-  auto load_inputs = [&](const T* r, T* h, T* bw, T* c, T& gv) {
+  // Inputs of the step at waypoint r: row a of H_rr (lower part), of the coupling
+  // to the chain predecessor (top: H_{r,r-1} from record r; bottom: H_{r,r+1} =
+  // H_{r+1,r}^T, column a of record r+1's block, or its symmetric segment blocks),
+  // of the coupling two back (the segment blocks of record r or r+2, symmetric),
+  // and g_a.  hb, hc: the couplings exist.
+  auto load_step = [&](int r, bool hb, bool hc, T* h, T* bw, T* c, T& gv) {
+    const T* rr = recs + (int64_t)r * R::SIZE;
 #pragma unroll
-    for (int b = 0; b < NZ; ++b) h[b] = b <= a ? r[R::OHI + a * (a + 1) / 2 + b] : T(0);
-    if (dense_b) {
-      load_run<NZ>(r + R::OB + a * NZ, bw);
-    } else {
-      const T b0 = r[R::OBS + sa], b1 = r[R::OBS + sa + 1];
+    for (int b = 0; b < NZ; ++b) h[b] = b <= a ? rr[R::OHI + a * (a + 1) / 2 + b] : T(0);
+    gv = rr[R::OG + a];
+    const T* rb = half ? rr + R::SIZE : rr;
+    const T* rc = half ? rr + 2 * R::SIZE : rr;
+    if (hb) {
+      if (dense_b) {
+        if (half) {
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) bw[b] = b == (a & ~1) ? b0 : (b == (a | 1) ? b1 : T(0));
-    }
-    const T c0 = r[R::OCS + sa], c1 = r[R::OCS + sa + 1];
-#pragma unroll
-    for (int b = 0; b < NZ; ++b) c[b] = b == (a & ~1) ? c0 : (b == (a | 1) ? c1 : T(0));
-    gv = r[R::OG + a];
-  };
-  // FP32 rows of the next waypoint's blocks are loaded while the current one is
-  // factored (the chain over waypoints is latency-bound)
-  constexpr bool PF = sizeof(T) == 4 && NZ <= 10;
-  T pH[NZ], pB[NZ], pC[NZ], pG = T(0);
-  if constexpr (PF) {
-    if (act && 0 < Tn) load_inputs(recs, pH, pB, pC, pG);
-  }
-  // every lane runs the longest horizon of the launch (workgroup-uniform barriers);
-  // a trajectory's lanes work only while t < its own horizon
-  for (int t = 0; t < ta.Tmax; ++t) {
-    const bool on = act && t < Tn;
-    T* rec = recs + (int64_t)t * R::SIZE;
-    T cH[NZ], cB[NZ], cC[NZ], cG = T(0);
-    if constexpr (PF) {
-#pragma unroll
-      for (int k = 0; k < NZ; ++k) {
-        cH[k] = pH[k];
-        cB[k] = pB[k];
-        cC[k] = pC[k];
-      }
-      cG = pG;
-      if (act && t + 1 < Tn) load_inputs(rec + R::SIZE, pH, pB, pC, pG);
-    } else {
-      if (on) load_inputs(rec, cH, cB, cC, cG);
-    }
-    const int s0 = t % 3, s1 = (t + 2) % 3, s2 = (t + 1) % 3;  // slots of t, t-1, t-2
-    const int b0 = t & 1, b1 = b0 ^ 1;
-    T S[NZ];  // row a of H_tt, lower part (b <= a)
-    if (on) {
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) S[b] = cH[b];
-    } else {
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) S[b] = T(b == a);
-    }
-#pragma unroll
-    for (int b = 0; b < NZ; ++b)
-      if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
-    T y = on ? -cG : T(0);
-    T Bw[NZ];  // row a of H_{t,t-1}
-    if (on && t >= 1) {
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) Bw[b] = cB[b];
-    } else {
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) Bw[b] = T(0);
-    }
-    if (t >= 2) {
-      // row a of L_{t,t-2} = H_{t,t-2} L_{t-2,t-2}^-T (forward substitution)
-      const T* L2 = &sL[s2][g * GS];
-      const T* D2 = &sD[s2][g * RS];
-      T x[NZ];  // row a of H_{t,t-2}, then of L_{t,t-2}
-      if (on) {
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) x[i] = cC[i];
+          for (int b = 0; b < NZ; ++b) bw[b] = rb[R::OB + b * NZ + a];
+        } else {
+          load_run<NZ>(rb + R::OB + a * NZ, bw);
+        }
       } else {
+        const T b0 = rb[R::OBS + sa], b1 = rb[R::OBS + sa + 1];
 #pragma unroll
-        for (int i = 0; i < NZ; ++i) x[i] = T(0);
+        for (int b = 0; b < NZ; ++b) bw[b] = b == (a & ~1) ? b0 : (b == (a | 1) ? b1 : T(0));
       }
+    } else {
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        T v = x[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) v -= L2[i * RS + j] * x[j];
-        x[i] = v * D2[i];
-      }
-      const T* Y2 = &sY[s2][g * RS];
-      const T* B1 = &sB[b1][g * GS];  // L_{t-1,t-2}
-#pragma unroll
-      for (int i = 0; i < NZ; ++i) y -= x[i] * Y2[i];
-      if (on) store_run<NZ>(x, rec + R::OC + a * NZ);
-      // H_{t,t-1} -= L_{t,t-2} L_{t-1,t-2}^T
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) {
-        T v = T(0);
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) v += x[i] * B1[b * RS + i];
-        Bw[b] -= v;
-      }
-      if (inw) {
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) sX[g * GS + a * RS + i] = x[i];
-      }
-      __syncthreads();
-      // S -= L_{t,t-2} L_{t,t-2}^T (row a)
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) {
-        T v = T(0);
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) v += x[i] * sX[g * GS + b * RS + i];
-        S[b] -= v;
-      }
-      __syncthreads();
+      for (int b = 0; b < NZ; ++b) bw[b] = T(0);
     }
-    if (t >= 1) {
-      // row a of L_{t,t-1} = (H_{t,t-1} - ...) L_{t-1,t-1}^-T
-      const T* L1 = &sL[s1][g * GS];
-      const T* D1 = &sD[s1][g * RS];
+    if (hc) {
+      const T c0 = rc[R::OCS + sa], c1 = rc[R::OCS + sa + 1];
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) c[b] = b == (a & ~1) ? c0 : (b == (a | 1) ? c1 : T(0));
+    } else {
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) c[b] = T(0);
+    }
+  };
+  auto row_of = [&](int p) { return half ? Tn - 1 - p : p; };
+  // One step of the chain at position p (waypoint r), workgroup-uniform barriers.
+  //   on: this lane's group works; hp1, hp2: the predecessors' factors exist;
+  //   cross: the p - 1 coupling in sB is used even without hp1 (the middle);
+  //   fac: factor the diagonal block (else S and y stay the downdates);
+  //   S, y, Bw, Cc: row a of the damped diagonal block, y, the couplings;
+  //   oB: where row a of the coupling to p - 1 goes (nullptr: nowhere);
+  //   orec: record of the factor and y (nullptr: not stored).
+  auto step = [&](bool on, int p, bool hp1, bool hp2, bool cross, bool fac, T* S, T& y, T* Bw, const T* Cc, T* oB,
+                  T* orec) {
+    const int s0 = p % 3, s1 = (p + 2) % 3, s2 = (p + 1) % 3;  // slots of p, p-1, p-2
+    {
+      // row a of L_{p,p-2} = H_{p,p-2} L_{p-2}^-T (forward substitution)
+      const T* L2 = &sL[s2][gg * PS];
+      const T* D2 = &sD[s2][gg * RS];
       T x[NZ];
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-        T v = Bw[i];
-#pragma unroll
-        for (int j = 0; j < i; ++j) v -= L1[i * RS + j] * x[j];
-        x[i] = v * D1[i];
-      }
-      const T* Y1 = &sY[s1][g * RS];
-#pragma unroll
-      for (int i = 0; i < NZ; ++i) y -= x[i] * Y1[i];
-      if (on) store_run<NZ>(x, rec + R::OB + a * NZ);
-      if (inw) {
+      for (int i = 0; i < NZ; ++i) x[i] = on && hp2 ? Cc[i] : T(0);
+      if (on && hp2) {
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-          sX[g * GS + a * RS + i] = x[i];
-          sB[b0][g * GS + a * RS + i] = x[i];
+          T v = x[i];
+#pragma unroll
+          for (int j = 0; j < i; ++j) v -= L2[tri(i, j)] * x[j];
+          x[i] = v * D2[i];
+        }
+        const T* Y2 = &sY[s2][gg * RS];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) y -= x[i] * Y2[i];
+        if (hp1 || cross) {
+          // H_{p,p-1} -= L_{p,p-2} L_{p-1,p-2}^T
+          const T* B1 = &sB[gg * GS];
+#pragma unroll
+          for (int b = 0; b < NZ; ++b) {
+            T v = T(0);
+#pragma unroll
+            for (int i = 0; i < NZ; ++i) v += x[i] * B1[b * RS + i];
+            Bw[b] -= v;
+          }
+        }
+      }
+      __syncthreads();  // sB read
+      if (inw) {
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) sX[gg * GS + a * RS + i] = x[i];
+      }
+      __syncthreads();
+      // S -= L_{p,p-2} L_{p,p-2}^T (row a)
+      if (on && hp2) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) {
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) v += x[i] * sX[gg * GS + b * RS + i];
+          S[b] -= v;
         }
       }
       __syncthreads();
-#pragma unroll
-      for (int b = 0; b < NZ; ++b) {
-        T v = T(0);
-#pragma unroll
-        for (int i = 0; i < NZ; ++i) v += x[i] * sX[g * GS + b * RS + i];
-        S[b] -= v;
-      }
     }
-    T* Lt = &sL[s0][g * GS];
-    T* Dt = &sD[s0][g * RS];
-    T* Yt = &sY[s0][g * RS];
-    if constexpr (sizeof(T) == 4) {
-      // L_tt L_tt^T = S and y_t = L_tt^-1 y in one exchange: the rows of S and y go
-      // to LDS (the slot of waypoint t - 3, no longer read), every lane of the
-      // trajectory factors the whole block in registers with the same arithmetic,
-      // and the first lane publishes the factor for the rows and later waypoints.
+    {
+      // row a of L_{p,p-1} = (H_{p,p-1} - ...) L_{p-1}^-T
+      const T* L1 = &sL[s1][gg * PS];
+      const T* D1 = &sD[s1][gg * RS];
+      T x[NZ];
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) x[i] = T(0);
+      if (on && hp1) {
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+          T v = Bw[i];
+#pragma unroll
+          for (int j = 0; j < i; ++j) v -= L1[tri(i, j)] * x[j];
+          x[i] = v * D1[i];
+        }
+        const T* Y1 = &sY[s1][gg * RS];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) y -= x[i] * Y1[i];
+        if (oB) store_run<NZ>(x, oB);
+      }
       if (inw) {
 #pragma unroll
-        for (int b = 0; b < NZ; ++b) Lt[a * RS + b] = S[b];
+        for (int i = 0; i < NZ; ++i) sX[gg * GS + a * RS + i] = x[i];
+        // the coupling of this position to the previous one, for the next step
+        // (the middle keeps its cross downdate there instead)
+        if (on && (hp1 || !cross)) {
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) sB[gg * GS + a * RS + i] = x[i];
+        }
+        if (on && cross) {
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) sB[gg * GS + a * RS + i] = Bw[i];
+        }
+      }
+      __syncthreads();
+      if (on && hp1) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) {
+          T v = T(0);
+#pragma unroll
+          for (int i = 0; i < NZ; ++i) v += x[i] * sX[gg * GS + b * RS + i];
+          S[b] -= v;
+        }
+      }
+    }
+    T* Lt = &sL[s0][gg * PS];
+    T* Dt = &sD[s0][gg * RS];
+    T* Yt = &sY[s0][gg * RS];
+    if (!fac) {
+      // the middle's downdates, packed like a factor, for the top group
+      __syncthreads();
+      if (inw && on) {
+#pragma unroll
+        for (int b = 0; b < NZ; ++b)
+          if (b <= a) Lt[tri(a, b)] = S[b];
         Yt[a] = y;
       }
       __syncthreads();
-      T L[NZ * (NZ + 1) / 2], yv[NZ], dv[NZ];
+      return;
+    }
+    if constexpr (sizeof(T) == 4) {
+      // L L^T = S and y_p = L^-1 y in one exchange: the rows of S and y go to LDS
+      // (the slot of position p - 3, no longer read), every lane of the group
+      // factors the whole block in registers with the same arithmetic, and the
+      // first lane publishes the factor for the rows and later positions.
+      if (inw && on) {
 #pragma unroll
-      for (int i = 0; i < NZ; ++i) {
-#pragma unroll
-        for (int j = 0; j <= i; ++j) L[tri(i, j)] = Lt[i * RS + j];
-        yv[i] = Yt[i];
+        for (int b = 0; b < NZ; ++b)
+          if (b <= a) Lt[tri(a, b)] = S[b];
+        Yt[a] = y;
       }
+      __syncthreads();
+      T L[NP], yv[NZ], dv[NZ];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) L[i] = Lt[i];
+#pragma unroll
+      for (int i = 0; i < NZ; ++i) yv[i] = Yt[i];
 #pragma unroll
       for (int j = 0; j < NZ; ++j) {
         T dd = L[tri(j, j)];
@@ -1086,27 +1121,27 @@ __global__ void __launch_bounds__(64)
         }
       }
       __syncthreads();
-      if (inw && a == 0) {
+      if (inw && on && a == 0) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) Lt[i] = L[i];
 #pragma unroll
         for (int i = 0; i < NZ; ++i) {
-#pragma unroll
-          for (int j = 0; j <= i; ++j) Lt[i * RS + j] = L[tri(i, j)];
           Dt[i] = dv[i];
           Yt[i] = yv[i];
         }
       }
       __syncthreads();
       y = Yt[a];
-      if (on) {
-        // column a of L_tt, rows a .. NZ - 1
+      if (on && orec) {
+        // column a of L_pp, rows a .. NZ - 1
 #pragma unroll
         for (int k = 0; k < NZ; ++k)
-          if (k >= a) rec[R::OL + R::lcol(a) + k - a] = Lt[k * RS + a];
-        rec[R::OY + a] = y;
+          if (k >= a) orec[R::OL + R::lcol(a) + k - a] = Lt[tri(k, a)];
+        orec[R::OY + a] = y;
       }
     } else {
-      // L_tt L_tt^T = S and y_t = L_tt^-1 y, column by column: in round j lane j
-      // finishes its pivot and y_j and publishes its row; rows below take column j.
+      // L L^T = S and y_p = L^-1 y, column by column: in round j lane j finishes
+      // its pivot and y_j and publishes its row; rows below take column j.
 #pragma unroll
       for (int j = 0; j < NZ; ++j) {
         if (a == j) {
@@ -1117,9 +1152,9 @@ __global__ void __launch_bounds__(64)
           const T ljj = tsqrt(dd > T(0) ? dd : T(1));
           S[j] = ljj;
           y = y / ljj;
-          if (inw) {
+          if (inw && on) {
 #pragma unroll
-            for (int k = 0; k <= j; ++k) Lt[j * RS + k] = S[k];
+            for (int k = 0; k <= j; ++k) Lt[tri(j, k)] = S[k];
             Dt[j] = T(1) / ljj;
             Yt[j] = y;
           }
@@ -1128,78 +1163,207 @@ __global__ void __launch_bounds__(64)
         if (a > j) {
           T v = S[j];
 #pragma unroll
-          for (int k = 0; k < j; ++k) v -= S[k] * Lt[j * RS + k];
+          for (int k = 0; k < j; ++k) v -= S[k] * Lt[tri(j, k)];
           S[j] = v * Dt[j];
           y -= S[j] * Yt[j];
         }
       }
-      if (on) {
+      if (on && orec) {
 #pragma unroll
         for (int b = 0; b < NZ; ++b)
-          if (b <= a) rec[R::OL + R::lcol(b) + a - b] = S[b];  // row a of L_tt
-        rec[R::OY + a] = y;
+          if (b <= a) orec[R::OL + R::lcol(b) + a - b] = S[b];  // row a of L_pp
+        orec[R::OY + a] = y;
       }
     }
     __syncthreads();
+  };
+  // damped diagonal row: H + lambda max(diag, 1e-12) on the pivot
+  auto damp = [&](T* S) {
+#pragma unroll
+    for (int b = 0; b < NZ; ++b)
+      if (b == a) S[b] += lm * (S[b] > T(1e-12) ? S[b] : T(1e-12));
+  };
+  // FP32 inputs of the next step are loaded while the current one is factored
+  // (the chain is latency-bound)
+  constexpr bool PF = sizeof(T) == 4 && NZ <= 10;
+  T pH[NZ], pB[NZ], pC[NZ], pG = T(0);
+  if constexpr (PF) {
+    if (act && 0 < nfull) load_step(row_of(0), false, false, pH, pB, pC, pG);
   }
-  // backward: delta_t = L_tt^-T (y_t - L_{t+1,t}^T delta_{t+1} - L_{t+2,t}^T delta_{t+2})
-  T gd = T(0);
-  for (int t = ta.Tmax - 1; t >= 0; --t) {
-    const bool on = act && t < Tn;
-    T* rec = recs + (int64_t)t * R::SIZE;
-    const int s0 = t % 3, s1 = (t + 1) % 3, s2 = (t + 2) % 3;  // slots of t, t+1, t+2
-    T r = on ? rec[R::OY + a] : T(0);
-    // column a of L_{t+1,t} and of L_{t+2,t} (their rows are stored contiguously)
-    if (t + 1 < Tn && on) {
-      const T* q = rec + R::SIZE + R::OB + a;
-      const T* d1 = &sY[s1][g * RS];
+  // phase 1: full steps of both groups, positions 0 .. K1 - 1
+  for (int p = 0; p < K1; ++p) {
+    const bool on = act && p < nfull;
+    const int r = row_of(p);
+    T S[NZ], Bw[NZ], Cc[NZ], gv = T(0);
+    if constexpr (PF) {
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= q[b * NZ] * d1[b];
+      for (int k = 0; k < NZ; ++k) {
+        S[k] = pH[k];
+        Bw[k] = pB[k];
+        Cc[k] = pC[k];
+      }
+      gv = pG;
+      if (act && p + 1 < nfull) load_step(row_of(p + 1), p + 1 >= 1, p + 1 >= 2, pH, pB, pC, pG);
+    } else {
+      if (on) load_step(r, p >= 1, p >= 2, S, Bw, Cc, gv);
     }
-    if (t + 2 < Tn && on) {
-      const T* q = rec + 2 * R::SIZE + R::OC + a;
-      const T* d2 = &sY[s2][g * RS];
+    if (!on) {
 #pragma unroll
-      for (int b = 0; b < NZ; ++b) r -= q[b * NZ] * d2[b];
+      for (int b = 0; b < NZ; ++b) S[b] = T(b == a);
+    } else {
+      damp(S);
     }
-    // L_tt^T delta = r: column a of L_tt is L[k][a], k >= a
-    T Lc[NZ];
+    T y = on ? -gv : T(0);
+    T* rec = recs + (int64_t)r * R::SIZE;
+    T* oB = on && p >= 1 ? (half ? rec + R::SIZE : rec) + R::OB + a * NZ : nullptr;
+    step(on, p, p >= 1, p >= 2, false, true, S, y, Bw, Cc, oB, on ? rec : nullptr);
+  }
+  // phase 2: the bottom group's part of the middle's Schur complement: waypoint
+  // m + 1 (predecessors m + 2, m + 3), then m (predecessor m + 2 two back; the
+  // cross term with m + 1 is left in sB); results packed in the slots of
+  // positions nbot and nbot + 1
+  const bool mid = act && nbot > 0;
+  for (int q = 0; q < 2; ++q) {
+    const bool on = mid && half;
+    const int p = nbot + q, r = m + 1 - q;
+    T S[NZ], Bw[NZ], Cc[NZ], gv;
+#pragma unroll
+    for (int b = 0; b < NZ; ++b) S[b] = T(0);
     if (on) {
+      // couplings of waypoint m + 1 to m + 2 and m + 3, of waypoint m to m + 2 (the
+      // diagonal block and g of the waypoint are the top group's)
+      load_step(r, q == 0, q == 0 ? nbot >= 2 : true, S, Bw, Cc, gv);
 #pragma unroll
-      for (int k = 0; k < NZ; ++k) Lc[k] = k >= a ? rec[R::OL + R::lcol(a) + k - a] : T(0);
+      for (int b = 0; b < NZ; ++b) S[b] = T(0);
     } else {
 #pragma unroll
-      for (int k = 0; k < NZ; ++k) Lc[k] = T(k == a);
+      for (int b = 0; b < NZ; ++b) Bw[b] = Cc[b] = T(0);
     }
-    T d = T(0);
+    T y = T(0);
+    T* rec = recs + (int64_t)r * R::SIZE;
+    T* oB = on && q == 0 ? rec + R::SIZE + R::OB + a * NZ : nullptr;
+    step(on, p, q == 0, q == 0 ? nbot >= 2 : true, q == 1, false, S, y, Bw, Cc, oB, nullptr);
+  }
+  // phase 3: the top group factors waypoints m and m + 1 with the bottom group's
+  // downdates added (diagonal blocks, y, and the cross coupling H_{m+1,m})
+  for (int q = 0; q < 2; ++q) {
+    const bool on = mid && !half;
+    const int p = m + q, r = m + q;
+    T S[NZ], Bw[NZ], Cc[NZ], gv = T(0);
+    if (on) {
+      load_step(r, p >= 1, p >= 2, S, Bw, Cc, gv);
+      damp(S);
+      const int sp = (nbot + 1 - q) % 3;  // the bottom group's slot of this waypoint's downdates
+#pragma unroll
+      for (int b = 0; b < NZ; ++b)
+        if (b <= a) S[b] += sL[sp][pg * PS + tri(a, b)];
+      gv -= sY[sp][pg * RS + a];
+      if (q == 1) {
+        // H_{m+1,m} += (the bottom's downdate of H_{m,m+1})^T: column a of it
+#pragma unroll
+        for (int b = 0; b < NZ; ++b) Bw[b] += sB[pg * GS + b * RS + a];
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) {
+        S[b] = T(b == a);
+        Bw[b] = Cc[b] = T(0);
+      }
+    }
+    T y = on ? -gv : T(0);
+    T* rec = recs + (int64_t)r * R::SIZE;
+    T* oB = on && p >= 1 ? rec + R::OB + a * NZ : nullptr;
+    step(on, p, p >= 1, p >= 2, false, true, S, y, Bw, Cc, oB, on ? rec : nullptr);
+  }
+  // backward: top positions k = 0 .. ntop - 1 (waypoints ntop - 1 down to 0),
+  // bottom positions k - 2 (waypoints m + 2 upward); delta_t = L_tt^-T (y_t -
+  // the couplings' columns times the deltas already known)
+  const int K2 = Tm >= 4 ? (Tm - 1) / 2 + 2 : Tm;
+  T gd = T(0);
+  for (int k = 0; k < K2; ++k) {
+    const int q = half ? k - 2 : k;
+    const bool on = act && q >= 0 && q < (half ? nbot : ntop);
+    const int t = half ? ntop + q : ntop - 1 - q;
+    T* rec = recs + (int64_t)t * R::SIZE;
+    const int qq = q < 0 ? 0 : q;
+    const int s0 = qq % 3, s1 = (qq + 2) % 3, s2 = (qq + 1) % 3;  // slots of q, q-1, q-2
+    T r = on ? rec[R::OY + a] : T(0);
+    // column a of the coupling to the neighbour: top: L_{t+1,t} (record t+1, OB);
+    // bottom: its own record's OB (the coupling of t - 1 to t)
+    const bool h1 = half ? true : q >= 1, h2 = half ? true : q >= 2;
+    if (on && h1) {
+      const T* cq = (half ? rec : rec + R::SIZE) + R::OB + a;
+      const T* d1 = &sY[s1][gg * RS];
+#pragma unroll
+      for (int b = 0; b < NZ; ++b) r -= cq[b * NZ] * d1[b];
+    }
+    // column a and row a of L_tt (L[c][a], c >= a; L[a][b], b <= a)
+    T Lc[NZ], Lr[NZ];
+    if (on) {
+#pragma unroll
+      for (int c = 0; c < NZ; ++c) {
+        Lc[c] = c >= a ? rec[R::OL + R::lcol(a) + c - a] : T(0);
+        Lr[c] = c <= a ? rec[R::OL + R::lcol(c) + a - c] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NZ; ++c) Lc[c] = Lr[c] = T(c == a);
+    }
     T laa = T(1);  // this lane's pivot L[a][a], inverted once
 #pragma unroll
-    for (int q = 0; q < NZ; ++q)
-      if (q == a) laa = Lc[q];
+    for (int c = 0; c < NZ; ++c)
+      if (c == a) laa = Lc[c];
     const T ilaa = trcp(laa);
+    // the coupling two apart, L_{t',t}^T delta_{t'} = L_tt^-1 (H_{t',t}^T delta_{t'})
+    // with t' = t + 2 (top) or t - 2 (bottom): the segment blocks of record t + 2
+    // (top) or t (bottom), symmetric, times delta_{t'}, then a forward substitution
+    {
+      T u = T(0);
+      if (on && h2) {
+        const T* rc = half ? rec : rec + 2 * R::SIZE;
+        const T* d2 = &sY[s2][gg * RS];
+        u = rc[R::OCS + sa] * d2[a & ~1] + rc[R::OCS + sa + 1] * d2[a | 1];
+      }
+      T acc = T(0), v = T(0);
 #pragma unroll
-    for (int k = NZ - 1; k >= 0; --k) {
-      if (a == k) d = r * ilaa;
-      const T dk = __shfl(d, base + k, 64);
-      if (a < k) r -= Lc[k] * dk;
+      for (int c = 0; c < NZ; ++c) {
+        if (a == c) v = (u - acc) * ilaa;
+        const T vc = __shfl(v, base + c, 64);
+        if (a > c) acc += Lr[c] * vc;
+      }
+      r -= v;
+    }
+    // L_tt^T delta = r
+    T d = T(0);
+#pragma unroll
+    for (int c = NZ - 1; c >= 0; --c) {
+      if (a == c) d = r * ilaa;
+      const T dk = __shfl(d, base + c, 64);
+      if (a < c) r -= Lc[c] * dk;
     }
     __syncthreads();
-    if (inw) sY[s0][g * RS + a] = d;
+    if (inw && on) {
+      sY[s0][gg * RS + a] = d;
+      // the middle's deltas also seed the bottom group's backward chain, as its
+      // positions -1 (waypoint m + 1) and -2 (waypoint m)
+      if (!half && nbot > 0 && q < 2) sY[q == 0 ? 2 : 1][pg * RS + a] = d;
+    }
     if (on) {
       rec[R::OY + a] = d;
       gd += rec[R::OG + a] * d;
     }
     __syncthreads();
   }
-  // per-trajectory reductions over the NZ row lanes
+  // per-trajectory reductions over the 2 NZ lanes of both groups
   T gsum = T(0);
   int okall = 1;
+  const int tb = j2 * 2 * NZ;
 #pragma unroll
-  for (int k = 0; k < NZ; ++k) {
-    gsum += __shfl(gd, base + k, 64);
-    okall &= __shfl((int)ok, base + k, 64);
+  for (int k = 0; k < 2 * NZ; ++k) {
+    gsum += __shfl(gd, tb + k, 64);
+    okall &= __shfl((int)ok, tb + k, 64);
   }
-  if (act && a == 0) {
+  if (act && half == 0 && a == 0) {
     chol_ok[traj] = okall;
     gd_out[traj] = gsum;
   }
@@ -1682,7 +1846,7 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   // the launch is large enough to need several rounds of resident waves (small
   // launches, such as the FP64 refinement, keep one wave per trajectory)
   const int gb = ta.Tmax <= 32 && nt >= 4096 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
-  constexpr int G = 64 / (2 * NS);  // trajectories per k_traj_solve workgroup
+  constexpr int G = 64 / (4 * NS);  // trajectories per k_traj_solve workgroup (2 NZ lanes each)
   // the normal-equation kernel rewrites the same records from the same z, so the
   // autotuner may time its variants on the first iteration
   auto build = [&](int v) {
