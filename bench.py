@@ -472,7 +472,8 @@ def main():
             roofline["counter_frac"] = round(cf / (stage_avg[0] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)
         if traffic:
             roofline["hbm_frac"] = round(traffic / (stage_avg[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 6)
-    s2name = "k_ik_stage2<3,float,false>"
+    lanes = [l.split("lanes per candidate ")[1].split()[0] for l in (tuned or []) if "ik_stage2 n_seg 3" in l]
+    s2name = "k_ik_stage2_grp<3,float,%s>" % (lanes[0] if lanes else "2")
     if s2name in meas and meas[s2name].get("valu_f64_flops_per_launch"):
         f64 = meas[s2name]["valu_f64_flops_per_launch"]
         roofline["stage2_fp64"] = dict(kernel=s2name, counter_f64_flops_per_launch=f64, launch_ms=round(stage_avg[2], 4),
