@@ -1453,20 +1453,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 }
 
 // The line search with its step lengths tried at once, for horizons of at most
-// 32 waypoints and at most 4 trials: a workgroup of two waves holds one
-// trajectory and each half-wave evaluates one trial alpha = 2^-q (q = 0 .. 3),
-// one lane per waypoint; the accepted step is the first that passes in the
-// sequential order.  Each lane sums its own waypoint's clearance (segment-ball
-// culls, no shared work list).  The sequential kernel above spends a whole wave
-// per trial on such horizons, half of it idle outside the clearance sums, and
-// about 2.7 trials per iteration on the trajectory workload.
-template <int NS, typename T>
-__global__ void __launch_bounds__(128)
+// 64 waypoints and at most 4 trials: a workgroup of 4 TP lanes holds one
+// trajectory and each slice of TP lanes (a half-wave for horizons of at most 32,
+// else a wave) evaluates one trial alpha = 2^-q (q = 0 .. 3), one lane per
+// waypoint; the accepted step is the first that passes in the sequential order.
+// Each lane sums its own waypoint's clearance (segment-ball culls, no shared work
+// list).  The sequential kernel above spends a whole wave per trial, half of it
+// idle outside the clearance sums on short horizons, and about 2.7 trials per
+// iteration on the trajectory workload.
+template <int NS, typename T, int TP>
+__global__ void __launch_bounds__(4 * TP)
     k_traj_search4(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                    const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                    const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
                    int32_t* __restrict__ trials) {
-  constexpr int NZ = 2 * NS, NU = 3 * NS, TP = 32;
+  constexpr int NZ = 2 * NS, NU = 3 * NS;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_ok[4];
@@ -1991,9 +1992,9 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   // launches, such as the FP64 refinement, keep one wave per trajectory)
   const int gb = ta.Tmax <= 32 && nt >= 4096 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
   constexpr int G = 64 / (4 * NS);  // trajectories per k_traj_solve workgroup (2 NZ lanes each)
-  // horizons of at most 32 waypoints and at most 4 trials: the trials at once
-  const bool par_search = ta.Tmax <= 32 && lo.ls_max <= 4;
-  const size_t lds_4 = sizeof(T) * (size_t)(4 * Mmax + 4 * 32 * (3 * NS + 3));
+  // horizons of at most 64 waypoints and at most 4 trials: the trials at once
+  const bool par_search = ta.Tmax <= 64 && lo.ls_max <= 4;
+  const size_t lds_4 = sizeof(T) * (size_t)(4 * Mmax + 4 * (ta.Tmax <= 32 ? 32 : 64) * (3 * NS + 3));
   // the normal-equation kernel rewrites the same records from the same z, so the
   // autotuner may time its variants on the first iteration
   auto build = [&](int v) {
@@ -2026,9 +2027,12 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
     if (!done) build(vb);
     hipLaunchKernelGGL((k_traj_solve<NS, T>), dim3((unsigned)((nt + G - 1) / G)), dim3(64), 0, st, ta, nt, blk, lam,
                        failed, chol, gd);
-    if (par_search)
-      hipLaunchKernelGGL((k_traj_search4<NS, T>), dim3((unsigned)nt), dim3(128), lds_4, st, rb, w, ta, lo, Z, blk, lam,
-                         c0, gd, chol, failed, trials);
+    if (par_search && ta.Tmax <= 32)
+      hipLaunchKernelGGL((k_traj_search4<NS, T, 32>), dim3((unsigned)nt), dim3(128), lds_4, st, rb, w, ta, lo, Z, blk,
+                         lam, c0, gd, chol, failed, trials);
+    else if (par_search)
+      hipLaunchKernelGGL((k_traj_search4<NS, T, 64>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z, blk,
+                         lam, c0, gd, chol, failed, trials);
     else
       hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
                          lam, c0, gd, chol, failed, trials, cap);
