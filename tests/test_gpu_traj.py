@@ -103,6 +103,25 @@ def test_fp64_lm_iterates_match_oracle(oracle, cr, kind, k):
 
 
 @pytest.mark.parametrize("kind", ["path", "traj"])
+def test_fp64_lm_iterates_short_horizons(oracle, cr, kind):
+    """The block solve factors from both ends of a trajectory and meets in the
+    middle pair of waypoints; horizons of 1 to 7 waypoints cover the one-sided
+    case (fewer than 4), the smallest splits and odd and even lengths.  Two FP64
+    LM iterations with clearance and kinodynamic hinges equal the oracle's."""
+    for H in range(0 if kind == "path" else 1, 7):
+        print(f"traj fp64 short horizon kind={kind} H={H}", flush=True)
+        c = case(oracle, kind, 360 + H, n=3, H=H, P=2, S=1, M=2)
+        u, _, _ = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=2, k_final=0), "f64")
+        W = oracle.Weights(**c["W"])
+        for p in range(c["P"]):
+            pb = oracle_problem(oracle, c, p)
+            z0 = oracle.u_to_z(c["ro"], c["seeds"][p, 0]).ravel()
+            zk, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, 2)
+            uk = oracle.z_to_u(c["ro"], zk.reshape(H + 1, c["n"], 2))
+            assert np.abs(u[p] - uk).max() <= 1e-9 * c["b"], (H, p, np.abs(u[p] - uk).max())
+
+
+@pytest.mark.parametrize("kind", ["path", "traj"])
 @pytest.mark.parametrize("n", [3, 4, 5, 6])
 def test_fp32_lm_step_matches_oracle(oracle, cr, kind, n):
     """One FP32 LM iteration over whole trajectories (FP32 normal equations and
