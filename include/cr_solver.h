@@ -405,7 +405,7 @@ typedef struct {
   int64_t task_off, seed_off, sph_off, out_off;
 } cr_problem;
 
-enum { CR_BATCH_GRAPH = 1 }; /* cr_solve_batch flags */
+enum { CR_BATCH_GRAPH = 1, CR_BATCH_PERSISTENT = 2 }; /* cr_solve_batch flags */
 
 /* Solves an uneven batch of P problems (Algorithm 1 for each, the same stages as
  * cr_solve_ik / cr_solve_path / cr_solve_traj).  A native scheduler groups the
@@ -424,6 +424,11 @@ enum { CR_BATCH_GRAPH = 1 }; /* cr_solve_batch flags */
  * hipGraph, cached by the call's arguments (table contents, pointers, options)
  * and replayed on later identical calls.  The cache owns the graphs and their
  * pinned table copies until the process ends.
+ * flags & CR_BATCH_PERSISTENT: IK stage 1 of each group runs as one persistent
+ * kernel that takes 64-seed tiles of all its problems from a device queue and
+ * performs SelectTop inside the same launch, in the last workgroup to finish
+ * a problem's tiles (no separate selection launch).  Results are identical
+ * to the default launch sequence.
  * Errors: CR_EINVAL for a malformed table (kind, robot index, H, S, n_sph out of
  * range, negative offsets); array extents cannot be checked and are the
  * caller's responsibility.  Calls sharing a workspace must not overlap. */

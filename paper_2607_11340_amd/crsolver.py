@@ -542,6 +542,7 @@ def baseline_solve_traj(robot: Robot, u_start_goal: torch.Tensor, u_seed: torch.
 
 
 BATCH_GRAPH = 1
+BATCH_PERSISTENT = 2
 
 
 class Batch:
@@ -608,9 +609,10 @@ def batch_workspace_bytes(batch: "Batch", opts, dtype) -> int:
 
 
 def solve_batch(batch: "Batch", weights, opts, dtype=torch.float32, device="cuda", graph=False, workspace=None,
-                dev_arrays=None, out=None):
+                dev_arrays=None, out=None, persistent=False):
     """cr_solve_batch on a packed Batch.  weights, opts: 3 each, indexed by kind
-    (ik, path, traj).  Returns (u_out flat [device], err [2, P], status [P])."""
+    (ik, path, traj).  persistent: IK stage 1 as one work-queue kernel per group
+    with SelectTop fused in.  Returns (u_out flat [device], err [2, P], status [P])."""
     if dev_arrays is None:
         mk = lambda a: torch.tensor(a if a.size else [0.0], dtype=torch.float64, device=device)
         dev_arrays = (mk(batch.task), mk(batch.seed), mk(batch.sph))
@@ -628,7 +630,8 @@ def solve_batch(batch: "Batch", weights, opts, dtype=torch.float32, device="cuda
         ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
     _check(lib.cr_solve_batch(rob, len(batch.robots), batch.table, batch.P, _ptr(task), _ptr(seed), _ptr(sph), wc, oc,
                               _ptr(u), _ptr(err), _ptr(st), ws_ptr, ws_bytes, _dt(dtype),
-                              BATCH_GRAPH if graph else 0, _stream(task)))
+                              (BATCH_GRAPH if graph else 0) | (BATCH_PERSISTENT if persistent else 0),
+                              _stream(task)))
     return u, err, st
 
 

@@ -30,6 +30,7 @@ struct Group {
   int64_t P, B;               // problems; IK seeds (B) or trajectories
   TrajShape sh;
   int Smax;
+  int64_t tiles;  // IK: work items of the persistent stage 1 (seed tiles)
   size_t ws_off, ws_bytes;
 };
 
@@ -119,12 +120,15 @@ cr_status make_plan(const cr_robot* robots, const cr_problem* probs, int64_t P, 
     if (g.kind == CR_KIND_IK) {
       std::vector<IkProb> tab(g.P);
       int64_t seed0 = 0;
+      g.tiles = 0;
       for (int64_t k = 0; k < g.P; ++k) {
         const cr_problem& p = probs[g.rows[k]];
         IkProb r{};
         r.S = p.S;
         r.M = p.n_sph;
         r.idx = (int32_t)g.rows[k];
+        r.pad = (int32_t)g.tiles;  // first seed tile of the problem (persistent stage 1)
+        g.tiles += (p.S + 63) / 64;
         r.seed0 = seed0;
         r.task = p.task_off;
         r.task_ld = 1;
@@ -256,7 +260,7 @@ cr_status pinned_copy(const Plan& plan, Pinned* pb) {
 
 cr_status enqueue(const cr_robot* robots, const Plan& plan, const void* pinned, const void* task, const void* u_seed,
                   const void* sph, const cr_weights* weights, const cr_opts* opts, void* u_out, void* err_out,
-                  int32_t* status_out, int64_t P, char* ws, cr_dtype dtype, hipStream_t stream) {
+                  int32_t* status_out, int64_t P, char* ws, cr_dtype dtype, bool persistent, hipStream_t stream) {
   std::vector<hipStream_t> side;
   cr_status rc = side_streams(&side);
   if (rc != CR_OK) return rc;
@@ -284,7 +288,7 @@ cr_status enqueue(const cr_robot* robots, const Plan& plan, const void* pinned, 
       if (rc == CR_OK)
         rc = launch_ik_group(rb, g.P, g.B, g.Smax, tp, (const double*)task, (const double*)u_seed,
                              (const double*)sph, weights[g.kind], opts[g.kind], (double*)u_out, (double*)err_out, P,
-                             status_out, gws, dtype, s);
+                             status_out, gws, dtype, persistent, g.tiles, s);
     } else {
       TrajProb* tp = traj_table_slot(rb, g.sh, opts[g.kind], dtype, gws);
       rc = check_hip(hipMemcpyAsync(tp, src, sizeof(TrajProb) * g.P, hipMemcpyHostToDevice, s), "table upload");
@@ -321,7 +325,7 @@ std::map<std::string, GraphEntry> g_graphs;
 std::string graph_key(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P, const void* task,
                       const void* u_seed, const void* sph, const cr_weights* weights, const cr_opts* opts,
                       const void* u_out, const void* err_out, const void* status_out, const void* ws, size_t ws_bytes,
-                      cr_dtype dtype, hipStream_t stream) {
+                      cr_dtype dtype, int32_t flags, hipStream_t stream) {
   std::string k;
   auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
   int dev = 0;
@@ -337,6 +341,7 @@ std::string graph_key(const cr_robot* robots, int32_t n_robots, const cr_problem
   put(weights, sizeof(cr_weights) * 3);
   put(opts, sizeof(cr_opts) * 3);
   put(&dtype, sizeof dtype);
+  put(&flags, sizeof flags);
   return k;
 }
 
@@ -364,11 +369,12 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
   for (int64_t i = 0; i < P; ++i)
     if (probs[i].n_sph > 0 && !sph) return fail(CR_EINVAL, "problem %lld has spheres but sph is NULL", (long long)i);
   const bool graph = (flags & CR_BATCH_GRAPH) != 0;
+  const bool persistent = (flags & CR_BATCH_PERSISTENT) != 0;
   if (graph && !ws) return fail(CR_EINVAL, "CR_BATCH_GRAPH needs a caller workspace");
   std::lock_guard<std::mutex> lk(g_call_mu);
   if (graph) {
     const std::string key = graph_key(robots, n_robots, probs, P, task, u_seed, sph, weights, opts, u_out, err_out,
-                                      status_out, ws, ws_bytes, dtype, stream);
+                                      status_out, ws, ws_bytes, dtype, flags, stream);
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) return check_hip(hipGraphLaunch(it->second.exec, stream), "hipGraphLaunch");
   }
@@ -393,7 +399,7 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
     rc = check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (rc != CR_OK) return rc;
     cr_status rc_enq = enqueue(robots, plan, e.pinned.ptr, task, u_seed, sph, weights, opts, u_out, err_out,
-                               status_out, P, (char*)mem, dtype, cap);
+                               status_out, P, (char*)mem, dtype, persistent, cap);
     hipGraph_t gr = nullptr;
     rc = check_hip(hipStreamEndCapture(cap, &gr), "hipStreamEndCapture");
     if (rc_enq != CR_OK) rc = rc_enq;
@@ -401,7 +407,7 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
     if (gr) (void)hipGraphDestroy(gr);
     if (rc != CR_OK) return rc;
     const std::string key = graph_key(robots, n_robots, probs, P, task, u_seed, sph, weights, opts, u_out, err_out,
-                                      status_out, ws, ws_bytes, dtype, stream);
+                                      status_out, ws, ws_bytes, dtype, flags, stream);
     auto ins = g_graphs.emplace(key, e).first;
     return check_hip(hipGraphLaunch(ins->second.exec, stream), "hipGraphLaunch");
   }
@@ -416,7 +422,7 @@ cr_status solve_batch(const cr_robot* robots, int32_t n_robots, const cr_problem
   }
   if ((rc = pinned_copy(plan, &pb)) != CR_OK) return rc;
   rc = enqueue(robots, plan, pb.ptr, task, u_seed, sph, weights, opts, u_out, err_out, status_out, P, (char*)mem,
-               dtype, stream);
+               dtype, persistent, stream);
   cr_status r2 = check_hip(hipEventRecord(pb.done, stream), "hipEventRecord");
   if (rc == CR_OK) rc = r2;
   if (!ws) {

@@ -104,12 +104,14 @@ static inline size_t select_lds(int Spad, int stage_pen, int stage_nz, size_t tb
 // Candidate c of problem p, coordinate m is z[m * zs_m + (p * S + c) * zc] and
 // its keys sit at p * S + c; with rows != NULL problem p has its own candidate
 // count, key base and z layout (ragged batches, trajectories).
+// SelectTop of problem p by the calling workgroup (any multiple of 64 lanes; its
+// first wave takes the decisions); row: that problem's own candidate layout, or
+// NULL for the uniform one.  smem: select_lds() bytes.
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_select(int64_t P, int S0, int Spad0, int nz0, int stage_pen, int stage_nz, const T* __restrict__ z, int64_t zs_m,
-             int64_t zs_c, const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed,
-             int n_final, T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ void select_top_one(int64_t P, int64_t p, int S0, int Spad0, int nz0, int stage_pen, int stage_nz,
+                               const T* __restrict__ z, int64_t zs_m, int64_t zs_c, const T* __restrict__ e,
+                               const T* __restrict__ pen, const int32_t* __restrict__ failed, int n_final, T dup_eps,
+                               const SelRow* row, int32_t* __restrict__ idx_out, unsigned char* smem) {
   T* se = reinterpret_cast<T*>(smem);
   T* spen = se + Spad0;  // penalties for the duplicate rule, when staged
   int* sf = reinterpret_cast<int*>(stage_pen ? spen + Spad0 : spen);
@@ -117,11 +119,10 @@ __global__ void __launch_bounds__(256)
   int* kept = reinterpret_cast<int*>(
       smem + ((((size_t)Spad0 * ((stage_pen ? 2 : 1) * sizeof(T) + 4) + Spad0) + 7) & ~(size_t)7));
   T* sz = reinterpret_cast<T*>(kept + 64);
-  const int64_t p = blockIdx.x;
   int S = S0, nz = nz0, Spad = Spad0;
   int64_t kb = p * S0, zb = p * S0 * zs_c, zc = zs_c;
-  if (rows) {
-    const SelRow r = rows[p];
+  if (row) {
+    const SelRow r = *row;
     S = r.S;
     nz = r.nz;
     kb = r.kbase;
@@ -290,6 +291,17 @@ __global__ void __launch_bounds__(256)
   if (lane < n_final) idx_out[(int64_t)lane * P + p] = lane < nk ? kept[lane] : -1;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_select(int64_t P, int S0, int Spad0, int nz0, int stage_pen, int stage_nz, const T* __restrict__ z, int64_t zs_m,
+             int64_t zs_c, const T* __restrict__ e, const T* __restrict__ pen, const int32_t* __restrict__ failed,
+             int n_final, T dup_eps, const SelRow* __restrict__ rows, int32_t* __restrict__ idx_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t p = blockIdx.x;
+  select_top_one<T>(P, p, S0, Spad0, nz0, stage_pen, stage_nz, z, zs_m, zs_c, e, pen, failed, n_final, dup_eps,
+                    rows ? rows + p : nullptr, idx_out, smem);
+}
+
 // Stage 2 for robots without clearance rows, G lanes per kept candidate (G = 1, 2
 // or 4).  One lane per candidate leaves SIMDs idle when the candidates are few
 // (32,768 candidates are 512 waves for 1024 SIMDs), and a wave with half its lanes
@@ -408,17 +420,15 @@ __device__ __forceinline__ int64_t ik_find(const IkProb* tp, int64_t P, int64_t 
   return lo;
 }
 
-template <int NS, typename T, int OCC = 1>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
-    k_ik_stage1_rag(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
-                    const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
-                    int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
-                    T* __restrict__ cost_out, int32_t* __restrict__ failed_out) {
+// Stage 1 of seed s of problem pr (the seed at b in the launch's stage-1 arrays).
+template <int NS, typename T>
+__device__ __forceinline__ void ik_rag_seed(const RobotT<T>& rb, const WeightsT<T>& w, const LMOpts<T>& o,
+                                            const IkProb& pr, int64_t b, int64_t s, int64_t B,
+                                            const double* __restrict__ task, const double* __restrict__ useed,
+                                            const double* __restrict__ sph, int iters, T lam0, T* __restrict__ z_out,
+                                            T* __restrict__ e_out, T* __restrict__ pen_out, T* __restrict__ cost_out,
+                                            int32_t* __restrict__ failed_out) {
   constexpr int NZ = 2 * NS;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const IkProb pr = tp[ik_find(tp, P, b)];
-  const int64_t s = b - pr.seed0;
   T tt[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) tt[c] = (T)task[pr.task + c * pr.task_ld];
@@ -451,6 +461,80 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
   pen_out[b] = pen;
   cost_out[b] = c;
   failed_out[b] = failed ? 1 : 0;
+}
+
+template <int NS, typename T, int OCC = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
+    k_ik_stage1_rag(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
+                    const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
+                    int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
+                    T* __restrict__ cost_out, int32_t* __restrict__ failed_out) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const IkProb pr = tp[ik_find(tp, P, b)];
+  ik_rag_seed<NS, T>(rb, w, o, pr, b, b - pr.seed0, B, task, useed, sph, iters, lam0, z_out, e_out, pen_out, cost_out,
+                     failed_out);
+}
+
+// Persistent stage 1 of a ragged IK group over a work queue.  The items are tiles
+// of kIkTile consecutive seeds of one problem, in the table's order (problems
+// longest first, their tiles in seed order; tile0 of problem q in its table row's
+// `pad`).  Each one-wave workgroup takes items from an atomic counter until the
+// queue is empty, runs stage 1 on the tile's seeds (one lane per seed, the same
+// per-seed code as k_ik_stage1_rag, so the same results), and counts the tile
+// done for its problem; the wave that finishes a problem's last tile then runs
+// that problem's SelectTop (n_final > 0).  No wave waits for another: the last
+// arrival does the problem's remaining work, so every wave reaches the exit.
+// q[0]: the queue head, q[1 + k]: tiles done of problem k (all zero on entry).
+constexpr int kIkTile = 64;
+
+template <int NS, typename T, int OCC = 1>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC)))
+    k_ik_stage1_q(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
+                  const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
+                  int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
+                  T* __restrict__ cost_out, int32_t* __restrict__ failed_out, int32_t* __restrict__ q, int n_final,
+                  int Spad, int stage_pen, int stage_nz, T dup_eps, int32_t* __restrict__ sel) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  const IkProb last = tp[P - 1];
+  const int n_tiles = last.pad + (last.S + kIkTile - 1) / kIkTile;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&q[0], 1);
+    item = __shfl(item, 0, 64);
+    if (item >= n_tiles) break;
+    // the problem of the tile: the last row whose first tile is <= item
+    int64_t lo = 0, hi = P - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (tp[mid].pad <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const IkProb pr = tp[lo];
+    const int64_t s = (int64_t)(item - pr.pad) * kIkTile + lane;
+    if (s < pr.S)
+      ik_rag_seed<NS, T>(rb, w, o, pr, pr.seed0 + s, s, B, task, useed, sph, iters, lam0, z_out, e_out, pen_out,
+                         cost_out, failed_out);
+    if (n_final <= 0) continue;
+    // publish this tile's results, then count it; the last tile's wave sees every
+    // other tile's results after its own fence
+    __threadfence();
+    int done = 0;
+    if (lane == 0) done = atomicAdd(&q[1 + lo], 1) + 1;
+    done = __shfl(done, 0, 64);
+    if (done != (pr.S + kIkTile - 1) / kIkTile) continue;
+    __threadfence();
+    SelRow row;
+    row.S = pr.S;
+    row.nz = 2 * NS;
+    row.kbase = pr.seed0;
+    row.zbase = pr.seed0;
+    row.zsc = 1;
+    select_top_one<T>(P, lo, pr.S, Spad, 2 * NS, stage_pen, stage_nz, z_out, B, 1, e_out, pen_out, failed_out, n_final,
+                      dup_eps, &row, sel, smem);
+    __syncthreads();  // the LDS of the selection is reused by the next problem
+  }
 }
 
 __global__ void k_ik_selrows(int64_t P, int nz, const IkProb* __restrict__ tp, SelRow* __restrict__ rows) {
@@ -760,18 +844,32 @@ cr_status launch_solve_ik(const cr_robot& rb, const cr_spheres* sp, int64_t P, c
 #undef CR_IK_CASE
 }
 
+// LDS plan of SelectTop for candidate counts up to S of nz coordinates: the
+// padded count, whether penalties and coordinates are staged, and the bytes.
+struct SelPlan {
+  int Spad, stage_pen, stage_nz;
+  size_t lds;
+};
+
+static SelPlan select_plan(int32_t S, int32_t nz, size_t tb) {
+  SelPlan sp;
+  sp.Spad = 1;
+  while (sp.Spad < S) sp.Spad <<= 1;
+  // stage the coordinates when every problem's fit in 32 KiB (nz == 0: per-row
+  // counts unknown here, read from z)
+  sp.stage_pen = select_lds(sp.Spad, 1, 0, tb) <= 64 * 1024 ? 1 : 0;
+  sp.stage_nz = nz > 0 && (size_t)sp.Spad * nz * tb <= 32 * 1024 ? nz : 0;
+  if (select_lds(sp.Spad, sp.stage_pen, sp.stage_nz, tb) > 64 * 1024) sp.stage_nz = 0;
+  sp.lds = select_lds(sp.Spad, sp.stage_pen, sp.stage_nz, tb);
+  return sp;
+}
+
 cr_status launch_select_strided(int64_t P, int32_t S, int32_t nz, const void* z, int64_t zs_m, int64_t zs_c,
                                 const void* e, const void* pen, const int32_t* failed, int32_t n_final, double dup_eps,
                                 int32_t* idx_out, cr_dtype dtype, hipStream_t st, const SelRow* rows) {
-  int Spad = 1;
-  while (Spad < S) Spad <<= 1;
-  const size_t tb = dtype == CR_F64 ? 8 : 4;
-  // stage the coordinates when every problem's fit in 32 KiB (nz == 0: per-row
-  // counts unknown here, read from z)
-  const int stage_pen = select_lds(Spad, 1, 0, tb) <= 64 * 1024 ? 1 : 0;
-  int stage_nz = nz > 0 && (size_t)Spad * nz * tb <= 32 * 1024 ? nz : 0;
-  if (select_lds(Spad, stage_pen, stage_nz, tb) > 64 * 1024) stage_nz = 0;
-  const size_t lds = select_lds(Spad, stage_pen, stage_nz, tb);
+  const SelPlan sp = select_plan(S, nz, dtype == CR_F64 ? 8 : 4);
+  const int Spad = sp.Spad, stage_pen = sp.stage_pen, stage_nz = sp.stage_nz;
+  const size_t lds = sp.lds;
   if (P == 0) return CR_OK;
   if (dtype == CR_F64)
     hipLaunchKernelGGL((k_select<double>), dim3((unsigned)P), dim3(256), lds, st, P, (int)S, Spad, (int)nz, stage_pen,
@@ -797,6 +895,7 @@ struct IkGroupWs {
   int32_t* failed2;
   IkProb* tp;
   SelRow* rows;
+  int32_t* queue;  // persistent stage 1: queue head and tiles done per problem
 };
 
 static size_t ik_group_layout(int ns, int64_t P, int64_t B, int nf, cr_dtype dtype, char* base, IkGroupWs* w) {
@@ -821,6 +920,7 @@ static size_t ik_group_layout(int ns, int64_t P, int64_t B, int nf, cr_dtype dty
   x.failed2 = (int32_t*)take(4 * n2);
   x.tp = (IkProb*)take(sizeof(IkProb) * P);
   x.rows = (SelRow*)take(sizeof(SelRow) * P);
+  x.queue = (int32_t*)take(4 * (P + 1));
   if (w) *w = x;
   return off;
 }
@@ -835,21 +935,39 @@ IkProb* ik_table_slot(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o
   return w.tp;
 }
 
+__global__ void k_zero_i32(int64_t n, int32_t* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
 template <int NS, typename T>
 static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Smax, const IkProb* tp,
                               const double* task, const double* useed, const double* sph, const cr_weights& w0,
                               const cr_opts& o, double* u_out, double* err_out, int64_t err_ld, int32_t* status_out,
-                              const IkGroupWs& ws, hipStream_t st) {
+                              const IkGroupWs& ws, bool persistent, int64_t n_tiles, hipStream_t st) {
   RobotT<T> rb = robot_to<T>(rb0);
   WeightsT<T> w = weights_to<T>(w0);
   LMOpts<T> lo{o.ls_max, (T)o.lambda_min, (T)o.lambda_max};
   RobotT<double> rbd = robot_to<double>(rb0);
+  const SelPlan sp = select_plan(Smax, 2 * NS, sizeof(T));
+  // persistent: enough one-wave workgroups to fill the chip several times over,
+  // at most one per tile
+  const unsigned qgrid = (unsigned)(n_tiles < 8192 ? n_tiles : 8192);
   auto launch = [&](int v) {
     const int occ = tune_occ(TK_IK_STAGE1_RAG, v);
-#define CR_S1R(O)                                                                                                 \
-  hipLaunchKernelGGL((k_ik_stage1_rag<NS, T, O>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B, tp, \
-                     task, useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,    \
-                     ws.failed1)
+#define CR_S1R(O)                                                                                                   \
+  do {                                                                                                              \
+    if (persistent) {                                                                                               \
+      hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(P + 1, 256)), dim3(256), 0, st, P + 1, ws.queue);             \
+      hipLaunchKernelGGL((k_ik_stage1_q<NS, T, O>), dim3(qgrid), dim3(64), sp.lds, st, rb, w, lo, P, B, tp, task,  \
+                         useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,     \
+                         ws.failed1, ws.queue, o.n_final, sp.Spad, sp.stage_pen, sp.stage_nz, (T)o.dup_eps, ws.sel); \
+    } else {                                                                                                        \
+      hipLaunchKernelGGL((k_ik_stage1_rag<NS, T, O>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B,  \
+                         tp, task, useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1,          \
+                         (T*)ws.cost1, ws.failed1);                                                                 \
+    }                                                                                                               \
+  } while (0)
     if constexpr (sizeof(T) == 4) {
       if (occ == tune_occ(TK_IK_STAGE1_RAG, 1)) CR_S1R(tune_occ(TK_IK_STAGE1_RAG, 1));
       else if (occ == tune_occ(TK_IK_STAGE1_RAG, 2)) CR_S1R(tune_occ(TK_IK_STAGE1_RAG, 2));
@@ -862,7 +980,7 @@ static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Sma
   int v = 0;
   bool done = false;
   if (sizeof(T) == 4) {
-    cr_status rt = tune_choose(TK_IK_STAGE1_RAG, NS, CR_F32, B, st, launch, &v, &done);
+    cr_status rt = tune_choose(persistent ? TK_IK_STAGE1_Q : TK_IK_STAGE1_RAG, NS, CR_F32, B, st, launch, &v, &done);
     if (rt != CR_OK) return rt;
   }
   if (!done) launch(v);
@@ -870,10 +988,12 @@ static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Sma
   if (rc != CR_OK) return rc;
   if (o.n_final > 0) {
     const int nf = o.n_final;
-    hipLaunchKernelGGL(k_ik_selrows, dim3(blocks_for(P, 256)), dim3(256), 0, st, P, 2 * NS, tp, ws.rows);
-    rc = launch_select_strided(P, Smax, 2 * NS, ws.z1, B, 1, ws.e1, ws.pen1, ws.failed1, nf, o.dup_eps, ws.sel,
-                               sizeof(T) == 8 ? CR_F64 : CR_F32, st, ws.rows);
-    if (rc != CR_OK) return rc;
+    if (!persistent) {  // the persistent kernel has already selected
+      hipLaunchKernelGGL(k_ik_selrows, dim3(blocks_for(P, 256)), dim3(256), 0, st, P, 2 * NS, tp, ws.rows);
+      rc = launch_select_strided(P, Smax, 2 * NS, ws.z1, B, 1, ws.e1, ws.pen1, ws.failed1, nf, o.dup_eps, ws.sel,
+                                 sizeof(T) == 8 ? CR_F64 : CR_F32, st, ws.rows);
+      if (rc != CR_OK) return rc;
+    }
     WeightsT<double> wd = weights_to<double>(w0);
     LMOpts<double> lod{o.ls_max, o.lambda_min, o.lambda_max};
     const int64_t B2 = P * (int64_t)nf;
@@ -892,15 +1012,16 @@ static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Sma
 cr_status launch_ik_group(const cr_robot& rb, int64_t P, int64_t B, int Smax, const IkProb* tp, const double* task,
                           const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
                           double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
-                          cr_dtype dtype, hipStream_t st) {
+                          cr_dtype dtype, bool persistent, int64_t n_tiles, hipStream_t st) {
   IkGroupWs ws;
   ik_group_layout(rb.n_seg, P, B, o.n_final, dtype, (char*)wsmem, &ws);
+  if (persistent && select_plan(Smax, 2 * rb.n_seg, dtype == CR_F64 ? 8 : 4).lds > 64 * 1024) persistent = false;
 #define CR_IKG_CASE(N)                                                                                         \
   case N:                                                                                                      \
     return dtype == CR_F64 ? run_ik_group<N, double>(rb, P, B, Smax, tp, task, useed, sph, w, o, u_out, err_out, \
-                                                     err_ld, status_out, ws, st)                               \
+                                                     err_ld, status_out, ws, persistent, n_tiles, st)          \
                            : run_ik_group<N, float>(rb, P, B, Smax, tp, task, useed, sph, w, o, u_out, err_out,  \
-                                                    err_ld, status_out, ws, st);
+                                                    err_ld, status_out, ws, persistent, n_tiles, st);
   switch (rb.n_seg) {
     CR_IKG_CASE(1)
     CR_IKG_CASE(2)

@@ -54,7 +54,14 @@ cr_status check_hip(hipError_t e, const char* what);
 // The FP64 IK stage 2 is tuned over its lanes per kept candidate instead (1, 2 or
 // 4; every width takes the same decisions, so its outputs do not depend on the
 // variant); untuned, it takes the width that gives every SIMD one wave.
-enum TuneKernel { TK_IK_STAGE1 = 0, TK_IK_STAGE1_RAG = 1, TK_TRAJ_BUILD = 2, TK_IK_STAGE2 = 3, TK_COUNT = 4 };
+enum TuneKernel {
+  TK_IK_STAGE1 = 0,
+  TK_IK_STAGE1_RAG = 1,
+  TK_TRAJ_BUILD = 2,
+  TK_IK_STAGE2 = 3,
+  TK_IK_STAGE1_Q = 4,  // the persistent stage 1 of ragged IK groups (occupancy targets as TK_IK_STAGE1_RAG)
+  TK_COUNT = 5
+};
 constexpr int TUNE_NV = 3;      // variants per kernel
 constexpr int TUNE_ROUNDS = 3;  // timings per variant
 // parameter of variant v of kernel k: the occupancy target (1 = the compiler's
@@ -179,7 +186,7 @@ IkProb* ik_table_slot(const cr_robot& rb, int64_t P, int64_t B, const cr_opts& o
 cr_status launch_ik_group(const cr_robot& rb, int64_t P, int64_t B, int Smax, const IkProb* tp, const double* task,
                           const double* useed, const double* sph, const cr_weights& w, const cr_opts& o,
                           double* u_out, double* err_out, int64_t err_ld, int32_t* status_out, void* wsmem,
-                          cr_dtype dtype, hipStream_t st);
+                          cr_dtype dtype, bool persistent, int64_t n_tiles, hipStream_t st);
 
 size_t batch_workspace_bytes(const cr_robot* robots, int32_t n_robots, const cr_problem* probs, int64_t P,
                              const cr_opts* opts, cr_dtype dtype);

@@ -42,6 +42,7 @@ const char* kernel_name(int k) {
     case TK_IK_STAGE1_RAG: return "ik_stage1_ragged";
     case TK_TRAJ_BUILD: return "traj_build";
     case TK_IK_STAGE2: return "ik_stage2";
+    case TK_IK_STAGE1_Q: return "ik_stage1_persistent";
   }
   return "?";
 }

@@ -168,3 +168,52 @@ def test_batch_graph_replays_equal_eager(oracle, cr):
         assert float(junk) == float(junk)
         for a, b in zip(out, ref):
             assert torch.equal(a, b), rep
+
+
+def ik_tile_problems(oracle, seed):
+    """IK problems whose seed counts straddle the 64-seed tiles of the persistent
+    stage 1 (one seed, 63, 64, 65, several tiles with a ragged tail)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(0, 1, 0), (1, 63, 3), (2, 64, 0), (1, 65, 0), (0, 200, 2), (2, 130, 4), (1, 7, 0), (0, 128, 0),
+              (2, 300, 0), (1, 2, 1)]
+    out = []
+    for r, S, M in shapes:
+        L, rr, b = GEOMS[r]
+        n = len(L)
+        rb = oracle.Robot(L=L, r=rr, u_max=[b] * n, pts_per_seg=4)
+        ut = I.uniform_actuation(rng, n, b, 1)[0]
+        seeds = I.uniform_actuation(rng, n, b, S).reshape(S, 1, n, 3)
+        sph = near_spheres(rng, oracle, rb, seeds[0], M, 4) if M else None
+        out.append(dict(kind="ik", robot=r, H=0, task=oracle.fk(rb, ut)[1][-1], seeds=seeds, spheres=sph, rb=rb, b=b))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_batch_persistent_equals_default(oracle, cr, dtype):
+    """The persistent IK stage 1 (work queue of seed tiles, SelectTop by the last
+    tile's workgroup) gives the default launch sequence's results bit for bit,
+    eagerly and replayed from a graph, with more kept candidates than some
+    problems have seeds."""
+    print("batch persistent vs default", dtype, flush=True)
+    dt = getattr(torch, dtype)
+    _, rg = robots(oracle, cr)
+    probs = ik_tile_problems(oracle, 503) + mixed_problems(oracle, 504)
+    batch = cr.Batch(rg, probs)
+    opts = [cr.Opts(n_final=4, k_init=12, k_final=4)] * 3
+    W = weights3(cr)
+    ref = [x.clone() for x in cr.solve_batch(batch, W, opts, dtype=dt)]
+    got = [x.clone() for x in cr.solve_batch(batch, W, opts, dtype=dt, persistent=True)]
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    ws = torch.empty(cr.batch_workspace_bytes(batch, opts, dt), dtype=torch.uint8, device="cuda")
+    dev = tuple(torch.tensor(a if a.size else [0.0], dtype=torch.float64, device="cuda")
+                for a in (batch.task, batch.seed, batch.sph))
+    out = tuple(torch.empty_like(x) for x in ref)
+    for rep in range(2):
+        for x in out:
+            x.zero_()
+        cr.solve_batch(batch, W, opts, dtype=dt, workspace=ws, dev_arrays=dev, graph=True, out=out, persistent=True)
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), rep
