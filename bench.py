@@ -57,6 +57,8 @@ def parse():
                     help="targets timed with the plain per-problem FP32 solve (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device copy of this many bytes (HBM counter calibration)")
+    ap.add_argument("--no-persistent-compare", dest="persistent_compare", action="store_false",
+                    help="uneven batch: skip timing the persistent IK stage 1 beside the default launches")
     ap.add_argument("--calib", action="store_true",
                     help="time the vector-ALU calibration loops (known instruction counts) and exit")
     return ap.parse_args()
@@ -1054,7 +1056,7 @@ def run_uneven(args, cr, I, torch, steps, warmup, extras):
     # IK stage 1 as one persistent work-queue kernel per group (SelectTop fused),
     # timed beside the default grid launches; same results bit for bit
     alt = {}
-    for pers in (True, False):
+    for pers in ((True, False) if args.persistent_compare else (False,)):
         # tuned eagerly: the graph captured by the first warm-up step then holds the chosen variants
         tuned = autotune(args, cr, torch, lambda: step(graph=False, persistent=pers))
         for _ in range(warmup):
@@ -1066,7 +1068,8 @@ def run_uneven(args, cr, I, torch, steps, warmup, extras):
         if pers:
             res_p = [x.clone() for x in out]
             alt = dict(ms_per_step=round(ms, 3), value=round(P / (ms * 1e-3), 2), autotune=tuned)
-    alt["identical_results"] = all(bool(torch.equal(a, b)) for a, b in zip(res_p, out))
+    if alt:
+        alt["identical_results"] = all(bool(torch.equal(a, b)) for a, b in zip(res_p, out))
     st = out[2].cpu().numpy()
     kinds = np.array([("ik", "path", "traj").index(p["kind"]) for p in probs])
     succ = {k: round(float((st[kinds == i] == cr.SOLVED).mean()), 4) for i, k in enumerate(("ik", "path", "traj"))}
@@ -1080,7 +1083,7 @@ def run_uneven(args, cr, I, torch, steps, warmup, extras):
                             segments="U{1..6}", horizons="U{1..64}", seeds="U{16..512}", spheres="U{0..64}",
                             spheres_kept=n_sph, seeds_total=int(sum(p["S"] for p in probs)), graph=True),
                 success_rate=round(float((st == cr.SOLVED).mean()), 4), success_by_kind=succ, autotune=tuned,
-                ik_stage1_persistent=alt)
+                ik_stage1_persistent=alt or None)
     line.update(counter_roofline("uneven_batch", ms))
     if extras:
         print("bench: timing the plain per-problem baseline on a per-kind sample", file=sys.stderr, flush=True)
