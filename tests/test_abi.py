@@ -181,3 +181,19 @@ def test_prm_rejects_bad_arguments_on_host(cr):
                           fake, fake, None, None) == cr.CR_EINVAL
     assert L.cr_prm_query(C.byref(rb), C.byref(sp), 4, C.byref(o), None, None, None, None, None, fake, 8, 4, None, 2,
                           fake, fake, None, None) == cr.CR_EINVAL
+
+
+def header_constants():
+    src = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    return {k: int(v) for k, v in re.findall(r"\b(CR_[A-Z_0-9]+)\s*=\s*(\d+)", src)}
+
+
+def test_binding_constants_match_the_header(cr):
+    """The binding's enum values and flag bits are the header's."""
+    h = header_constants()
+    assert (cr.F32, cr.F64) == (h["CR_F32"], h["CR_F64"])
+    assert cr.KIND == {"ik": h["CR_KIND_IK"], "path": h["CR_KIND_PATH"], "traj": h["CR_KIND_TRAJ"]}
+    assert (cr.SOLVED, cr.LIMIT_VIOLATION, cr.COLLISION, cr.NONFINITE, cr.NOT_CONVERGED) == (
+        h["CR_SOLVED"], h["CR_LIMIT_VIOLATION"], h["CR_COLLISION"], h["CR_NONFINITE"], h["CR_NOT_CONVERGED"])
+    assert (cr.BATCH_GRAPH, cr.BATCH_PERSISTENT) == (h["CR_BATCH_GRAPH"], h["CR_BATCH_PERSISTENT"])
+    assert cr.BATCH_GRAPH & cr.BATCH_PERSISTENT == 0
