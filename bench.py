@@ -884,7 +884,7 @@ def sub_workload(name, args, cr, I, torch):
         ln = run_trajectories(name, args, cr, I, torch, args.sub_steps, 1, False)
     keep = ("value", "unit", "ms_per_step", "ms_per_step_mean", "steps", "success_rate", "success_by_kind",
             "status_counts", "config", "counter_roofline", "autotune", "initializer", "linear_initializer", "roadmap",
-            "query")
+            "query", "ik_stage1_persistent")
     return {k: ln[k] for k in keep if k in ln}
 
 
@@ -1067,7 +1067,7 @@ def run_uneven(args, cr, I, torch, steps, warmup, extras):
         ms = float(np.median(per_step))
         if pers:
             res_p = [x.clone() for x in out]
-            alt = dict(ms_per_step=round(ms, 3), value=round(P / (ms * 1e-3), 2), autotune=tuned)
+            alt = dict(ms_per_step=round(ms, 3), value=round(P / (ms * 1e-3), 2))
     if alt:
         alt["identical_results"] = all(bool(torch.equal(a, b)) for a, b in zip(res_p, out))
     st = out[2].cpu().numpy()
