@@ -5,8 +5,9 @@
 // TrajProb rows) whose kernels look their problem up by seed or trajectory index.
 // Within a group, problems are ordered longest-first by estimated work, so the
 // first workgroups dispatched carry the longest chains (LPT list scheduling over
-// the compute units).  Groups are ordered the same way and dealt to up to four
-// streams forked from the caller's stream and joined back into it.  With
+// the compute units).  Groups are ordered the same way and each goes to the
+// least loaded (by estimated work) of up to four streams forked from the
+// caller's stream and joined back into it.  With
 // CR_BATCH_GRAPH the whole sequence is captured once into a hipGraph and
 // replayed on identical calls.
 #include <algorithm>
@@ -276,9 +277,14 @@ cr_status enqueue(const cr_robot* robots, const Plan& plan, const void* pinned, 
     for (int k = 1; k < nstreams && rc == CR_OK; ++k) rc = check_hip(hipStreamWaitEvent(lanes[k], fork, 0), "wait");
     if (rc != CR_OK) return rc;
   }
+  // LPT over the streams: groups come longest first, each goes to the stream with
+  // the least estimated work so far
+  std::vector<double> load(nstreams, 0.0);
   for (size_t gi = 0; gi < plan.groups.size() && rc == CR_OK; ++gi) {
     const Group& g = plan.groups[gi];
-    hipStream_t s = lanes[gi % nstreams];
+    const int li = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[li] += g.work;
+    hipStream_t s = lanes[li];
     char* gws = ws + g.ws_off;
     const cr_robot& rb = robots[g.robot];
     const unsigned char* src = (const unsigned char*)pinned + plan.table_off[gi];
