@@ -1453,21 +1453,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 }
 
 // The line search with its step lengths tried at once, for horizons of at most
-// 64 waypoints and at most 4 trials: a workgroup of 4 TP lanes holds one
+// 128 waypoints and at most 4 trials: a workgroup of 4 TP lanes holds one
 // trajectory and each slice of TP lanes (a half-wave for horizons of at most 32,
-// else a wave) evaluates one trial alpha = 2^-q (q = 0 .. 3), one lane per
-// waypoint; the accepted step is the first that passes in the sequential order.
-// Each lane sums its own waypoint's clearance (segment-ball culls, no shared work
-// list).  The sequential kernel above spends a whole wave per trial, half of it
-// idle outside the clearance sums on short horizons, and about 2.7 trials per
-// iteration on the trajectory workload.
-template <int NS, typename T, int TP>
+// else a wave) evaluates one trial alpha = 2^-q (q = 0 .. 3), WPL waypoints per
+// lane (waypoints t, t + TP, ...); the accepted step is the first that passes in
+// the sequential order.  Each lane sums its own waypoints' clearance
+// (segment-ball culls, no shared work list).  The sequential kernel above spends
+// a whole wave per trial, half of it idle outside the clearance sums on short
+// horizons, and about 2.7 trials per iteration on the trajectory workload.
+template <int NS, typename T, int TP, int WPL = 1>
 __global__ void __launch_bounds__(4 * TP)
     k_traj_search4(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                    const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                    const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
                    int32_t* __restrict__ trials) {
-  constexpr int NZ = 2 * NS, NU = 3 * NS;
+  constexpr int NZ = 2 * NS, NU = 3 * NS, TW = TP * WPL;
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_ok[4];
@@ -1483,31 +1483,37 @@ __global__ void __launch_bounds__(4 * TP)
   }
   const TrajCtx cx = traj_ctx(ta, traj);
   const int Tn = cx.pr.Tn, H = Tn - 1, M = cx.pr.M;
-  const int sub = (int)threadIdx.x / TP, t = (int)threadIdx.x - sub * TP;
+  const int sub = (int)threadIdx.x / TP, lane = (int)threadIdx.x - sub * TP;
   T* s_sph = reinterpret_cast<T*>(smem_raw);
-  T* s_u = s_sph + 4 * M + sub * TP * (NU + 3);
-  T* s_p = s_u + TP * NU;
+  T* s_u = s_sph + 4 * M + sub * TW * (NU + 3);
+  T* s_p = s_u + TW * NU;
   stage_spheres(ta, cx, s_sph);
-  const bool act = t < Tn;
   const T alpha = T(1) / T(1 << sub);
-  T zt[NZ];
-  if (act) {
+  T zt[WPL][NZ];
 #pragma unroll
-    for (int k = 0; k < NZ; ++k)
-      zt[k] = Z[(cx.wp + t) * NZ + k] + alpha * blk[(cx.wp + t) * R::SIZE + R::OY + k];
+  for (int j = 0; j < WPL; ++j) {
+    const int t = lane + j * TP;
+    if (t < Tn) {
+#pragma unroll
+      for (int k = 0; k < NZ; ++k)
+        zt[j][k] = Z[(cx.wp + t) * NZ + k] + alpha * blk[(cx.wp + t) * R::SIZE + R::OY + k];
+    }
   }
   __syncthreads();
   T cst = T(0);
-  if (act) {
+#pragma unroll
+  for (int j = 0; j < WPL; ++j) {
+    const int t = lane + j * TP;
+    if (t >= Tn) continue;
     T Rt[9], pt[3];
     if (M == 0) {
-      fk_tip<NS>(rb, zt, Rt, pt);
-      cst = bounds_cost<NS>(rb, w, zt);
+      fk_tip<NS>(rb, zt[j], Rt, pt);
+      cst += bounds_cost<NS>(rb, w, zt[j]);
     } else {
       Fwd<NS, T> f;
       WeightsT<T> wb = w;  // clearance alone here; the bounds below
       wb.sq_lim = wb.sq_curv = T(0);
-      cst = config_forward<NS, T, false>(rb, wb, zt, s_sph, M, 4, 1, f) + bounds_cost<NS>(rb, w, zt);
+      cst += config_forward<NS, T, false>(rb, wb, zt[j], s_sph, M, 4, 1, f) + bounds_cost<NS>(rb, w, zt[j]);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rt[k] = f.R[k];
       pt[0] = f.p[0];
@@ -1522,17 +1528,20 @@ __global__ void __launch_bounds__(4 * TP)
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T u[3];
-      ab_to_u(zt[2 * i], zt[2 * i + 1], rb.r[i], u);
+      ab_to_u(zt[j][2 * i], zt[j][2 * i + 1], rb.r[i], u);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = u[j];
+      for (int c = 0; c < 3; ++c) s_u[t * NU + 3 * i + c] = u[c];
     }
     s_p[3 * t] = pt[0];
     s_p[3 * t + 1] = pt[1];
     s_p[3 * t + 2] = pt[2];
   }
   __syncthreads();
-  if (act) {
-    const T idt = T(1) / w.dt, idt2 = idt * idt;
+  const T idt = T(1) / w.dt, idt2 = idt * idt;
+#pragma unroll
+  for (int j = 0; j < WPL; ++j) {
+    const int t = lane + j * TP;
+    if (t >= Tn) continue;
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
       if (t >= 1) {
@@ -1567,7 +1576,7 @@ __global__ void __launch_bounds__(4 * TP)
         for (int i = 0; i < NS; ++i) {
           T za, zb;
           load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.r[i], &za, &zb);
-          const T ra = w.sq_eq * (zt[2 * i] - za), rb2 = w.sq_eq * (zt[2 * i + 1] - zb);
+          const T ra = w.sq_eq * (zt[j][2 * i] - za), rb2 = w.sq_eq * (zt[j][2 * i + 1] - zb);
           cst += T(0.5) * (ra * ra + rb2 * rb2);
         }
       }
@@ -1575,15 +1584,21 @@ __global__ void __launch_bounds__(4 * TP)
   }
 #pragma unroll
   for (int off = TP / 2; off > 0; off >>= 1) cst += __shfl_xor(cst, off, TP);
-  if (t == 0) s_ok[sub] = sub < o.ls_max && cst <= cost0[traj] + T(1e-4) * alpha * gd_in[traj];
+  if (lane == 0) s_ok[sub] = sub < o.ls_max && cst <= cost0[traj] + T(1e-4) * alpha * gd_in[traj];
   __syncthreads();
   int acc = -1;
 #pragma unroll
   for (int q = 3; q >= 0; --q)
     if (s_ok[q]) acc = q;
-  if (acc == sub && act) {
+  if (acc == sub) {
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zt[k];
+    for (int j = 0; j < WPL; ++j) {
+      const int t = lane + j * TP;
+      if (t < Tn) {
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zt[j][k];
+      }
+    }
   }
   if (threadIdx.x == 0) {
     T l = lam[traj];
@@ -1992,9 +2007,11 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   // launches, such as the FP64 refinement, keep one wave per trajectory)
   const int gb = ta.Tmax <= 32 && nt >= 4096 && 2 * lds_b <= 64 * 1024 ? 2 : 1;
   constexpr int G = 64 / (4 * NS);  // trajectories per k_traj_solve workgroup (2 NZ lanes each)
-  // horizons of at most 64 waypoints and at most 4 trials: the trials at once
-  const bool par_search = ta.Tmax <= 64 && lo.ls_max <= 4;
-  const size_t lds_4 = sizeof(T) * (size_t)(4 * Mmax + 4 * (ta.Tmax <= 32 ? 32 : 64) * (3 * NS + 3));
+  // horizons of at most 128 waypoints and at most 4 trials: the trials at once
+  // (one waypoint per lane up to 64, two beyond)
+  const int tw4 = ta.Tmax <= 32 ? 32 : (ta.Tmax <= 64 ? 64 : 128);
+  const size_t lds_4 = sizeof(T) * (size_t)(4 * Mmax + 4 * tw4 * (3 * NS + 3));
+  const bool par_search = ta.Tmax <= 128 && lo.ls_max <= 4 && lds_4 <= 64 * 1024;
   // the normal-equation kernel rewrites the same records from the same z, so the
   // autotuner may time its variants on the first iteration
   auto build = [&](int v) {
@@ -2030,9 +2047,12 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
     if (par_search && ta.Tmax <= 32)
       hipLaunchKernelGGL((k_traj_search4<NS, T, 32>), dim3((unsigned)nt), dim3(128), lds_4, st, rb, w, ta, lo, Z, blk,
                          lam, c0, gd, chol, failed, trials);
-    else if (par_search)
+    else if (par_search && ta.Tmax <= 64)
       hipLaunchKernelGGL((k_traj_search4<NS, T, 64>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z, blk,
                          lam, c0, gd, chol, failed, trials);
+    else if (par_search)
+      hipLaunchKernelGGL((k_traj_search4<NS, T, 64, 2>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z,
+                         blk, lam, c0, gd, chol, failed, trials);
     else
       hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,
                          lam, c0, gd, chol, failed, trials, cap);

@@ -122,6 +122,34 @@ def test_fp64_lm_iterates_short_horizons(oracle, cr, kind):
 
 
 @pytest.mark.parametrize("kind", ["path", "traj"])
+@pytest.mark.parametrize("H", [64, 100, 127])
+def test_lm_two_waypoints_per_lane_search(oracle, cr, kind, H):
+    """Horizons of 65 to 128 waypoints take the line search with all step lengths
+    tried at once and two waypoints per lane.  Three FP64 LM iterations with
+    clearance and kinodynamic hinges equal the oracle's (1e-9); one FP32
+    iteration meets the FP32 step tolerance of test_fp32_lm_step_matches_oracle."""
+    print(f"traj two waypoints per lane kind={kind} H={H}", flush=True)
+    c = case(oracle, kind, 380 + H, n=3, H=H, P=2, S=1, M=3)
+    W = oracle.Weights(**c["W"])
+    u, _, _ = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=3, k_final=0), "f64")
+    u32, _, _ = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=1, k_final=0), "f32")
+    for p in range(c["P"]):
+        pb = oracle_problem(oracle, c, p)
+        z0 = oracle.u_to_z(c["ro"], c["seeds"][p, 0]).ravel()
+        zk, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, 3)
+        uk = oracle.z_to_u(c["ro"], zk.reshape(H + 1, c["n"], 2))
+        assert np.abs(u[p] - uk).max() <= 1e-9 * c["b"], (p, np.abs(u[p] - uk).max())
+        z1, _, _, _, _ = oracle.lm(c["ro"], W, pb, oracle.Opts(), z0, 1e-3, 1)
+        u1 = oracle.z_to_u(c["ro"], z1.reshape(H + 1, c["n"], 2))
+        step = np.abs(u1 - c["seeds"][p, 0]).max()
+        dev = np.abs(u32[p] - u1).max()
+        if step > 1e-9:
+            assert dev <= 5e-4 * step + 1e-7 * c["b"], (p, dev, step)
+        else:
+            assert dev <= 1e-5 * c["b"], (p, dev)
+
+
+@pytest.mark.parametrize("kind", ["path", "traj"])
 @pytest.mark.parametrize("n", [3, 4, 5, 6])
 def test_fp32_lm_step_matches_oracle(oracle, cr, kind, n):
     """One FP32 LM iteration over whole trajectories (FP32 normal equations and
