@@ -5,8 +5,10 @@
 // TrajProb rows) whose kernels look their problem up by seed or trajectory index.
 // Within a group, problems are ordered longest-first by estimated work, so the
 // first workgroups dispatched carry the longest chains (LPT list scheduling over
-// the compute units).  Groups are ordered the same way and each goes to the
-// least loaded (by estimated work) of up to four streams forked from the
+// the compute units).  IK groups go first (a few long launches each, whose
+// length follows the iteration count rather than the work), then path and
+// trajectory groups by estimated span (work plus an allowance for their launch
+// chains); each goes to the least loaded of up to four streams forked from the
 // caller's stream and joined back into it.  With
 // CR_BATCH_GRAPH the whole sequence is captured once into a hipGraph and
 // replayed on identical calls.
@@ -28,6 +30,7 @@ struct Group {
   int kind, robot;
   std::vector<int64_t> rows;  // problem indices, longest first
   double work;
+  double span;  // work plus a launch-chain allowance (stream assignment)
   int64_t P, B;               // problems; IK seeds (B) or trajectories
   TrajShape sh;
   int Smax;
@@ -109,7 +112,22 @@ cr_status make_plan(const cr_robot* robots, const cr_problem* probs, int64_t P, 
     for (size_t k = 0; k < ord.size(); ++k) rows[k] = g.rows[ord[k]];
     g.rows.swap(rows);
   }
-  std::stable_sort(G.begin(), G.end(), [](const Group& a, const Group& b) { return a.work > b.work; });
+  // IK groups first: each is a few long launches whose length is set by the
+  // iteration count, not by its (small) work, so they start at once and overlap
+  // the path and trajectory groups instead of running alone at the end
+  // Path and trajectory groups: a launch chain of some hundred kernels each, so
+  // even a small group lasts a while; their span adds half the mean group work
+  // to their own, which moves small groups forward and spreads them over the
+  // streams instead of leaving them for the end
+  double tw = 0.0;
+  int nt = 0;
+  for (const Group& g : G)
+    if (g.kind != CR_KIND_IK) tw += g.work, ++nt;
+  for (Group& g : G) g.span = g.work + (g.kind != CR_KIND_IK && nt > 0 ? 0.5 * tw / nt : 0.0);
+  std::stable_sort(G.begin(), G.end(), [](const Group& a, const Group& b) {
+    const bool ia = a.kind == CR_KIND_IK, ib = b.kind == CR_KIND_IK;
+    return ia != ib ? ia : a.span > b.span;
+  });
   size_t off = 0;
   for (Group& g : G) {
     const cr_robot& rb = robots[g.robot];
@@ -283,7 +301,7 @@ cr_status enqueue(const cr_robot* robots, const Plan& plan, const void* pinned, 
   for (size_t gi = 0; gi < plan.groups.size() && rc == CR_OK; ++gi) {
     const Group& g = plan.groups[gi];
     const int li = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    load[li] += g.work;
+    load[li] += g.span;
     hipStream_t s = lanes[li];
     char* gws = ws + g.ws_off;
     const cr_robot& rb = robots[g.robot];
