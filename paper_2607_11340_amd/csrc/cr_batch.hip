@@ -6,10 +6,10 @@
 // Within a group, problems are ordered longest-first by estimated work, so the
 // first workgroups dispatched carry the longest chains (LPT list scheduling over
 // the compute units).  IK groups go first (a few long launches each, whose
-// length follows the iteration count rather than the work), then path and
-// trajectory groups by estimated span (work plus an allowance for their launch
-// chains); each goes to the least loaded of up to four streams forked from the
-// caller's stream and joined back into it.  With
+// length follows the iteration count rather than the work), then the small path
+// and trajectory groups, then the others by estimated span (work plus an
+// allowance for their launch chains); each goes to the least loaded of up to four
+// streams forked from the caller's stream and joined back into it.  With
 // CR_BATCH_GRAPH the whole sequence is captured once into a hipGraph and
 // replayed on identical calls.
 #include <algorithm>
@@ -116,17 +116,20 @@ cr_status make_plan(const cr_robot* robots, const cr_problem* probs, int64_t P, 
   // iteration count, not by its (small) work, so they start at once and overlap
   // the path and trajectory groups instead of running alone at the end
   // Path and trajectory groups: a launch chain of some hundred kernels each, so
-  // even a small group lasts a while; their span adds half the mean group work
-  // to their own, which moves small groups forward and spreads them over the
-  // streams instead of leaving them for the end
+  // even a small group lasts a while.  Groups with less than half the mean work
+  // go right after the IK groups (their chains overlap those long launches,
+  // which leave room on the chip), the others follow by span: their work plus
+  // half the mean group work, an allowance for the chain
   double tw = 0.0;
   int nt = 0;
   for (const Group& g : G)
     if (g.kind != CR_KIND_IK) tw += g.work, ++nt;
   for (Group& g : G) g.span = g.work + (g.kind != CR_KIND_IK && nt > 0 ? 0.5 * tw / nt : 0.0);
-  std::stable_sort(G.begin(), G.end(), [](const Group& a, const Group& b) {
-    const bool ia = a.kind == CR_KIND_IK, ib = b.kind == CR_KIND_IK;
-    return ia != ib ? ia : a.span > b.span;
+  const double small = nt > 0 ? 0.5 * tw / nt : 0.0;
+  auto rank = [&](const Group& g) { return g.kind == CR_KIND_IK ? 0 : (g.work < small ? 1 : 2); };
+  std::stable_sort(G.begin(), G.end(), [&](const Group& a, const Group& b) {
+    const int ra = rank(a), rb = rank(b);
+    return ra != rb ? ra < rb : a.span > b.span;
   });
   size_t off = 0;
   for (Group& g : G) {
