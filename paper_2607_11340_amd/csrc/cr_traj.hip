@@ -1453,17 +1453,157 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
 }
 
 // The line search with its step lengths tried at once, for horizons of at most
-// 128 waypoints and at most 4 trials: a workgroup of 4 TP lanes holds one
+// 64 waypoints (k_traj_search4w below: up to 128) and at most 4 trials: a workgroup of 4 TP lanes holds one
 // trajectory and each slice of TP lanes (a half-wave for horizons of at most 32,
-// else a wave) evaluates one trial alpha = 2^-q (q = 0 .. 3), WPL waypoints per
-// lane (waypoints t, t + TP, ...); the accepted step is the first that passes in
-// the sequential order.  Each lane sums its own waypoints' clearance
-// (segment-ball culls, no shared work list).  The sequential kernel above spends
-// a whole wave per trial, half of it idle outside the clearance sums on short
-// horizons, and about 2.7 trials per iteration on the trajectory workload.
-template <int NS, typename T, int TP, int WPL = 1>
+// else a wave) evaluates one trial alpha = 2^-q (q = 0 .. 3), one lane per
+// waypoint; the accepted step is the first that passes in the sequential order.
+// Each lane sums its own waypoint's clearance (segment-ball culls, no shared work
+// list).  The sequential kernel above spends a whole wave per trial, half of it
+// idle outside the clearance sums on short horizons, and about 2.7 trials per
+// iteration on the trajectory workload.
+template <int NS, typename T, int TP>
 __global__ void __launch_bounds__(4 * TP)
     k_traj_search4(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
+                   const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
+                   const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
+                   int32_t* __restrict__ trials) {
+  constexpr int NZ = 2 * NS, NU = 3 * NS;
+  using R = Rec<NS>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_ok[4];
+  const int64_t traj = blockIdx.x;
+  if (failed[traj]) return;
+  if (!chol_ok[traj]) {
+    if (threadIdx.x == 0) {
+      const T l = lam[traj];
+      if (!(l < o.lam_max)) failed[traj] = 2;  // z and lambda would repeat from here on
+      else lam[traj] = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    }
+    return;
+  }
+  const TrajCtx cx = traj_ctx(ta, traj);
+  const int Tn = cx.pr.Tn, H = Tn - 1, M = cx.pr.M;
+  const int sub = (int)threadIdx.x / TP, t = (int)threadIdx.x - sub * TP;
+  T* s_sph = reinterpret_cast<T*>(smem_raw);
+  T* s_u = s_sph + 4 * M + sub * TP * (NU + 3);
+  T* s_p = s_u + TP * NU;
+  stage_spheres(ta, cx, s_sph);
+  const bool act = t < Tn;
+  const T alpha = T(1) / T(1 << sub);
+  T zt[NZ];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k)
+      zt[k] = Z[(cx.wp + t) * NZ + k] + alpha * blk[(cx.wp + t) * R::SIZE + R::OY + k];
+  }
+  __syncthreads();
+  T cst = T(0);
+  if (act) {
+    T Rt[9], pt[3];
+    if (M == 0) {
+      fk_tip<NS>(rb, zt, Rt, pt);
+      cst = bounds_cost<NS>(rb, w, zt);
+    } else {
+      Fwd<NS, T> f;
+      WeightsT<T> wb = w;  // clearance alone here; the bounds below
+      wb.sq_lim = wb.sq_curv = T(0);
+      cst = config_forward<NS, T, false>(rb, wb, zt, s_sph, M, 4, 1, f) + bounds_cost<NS>(rb, w, zt);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Rt[k] = f.R[k];
+      pt[0] = f.p[0];
+      pt[1] = f.p[1];
+      pt[2] = f.p[2];
+    }
+    if (ta.kind == CR_KIND_PATH) {
+      T Tt[12], ft[3], tq[3];
+      load_pose(ta, cx, t, Tt);
+      cst += pose_term<T, false>(w, Rt, pt, Tt, ft, tq);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      T u[3];
+      ab_to_u(zt[2 * i], zt[2 * i + 1], rb.r[i], u);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s_u[t * NU + 3 * i + j] = u[j];
+    }
+    s_p[3 * t] = pt[0];
+    s_p[3 * t + 1] = pt[1];
+    s_p[3 * t + 2] = pt[2];
+  }
+  __syncthreads();
+  if (act) {
+    const T idt = T(1) / w.dt, idt2 = idt * idt;
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      if (t >= 1) {
+        const T v = (s_u[t * NU + m] - s_u[(t - 1) * NU + m]) * idt;
+        const T rr = w.sq_vel * v;
+        cst += T(0.5) * rr * rr;
+        if (w.has_vmax && fabs(v) > w.v_max) {
+          const T hr = w.sq_lim * (fabs(v) - w.v_max);
+          cst += T(0.5) * hr * hr;
+        }
+      }
+      if (t >= 2) {
+        const T a = (s_u[t * NU + m] - T(2) * s_u[(t - 1) * NU + m] + s_u[(t - 2) * NU + m]) * idt2;
+        const T rr = w.sq_acc * a;
+        cst += T(0.5) * rr * rr;
+        if (w.has_amax && fabs(a) > w.a_max) {
+          const T hr = w.sq_lim * (fabs(a) - w.a_max);
+          cst += T(0.5) * hr * hr;
+        }
+      }
+    }
+    if (ta.kind == CR_KIND_TRAJ) {
+      if (t >= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T rr = w.sq_len * (s_p[3 * t + c] - s_p[3 * (t - 1) + c]);
+          cst += T(0.5) * rr * rr;
+        }
+      }
+      if (t == 0 || t == H) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          T za, zb;
+          load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.r[i], &za, &zb);
+          const T ra = w.sq_eq * (zt[2 * i] - za), rb2 = w.sq_eq * (zt[2 * i + 1] - zb);
+          cst += T(0.5) * (ra * ra + rb2 * rb2);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = TP / 2; off > 0; off >>= 1) cst += __shfl_xor(cst, off, TP);
+  if (t == 0) s_ok[sub] = sub < o.ls_max && cst <= cost0[traj] + T(1e-4) * alpha * gd_in[traj];
+  __syncthreads();
+  int acc = -1;
+#pragma unroll
+  for (int q = 3; q >= 0; --q)
+    if (s_ok[q]) acc = q;
+  if (acc == sub && act) {
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zt[k];
+  }
+  if (threadIdx.x == 0) {
+    T l = lam[traj];
+    if (acc == 0) l = l / T(10) > o.lam_min ? l / T(10) : o.lam_min;
+    if (acc < 0) {
+      if (!(l < o.lam_max)) failed[traj] = 2;  // rejected at the largest damping: a fixed point
+      l = l * T(10) < o.lam_max ? l * T(10) : o.lam_max;
+    }
+    lam[traj] = l;
+    trials[traj] += acc >= 0 ? acc + 1 : (o.ls_max < 4 ? o.ls_max : 4);
+  }
+}
+
+// k_traj_search4 for horizons of 65 to 128 waypoints: each lane of a slice takes
+// WPL waypoints (t, t + TP, ...).  A kernel of its own, because folding the
+// waypoint loop into k_traj_search4 raised that kernel's registers from 90 to
+// 161 per lane (5 waves per SIMD to 3) on the common horizons.
+template <int NS, typename T, int TP, int WPL>
+__global__ void __launch_bounds__(4 * TP)
+    k_traj_search4w(RobotT<T> rb, WeightsT<T> w, TrajArgs<T> ta, LMOpts<T> o, T* __restrict__ Z,
                    const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                    const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
                    int32_t* __restrict__ trials) {
@@ -2051,7 +2191,7 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
       hipLaunchKernelGGL((k_traj_search4<NS, T, 64>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z, blk,
                          lam, c0, gd, chol, failed, trials);
     else if (par_search)
-      hipLaunchKernelGGL((k_traj_search4<NS, T, 64, 2>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z,
+      hipLaunchKernelGGL((k_traj_search4w<NS, T, 64, 2>), dim3((unsigned)nt), dim3(256), lds_4, st, rb, w, ta, lo, Z,
                          blk, lam, c0, gd, chol, failed, trials);
     else
       hipLaunchKernelGGL((k_traj_search<NS, T>), dim3((unsigned)nt), dim3(threads), lds_s, st, rb, w, ta, lo, Z, blk,

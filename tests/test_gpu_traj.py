@@ -123,12 +123,13 @@ def test_fp64_lm_iterates_short_horizons(oracle, cr, kind):
 
 @pytest.mark.parametrize("kind", ["path", "traj"])
 @pytest.mark.parametrize("H", [64, 100, 127])
-def test_lm_two_waypoints_per_lane_search(oracle, cr, kind, H):
-    """Horizons of 65 to 128 waypoints take the line search with all step lengths
-    tried at once and two waypoints per lane.  Three FP64 LM iterations with
+def test_lm_horizons_65_to_128(oracle, cr, kind, H):
+    """Horizons of 65 to 128 waypoints: more than one wave of waypoint lanes, the
+    line search with all step lengths tried at once and two waypoints per lane,
+    the two-ended block solve with long halves.  Three FP64 LM iterations with
     clearance and kinodynamic hinges equal the oracle's (1e-9); one FP32
     iteration meets the FP32 step tolerance of test_fp32_lm_step_matches_oracle."""
-    print(f"traj two waypoints per lane kind={kind} H={H}", flush=True)
+    print(f"traj long horizon kind={kind} H={H}", flush=True)
     c = case(oracle, kind, 380 + H, n=3, H=H, P=2, S=1, M=3)
     W = oracle.Weights(**c["W"])
     u, _, _ = gpu_solve(cr, c, cr.Opts(n_final=0, k_init=3, k_final=0), "f64")
