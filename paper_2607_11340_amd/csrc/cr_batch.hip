@@ -5,11 +5,12 @@
 // TrajProb rows) whose kernels look their problem up by seed or trajectory index.
 // Within a group, problems are ordered longest-first by estimated work, so the
 // first workgroups dispatched carry the longest chains (LPT list scheduling over
-// the compute units).  IK groups go first (a few long launches each, whose
-// length follows the iteration count rather than the work), then the small path
-// and trajectory groups, then the others by estimated span (work plus an
-// allowance for their launch chains); each goes to the least loaded of up to four
-// streams forked from the caller's stream and joined back into it.  With
+// the compute units).  The largest path or trajectory group goes first, then
+// the IK groups (a few long launches each, whose length follows the iteration
+// count rather than the work), then the small path and trajectory groups, then
+// the others by estimated span (work plus an allowance for their launch chains);
+// each goes to the least loaded of up to four streams forked from the caller's
+// stream and joined back into it.  With
 // CR_BATCH_GRAPH the whole sequence is captured once into a hipGraph and
 // replayed on identical calls.
 #include <algorithm>
@@ -116,9 +117,10 @@ cr_status make_plan(const cr_robot* robots, const cr_problem* probs, int64_t P, 
   // iteration count, not by its (small) work, so they start at once and overlap
   // the path and trajectory groups instead of running alone at the end
   // Path and trajectory groups: a launch chain of some hundred kernels each, so
-  // even a small group lasts a while.  Groups with less than half the mean work
-  // go right after the IK groups (their chains overlap those long launches,
-  // which leave room on the chip), the others follow by span: their work plus
+  // even a small group lasts a while.  The largest one starts first (it would
+  // otherwise end the batch alone), then the IK groups, then the groups with
+  // less than half the mean work (their chains overlap the long IK launches,
+  // which leave room on the chip), then the others by span: their work plus
   // half the mean group work, an allowance for the chain
   double tw = 0.0;
   int nt = 0;
@@ -126,7 +128,13 @@ cr_status make_plan(const cr_robot* robots, const cr_problem* probs, int64_t P, 
     if (g.kind != CR_KIND_IK) tw += g.work, ++nt;
   for (Group& g : G) g.span = g.work + (g.kind != CR_KIND_IK && nt > 0 ? 0.5 * tw / nt : 0.0);
   const double small = nt > 0 ? 0.5 * tw / nt : 0.0;
-  auto rank = [&](const Group& g) { return g.kind == CR_KIND_IK ? 0 : (g.work < small ? 1 : 2); };
+  double wmax = 0.0;
+  for (const Group& g : G)
+    if (g.kind != CR_KIND_IK && g.work > wmax) wmax = g.work;
+  auto rank = [&](const Group& g) {
+    if (g.kind == CR_KIND_IK) return 1;
+    return g.work >= wmax ? 0 : (g.work < small ? 2 : 3);
+  };
   std::stable_sort(G.begin(), G.end(), [&](const Group& a, const Group& b) {
     const int ra = rank(a), rb = rank(b);
     return ra != rb ? ra < rb : a.span > b.span;
