@@ -727,7 +727,8 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
   const bool timed = timer_on();
   if (timed) timer_begin_call(st);
   if (sa.M > 0) {
-    hipLaunchKernelGGL((k_ik_stage1_sph<NS, T>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
+    hipLaunchKernelGGL((k_ik_stage1_sph<NS, T>), dim3(blocks_for(P * (int64_t)((S + 63) / 64) * 64, 256)), dim3(256), 0,
+                       st, rb, w, lo, P, (int)S,
                        Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
                        ws.failed1, ws.trials1);
   } else {

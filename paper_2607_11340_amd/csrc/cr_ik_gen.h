@@ -44,9 +44,15 @@ __global__ void __launch_bounds__(256)
                     int32_t* __restrict__ failed_out, int32_t* __restrict__ trials_out) {
   constexpr int NC = EXT ? 3 : 2, NZ = NC * NS;
   const int64_t B = P * (int64_t)S;
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const int64_t p = b / S;
+  // ceil(S / 64) waves per problem, so every wave holds seeds of one problem: the
+  // problem index and its obstacle pointers are then wave-uniform and the
+  // obstacle reads are scalar loads (scalar cache) instead of vector ones
+  const int wpp = (S + 63) / 64;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t p = (int64_t)__builtin_amdgcn_readfirstlane((int)(wave / wpp));
+  const int s = (int)(wave - (wave / wpp) * wpp) * 64 + (int)(threadIdx.x & 63);
+  if (p >= P || s >= S) return;
+  const int64_t b = p * S + s;
   const double* sp = sa.M > 0 ? sa.sph + (sa.per_problem ? p * sa.M : 0) : nullptr;
   T tt[12];
 #pragma unroll
@@ -240,7 +246,8 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
   const int64_t B = P * (int64_t)S;
   const bool timed = timer_on();
   if (timed) timer_begin_call(st);
-  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, EXT, SELF, POLY>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, (int)S,
+  hipLaunchKernelGGL((k_ik_stage1_sph<NS, T, EXT, SELF, POLY>), dim3(blocks_for(P * (int64_t)((S + 63) / 64) * 64, 256)),
+                     dim3(256), 0, st, rb, w, lo, P, (int)S,
                      Tt, useed, o.k_init, (T)o.lambda0, sa, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,
                      ws.failed1, ws.trials1);
   cr_status rc = check_hip(hipGetLastError(), "k_ik_stage1_sph");
