@@ -410,16 +410,6 @@ __global__ void __launch_bounds__(256)
 // sphere set and array offsets (struct IkProb); same per-seed iteration.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int64_t ik_find(const IkProb* tp, int64_t P, int64_t b) {
-  int64_t lo = 0, hi = P - 1;  // last problem whose first seed is <= b
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (tp[mid].seed0 <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Stage 1 of seed s of problem pr (the seed at b in the launch's stage-1 arrays).
 template <int NS, typename T>
 __device__ __forceinline__ void ik_rag_seed(const RobotT<T>& rb, const WeightsT<T>& w, const LMOpts<T>& o,
@@ -463,16 +453,30 @@ __device__ __forceinline__ void ik_rag_seed(const RobotT<T>& rb, const WeightsT<
   failed_out[b] = failed ? 1 : 0;
 }
 
+constexpr int kIkTile = 64;  // seeds per tile of the ragged IK stage 1
+
+// One wave per tile of 64 consecutive seeds of one problem (tile0 of a problem in
+// its table row's `pad`), so the problem's row, target and spheres are
+// wave-uniform: scalar loads, and no wave mixes problems with and without
+// clearance rows.
 template <int NS, typename T, int OCC = 1>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     k_ik_stage1_rag(RobotT<T> rb, WeightsT<T> w, LMOpts<T> o, int64_t P, int64_t B, const IkProb* __restrict__ tp,
                     const double* __restrict__ task, const double* __restrict__ useed, const double* __restrict__ sph,
                     int iters, T lam0, T* __restrict__ z_out, T* __restrict__ e_out, T* __restrict__ pen_out,
-                    T* __restrict__ cost_out, int32_t* __restrict__ failed_out) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const IkProb pr = tp[ik_find(tp, P, b)];
-  ik_rag_seed<NS, T>(rb, w, o, pr, b, b - pr.seed0, B, task, useed, sph, iters, lam0, z_out, e_out, pen_out, cost_out,
+                    T* __restrict__ cost_out, int32_t* __restrict__ failed_out, int n_tiles) {
+  const int tile = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  if (tile >= n_tiles) return;
+  int64_t lo = 0, hi = P - 1;  // the last row whose first tile is <= tile
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (tp[mid].pad <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const IkProb pr = tp[lo];
+  const int64_t s = (int64_t)(tile - pr.pad) * kIkTile + (threadIdx.x & 63);
+  if (s >= pr.S) return;
+  ik_rag_seed<NS, T>(rb, w, o, pr, pr.seed0 + s, s, B, task, useed, sph, iters, lam0, z_out, e_out, pen_out, cost_out,
                      failed_out);
 }
 
@@ -486,7 +490,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 // that problem's SelectTop (n_final > 0).  No wave waits for another: the last
 // arrival does the problem's remaining work, so every wave reaches the exit.
 // q[0]: the queue head, q[1 + k]: tiles done of problem k (all zero on entry).
-constexpr int kIkTile = 64;
 
 template <int NS, typename T, int OCC = 1>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC)))
@@ -502,7 +505,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC)))
   for (;;) {
     int item = 0;
     if (lane == 0) item = atomicAdd(&q[0], 1);
-    item = __shfl(item, 0, 64);
+    item = __builtin_amdgcn_readfirstlane(item);  // lane 0's item, wave-uniform
     if (item >= n_tiles) break;
     // the problem of the tile: the last row whose first tile is <= item
     int64_t lo = 0, hi = P - 1;
@@ -964,9 +967,9 @@ static cr_status run_ik_group(const cr_robot& rb0, int64_t P, int64_t B, int Sma
                          useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, (T*)ws.cost1,     \
                          ws.failed1, ws.queue, o.n_final, sp.Spad, sp.stage_pen, sp.stage_nz, (T)o.dup_eps, ws.sel); \
     } else {                                                                                                        \
-      hipLaunchKernelGGL((k_ik_stage1_rag<NS, T, O>), dim3(blocks_for(B, 256)), dim3(256), 0, st, rb, w, lo, P, B,  \
-                         tp, task, useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1,          \
-                         (T*)ws.cost1, ws.failed1);                                                                 \
+      hipLaunchKernelGGL((k_ik_stage1_rag<NS, T, O>), dim3(blocks_for(n_tiles * 64, 256)), dim3(256), 0, st, rb, w, \
+                         lo, P, B, tp, task, useed, sph, o.k_init, (T)o.lambda0, (T*)ws.z1, (T*)ws.e1, (T*)ws.pen1, \
+                         (T*)ws.cost1, ws.failed1, (int)n_tiles);                                                   \
     }                                                                                                               \
   } while (0)
     if constexpr (sizeof(T) == 4) {
