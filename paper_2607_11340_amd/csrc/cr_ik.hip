@@ -774,7 +774,8 @@ static cr_status run_ik(const cr_robot& rb0, const cr_spheres* sp, int64_t P, co
     if (sa.M > 0) {
       const int g2 = stage2_cfg_lanes(B2);
 #define CR_S2C(GL)                                                                                                    \
-  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, false, false, GL>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, \
+  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, false, false, GL>), dim3(blocks_for(stage2_threads(P, o.n_final, GL), 256)), \
+                     dim3(256), 0, st, \
                      rbd, wd, lod, P, (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa,  \
                      ws.z2, ws.cost2, ws.failed2)
       if (g2 == 4) CR_S2C(4);

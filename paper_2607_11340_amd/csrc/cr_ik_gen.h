@@ -26,6 +26,12 @@ struct SphArgs {
 };
 
 // the polytopes of problem p
+// Threads of a k_ik_stage2 launch: whole waves per problem, G lanes per candidate.
+static inline int64_t stage2_threads(int64_t P, int nf, int G) {
+  const int cpw = 64 / G;
+  return P * (int64_t)((nf + cpw - 1) / cpw) * 64;
+}
+
 __device__ __forceinline__ PolyArgs<double> poly_of(const SphArgs& sa, int64_t p) {
   return PolyArgs<double>{sa.NPO > 0 ? sa.pl + (sa.per_problem ? p * sa.NPO * sa.F : 0) : nullptr, sa.pld, sa.NPO,
                           sa.F};
@@ -98,14 +104,18 @@ __global__ void __launch_bounds__(256)
                 const double* __restrict__ Tt, const T1* __restrict__ z1, const int32_t* __restrict__ sel,
                 int iters, double lam0, SphArgs sa, double* __restrict__ z2, double* __restrict__ cost2,
                 int32_t* __restrict__ failed2) {
-  constexpr int NZ = (EXT ? 3 : 2) * NS;
+  constexpr int NZ = (EXT ? 3 : 2) * NS, CPW = 64 / G;  // candidates per wave
   const int64_t B2 = P * (int64_t)nf, B1 = P * (int64_t)S;
-  const int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t b = tg / G;
-  const bool lead = tg % G == 0;
-  if (b >= B2) return;
-  const int64_t p = b / nf;
-  const int k = (int)(b % nf);
+  // ceil(nf / CPW) waves per problem, so the problem index and its obstacle
+  // pointers are wave-uniform (scalar loads), as in k_ik_stage1_sph
+  const int wpp = (nf + CPW - 1) / CPW;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t p = (int64_t)__builtin_amdgcn_readfirstlane((int)(wave / wpp));
+  const int lanew = (int)(threadIdx.x & 63);
+  const int k = (int)(wave - (wave / wpp) * wpp) * CPW + lanew / G;
+  const bool lead = lanew % G == 0;
+  if (p >= P || k >= nf) return;  // whole groups of G lanes leave together
+  const int64_t b = p * nf + k;
   const int s = sel[k * P + p];
   if (s < 0) {
     if (lead) {
@@ -264,7 +274,8 @@ cr_status run_ik_gen(const cr_robot& rb0, const SphArgs& sa, int64_t P, const do
     const int64_t B2 = P * (int64_t)o.n_final;
     const int g2 = stage2_cfg_lanes(B2);
 #define CR_S2C(GL)                                                                                                  \
-  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF, GL, POLY>), dim3(blocks_for(GL * B2, 256)), dim3(256), 0, st, rbd, \
+  hipLaunchKernelGGL((k_ik_stage2<NS, T, true, EXT, SELF, GL, POLY>), dim3(blocks_for(stage2_threads(P, o.n_final, GL), 256)), \
+                     dim3(256), 0, st, rbd, \
                      wd, lod, P, (int)S, (int)o.n_final, Tt, (const T*)ws.z1, ws.sel, o.k_final, o.lambda0, sa, ws.z2, \
                      ws.cost2, ws.failed2)
     if (g2 == 4) CR_S2C(4);
