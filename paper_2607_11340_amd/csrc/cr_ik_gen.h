@@ -38,8 +38,9 @@ __device__ __forceinline__ PolyArgs<double> poly_of(const SphArgs& sa, int64_t p
 }
 
 // Stage 1 with clearance rows (eq. 10): one lane per seed as k_ik_stage1, the
-// generic per-configuration normal equations; spheres read from HBM (every lane
-// of a wave reads the same sphere: one broadcast load).  Also the stage 1 of
+// generic per-configuration normal equations; the problem's spheres and polytope
+// planes are read by scalar loads (each wave holds seeds of one problem only).
+// Also the stage 1 of
 // extensible robots (EXT: three coordinates a, b, e per segment), with or
 // without spheres (sa.M may be 0).
 template <int NS, typename T, bool EXT = false, bool SELF = false, bool POLY = false>
