@@ -1629,31 +1629,29 @@ __global__ void __launch_bounds__(4 * TP)
   T* s_p = s_u + TW * NU;
   stage_spheres(ta, cx, s_sph);
   const T alpha = T(1) / T(1 << sub);
-  T zt[WPL][NZ];
+  // the trial point of waypoint t, formed where it is used rather than kept in
+  // registers across the barriers (the same expression gives the same bits)
+  auto trial = [&](int t, T* zt) {
 #pragma unroll
-  for (int j = 0; j < WPL; ++j) {
-    const int t = lane + j * TP;
-    if (t < Tn) {
-#pragma unroll
-      for (int k = 0; k < NZ; ++k)
-        zt[j][k] = Z[(cx.wp + t) * NZ + k] + alpha * blk[(cx.wp + t) * R::SIZE + R::OY + k];
-    }
-  }
+    for (int k = 0; k < NZ; ++k) zt[k] = Z[(cx.wp + t) * NZ + k] + alpha * blk[(cx.wp + t) * R::SIZE + R::OY + k];
+  };
   __syncthreads();
   T cst = T(0);
 #pragma unroll
   for (int j = 0; j < WPL; ++j) {
     const int t = lane + j * TP;
     if (t >= Tn) continue;
+    T zj[NZ];
+    trial(t, zj);
     T Rt[9], pt[3];
     if (M == 0) {
-      fk_tip<NS>(rb, zt[j], Rt, pt);
-      cst += bounds_cost<NS>(rb, w, zt[j]);
+      fk_tip<NS>(rb, zj, Rt, pt);
+      cst += bounds_cost<NS>(rb, w, zj);
     } else {
       Fwd<NS, T> f;
       WeightsT<T> wb = w;  // clearance alone here; the bounds below
       wb.sq_lim = wb.sq_curv = T(0);
-      cst += config_forward<NS, T, false>(rb, wb, zt[j], s_sph, M, 4, 1, f) + bounds_cost<NS>(rb, w, zt[j]);
+      cst += config_forward<NS, T, false>(rb, wb, zj, s_sph, M, 4, 1, f) + bounds_cost<NS>(rb, w, zj);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rt[k] = f.R[k];
       pt[0] = f.p[0];
@@ -1668,7 +1666,7 @@ __global__ void __launch_bounds__(4 * TP)
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       T u[3];
-      ab_to_u(zt[j][2 * i], zt[j][2 * i + 1], rb.r[i], u);
+      ab_to_u(zj[2 * i], zj[2 * i + 1], rb.r[i], u);
 #pragma unroll
       for (int c = 0; c < 3; ++c) s_u[t * NU + 3 * i + c] = u[c];
     }
@@ -1712,11 +1710,13 @@ __global__ void __launch_bounds__(4 * TP)
         }
       }
       if (t == 0 || t == H) {
+        T zj[NZ];
+        trial(t, zj);
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
           T za, zb;
           load_end<NS>(ta, cx, t == 0 ? 0 : 1, i, rb.r[i], &za, &zb);
-          const T ra = w.sq_eq * (zt[j][2 * i] - za), rb2 = w.sq_eq * (zt[j][2 * i + 1] - zb);
+          const T ra = w.sq_eq * (zj[2 * i] - za), rb2 = w.sq_eq * (zj[2 * i + 1] - zb);
           cst += T(0.5) * (ra * ra + rb2 * rb2);
         }
       }
@@ -1735,8 +1735,10 @@ __global__ void __launch_bounds__(4 * TP)
     for (int j = 0; j < WPL; ++j) {
       const int t = lane + j * TP;
       if (t < Tn) {
+        T zj[NZ];
+        trial(t, zj);
 #pragma unroll
-        for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zt[j][k];
+        for (int k = 0; k < NZ; ++k) Z[(cx.wp + t) * NZ + k] = zj[k];
       }
     }
   }
