@@ -456,7 +456,7 @@ def main():
     meas = stored_counters(WORKLOAD) or {}
     kmeas = meas.get(kname, {})
     traffic = kmeas.get("hbm_bytes_per_launch")
-    # the build's survey estimate of about 3 kflop per FP32 seed-iteration, for comparison
+    # a coarser count of about 3 kflop per FP32 seed-iteration, for comparison
     survey_flops = 3.0e3 * P * S * spec["k_init"]
     roofline = dict(bound="alu", kernel=kname, achieved=round(achieved, 3),
                     peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
