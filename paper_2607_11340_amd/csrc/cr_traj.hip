@@ -1607,7 +1607,8 @@ __global__ void __launch_bounds__(4 * TP)
                    const T* __restrict__ blk, T* __restrict__ lam, const T* __restrict__ cost0,
                    const T* __restrict__ gd_in, const int32_t* __restrict__ chol_ok, int32_t* __restrict__ failed,
                    int32_t* __restrict__ trials) {
-  constexpr int NZ = 2 * NS, NU = 3 * NS, TW = TP * WPL;
+  constexpr int NZ = 2 * NS, NU = 3 * NS;
+  const int TW = ta.Tmax;  // waypoints per slice in LDS: the launch's longest horizon (<= TP * WPL)
   using R = Rec<NS>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_ok[4];
@@ -2151,7 +2152,7 @@ static cr_status traj_stage(const RobotT<T>& rb, const WeightsT<T>& w, const Tra
   constexpr int G = 64 / (4 * NS);  // trajectories per k_traj_solve workgroup (2 NZ lanes each)
   // horizons of at most 128 waypoints and at most 4 trials: the trials at once
   // (one waypoint per lane up to 64, two beyond)
-  const int tw4 = ta.Tmax <= 32 ? 32 : (ta.Tmax <= 64 ? 64 : 128);
+  const int tw4 = ta.Tmax <= 32 ? 32 : (ta.Tmax <= 64 ? 64 : ta.Tmax);  // k_traj_search4w: Tmax per slice
   const size_t lds_4 = sizeof(T) * (size_t)(4 * Mmax + 4 * tw4 * (3 * NS + 3));
   const bool par_search = ta.Tmax <= 128 && lo.ls_max <= 4 && lds_4 <= 64 * 1024;
   // the normal-equation kernel rewrites the same records from the same z, so the
